@@ -1,0 +1,290 @@
+"""Oracle binding (test infrastructure only).
+
+A ctypes wrapper around ``ipc_oracle.c``, the plain FP64 CPU implementation of
+one IPC Newton step.  Only the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the library never does.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libipc_oracle.so")
+_SRC = os.path.join(_HERE, "ipc_oracle.c")
+
+PTR_KEYS = ("X", "V", "tets", "tet_E", "tet_nu", "tet_rho", "vobj",
+            "body_q", "body_qdot", "body_mass", "body_S", "body_vol", "body_kappa",
+            "body_ext", "body_obj", "bv_xbar", "bv_body", "btri", "sv_x", "stri",
+            "obj_kind", "excl", "sp_ka", "sp_ia", "sp_xa", "sp_kb", "sp_ib", "sp_xb",
+            "sp_k", "driven_body")
+
+
+def build(force=True):
+    """Compile the oracle with gcc (no FMA contraction, OpenMP over elements)."""
+    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= os.path.getmtime(_SRC):
+        return _SO
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+           "-o", _SO, _SRC, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.POINTER(ctypes.c_int)
+        L.or_create.restype = P
+        L.or_create.argtypes = [I, ctypes.POINTER(P), D]
+        L.or_destroy.argtypes = [P]
+        L.or_count.restype = ctypes.c_int
+        L.or_count.argtypes = [P, ctypes.c_int]
+        L.or_scalar.restype = ctypes.c_double
+        L.or_scalar.argtypes = [P, ctypes.c_int]
+        for n in ("or_get_mass",):
+            getattr(L, n).argtypes = [P, D]
+        L.or_get_tris.argtypes = [P, I]
+        L.or_get_edges.argtypes = [P, I]
+        L.or_get_state.argtypes = [P, D, D]
+        L.or_set_state.argtypes = [P, D, D]
+        L.or_world.argtypes = [P, D, D]
+        L.or_begin_step.argtypes = [P, D]
+        L.or_energy.restype = ctypes.c_double
+        L.or_energy.argtypes = [P, D, D]
+        L.or_gradient.argtypes = [P, D, D, D]
+        L.or_hessian_matvec.argtypes = [P, D, ctypes.c_int, D, D]
+        L.or_pairs.restype = ctypes.c_int
+        L.or_pairs.argtypes = [P, D, I, ctypes.c_int, I, ctypes.c_int, I, I]
+        L.or_ccd.restype = ctypes.c_double
+        L.or_ccd.argtypes = [P, D, D]
+        L.or_pcg.restype = ctypes.c_int
+        L.or_pcg.argtypes = [P, D, D, D, ctypes.c_double]
+        L.or_step.restype = ctypes.c_int
+        L.or_step.argtypes = [P, D, ctypes.POINTER(OStats)]
+        L.or_dist2_pt.restype = ctypes.c_double
+        L.or_dist2_pt.argtypes = [D, I]
+        L.or_dist2_ee.restype = ctypes.c_double
+        L.or_dist2_ee.argtypes = [D, I]
+        L.or_dist2_derivs.restype = ctypes.c_double
+        L.or_dist2_derivs.argtypes = [ctypes.c_int, D, D, D]
+        L.or_accd.restype = ctypes.c_double
+        L.or_accd.argtypes = [ctypes.c_int, D, D, ctypes.c_double]
+        L.or_snh.restype = ctypes.c_double
+        L.or_snh.argtypes = [D, ctypes.c_double, ctypes.c_double, D, D]
+        L.or_psd_project.argtypes = [D, ctypes.c_int]
+        L.or_barrier3.argtypes = [ctypes.c_double, ctypes.c_double, D]
+        _lib = L
+    return _lib
+
+
+class OStats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int), ("pcg_iters_total", ctypes.c_int),
+                ("pcg_iters_max", ctypes.c_int), ("n_pt_max", ctypes.c_int), ("n_ee_max", ctypes.c_int),
+                ("n_lag", ctypes.c_int), ("status", ctypes.c_int), ("alpha_min", ctypes.c_double),
+                ("energy", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def scene_sizes(sc):
+    return [len(sc["X"]), len(sc["tets"]), len(sc["body_q"]), len(sc["bv_xbar"]), len(sc["btri"]),
+            len(sc["sv_x"]), len(sc["stri"]), len(sc["obj_kind"]), len(sc["excl"]), len(sc["sp_k"]),
+            len(sc["driven_body"])]
+
+
+def scene_params(sc):
+    g = sc["g"]
+    return [float(sc["h"]), float(g[0]), float(g[1]), float(g[2]), float(sc["dhat"]), float(sc["kappa"]),
+            float(sc["mu"]), float(sc["eps_v"]), float(sc["newton_tol"]), float(sc["max_newton"]),
+            float(sc["pcg_tol"]), float(sc["max_pcg"]), float(sc["ccd_s"])]
+
+
+class Oracle:
+    """One scene held by the oracle."""
+
+    def __init__(self, scene):
+        L = lib()
+        self.scene = scene
+        sizes = np.array(scene_sizes(scene), np.int32)
+        arrs = [np.ascontiguousarray(scene[k]) for k in PTR_KEYS]
+        ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        prm = np.array(scene_params(scene), np.float64)
+        self._h = L.or_create(_i(sizes), ptrs, _d(prm))
+        self._keep = arrs
+        self.ndof = L.or_count(self._h, 0)
+        self.nnodes = L.or_count(self._h, 1)
+        self.ncv = L.or_count(self._h, 2)
+        self.ntri = L.or_count(self._h, 3)
+        self.nedge = L.or_count(self._h, 4)
+        self.step_index = 0
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_destroy(self._h)
+            self._h = None
+
+    # scalars
+    @property
+    def kappa(self):
+        return lib().or_scalar(self._h, 0)
+
+    @property
+    def L(self):
+        return lib().or_scalar(self._h, 1)
+
+    @property
+    def newton_threshold(self):
+        return lib().or_scalar(self._h, 3)
+
+    def mass(self):
+        m = np.zeros(len(self.scene["X"]))
+        lib().or_get_mass(self._h, _d(m))
+        return m
+
+    def tris(self):
+        t = np.zeros((self.ntri, 3), np.int32)
+        lib().or_get_tris(self._h, _i(t))
+        return t
+
+    def edges(self):
+        e = np.zeros((self.nedge, 2), np.int32)
+        lib().or_get_edges(self._h, _i(e))
+        return e
+
+    def state(self):
+        y = np.zeros(self.ndof)
+        v = np.zeros(self.ndof)
+        lib().or_get_state(self._h, _d(y), _d(v))
+        return y, v
+
+    def set_state(self, y, v):
+        y = _f64(y); v = _f64(v)
+        lib().or_set_state(self._h, _d(y), _d(v))
+
+    def world(self, y):
+        y = _f64(y)
+        x = np.zeros((self.ncv, 3))
+        lib().or_world(self._h, _d(y), _d(x))
+        return x
+
+    def targets(self, n):
+        dq = self.scene["drive_q"]
+        if dq.shape[1] == 0:
+            return None
+        return np.ascontiguousarray(dq[n])
+
+    def begin_step(self, n=None):
+        n = self.step_index if n is None else n
+        t = self.targets(n)
+        lib().or_begin_step(self._h, _d(t) if t is not None else None)
+
+    def energy(self, y):
+        y = _f64(y)
+        terms = np.zeros(7)
+        E = lib().or_energy(self._h, _d(y), _d(terms))
+        return E, terms
+
+    def gradient(self, y):
+        y = _f64(y)
+        g = np.zeros(self.ndof)
+        ga = np.zeros(self.ndof)
+        lib().or_gradient(self._h, _d(y), _d(g), _d(ga))
+        return g, ga
+
+    def hess_matvec(self, y, v, project=True):
+        y = _f64(y); v = _f64(v)
+        out = np.zeros(self.ndof)
+        lib().or_hessian_matvec(self._h, _d(y), int(project), _d(v), _d(out))
+        return out
+
+    def pairs(self, y, cap=1 << 22):
+        y = _f64(y)
+        while True:
+            pt = np.zeros((cap, 4), np.int32)
+            ee = np.zeros((cap, 4), np.int32)
+            npt = ctypes.c_int(); nee = ctypes.c_int()
+            rc = lib().or_pairs(self._h, _d(y), _i(pt), cap, _i(ee), cap, ctypes.byref(npt), ctypes.byref(nee))
+            if rc == 0:
+                return pt[:npt.value].copy(), ee[:nee.value].copy()
+            cap = max(npt.value, nee.value)
+
+    def ccd(self, y, p):
+        y = _f64(y); p = _f64(p)
+        return lib().or_ccd(self._h, _d(y), _d(p))
+
+    def pcg(self, y, b, eta):
+        y = _f64(y); b = _f64(b)
+        x = np.zeros(self.ndof)
+        it = lib().or_pcg(self._h, _d(y), _d(b), _d(x), eta)
+        return x, it
+
+    def step(self):
+        t = self.targets(self.step_index)
+        st = OStats()
+        rc = lib().or_step(self._h, _d(t) if t is not None else None, ctypes.byref(st))
+        self.step_index += 1
+        return rc, st.as_dict()
+
+
+# single-pair helpers for unit pins
+def dist2_pt(x):
+    x = _f64(x); t = ctypes.c_int()
+    return lib().or_dist2_pt(_d(x), ctypes.byref(t)), t.value
+
+
+def dist2_ee(x):
+    x = _f64(x); t = ctypes.c_int()
+    return lib().or_dist2_ee(_d(x), ctypes.byref(t)), t.value
+
+
+def dist2_derivs(kind, x):
+    x = _f64(x)
+    g = np.zeros(12); H = np.zeros(144)
+    d2 = lib().or_dist2_derivs(kind, _d(x), _d(g), _d(H))
+    return d2, g, H.reshape(12, 12)
+
+
+def accd(kind, x, p, s=0.1):
+    x = _f64(x); p = _f64(p)
+    return lib().or_accd(kind, _d(x), _d(p), s)
+
+
+def snh(F, mu, lam):
+    """F as a 3x3 matrix; returns (Psi, P 3x3, dP/dF as 9x9 over column-major vec)."""
+    Fv = _f64(np.asarray(F).T.ravel())
+    P = np.zeros(9); H = np.zeros(81)
+    psi = lib().or_snh(_d(Fv), mu, lam, _d(P), _d(H))
+    return psi, P.reshape(3, 3).T, H.reshape(9, 9)
+
+
+def barrier3(d, dhat):
+    out = np.zeros(3)
+    lib().or_barrier3(float(d), float(dhat), _d(out))
+    return out
+
+
+def psd_project(A):
+    A = _f64(A).copy()
+    lib().or_psd_project(_d(A), A.shape[0])
+    return A
