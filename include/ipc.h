@@ -1,0 +1,193 @@
+/*
+ * ipc.h - C-ABI of the MI355X (gfx950) IPC Newton-step library.
+ *
+ * The library advances one or more independent scenes by one implicit step
+ * each call, minimising the incremental potential of PhyVisGen Eq. (3)
+ * (Sec. III-C.2):
+ *     E = E_inertia + E_barrier + E_friction + E_FEM + E_ABD
+ *       + E_joint(q_ref) + E_couple,         E_couple = E_fixed + E_stitch (Eq. (1)),
+ * with E_stitch the attachment springs of Eq. (2), over all degrees of freedom
+ * jointly (the arm links, the rigid gripper parts, the soft fingertips and the
+ * manipulated objects).  The state a call returns is the physical record of
+ * Eq. (4): FEM vertex positions and affine-body states.
+ *
+ * Conventions shared by every entry point
+ *  - Units SI, FP64 throughout.
+ *  - DOF vector layout ("external layout"): scenes concatenated in creation
+ *    order; within a scene, the FEM vertices (x, y, z each) followed by the
+ *    affine bodies, 12 numbers per body: translation p, then the three columns
+ *    of the affine matrix A.  A body point with body-frame coordinates xb sits
+ *    at p + xb0 A[:,0] + xb1 A[:,1] + xb2 A[:,2].
+ *  - Pointers named *_dev are device pointers (HIP global memory of the device
+ *    the context was created on); *_host are host pointers.  The caller owns
+ *    every buffer it passes; the library reads or writes it only during the
+ *    call, stream-ordered on the context's stream.
+ *  - Every call returns an int status.  On error the context keeps a message
+ *    readable through ipc_last_error().  No C++ exception crosses the ABI.
+ */
+#ifndef IPC_H
+#define IPC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IPC_OK = 0,
+    IPC_E_INVALID = 1,        /* bad argument or scene data (checked on the host)      */
+    IPC_E_CAPACITY = 2,       /* a size limit was exceeded                              */
+    IPC_E_NOT_CONVERGED = 3,  /* Newton hit max_newton; the state holds the last iterate */
+    IPC_E_LINESEARCH = 4,     /* no decrease after 40 halvings                           */
+    IPC_E_INTERSECTING = 5,   /* a contact pair has zero distance                        */
+    IPC_E_INDEFINITE = 6,     /* adjoint PCG met p^T H p <= 0                            */
+    IPC_E_DEVICE = 7          /* a HIP runtime call failed                               */
+};
+
+/* Host description of one scene.  Arrays are host pointers with the layouts
+ * below; they are copied by ipc_create() and may be freed afterwards.
+ *
+ *  FEM tetrahedra (Sec. III-C.1, Stable Neo-Hookean material)
+ *    X[nv*3], V[nv*3]      rest (= initial) positions and initial velocities
+ *    tets[nt*4]            vertex indices, det[X1-X0,X2-X0,X3-X0] > 0 required
+ *    tet_E, tet_nu, tet_rho[nt]  Young's modulus (> 0), Poisson ratio in (0, 0.5),
+ *                          density (> 0)
+ *    vobj[nv]              object id of each FEM vertex
+ *  Affine bodies (rigid parts, arm links, rigid objects; affine body dynamics)
+ *    body_q, body_qdot[nb*12]  state (p, A[:,0..2]) and its rate
+ *    body_mass[nb], body_S[nb*9]  mass and second moment of mass (row-major
+ *                          3x3) about the frame origin, which must be the centroid
+ *    body_vol, body_kappa[nb]  volume and orthogonality stiffness
+ *    body_ext[nb*3]        half extents of the body box (convergence measure)
+ *    body_obj[nb]          object id
+ *  Contact geometry
+ *    bv_xbar[nbv*3], bv_body[nbv], btri[nbt*3]  body-frame surface vertices of
+ *                          bodies and their outward triangles (body-vertex indices)
+ *    sv_x[nsv*3], stri[nst*3]  static world geometry
+ *    obj_kind[nobj]        0 FEM mesh, 1 affine body, 2 static
+ *    excl[nex*2]           object pairs that never collide
+ *  Springs E = h^2 k/2 |a - b|^2: stitch springs (Eq. (2)), fixed joints and
+ *  joint drives toward per-step link targets
+ *    sp_ka, sp_kb[ns]      side kind: 0 FEM vertex, 1 body point, 2 drive target
+ *    sp_ia, sp_ib[ns]      FEM vertex / body / driven-link slot
+ *    sp_xa, sp_xb[ns*3]    body-frame point (kind 1) or link-frame anchor (kind 2)
+ *    sp_k[ns]              stiffness (N/m)
+ *    driven_body[nd]       body driven by slot d
+ *  Parameters
+ *    h time step; g gravity; dhat barrier threshold; kappa barrier stiffness
+ *    (<= 0: 10 * mean FEM vertex mass * |g| * h^2 / dhat); mu friction;
+ *    eps_v friction velocity threshold; newton_tol (stop when the largest world
+ *    displacement of the Newton direction is below newton_tol * h * L, L the
+ *    initial bounding-box diagonal); pcg_tol (relative residual); ccd_s (CCD
+ *    gap fraction); max_newton, max_pcg iteration caps. */
+typedef struct ipc_scene_desc {
+    int32_t nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd;
+    const double *X, *V;
+    const int32_t *tets;
+    const double *tet_E, *tet_nu, *tet_rho;
+    const int32_t *vobj;
+    const double *body_q, *body_qdot, *body_mass, *body_S, *body_vol, *body_kappa, *body_ext;
+    const int32_t *body_obj;
+    const double *bv_xbar;
+    const int32_t *bv_body, *btri;
+    const double *sv_x;
+    const int32_t *stri, *obj_kind, *excl;
+    const int32_t *sp_ka, *sp_ia;
+    const double *sp_xa;
+    const int32_t *sp_kb, *sp_ib;
+    const double *sp_xb, *sp_k;
+    const int32_t *driven_body;
+    double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
+    int32_t max_newton, max_pcg;
+} ipc_scene_desc;
+
+/* Per-scene statistics of the last ipc_step(). */
+typedef struct ipc_stats {
+    int32_t status;            /* IPC_OK or the scene's error code                 */
+    int32_t newton_iters;
+    int32_t pcg_iters_total;
+    int32_t pcg_iters_max;
+    int32_t n_pt_max, n_ee_max;  /* active pairs, max over Newton iterations    */
+    int32_t n_lag;             /* friction pairs lagged at the step start         */
+    int32_t n_cand_max;        /* CCD candidates, max over Newton iterations      */
+    double alpha_min;          /* smallest accepted line-search step              */
+    double energy;             /* potential at the final iterate                  */
+} ipc_stats;
+
+typedef struct ipc_ctx ipc_ctx;
+
+/* Size queries (ipc_query). */
+enum {
+    IPC_Q_NDOF = 0,       /* DOFs of all scenes (external layout)             */
+    IPC_Q_NSCENES = 1,
+    IPC_Q_NDRIVEN = 2,    /* driven-link slots of all scenes                  */
+    IPC_Q_NTRI = 3,       /* contact triangles of all scenes                   */
+    IPC_Q_NEDGE = 4,
+    IPC_Q_NNODES = 5,     /* internal padded node count                        */
+    IPC_Q_NTETS = 6       /* internal padded tetrahedron count                 */
+};
+
+/* Flags of ipc_energy_grad_hess. */
+enum { IPC_PSD_PROJECT = 1u, IPC_WITH_FRICTION = 2u };
+
+/* Create a context over n_scenes >= 1 scenes (batching uses the same API:
+ * all scenes are stepped together, each with its own Newton, PCG and line
+ * search decisions).  hip_stream is a hipStream_t (NULL = default stream) on
+ * the current device.  Validates the scene data on the host; allocates the
+ * device memory the context needs (released by ipc_destroy). */
+int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_stream, ipc_ctx **out);
+int ipc_destroy(ipc_ctx *ctx);
+const char *ipc_last_error(const ipc_ctx *ctx);
+int ipc_query(const ipc_ctx *ctx, int what, int64_t *value);
+/* Per-scene scalars: kappa (as used), L, Newton threshold (newton_tol*h*L). */
+int ipc_scene_scalars(const ipc_ctx *ctx, int scene, double *kappa, double *L, double *newton_thr);
+
+/* State in the external layout (ndof doubles each).  ydot may be NULL on get. */
+int ipc_get_state(ipc_ctx *ctx, double *y_dev, double *ydot_dev);
+int ipc_set_state(ipc_ctx *ctx, const double *y_dev, const double *ydot_dev);
+
+/* Step set-up at the current state: predictive positions x~ = x + h v + h^2 g
+ * (bodies: q + h qdot + h^2 (g, 0, 0, 0)), the drive targets of this step
+ * (targets_dev: 12 doubles per driven slot, all scenes concatenated; may be
+ * NULL when there are no driven links) and the friction data lagged at the
+ * current state.  ipc_step() calls it itself. */
+int ipc_begin_step(ipc_ctx *ctx, const double *targets_dev);
+
+/* Evaluate the potential of the step set up by ipc_begin_step() at any y_dev
+ * (external layout): E_dev[n_scenes] (nullable), the gradient g_dev[ndof]
+ * (nullable) and, when both v_dev and Hv_dev are given, Hv_dev = H(y) v_dev.
+ * flags: IPC_PSD_PROJECT projects the element / body / contact Hessians to PSD
+ * (what the Newton solve uses); IPC_WITH_FRICTION includes the lagged friction.
+ * Returns IPC_E_INTERSECTING (and E = +inf) when a pair has zero distance. */
+int ipc_energy_grad_hess(ipc_ctx *ctx, const double *y_dev, double *E_dev, double *g_dev,
+                         const double *v_dev, double *Hv_dev, uint32_t flags);
+
+/* Active contact pairs at y_dev for one scene, as vertex tuples in the scene's
+ * own vertex numbering (FEM vertices, then body surface vertices, then static
+ * vertices): point-triangle (v, t0, t1, t2) and edge-edge (a0, a1, b0, b1),
+ * sorted lexicographically.  n_pt / n_ee receive the counts; returns
+ * IPC_E_CAPACITY (with the counts set) when cap is too small. */
+int ipc_get_pairs(ipc_ctx *ctx, const double *y_dev, int scene, int32_t *pt_host, int32_t *ee_host,
+                  int64_t cap, int64_t *n_pt, int64_t *n_ee);
+
+/* Largest safe step alpha_dev[n_scenes] in [0, 1] from additive CCD over the
+ * swept candidates of [y, y + p] (external layout). */
+int ipc_ccd(ipc_ctx *ctx, const double *y_dev, const double *p_dev, double *alpha_dev);
+
+/* Solve H(y) x = b with the block-Jacobi PCG of the Newton step (projected
+ * Hessian at y, relative tolerance eta); iters_host[n_scenes] (nullable). */
+int ipc_pcg(ipc_ctx *ctx, const double *y_dev, const double *b_dev, double *x_dev, double eta,
+            int32_t *iters_host);
+
+/* Advance every scene by one step: ipc_begin_step(targets_dev), then projected
+ * Newton iterations with PCG directions, CCD step bounds and backtracking line
+ * search until each scene's Newton measure is below its threshold.  stats_host
+ * (nullable) receives n_scenes records.  Returns IPC_OK, or the first non-OK
+ * scene status (IPC_E_NOT_CONVERGED leaves that scene at its last iterate). */
+int ipc_step(ipc_ctx *ctx, const double *targets_dev, ipc_stats *stats_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

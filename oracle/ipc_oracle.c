@@ -1154,6 +1154,9 @@ static double eval_ip(OScene *s, const double *y, const IVec *apt, const IVec *a
     }
     double *pe = xmalloc(sizeof(double) * (size_t)(s->nt ? s->nt : 1));
     double *ge = g ? xmalloc(sizeof(double) * 12 * (size_t)(s->nt ? s->nt : 1)) : NULL;
+    /* gradient scale of each tet: the stress terms mu F and (lh (J-1) - mu) cof F
+     * before they cancel (near rest they do, and rounding follows their size) */
+    double *gs = gabs ? xmalloc(sizeof(double) * 12 * (size_t)(s->nt ? s->nt : 1)) : NULL;
     #pragma omp parallel for schedule(static)
     for (int e = 0; e < s->nt; ++e) {
         double F[9], c[4][3], P[9], HF[81];
@@ -1167,6 +1170,17 @@ static double eval_ip(OScene *s, const double *y, const IVec *apt, const IVec *a
                     for (int j = 0; j < 3; ++j) acc += c[a][j] * P[3 * j + r];
                     ge[12 * e + 3 * a + r] = w * acc;
                 }
+        if (gs) {
+            double cof[9];
+            cross3(F + 3, F + 6, cof); cross3(F + 6, F, cof + 3); cross3(F, F + 3, cof + 6);
+            double J = dot3(F, cof), mu = s->lmu[e], sc = (s->llam[e] + mu) * (J - 1.0) - mu;
+            for (int a = 0; a < 4; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    double acc = 0.0;
+                    for (int j = 0; j < 3; ++j) acc += fabs(c[a][j]) * (fabs(mu * F[3 * j + r]) + fabs(sc * cof[3 * j + r]));
+                    gs[12 * e + 3 * a + r] = w * acc;
+                }
+        }
         if (T) {
             if (project) or_psd_project(HF, 9);
             OTerm *tt = T->t + t_fem0 + e;
@@ -1188,17 +1202,32 @@ static double eval_ip(OScene *s, const double *y, const IVec *apt, const IVec *a
         if (g)
             for (int a = 0; a < 4; ++a) {
                 OPt p = {1, {s->tets[4 * e + a]}, {1.0}};
-                scatter_grad(&p, ge + 12 * e + 3 * a, g, gabs);
+                scatter_grad(&p, ge + 12 * e + 3 * a, g, NULL);
+                if (gabs) for (int r = 0; r < 3; ++r) gabs[3 * (size_t)s->tets[4 * e + a] + r] += gs[12 * e + 3 * a + r];
             }
     }
-    free(pe); free(ge);
+    free(pe); free(ge); free(gs);
     /* affine bodies (C4) */
     for (int b = 0; b < s->nb; ++b) {
         int n0 = s->nv + 4 * b;
         double gA[9], HA[81];
         double kv = h2 * s->bkappa[b] * s->bvol[b];
         Eabd += abd_energy(y + 3 * n0, kv, g ? gA : NULL, T ? HA : NULL);
-        if (g) for (int c = 0; c < 3; ++c) { OPt p = {1, {n0 + 1 + c}, {1.0}}; scatter_grad(&p, gA + 3 * c, g, gabs); }
+        if (g) for (int c = 0; c < 3; ++c) { OPt p = {1, {n0 + 1 + c}, {1.0}}; scatter_grad(&p, gA + 3 * c, g, NULL); }
+        if (gabs) {
+            /* scale: 4 kappa V (|A A^T| + I) |A|, the operands of A A^T - I before they cancel */
+            const double *q = y + 3 * (size_t)n0;
+            for (int bcol = 0; bcol < 3; ++bcol)
+                for (int a = 0; a < 3; ++a) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k) {
+                        double aat = 0.0;
+                        for (int m = 0; m < 3; ++m) aat += fabs(q[3 + 3 * m + a] * q[3 + 3 * m + k]);
+                        acc += (aat + (a == k ? 1.0 : 0.0)) * fabs(q[3 + 3 * bcol + k]);
+                    }
+                    gabs[3 * (size_t)(n0 + 1 + bcol) + a] += 4.0 * kv * acc;
+                }
+        }
         if (T) {
             if (project) or_psd_project(HA, 9);
             memset(&tm, 0, sizeof tm); tm.np = 3;
@@ -1218,7 +1247,16 @@ static double eval_ip(OScene *s, const double *y, const IVec *apt, const IVec *a
         Esp += 0.5 * kk * dot3(d, d);
         if (g) {
             double ga[3] = {kk * d[0], kk * d[1], kk * d[2]}, gb[3] = {-ga[0], -ga[1], -ga[2]};
-            scatter_grad(&pa, ga, g, gabs); scatter_grad(&pb, gb, g, gabs);
+            scatter_grad(&pa, ga, g, NULL); scatter_grad(&pb, gb, g, NULL);
+            if (gabs) {
+                /* scale: h^2 k (|a| + |b|), the operands of a - b before they cancel */
+                double sa[3] = {kk * (fabs(xa[0]) + fabs(xb[0])), kk * (fabs(xa[1]) + fabs(xb[1])), kk * (fabs(xa[2]) + fabs(xb[2]))};
+                for (int side = 0; side < 2; ++side) {
+                    const OPt *pp = side ? &pb : &pa;
+                    for (int c = 0; c < pp->n; ++c)
+                        for (int k2 = 0; k2 < 3; ++k2) gabs[3 * (size_t)pp->node[c] + k2] += fabs(pp->w[c]) * sa[k2];
+                }
+            }
         }
         if (T) {
             memset(&tm, 0, sizeof tm); tm.np = 2; tm.pt[0] = pa; tm.pt[1] = pb;

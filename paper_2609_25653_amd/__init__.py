@@ -1,0 +1,156 @@
+"""MI355X-native IPC Newton step of the PhyVisGen arm-gripper system.
+
+``Sim`` wraps one context of the HIP library (one or more scenes stepped
+together).  Tensors are torch CUDA (HIP) float64 tensors in the external DOF
+layout: per scene, FEM vertices (x, y, z) then 12 numbers per affine body
+(p, A[:,0], A[:,1], A[:,2]).  All work is done by the library's kernels on the
+current torch stream; torch only provides device memory and the stream.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (IPC_PSD_PROJECT, IPC_WITH_FRICTION, STATUS_NAMES, Stats, lib)  # noqa: F401
+
+
+class IPCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the IPC library needs a ROCm GPU (torch.cuda is not available)")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Sim:
+    """A context over ``scenes`` (a scene dict or a list of them)."""
+
+    def __init__(self, scenes, device="cuda"):
+        torch = _torch()
+        if isinstance(scenes, dict):
+            scenes = [scenes]
+        self.scenes = list(scenes)
+        self.device = torch.device(device)
+        L = lib()
+        keep = []
+        arr = (_lib.SceneDesc * len(self.scenes))(*[_lib.make_desc(s, keep) for s in self.scenes])
+        h = ctypes.c_void_p()
+        self._stream = torch.cuda.current_stream(self.device)
+        rc = L.ipc_create(arr, len(self.scenes), ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise IPCError(rc, L.ipc_last_error(None).decode())
+        self._h = h
+        self.ndof = self._query(_lib.Q_NDOF)
+        self.n_scenes = self._query(_lib.Q_NSCENES)
+        self.n_driven = self._query(_lib.Q_NDRIVEN)
+        self.dof_offsets = np.cumsum([0] + [3 * (len(s["X"]) + 4 * len(s["body_q"])) for s in self.scenes])
+        self.step_index = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().ipc_destroy(h)
+            self._h = None
+
+    def _query(self, what):
+        v = ctypes.c_int64()
+        self._check(lib().ipc_query(self._h, what, ctypes.byref(v)))
+        return v.value
+
+    def _check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise IPCError(rc, lib().ipc_last_error(self._h).decode())
+        return rc
+
+    def _vec(self, n=None):
+        torch = _torch()
+        return torch.empty(self.ndof if n is None else n, dtype=torch.float64, device=self.device)
+
+    def _as_dev(self, a, n=None):
+        torch = _torch()
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+        if n is not None and t.numel() != n:
+            raise ValueError(f"expected {n} values, got {t.numel()}")
+        return t
+
+    def scene_scalars(self, s=0):
+        k, L, t = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().ipc_scene_scalars(self._h, s, ctypes.byref(k), ctypes.byref(L), ctypes.byref(t)))
+        return dict(kappa=k.value, L=L.value, newton_threshold=t.value)
+
+    def state(self):
+        y, v = self._vec(), self._vec()
+        self._check(lib().ipc_get_state(self._h, _ptr(y), _ptr(v)))
+        return y, v
+
+    def set_state(self, y, ydot):
+        y = self._as_dev(y, self.ndof); v = self._as_dev(ydot, self.ndof)
+        self._check(lib().ipc_set_state(self._h, _ptr(y), _ptr(v)))
+
+    def targets(self, n):
+        """Drive targets of step n for all scenes, concatenated (nd x 12)."""
+        parts = [s["drive_q"][n] for s in self.scenes if s["drive_q"].shape[1] > 0]
+        if not parts:
+            return None
+        return self._as_dev(np.concatenate(parts, 0))
+
+    def begin_step(self, n=None):
+        t = self.targets(self.step_index if n is None else n)
+        self._check(lib().ipc_begin_step(self._h, _ptr(t)))
+
+    def energy_grad_hess(self, y, v=None, project=True, friction=True, energy=True, grad=True):
+        """Energies per scene, gradient and H v at y (external layout)."""
+        torch = _torch()
+        y = self._as_dev(y, self.ndof)
+        E = torch.empty(self.n_scenes, dtype=torch.float64, device=self.device) if energy else None
+        g = self._vec() if grad else None
+        vv = self._as_dev(v, self.ndof) if v is not None else None
+        Hv = self._vec() if v is not None else None
+        flags = (IPC_PSD_PROJECT if project else 0) | (IPC_WITH_FRICTION if friction else 0)
+        rc = self._check(lib().ipc_energy_grad_hess(self._h, _ptr(y), _ptr(E), _ptr(g), _ptr(vv), _ptr(Hv), flags),
+                         allow=(_lib.IPC_E_INTERSECTING,))
+        return E, g, Hv, rc
+
+    def pairs(self, y, scene=0, cap=1 << 20):
+        y = self._as_dev(y, self.ndof)
+        while True:
+            pt = np.zeros((cap, 4), np.int32); ee = np.zeros((cap, 4), np.int32)
+            npt, nee = ctypes.c_int64(), ctypes.c_int64()
+            rc = lib().ipc_get_pairs(self._h, _ptr(y), scene, pt.ctypes.data_as(_lib._I), ee.ctypes.data_as(_lib._I),
+                                     cap, ctypes.byref(npt), ctypes.byref(nee))
+            if rc == _lib.IPC_E_CAPACITY:
+                cap = max(npt.value, nee.value)
+                continue
+            self._check(rc)
+            return pt[:npt.value].copy(), ee[:nee.value].copy()
+
+    def ccd(self, y, p):
+        torch = _torch()
+        y = self._as_dev(y, self.ndof); p = self._as_dev(p, self.ndof)
+        a = torch.empty(self.n_scenes, dtype=torch.float64, device=self.device)
+        self._check(lib().ipc_ccd(self._h, _ptr(y), _ptr(p), _ptr(a)))
+        return a
+
+    def pcg(self, y, b, eta):
+        y = self._as_dev(y, self.ndof); b = self._as_dev(b, self.ndof)
+        x = self._vec()
+        it = np.zeros(self.n_scenes, np.int32)
+        self._check(lib().ipc_pcg(self._h, _ptr(y), _ptr(b), _ptr(x), float(eta), it.ctypes.data_as(_lib._I)))
+        return x, it
+
+    def step(self, n=None, allow_status=()):
+        t = self.targets(self.step_index if n is None else n)
+        st = (Stats * self.n_scenes)()
+        rc = lib().ipc_step(self._h, _ptr(t), st)
+        self._check(rc, allow=allow_status)
+        self.step_index += 1
+        return rc, [s.as_dict() for s in st]

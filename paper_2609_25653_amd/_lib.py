@@ -1,0 +1,125 @@
+"""ctypes binding of the C-ABI in include/ipc.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libipc_hip.so``; this module only
+converts scene dictionaries to ``ipc_scene_desc`` records and passes device
+pointers and the current torch stream.  Importing it without the built
+library raises immediately: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libipc_hip.so")
+
+IPC_OK = 0
+IPC_E_INVALID = 1
+IPC_E_CAPACITY = 2
+IPC_E_NOT_CONVERGED = 3
+IPC_E_LINESEARCH = 4
+IPC_E_INTERSECTING = 5
+IPC_E_INDEFINITE = 6
+IPC_E_DEVICE = 7
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "NOT_CONVERGED", 4: "LINESEARCH", 5: "INTERSECTING",
+                6: "INDEFINITE", 7: "DEVICE"}
+
+IPC_PSD_PROJECT = 1
+IPC_WITH_FRICTION = 2
+
+Q_NDOF, Q_NSCENES, Q_NDRIVEN, Q_NTRI, Q_NEDGE, Q_NNODES, Q_NTETS = range(7)
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("nv", "nt", "nb", "nbv", "nbt", "nsv", "nst", "nobj", "nex", "ns", "nd")] + [
+        ("X", _D), ("V", _D), ("tets", _I), ("tet_E", _D), ("tet_nu", _D), ("tet_rho", _D), ("vobj", _I),
+        ("body_q", _D), ("body_qdot", _D), ("body_mass", _D), ("body_S", _D), ("body_vol", _D), ("body_kappa", _D),
+        ("body_ext", _D), ("body_obj", _I), ("bv_xbar", _D), ("bv_body", _I), ("btri", _I), ("sv_x", _D),
+        ("stri", _I), ("obj_kind", _I), ("excl", _I), ("sp_ka", _I), ("sp_ia", _I), ("sp_xa", _D), ("sp_kb", _I),
+        ("sp_ib", _I), ("sp_xb", _D), ("sp_k", _D), ("driven_body", _I),
+        ("h", ctypes.c_double), ("g", ctypes.c_double * 3), ("dhat", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("mu", ctypes.c_double), ("eps_v", ctypes.c_double), ("newton_tol", ctypes.c_double),
+        ("pcg_tol", ctypes.c_double), ("ccd_s", ctypes.c_double), ("max_newton", ctypes.c_int32),
+        ("max_pcg", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("newton_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32),
+                ("pcg_iters_max", ctypes.c_int32), ("n_pt_max", ctypes.c_int32), ("n_ee_max", ctypes.c_int32),
+                ("n_lag", ctypes.c_int32), ("n_cand_max", ctypes.c_int32), ("alpha_min", ctypes.c_double),
+                ("energy", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"HIP library not built: {SO_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(SO_PATH)
+        P = ctypes.c_void_p
+        L.ipc_create.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_int, P, ctypes.POINTER(P)]
+        L.ipc_destroy.argtypes = [P]
+        L.ipc_last_error.restype = ctypes.c_char_p
+        L.ipc_last_error.argtypes = [P]
+        L.ipc_query.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.ipc_scene_scalars.argtypes = [P, ctypes.c_int, _D, _D, _D]
+        L.ipc_get_state.argtypes = [P, P, P]
+        L.ipc_set_state.argtypes = [P, P, P]
+        L.ipc_begin_step.argtypes = [P, P]
+        L.ipc_energy_grad_hess.argtypes = [P, P, P, P, P, P, ctypes.c_uint32]
+        L.ipc_get_pairs.argtypes = [P, P, ctypes.c_int, _I, _I, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_int64)]
+        L.ipc_ccd.argtypes = [P, P, P, P]
+        L.ipc_pcg.argtypes = [P, P, P, P, ctypes.c_double, _I]
+        L.ipc_step.argtypes = [P, P, ctypes.POINTER(Stats)]
+        for n in ("ipc_create", "ipc_destroy", "ipc_query", "ipc_scene_scalars", "ipc_get_state", "ipc_set_state",
+                  "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg", "ipc_step"):
+            getattr(L, n).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Names of the ipc_* functions the library exports (checked against include/ipc.h)."""
+    L = lib()
+    names = []
+    for n in ("ipc_create", "ipc_destroy", "ipc_last_error", "ipc_query", "ipc_scene_scalars", "ipc_get_state",
+              "ipc_set_state", "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg",
+              "ipc_step"):
+        if hasattr(L, n):
+            names.append(n)
+    return names
+
+
+def make_desc(sc, keep):
+    """Fill an ipc_scene_desc from a scene dict; arrays are kept alive in ``keep``."""
+    d = SceneDesc()
+    sizes = dict(nv=len(sc["X"]), nt=len(sc["tets"]), nb=len(sc["body_q"]), nbv=len(sc["bv_xbar"]),
+                 nbt=len(sc["btri"]), nsv=len(sc["sv_x"]), nst=len(sc["stri"]), nobj=len(sc["obj_kind"]),
+                 nex=len(sc["excl"]), ns=len(sc["sp_k"]), nd=len(sc["driven_body"]))
+    for k, v in sizes.items():
+        setattr(d, k, int(v))
+    for name, typ in SceneDesc._fields_:
+        if typ is _D or typ is _I:
+            dt = np.float64 if typ is _D else np.int32
+            a = np.ascontiguousarray(sc[name], dtype=dt)
+            keep.append(a)
+            setattr(d, name, a.ctypes.data_as(typ))
+    d.h = float(sc["h"])
+    for k in range(3):
+        d.g[k] = float(sc["g"][k])
+    for k in ("dhat", "kappa", "mu", "eps_v", "newton_tol", "pcg_tol", "ccd_s"):
+        setattr(d, k, float(sc[k]))
+    d.max_newton = int(sc["max_newton"])
+    d.max_pcg = int(sc["max_pcg"])
+    return d

@@ -1,0 +1,734 @@
+// C-ABI entry points and the host orchestration of the Newton step
+// (PhyVisGen Sec. III-C.2: all degrees of freedom advanced jointly by
+// minimising one incremental potential per step, Eq. (3)).
+//
+// Stream-ordered on the context's stream.  Host synchronisation happens only
+// at control decisions: PCG convergence (every few iterations), candidate and
+// pair counts (to size buffers), the Newton measure and line-search energies.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "ipc_device.h"
+#include "ipc_internal.h"
+#include "ipc_kernels.h"
+
+namespace ipc {
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// ---- node-vector kernels -----------------------------------------------------
+__global__ void k_to_internal(int64_t NE, const int *__restrict__ ext2node, const double *__restrict__ ext, double *__restrict__ v)
+{
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= NE) return;
+    int n = ext2node[e];
+    v[3 * (size_t)n] = ext[3 * e]; v[3 * (size_t)n + 1] = ext[3 * e + 1]; v[3 * (size_t)n + 2] = ext[3 * e + 2];
+}
+__global__ void k_to_external(int64_t NE, const int *__restrict__ ext2node, const double *__restrict__ v, double *__restrict__ ext)
+{
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= NE) return;
+    int n = ext2node[e];
+    ext[3 * e] = v[3 * (size_t)n]; ext[3 * e + 1] = v[3 * (size_t)n + 1]; ext[3 * e + 2] = v[3 * (size_t)n + 2];
+}
+__global__ void k_zero(int64_t n, double *p)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+// x~ = y + h ydot + h^2 g on FEM nodes and body translation nodes; y + h ydot on A nodes
+__global__ void k_predict(int N, const int *__restrict__ kind, const int *__restrict__ node_scene, const int *__restrict__ is_trans,
+                          const double *__restrict__ sparam, const double *__restrict__ grav, const double *__restrict__ y,
+                          const double *__restrict__ yd, double *__restrict__ xt)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    int s = node_scene[n];
+    double h = sparam[8 * s + P_H];
+    bool gv = kind[n] == 0 || (kind[n] == 1 && is_trans[n]);
+    for (int k = 0; k < 3; ++k) {
+        double v = y[3 * (size_t)n + k] + h * yd[3 * (size_t)n + k];
+        if (gv) v += h * h * grav[3 * s + k];
+        xt[3 * (size_t)n + k] = v;
+    }
+}
+__global__ void k_negate(int64_t n, const double *__restrict__ a, double *__restrict__ b)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = -a[i];
+}
+// yt = y + alpha_s p (alpha from the scene's line-search slot, 0 when off)
+__global__ void k_trial(int N, const int *__restrict__ node_scene, const double *__restrict__ scal, const double *__restrict__ y,
+                        const double *__restrict__ p, double *__restrict__ yt)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    int s = node_scene[n];
+    const double *S = scal + (size_t)s * NSLOT;
+    double a = S[S_LS_ON] != 0.0 ? S[S_LS_ALPHA] : 0.0;
+    for (int k = 0; k < 3; ++k) yt[3 * (size_t)n + k] = y[3 * (size_t)n + k] + a * p[3 * (size_t)n + k];
+}
+__global__ void k_velocity(int N, const int *__restrict__ node_scene, const double *__restrict__ sparam, const double *__restrict__ y,
+                           const double *__restrict__ y0, double *__restrict__ yd)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double h = sparam[8 * node_scene[n] + P_H];
+    for (int k = 0; k < 3; ++k) yd[3 * (size_t)n + k] = (y[3 * (size_t)n + k] - y0[3 * (size_t)n + k]) / h;
+}
+// Newton measure: largest world displacement of p (FEM DOFs; bodies through
+// their box corners), one partial max per wavefront / per body
+__global__ void k_measure_nodes(int N, const int *__restrict__ kind, const double *__restrict__ p, double *__restrict__ part)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double m = 0.0;
+    if (n < N && kind[n] == 0) m = fmax(fabs(p[3 * (size_t)n]), fmax(fabs(p[3 * (size_t)n + 1]), fabs(p[3 * (size_t)n + 2])));
+    m = wave_max(m);
+    if ((threadIdx.x & (TILE - 1)) == 0 && n < N) part[n / TILE] = m;
+}
+__global__ void k_measure_bodies(int NB, const int *__restrict__ node0, const double *__restrict__ ext, const double *__restrict__ p,
+                                 double *__restrict__ part)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= NB) return;
+    const double *q = p + 3 * (size_t)node0[b], *e = ext + 3 * (size_t)b;
+    double m = 0.0;
+    for (int k = 0; k < 3; ++k) m = fmax(m, fabs(q[k]) + e[0] * fabs(q[3 + k]) + e[1] * fabs(q[6 + k]) + e[2] * fabs(q[9 + k]));
+    part[b] = m;
+}
+__global__ void k_set_slot(int ns, double *scal, int slot, double v)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) scal[(size_t)s * NSLOT + slot] = v;
+}
+__global__ void k_gather_slot(int ns, const double *scal, int slot, double *out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) out[s] = scal[(size_t)s * NSLOT + slot];
+}
+__global__ void k_copy_int(int n, const int *a, int *b)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+__global__ void k_inf_to_scal(int ns, int *flag, double *scal)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    scal[(size_t)s * NSLOT + S_INF] = flag[s] ? 1.0 : 0.0;
+    if (flag[s]) scal[(size_t)s * NSLOT + S_E] = INFINITY;
+}
+
+// ---- host helpers --------------------------------------------------------------
+void sync(ipc_ctx *c) { IPC_HIP(hipStreamSynchronize(c->stream)); }
+
+std::vector<double> read_scal(ipc_ctx *c)
+{
+    std::vector<double> h((size_t)c->n_scenes * NSLOT);
+    IPC_HIP(hipMemcpyAsync(h.data(), c->d.scal.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    return h;
+}
+void write_scal(ipc_ctx *c, const std::vector<double> &h)
+{
+    // staged through a context-owned buffer so the source outlives the copy
+    c->h_scal_stage = h;
+    IPC_HIP(hipMemcpyAsync(c->d.scal.p, c->h_scal_stage.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    sync(c);
+}
+
+void upload_seg_region(ipc_ctx *c, int region, const std::vector<int> &h)
+{
+    c->h_seg_stage = h;
+    IPC_HIP(hipMemcpyAsync(seg_ptr(c, region), c->h_seg_stage.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    sync(c);
+}
+
+void setup_after_create(ipc_ctx *c)
+{
+    Dev &D = c->d;
+    int ns = c->n_scenes;
+    std::vector<double> sp(8 * (size_t)ns, 0.0), h2(ns), grav(3 * (size_t)ns), lo(6 * (size_t)ns);
+    std::vector<int> maxpcg(ns);
+    for (int s = 0; s < ns; ++s) {
+        SceneInfo &S = c->sc[s];
+        sp[8 * s + P_H2] = S.h * S.h; sp[8 * s + P_KAPPA] = S.kappa; sp[8 * s + P_DHAT] = S.dhat; sp[8 * s + P_MU] = S.mu;
+        sp[8 * s + P_EPSH] = S.eps_v * S.h; sp[8 * s + P_CCDS] = S.ccd_s; sp[8 * s + P_H] = S.h;
+        h2[s] = S.h * S.h;
+        for (int k = 0; k < 3; ++k) grav[3 * s + k] = S.g[k];
+        maxpcg[s] = S.max_pcg;
+    }
+    D.sparam.upload(sp, c->stream); D.h2s.upload(h2, c->stream); D.grav.upload(grav, c->stream); D.maxpcg.upload(maxpcg, c->stream);
+    // Morton boxes: initial world bounds of each scene's contact vertices, enlarged
+    {
+        launch_world(c, D.y.p, D.xw.p);
+        std::vector<double> xw(3 * (size_t)c->CV);
+        if (c->CV) IPC_HIP(hipMemcpyAsync(xw.data(), D.xw.p, xw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        sync(c);
+        for (int s = 0; s < ns; ++s) {
+            SceneInfo &S = c->sc[s];
+            double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int i = S.cv0; i < S.cv0 + S.ncv; ++i)
+                for (int k = 0; k < 3; ++k) { l[k] = std::min(l[k], xw[3 * i + k]); h[k] = std::max(h[k], xw[3 * i + k]); }
+            for (int k = 0; k < 3; ++k) {
+                if (!(h[k] >= l[k])) { l[k] = 0.0; h[k] = 1.0; }
+                double ext = std::max(h[k] - l[k], 1e-3), m = 0.25 * ext;
+                lo[6 * s + k] = l[k] - m;
+                lo[6 * s + 3 + k] = 1023.0 / (ext + 2.0 * m);
+            }
+        }
+        D.scene_lo.upload(lo, c->stream);
+    }
+    std::vector<int> is_trans(c->N, 0);
+    for (int s = 0; s < ns; ++s) {
+        SceneInfo &S = c->sc[s];
+        for (int b = 0; b < S.nb; ++b) is_trans[S.node0 + S.nv + 4 * b] = 1;
+    }
+    D.is_trans.upload(is_trans, c->stream);
+    for (auto *b : {&D.inf_flag, &D.ls_active, &D.pcg_active, &D.pcg_iters, &D.newton_on}) b->alloc(ns);
+    D.part_node2.alloc(c->N / TILE + 1);
+    D.segs.alloc((size_t)NREGION * (ns + 1));
+    D.segs.zero(c->stream, (size_t)NREGION * (ns + 1));
+    std::vector<int> nodew(ns + 1), tetw(ns + 1);
+    for (int s = 0; s < ns; ++s) { nodew[s] = c->sc[s].node0 / TILE; tetw[s] = c->sc[s].tet0 / TILE; }
+    nodew[ns] = c->N / TILE; tetw[ns] = c->T / TILE;
+    upload_seg_region(c, R_NODEW, nodew);
+    upload_seg_region(c, R_TETW, tetw);
+    upload_seg_region(c, R_BODY, c->seg_body);
+    upload_seg_region(c, R_SP, c->seg_sp);
+    upload_seg_region(c, R_SURF, c->seg_surf);
+    upload_seg_region(c, R_TRI, c->seg_tri);
+    upload_seg_region(c, R_EDGE, c->seg_edge);
+    sync(c);
+}
+
+// ---- potential evaluation --------------------------------------------------------
+// Energy per scene into S_E (and the per-term slots).  The barrier runs over
+// the candidate lists (from_candidates) or over the active pairs.
+void eval_energy(ipc_ctx *c, const double *y, bool from_candidates)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    launch_world(c, y, D.xw.p);
+    hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
+    launch_node_inertia(c, y, nullptr, D.part_node.p);
+    launch_fem(c, 0, y, nullptr, false, D.part_tet.p, D.h2s.p);
+    launch_body(c, 0, y, nullptr, false, D.body_part.p, D.h2s.p);
+    launch_spring(c, 0, y, nullptr, D.sp_part.p, D.h2s.p);
+    launch_barrier(c, 0, from_candidates, D.xw.p, nullptr, false);
+    if (c->fr_on) launch_friction(c, 0, D.xw.p, nullptr);
+    int64_t npt = from_candidates ? c->n_cand_pt : c->n_pt, nee = from_candidates ? c->n_cand_ee : c->n_ee;
+    RedArgs a{};
+    a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = S_E_IN;
+    a.src[a.nsrc] = src(c->T ? D.part_tet.p : nullptr, seg_ptr(c, R_TETW), 0, 0); a.slots[a.nsrc++] = S_E_FEM;
+    a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = S_E_ABD;
+    a.src[a.nsrc] = src(c->NS ? D.sp_part.p : nullptr, seg_ptr(c, R_SP), 0, 0); a.slots[a.nsrc++] = S_E_SP;
+    a.src[a.nsrc++] = src(npt ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CPT : R_PT), 0, 0);
+    a.src[a.nsrc++] = src(nee ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CEE : R_EE), (int)npt, 0);
+    if (c->fr_on) {
+        a.src[a.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
+        a.src[a.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
+    }
+    a.slot = S_E;
+    reduce(c, a);
+    // barrier and friction terms for reporting
+    RedArgs b{};
+    b.src[b.nsrc++] = src(npt ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CPT : R_PT), 0, 0);
+    b.src[b.nsrc++] = src(nee ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CEE : R_EE), (int)npt, 0);
+    b.slot = S_E_BAR;
+    reduce(c, b);
+    RedArgs f{};
+    if (c->fr_on) {
+        f.src[f.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
+        f.src[f.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
+    }
+    f.slot = S_E_FR;
+    reduce(c, f);
+    hipLaunchKernelGGL(k_inf_to_scal, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.inf_flag.p, D.scal.p);
+}
+
+// Gradient into g (internal layout) and, with hess, the projected (or not)
+// Hessian: FEM block-CSR values, body blocks, contact blocks, friction blocks
+// and the diagonal accumulators of the preconditioner.  Pairs must be current.
+void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool project)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    launch_world(c, y, D.xw.p);
+    if (hess) {
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(9 * (int64_t)c->N)), dim3(BLOCK), 0, st, 9 * (int64_t)c->N, D.diagF.p);
+        if (c->NB) hipLaunchKernelGGL(k_zero, dim3(blocks_for(144 * (int64_t)c->NB)), dim3(BLOCK), 0, st, 144 * (int64_t)c->NB, D.diagB.p);
+        launch_bsr_init(c);
+    }
+    hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
+    launch_node_inertia(c, y, g, D.part_node.p);
+    launch_body(c, hess ? 2 : 1, y, g, project, D.body_part.p, D.h2s.p);
+    launch_fem(c, hess ? 2 : 1, y, g, project, D.part_tet.p, D.h2s.p);
+    launch_spring(c, 1, y, g, D.sp_part.p, D.h2s.p);
+    launch_barrier(c, hess ? 2 : 1, false, D.xw.p, g, project);
+    if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p, g);
+}
+
+// Active pairs at internal y from a static broad phase.
+void pairs_from_scratch(ipc_ctx *c, const double *y)
+{
+    launch_world(c, y, c->d.xw.p);
+    broad_phase(c, c->d.xw.p, nullptr);
+    store_cand_segs(c);
+    narrow_phase(c, c->d.xw.p);
+    store_pair_segs(c);
+}
+
+void begin_step_impl(ipc_ctx *c, const double *targets_dev)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    if (targets_dev && c->ND)
+        IPC_HIP(hipMemcpyAsync(D.targets.p, targets_dev, 12 * (size_t)c->ND * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_predict, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.node_scene.p, D.is_trans.p,
+                       D.sparam.p, D.grav.p, D.y.p, D.ydot.p, D.xt.p);
+    pairs_from_scratch(c, D.y.p);
+    launch_lag(c, D.xw.p);
+    c->n_lag_pt = c->n_pt;
+    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_PT), seg_ptr(c, R_LPT));
+    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_EE), seg_ptr(c, R_LEE));
+    c->step_ready = true;
+}
+
+} // namespace
+
+// segment tables computed by the broad / narrow phase live in host vectors;
+// mirror them into the device regions used by the reductions
+void store_cand_segs(ipc_ctx *c)
+{
+    upload_seg_region(c, R_CPT, c->h_cand_pt_seg);
+    upload_seg_region(c, R_CEE, c->h_cand_ee_seg);
+}
+void store_pair_segs(ipc_ctx *c)
+{
+    upload_seg_region(c, R_PT, c->h_pt_seg);
+    upload_seg_region(c, R_EE, c->h_ee_seg);
+}
+
+int *upload_seg(ipc_ctx *c, const std::vector<int> &seg, int which)
+{
+    int region = which == 0 ? R_PSEG : R_QSEG;
+    upload_seg_region(c, region, seg);
+    return seg_ptr(c, region);
+}
+
+__global__ void k_fill_int_api(int n, int *p, int v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+} // namespace ipc
+
+using namespace ipc;
+
+// ---------------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------------
+template <class F>
+static int guard(ipc_ctx *c, F f)
+{
+    try {
+        f();
+        return IPC_OK;
+    } catch (const Error &e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        if (c) c->err = e.what();
+        return IPC_E_DEVICE;
+    } catch (...) {
+        if (c) c->err = "unknown error";
+        return IPC_E_DEVICE;
+    }
+}
+
+extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_stream, ipc_ctx **out)
+{
+    if (!out) return IPC_E_INVALID;
+    *out = nullptr;
+    if (!scenes || n_scenes < 1) { g_create_error = "need at least one scene"; return IPC_E_INVALID; }
+    ipc_ctx *c = new ipc_ctx;
+    c->stream = (hipStream_t)hip_stream;
+    int rc = guard(c, [&] {
+        create_context(c, scenes, n_scenes);
+        setup_after_create(c);
+    });
+    if (rc != IPC_OK) {
+        g_create_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return IPC_OK;
+}
+
+extern "C" int ipc_destroy(ipc_ctx *c)
+{
+    if (!c) return IPC_E_INVALID;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return IPC_OK;
+}
+
+extern "C" const char *ipc_last_error(const ipc_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
+{
+    if (!c || !v) return IPC_E_INVALID;
+    switch (what) {
+    case IPC_Q_NDOF: *v = c->ndof; return IPC_OK;
+    case IPC_Q_NSCENES: *v = c->n_scenes; return IPC_OK;
+    case IPC_Q_NDRIVEN: *v = c->ND; return IPC_OK;
+    case IPC_Q_NTRI: *v = c->TRI; return IPC_OK;
+    case IPC_Q_NEDGE: *v = c->EDGE; return IPC_OK;
+    case IPC_Q_NNODES: *v = c->N; return IPC_OK;
+    case IPC_Q_NTETS: *v = c->T; return IPC_OK;
+    }
+    return IPC_E_INVALID;
+}
+
+extern "C" int ipc_scene_scalars(const ipc_ctx *c, int s, double *kappa, double *L, double *thr)
+{
+    if (!c || s < 0 || s >= c->n_scenes) return IPC_E_INVALID;
+    if (kappa) *kappa = c->sc[s].kappa;
+    if (L) *L = c->sc[s].L;
+    if (thr) *thr = c->sc[s].thr;
+    return IPC_OK;
+}
+
+extern "C" int ipc_get_state(ipc_ctx *c, double *y_dev, double *ydot_dev)
+{
+    if (!c || !y_dev) return IPC_E_INVALID;
+    return guard(c, [&] {
+        hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, c->stream, c->ext_nodes, c->d.ext2node.p,
+                           c->d.y.p, y_dev);
+        if (ydot_dev)
+            hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, c->stream, c->ext_nodes,
+                               c->d.ext2node.p, c->d.ydot.p, ydot_dev);
+        IPC_HIP(hipGetLastError());
+    });
+}
+
+extern "C" int ipc_set_state(ipc_ctx *c, const double *y_dev, const double *ydot_dev)
+{
+    if (!c || !y_dev || !ydot_dev) return IPC_E_INVALID;
+    return guard(c, [&] {
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, c->stream, c->ext_nodes, c->d.ext2node.p,
+                           y_dev, c->d.y.p);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, c->stream, c->ext_nodes, c->d.ext2node.p,
+                           ydot_dev, c->d.ydot.p);
+        IPC_HIP(hipGetLastError());
+        c->step_ready = false;
+    });
+}
+
+extern "C" int ipc_begin_step(ipc_ctx *c, const double *targets_dev)
+{
+    if (!c) return IPC_E_INVALID;
+    if (c->ND && !targets_dev) { c->err = "targets required: the scenes have driven links"; return IPC_E_INVALID; }
+    return guard(c, [&] { begin_step_impl(c, targets_dev); });
+}
+
+extern "C" int ipc_energy_grad_hess(ipc_ctx *c, const double *y_dev, double *E_dev, double *g_dev, const double *v_dev, double *Hv_dev,
+                                    uint32_t flags)
+{
+    if (!c || !y_dev) return IPC_E_INVALID;
+    if (!c->step_ready) { c->err = "call ipc_begin_step first"; return IPC_E_INVALID; }
+    int status = IPC_OK;
+    int rc = guard(c, [&] {
+        Dev &D = c->d;
+        hipStream_t st = c->stream;
+        c->fr_on = (flags & IPC_WITH_FRICTION) != 0;
+        double *y = D.v2.p;
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, y);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, y_dev, y);
+        pairs_from_scratch(c, y);
+        if (E_dev) {
+            eval_energy(c, y, false);
+            hipLaunchKernelGGL(k_gather_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_E, E_dev);
+        }
+        bool hv = v_dev && Hv_dev;
+        if (g_dev || hv) {
+            eval_grad_hess(c, y, D.g.p, hv, (flags & IPC_PSD_PROJECT) != 0);
+            if (g_dev)
+                hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, D.g.p,
+                                   g_dev);
+        }
+        if (hv) {
+            hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.v1.p);
+            hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, v_dev, D.v1.p);
+            hess_apply(c, D.v1.p, D.q.p, nullptr, false);
+            hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, D.q.p, Hv_dev);
+        }
+        std::vector<int> inf(c->n_scenes);
+        IPC_HIP(hipMemcpyAsync(inf.data(), D.inf_flag.p, c->n_scenes * sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        for (int s = 0; s < c->n_scenes; ++s) if (inf[s]) status = IPC_E_INTERSECTING;
+        c->fr_on = true;
+    });
+    return rc != IPC_OK ? rc : status;
+}
+
+extern "C" int ipc_get_pairs(ipc_ctx *c, const double *y_dev, int scene, int32_t *pt_host, int32_t *ee_host, int64_t cap, int64_t *n_pt,
+                             int64_t *n_ee)
+{
+    if (!c || !y_dev || scene < 0 || scene >= c->n_scenes || !n_pt || !n_ee) return IPC_E_INVALID;
+    int status = IPC_OK;
+    int rc = guard(c, [&] {
+        Dev &D = c->d;
+        hipStream_t st = c->stream;
+        double *y = D.v2.p;
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, y);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, y_dev, y);
+        pairs_from_scratch(c, y);
+        SceneInfo &S = c->sc[scene];
+        int a0 = c->h_pt_seg[scene], a1 = c->h_pt_seg[scene + 1], b0 = c->h_ee_seg[scene], b1 = c->h_ee_seg[scene + 1];
+        *n_pt = a1 - a0; *n_ee = b1 - b0;
+        if (*n_pt > cap || *n_ee > cap) { status = IPC_E_CAPACITY; return; }
+        std::vector<int2> hp(a1 - a0), he(b1 - b0);
+        if (a1 > a0) IPC_HIP(hipMemcpyAsync(hp.data(), D.pt.p + a0, hp.size() * sizeof(int2), hipMemcpyDeviceToHost, st));
+        if (b1 > b0) IPC_HIP(hipMemcpyAsync(he.data(), D.ee.p + b0, he.size() * sizeof(int2), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        std::vector<std::array<int, 4>> P, E;
+        for (auto &q : hp) {
+            int t = q.y - S.tri0;
+            P.push_back({S.surf_ext[q.x - S.cv0], S.tri_ext[3 * t], S.tri_ext[3 * t + 1], S.tri_ext[3 * t + 2]});
+        }
+        for (auto &q : he) {
+            int e = q.x - S.edge0, f = q.y - S.edge0;
+            E.push_back({S.edge_ext[2 * e], S.edge_ext[2 * e + 1], S.edge_ext[2 * f], S.edge_ext[2 * f + 1]});
+        }
+        std::sort(P.begin(), P.end());
+        std::sort(E.begin(), E.end());
+        for (size_t k = 0; k < P.size(); ++k) for (int m = 0; m < 4; ++m) pt_host[4 * k + m] = P[k][m];
+        for (size_t k = 0; k < E.size(); ++k) for (int m = 0; m < 4; ++m) ee_host[4 * k + m] = E[k][m];
+    });
+    return rc != IPC_OK ? rc : status;
+}
+
+extern "C" int ipc_ccd(ipc_ctx *c, const double *y_dev, const double *p_dev, double *alpha_dev)
+{
+    if (!c || !y_dev || !p_dev || !alpha_dev) return IPC_E_INVALID;
+    return guard(c, [&] {
+        Dev &D = c->d;
+        hipStream_t st = c->stream;
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.v2.p);
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.v1.p);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, y_dev, D.v2.p);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, p_dev, D.v1.p);
+        hipLaunchKernelGGL(k_set_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_LS_ON, 1.0);
+        hipLaunchKernelGGL(k_set_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_LS_ALPHA, 1.0);
+        hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.v2.p, D.v1.p, D.yt.p);
+        launch_world(c, D.v2.p, D.xw.p);
+        launch_world(c, D.yt.p, D.xw1.p);
+        broad_phase(c, D.xw.p, D.xw1.p);
+        store_cand_segs(c);
+        hipLaunchKernelGGL(k_set_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_CCD, 1.0);
+        hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.ls_active.p, 1);
+        launch_ccd(c, D.xw.p, D.xw1.p);
+        hipLaunchKernelGGL(k_gather_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_CCD, alpha_dev);
+        IPC_HIP(hipStreamSynchronize(st));
+    });
+}
+
+extern "C" int ipc_pcg(ipc_ctx *c, const double *y_dev, const double *b_dev, double *x_dev, double eta, int32_t *iters_host)
+{
+    if (!c || !y_dev || !b_dev || !x_dev) return IPC_E_INVALID;
+    if (!c->step_ready) { c->err = "call ipc_begin_step first"; return IPC_E_INVALID; }
+    return guard(c, [&] {
+        Dev &D = c->d;
+        hipStream_t st = c->stream;
+        double *y = D.y0.p;   // y0 is free outside ipc_step
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, y);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, y_dev, y);
+        pairs_from_scratch(c, y);
+        eval_grad_hess(c, y, D.g.p, true, true);
+        build_preconditioner(c);
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.v1.p);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, b_dev, D.v1.p);
+        pcg_solve(c, D.v1.p, D.x.p, eta, nullptr);
+        hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, D.x.p, x_dev);
+        if (iters_host) IPC_HIP(hipMemcpyAsync(iters_host, D.pcg_iters.p, c->n_scenes * sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+    });
+}
+
+// ---------------------------------------------------------------------------------
+// the Newton step
+// ---------------------------------------------------------------------------------
+namespace ipc {
+
+void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    int ns = c->n_scenes;
+    begin_step_impl(c, targets_dev);
+    c->fr_on = true;
+    IPC_HIP(hipMemcpyAsync(D.y0.p, D.y.p, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<ipc_stats> S(ns);
+    for (int s = 0; s < ns; ++s) {
+        std::memset(&S[s], 0, sizeof(ipc_stats));
+        S[s].status = IPC_E_NOT_CONVERGED;
+        S[s].alpha_min = 1.0;
+        S[s].n_lag = 0;
+    }
+    for (int s = 0; s < ns; ++s) S[s].n_lag = c->h_lag_seg.empty() ? 0 : 0;
+    std::vector<int> on(ns, 1);
+    // energy at the start
+    eval_energy(c, D.y.p, false);
+    std::vector<double> sc = read_scal(c);
+    std::vector<double> E0(ns);
+    for (int s = 0; s < ns; ++s) {
+        E0[s] = sc[(size_t)s * NSLOT + S_E];
+        if (sc[(size_t)s * NSLOT + S_INF] != 0.0) { S[s].status = IPC_E_INTERSECTING; on[s] = 0; }
+        S[s].energy = E0[s];
+        S[s].n_lag = (c->h_pt_seg[s + 1] - c->h_pt_seg[s]) + (c->h_ee_seg[s + 1] - c->h_ee_seg[s]);
+    }
+    int max_newton = 0;
+    for (auto &si : c->sc) max_newton = std::max(max_newton, si.max_newton);
+    std::vector<int> want(ns);
+    for (int j = 0; j < max_newton; ++j) {
+        bool any = false;
+        for (int s = 0; s < ns; ++s) {
+            if (on[s] && j >= c->sc[s].max_newton) on[s] = 0;
+            any |= on[s] != 0;
+        }
+        if (!any) break;
+        for (int s = 0; s < ns; ++s) {
+            S[s].n_pt_max = std::max(S[s].n_pt_max, c->h_pt_seg[s + 1] - c->h_pt_seg[s]);
+            S[s].n_ee_max = std::max(S[s].n_ee_max, c->h_ee_seg[s + 1] - c->h_ee_seg[s]);
+        }
+        // assemble and solve H p = -g for the scenes still iterating
+        eval_grad_hess(c, D.y.p, D.g.p, true, true);
+        build_preconditioner(c);
+        hipLaunchKernelGGL(k_negate, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.g.p, D.v1.p);
+        c->h_int_stage = on;
+        IPC_HIP(hipMemcpyAsync(D.newton_on.p, c->h_int_stage.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+        std::vector<double> eta(ns);
+        for (int s = 0; s < ns; ++s) eta[s] = c->sc[s].pcg_tol;
+        sc = read_scal(c);
+        for (int s = 0; s < ns; ++s) sc[(size_t)s * NSLOT + S_ETA] = eta[s];
+        write_scal(c, sc);
+        pcg_solve(c, D.v1.p, D.x.p, -1.0, D.newton_on.p);
+        std::vector<int> it(ns);
+        IPC_HIP(hipMemcpyAsync(it.data(), D.pcg_iters.p, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+        // Newton measure
+        hipLaunchKernelGGL(k_measure_nodes, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.x.p, D.part_node.p);
+        if (c->NB)
+            hipLaunchKernelGGL(k_measure_bodies, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.bext.p, D.x.p,
+                               D.body_part.p);
+        {
+            RedArgs a{};
+            a.op = 1;
+            a.src[a.nsrc++] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0);
+            a.src[a.nsrc++] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0);
+            a.slot = S_NEWTON_MAX;
+            reduce(c, a);
+        }
+        sc = read_scal(c);
+        any = false;
+        for (int s = 0; s < ns; ++s) {
+            if (!on[s]) continue;
+            S[s].newton_iters = j + 1;
+            S[s].pcg_iters_total += it[s];
+            S[s].pcg_iters_max = std::max(S[s].pcg_iters_max, it[s]);
+            if (sc[(size_t)s * NSLOT + S_NEWTON_MAX] <= c->sc[s].thr) { on[s] = 0; S[s].status = IPC_OK; }
+            any |= on[s] != 0;
+        }
+        if (!any) break;
+        // CCD over the swept candidates of [y, y + p]
+        for (int s = 0; s < ns; ++s) {
+            sc[(size_t)s * NSLOT + S_LS_ON] = on[s] ? 1.0 : 0.0;
+            sc[(size_t)s * NSLOT + S_LS_ALPHA] = 1.0;
+            sc[(size_t)s * NSLOT + S_CCD] = 1.0;
+        }
+        write_scal(c, sc);
+        hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
+        launch_world(c, D.y.p, D.xw.p);
+        launch_world(c, D.yt.p, D.xw1.p);
+        broad_phase(c, D.xw.p, D.xw1.p);
+        store_cand_segs(c);
+        for (int s = 0; s < ns; ++s) S[s].n_cand_max = std::max(S[s].n_cand_max, (c->h_cand_pt_seg[s + 1] - c->h_cand_pt_seg[s]) +
+                                                                             (c->h_cand_ee_seg[s + 1] - c->h_cand_ee_seg[s]));
+        c->h_int_stage = on;
+        IPC_HIP(hipMemcpyAsync(D.ls_active.p, c->h_int_stage.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+        launch_ccd(c, D.xw.p, D.xw1.p);
+        sc = read_scal(c);
+        std::vector<double> alpha(ns, 0.0);
+        std::vector<int> ls(ns, 0);
+        for (int s = 0; s < ns; ++s) {
+            if (!on[s]) continue;
+            alpha[s] = std::min(1.0, sc[(size_t)s * NSLOT + S_CCD]);
+            ls[s] = 1;
+        }
+        // backtracking: halve each scene's step until its energy does not increase
+        std::vector<double> Eacc(ns, 0.0);
+        for (int h = 0; h <= 40; ++h) {
+            bool pending = false;
+            for (int s = 0; s < ns; ++s) {
+                sc[(size_t)s * NSLOT + S_LS_ON] = on[s] ? 1.0 : 0.0;
+                sc[(size_t)s * NSLOT + S_LS_ALPHA] = alpha[s];
+                pending |= ls[s] != 0;
+            }
+            if (!pending) break;
+            write_scal(c, sc);
+            hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
+            eval_energy(c, D.yt.p, true);
+            sc = read_scal(c);
+            for (int s = 0; s < ns; ++s) {
+                if (!ls[s]) continue;
+                double E1 = sc[(size_t)s * NSLOT + S_E];
+                if (E1 <= E0[s]) { ls[s] = 0; Eacc[s] = E1; }
+                else if (h == 40) { ls[s] = 0; on[s] = 0; S[s].status = IPC_E_LINESEARCH; alpha[s] = 0.0; }
+                else alpha[s] *= 0.5;
+            }
+        }
+        // accept: y <- y + alpha p (alpha = 0 for scenes that stopped)
+        for (int s = 0; s < ns; ++s) {
+            sc[(size_t)s * NSLOT + S_LS_ON] = alpha[s] > 0.0 ? 1.0 : 0.0;
+            sc[(size_t)s * NSLOT + S_LS_ALPHA] = alpha[s];
+            if (alpha[s] > 0.0) {
+                E0[s] = Eacc[s];
+                S[s].energy = Eacc[s];
+                S[s].alpha_min = std::min(S[s].alpha_min, alpha[s]);
+            }
+        }
+        write_scal(c, sc);
+        hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
+        IPC_HIP(hipMemcpyAsync(D.y.p, D.yt.p, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // pairs at the new iterate from the swept candidates (a superset)
+        launch_world(c, D.y.p, D.xw.p);
+        narrow_phase(c, D.xw.p);
+        store_pair_segs(c);
+    }
+    hipLaunchKernelGGL(k_velocity, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.sparam.p, D.y.p, D.y0.p, D.ydot.p);
+    IPC_HIP(hipStreamSynchronize(st));
+    c->step_ready = false;
+    if (stats) for (int s = 0; s < ns; ++s) stats[s] = S[s];
+    c->last_status = IPC_OK;
+    for (int s = 0; s < ns; ++s) if (S[s].status != IPC_OK) { c->last_status = S[s].status; break; }
+}
+
+} // namespace ipc
+
+extern "C" int ipc_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats_host)
+{
+    if (!c) return IPC_E_INVALID;
+    if (c->ND && !targets_dev) { c->err = "targets required: the scenes have driven links"; return IPC_E_INVALID; }
+    int rc = guard(c, [&] { newton_step(c, targets_dev, stats_host); });
+    if (rc != IPC_OK) return rc;
+    if (c->last_status != IPC_OK) c->err = "a scene did not finish its step cleanly (see ipc_stats.status)";
+    return c->last_status;
+}

@@ -1,0 +1,946 @@
+// Contact: world positions, LBVH broad phase, narrow phase, IPC log-barrier,
+// lagged friction, contact Hessian products and additive CCD
+// (Sec. III-C.1, "barrier potentials together with continuous collision
+// detection"; Eq. (3) E_barrier and E_friction).
+//
+// Broad phase: one linear BVH per scene and primitive kind (triangles for
+// point-triangle queries, edges for edge-edge queries), built in a single
+// launch sequence over all scenes: Morton keys carry the scene id in their
+// high bits so one radix sort groups the scenes; the Karras hierarchy is
+// built per scene segment; boxes are refitted bottom-up with arrival
+// counters; queries traverse only their own scene's tree.  Candidates are
+// compacted with count / exclusive-scan / write passes, which keeps their
+// order deterministic.  The narrow phase keeps a candidate when d^2 < dhat^2
+// and compacts the survivors with a wavefront ballot and a scan over
+// per-wavefront counts.
+#include <hipcub/hipcub.hpp>
+
+#include "ipc_device.h"
+#include "ipc_internal.h"
+#include "ipc_kernels.h"
+
+namespace ipc {
+
+// ---------------------------------------------------------------------------
+// world positions of contact vertices (exact operation order)
+// ---------------------------------------------------------------------------
+__global__ void k_world(int CV, const double *__restrict__ y, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
+                        const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ xw)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= CV) return;
+    int n = cv_node[i];
+    d3 x;
+    if (n >= 0) x = ld3(y, n);
+    else {
+        int b = cv_body[i];
+        d3 xb = ld3(cv_x, i);
+        if (b >= 0) {
+            int n0 = body_node0[b];
+            x = xaffine(ld3(y, n0), ld3(y, n0 + 1), ld3(y, n0 + 2), ld3(y, n0 + 3), xb);
+        } else x = xb;
+    }
+    st3(xw, i, x);
+}
+
+void launch_world(ipc_ctx *c, const double *y, double *xw)
+{
+    if (c->CV == 0) return;
+    hipLaunchKernelGGL(k_world, dim3(blocks_for(c->CV)), dim3(BLOCK), 0, c->stream, c->CV, y, c->d.cv_node.p, c->d.cv_body.p,
+                       c->d.cv_x.p, c->d.body_node0.p, xw);
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void box_of(const double *xw0, const double *xw1, const int *v, int nv, double r, double *b)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < nv; ++k) {
+        d3 p = ld3(xw0, v[k]);
+        lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
+        hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
+        if (xw1) {
+            d3 q = ld3(xw1, v[k]);
+            lo[0] = fmin(lo[0], q.x); lo[1] = fmin(lo[1], q.y); lo[2] = fmin(lo[2], q.z);
+            hi[0] = fmax(hi[0], q.x); hi[1] = fmax(hi[1], q.y); hi[2] = fmax(hi[2], q.z);
+        }
+    }
+    for (int k = 0; k < 3; ++k) { b[k] = lo[k] - r; b[3 + k] = hi[k] + r; }
+}
+
+__device__ __forceinline__ bool overlap(const double *a, const double *b)
+{
+    return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
+}
+
+__device__ __forceinline__ bool allowed(int oa, int ob, const int *okind, const int *excl, int nex)
+{
+    int ka = oa >= 0 ? okind[oa] : 2, kb = ob >= 0 ? okind[ob] : 2;
+    if (ka == 2 && kb == 2) return false;
+    if (oa == ob && ka == 1) return false;
+    for (int i = 0; i < nex; ++i) {
+        int a = excl[2 * i], b = excl[2 * i + 1];
+        if ((a == oa && b == ob) || (a == ob && b == oa)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ unsigned int expand_bits(unsigned int v)
+{
+    v = (v * 0x00010001u) & 0xFF0000FFu;
+    v = (v * 0x00000101u) & 0x0F00F00Fu;
+    v = (v * 0x00000011u) & 0xC30C30C3u;
+    v = (v * 0x00000005u) & 0x49249249u;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// LBVH
+// ---------------------------------------------------------------------------
+// primitive boxes + Morton keys.  kind 0: triangles, 1: edges.
+__global__ void k_prim_box(int P, int kind, const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_scene,
+                           const double *__restrict__ xw0, const double *__restrict__ xw1, const double *__restrict__ sparam,
+                           const double *__restrict__ sbox, double *__restrict__ box, unsigned long long *__restrict__ key,
+                           int *__restrict__ id)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    int v[3], nv, s;
+    if (kind == 0) { int4 t = tri[i]; v[0] = t.x; v[1] = t.y; v[2] = t.z; nv = 3; s = t.w; }
+    else { int2 e = edge[i]; v[0] = e.x; v[1] = e.y; nv = 2; s = cv_scene[e.x]; }
+    double r = kind == 0 ? 0.0 : 0.5 * 1.01 * sparam[8 * s + 2];
+    double b[6];
+    box_of(xw0, xw1, v, nv, r, b);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) box[6 * (size_t)i + k] = b[k];
+    const double *sb = sbox + 6 * (size_t)s;
+    unsigned int q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double cc = (0.5 * (b[k] + b[3 + k]) - sb[k]) * sb[3 + k];
+        cc = fmin(fmax(cc, 0.0), 1023.0);
+        q[k] = (unsigned int)cc;
+    }
+    unsigned int m = (expand_bits(q[0]) << 2) | (expand_bits(q[1]) << 1) | expand_bits(q[2]);
+    key[i] = ((unsigned long long)s << 32) | m;
+    id[i] = i;
+}
+
+__device__ __forceinline__ int lcp(const unsigned long long *key, int base, int n, int a, int b)
+{
+    if (b < 0 || b >= n) return -1;
+    unsigned long long ka = key[base + a], kb = key[base + b];
+    if (ka == kb) return 64 + __clz((unsigned int)(a ^ b));
+    return __clzll(ka ^ kb);
+}
+
+// Karras (2012) internal nodes per scene segment [seg[s], seg[s+1]).
+// Internal node ids share the leaf numbering: node seg[s]+j, j < n-1.
+// Child encoding: >= 0 internal node, < 0 leaf -1-k (k = sorted position).
+__global__ void k_karras(int P, const int *__restrict__ prim_scene_of_sorted, const int *__restrict__ seg,
+                         const unsigned long long *__restrict__ key, int *__restrict__ left, int *__restrict__ right,
+                         int *__restrict__ parent, int *__restrict__ leaf_parent)
+{
+    int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= P) return;
+    int s = prim_scene_of_sorted[gi];
+    int base = seg[s], n = seg[s + 1] - base;
+    int i = gi - base;
+    if (i == 0) parent[gi] = -1;
+    if (n == 1) leaf_parent[gi] = -1;
+    if (i >= n - 1) return;
+    int d = (lcp(key, base, n, i, i + 1) - lcp(key, base, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = lcp(key, base, n, i, i - d);
+    int lmax = 2;
+    while (lcp(key, base, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (lcp(key, base, n, i, i + (l + t) * d) > dmin) l += t;
+    int j = i + l * d;
+    int dnode = lcp(key, base, n, i, j);
+    int sp = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (lcp(key, base, n, i, i + (sp + t) * d) > dnode) sp += t;
+    } while (t > 1);
+    int gamma = i + sp * d + min(d, 0);
+    int lo = min(i, j), hi = max(i, j);
+    int L = (lo == gamma) ? -1 - (base + gamma) : base + gamma;
+    int R = (hi == gamma + 1) ? -1 - (base + gamma + 1) : base + gamma + 1;
+    left[gi] = L;
+    right[gi] = R;
+    if (L < 0) leaf_parent[-1 - L] = gi; else parent[L] = gi;
+    if (R < 0) leaf_parent[-1 - R] = gi; else parent[R] = gi;
+}
+
+__global__ void k_refit(int P, const int *__restrict__ sorted_id, const double *__restrict__ pbox, const int *__restrict__ left,
+                        const int *__restrict__ right, const int *__restrict__ parent, const int *__restrict__ leaf_parent,
+                        int *__restrict__ flag, double *__restrict__ nbox)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    int node = leaf_parent[k];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(flag + node, 1) == 0) return;   // the second arrival merges
+        __threadfence();
+        double b[6];
+        int ch[2] = {left[node], right[node]};
+        for (int m = 0; m < 6; ++m) b[m] = (m < 3) ? INFINITY : -INFINITY;
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const double *cb = ch[c2] < 0 ? pbox + 6 * (size_t)sorted_id[-1 - ch[c2]] : nbox + 6 * (size_t)ch[c2];
+            for (int m = 0; m < 3; ++m) { b[m] = fmin(b[m], cb[m]); b[3 + m] = fmax(b[3 + m], cb[3 + m]); }
+        }
+        for (int m = 0; m < 6; ++m) nbox[6 * (size_t)node + m] = b[m];
+        node = parent[node];
+    }
+}
+
+// Queries.  kind 0: surface vertex vs triangle tree; kind 1: edge vs edge tree.
+// WRITE = false counts, WRITE = true writes at off[q].
+template <bool WRITE>
+__global__ void k_traverse(int Q, int kind, const int2 *__restrict__ qedge, const int *__restrict__ cv_scene,
+                           const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_obj,
+                           const int *__restrict__ okind, const int *__restrict__ excl, int nex, const double *__restrict__ xw0,
+                           const double *__restrict__ xw1, const double *__restrict__ sparam, const int *__restrict__ seg,
+                           const int *__restrict__ sorted_id, const double *__restrict__ pbox, const int *__restrict__ left,
+                           const int *__restrict__ right, const double *__restrict__ nbox, int *__restrict__ count,
+                           const int *__restrict__ off, int2 *__restrict__ out, int *__restrict__ overflow)
+{
+    int qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= Q) return;
+    int qv[2], nq, s;
+    if (kind == 0) { qv[0] = qi; nq = 1; s = cv_scene[qi]; }
+    else { int2 e = qedge[qi]; qv[0] = e.x; qv[1] = e.y; nq = 2; s = cv_scene[e.x]; }
+    double r = 1.01 * sparam[8 * s + 2] * (kind == 0 ? 1.0 : 0.5);
+    double qb[6];
+    box_of(xw0, xw1, qv, nq, r, qb);
+    int oq = cv_obj[qv[0]];
+    int base = seg[s], n = seg[s + 1] - base;
+    int cnt = 0, w = WRITE ? off[qi] : 0;
+    if (n > 0) {
+        int stack[64];
+        int sp = 0;
+        stack[sp++] = (n == 1) ? -1 - base : base;
+        while (sp > 0) {
+            int node = stack[--sp];
+            if (node < 0) {
+                int pid = sorted_id[-1 - node];
+                if (!overlap(qb, pbox + 6 * (size_t)pid)) continue;
+                bool ok;
+                int ob;
+                if (kind == 0) {
+                    int4 t = tri[pid];
+                    ok = qi != t.x && qi != t.y && qi != t.z;
+                    ob = cv_obj[t.x];
+                } else {
+                    int2 f = edge[pid];
+                    ok = pid > qi && qv[0] != f.x && qv[0] != f.y && qv[1] != f.x && qv[1] != f.y;
+                    ob = cv_obj[f.x];
+                }
+                if (ok && allowed(oq, ob, okind, excl, nex)) {
+                    if (WRITE) out[w + cnt] = make_int2(qi, pid);
+                    ++cnt;
+                }
+            } else {
+                if (!overlap(qb, nbox + 6 * (size_t)node)) continue;
+                if (sp + 2 > 64) { atomicOr(overflow, 1); continue; }
+                stack[sp++] = left[node];
+                stack[sp++] = right[node];
+            }
+        }
+    }
+    if (!WRITE) count[qi] = cnt;
+}
+
+__global__ void k_scene_of_sorted(int P, const unsigned long long *__restrict__ key, int *__restrict__ sc)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) sc[i] = (int)(key[i] >> 32);
+}
+
+__global__ void k_fill_int(int n, int *p, int v)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// per-scene segment offsets of a query-ordered output from its exclusive scan
+__global__ void k_seg_from_scan(int n_scenes, const int *__restrict__ qseg, const int *__restrict__ off, int total, int *__restrict__ seg)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_scenes) return;
+    int q = qseg[s];
+    seg[s] = (s == n_scenes) ? total : off[q];
+}
+
+// exclusive scan helper (count[n] -> off[n + 1], off[n] = total)
+static void exclusive_scan(ipc_ctx *c, const int *in, int *out, int n)
+{
+    size_t bytes = 0;
+    IPC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n + 1, c->stream));
+    c->d.sort_tmp.alloc(bytes + 16);
+    IPC_HIP(hipcub::DeviceScan::ExclusiveSum(c->d.sort_tmp.p, bytes, in, out, n + 1, c->stream));
+}
+
+static int read_int(ipc_ctx *c, const int *p)
+{
+    int v = 0;
+    IPC_HIP(hipMemcpyAsync(&v, p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    IPC_HIP(hipStreamSynchronize(c->stream));
+    return v;
+}
+
+static void read_ints(ipc_ctx *c, const int *p, std::vector<int> &v, int n)
+{
+    v.resize(n);
+    IPC_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    IPC_HIP(hipStreamSynchronize(c->stream));
+}
+
+// Build the tree over one primitive kind and run one query kind against it.
+static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1, DBuf<int2> &outbuf, int64_t &cap, int64_t &count,
+                      std::vector<int> &hseg)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    int P = kind == 0 ? c->TRI : c->EDGE;
+    int Q = kind == 0 ? c->NSURF : c->EDGE;
+    const std::vector<int> &pseg = kind == 0 ? c->seg_tri : c->seg_edge;
+    const std::vector<int> &qseg = kind == 0 ? c->seg_surf : c->seg_edge;
+    int ns = c->n_scenes;
+    hseg.assign(ns + 1, 0);
+    count = 0;
+    if (P == 0 || Q == 0) return;
+    D.box.alloc(6 * (size_t)P); D.mkey.alloc(P); D.mkey2.alloc(P); D.mid.alloc(P); D.mid2.alloc(P);
+    D.bvh_left.alloc(P); D.bvh_right.alloc(P); D.bvh_parent.alloc(P); D.bvh_flag.alloc(2 * (size_t)P); D.bvh_box.alloc(6 * (size_t)P);
+    D.qcount.alloc(Q + 1); D.qoff.alloc(Q + 1);
+    hipLaunchKernelGGL(k_prim_box, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, kind, D.tri.p, D.edge.p, D.cv_scene.p, xw0, xw1,
+                       D.sparam.p, D.scene_lo.p, D.box.p, D.mkey.p, D.mid.p);
+    size_t bytes = 0;
+    int end_bit = 32;
+    while ((1 << (end_bit - 32)) < ns) ++end_bit;
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.mkey.p, D.mkey2.p, D.mid.p, D.mid2.p, P, 0, end_bit, st));
+    D.sort_tmp.alloc(bytes + 16);
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.sort_tmp.p, bytes, D.mkey.p, D.mkey2.p, D.mid.p, D.mid2.p, P, 0, end_bit, st));
+    int *pseg_d = upload_seg(c, pseg, 0);
+    int *qseg_d = upload_seg(c, qseg, 1);
+    int *scene_sorted = D.bvh_flag.p + P;   // scratch: scene of each sorted leaf
+    hipLaunchKernelGGL(k_scene_of_sorted, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mkey2.p, scene_sorted);
+    DBuf<int> &leafpar = D.leafpar;
+    leafpar.alloc(P);
+    hipLaunchKernelGGL(k_karras, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, scene_sorted, pseg_d, D.mkey2.p, D.bvh_left.p,
+                       D.bvh_right.p, D.bvh_parent.p, leafpar.p);
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.bvh_flag.p, 0);
+    hipLaunchKernelGGL(k_refit, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mid2.p, D.box.p, D.bvh_left.p, D.bvh_right.p,
+                       D.bvh_parent.p, leafpar.p, D.bvh_flag.p, D.bvh_box.p);
+    DBuf<int> &ovf = D.woff;
+    ovf.alloc(2);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 2, ovf.p, 0);
+    const int2 *qedge = D.edge.p;
+    hipLaunchKernelGGL(k_traverse<false>, dim3(blocks_for(Q, 128)), dim3(128), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
+                       D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
+                       D.bvh_right.p, D.bvh_box.p, D.qcount.p, nullptr, nullptr, ovf.p);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.qcount.p + Q, 0);
+    exclusive_scan(c, D.qcount.p, D.qoff.p, Q);
+    int total = read_int(c, D.qoff.p + Q);
+    if (read_int(c, ovf.p)) throw Error(IPC_E_CAPACITY, "BVH traversal stack overflow");
+    if (total > cap) {
+        cap = (int64_t)(total * 1.5) + 1024;
+        outbuf.alloc(cap);
+    }
+    count = total;
+    hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, 128)), dim3(128), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
+                       D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
+                       D.bvh_right.p, D.bvh_box.p, D.qcount.p, D.qoff.p, outbuf.p, ovf.p);
+    int *sseg = D.seg.p + 2 * (ns + 1);
+    hipLaunchKernelGGL(k_seg_from_scan, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns, qseg_d, D.qoff.p, total, sseg);
+    read_ints(c, sseg, hseg, ns + 1);
+}
+
+void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1)
+{
+    bvh_query(c, 0, xw0, xw1, c->d.cand_pt, c->cap_cand_pt, c->n_cand_pt, c->h_cand_pt_seg);
+    bvh_query(c, 1, xw0, xw1, c->d.cand_ee, c->cap_cand_ee, c->n_cand_ee, c->h_cand_ee_seg);
+}
+
+// ---------------------------------------------------------------------------
+// narrow phase: keep candidates with d^2 < dhat^2 (ballot compaction)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_vertices(int kind, int2 p, const int4 *tri, const int2 *edge, int *cv)
+{
+    if (kind == 0) { int4 t = tri[p.y]; cv[0] = p.x; cv[1] = t.x; cv[2] = t.y; cv[3] = t.z; }
+    else { int2 a = edge[p.x], b = edge[p.y]; cv[0] = a.x; cv[1] = a.y; cv[2] = b.x; cv[3] = b.y; }
+}
+
+template <bool WRITE>
+__global__ void k_narrow(int n, int kind, const int2 *__restrict__ cand, const int4 *__restrict__ tri, const int2 *__restrict__ edge,
+                         const int *__restrict__ cv_scene, const double *__restrict__ xw, const double *__restrict__ sparam,
+                         unsigned long long *__restrict__ mask, int *__restrict__ wcount, const int *__restrict__ woff,
+                         int2 *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int wave = i / TILE, lane = threadIdx.x & (TILE - 1);
+    if (!WRITE) {
+        bool act = false;
+        if (i < n) {
+            int cv[4];
+            pair_vertices(kind, cand[i], tri, edge, cv);
+            d3 x[4] = {ld3(xw, cv[0]), ld3(xw, cv[1]), ld3(xw, cv[2]), ld3(xw, cv[3])};
+            int t;
+            double d2 = pair_d2(kind, x, &t);
+            double dh = sparam[8 * cv_scene[cv[0]] + 2];
+            act = d2 < dh * dh;
+        }
+        unsigned long long m = __ballot(act);
+        if (lane == 0 && wave * TILE < n) { mask[wave] = m; wcount[wave] = __popcll(m); }
+    } else {
+        if (i >= n) return;
+        unsigned long long m = mask[wave];
+        if ((m >> lane) & 1ull) {
+            int pos = woff[wave] + __popcll(m & ((1ull << lane) - 1ull));
+            out[pos] = cand[i];
+        }
+    }
+}
+
+static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &cand, int64_t ncand, const std::vector<int> &cseg,
+                    DBuf<int2> &out, int64_t &cap, int64_t &count, std::vector<int> &hseg)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    int ns = c->n_scenes;
+    hseg.assign(ns + 1, 0);
+    count = 0;
+    if (ncand == 0) return;
+    int nw = (int)((ncand + TILE - 1) / TILE);
+    DBuf<unsigned long long> &mask = D.mkey;   // scratch reuse
+    mask.alloc(nw);
+    D.wcount.alloc(nw + 1); D.woff.alloc(nw + 1);
+    hipLaunchKernelGGL(k_narrow<false>, dim3(blocks_for(ncand)), dim3(BLOCK), 0, st, (int)ncand, kind, cand.p, D.tri.p, D.edge.p,
+                       D.cv_scene.p, xw, D.sparam.p, mask.p, D.wcount.p, nullptr, nullptr);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.wcount.p + nw, 0);
+    exclusive_scan(c, D.wcount.p, D.woff.p, nw);
+    int total = read_int(c, D.woff.p + nw);
+    if (total > cap) { cap = (int64_t)(total * 1.5) + 1024; out.alloc(cap); }
+    count = total;
+    hipLaunchKernelGGL(k_narrow<true>, dim3(blocks_for(ncand)), dim3(BLOCK), 0, st, (int)ncand, kind, cand.p, D.tri.p, D.edge.p,
+                       D.cv_scene.p, xw, D.sparam.p, mask.p, D.wcount.p, D.woff.p, out.p);
+    // per-scene segments: candidates are grouped by scene and the order is kept, so
+    // each scene's first survivor index is the prefix count before its first candidate
+    std::vector<int> hoff;
+    read_ints(c, D.woff.p, hoff, nw + 1);
+    std::vector<unsigned long long> hm(nw);
+    IPC_HIP(hipMemcpyAsync(hm.data(), mask.p, nw * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    IPC_HIP(hipStreamSynchronize(st));
+    for (int s = 0; s <= ns; ++s) {
+        int q = cseg[s];
+        if (q >= ncand) { hseg[s] = total; continue; }
+        int w = q / TILE, l = q % TILE;
+        hseg[s] = hoff[w] + (l ? __builtin_popcountll(hm[w] & ((1ull << l) - 1ull)) : 0);
+    }
+}
+
+void narrow_phase(ipc_ctx *c, const double *xw)
+{
+    compact(c, 0, xw, c->d.cand_pt, c->n_cand_pt, c->h_cand_pt_seg, c->d.pt, c->cap_pt, c->n_pt, c->h_pt_seg);
+    compact(c, 1, xw, c->d.cand_ee, c->n_cand_ee, c->h_cand_ee_seg, c->d.ee, c->cap_ee, c->n_ee, c->h_ee_seg);
+}
+
+// ---------------------------------------------------------------------------
+// barrier: energy / gradient / projected Hessian of one pair
+// ---------------------------------------------------------------------------
+struct Map {   // contact vertex -> DOFs
+    int node;  // FEM node or -1
+    int body;  // body node0 or -1
+    d3 xb;
+};
+__device__ __forceinline__ Map cv_map(int cv, const int *cv_node, const int *cv_body, const double *cv_x, const int *body_node0)
+{
+    Map m;
+    m.node = cv_node[cv];
+    int b = cv_body[cv];
+    m.body = b >= 0 ? body_node0[b] : -1;
+    m.xb = (b >= 0) ? ld3(cv_x, cv) : mk(0, 0, 0);
+    return m;
+}
+__device__ __forceinline__ void scatter_cv(const Map &m, double *out, d3 f)
+{
+    if (m.node >= 0) atomic_add3(out, m.node, f);
+    else if (m.body >= 0) {
+        atomic_add3(out, m.body, f);
+        atomic_add3(out, m.body + 1, {m.xb.x * f.x, m.xb.x * f.y, m.xb.x * f.z});
+        atomic_add3(out, m.body + 2, {m.xb.y * f.x, m.xb.y * f.y, m.xb.y * f.z});
+        atomic_add3(out, m.body + 3, {m.xb.z * f.x, m.xb.z * f.y, m.xb.z * f.z});
+    }
+}
+__device__ __forceinline__ d3 gather_cv(const Map &m, const double *v)
+{
+    if (m.node >= 0) return ld3(v, m.node);
+    if (m.body >= 0) {
+        d3 p = ld3(v, m.body), a0 = ld3(v, m.body + 1), a1 = ld3(v, m.body + 2), a2 = ld3(v, m.body + 3);
+        return {p.x + m.xb.x * a0.x + m.xb.y * a1.x + m.xb.z * a2.x, p.y + m.xb.x * a0.y + m.xb.y * a1.y + m.xb.z * a2.y,
+                p.z + m.xb.x * a0.z + m.xb.y * a1.z + m.xb.z * a2.z};
+    }
+    return {0.0, 0.0, 0.0};
+}
+
+// body diagonal block: add (w_k w_l^T) (x) B into the body's 12x12 block
+__device__ __forceinline__ void body_diag_add(double *diagB, int bidx, d3 wk3, d3 wl3, const double *B)
+{
+    double wk[4] = {1.0, wk3.x, wk3.y, wk3.z}, wl[4] = {1.0, wl3.x, wl3.y, wl3.z};
+    double *D = diagB + 144 * (size_t)bidx;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) atomicAdd(D + (3 * a + i) * 12 + 3 * b + j, wk[a] * wl[b] * B[3 * i + j]);
+}
+
+// Add the diagonal-block contributions of a 4-vertex local Hessian given by
+// the function blk(k, l, B[9]) into the FEM / body diagonal accumulators.
+template <class F>
+__device__ __forceinline__ void diag_contrib(const Map *m, const int *cvb, double *diagF, double *diagB, F blk)
+{
+    double B[9];
+    for (int k = 0; k < 4; ++k) {
+        if (m[k].node >= 0) {
+            blk(k, k, B);
+            for (int q = 0; q < 9; ++q) atomicAdd(diagF + 9 * (size_t)m[k].node + q, B[q]);
+        } else if (m[k].body >= 0) {
+            for (int l = 0; l < 4; ++l) {
+                if (cvb[l] != cvb[k]) continue;
+                blk(k, l, B);
+                body_diag_add(diagB, cvb[k], m[k].xb, m[l].xb, B);
+            }
+        }
+    }
+}
+
+template <int MODE>   // 0 energy, 1 energy + gradient, 2 gradient + projected Hessian
+__global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee,
+    const int4 *__restrict__ tri, const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
+    const double *__restrict__ sparam, const double *__restrict__ rest2, const int *__restrict__ cv_node,
+    const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ g,
+    int4 *__restrict__ pair_cv, double *__restrict__ pair_H, double *__restrict__ diagF, double *__restrict__ diagB,
+    double *__restrict__ pe, int project, int *__restrict__ inf_flag)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npt + nee) return;
+    int kind = i < npt ? 0 : 1;
+    int2 pr = kind == 0 ? pt[i] : ee[i - npt];
+    int cv[4];
+    pair_vertices(kind, pr, tri, edge, cv);
+    d3 x[4] = {ld3(xw, cv[0]), ld3(xw, cv[1]), ld3(xw, cv[2]), ld3(xw, cv[3])};
+    int s = cv_scene[cv[0]];
+    double kappa = sparam[8 * s + 1], dh = sparam[8 * s + 2];
+    int type;
+    double d2 = pair_d2(kind, x, &type);
+    if (MODE == 2) pair_cv[i] = make_int4(cv[0], cv[1], cv[2], cv[3]);
+    if (!(d2 > 0.0)) {
+        if (pe) pe[i] = 0.0;
+        atomicOr(inf_flag + s, 1);
+        if (MODE == 2) for (int q = 0; q < 45; ++q) pair_H[45 * (size_t)i + q] = 0.0;
+        return;
+    }
+    if (d2 >= dh * dh) {
+        if (pe) pe[i] = 0.0;
+        if (MODE == 2) for (int q = 0; q < 45; ++q) pair_H[45 * (size_t)i + q] = 0.0;
+        return;
+    }
+    double d = sqrt(d2);
+    double b = barrier(d, dh);
+    double m = 1.0, m1 = 0.0, m2 = 0.0, ex = 1.0, cval = 0.0;
+    d3 u, v, nn;
+    if (kind == 1) {
+        u = {x[1].x - x[0].x, x[1].y - x[0].y, x[1].z - x[0].z};
+        v = {x[3].x - x[2].x, x[3].y - x[2].y, x[3].z - x[2].z};
+        nn = cr(u, v);
+        cval = dt(nn, nn);
+        ex = 1e-3 * rest2[pr.x] * rest2[pr.y];
+        if (cval < ex) {
+            double rr = cval / ex;
+            m = (2.0 - rr) * rr;
+            m1 = 2.0 / ex - 2.0 * cval / (ex * ex);
+            m2 = -2.0 / (ex * ex);
+        }
+    }
+    if (pe) pe[i] = kappa * m * b;
+    if (MODE == 0) return;
+    TypeParam P = type_param(kind, type);
+    double beta[4];
+    d3 r, D0, D1;
+    closest_point(P, x, beta, r, D0, D1);
+    double b1 = barrier1(d, dh), b2 = barrier2(d, dh);
+    double Bq1 = b1 / (2.0 * d), Bq2 = (b2 - b1 / d) / (4.0 * d2);
+    bool moll = kind == 1 && cval < ex;
+    d3 cu = {0, 0, 0}, cvv = {0, 0, 0};
+    if (moll) {
+        d3 t1 = cr(v, nn), t2 = cr(nn, u);
+        cu = {2.0 * t1.x, 2.0 * t1.y, 2.0 * t1.z};
+        cvv = {2.0 * t2.x, 2.0 * t2.y, 2.0 * t2.z};
+    }
+    Map mp[4];
+    int cvb[4];
+    for (int k = 0; k < 4; ++k) { mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0); cvb[k] = cv_body[cv[k]]; }
+    // gradient in world coordinates
+    const double su[4] = {-1.0, 1.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, -1.0, 1.0};
+    for (int k = 0; k < 4; ++k) {
+        double cq = kappa * m * Bq1 * 2.0 * beta[k];
+        d3 gk = {cq * r.x, cq * r.y, cq * r.z};
+        if (moll) {
+            double cb = kappa * b * m1;
+            gk.x += cb * (su[k] * cu.x + sv[k] * cvv.x);
+            gk.y += cb * (su[k] * cu.y + sv[k] * cvv.y);
+            gk.z += cb * (su[k] * cu.z + sv[k] * cvv.z);
+        }
+        scatter_cv(mp[k], g, gk);
+    }
+    if (MODE < 2) return;
+    // reduced (translation-free) 9x9 Hessian, index 3*i + c
+    double gam[3], al0[3], al1[3], etu[3], etv[3];
+    for (int ii = 0; ii < 3; ++ii) {
+        gam[ii] = al0[ii] = al1[ii] = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            double U = helmert(k, ii);
+            gam[ii] += U * beta[k]; al0[ii] += U * P.a1[k]; al1[ii] += U * P.a2[k];
+        }
+        etu[ii] = helmert(1, ii) - helmert(0, ii);
+        etv[ii] = helmert(3, ii) - helmert(2, ii);
+    }
+    double gq[9], F0[9], F1[9], gc[9];
+    for (int ii = 0; ii < 3; ++ii)
+        for (int cc = 0; cc < 3; ++cc) {
+            double rc = comp(r, cc);
+            gq[3 * ii + cc] = 2.0 * gam[ii] * rc;
+            F0[3 * ii + cc] = 2.0 * al0[ii] * rc + 2.0 * gam[ii] * comp(D0, cc);
+            F1[3 * ii + cc] = 2.0 * al1[ii] * rc + 2.0 * gam[ii] * comp(D1, cc);
+            gc[3 * ii + cc] = etu[ii] * comp(cu, cc) + etv[ii] * comp(cvv, cc);
+        }
+    double Fi00 = 0, Fi01 = 0, Fi11 = 0;
+    if (P.npar == 1) Fi00 = 1.0 / (2.0 * dt(D0, D0));
+    else if (P.npar == 2) {
+        double s00 = 2.0 * dt(D0, D0), s01 = 2.0 * dt(D0, D1), s11 = 2.0 * dt(D1, D1);
+        double det = s00 * s11 - s01 * s01;
+        Fi00 = s11 / det; Fi11 = s00 / det; Fi01 = -s01 / det;
+    }
+    double H[45];
+    for (int R = 0; R < 9; ++R)
+        for (int C = R; C < 9; ++C) {
+            int iR = R / 3, cR = R % 3, iC = C / 3, cC = C % 3;
+            double hq = (cR == cC ? 2.0 * gam[iR] * gam[iC] : 0.0)
+                      - (F0[R] * Fi00 * F0[C] + F0[R] * Fi01 * F1[C] + F1[R] * Fi01 * F0[C] + F1[R] * Fi11 * F1[C]);
+            double hv = kappa * m * (Bq2 * gq[R] * gq[C] + Bq1 * hq);
+            if (moll) {
+                // Hessian of c = |u x v|^2 in (u, v): Huu = 2[v]x^T[v]x, Hvv = 2[u]x^T[u]x, Huv = 2[v]x[u]x - 2[n]x
+                double huu = 0, hvv = 0, huv = 0, hvu = 0;
+                for (int k = 0; k < 3; ++k) {
+                    huu += skew(v, k, cR) * skew(v, k, cC);
+                    hvv += skew(u, k, cR) * skew(u, k, cC);
+                    huv += skew(v, cR, k) * skew(u, k, cC);
+                    hvu += skew(v, cC, k) * skew(u, k, cR);
+                }
+                huu *= 2.0; hvv *= 2.0;
+                huv = 2.0 * huv - 2.0 * skew(nn, cR, cC);
+                hvu = 2.0 * hvu - 2.0 * skew(nn, cC, cR);   // (Huv)^T entry (cR, cC)
+                double hc = etu[iR] * etu[iC] * huu + etv[iR] * etv[iC] * hvv + etu[iR] * etv[iC] * huv + etv[iR] * etu[iC] * hvu;
+                hv += kappa * (b * (m2 * gc[R] * gc[C] + m1 * hc) + m1 * Bq1 * (gc[R] * gq[C] + gq[R] * gc[C]));
+            }
+            H[pk9(R, C)] = hv;
+        }
+    if (project) psd_project9(H);
+    double *out = pair_H + 45 * (size_t)i;
+    for (int q = 0; q < 45; ++q) out[q] = H[q];
+    // diagonal blocks for the preconditioner: H12[k][l] = sum_ij U_ki U_lj H9[i][j]
+    diag_contrib(mp, cvb, diagF, diagB, [&](int k, int l, double *B) {
+        for (int a = 0; a < 3; ++a)
+            for (int bb = 0; bb < 3; ++bb) {
+                double acc = 0.0;
+                for (int ii = 0; ii < 3; ++ii)
+                    for (int jj = 0; jj < 3; ++jj) acc += helmert(k, ii) * helmert(l, jj) * H[pk9(3 * ii + a, 3 * jj + bb)];
+                B[3 * a + bb] = acc;
+            }
+    });
+}
+
+void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project)
+{
+    Dev &D = c->d;
+    int64_t npt = candidates ? c->n_cand_pt : c->n_pt, nee = candidates ? c->n_cand_ee : c->n_ee;
+    const int2 *pt = candidates ? D.cand_pt.p : D.pt.p, *ee = candidates ? D.cand_ee.p : D.ee.p;
+    int64_t n = npt + nee;
+    D.pair_part.alloc(n + 1);
+    if (mode == 2) { D.pair_cv.alloc(n + 1); D.pair_H.alloc(45 * (size_t)(n + 1)); }
+    if (n == 0) return;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)npt, (int)nee, pt, ee, D.tri.p, D.edge.p, xw,
+                           D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, g,
+                           D.pair_cv.p, D.pair_H.p, D.diagF.p, D.diagB.p, D.pair_part.p, (int)project, D.inf_flag.p);
+    };
+    if (mode == 0) go(k_barrier<0>);
+    else if (mode == 1) go(k_barrier<1>);
+    else go(k_barrier<2>);
+}
+
+// ---------------------------------------------------------------------------
+// friction, lagged at the step start (closest-point weights beta, normal n,
+// normal force lambda = -kappa m b'(d))
+// ---------------------------------------------------------------------------
+__global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee, const int4 *__restrict__ tri,
+                      const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
+                      const double *__restrict__ sparam, const double *__restrict__ rest2, int4 *__restrict__ lcv,
+                      double *__restrict__ lbeta, double *__restrict__ lnrm, double *__restrict__ llam, double *__restrict__ lrn)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npt + nee) return;
+    int kind = i < npt ? 0 : 1;
+    int2 pr = kind == 0 ? pt[i] : ee[i - npt];
+    int cv[4];
+    pair_vertices(kind, pr, tri, edge, cv);
+    d3 x[4] = {ld3(xw, cv[0]), ld3(xw, cv[1]), ld3(xw, cv[2]), ld3(xw, cv[3])};
+    int s = cv_scene[cv[0]];
+    double kappa = sparam[8 * s + 1], dh = sparam[8 * s + 2];
+    int type;
+    double d2 = pair_d2(kind, x, &type);
+    double d = sqrt(d2);
+    TypeParam P = type_param(kind, type);
+    double beta[4];
+    d3 r, D0, D1;
+    closest_point(P, x, beta, r, D0, D1);
+    double rn = sqrt(dt(r, r));
+    double m = 1.0;
+    if (kind == 1) {
+        d3 u = {x[1].x - x[0].x, x[1].y - x[0].y, x[1].z - x[0].z}, v = {x[3].x - x[2].x, x[3].y - x[2].y, x[3].z - x[2].z};
+        d3 nn = cr(u, v);
+        double cval = dt(nn, nn), ex = 1e-3 * rest2[pr.x] * rest2[pr.y];
+        if (cval < ex) m = (2.0 - cval / ex) * (cval / ex);
+    }
+    lcv[i] = make_int4(cv[0], cv[1], cv[2], cv[3]);
+    for (int k = 0; k < 4; ++k) lbeta[4 * (size_t)i + k] = beta[k];
+    lnrm[3 * (size_t)i] = r.x / rn; lnrm[3 * (size_t)i + 1] = r.y / rn; lnrm[3 * (size_t)i + 2] = r.z / rn;
+    lrn[3 * (size_t)i] = r.x; lrn[3 * (size_t)i + 1] = r.y; lrn[3 * (size_t)i + 2] = r.z;
+    llam[i] = -kappa * m * barrier1(d, dh);
+}
+
+void launch_lag(ipc_ctx *c, const double *xw)
+{
+    Dev &D = c->d;
+    int64_t n = c->n_pt + c->n_ee;
+    if (n > c->cap_lag) {
+        c->cap_lag = (int64_t)(n * 1.5) + 1024;
+        D.lag_cv.alloc(c->cap_lag); D.lag_beta.alloc(4 * c->cap_lag); D.lag_nrm.alloc(3 * c->cap_lag);
+        D.lag_lam.alloc(c->cap_lag); D.lag_rn.alloc(3 * c->cap_lag); D.lag_M.alloc(6 * c->cap_lag);
+    }
+    c->n_lag = n;
+    c->h_lag_seg.assign(c->n_scenes + 1, 0);
+    for (int s = 0; s <= c->n_scenes; ++s) c->h_lag_seg[s] = c->h_pt_seg[s] + c->h_ee_seg[s];
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_lag, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,
+                       D.edge.p, xw, D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p, D.lag_lam.p,
+                       D.lag_rn.p);
+}
+
+template <int MODE>
+__global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__restrict__ lbeta, const double *__restrict__ lnrm,
+                           const double *__restrict__ llam, const double *__restrict__ lrn, const double *__restrict__ xw,
+                           const int *__restrict__ cv_scene, const double *__restrict__ sparam, const int *__restrict__ cv_node,
+                           const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
+                           double *__restrict__ g, double *__restrict__ lM, double *__restrict__ diagF, double *__restrict__ diagB,
+                           double *__restrict__ pe)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int4 c4 = lcv[i];
+    int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+    int s = cv_scene[cv[0]];
+    double mu = sparam[8 * s + 3], ea = sparam[8 * s + 4];
+    double beta[4];
+    for (int k = 0; k < 4; ++k) beta[k] = lbeta[4 * (size_t)i + k];
+    d3 sx = {0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+        d3 p = ld3(xw, cv[k]);
+        sx.x += beta[k] * p.x; sx.y += beta[k] * p.y; sx.z += beta[k] * p.z;
+    }
+    d3 rn = ld3(lrn, i), nr = ld3(lnrm, i);
+    d3 dv = {sx.x - rn.x, sx.y - rn.y, sx.z - rn.z};
+    double nd = dt(nr, dv);
+    d3 u = {dv.x - nr.x * nd, dv.y - nr.y * nd, dv.z - nr.z * nd};
+    double sn = sqrt(dt(u, u));
+    double f0 = sn < ea ? -sn * sn * sn / (3.0 * ea * ea) + sn * sn / ea + ea / 3.0 : sn;
+    double w = mu * llam[i];
+    if (pe) pe[i] = w * f0;
+    if (MODE == 0) return;
+    double f1s = sn < ea ? 2.0 / ea - sn / (ea * ea) : 1.0 / sn;
+    Map mp[4];
+    int cvb[4];
+    for (int k = 0; k < 4; ++k) { mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0); cvb[k] = cv_body[cv[k]]; }
+    for (int k = 0; k < 4; ++k) {
+        double cc = w * f1s * beta[k];
+        scatter_cv(mp[k], g, {cc * u.x, cc * u.y, cc * u.z});
+    }
+    if (MODE < 2) return;
+    double cu = sn < ea ? (sn > 0.0 ? -1.0 / (sn * ea * ea) : 0.0) : -1.0 / (sn * sn * sn);
+    double M[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            M[3 * a + b] = w * (cu * comp(u, a) * comp(u, b) + f1s * ((a == b ? 1.0 : 0.0) - comp(nr, a) * comp(nr, b)));
+    double *o = lM + 6 * (size_t)i;
+    o[0] = M[0]; o[1] = M[1]; o[2] = M[2]; o[3] = M[4]; o[4] = M[5]; o[5] = M[8];
+    diag_contrib(mp, cvb, diagF, diagB, [&](int k, int l, double *B) {
+        for (int q = 0; q < 9; ++q) B[q] = beta[k] * beta[l] * M[q];
+    });
+}
+
+void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
+{
+    Dev &D = c->d;
+    int64_t n = c->n_lag;
+    D.pair_part.alloc(std::max<int64_t>(n, c->n_pt + c->n_ee) + 1);
+    if (n == 0) return;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p,
+                           D.lag_lam.p, D.lag_rn.p, xw, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p,
+                           g, D.lag_M.p, D.diagF.p, D.diagB.p, D.fr_part.p);
+    };
+    D.fr_part.alloc(n + 1);
+    if (mode == 0) go(k_friction<0>);
+    else if (mode == 1) go(k_friction<1>);
+    else go(k_friction<2>);
+}
+
+// ---------------------------------------------------------------------------
+// contact Hessian product: out += sum_pairs J^T H J v (barrier pairs through the
+// reduced 9x9 blocks, friction pairs through beta and the 3x3 blocks), with the
+// local quadratic forms v^T H v per pair
+// ---------------------------------------------------------------------------
+__global__ void k_contact_apply(int nb, int nf, const int4 *__restrict__ pcv, const double *__restrict__ pH,
+                                const int4 *__restrict__ lcv, const double *__restrict__ lbeta, const double *__restrict__ lM,
+                                const int *__restrict__ cv_scene, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
+                                const double *__restrict__ cv_x, const int *__restrict__ body_node0, const int *__restrict__ active,
+                                const double *__restrict__ v, double *__restrict__ out, double *__restrict__ part_b,
+                                double *__restrict__ part_f)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb + nf) return;
+    bool fr = i >= nb;
+    int j = fr ? i - nb : i;
+    int4 c4 = fr ? lcv[j] : pcv[j];
+    int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+    int s = cv_scene[cv[0]];
+    double *part = fr ? part_f : part_b;
+    if (active && !active[s]) { if (part) part[j] = 0.0; return; }
+    Map mp[4];
+    d3 vw[4];
+    for (int k = 0; k < 4; ++k) { mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0); vw[k] = gather_cv(mp[k], v); }
+    if (!fr) {
+        double z[9], yv[9];
+        for (int ii = 0; ii < 3; ++ii) {
+            double a = 0, b = 0, cc = 0;
+            for (int k = 0; k < 4; ++k) { double U = helmert(k, ii); a += U * vw[k].x; b += U * vw[k].y; cc += U * vw[k].z; }
+            z[3 * ii] = a; z[3 * ii + 1] = b; z[3 * ii + 2] = cc;
+        }
+        const double *H = pH + 45 * (size_t)j;
+        double qf = 0.0;
+        for (int R = 0; R < 9; ++R) {
+            double acc = 0.0;
+            for (int C = 0; C < 9; ++C) acc += H[pk9(R, C)] * z[C];
+            yv[R] = acc;
+            qf += z[R] * acc;
+        }
+        if (part) part[j] = qf;
+        for (int k = 0; k < 4; ++k) {
+            d3 o = {0, 0, 0};
+            for (int ii = 0; ii < 3; ++ii) {
+                double U = helmert(k, ii);
+                o.x += U * yv[3 * ii]; o.y += U * yv[3 * ii + 1]; o.z += U * yv[3 * ii + 2];
+            }
+            scatter_cv(mp[k], out, o);
+        }
+    } else {
+        double be[4];
+        for (int k = 0; k < 4; ++k) be[k] = lbeta[4 * (size_t)j + k];
+        d3 z = {0, 0, 0};
+        for (int k = 0; k < 4; ++k) { z.x += be[k] * vw[k].x; z.y += be[k] * vw[k].y; z.z += be[k] * vw[k].z; }
+        const double *M = lM + 6 * (size_t)j;
+        d3 yv = {M[0] * z.x + M[1] * z.y + M[2] * z.z, M[1] * z.x + M[3] * z.y + M[4] * z.z, M[2] * z.x + M[4] * z.y + M[5] * z.z};
+        if (part) part[j] = dt(z, yv);
+        for (int k = 0; k < 4; ++k) scatter_cv(mp[k], out, {be[k] * yv.x, be[k] * yv.y, be[k] * yv.z});
+    }
+}
+
+void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part_b, double *part_f)
+{
+    Dev &D = c->d;
+    int64_t nb = c->n_pt + c->n_ee, nf = c->fr_on ? c->n_lag : 0;
+    if (nb + nf == 0) return;
+    hipLaunchKernelGGL(k_contact_apply, dim3(blocks_for(nb + nf)), dim3(BLOCK), 0, c->stream, (int)nb, (int)nf, D.pair_cv.p,
+                       D.pair_H.p, D.lag_cv.p, D.lag_beta.p, D.lag_M.p, D.cv_scene.p, D.cv_node.p, D.cv_body.p, D.cv_x.p,
+                       D.body_node0.p, active, v, out, part_b, part_f);
+}
+
+// ---------------------------------------------------------------------------
+// additive CCD over swept candidates; per-scene minimum through the bit
+// pattern of non-negative doubles (monotone as unsigned integers)
+// ---------------------------------------------------------------------------
+__device__ double accd(int kind, const d3 *x0, const d3 *p, double s)
+{
+    d3 pm = {0.25 * (p[0].x + p[1].x + p[2].x + p[3].x), 0.25 * (p[0].y + p[1].y + p[2].y + p[3].y),
+             0.25 * (p[0].z + p[1].z + p[2].z + p[3].z)};
+    d3 dp[4];
+    double nrm[4];
+    for (int k = 0; k < 4; ++k) {
+        dp[k] = {p[k].x - pm.x, p[k].y - pm.y, p[k].z - pm.z};
+        nrm[k] = sqrt(dt(dp[k], dp[k]));
+    }
+    double lp = kind == 0 ? nrm[0] + fmax(nrm[1], fmax(nrm[2], nrm[3])) : fmax(nrm[0], nrm[1]) + fmax(nrm[2], nrm[3]);
+    if (lp == 0.0) return 1.0;
+    d3 xx[4] = {x0[0], x0[1], x0[2], x0[3]};
+    int ty;
+    double d = sqrt(pair_d2(kind, xx, &ty));
+    double gap = s * d;
+    double t = 0.0, tl = (1.0 - s) * d / lp;
+    for (int it = 0; it < 10000; ++it) {
+        for (int k = 0; k < 4; ++k) { xx[k].x += tl * dp[k].x; xx[k].y += tl * dp[k].y; xx[k].z += tl * dp[k].z; }
+        d = sqrt(pair_d2(kind, xx, &ty));
+        if (t > 0.0 && d < gap) return t;
+        t += tl;
+        if (t > 1.0) return 1.0;
+        tl = 0.9 * d / lp;
+    }
+    return t;
+}
+
+__global__ void k_ccd(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee, const int4 *__restrict__ tri,
+                      const int2 *__restrict__ edge, const double *__restrict__ xw0, const double *__restrict__ xw1,
+                      const int *__restrict__ cv_scene, const double *__restrict__ sparam, const int *__restrict__ active,
+                      unsigned long long *__restrict__ amin, int stride)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npt + nee) return;
+    int kind = i < npt ? 0 : 1;
+    int2 pr = kind == 0 ? pt[i] : ee[i - npt];
+    int cv[4];
+    pair_vertices(kind, pr, tri, edge, cv);
+    int s = cv_scene[cv[0]];
+    if (active && !active[s]) return;
+    d3 x0[4], p[4];
+    for (int k = 0; k < 4; ++k) {
+        x0[k] = ld3(xw0, cv[k]);
+        d3 x1 = ld3(xw1, cv[k]);
+        p[k] = {x1.x - x0[k].x, x1.y - x0[k].y, x1.z - x0[k].z};
+    }
+    double t = accd(kind, x0, p, sparam[8 * s + 5]);
+    if (t < 1.0) atomicMin(amin + (size_t)stride * s, (unsigned long long)__double_as_longlong(t));
+}
+
+void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1)
+{
+    Dev &D = c->d;
+    int64_t n = c->n_cand_pt + c->n_cand_ee;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_ccd, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream, (int)c->n_cand_pt, (int)c->n_cand_ee, D.cand_pt.p,
+                       D.cand_ee.p, D.tri.p, D.edge.p, xw0, xw1, D.cv_scene.p, D.sparam.p, D.ls_active.p,
+                       (unsigned long long *)(D.scal.p + S_CCD), NSLOT);
+}
+
+} // namespace ipc

@@ -1,0 +1,506 @@
+// Context creation: host validation and topology, device precompute.
+//
+// Host side (once per scene): surface extraction (faces owned by exactly one
+// tetrahedron, outward, canonical rotation, sorted), unique surface edges,
+// contact-vertex numbering, block-CSR pattern of the FEM matrix and the
+// per-tetrahedron scatter slots.  Device side: inverse rest shape matrices,
+// volumes, Lame parameters, lumped masses and the constant spring diagonals.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ipc_device.h"
+#include "ipc_internal.h"
+
+namespace ipc {
+
+namespace {
+
+// ---- device precompute kernels ---------------------------------------------
+__global__ void k_tet_precompute(int T, const int4 *__restrict__ tv, const double *__restrict__ X, const double *__restrict__ E,
+                                 const double *__restrict__ nu, double *__restrict__ Bm, double *__restrict__ vol,
+                                 double *__restrict__ tmu, double *__restrict__ tlam, const int *__restrict__ valid)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= T) return;
+    if (!valid[e]) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Bm[(size_t)k * T + e] = 0.0;
+        vol[e] = 0.0; tmu[e] = 0.0; tlam[e] = 0.0;
+        return;
+    }
+    int4 t = tv[e];
+    d3 x0 = ld3(X, t.x), x1 = ld3(X, t.y), x2 = ld3(X, t.z), x3 = ld3(X, t.w);
+    // Dm columns: x1-x0, x2-x0, x3-x0
+    double m[3][3] = {{x1.x - x0.x, x2.x - x0.x, x3.x - x0.x},
+                      {x1.y - x0.y, x2.y - x0.y, x3.y - x0.y},
+                      {x1.z - x0.z, x2.z - x0.z, x3.z - x0.z}};
+    double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    double c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+    double c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    double det = m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02;
+    double id = 1.0 / det;
+    // inverse = adj^T / det, row-major B[r][c]
+    double B[9];
+    B[0] = c00 * id;
+    B[1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+    B[2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+    B[3] = c01 * id;
+    B[4] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+    B[5] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+    B[6] = c02 * id;
+    B[7] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+    B[8] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Bm[(size_t)k * T + e] = B[k];
+    vol[e] = det / 6.0;
+    double Ee = E[e], n = nu[e];
+    tmu[e] = Ee / (2.0 * (1.0 + n));
+    tlam[e] = Ee * n / ((1.0 + n) * (1.0 - 2.0 * n));
+}
+
+// lumped mass by gathering incident tetrahedra in a fixed order
+__global__ void k_node_mass(int N, const int *__restrict__ adj_ptr, const int *__restrict__ adj, const double *__restrict__ vol,
+                            const double *__restrict__ rho, double *__restrict__ mass)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double m = 0.0;
+    for (int k = adj_ptr[n]; k < adj_ptr[n + 1]; ++k) {
+        int e = adj[k];
+        m += rho[e] * vol[e] / 4.0;
+    }
+    mass[n] = m;
+}
+
+// constant diagonal blocks contributed by springs: h^2 k w_c w_c' I on the
+// side's own nodes (FEM node: 3x3; body: 12x12 over its 4 nodes)
+__global__ void k_spring_diag(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
+                              const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
+                              const double *__restrict__ k, const int *__restrict__ sp_scene, const double *__restrict__ h2s,
+                              double *__restrict__ fem_diag, double *__restrict__ body_diag)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= NS) return;
+    double kk = h2s[sp_scene[s]] * k[s];
+    for (int side = 0; side < 2; ++side) {
+        int kind = side ? kb[s] : ka[s];
+        int idx = side ? ib[s] : ia[s];
+        const double *xbar = (side ? xb : xa) + 3 * (size_t)s;
+        if (kind == 0) {
+            for (int c = 0; c < 3; ++c) atomicAdd(fem_diag + 9 * (size_t)idx + 4 * c, kk);
+        } else if (kind == 1) {
+            double w[4] = {1.0, xbar[0], xbar[1], xbar[2]};
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    for (int c = 0; c < 3; ++c)
+                        atomicAdd(body_diag + 144 * (size_t)idx + (3 * a + c) * 12 + 3 * b + c, kk * w[a] * w[b]);
+        }
+    }
+}
+
+__global__ void k_sum_mass(int nv, const double *__restrict__ mass, int node0, double *out)
+{
+    // one block; fixed-order strided sums then a tree
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nv; i += 256) acc += mass[node0 + i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ---- host helpers -----------------------------------------------------------
+void fail(const std::string &m) { throw Error(IPC_E_INVALID, m); }
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i) if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+void validate(const ipc_scene_desc &s, int si)
+{
+    auto pre = "scene " + std::to_string(si) + ": ";
+    if (s.nv < 0 || s.nt < 0 || s.nb < 0 || s.nbv < 0 || s.nbt < 0 || s.nsv < 0 || s.nst < 0 || s.nobj < 0 || s.nex < 0 ||
+        s.ns < 0 || s.nd < 0)
+        fail(pre + "negative size");
+    if (s.nv + s.nb == 0) fail(pre + "no degrees of freedom");
+    if (!(s.h > 0) || !(s.dhat > 0) || !(s.mu >= 0) || !(s.eps_v > 0) || !(s.newton_tol > 0) || !(s.pcg_tol > 0) ||
+        !(s.ccd_s > 0 && s.ccd_s < 1) || s.max_newton < 1 || s.max_pcg < 1)
+        fail(pre + "invalid parameters");
+    if (!finite_all(s.X, 3 * (size_t)s.nv) || !finite_all(s.V, 3 * (size_t)s.nv)) fail(pre + "non-finite FEM state");
+    for (int e = 0; e < s.nt; ++e) {
+        for (int k = 0; k < 4; ++k)
+            if (s.tets[4 * e + k] < 0 || s.tets[4 * e + k] >= s.nv) fail(pre + "tet index out of range");
+        if (!(s.tet_E[e] > 0) || !(s.tet_nu[e] > 0 && s.tet_nu[e] < 0.5) || !(s.tet_rho[e] > 0))
+            fail(pre + "invalid material at tet " + std::to_string(e));
+        const double *x0 = s.X + 3 * s.tets[4 * e], *x1 = s.X + 3 * s.tets[4 * e + 1], *x2 = s.X + 3 * s.tets[4 * e + 2],
+                     *x3 = s.X + 3 * s.tets[4 * e + 3];
+        double a[3], b[3], c[3];
+        for (int k = 0; k < 3; ++k) { a[k] = x1[k] - x0[k]; b[k] = x2[k] - x0[k]; c[k] = x3[k] - x0[k]; }
+        double det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+        if (!(det > 0)) fail(pre + "tet " + std::to_string(e) + " is inverted or degenerate");
+    }
+    for (int i = 0; i < s.nv; ++i)
+        if (s.vobj[i] < 0 || s.vobj[i] >= s.nobj || s.obj_kind[s.vobj[i]] != 0) fail(pre + "bad FEM vertex object");
+    for (int b = 0; b < s.nb; ++b) {
+        if (!(s.body_mass[b] > 0) || !(s.body_vol[b] > 0) || !(s.body_kappa[b] >= 0)) fail(pre + "invalid body");
+        if (s.body_obj[b] < 0 || s.body_obj[b] >= s.nobj || s.obj_kind[s.body_obj[b]] != 1) fail(pre + "bad body object");
+        if (!finite_all(s.body_q + 12 * b, 12) || !finite_all(s.body_qdot + 12 * b, 12)) fail(pre + "non-finite body state");
+    }
+    for (int i = 0; i < s.nbv; ++i) if (s.bv_body[i] < 0 || s.bv_body[i] >= s.nb) fail(pre + "bad body vertex");
+    for (int i = 0; i < 3 * s.nbt; ++i) if (s.btri[i] < 0 || s.btri[i] >= s.nbv) fail(pre + "bad body triangle");
+    for (int i = 0; i < 3 * s.nst; ++i) if (s.stri[i] < 0 || s.stri[i] >= s.nsv) fail(pre + "bad static triangle");
+    for (int i = 0; i < 2 * s.nex; ++i) if (s.excl[i] < 0 || s.excl[i] >= s.nobj) fail(pre + "bad exclusion");
+    for (int k = 0; k < s.ns; ++k) {
+        for (int side = 0; side < 2; ++side) {
+            int kind = side ? s.sp_kb[k] : s.sp_ka[k], idx = side ? s.sp_ib[k] : s.sp_ia[k];
+            int lim = kind == 0 ? s.nv : (kind == 1 ? s.nb : (kind == 2 ? s.nd : -1));
+            if (lim < 0 || idx < 0 || idx >= lim) fail(pre + "bad spring " + std::to_string(k));
+        }
+        if (!(s.sp_k[k] >= 0)) fail(pre + "negative spring stiffness");
+    }
+    for (int d = 0; d < s.nd; ++d) if (s.driven_body[d] < 0 || s.driven_body[d] >= s.nb) fail(pre + "bad driven body");
+}
+
+int pad64(int n) { return (n + TILE - 1) / TILE * TILE; }
+
+struct HostTopo {
+    std::vector<std::array<int, 3>> tri;   // scene-local external vertex ids, canonical
+    std::vector<std::array<int, 2>> edge;
+    std::vector<int> surf;                 // sorted external ids referenced by triangles
+};
+
+HostTopo topology(const ipc_scene_desc &s)
+{
+    HostTopo t;
+    static const int fl[4][3] = {{0, 2, 1}, {0, 1, 3}, {0, 3, 2}, {1, 2, 3}};
+    std::vector<std::pair<std::array<int, 3>, int>> faces;
+    faces.reserve(4 * (size_t)s.nt);
+    for (int e = 0; e < s.nt; ++e)
+        for (int f = 0; f < 4; ++f) {
+            std::array<int, 3> k = {s.tets[4 * e + fl[f][0]], s.tets[4 * e + fl[f][1]], s.tets[4 * e + fl[f][2]]};
+            std::sort(k.begin(), k.end());
+            faces.push_back({k, 4 * e + f});
+        }
+    std::sort(faces.begin(), faces.end());
+    for (size_t i = 0; i < faces.size();) {
+        size_t j = i + 1;
+        while (j < faces.size() && faces[j].first == faces[i].first) ++j;
+        if (j - i == 1) {
+            int e = faces[i].second / 4, f = faces[i].second % 4;
+            t.tri.push_back({s.tets[4 * e + fl[f][0]], s.tets[4 * e + fl[f][1]], s.tets[4 * e + fl[f][2]]});
+        }
+        i = j;
+    }
+    for (int k = 0; k < s.nbt; ++k)
+        t.tri.push_back({s.nv + s.btri[3 * k], s.nv + s.btri[3 * k + 1], s.nv + s.btri[3 * k + 2]});
+    for (int k = 0; k < s.nst; ++k)
+        t.tri.push_back({s.nv + s.nbv + s.stri[3 * k], s.nv + s.nbv + s.stri[3 * k + 1], s.nv + s.nbv + s.stri[3 * k + 2]});
+    for (auto &v : t.tri)
+        while (v[0] > v[1] || v[0] > v[2]) std::rotate(v.begin(), v.begin() + 1, v.end());
+    std::sort(t.tri.begin(), t.tri.end());
+    for (auto &v : t.tri)
+        for (int k = 0; k < 3; ++k) {
+            int a = v[k], b = v[(k + 1) % 3];
+            t.edge.push_back({std::min(a, b), std::max(a, b)});
+        }
+    std::sort(t.edge.begin(), t.edge.end());
+    t.edge.erase(std::unique(t.edge.begin(), t.edge.end()), t.edge.end());
+    for (auto &v : t.tri) for (int k = 0; k < 3; ++k) t.surf.push_back(v[k]);
+    std::sort(t.surf.begin(), t.surf.end());
+    t.surf.erase(std::unique(t.surf.begin(), t.surf.end()), t.surf.end());
+    return t;
+}
+
+} // namespace
+
+void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
+{
+    hipStream_t st = c->stream;
+    c->n_scenes = n;
+    c->sc.resize(n);
+    for (int s = 0; s < n; ++s) validate(scenes[s], s);
+
+    // ---- offsets
+    int node = 0, tet = 0, body = 0, drv = 0, sp = 0, cv = 0, tri = 0, edge = 0, obj = 0, ex = 0;
+    int64_t dof = 0;
+    std::vector<HostTopo> topo(n);
+    for (int s = 0; s < n; ++s) {
+        const ipc_scene_desc &d = scenes[s];
+        SceneInfo &S = c->sc[s];
+        S.nv = d.nv; S.nt = d.nt; S.nb = d.nb; S.nbv = d.nbv; S.nbt = d.nbt; S.nsv = d.nsv; S.nst = d.nst;
+        S.nobj = d.nobj; S.nex = d.nex; S.ns = d.ns; S.nd = d.nd;
+        S.h = d.h; S.g[0] = d.g[0]; S.g[1] = d.g[1]; S.g[2] = d.g[2]; S.dhat = d.dhat; S.kappa = d.kappa; S.mu = d.mu;
+        S.eps_v = d.eps_v; S.newton_tol = d.newton_tol; S.pcg_tol = d.pcg_tol; S.ccd_s = d.ccd_s;
+        S.max_newton = d.max_newton; S.max_pcg = d.max_pcg;
+        topo[s] = topology(d);
+        S.node0 = node; S.nnode = d.nv + 4 * d.nb; S.nnode_pad = pad64(S.nnode);
+        S.tet0 = tet; S.nt_pad = pad64(d.nt);
+        S.body0 = body; S.drv0 = drv; S.sp0 = sp;
+        S.cv0 = cv; S.ncv = (int)topo[s].surf.size(); S.nsurf = S.ncv;
+        S.tri0 = tri; S.ntri = (int)topo[s].tri.size();
+        S.edge0 = edge; S.nedge = (int)topo[s].edge.size();
+        S.obj0 = obj;
+        S.dof0 = dof;
+        node += S.nnode_pad; tet += S.nt_pad; body += d.nb; drv += d.nd; sp += d.ns; cv += S.ncv;
+        tri += S.ntri; edge += S.nedge; obj += d.nobj; ex += d.nex;
+        dof += 3 * (int64_t)S.nnode;
+        S.surf_ext = topo[s].surf;
+        S.tri_ext.resize(3 * (size_t)S.ntri);
+        for (int k = 0; k < S.ntri; ++k) for (int m = 0; m < 3; ++m) S.tri_ext[3 * k + m] = topo[s].tri[k][m];
+        S.edge_ext.resize(2 * (size_t)S.nedge);
+        for (int k = 0; k < S.nedge; ++k) for (int m = 0; m < 2; ++m) S.edge_ext[2 * k + m] = topo[s].edge[k][m];
+    }
+    c->N = node; c->T = tet; c->NB = body; c->ND = drv; c->NS = sp; c->CV = cv; c->NSURF = cv; c->TRI = tri;
+    c->EDGE = edge; c->NOBJ = obj; c->NEX = ex; c->ndof = dof; c->ext_nodes = dof / 3;
+
+    // ---- host arrays
+    std::vector<double> X(3 * (size_t)node, 0.0), V(3 * (size_t)node, 0.0), mass_dummy;
+    std::vector<int> node_scene(node), node_kind(node, 2), ext2node((size_t)c->ext_nodes);
+    std::vector<int4> tv(tet);
+    std::vector<int> tvalid(tet, 0);
+    std::vector<double> tE(tet, 1.0), tnu(tet, 0.25), trho(tet, 0.0);
+    std::vector<double> bM(16 * (size_t)std::max(body, 1), 0.0), bvol(body), bkappa(body), bext(3 * (size_t)body);
+    std::vector<int> body_node0(body), body_scene(body);
+    std::vector<int> ska(sp), sia(sp), skb(sp), sib(sp), sscene(sp);
+    std::vector<double> sxa(3 * (size_t)sp), sxb(3 * (size_t)sp), sk(sp);
+    std::vector<double> targets(12 * (size_t)std::max(drv, 1), 0.0);
+    std::vector<int> driven(drv);
+    std::vector<int> cv_node(cv, -1), cv_body(cv, -1), cv_obj(cv), cv_scene(cv);
+    std::vector<double> cv_x(3 * (size_t)cv, 0.0);
+    std::vector<int4> tri4(tri);
+    std::vector<int2> edge2(edge);
+    std::vector<double> rest2(edge);
+    std::vector<int> okind(obj), excl(2 * (size_t)std::max(ex, 1));
+    std::vector<int> tile_node(node / TILE), tile_tet(tet / TILE);
+    std::vector<int> adj_ptr(node + 1, 0), adj;
+    int exo = 0;
+    for (int s = 0; s < n; ++s) {
+        const ipc_scene_desc &d = scenes[s];
+        SceneInfo &S = c->sc[s];
+        for (int i = 0; i < S.nnode_pad; ++i) node_scene[S.node0 + i] = s;
+        for (int i = 0; i < S.nnode_pad / TILE; ++i) tile_node[S.node0 / TILE + i] = s;
+        for (int i = 0; i < S.nt_pad / TILE; ++i) tile_tet[S.tet0 / TILE + i] = s;
+        for (int i = 0; i < d.nv; ++i) {
+            node_kind[S.node0 + i] = 0;
+            for (int k = 0; k < 3; ++k) { X[3 * (size_t)(S.node0 + i) + k] = d.X[3 * i + k]; V[3 * (size_t)(S.node0 + i) + k] = d.V[3 * i + k]; }
+        }
+        for (int b = 0; b < d.nb; ++b)
+            for (int cc = 0; cc < 4; ++cc) {
+                int nd = S.node0 + d.nv + 4 * b + cc;
+                node_kind[nd] = 1;
+                for (int k = 0; k < 3; ++k) { X[3 * (size_t)nd + k] = d.body_q[12 * b + 3 * cc + k]; V[3 * (size_t)nd + k] = d.body_qdot[12 * b + 3 * cc + k]; }
+            }
+        for (int i = 0; i < S.nnode; ++i) ext2node[S.dof0 / 3 + i] = S.node0 + i;
+        for (int e = 0; e < S.nt_pad; ++e) {
+            int g = S.tet0 + e;
+            if (e < d.nt) {
+                tv[g] = make_int4(S.node0 + d.tets[4 * e], S.node0 + d.tets[4 * e + 1], S.node0 + d.tets[4 * e + 2], S.node0 + d.tets[4 * e + 3]);
+                tvalid[g] = 1; tE[g] = d.tet_E[e]; tnu[g] = d.tet_nu[e]; trho[g] = d.tet_rho[e];
+            } else {
+                tv[g] = make_int4(S.node0, S.node0, S.node0, S.node0);
+            }
+        }
+        for (int b = 0; b < d.nb; ++b) {
+            int g = S.body0 + b;
+            bM[16 * (size_t)g] = d.body_mass[b];
+            for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) bM[16 * (size_t)g + (1 + i) * 4 + 1 + j] = d.body_S[9 * b + 3 * i + j];
+            bvol[g] = d.body_vol[b]; bkappa[g] = d.body_kappa[b];
+            for (int k = 0; k < 3; ++k) bext[3 * (size_t)g + k] = d.body_ext[3 * b + k];
+            body_node0[g] = S.node0 + d.nv + 4 * b;
+            body_scene[g] = s;
+        }
+        for (int k = 0; k < d.ns; ++k) {
+            int g = S.sp0 + k;
+            auto conv = [&](int kind, int idx) { return kind == 0 ? S.node0 + idx : (kind == 1 ? S.body0 + idx : S.drv0 + idx); };
+            ska[g] = d.sp_ka[k]; sia[g] = conv(d.sp_ka[k], d.sp_ia[k]);
+            skb[g] = d.sp_kb[k]; sib[g] = conv(d.sp_kb[k], d.sp_ib[k]);
+            for (int m = 0; m < 3; ++m) { sxa[3 * (size_t)g + m] = d.sp_xa[3 * k + m]; sxb[3 * (size_t)g + m] = d.sp_xb[3 * k + m]; }
+            sk[g] = d.sp_k[k]; sscene[g] = s;
+        }
+        for (int k = 0; k < d.nd; ++k) {
+            driven[S.drv0 + k] = S.body0 + d.driven_body[k];
+            for (int m = 0; m < 12; ++m) targets[12 * (size_t)(S.drv0 + k) + m] = d.body_q[12 * d.driven_body[k] + m];
+        }
+        // contact vertices
+        const HostTopo &tp = topo[s];
+        std::vector<int> ext2cv(d.nv + d.nbv + d.nsv, -1);
+        int static_obj = -1;
+        for (int o = 0; o < d.nobj; ++o) if (d.obj_kind[o] == 2) { static_obj = o; break; }
+        for (int i = 0; i < S.ncv; ++i) {
+            int e = tp.surf[i], g = S.cv0 + i;
+            ext2cv[e] = g;
+            cv_scene[g] = s;
+            if (e < d.nv) { cv_node[g] = S.node0 + e; cv_obj[g] = S.obj0 + d.vobj[e]; }
+            else if (e < d.nv + d.nbv) {
+                int j = e - d.nv;
+                cv_body[g] = S.body0 + d.bv_body[j];
+                cv_obj[g] = S.obj0 + d.body_obj[d.bv_body[j]];
+                for (int m = 0; m < 3; ++m) cv_x[3 * (size_t)g + m] = d.bv_xbar[3 * j + m];
+            } else {
+                int j = e - d.nv - d.nbv;
+                cv_obj[g] = static_obj >= 0 ? S.obj0 + static_obj : -1;
+                for (int m = 0; m < 3; ++m) cv_x[3 * (size_t)g + m] = d.sv_x[3 * j + m];
+            }
+        }
+        for (int k = 0; k < S.ntri; ++k)
+            tri4[S.tri0 + k] = make_int4(ext2cv[tp.tri[k][0]], ext2cv[tp.tri[k][1]], ext2cv[tp.tri[k][2]], s);
+        auto rest = [&](int e, double *x) {
+            if (e < d.nv) for (int m = 0; m < 3; ++m) x[m] = d.X[3 * e + m];
+            else if (e < d.nv + d.nbv) for (int m = 0; m < 3; ++m) x[m] = d.bv_xbar[3 * (e - d.nv) + m];
+            else for (int m = 0; m < 3; ++m) x[m] = d.sv_x[3 * (e - d.nv - d.nbv) + m];
+        };
+        for (int k = 0; k < S.nedge; ++k) {
+            edge2[S.edge0 + k] = make_int2(ext2cv[tp.edge[k][0]], ext2cv[tp.edge[k][1]]);
+            double a[3], b[3];
+            rest(tp.edge[k][0], a); rest(tp.edge[k][1], b);
+            double dd = 0.0;
+            for (int m = 0; m < 3; ++m) dd += (b[m] - a[m]) * (b[m] - a[m]);
+            rest2[S.edge0 + k] = dd;
+        }
+        for (int o = 0; o < d.nobj; ++o) okind[S.obj0 + o] = d.obj_kind[o];
+        for (int k = 0; k < d.nex; ++k) { excl[2 * exo] = S.obj0 + d.excl[2 * k]; excl[2 * exo + 1] = S.obj0 + d.excl[2 * k + 1]; ++exo; }
+        // characteristic length L (initial bounding box of FEM vertices and body boxes)
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int i = 0; i < d.nv; ++i)
+            for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], d.X[3 * i + k]); hi[k] = std::max(hi[k], d.X[3 * i + k]); }
+        for (int b = 0; b < d.nb; ++b)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], d.body_q[12 * b + k] - d.body_ext[3 * b + k]);
+                hi[k] = std::max(hi[k], d.body_q[12 * b + k] + d.body_ext[3 * b + k]);
+            }
+        double dd = 0.0;
+        for (int k = 0; k < 3; ++k) if (hi[k] > lo[k]) dd += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+        S.L = std::sqrt(dd);
+        S.thr = S.newton_tol * S.h * S.L;
+    }
+    // node -> incident tets (fixed order) for the lumped mass
+    for (int e = 0; e < tet; ++e)
+        if (tvalid[e]) { adj_ptr[tv[e].x + 1]++; adj_ptr[tv[e].y + 1]++; adj_ptr[tv[e].z + 1]++; adj_ptr[tv[e].w + 1]++; }
+    for (int i = 0; i < node; ++i) adj_ptr[i + 1] += adj_ptr[i];
+    adj.resize(adj_ptr[node]);
+    {
+        std::vector<int> fill(adj_ptr.begin(), adj_ptr.end() - 1);
+        for (int e = 0; e < tet; ++e)
+            if (tvalid[e]) { adj[fill[tv[e].x]++] = e; adj[fill[tv[e].y]++] = e; adj[fill[tv[e].z]++] = e; adj[fill[tv[e].w]++] = e; }
+    }
+    // FEM block-CSR pattern over node rows
+    std::vector<int> row_ptr(node + 1, 0), col;
+    {
+        std::vector<std::vector<int>> cols(node);
+        for (int e = 0; e < tet; ++e) {
+            if (!tvalid[e]) continue;
+            int v[4] = {tv[e].x, tv[e].y, tv[e].z, tv[e].w};
+            for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) cols[v[a]].push_back(v[b]);
+        }
+        for (int i = 0; i < node; ++i) {
+            auto &cl = cols[i];
+            if (node_kind[i] == 0) cl.push_back(i);   // every FEM node keeps a diagonal block (mass)
+            std::sort(cl.begin(), cl.end());
+            cl.erase(std::unique(cl.begin(), cl.end()), cl.end());
+            row_ptr[i + 1] = row_ptr[i] + (int)cl.size();
+        }
+        col.resize(row_ptr[node]);
+        for (int i = 0; i < node; ++i) std::copy(cols[i].begin(), cols[i].end(), col.begin() + row_ptr[i]);
+    }
+    c->nnzb = row_ptr[node];
+    std::vector<int> tslot(16 * (size_t)tet, 0), diag_slot(node, -1);
+    auto find_slot = [&](int r, int cc) {
+        auto b = col.begin() + row_ptr[r], e = col.begin() + row_ptr[r + 1];
+        return (int)(std::lower_bound(b, e, cc) - col.begin());
+    };
+    for (int e = 0; e < tet; ++e) {
+        if (!tvalid[e]) continue;
+        int v[4] = {tv[e].x, tv[e].y, tv[e].z, tv[e].w};
+        for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) tslot[16 * (size_t)e + 4 * a + b] = find_slot(v[a], v[b]);
+    }
+    for (int i = 0; i < node; ++i) if (node_kind[i] == 0) diag_slot[i] = find_slot(i, i);
+    // segment tables (per-scene ranges) used by the segmented reductions
+    c->seg_surf.resize(n + 1); c->seg_tri.resize(n + 1); c->seg_edge.resize(n + 1); c->seg_sp.resize(n + 1); c->seg_body.resize(n + 1);
+    for (int s = 0; s < n; ++s) {
+        c->seg_surf[s] = c->sc[s].cv0; c->seg_tri[s] = c->sc[s].tri0; c->seg_edge[s] = c->sc[s].edge0;
+        c->seg_sp[s] = c->sc[s].sp0; c->seg_body[s] = c->sc[s].body0;
+    }
+    c->seg_surf[n] = cv; c->seg_tri[n] = tri; c->seg_edge[n] = edge; c->seg_sp[n] = sp; c->seg_body[n] = body;
+
+    // ---- upload
+    Dev &D = c->d;
+    D.y.upload(X, st); D.ydot.upload(V, st);
+    for (auto *b : {&D.xt, &D.y0, &D.yt, &D.g, &D.p, &D.r, &D.z, &D.q, &D.x, &D.v1, &D.v2}) b->alloc(3 * (size_t)node);
+    IPC_HIP(hipMemcpyAsync(D.xt.p, D.y.p, 3 * (size_t)node * sizeof(double), hipMemcpyDeviceToDevice, st));
+    D.node_scene.upload(node_scene, st); D.node_kind.upload(node_kind, st); D.ext2node.upload(ext2node, st);
+    D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node); D.diagF.alloc(9 * (size_t)node);
+    D.fem_sp_diag.alloc(9 * (size_t)node); D.fem_sp_diag.zero(st, 9 * (size_t)node);
+    D.tv.upload(tv, st);
+    D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);
+    D.tslot.upload(tslot, st);
+    D.row_ptr.upload(row_ptr, st); D.col.upload(col, st); D.diag_slot.upload(diag_slot, st);
+    D.val.alloc(9 * (size_t)std::max(c->nnzb, 1));
+    D.bM.upload(bM, st); D.bvol.upload(bvol, st); D.bkappa.upload(bkappa, st); D.bext.upload(bext, st);
+    D.body_node0.upload(body_node0, st); D.body_scene.upload(body_scene, st);
+    D.Hb.alloc(144 * (size_t)std::max(body, 1)); D.diagB.alloc(144 * (size_t)std::max(body, 1));
+    D.dinvB.alloc(144 * (size_t)std::max(body, 1));
+    D.body_sp_diag.alloc(144 * (size_t)std::max(body, 1)); D.body_sp_diag.zero(st, 144 * (size_t)std::max(body, 1));
+    D.body_part.alloc(std::max(body, 1));
+    D.sp_ka.upload(ska, st); D.sp_ia.upload(sia, st); D.sp_kb.upload(skb, st); D.sp_ib.upload(sib, st);
+    D.sp_scene.upload(sscene, st); D.sp_xa.upload(sxa, st); D.sp_xb.upload(sxb, st); D.sp_k.upload(sk, st);
+    D.sp_part.alloc(std::max(sp, 1));
+    D.targets.upload(targets, st); D.driven_body.upload(driven, st);
+    D.cv_node.upload(cv_node, st); D.cv_body.upload(cv_body, st); D.cv_obj.upload(cv_obj, st); D.cv_scene.upload(cv_scene, st);
+    D.cv_x.upload(cv_x, st);
+    D.xw.alloc(3 * (size_t)std::max(cv, 1)); D.xw1.alloc(3 * (size_t)std::max(cv, 1));
+    D.tri.upload(tri4, st); D.edge.upload(edge2, st); D.edge_rest2.upload(rest2, st);
+    D.obj_kind.upload(okind, st); D.excl.upload(excl, st);
+    D.scal.alloc((size_t)n * NSLOT); D.scal.zero(st, (size_t)n * NSLOT);
+    D.part_node.alloc(node / TILE + 1); D.part_tet.alloc(tet / TILE + 1);
+    D.tile_scene_node.upload(tile_node, st); D.tile_scene_tet.upload(tile_tet, st);
+    D.seg.alloc(4 * (size_t)(n + 1));
+
+    // ---- device precompute
+    {
+        DBuf<double> dE, dnu, drho;
+        DBuf<int> dvalid, dadjp, dadj;
+        dE.upload(tE, st); dnu.upload(tnu, st); drho.upload(trho, st); dvalid.upload(tvalid, st);
+        dadjp.upload(adj_ptr, st); dadj.upload(adj, st);
+        if (tet > 0)
+            hipLaunchKernelGGL(k_tet_precompute, dim3(blocks_for(tet)), dim3(BLOCK), 0, st, tet, D.tv.p, D.y.p, dE.p, dnu.p,
+                               D.Bm.p, D.vol.p, D.tmu.p, D.tlam.p, dvalid.p);
+        hipLaunchKernelGGL(k_node_mass, dim3(blocks_for(node)), dim3(BLOCK), 0, st, node, dadjp.p, dadj.p, D.vol.p, drho.p, D.mass.p);
+        std::vector<double> h2s(n);
+        for (int s = 0; s < n; ++s) h2s[s] = c->sc[s].h * c->sc[s].h;
+        DBuf<double> dh2; dh2.upload(h2s, st);
+        if (sp > 0)
+            hipLaunchKernelGGL(k_spring_diag, dim3(blocks_for(sp)), dim3(BLOCK), 0, st, sp, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
+                               D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, dh2.p, D.fem_sp_diag.p, D.body_sp_diag.p);
+        // kappa (automatic: 10 * mean FEM vertex mass * |g| * h^2 / dhat)
+        DBuf<double> msum; msum.alloc(n);
+        for (int s = 0; s < n; ++s)
+            if (scenes[s].nv > 0)
+                hipLaunchKernelGGL(k_sum_mass, dim3(1), dim3(256), 0, st, scenes[s].nv, D.mass.p, c->sc[s].node0, msum.p + s);
+        std::vector<double> hm(n, 0.0);
+        IPC_HIP(hipMemcpyAsync(hm.data(), msum.p, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        for (int s = 0; s < n; ++s) {
+            SceneInfo &S = c->sc[s];
+            const ipc_scene_desc &d = scenes[s];
+            if (d.nv > 0) S.mbar = hm[s] / d.nv;
+            else {
+                double bm = 0.0;
+                for (int b = 0; b < d.nb; ++b) bm += d.body_mass[b];
+                S.mbar = d.nbv ? bm / d.nbv : 0.0;
+            }
+            double gn = std::sqrt(S.g[0] * S.g[0] + S.g[1] * S.g[1] + S.g[2] * S.g[2]);
+            if (S.kappa <= 0.0) S.kappa = 10.0 * S.mbar * gn * S.h * S.h / S.dhat;
+        }
+    }
+}
+
+} // namespace ipc

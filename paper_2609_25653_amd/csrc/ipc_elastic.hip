@@ -1,0 +1,382 @@
+// Inertia, Stable Neo-Hookean FEM, affine-body orthogonality and point-spring
+// terms of the incremental potential (Sec. III-C.1-2, Eq. (1)-(3)).
+//
+// One thread per tetrahedron / body / spring.  The FEM kernel forms the 9x9
+// Hessian of the energy density in F, projects it to PSD in registers, maps it
+// to the 16 3x3 blocks of the element and adds them into the block-CSR matrix
+// through precomputed slots; gradients go out through FP64 atomics.  Energies
+// are reduced per wavefront (scene-aligned tiles) for a deterministic sum.
+#include "ipc_device.h"
+#include "ipc_internal.h"
+#include "ipc_kernels.h"
+
+namespace ipc {
+
+// ---------------------------------------------------------------------------
+// nodes: inertia of FEM vertices; initialises g (FEM nodes) and zeroes the rest
+// ---------------------------------------------------------------------------
+__global__ void k_node_inertia(int N, const double *__restrict__ y, const double *__restrict__ xt, const double *__restrict__ mass,
+                               const int *__restrict__ kind, double *__restrict__ g, double *__restrict__ part)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (n < N) {
+        d3 gv = {0.0, 0.0, 0.0};
+        if (kind[n] == 0) {
+            double m = mass[n];
+            d3 d = {y[3 * (size_t)n] - xt[3 * (size_t)n], y[3 * (size_t)n + 1] - xt[3 * (size_t)n + 1], y[3 * (size_t)n + 2] - xt[3 * (size_t)n + 2]};
+            e = 0.5 * m * (d.x * d.x + d.y * d.y + d.z * d.z);
+            gv = {m * d.x, m * d.y, m * d.z};
+        }
+        if (g) st3(g, n, gv);
+    }
+    e = wave_sum(e);
+    if (part && (threadIdx.x & (TILE - 1)) == 0 && n < N) part[n / TILE] = e;
+}
+
+// ---------------------------------------------------------------------------
+// FEM (rest-stable Stable Neo-Hookean)
+// ---------------------------------------------------------------------------
+template <int MODE>   // 0 energy, 1 energy+gradient, 2 gradient+Hessian
+__global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv, const double *__restrict__ Bm,
+                                             const double *__restrict__ vol, const double *__restrict__ tmu,
+                                             const double *__restrict__ tlam, const double *__restrict__ y,
+                                             const int *__restrict__ tile_scene, const double *__restrict__ h2s,
+                                             double *__restrict__ g, double *__restrict__ val, const int *__restrict__ tslot,
+                                             int project, double *__restrict__ part)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double energy = 0.0;
+    if (e < T && vol[e] > 0.0) {
+        int4 t = tv[e];
+        int vi[4] = {t.x, t.y, t.z, t.w};
+        d3 x[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = ld3(y, vi[a]);
+        double c[4][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            c[1][j] = Bm[(size_t)(0 * 3 + j) * T + e];
+            c[2][j] = Bm[(size_t)(1 * 3 + j) * T + e];
+            c[3][j] = Bm[(size_t)(2 * 3 + j) * T + e];
+            c[0][j] = -(c[1][j] + c[2][j] + c[3][j]);
+        }
+        d3 f[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            f[j] = {c[0][j] * x[0].x + c[1][j] * x[1].x + c[2][j] * x[2].x + c[3][j] * x[3].x,
+                    c[0][j] * x[0].y + c[1][j] * x[1].y + c[2][j] * x[2].y + c[3][j] * x[3].y,
+                    c[0][j] * x[0].z + c[1][j] * x[1].z + c[2][j] * x[2].z + c[3][j] * x[3].z};
+        double mu = tmu[e], lh = tlam[e] + mu;
+        d3 cof[3] = {cr(f[1], f[2]), cr(f[2], f[0]), cr(f[0], f[1])};
+        double J = dt(f[0], cof[0]);
+        double I2 = dt(f[0], f[0]) + dt(f[1], f[1]) + dt(f[2], f[2]);
+        double w = h2s[tile_scene[e / TILE]] * vol[e];
+        energy = w * (0.5 * mu * (I2 - 3.0) - mu * (J - 1.0) + 0.5 * lh * (J - 1.0) * (J - 1.0));
+        double sc = lh * (J - 1.0) - mu;
+        if (MODE >= 1) {
+            d3 P[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[j] = {mu * f[j].x + sc * cof[j].x, mu * f[j].y + sc * cof[j].y, mu * f[j].z + sc * cof[j].z};
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                d3 ga = {w * (c[a][0] * P[0].x + c[a][1] * P[1].x + c[a][2] * P[2].x),
+                         w * (c[a][0] * P[0].y + c[a][1] * P[1].y + c[a][2] * P[2].y),
+                         w * (c[a][0] * P[0].z + c[a][1] * P[1].z + c[a][2] * P[2].z)};
+                atomic_add3(g, vi[a], ga);
+            }
+        }
+        if (MODE == 2) {
+            double H[45];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            int R = 3 * a + i, C = 3 * b + j;
+                            if (R > C) continue;
+                            double v = lh * comp(cof[a], i) * comp(cof[b], j) + (R == C ? mu : 0.0);
+                            if (a != b) {
+                                int cc = 3 - a - b;
+                                double sg = (b == (a + 2) % 3) ? 1.0 : -1.0;
+                                v += sc * sg * skew(f[cc], i, j);
+                            }
+                            H[pk9(R, C)] = v;
+                        }
+            if (project) psd_project9(H);
+            const int *sl = tslot + 16 * (size_t)e;
+#pragma unroll
+            for (int B = 0; B < 4; ++B) {
+                double Tm[9][3];   // Tm[(j,r)][q] = sum_l c[B][l] H[(j,r),(l,q)]
+#pragma unroll
+                for (int R = 0; R < 9; ++R)
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        Tm[R][q] = c[B][0] * H[pk9(R, q)] + c[B][1] * H[pk9(R, 3 + q)] + c[B][2] * H[pk9(R, 6 + q)];
+#pragma unroll
+                for (int A = 0; A < 4; ++A) {
+                    double *blk = val + 9 * (size_t)sl[4 * A + B];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            atomicAdd(blk + 3 * r + q, w * (c[A][0] * Tm[r][q] + c[A][1] * Tm[3 + r][q] + c[A][2] * Tm[6 + r][q]));
+                }
+            }
+        }
+    }
+    energy = wave_sum(energy);
+    if (part && (threadIdx.x & (TILE - 1)) == 0 && e < T) part[e / TILE] = energy;
+}
+
+// block-CSR init: zero, with the lumped mass on FEM diagonal blocks
+__global__ void k_bsr_init(int N, const int *__restrict__ row_ptr, const int *__restrict__ col, const double *__restrict__ mass,
+                           double *__restrict__ val)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double m = mass[n];
+    for (int k = row_ptr[n]; k < row_ptr[n + 1]; ++k) {
+        double d = col[k] == n ? m : 0.0;
+        double *b = val + 9 * (size_t)k;
+        b[0] = d; b[1] = 0; b[2] = 0; b[3] = 0; b[4] = d; b[5] = 0; b[6] = 0; b[7] = 0; b[8] = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// affine bodies: inertia (4x4 mass matrix (x) I3) + orthogonality kappa V |AA^T - I|^2
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void k_body(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ bM,
+                       const double *__restrict__ bvol, const double *__restrict__ bkappa, const double *__restrict__ h2s,
+                       const double *__restrict__ y, const double *__restrict__ xt, double *__restrict__ g,
+                       double *__restrict__ Hb, int project, double *__restrict__ part)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= NB) return;
+    int n0 = node0[b];
+    const double *M = bM + 16 * (size_t)b;
+    d3 q[4], dq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        q[c] = ld3(y, n0 + c);
+        d3 t = ld3(xt, n0 + c);
+        dq[c] = {q[c].x - t.x, q[c].y - t.y, q[c].z - t.z};
+    }
+    double E = 0.0;
+    d3 gq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        gq[c] = {0, 0, 0};
+#pragma unroll
+        for (int c2 = 0; c2 < 4; ++c2) {
+            double m = M[4 * c + c2];
+            gq[c].x += m * dq[c2].x; gq[c].y += m * dq[c2].y; gq[c].z += m * dq[c2].z;
+        }
+        E += 0.5 * dt(dq[c], gq[c]);
+    }
+    // orthogonality: A[r][col] = q[1 + col].r
+    double A[3][3];
+#pragma unroll
+    for (int cl = 0; cl < 3; ++cl) { A[0][cl] = q[1 + cl].x; A[1][cl] = q[1 + cl].y; A[2][cl] = q[1 + cl].z; }
+    double C[3][3], AtA[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C[i][j] = A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2] - (i == j ? 1.0 : 0.0);
+            AtA[i][j] = A[0][i] * A[0][j] + A[1][i] * A[1][j] + A[2][i] * A[2][j];
+        }
+    double kv = h2s[bscene[b]] * bkappa[b] * bvol[b];
+    double eo = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) eo += C[i][j] * C[i][j];
+    E += kv * eo;
+    if (part) part[b] = E;
+    if (MODE == 0) return;
+    // gradient: 4 kv (C A)
+#pragma unroll
+    for (int cl = 0; cl < 3; ++cl) {
+        gq[1 + cl].x += 4.0 * kv * (C[0][0] * A[0][cl] + C[0][1] * A[1][cl] + C[0][2] * A[2][cl]);
+        gq[1 + cl].y += 4.0 * kv * (C[1][0] * A[0][cl] + C[1][1] * A[1][cl] + C[1][2] * A[2][cl]);
+        gq[1 + cl].z += 4.0 * kv * (C[2][0] * A[0][cl] + C[2][1] * A[1][cl] + C[2][2] * A[2][cl]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {   // body nodes are owned by this thread: plain read-modify-write
+        d3 o = ld3(g, n0 + c);
+        st3(g, n0 + c, {o.x + gq[c].x, o.y + gq[c].y, o.z + gq[c].z});
+    }
+    if (MODE < 2) return;
+    double H[45];   // over vec(A) column-major: index 3*col + row
+#pragma unroll
+    for (int bcol = 0; bcol < 3; ++bcol)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int dcol = 0; dcol < 3; ++dcol)
+#pragma unroll
+                for (int cr_ = 0; cr_ < 3; ++cr_) {
+                    int R = 3 * bcol + a, Cc = 3 * dcol + cr_;
+                    if (R > Cc) continue;
+                    H[pk9(R, Cc)] = 4.0 * kv * ((a == cr_ ? AtA[bcol][dcol] : 0.0) + A[a][dcol] * A[cr_][bcol] + (bcol == dcol ? C[a][cr_] : 0.0));
+                }
+    if (project) psd_project9(H);
+    double *Hout = Hb + 144 * (size_t)b;
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            double v = (i % 3 == j % 3) ? M[4 * (i / 3) + j / 3] : 0.0;
+            if (i >= 3 && j >= 3) v += H[pk9(i - 3, j - 3)];
+            Hout[12 * i + j] = v;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// point springs: E = h^2 k/2 |a - b|^2, each side a FEM node, a body point or a
+// drive target (the link's target affine state applied to the anchor)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ d3 spring_side(int kind, int idx, const double *xb, const double *y, const int *body_node0,
+                                          const double *targets)
+{
+    if (kind == 0) return ld3(y, idx);
+    d3 w = {xb[0], xb[1], xb[2]};
+    if (kind == 1) {
+        int n0 = body_node0[idx];
+        return xaffine(ld3(y, n0), ld3(y, n0 + 1), ld3(y, n0 + 2), ld3(y, n0 + 3), w);
+    }
+    const double *q = targets + 12 * (size_t)idx;
+    return xaffine(mk(q[0], q[1], q[2]), mk(q[3], q[4], q[5]), mk(q[6], q[7], q[8]), mk(q[9], q[10], q[11]), w);
+}
+
+__device__ __forceinline__ void spring_scatter(int kind, int idx, const double *xb, const int *body_node0, double *out, d3 f)
+{
+    if (kind == 0) atomic_add3(out, idx, f);
+    else if (kind == 1) {
+        int n0 = body_node0[idx];
+        atomic_add3(out, n0, f);
+        atomic_add3(out, n0 + 1, {xb[0] * f.x, xb[0] * f.y, xb[0] * f.z});
+        atomic_add3(out, n0 + 2, {xb[1] * f.x, xb[1] * f.y, xb[1] * f.z});
+        atomic_add3(out, n0 + 3, {xb[2] * f.x, xb[2] * f.y, xb[2] * f.z});
+    }
+}
+
+template <int MODE>   // 0 energy, 1 energy+gradient
+__global__ void k_spring(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
+                         const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
+                         const double *__restrict__ k, const int *__restrict__ sscene, const double *__restrict__ h2s,
+                         const double *__restrict__ y, const int *__restrict__ body_node0, const double *__restrict__ targets,
+                         double *__restrict__ g, double *__restrict__ part)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= NS) return;
+    d3 pa = spring_side(ka[s], ia[s], xa + 3 * (size_t)s, y, body_node0, targets);
+    d3 pb = spring_side(kb[s], ib[s], xb + 3 * (size_t)s, y, body_node0, targets);
+    d3 d = {pa.x - pb.x, pa.y - pb.y, pa.z - pb.z};
+    double kk = h2s[sscene[s]] * k[s];
+    if (part) part[s] = 0.5 * kk * dt(d, d);
+    if (MODE == 0) return;
+    d3 f = {kk * d.x, kk * d.y, kk * d.z};
+    spring_scatter(ka[s], ia[s], xa + 3 * (size_t)s, body_node0, g, f);
+    spring_scatter(kb[s], ib[s], xb + 3 * (size_t)s, body_node0, g, {-f.x, -f.y, -f.z});
+}
+
+// matrix-free spring Hessian product: out += h^2 k (J_a - J_b)^T (J_a - J_b) v,
+// with the local quadratic form v^T H v written per spring
+__global__ void k_spring_apply(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
+                               const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
+                               const double *__restrict__ k, const int *__restrict__ sscene, const double *__restrict__ h2s,
+                               const double *__restrict__ v, const int *__restrict__ body_node0, const int *__restrict__ active,
+                               double *__restrict__ out, double *__restrict__ part)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= NS) return;
+    int sc = sscene[s];
+    if (active && !active[sc]) { if (part) part[s] = 0.0; return; }
+    auto side = [&](int kind, int idx, const double *xbar) -> d3 {
+        if (kind == 0) return ld3(v, idx);
+        if (kind == 1) {
+            int n0 = body_node0[idx];
+            d3 p = ld3(v, n0), a0 = ld3(v, n0 + 1), a1 = ld3(v, n0 + 2), a2 = ld3(v, n0 + 3);
+            return {p.x + xbar[0] * a0.x + xbar[1] * a1.x + xbar[2] * a2.x, p.y + xbar[0] * a0.y + xbar[1] * a1.y + xbar[2] * a2.y,
+                    p.z + xbar[0] * a0.z + xbar[1] * a1.z + xbar[2] * a2.z};
+        }
+        return {0.0, 0.0, 0.0};
+    };
+    d3 va = side(ka[s], ia[s], xa + 3 * (size_t)s), vb = side(kb[s], ib[s], xb + 3 * (size_t)s);
+    d3 d = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
+    double kk = h2s[sc] * k[s];
+    if (part) part[s] = kk * dt(d, d);
+    d3 f = {kk * d.x, kk * d.y, kk * d.z};
+    spring_scatter(ka[s], ia[s], xa + 3 * (size_t)s, body_node0, out, f);
+    spring_scatter(kb[s], ib[s], xb + 3 * (size_t)s, body_node0, out, {-f.x, -f.y, -f.z});
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+void launch_node_inertia(ipc_ctx *c, const double *y, double *g, double *part)
+{
+    hipLaunchKernelGGL(k_node_inertia, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, y, c->d.xt.p, c->d.mass.p,
+                       c->d.node_kind.p, g, part);
+}
+
+void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)
+{
+    if (c->T == 0) return;
+    Dev &D = c->d;
+    auto args = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks_for(c->T)), dim3(BLOCK), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p, D.tmu.p,
+                           D.tlam.p, y, D.tile_scene_tet.p, h2s, g, D.val.p, D.tslot.p, (int)project, part);
+    };
+    if (mode == 0) args(k_fem<0>);
+    else if (mode == 1) args(k_fem<1>);
+    else args(k_fem<2>);
+}
+
+void launch_bsr_init(ipc_ctx *c)
+{
+    hipLaunchKernelGGL(k_bsr_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, c->d.row_ptr.p, c->d.col.p,
+                       c->d.mass.p, c->d.val.p);
+}
+
+void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)
+{
+    if (c->NB == 0) return;
+    Dev &D = c->d;
+    auto args = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.body_node0.p, D.body_scene.p,
+                           D.bM.p, D.bvol.p, D.bkappa.p, h2s, y, D.xt.p, g, D.Hb.p, (int)project, part);
+    };
+    if (mode == 0) args(k_body<0>);
+    else if (mode == 1) args(k_body<1>);
+    else args(k_body<2>);
+}
+
+void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *part, const double *h2s)
+{
+    if (c->NS == 0) return;
+    Dev &D = c->d;
+    auto args = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks_for(c->NS)), dim3(BLOCK), 0, c->stream, c->NS, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
+                           D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, y, D.body_node0.p, D.targets.p, g, part);
+    };
+    if (mode == 0) args(k_spring<0>);
+    else args(k_spring<1>);
+}
+
+void launch_spring_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part, const double *h2s)
+{
+    if (c->NS == 0) return;
+    Dev &D = c->d;
+    hipLaunchKernelGGL(k_spring_apply, dim3(blocks_for(c->NS)), dim3(BLOCK), 0, c->stream, c->NS, D.sp_ka.p, D.sp_ia.p,
+                       D.sp_xa.p, D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, v, D.body_node0.p, active, out,
+                       part);
+}
+
+} // namespace ipc

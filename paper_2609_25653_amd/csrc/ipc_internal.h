@@ -1,0 +1,252 @@
+// Internal declarations of the IPC Newton-step library (gfx950).
+//
+// Device data is laid out structure-of-arrays over all scenes.  Node ranges
+// (FEM vertices, then 4 pseudo-nodes per affine body) and tetrahedron ranges
+// of every scene are padded to a multiple of TILE = 64 (one wavefront), so a
+// wavefront never straddles two scenes: reductions write one partial per
+// wavefront and a per-scene pass sums a scene's partials in a fixed order,
+// which keeps energies and dot products bit-reproducible run to run.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ipc.h"
+
+namespace ipc {
+
+constexpr int TILE = 64;      // wavefront size on CDNA
+constexpr int BLOCK = 256;    // default workgroup: 4 wavefronts
+
+// per-scene device scalar slots
+enum Slot {
+    S_E = 0,        // energy (sum over terms)
+    S_RZ,           // PCG r.z
+    S_RZ_NEW,
+    S_PAP,          // p.Ap
+    S_RR,           // r.r
+    S_BB,           // b.b
+    S_ALPHA,        // PCG alpha
+    S_BETA,         // PCG beta
+    S_ACTIVE,       // 1 while the scene's PCG iterates
+    S_NEWTON_MAX,   // Newton measure (max world displacement of p)
+    S_CCD,          // CCD step bound (stored through its bit pattern, atomic min)
+    S_LS_ALPHA,     // line-search step of the scene
+    S_LS_ON,        // 1 while the scene takes part in the current Newton iteration
+    S_INF,          // 1 when some pair has d <= 0
+    S_E_IN, S_E_FEM, S_E_ABD, S_E_SP, S_E_BAR, S_E_FR,
+    S_ETA,          // PCG relative tolerance of the scene
+    S_E0,           // line search: energy at the current iterate
+    S_NEWTON_ON,    // 1 while the scene's Newton loop runs
+    NSLOT
+};
+
+// per-scene segment tables (device, n_scenes + 1 entries each)
+enum Region {
+    R_NODEW = 0,    // wavefront tiles of nodes
+    R_TETW,         // wavefront tiles of tetrahedra
+    R_BODY, R_SP, R_SURF, R_TRI, R_EDGE,
+    R_CPT, R_CEE,   // candidates
+    R_PT, R_EE,     // active pairs
+    R_LPT, R_LEE,   // friction lag lists
+    R_QSEG, R_PSEG, R_TMP,
+    NREGION
+};
+
+// per-scene parameters (device, 8 per scene)
+enum Param { P_H2 = 0, P_KAPPA = 1, P_DHAT = 2, P_MU = 3, P_EPSH = 4, P_CCDS = 5, P_H = 6 };
+
+struct RedSrc {
+    const double *v;
+    const int *seg;
+    int off;
+    int base;
+};
+struct RedArgs {
+    RedSrc src[8];
+    int nsrc = 0;
+    int slot = -1;          // total goes here (-1: none)
+    int acc = 0;            // accumulate into the total slot
+    int slots[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // per-source sums (-1: none)
+    int op = 0;             // 0 sum, 1 max
+};
+
+#define IPC_HIP(call)                                                           \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) throw ipc::Error(IPC_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Error {
+    int code;
+    std::string msg;
+    Error(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { if (p) (void)hipFree(p); }
+    void alloc(size_t count)
+    {
+        if (count <= n && p) return;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        if (count == 0) count = 1;
+        IPC_HIP(hipMalloc(&p, count * sizeof(T)));
+        n = count;
+    }
+    void upload(const std::vector<T> &h, hipStream_t s)
+    {
+        alloc(h.size());
+        if (!h.empty()) IPC_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void zero(hipStream_t s, size_t count)
+    {
+        if (count) IPC_HIP(hipMemsetAsync(p, 0, count * sizeof(T), s));
+    }
+};
+
+struct SceneInfo {
+    // sizes
+    int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd;
+    // offsets into the concatenated device arrays
+    int node0, nnode, nnode_pad;     // nodes: FEM vertices then 4 per body
+    int tet0, nt_pad;
+    int body0, drv0, sp0;
+    int cv0, ncv, nsurf;             // contact vertices; the first nsurf are PT query points
+    int tri0, ntri, edge0, nedge;
+    int obj0;
+    int64_t dof0;                    // external DOF offset
+    // parameters
+    double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
+    int max_newton, max_pcg;
+    double L, thr, mbar;
+    // host topology in the scene's vertex numbering (for the pair export)
+    std::vector<int> tri_ext, edge_ext, surf_ext;
+};
+
+struct Dev {
+    // nodes
+    DBuf<double> y, ydot, xt, y0, yt, g, p, r, z, q, x, v1, v2;
+    DBuf<int> node_scene, node_kind;       // kind: 0 FEM, 1 body node, 2 padding
+    DBuf<double> mass;                     // lumped FEM vertex mass (0 elsewhere)
+    DBuf<double> dinv;                     // 3x3 inverse diagonal block per node
+    DBuf<double> diagF;                    // 3x3 diagonal block accumulators
+    DBuf<double> fem_sp_diag;              // constant spring diagonal of FEM nodes
+    DBuf<int> ext2node;                    // external node -> internal node
+    // tetrahedra (SoA over the padded tet range)
+    DBuf<int4> tv;
+    DBuf<double> Bm;                       // 9 arrays of nT
+    DBuf<double> vol, tmu, tlam;
+    DBuf<int> tslot;                       // 16 BSR slots per tet (row-major a*4+b)
+    // FEM matrix (block CSR, 3x3 blocks, rows = nodes)
+    DBuf<int> row_ptr, col, diag_slot;
+    DBuf<double> val;
+    // bodies
+    DBuf<double> bM;                       // 4x4 mass matrix per body
+    DBuf<double> bvol, bkappa, bext;
+    DBuf<int> body_node0, body_scene;
+    DBuf<double> Hb;                       // 12x12 inertia + orthogonality block
+    DBuf<double> diagB, dinvB, body_sp_diag;
+    // springs
+    DBuf<int> sp_ka, sp_ia, sp_kb, sp_ib, sp_scene;
+    DBuf<double> sp_xa, sp_xb, sp_k;
+    DBuf<double> targets;                  // 12 per driven slot
+    DBuf<int> driven_body;
+    DBuf<double> sp_part;                  // per-spring values for reductions
+    DBuf<double> body_part;
+    // contact vertices, triangles, edges
+    DBuf<int> cv_node, cv_body, cv_obj, cv_scene;
+    DBuf<double> cv_x;                     // body-frame point or static world point
+    DBuf<double> xw, xw1;                  // world positions at y and at y + p
+    DBuf<int4> tri;                        // (cv0, cv1, cv2, scene)
+    DBuf<int2> edge;
+    DBuf<double> edge_rest2;
+    DBuf<int> obj_kind, excl;              // global object ids
+    // broad phase (LBVH per scene and primitive kind)
+    DBuf<double> box;                      // 6 per primitive (lo, hi)
+    DBuf<unsigned long long> mkey, mkey2;
+    DBuf<int> mid, mid2;
+    DBuf<int> bvh_left, bvh_right, bvh_parent, bvh_flag;
+    DBuf<double> bvh_box;
+    DBuf<int> qcount, qoff;                // per-query candidate counts and offsets
+    DBuf<unsigned char> sort_tmp;
+    DBuf<double> scene_lo;                 // Morton quantisation box per scene (6)
+    // candidates and active pairs
+    DBuf<int2> cand_pt, cand_ee;
+    DBuf<int2> pt, ee;
+    DBuf<int> wcount, woff;
+    DBuf<double> pair_part;                // per-pair reduction values
+    DBuf<int4> pair_cv;                    // 4 contact vertices per active pair (PT then EE)
+    DBuf<double> pair_H;                   // 45 per pair: projected reduced Hessian
+    // friction lag
+    DBuf<int4> lag_cv;
+    DBuf<double> lag_beta, lag_nrm, lag_lam, lag_rn;
+    DBuf<double> lag_M;                    // 6 (symmetric 3x3) per lag pair, scaled
+    // scalars and partials
+    DBuf<double> scal;                     // n_scenes x NSLOT
+    DBuf<double> part_node, part_tet;      // one partial per wavefront
+    DBuf<int> seg;                         // scratch segment offsets (broad phase)
+    DBuf<int> segs;                        // NREGION tables of n_scenes + 1
+    DBuf<int> tile_scene_node, tile_scene_tet;
+    DBuf<double> part_node2, fr_part;
+    DBuf<double> sparam, h2s;              // per-scene parameters
+    DBuf<int> inf_flag, ls_active, pcg_active, pcg_iters, maxpcg, newton_on;
+    DBuf<int> leafpar, is_trans;
+    DBuf<double> grav;
+    DBuf<double> red_tmp;
+};
+
+} // namespace ipc
+
+struct ipc_ctx {
+    hipStream_t stream = nullptr;
+    int n_scenes = 0;
+    std::vector<ipc::SceneInfo> sc;
+    int64_t ndof = 0;
+    int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
+    int nnzb = 0;
+    int64_t ext_nodes = 0;
+    // host copies of segment tables
+    std::vector<int> seg_surf, seg_tri, seg_edge, seg_sp, seg_body;
+    // dynamic counts
+    int64_t cap_cand_pt = 0, cap_cand_ee = 0, n_cand_pt = 0, n_cand_ee = 0;
+    int64_t cap_pt = 0, cap_ee = 0, n_pt = 0, n_ee = 0, cap_lag = 0, n_lag = 0;
+    std::vector<int> h_cand_pt_seg, h_cand_ee_seg, h_pt_seg, h_ee_seg, h_lag_seg;
+    ipc::Dev d;
+    bool step_ready = false;
+    bool fr_on = true;
+    int64_t n_lag_pt = 0;
+    int last_status = 0;
+    // host staging for small uploads (kept alive until the copy has completed)
+    std::vector<double> h_scal_stage;
+    std::vector<int> h_seg_stage, h_int_stage;
+    std::string err;
+};
+
+namespace ipc {
+
+// ---- helpers implemented in the .hip files ---------------------------------
+void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n);
+void reduce(ipc_ctx *c, const RedArgs &a);
+RedSrc src(const double *v, const int *seg, int off, int base);
+int *seg_ptr(ipc_ctx *c, int region);
+void store_cand_segs(ipc_ctx *c);
+void store_pair_segs(ipc_ctx *c);
+__global__ void k_fill_int_api(int n, int *p, int v);
+void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool partials);
+void build_preconditioner(ipc_ctx *c);
+void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
+
+// launch helper
+inline int blocks_for(int64_t n, int bs = BLOCK) { return (int)((n + bs - 1) / bs); }
+
+} // namespace ipc

@@ -1,0 +1,125 @@
+"""Parity of the HIP library with the oracle at identical inputs (needs a GPU).
+
+Bars: contact-pair sets bit-exact; energies within 1e-10 of the sum of the
+absolute terms; gradients within 1e-10 of the per-entry sum of absolute
+contributions; Hessian products within 1e-9 relative; trajectories within
+1e-6 of the scene's bounding-box diagonal at every step.
+"""
+import numpy as np
+import pytest
+
+import ipcscenes as S
+import oracle as O
+from gpu_util import assert_grad_close, energy_tol, oracle_states, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a ROCm GPU")]
+
+rng = np.random.default_rng(99)
+
+CASES = {
+    "block": (lambda: S.block_drop(n_steps=8), [0, 2, 6]),
+    "cube": (lambda: S.tiny_scene("cube", h=0.01, n_steps=8), [0, 6]),
+    "pad_box": (lambda: S.tiny_scene("pad_box", h=0.01, n_steps=34), [0, 20, 32]),
+}
+
+
+@pytest.fixture(scope="module")
+def states():
+    out = {}
+    for name, (mk, steps) in CASES.items():
+        sc = mk()
+        _, traj = oracle_states(sc, max(steps))
+        out[name] = (sc, [(k, traj[k]) for k in steps])
+    return out
+
+
+def _pair(sim, o, sc, k, y, v):
+    sim.set_state(y, v)
+    sim.begin_step(k)
+    o.set_state(y, v)
+    o.begin_step(k)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_gradient_hessian(name, states):
+    from paper_2609_25653_amd import Sim
+    sc, st = states[name]
+    sim = Sim(sc)
+    o = O.Oracle(sc)
+    assert sim.ndof == o.ndof
+    assert sim.scene_scalars()["kappa"] == pytest.approx(o.kappa, rel=1e-13)
+    for k, (y, v) in st:
+        _pair(sim, o, sc, k, y, v)
+        yq = y + 1e-7 * rng.standard_normal(len(y)) * (np.arange(len(y)) < 3 * len(sc["X"]))
+        E_or, terms = o.energy(yq)
+        g_or, gabs = o.gradient(yq)
+        for project in (True, False):
+            vv = rng.standard_normal(len(y))
+            E, g, Hv, rc = sim.energy_grad_hess(yq, vv, project=project, friction=True)
+            assert rc == 0
+            assert abs(to_np(E)[0] - E_or) <= energy_tol(terms), (k, to_np(E)[0], E_or)
+            assert_grad_close(to_np(g), g_or, gabs)
+            Hv_or = o.hess_matvec(yq, vv, project)
+            err = np.linalg.norm(to_np(Hv) - Hv_or)
+            assert err <= 1e-9 * np.linalg.norm(Hv_or), (name, k, project, err / np.linalg.norm(Hv_or))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pairs_bit_exact(name, states):
+    from paper_2609_25653_amd import Sim
+    sc, st = states[name]
+    sim = Sim(sc)
+    o = O.Oracle(sc)
+    for k, (y, v) in st:
+        pt, ee = sim.pairs(y)
+        opt, oee = o.pairs(y)
+        assert np.array_equal(pt, opt), (name, k, len(pt), len(opt))
+        assert np.array_equal(ee, oee), (name, k, len(ee), len(oee))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_ccd(name, states):
+    from paper_2609_25653_amd import Sim
+    sc, st = states[name]
+    sim = Sim(sc)
+    o = O.Oracle(sc)
+    for k, (y, v) in st:
+        for scale in (1e-4, 3e-3):
+            p = scale * rng.standard_normal(len(y))
+            a = to_np(sim.ccd(y, p))[0]
+            a_or = o.ccd(y, p)
+            assert a == pytest.approx(a_or, rel=1e-12, abs=1e-15), (name, k, scale, a, a_or)
+
+
+@pytest.mark.parametrize("name", ["block", "pad_box"])
+def test_pcg(name, states):
+    from paper_2609_25653_amd import Sim
+    sc, st = states[name]
+    sim = Sim(sc)
+    o = O.Oracle(sc)
+    k, (y, v) = st[-1]
+    _pair(sim, o, sc, k, y, v)
+    b = rng.standard_normal(len(y))
+    x, it = sim.pcg(y, b, 1e-12)
+    x_or, it_or = o.pcg(y, b, 1e-12)
+    assert np.linalg.norm(to_np(x) - x_or) <= 1e-9 * np.linalg.norm(x_or)
+    assert abs(int(it[0]) - it_or) <= max(2, it_or // 20)
+
+
+@pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34)])
+def test_trajectory(name, n):
+    from paper_2609_25653_amd import Sim
+    sc = S.block_drop(n_steps=n) if name == "block" else S.tiny_scene("pad_box", h=0.01, n_steps=n)
+    sim = Sim(sc)
+    o = O.Oracle(sc)
+    L = o.L
+    for k in range(n):
+        rc, stats = sim.step()
+        rco, so = o.step()
+        assert rc == 0 and rco == 0, (k, stats, so)
+        y = to_np(sim.state()[0])
+        yo, _ = o.state()
+        err = np.abs(y - yo).max()
+        assert err <= 1e-6 * L, (name, k, err / L, stats[0], so)
