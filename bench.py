@@ -1,0 +1,144 @@
+"""Benchmark: IPC Newton steps of the contact-rich soft-gripper scene on one MI355X.
+
+Workload: two 10k-tet pads squeezing a ~180k-tet soft cylinder (log-normal
+Young's modulus) that rests on a finely meshed static ground patch, 200k tets
+in all, dhat = 5e-4 m, dt = 5 ms.  Synthetic seeded geometry; FP64 throughout.
+
+Timed: K full steps (every Newton iteration with assembly, PCG, CCD, line
+search), after W untimed warm-up steps, between device synchronisations.  The
+JSON line reports Newton iterations per second as ``value`` plus steps per
+second, the roofline object of the dominant kernel (durations from HIP events
+the library records on its own stream during the timed steps) and the oracle's
+CPU throughput on a bounded sample of the same workload.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Newton iters/s & sim steps/s at 200k tets; batched scenes/s; adjoint/forward time"
+HBM_PEAK_GBS = 8000.0
+KERNELS = {0: "spmv_bsr", 1: "fem_grad_hess", 2: "barrier_grad_hess", 3: "contact_apply", 4: "pcg_update",
+           5: "broad_phase", 6: "ccd", 7: "fem_energy"}
+
+
+def kernel_times(sim):
+    from paper_2609_25653_amd import lib
+    out = {}
+    for k, name in KERNELS.items():
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        rc = lib().ipc_kernel_time(sim._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
+        if rc == 0 and n.value > 0:
+            out[name] = dict(total_ms=ms.value, launches=n.value, avg_us=1e3 * ms.value / n.value,
+                             bytes_per_launch=b.value / n.value)
+    return out
+
+
+def cpu_baseline(scene, pcg_per_newton):
+    """Oracle timing on a bounded sample: one assembly + solve of the first
+    Newton iteration of step 0, split into the assembly and the per-iteration
+    PCG cost, scaled to Newton iterations/s with the GPU's measured mean PCG
+    iterations per Newton iteration (CCD and line search are not counted, which
+    favours the CPU)."""
+    import numpy as np
+    import oracle as O
+    sc1 = dict(scene); sc1["max_pcg"] = np.asarray(1.0)
+    sc2 = dict(scene); sc2["max_pcg"] = np.asarray(6.0)
+    times = []
+    for sc in (sc1, sc2):
+        o = O.Oracle(sc)
+        o.begin_step(0)
+        y, _ = o.state()
+        g, _ = o.gradient(y)
+        t0 = time.perf_counter()
+        _, it = o.pcg(y, -g, 1e-300)
+        times.append((time.perf_counter() - t0, it))
+        del o
+    (t1, i1), (t2, i2) = times
+    t_iter = max((t2 - t1) / max(i2 - i1, 1), 0.0)
+    t_asm = max(t1 - i1 * t_iter, 0.0)
+    t_newton = t_asm + pcg_per_newton * t_iter
+    cores = len(os.sched_getaffinity(0))
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    return {"value": 1.0 / t_newton, "unit": "Newton iters/s", "cores": int(os.environ.get("OMP_NUM_THREADS", cores)),
+            "kind": "oracle",
+            "sample": (f"step 0 of the 200k-tet scene: assembly {t_asm:.2f} s + {t_iter:.3f} s per PCG iteration "
+                       f"(timed with 1 and 6 iterations), scaled by {pcg_per_newton:.0f} PCG iterations per Newton "
+                       f"iteration; CPU {model}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--s-g", type=float, default=1e-3, help="ground patch spacing (m)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (scenes would shard without "
+              f"communication, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import ipcscenes
+    from paper_2609_25653_amd import Sim, lib
+
+    n_total = args.warmup + args.steps
+    scene = ipcscenes.contact_rich(n_steps=n_total, s_g=args.s_g)
+    sim = Sim(scene)
+    for _ in range(args.warmup):
+        sim.step(allow_status=(3,))
+    torch.cuda.synchronize()
+    lib().ipc_profile(sim._h, 1)
+    newton = pcg = 0
+    pairs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, st = sim.step(allow_status=(3,))
+        newton += st[0]["newton_iters"]
+        pcg += st[0]["pcg_iters_total"]
+        pairs.append(st[0]["n_pt_max"] + st[0]["n_ee_max"])
+        print(f"# step {sim.step_index}: rc={rc} newton={st[0]['newton_iters']} pcg={st[0]['pcg_iters_total']} "
+              f"pairs={pairs[-1]} alpha_min={st[0]['alpha_min']:.3g}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    kt = kernel_times(sim)
+    lib().ipc_profile(sim._h, 0)
+    spmv = kt.get("spmv_bsr")
+    roof = None
+    if spmv:
+        achieved = spmv["bytes_per_launch"] / (spmv["avg_us"] * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_spmv (block-CSR FEM Hessian product)",
+                "bytes_per_launch": spmv["bytes_per_launch"], "avg_us": spmv["avg_us"]}
+    line = {
+        "metric": METRIC, "value": newton / t, "unit": "Newton iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "contact-rich squeeze: 2 pads + soft cylinder on a ground patch",
+                   "tets": int(len(scene["tets"])), "vertices": int(len(scene["X"])), "dhat": float(scene["dhat"]),
+                   "dt": float(scene["h"]), "ground_spacing": args.s_g, "parallelism": "single GPU"},
+        "steps_per_s": args.steps / t,
+        "newton_per_step": newton / args.steps,
+        "pcg_per_newton": pcg / max(newton, 1),
+        "active_pairs": {"min": int(min(pairs)), "median": float(np.median(pairs)), "max": int(max(pairs))},
+        "roofline": roof,
+        "kernels": kt,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, pcg / max(newton, 1))
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

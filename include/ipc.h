@@ -187,6 +187,28 @@ int ipc_pcg(ipc_ctx *ctx, const double *y_dev, const double *b_dev, double *x_de
  * scene status (IPC_E_NOT_CONVERGED leaves that scene at its last iterate). */
 int ipc_step(ipc_ctx *ctx, const double *targets_dev, ipc_stats *stats_host);
 
+/* Kernel timing for measurement.  ipc_profile(ctx, 1) resets the counters
+ * and starts recording HIP events on the context's stream around the timed
+ * kernels (ipc_profile(ctx, 0) stops).  ipc_kernel_time() returns, for one
+ * timed kernel, the summed duration of its launches since the reset, the
+ * launch count and the summed algorithmic bytes of those launches (the bytes
+ * the operation must move at minimum for its storage format: for IPC_K_SPMV,
+ * 76 per stored 3x3 block (9 doubles + column index), 4 per row pointer, and
+ * 24 read plus 24 written per FEM vertex). */
+enum {
+    IPC_K_SPMV = 0,          /* block-CSR product of the FEM Hessian            */
+    IPC_K_FEM_HESS = 1,      /* FEM gradient + projected Hessian assembly        */
+    IPC_K_BARRIER_HESS = 2,  /* barrier gradient + projected Hessian per pair    */
+    IPC_K_CONTACT_APPLY = 3, /* contact / friction Hessian product               */
+    IPC_K_PCG_UPDATE = 4,    /* PCG vector update + preconditioner               */
+    IPC_K_BROAD = 5,         /* LBVH build + traversal (both primitive kinds)    */
+    IPC_K_CCD = 6,           /* additive CCD over candidates                     */
+    IPC_K_FEM_ENERGY = 7,    /* FEM energy for the line search                    */
+    IPC_K_COUNT = 8
+};
+int ipc_profile(ipc_ctx *ctx, int enable);
+int ipc_kernel_time(ipc_ctx *ctx, int kernel, double *total_ms, int64_t *launches, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

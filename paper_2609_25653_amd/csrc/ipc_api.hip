@@ -732,3 +732,88 @@ extern "C" int ipc_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats_
     if (c->last_status != IPC_OK) c->err = "a scene did not finish its step cleanly (see ipc_stats.status)";
     return c->last_status;
 }
+
+// ---------------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------------
+namespace ipc {
+
+static void prof_flush(ipc_ctx *c, int k)
+{
+    auto &T = c->timers[k];
+    if (T.ev.empty()) return;
+    IPC_HIP(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i + 1 < T.ev.size(); i += 2) {
+        float ms = 0.0f;
+        IPC_HIP(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
+        T.total_ms += ms;
+    }
+    for (auto e : T.ev) T.pool.push_back(e);
+    T.ev.clear();
+}
+
+static hipEvent_t prof_event(ipc_ctx *c, int k)
+{
+    auto &T = c->timers[k];
+    if (T.pool.empty()) {
+        hipEvent_t e;
+        IPC_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = T.pool.back();
+    T.pool.pop_back();
+    return e;
+}
+
+void prof_begin(ipc_ctx *c, int k)
+{
+    if (!c->prof) return;
+    hipEvent_t e = prof_event(c, k);
+    IPC_HIP(hipEventRecord(e, c->stream));
+    c->timers[k].ev.push_back(e);
+}
+
+void prof_end(ipc_ctx *c, int k, double bytes)
+{
+    if (!c->prof) return;
+    hipEvent_t e = prof_event(c, k);
+    IPC_HIP(hipEventRecord(e, c->stream));
+    auto &T = c->timers[k];
+    T.ev.push_back(e);
+    T.launches += 1;
+    T.bytes += bytes;
+    if (T.ev.size() >= 2048) prof_flush(c, k);
+}
+
+} // namespace ipc
+
+ipc_ctx::~ipc_ctx()
+{
+    for (auto &T : timers) {
+        for (auto e : T.ev) (void)hipEventDestroy(e);
+        for (auto e : T.pool) (void)hipEventDestroy(e);
+    }
+}
+
+extern "C" int ipc_profile(ipc_ctx *c, int enable)
+{
+    if (!c) return IPC_E_INVALID;
+    return guard(c, [&] {
+        for (int k = 0; k < IPC_K_COUNT; ++k) {
+            prof_flush(c, k);
+            if (enable) { c->timers[k].total_ms = 0.0; c->timers[k].launches = 0; c->timers[k].bytes = 0.0; }
+        }
+        c->prof = enable != 0;
+    });
+}
+
+extern "C" int ipc_kernel_time(ipc_ctx *c, int kernel, double *total_ms, int64_t *launches, double *bytes)
+{
+    if (!c || kernel < 0 || kernel >= IPC_K_COUNT) return IPC_E_INVALID;
+    return guard(c, [&] {
+        prof_flush(c, kernel);
+        if (total_ms) *total_ms = c->timers[kernel].total_ms;
+        if (launches) *launches = c->timers[kernel].launches;
+        if (bytes) *bytes = c->timers[kernel].bytes;
+    });
+}

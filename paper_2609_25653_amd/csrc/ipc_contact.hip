@@ -361,8 +361,10 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
 
 void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1)
 {
+    prof_begin(c, IPC_K_BROAD);
     bvh_query(c, 0, xw0, xw1, c->d.cand_pt, c->cap_cand_pt, c->n_cand_pt, c->h_cand_pt_seg);
     bvh_query(c, 1, xw0, xw1, c->d.cand_ee, c->cap_cand_ee, c->n_cand_ee, c->h_cand_ee_seg);
+    prof_end(c, IPC_K_BROAD, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -677,9 +679,11 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, dou
                            D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, g,
                            D.pair_cv.p, D.pair_H.p, D.diagF.p, D.diagB.p, D.pair_part.p, (int)project, D.inf_flag.p);
     };
+    if (mode == 2) prof_begin(c, IPC_K_BARRIER_HESS);
     if (mode == 0) go(k_barrier<0>);
     else if (mode == 1) go(k_barrier<1>);
     else go(k_barrier<2>);
+    if (mode == 2) prof_end(c, IPC_K_BARRIER_HESS, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -938,9 +942,11 @@ void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1)
     Dev &D = c->d;
     int64_t n = c->n_cand_pt + c->n_cand_ee;
     if (n == 0) return;
+    prof_begin(c, IPC_K_CCD);
     hipLaunchKernelGGL(k_ccd, dim3(blocks_for(n, 64)), dim3(64), 0, c->stream, (int)c->n_cand_pt, (int)c->n_cand_ee, D.cand_pt.p,
                        D.cand_ee.p, D.tri.p, D.edge.p, xw0, xw1, D.cv_scene.p, D.sparam.p, D.ls_active.p,
                        (unsigned long long *)(D.scal.p + S_CCD), NSLOT);
+    prof_end(c, IPC_K_CCD, 0.0);
 }
 
 } // namespace ipc

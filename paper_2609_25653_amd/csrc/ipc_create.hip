@@ -259,6 +259,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         S.edge_ext.resize(2 * (size_t)S.nedge);
         for (int k = 0; k < S.nedge; ++k) for (int m = 0; m < 2; ++m) S.edge_ext[2 * k + m] = topo[s].edge[k][m];
     }
+    for (int s = 0; s < n; ++s) { c->NFEM += scenes[s].nv; c->TREAL += scenes[s].nt; }
     c->N = node; c->T = tet; c->NB = body; c->ND = drv; c->NS = sp; c->CV = cv; c->NSURF = cv; c->TRI = tri;
     c->EDGE = edge; c->NOBJ = obj; c->NEX = ex; c->ndof = dof; c->ext_nodes = dof / 3;
 

@@ -334,9 +334,12 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
         hipLaunchKernelGGL(kern, dim3(blocks_for(c->T)), dim3(BLOCK), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p, D.tmu.p,
                            D.tlam.p, y, D.tile_scene_tet.p, h2s, g, D.val.p, D.tslot.p, (int)project, part);
     };
+    int k = mode == 2 ? IPC_K_FEM_HESS : (mode == 0 ? IPC_K_FEM_ENERGY : -1);
+    if (k >= 0) prof_begin(c, k);
     if (mode == 0) args(k_fem<0>);
     else if (mode == 1) args(k_fem<1>);
     else args(k_fem<2>);
+    if (k >= 0) prof_end(c, k, mode == 2 ? 112.0 * c->TREAL + 48.0 * c->NFEM + 72.0 * c->nnzb : 112.0 * c->TREAL + 24.0 * c->NFEM);
 }
 
 void launch_bsr_init(ipc_ctx *c)

@@ -213,6 +213,7 @@ struct ipc_ctx {
     std::vector<ipc::SceneInfo> sc;
     int64_t ndof = 0;
     int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
+    int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
     int nnzb = 0;
     int64_t ext_nodes = 0;
     // host copies of segment tables
@@ -229,6 +230,17 @@ struct ipc_ctx {
     // host staging for small uploads (kept alive until the copy has completed)
     std::vector<double> h_scal_stage;
     std::vector<int> h_seg_stage, h_int_stage;
+    // kernel timing (HIP events on the context's stream, only while enabled)
+    struct Timer {
+        std::vector<hipEvent_t> ev;      // start/stop pairs not yet read
+        std::vector<hipEvent_t> pool;
+        double total_ms = 0.0;
+        int64_t launches = 0;
+        double bytes = 0.0;              // algorithmic bytes of the launches counted
+    };
+    bool prof = false;
+    Timer timers[IPC_K_COUNT];
+    ~ipc_ctx();
     std::string err;
 };
 
@@ -240,6 +252,8 @@ void reduce(ipc_ctx *c, const RedArgs &a);
 RedSrc src(const double *v, const int *seg, int off, int base);
 int *seg_ptr(ipc_ctx *c, int region);
 void store_cand_segs(ipc_ctx *c);
+void prof_begin(ipc_ctx *c, int k);
+void prof_end(ipc_ctx *c, int k, double bytes);
 void store_pair_segs(ipc_ctx *c);
 __global__ void k_fill_int_api(int n, int *p, int v);
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool partials);

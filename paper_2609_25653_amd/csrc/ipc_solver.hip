@@ -117,15 +117,19 @@ void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, boo
 {
     Dev &D = c->d;
     hipStream_t st = c->stream;
+    prof_begin(c, IPC_K_SPMV);
     hipLaunchKernelGGL(k_spmv, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.row_ptr.p, D.col.p, D.val.p, v, D.node_scene.p,
                        active, out, partials ? D.part_node.p : nullptr);
+    prof_end(c, IPC_K_SPMV, 76.0 * c->nnzb + 4.0 * (c->N + 1) + 48.0 * c->NFEM);
     if (c->NB)
         hipLaunchKernelGGL(k_body_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.body_scene.p, D.Hb.p,
                            active, v, out, partials ? D.body_part.p : nullptr);
     launch_spring_apply(c, v, out, active, partials ? D.sp_part.p : nullptr, D.h2s.p);
     D.pair_part.alloc(c->n_pt + c->n_ee + 1);
     D.fr_part.alloc(c->n_lag + 1);
+    prof_begin(c, IPC_K_CONTACT_APPLY);
     launch_contact_apply(c, v, out, active, partials ? D.pair_part.p : nullptr, partials ? D.fr_part.p : nullptr);
+    prof_end(c, IPC_K_CONTACT_APPLY, 0.0);
     if (partials) {
         RedArgs a{};
         a.nsrc = 0;
@@ -361,8 +365,10 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
     const int check_every = 8;
     for (int it = 0; it < maxit; ++it) {
         hess_apply(c, p, Ap, active, true);
+        prof_begin(c, IPC_K_PCG_UPDATE);
         hipLaunchKernelGGL(k_pcg_update, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.node_scene.p, active,
                            D.scal.p, D.dinv.p, p, Ap, x, r, z, D.part_node.p, D.part_node2.p);
+        prof_end(c, IPC_K_PCG_UPDATE, 240.0 * c->NFEM);
         if (c->NB)
             hipLaunchKernelGGL(k_body_prec_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.body_scene.p,
                                D.dinvB.p, active, r, z, D.body_part.p);
