@@ -1,0 +1,74 @@
+"""Batched form: scenes of uneven size stepped together in one context must
+match the same scenes stepped one at a time (each scene keeps its own Newton,
+PCG and line-search decisions), and the oracle (needs a GPU)."""
+import numpy as np
+import pytest
+
+import ipcscenes as S
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a ROCm GPU")]
+
+
+def _mixed(n_steps):
+    return [S.block_drop(n_steps=n_steps),
+            S.tiny_scene("pad_box", h=0.01, n_steps=n_steps),
+            S.tiny_scene("cube", h=0.01, n_steps=n_steps),
+            S.tiny_scene("pad_box", seed=3, h=0.01, n_steps=n_steps)]
+
+
+def test_batched_matches_single_and_oracle():
+    from paper_2609_25653_amd import Sim
+    n = 12
+    scenes = _mixed(n)
+    batch = Sim(scenes)
+    singles = [Sim(s) for s in scenes]
+    oracles = [O.Oracle(s) for s in scenes]
+    offs = batch.dof_offsets
+    for k in range(n):
+        rc, st = batch.step()
+        assert rc == 0, st
+        yb = batch.state()[0].cpu().numpy()
+        for i, (sim, o) in enumerate(zip(singles, oracles)):
+            rc1, st1 = sim.step()
+            assert rc1 == 0
+            assert o.step()[0] == 0
+            y1 = sim.state()[0].cpu().numpy()
+            yo = o.state()[0]
+            part = yb[offs[i]:offs[i + 1]]
+            assert abs(st[i]["newton_iters"] - st1[0]["newton_iters"]) <= 1, (k, i, st[i], st1[0])
+            assert np.abs(part - y1).max() <= 1e-6 * o.L, (k, i)
+            assert np.abs(part - yo).max() <= 1e-6 * o.L, (k, i)
+
+
+def test_batched_pairs_per_scene():
+    from paper_2609_25653_amd import Sim
+    scenes = _mixed(4)
+    batch = Sim(scenes)
+    y, _ = batch.state()
+    yb = y.cpu().numpy()
+    for i, s in enumerate(scenes):
+        o = O.Oracle(s)
+        pt, ee = batch.pairs(yb, scene=i)
+        opt, oee = o.pairs(yb[batch.dof_offsets[i]:batch.dof_offsets[i + 1]])
+        assert np.array_equal(pt, opt) and np.array_equal(ee, oee)
+
+
+def test_batched_squeeze_generator_small():
+    """A few scenes of the uneven squeeze batch: batched equals one at a time."""
+    from paper_2609_25653_amd import Sim
+    scenes = S.batched_squeeze(seed=5, n_scenes=3, n_steps=3)
+    batch = Sim(scenes)
+    singles = [Sim(s) for s in scenes]
+    for k in range(3):
+        rc, st = batch.step(allow_status=(3,))
+        yb = batch.state()[0].cpu().numpy()
+        for i, sim in enumerate(singles):
+            rc1, st1 = sim.step(allow_status=(3,))
+            assert rc1 == st[i]["status"]
+            y1 = sim.state()[0].cpu().numpy()
+            part = yb[batch.dof_offsets[i]:batch.dof_offsets[i + 1]]
+            L = sim.scene_scalars(0)["L"]
+            assert np.abs(part - y1).max() <= 1e-6 * L, (k, i)   # FP64 atomics make the sum order vary
