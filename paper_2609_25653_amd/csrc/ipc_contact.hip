@@ -519,13 +519,51 @@ __device__ __forceinline__ void diag_contrib(const Map *m, const int *cvb, doubl
     }
 }
 
+// When every dynamic vertex of a pair is a FEM node and each pair of them
+// already shares a block of the matrix (same tetrahedral mesh, adjacent - as
+// for a surface triangle or edge against static geometry), add the pair's
+// world-vertex blocks straight into the block-CSR values and report true; the
+// pair then costs nothing in the PCG products.
+__device__ __forceinline__ int find_block(const int *row_ptr, const int *col, int r, int cc)
+{
+    int lo = row_ptr[r], hi = row_ptr[r + 1];
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (col[m] < cc) lo = m + 1; else hi = m;
+    }
+    return (lo < row_ptr[r + 1] && col[lo] == cc) ? lo : -1;
+}
+template <class F>
+__device__ __forceinline__ bool merge_into_bsr(const Map *m, const int *row_ptr, const int *col, double *val, F blk)
+{
+    int slot[4][4];
+    for (int k = 0; k < 4; ++k) {
+        if (m[k].body >= 0) return false;
+        for (int l = 0; l < 4; ++l) {
+            slot[k][l] = -1;
+            if (m[k].node < 0 || m[l].node < 0) continue;
+            slot[k][l] = find_block(row_ptr, col, m[k].node, m[l].node);
+            if (slot[k][l] < 0) return false;
+        }
+    }
+    double B[9];
+    for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l) {
+            if (slot[k][l] < 0) continue;
+            blk(k, l, B);
+            double *d = val + 9 * (size_t)slot[k][l];
+            for (int q = 0; q < 9; ++q) atomicAdd(d + q, B[q]);
+        }
+    return true;
+}
+
 template <int MODE>   // 0 energy, 1 energy + gradient, 2 gradient + projected Hessian
 __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee,
     const int4 *__restrict__ tri, const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
     const double *__restrict__ sparam, const double *__restrict__ rest2, const int *__restrict__ cv_node,
     const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ g,
     int4 *__restrict__ pair_cv, double *__restrict__ pair_H, double *__restrict__ diagF, double *__restrict__ diagB,
-    double *__restrict__ pe, int project, int *__restrict__ inf_flag)
+    double *__restrict__ pe, int project, int *__restrict__ inf_flag, const int *__restrict__ row_ptr, const int *__restrict__ col, double *__restrict__ val, int *__restrict__ pair_flag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npt + nee) return;
@@ -542,12 +580,12 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     if (!(d2 > 0.0)) {
         if (pe) pe[i] = 0.0;
         atomicOr(inf_flag + s, 1);
-        if (MODE == 2) for (int q = 0; q < 45; ++q) pair_H[45 * (size_t)i + q] = 0.0;
+        if (MODE == 2) pair_flag[i] = 1;
         return;
     }
     if (d2 >= dh * dh) {
         if (pe) pe[i] = 0.0;
-        if (MODE == 2) for (int q = 0; q < 45; ++q) pair_H[45 * (size_t)i + q] = 0.0;
+        if (MODE == 2) pair_flag[i] = 1;
         return;
     }
     double d = sqrt(d2);
@@ -651,10 +689,8 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
             H[pk9(R, C)] = hv;
         }
     if (project) psd_project9(H);
-    double *out = pair_H + 45 * (size_t)i;
-    for (int q = 0; q < 45; ++q) out[q] = H[q];
-    // diagonal blocks for the preconditioner: H12[k][l] = sum_ij U_ki U_lj H9[i][j]
-    diag_contrib(mp, cvb, diagF, diagB, [&](int k, int l, double *B) {
+    // world-vertex block H12[k][l] = sum_ij U_ki U_lj H9[i][j]
+    auto blk = [&](int k, int l, double *B) {
         for (int a = 0; a < 3; ++a)
             for (int bb = 0; bb < 3; ++bb) {
                 double acc = 0.0;
@@ -662,7 +698,15 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
                     for (int jj = 0; jj < 3; ++jj) acc += helmert(k, ii) * helmert(l, jj) * H[pk9(3 * ii + a, 3 * jj + bb)];
                 B[3 * a + bb] = acc;
             }
-    });
+    };
+    if (merge_into_bsr(mp, row_ptr, col, val, blk)) {
+        pair_flag[i] = 1;
+        return;
+    }
+    pair_flag[i] = 0;
+    double *out = pair_H + 45 * (size_t)i;
+    for (int q = 0; q < 45; ++q) out[q] = H[q];
+    diag_contrib(mp, cvb, diagF, diagB, blk);
 }
 
 void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project)
@@ -672,12 +716,12 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, dou
     const int2 *pt = candidates ? D.cand_pt.p : D.pt.p, *ee = candidates ? D.cand_ee.p : D.ee.p;
     int64_t n = npt + nee;
     D.pair_part.alloc(n + 1);
-    if (mode == 2) { D.pair_cv.alloc(n + 1); D.pair_H.alloc(45 * (size_t)(n + 1)); }
+    if (mode == 2) { D.pair_cv.alloc(n + 1); D.pair_H.alloc(45 * (size_t)(n + 1)); D.pair_flag.alloc(n + 1); }
     if (n == 0) return;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)npt, (int)nee, pt, ee, D.tri.p, D.edge.p, xw,
                            D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, g,
-                           D.pair_cv.p, D.pair_H.p, D.diagF.p, D.diagB.p, D.pair_part.p, (int)project, D.inf_flag.p);
+                           D.pair_cv.p, D.pair_H.p, D.diagF.p, D.diagB.p, D.pair_part.p, (int)project, D.inf_flag.p, D.row_ptr.p, D.col.p, D.val.p, D.pair_flag.p);
     };
     if (mode == 2) prof_begin(c, IPC_K_BARRIER_HESS);
     if (mode == 0) go(k_barrier<0>);
@@ -734,6 +778,7 @@ void launch_lag(ipc_ctx *c, const double *xw)
         c->cap_lag = (int64_t)(n * 1.5) + 1024;
         D.lag_cv.alloc(c->cap_lag); D.lag_beta.alloc(4 * c->cap_lag); D.lag_nrm.alloc(3 * c->cap_lag);
         D.lag_lam.alloc(c->cap_lag); D.lag_rn.alloc(3 * c->cap_lag); D.lag_M.alloc(6 * c->cap_lag);
+        D.lag_flag.alloc(c->cap_lag);
     }
     c->n_lag = n;
     c->h_lag_seg.assign(c->n_scenes + 1, 0);
@@ -750,7 +795,8 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
                            const int *__restrict__ cv_scene, const double *__restrict__ sparam, const int *__restrict__ cv_node,
                            const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
                            double *__restrict__ g, double *__restrict__ lM, double *__restrict__ diagF, double *__restrict__ diagB,
-                           double *__restrict__ pe)
+                           double *__restrict__ pe, const int *__restrict__ row_ptr, const int *__restrict__ col,
+                           double *__restrict__ val, int *__restrict__ lflag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -788,11 +834,14 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
             M[3 * a + b] = w * (cu * comp(u, a) * comp(u, b) + f1s * ((a == b ? 1.0 : 0.0) - comp(nr, a) * comp(nr, b)));
+    auto blk = [&](int k, int l, double *B) {
+        for (int q = 0; q < 9; ++q) B[q] = beta[k] * beta[l] * M[q];
+    };
+    if (merge_into_bsr(mp, row_ptr, col, val, blk)) { lflag[i] = 1; return; }
+    lflag[i] = 0;
     double *o = lM + 6 * (size_t)i;
     o[0] = M[0]; o[1] = M[1]; o[2] = M[2]; o[3] = M[4]; o[4] = M[5]; o[5] = M[8];
-    diag_contrib(mp, cvb, diagF, diagB, [&](int k, int l, double *B) {
-        for (int q = 0; q < 9; ++q) B[q] = beta[k] * beta[l] * M[q];
-    });
+    diag_contrib(mp, cvb, diagF, diagB, blk);
 }
 
 void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
@@ -804,7 +853,7 @@ void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p,
                            D.lag_lam.p, D.lag_rn.p, xw, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p,
-                           g, D.lag_M.p, D.diagF.p, D.diagB.p, D.fr_part.p);
+                           g, D.lag_M.p, D.diagF.p, D.diagB.p, D.fr_part.p, D.row_ptr.p, D.col.p, D.val.p, D.lag_flag.p);
     };
     D.fr_part.alloc(n + 1);
     if (mode == 0) go(k_friction<0>);
@@ -822,12 +871,13 @@ __global__ void k_contact_apply(int nb, int nf, const int4 *__restrict__ pcv, co
                                 const int *__restrict__ cv_scene, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
                                 const double *__restrict__ cv_x, const int *__restrict__ body_node0, const int *__restrict__ active,
                                 const double *__restrict__ v, double *__restrict__ out, double *__restrict__ part_b,
-                                double *__restrict__ part_f)
+                                double *__restrict__ part_f, const int *__restrict__ pflag, const int *__restrict__ lflag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb + nf) return;
     bool fr = i >= nb;
     int j = fr ? i - nb : i;
+    if ((fr ? lflag[j] : pflag[j]) != 0) { double *pp = fr ? part_f : part_b; if (pp) pp[j] = 0.0; return; }   // merged into the matrix
     int4 c4 = fr ? lcv[j] : pcv[j];
     int cv[4] = {c4.x, c4.y, c4.z, c4.w};
     int s = cv_scene[cv[0]];
@@ -879,7 +929,7 @@ void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *a
     if (nb + nf == 0) return;
     hipLaunchKernelGGL(k_contact_apply, dim3(blocks_for(nb + nf)), dim3(BLOCK), 0, c->stream, (int)nb, (int)nf, D.pair_cv.p,
                        D.pair_H.p, D.lag_cv.p, D.lag_beta.p, D.lag_M.p, D.cv_scene.p, D.cv_node.p, D.cv_body.p, D.cv_x.p,
-                       D.body_node0.p, active, v, out, part_b, part_f);
+                       D.body_node0.p, active, v, out, part_b, part_f, D.pair_flag.p, D.lag_flag.p);
 }
 
 // ---------------------------------------------------------------------------

@@ -75,30 +75,59 @@ __global__ void k_node_mass(int N, const int *__restrict__ adj_ptr, const int *_
     mass[n] = m;
 }
 
-// constant diagonal blocks contributed by springs: h^2 k w_c w_c' I on the
-// side's own nodes (FEM node: 3x3; body: 12x12 over its 4 nodes)
-__global__ void k_spring_diag(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
-                              const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
-                              const double *__restrict__ k, const int *__restrict__ sp_scene, const double *__restrict__ h2s,
-                              double *__restrict__ fem_diag, double *__restrict__ body_diag)
+// find the block slot of column cc in row r (rows are sorted)
+__device__ __forceinline__ int slot_of(const int *row_ptr, const int *col, int r, int cc)
+{
+    int lo = row_ptr[r], hi = row_ptr[r + 1];
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (col[m] < cc) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
+// constant part of the matrix: lumped FEM mass on the diagonal blocks
+__global__ void k_const_mass(int N, const int *__restrict__ kind, const int *__restrict__ diag_slot, const double *__restrict__ mass,
+                             double *__restrict__ vc)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N || kind[n] != 0) return;
+    double *b = vc + 9 * (size_t)diag_slot[n];
+    b[0] += mass[n]; b[4] += mass[n]; b[8] += mass[n];
+}
+
+// constant part of the matrix: spring Hessians h^2 k (u u^T) (x) I3 where u
+// lists the side nodes with weights +w (side a) and -w (side b)
+__global__ void k_const_springs(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
+                                const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
+                                const double *__restrict__ k, const int *__restrict__ sp_scene, const double *__restrict__ h2s,
+                                const int *__restrict__ body_node0, const int *__restrict__ row_ptr, const int *__restrict__ col,
+                                double *__restrict__ vc)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= NS) return;
     double kk = h2s[sp_scene[s]] * k[s];
+    int nd[8];
+    double w[8];
+    int m = 0;
     for (int side = 0; side < 2; ++side) {
         int kind = side ? kb[s] : ka[s];
         int idx = side ? ib[s] : ia[s];
         const double *xbar = (side ? xb : xa) + 3 * (size_t)s;
-        if (kind == 0) {
-            for (int c = 0; c < 3; ++c) atomicAdd(fem_diag + 9 * (size_t)idx + 4 * c, kk);
-        } else if (kind == 1) {
-            double w[4] = {1.0, xbar[0], xbar[1], xbar[2]};
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b)
-                    for (int c = 0; c < 3; ++c)
-                        atomicAdd(body_diag + 144 * (size_t)idx + (3 * a + c) * 12 + 3 * b + c, kk * w[a] * w[b]);
+        double sg = side ? -1.0 : 1.0;
+        if (kind == 0) { nd[m] = idx; w[m++] = sg; }
+        else if (kind == 1) {
+            int n0 = body_node0[idx];
+            nd[m] = n0; w[m++] = sg;
+            for (int c = 0; c < 3; ++c) { nd[m] = n0 + 1 + c; w[m++] = sg * xbar[c]; }
         }
     }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double v = kk * w[i] * w[j];
+            double *b = vc + 9 * (size_t)slot_of(row_ptr, col, nd[i], nd[j]);
+            atomicAdd(b, v); atomicAdd(b + 4, v); atomicAdd(b + 8, v);
+        }
 }
 
 __global__ void k_sum_mass(int nv, const double *__restrict__ mass, int node0, double *out)
@@ -393,7 +422,13 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         for (int e = 0; e < tet; ++e)
             if (tvalid[e]) { adj[fill[tv[e].x]++] = e; adj[fill[tv[e].y]++] = e; adj[fill[tv[e].z]++] = e; adj[fill[tv[e].w]++] = e; }
     }
-    // FEM block-CSR pattern over node rows
+    // Block-CSR pattern over all node rows: tetrahedra, the 4x4 node blocks of
+    // every affine body, and the (constant) spring couplings between the nodes
+    // of a spring's two sides.  Padding nodes have empty rows.
+    auto spring_nodes = [&](int kind, int idx, std::vector<int> &out) {
+        if (kind == 0) out.push_back(idx);
+        else if (kind == 1) for (int k = 0; k < 4; ++k) out.push_back(body_node0[idx] + k);
+    };
     std::vector<int> row_ptr(node + 1, 0), col;
     {
         std::vector<std::vector<int>> cols(node);
@@ -401,6 +436,14 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
             if (!tvalid[e]) continue;
             int v[4] = {tv[e].x, tv[e].y, tv[e].z, tv[e].w};
             for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) cols[v[a]].push_back(v[b]);
+        }
+        for (int b = 0; b < body; ++b)
+            for (int k = 0; k < 4; ++k) for (int m = 0; m < 4; ++m) cols[body_node0[b] + k].push_back(body_node0[b] + m);
+        for (int k = 0; k < sp; ++k) {
+            std::vector<int> nd;
+            spring_nodes(ska[k], sia[k], nd);
+            spring_nodes(skb[k], sib[k], nd);
+            for (int a : nd) for (int b : nd) cols[a].push_back(b);
         }
         for (int i = 0; i < node; ++i) {
             auto &cl = cols[i];
@@ -413,7 +456,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         for (int i = 0; i < node; ++i) std::copy(cols[i].begin(), cols[i].end(), col.begin() + row_ptr[i]);
     }
     c->nnzb = row_ptr[node];
-    std::vector<int> tslot(16 * (size_t)tet, 0), diag_slot(node, -1);
+    c->nnzb_fem = 0;
+    std::vector<int> tslot(16 * (size_t)tet, 0), diag_slot(node, -1), bslot(16 * (size_t)std::max(body, 1), 0), long_rows;
     auto find_slot = [&](int r, int cc) {
         auto b = col.begin() + row_ptr[r], e = col.begin() + row_ptr[r + 1];
         return (int)(std::lower_bound(b, e, cc) - col.begin());
@@ -423,7 +467,14 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         int v[4] = {tv[e].x, tv[e].y, tv[e].z, tv[e].w};
         for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) tslot[16 * (size_t)e + 4 * a + b] = find_slot(v[a], v[b]);
     }
-    for (int i = 0; i < node; ++i) if (node_kind[i] == 0) diag_slot[i] = find_slot(i, i);
+    for (int i = 0; i < node; ++i) {
+        if (node_kind[i] != 2) diag_slot[i] = find_slot(i, i);
+        if (node_kind[i] == 0) c->nnzb_fem += row_ptr[i + 1] - row_ptr[i];
+        if (row_ptr[i + 1] - row_ptr[i] > LONG_ROW) long_rows.push_back(i);
+    }
+    for (int b = 0; b < body; ++b)
+        for (int k = 0; k < 4; ++k) for (int m = 0; m < 4; ++m) bslot[16 * b + 4 * k + m] = find_slot(body_node0[b] + k, body_node0[b] + m);
+    c->n_long = (int)long_rows.size();
     // segment tables (per-scene ranges) used by the segmented reductions
     c->seg_surf.resize(n + 1); c->seg_tri.resize(n + 1); c->seg_edge.resize(n + 1); c->seg_sp.resize(n + 1); c->seg_body.resize(n + 1);
     for (int s = 0; s < n; ++s) {
@@ -439,17 +490,17 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     IPC_HIP(hipMemcpyAsync(D.xt.p, D.y.p, 3 * (size_t)node * sizeof(double), hipMemcpyDeviceToDevice, st));
     D.node_scene.upload(node_scene, st); D.node_kind.upload(node_kind, st); D.ext2node.upload(ext2node, st);
     D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node); D.diagF.alloc(9 * (size_t)node);
-    D.fem_sp_diag.alloc(9 * (size_t)node); D.fem_sp_diag.zero(st, 9 * (size_t)node);
     D.tv.upload(tv, st);
     D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);
     D.tslot.upload(tslot, st);
     D.row_ptr.upload(row_ptr, st); D.col.upload(col, st); D.diag_slot.upload(diag_slot, st);
     D.val.alloc(9 * (size_t)std::max(c->nnzb, 1));
+    D.val_const.alloc(9 * (size_t)std::max(c->nnzb, 1)); D.val_const.zero(st, 9 * (size_t)std::max(c->nnzb, 1));
+    D.bslot.upload(bslot, st); D.long_rows.upload(long_rows, st);
     D.bM.upload(bM, st); D.bvol.upload(bvol, st); D.bkappa.upload(bkappa, st); D.bext.upload(bext, st);
     D.body_node0.upload(body_node0, st); D.body_scene.upload(body_scene, st);
-    D.Hb.alloc(144 * (size_t)std::max(body, 1)); D.diagB.alloc(144 * (size_t)std::max(body, 1));
+    D.diagB.alloc(144 * (size_t)std::max(body, 1));
     D.dinvB.alloc(144 * (size_t)std::max(body, 1));
-    D.body_sp_diag.alloc(144 * (size_t)std::max(body, 1)); D.body_sp_diag.zero(st, 144 * (size_t)std::max(body, 1));
     D.body_part.alloc(std::max(body, 1));
     D.sp_ka.upload(ska, st); D.sp_ia.upload(sia, st); D.sp_kb.upload(skb, st); D.sp_ib.upload(sib, st);
     D.sp_scene.upload(sscene, st); D.sp_xa.upload(sxa, st); D.sp_xb.upload(sxb, st); D.sp_k.upload(sk, st);
@@ -478,9 +529,12 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         std::vector<double> h2s(n);
         for (int s = 0; s < n; ++s) h2s[s] = c->sc[s].h * c->sc[s].h;
         DBuf<double> dh2; dh2.upload(h2s, st);
+        hipLaunchKernelGGL(k_const_mass, dim3(blocks_for(node)), dim3(BLOCK), 0, st, node, D.node_kind.p, D.diag_slot.p, D.mass.p,
+                           D.val_const.p);
         if (sp > 0)
-            hipLaunchKernelGGL(k_spring_diag, dim3(blocks_for(sp)), dim3(BLOCK), 0, st, sp, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
-                               D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, dh2.p, D.fem_sp_diag.p, D.body_sp_diag.p);
+            hipLaunchKernelGGL(k_const_springs, dim3(blocks_for(sp)), dim3(BLOCK), 0, st, sp, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
+                               D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, dh2.p, D.body_node0.p, D.row_ptr.p, D.col.p,
+                               D.val_const.p);
         // kappa (automatic: 10 * mean FEM vertex mass * |g| * h^2 / dhat)
         DBuf<double> msum; msum.alloc(n);
         for (int s = 0; s < n; ++s)

@@ -132,18 +132,11 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
     if (part && (threadIdx.x & (TILE - 1)) == 0 && e < T) part[e / TILE] = energy;
 }
 
-// block-CSR init: zero, with the lumped mass on FEM diagonal blocks
-__global__ void k_bsr_init(int N, const int *__restrict__ row_ptr, const int *__restrict__ col, const double *__restrict__ mass,
-                           double *__restrict__ val)
+// block-CSR init: the constant part (lumped mass, springs)
+__global__ void k_bsr_init(int64_t n, const double *__restrict__ vc, double *__restrict__ val)
 {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    double m = mass[n];
-    for (int k = row_ptr[n]; k < row_ptr[n + 1]; ++k) {
-        double d = col[k] == n ? m : 0.0;
-        double *b = val + 9 * (size_t)k;
-        b[0] = d; b[1] = 0; b[2] = 0; b[3] = 0; b[4] = d; b[5] = 0; b[6] = 0; b[7] = 0; b[8] = d;
-    }
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) val[i] = vc[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -153,7 +146,7 @@ template <int MODE>
 __global__ void k_body(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ bM,
                        const double *__restrict__ bvol, const double *__restrict__ bkappa, const double *__restrict__ h2s,
                        const double *__restrict__ y, const double *__restrict__ xt, double *__restrict__ g,
-                       double *__restrict__ Hb, int project, double *__restrict__ part)
+                       double *__restrict__ val, const int *__restrict__ bslot, int project, double *__restrict__ part)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= NB) return;
@@ -226,14 +219,22 @@ __global__ void k_body(int NB, const int *__restrict__ node0, const int *__restr
                     H[pk9(R, Cc)] = 4.0 * kv * ((a == cr_ ? AtA[bcol][dcol] : 0.0) + A[a][dcol] * A[cr_][bcol] + (bcol == dcol ? C[a][cr_] : 0.0));
                 }
     if (project) psd_project9(H);
-    double *Hout = Hb + 144 * (size_t)b;
+    // add the 16 node blocks into the block-CSR values (the body's blocks are
+    // touched by no other kernel during assembly)
+    const int *sl = bslot + 16 * (size_t)b;
 #pragma unroll
-    for (int i = 0; i < 12; ++i)
+    for (int ca = 0; ca < 4; ++ca)
 #pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            double v = (i % 3 == j % 3) ? M[4 * (i / 3) + j / 3] : 0.0;
-            if (i >= 3 && j >= 3) v += H[pk9(i - 3, j - 3)];
-            Hout[12 * i + j] = v;
+        for (int cb = 0; cb < 4; ++cb) {
+            double *blk = val + 9 * (size_t)sl[4 * ca + cb];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double v = (i == j) ? M[4 * ca + cb] : 0.0;
+                    if (ca >= 1 && cb >= 1) v += H[pk9(3 * (ca - 1) + i, 3 * (cb - 1) + j)];
+                    blk[3 * i + j] += v;
+                }
         }
 }
 
@@ -286,37 +287,6 @@ __global__ void k_spring(int NS, const int *__restrict__ ka, const int *__restri
     spring_scatter(kb[s], ib[s], xb + 3 * (size_t)s, body_node0, g, {-f.x, -f.y, -f.z});
 }
 
-// matrix-free spring Hessian product: out += h^2 k (J_a - J_b)^T (J_a - J_b) v,
-// with the local quadratic form v^T H v written per spring
-__global__ void k_spring_apply(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
-                               const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
-                               const double *__restrict__ k, const int *__restrict__ sscene, const double *__restrict__ h2s,
-                               const double *__restrict__ v, const int *__restrict__ body_node0, const int *__restrict__ active,
-                               double *__restrict__ out, double *__restrict__ part)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= NS) return;
-    int sc = sscene[s];
-    if (active && !active[sc]) { if (part) part[s] = 0.0; return; }
-    auto side = [&](int kind, int idx, const double *xbar) -> d3 {
-        if (kind == 0) return ld3(v, idx);
-        if (kind == 1) {
-            int n0 = body_node0[idx];
-            d3 p = ld3(v, n0), a0 = ld3(v, n0 + 1), a1 = ld3(v, n0 + 2), a2 = ld3(v, n0 + 3);
-            return {p.x + xbar[0] * a0.x + xbar[1] * a1.x + xbar[2] * a2.x, p.y + xbar[0] * a0.y + xbar[1] * a1.y + xbar[2] * a2.y,
-                    p.z + xbar[0] * a0.z + xbar[1] * a1.z + xbar[2] * a2.z};
-        }
-        return {0.0, 0.0, 0.0};
-    };
-    d3 va = side(ka[s], ia[s], xa + 3 * (size_t)s), vb = side(kb[s], ib[s], xb + 3 * (size_t)s);
-    d3 d = {va.x - vb.x, va.y - vb.y, va.z - vb.z};
-    double kk = h2s[sc] * k[s];
-    if (part) part[s] = kk * dt(d, d);
-    d3 f = {kk * d.x, kk * d.y, kk * d.z};
-    spring_scatter(ka[s], ia[s], xa + 3 * (size_t)s, body_node0, out, f);
-    spring_scatter(kb[s], ib[s], xb + 3 * (size_t)s, body_node0, out, {-f.x, -f.y, -f.z});
-}
-
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -344,8 +314,8 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
 
 void launch_bsr_init(ipc_ctx *c)
 {
-    hipLaunchKernelGGL(k_bsr_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, c->d.row_ptr.p, c->d.col.p,
-                       c->d.mass.p, c->d.val.p);
+    int64_t n = 9 * (int64_t)c->nnzb;
+    hipLaunchKernelGGL(k_bsr_init, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n, c->d.val_const.p, c->d.val.p);
 }
 
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)
@@ -354,7 +324,7 @@ void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project,
     Dev &D = c->d;
     auto args = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.body_node0.p, D.body_scene.p,
-                           D.bM.p, D.bvol.p, D.bkappa.p, h2s, y, D.xt.p, g, D.Hb.p, (int)project, part);
+                           D.bM.p, D.bvol.p, D.bkappa.p, h2s, y, D.xt.p, g, D.val.p, D.bslot.p, (int)project, part);
     };
     if (mode == 0) args(k_body<0>);
     else if (mode == 1) args(k_body<1>);
@@ -371,15 +341,6 @@ void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *par
     };
     if (mode == 0) args(k_spring<0>);
     else args(k_spring<1>);
-}
-
-void launch_spring_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part, const double *h2s)
-{
-    if (c->NS == 0) return;
-    Dev &D = c->d;
-    hipLaunchKernelGGL(k_spring_apply, dim3(blocks_for(c->NS)), dim3(BLOCK), 0, c->stream, c->NS, D.sp_ka.p, D.sp_ia.p,
-                       D.sp_xa.p, D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, v, D.body_node0.p, active, out,
-                       part);
 }
 
 } // namespace ipc

@@ -19,6 +19,7 @@ namespace ipc {
 
 constexpr int TILE = 64;      // wavefront size on CDNA
 constexpr int BLOCK = 256;    // default workgroup: 4 wavefronts
+constexpr int LONG_ROW = 48;  // rows with more blocks go to the wavefront-per-row path
 
 // per-scene device scalar slots
 enum Slot {
@@ -40,6 +41,8 @@ enum Slot {
     S_ETA,          // PCG relative tolerance of the scene
     S_E0,           // line search: energy at the current iterate
     S_NEWTON_ON,    // 1 while the scene's Newton loop runs
+    S_ETA2,         // PCG stop: eta^2 b.b
+    S_MAXIT,        // PCG iteration cap
     NSLOT
 };
 
@@ -71,6 +74,7 @@ struct RedArgs {
     int acc = 0;            // accumulate into the total slot
     int slots[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // per-source sums (-1: none)
     int op = 0;             // 0 sum, 1 max
+    int split = 0;          // > 0: only the first `split` sources enter the total
 };
 
 #define IPC_HIP(call)                                                           \
@@ -140,7 +144,6 @@ struct Dev {
     DBuf<double> mass;                     // lumped FEM vertex mass (0 elsewhere)
     DBuf<double> dinv;                     // 3x3 inverse diagonal block per node
     DBuf<double> diagF;                    // 3x3 diagonal block accumulators
-    DBuf<double> fem_sp_diag;              // constant spring diagonal of FEM nodes
     DBuf<int> ext2node;                    // external node -> internal node
     // tetrahedra (SoA over the padded tet range)
     DBuf<int4> tv;
@@ -149,13 +152,13 @@ struct Dev {
     DBuf<int> tslot;                       // 16 BSR slots per tet (row-major a*4+b)
     // FEM matrix (block CSR, 3x3 blocks, rows = nodes)
     DBuf<int> row_ptr, col, diag_slot;
-    DBuf<double> val;
+    DBuf<double> val, val_const;           // assembled values; constant part (mass, springs)
+    DBuf<int> bslot, long_rows;            // 16 body-block slots per body; rows with > LONG_ROW blocks
     // bodies
     DBuf<double> bM;                       // 4x4 mass matrix per body
     DBuf<double> bvol, bkappa, bext;
     DBuf<int> body_node0, body_scene;
-    DBuf<double> Hb;                       // 12x12 inertia + orthogonality block
-    DBuf<double> diagB, dinvB, body_sp_diag;
+    DBuf<double> diagB, dinvB;
     // springs
     DBuf<int> sp_ka, sp_ia, sp_kb, sp_ib, sp_scene;
     DBuf<double> sp_xa, sp_xb, sp_k;
@@ -201,6 +204,7 @@ struct Dev {
     DBuf<double> sparam, h2s;              // per-scene parameters
     DBuf<int> inf_flag, ls_active, pcg_active, pcg_iters, maxpcg, newton_on;
     DBuf<int> leafpar, is_trans;
+    DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
     DBuf<double> grav;
     DBuf<double> red_tmp;
 };
@@ -214,7 +218,7 @@ struct ipc_ctx {
     int64_t ndof = 0;
     int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
     int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
-    int nnzb = 0;
+    int nnzb = 0, nnzb_fem = 0, n_long = 0;
     int64_t ext_nodes = 0;
     // host copies of segment tables
     std::vector<int> seg_surf, seg_tri, seg_edge, seg_sp, seg_body;

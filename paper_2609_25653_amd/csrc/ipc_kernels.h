@@ -23,7 +23,6 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
 void launch_bsr_init(ipc_ctx *c);
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s);
 void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *part, const double *h2s);
-void launch_spring_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part, const double *h2s);
 
 // contact (ipc_contact.hip)
 void launch_world(ipc_ctx *c, const double *y, double *xw);

@@ -1,8 +1,9 @@
 // Linear algebra of the Newton step: deterministic per-scene reductions, the
-// Hessian product (block-CSR FEM part + affine-body blocks + matrix-free
-// springs and contacts), the block-Jacobi preconditioner (3x3 per FEM vertex,
-// 12x12 per body) and a PCG that runs all scenes at once with per-scene
-// scalars and convergence flags.
+// Hessian product (one block-CSR matrix over FEM vertices and affine-body
+// nodes holding elasticity, inertia, orthogonality, springs and the contact
+// blocks that fit its pattern, plus pair-local contact blocks for the rest),
+// the block-Jacobi preconditioner (3x3 per FEM vertex, 12x12 per body) and a
+// PCG that runs all scenes at once with per-scene scalars and flags.
 #include <cmath>
 
 #include "ipc_device.h"
@@ -12,13 +13,16 @@
 namespace ipc {
 
 // ---------------------------------------------------------------------------
-// reductions: one workgroup per scene, fixed-order strided sums and a tree
+// reductions: one workgroup per scene, fixed-order strided sums and a tree.
+// The post step runs in the same workgroup once the sums are known.
 // ---------------------------------------------------------------------------
-__global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal)
+enum Post { POST_NONE = 0, POST_ALPHA = 1, POST_PCG = 2 };
+
+__global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post, int *__restrict__ active, int *__restrict__ iters)
 {
     int s = blockIdx.x;
     __shared__ double sh[256];
-    double total = a.op ? 0.0 : 0.0;
+    double total = 0.0;
     for (int k = 0; k < a.nsrc; ++k) {
         const RedSrc &r = a.src[k];
         double part = 0.0;
@@ -38,18 +42,28 @@ __global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal)
         double v = sh[0];
         __syncthreads();
         if (threadIdx.x == 0 && a.slots[k] >= 0) scal[(size_t)s * NSLOT + a.slots[k]] = v;
-        total = a.op ? fmax(total, v) : total + v;
+        if (a.split == 0 || k < a.split) total = a.op ? fmax(total, v) : total + v;
     }
-    if (threadIdx.x == 0 && a.slot >= 0) {
-        double *d = scal + (size_t)s * NSLOT + a.slot;
-        *d = a.acc ? (a.op ? fmax(*d, total) : *d + total) : total;
+    if (threadIdx.x != 0) return;
+    double *S = scal + (size_t)s * NSLOT;
+    if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], total) : S[a.slot] + total) : total;
+    if (post == POST_ALPHA) {
+        S[S_ALPHA] = S[S_RZ] / S[S_PAP];
+    } else if (post == POST_PCG && active[s]) {
+        iters[s] += 1;
+        if (S[S_RR] <= S[S_ETA2] || iters[s] >= (int)S[S_MAXIT]) { active[s] = 0; return; }
+        S[S_BETA] = S[S_RZ_NEW] / S[S_RZ];
+        S[S_RZ] = S[S_RZ_NEW];
     }
 }
 
-void reduce(ipc_ctx *c, const RedArgs &a)
+void reduce_post(ipc_ctx *c, const RedArgs &a, int post)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(c->n_scenes), dim3(256), 0, c->stream, c->n_scenes, a, c->d.scal.p);
+    hipLaunchKernelGGL(k_reduce, dim3(c->n_scenes), dim3(256), 0, c->stream, c->n_scenes, a, c->d.scal.p, post, c->d.pcg_active.p,
+                       c->d.pcg_iters.p);
 }
+
+void reduce(ipc_ctx *c, const RedArgs &a) { reduce_post(c, a, POST_NONE); }
 
 RedSrc src(const double *v, const int *seg, int off, int base)
 {
@@ -63,17 +77,22 @@ int *seg_ptr(ipc_ctx *c, int region) { return c->d.segs.p + (size_t)region * (c-
 // ---------------------------------------------------------------------------
 // Hessian product
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_spmv(int N, const int *__restrict__ row_ptr, const int *__restrict__ col,
+// Rows with at most LONG_ROW blocks: one thread per row.  Longer rows (affine
+// body nodes carrying many springs): one wavefront per row, lanes striding
+// over the blocks, then a wavefront reduction.  Same launch.
+__global__ void __launch_bounds__(256) k_spmv(int N, int nshort_blocks, int nlong, const int *__restrict__ long_rows,
+                                              const int *__restrict__ row_ptr, const int *__restrict__ col,
                                               const double *__restrict__ val, const double *__restrict__ v,
                                               const int *__restrict__ node_scene, const int *__restrict__ active,
-                                              double *__restrict__ out, double *__restrict__ part)
+                                              double *__restrict__ out)
 {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    double qf = 0.0;
-    if (n < N) {
+    if ((int)blockIdx.x < nshort_blocks) {
+        int n = blockIdx.x * blockDim.x + threadIdx.x;
+        if (n >= N) return;
+        int k0 = row_ptr[n], k1 = row_ptr[n + 1];
+        if (k1 - k0 > LONG_ROW) return;
         double ax = 0.0, ay = 0.0, az = 0.0;
         if (!active || active[node_scene[n]]) {
-            int k0 = row_ptr[n], k1 = row_ptr[n + 1];
             for (int k = k0; k < k1; ++k) {
                 const double *B = val + 9 * (size_t)k;
                 d3 w = ld3(v, col[k]);
@@ -81,78 +100,67 @@ __global__ void __launch_bounds__(256) k_spmv(int N, const int *__restrict__ row
                 ay += B[3] * w.x + B[4] * w.y + B[5] * w.z;
                 az += B[6] * w.x + B[7] * w.y + B[8] * w.z;
             }
-            if (k1 > k0) {
-                d3 w = ld3(v, n);
-                qf = w.x * ax + w.y * ay + w.z * az;
-            }
         }
         st3(out, n, {ax, ay, az});
+        return;
     }
-    qf = wave_sum(qf);
-    if (part && (threadIdx.x & (TILE - 1)) == 0 && n < N) part[n / TILE] = qf;
+    int w = (blockIdx.x - nshort_blocks) * (blockDim.x / TILE) + threadIdx.x / TILE;
+    int lane = threadIdx.x & (TILE - 1);
+    if (w >= nlong) return;
+    int n = long_rows[w];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    if (!active || active[node_scene[n]]) {
+        for (int k = row_ptr[n] + lane; k < row_ptr[n + 1]; k += TILE) {
+            const double *B = val + 9 * (size_t)k;
+            d3 x = ld3(v, col[k]);
+            ax += B[0] * x.x + B[1] * x.y + B[2] * x.z;
+            ay += B[3] * x.x + B[4] * x.y + B[5] * x.z;
+            az += B[6] * x.x + B[7] * x.y + B[8] * x.z;
+        }
+    }
+    ax = wave_sum(ax); ay = wave_sum(ay); az = wave_sum(az);
+    if (lane == 0) st3(out, n, {ax, ay, az});
 }
 
-__global__ void k_body_apply(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ Hb,
-                             const int *__restrict__ active, const double *__restrict__ v, double *__restrict__ out,
-                             double *__restrict__ part)
+// p.Ap per wavefront of nodes
+__global__ void k_dot(int N, const int *__restrict__ node_scene, const int *__restrict__ active, const double *__restrict__ a,
+                      const double *__restrict__ b, double *__restrict__ part)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= NB) return;
-    if (active && !active[bscene[b]]) { if (part) part[b] = 0.0; return; }
-    int n0 = node0[b];
-    double w[12];
-    for (int c = 0; c < 4; ++c) { d3 t = ld3(v, n0 + c); w[3 * c] = t.x; w[3 * c + 1] = t.y; w[3 * c + 2] = t.z; }
-    const double *H = Hb + 144 * (size_t)b;
-    double qf = 0.0;
-    for (int i = 0; i < 12; ++i) {
-        double acc = 0.0;
-        for (int j = 0; j < 12; ++j) acc += H[12 * i + j] * w[j];
-        out[3 * (size_t)n0 + i] += acc;
-        qf += w[i] * acc;
-    }
-    if (part) part[b] = qf;
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (n < N && (!active || active[node_scene[n]])) s = dt(ld3(a, n), ld3(b, n));
+    s = wave_sum(s);
+    if ((threadIdx.x & (TILE - 1)) == 0 && n < N) part[n / TILE] = s;
 }
 
-void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool partials)
+void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool pap)
 {
     Dev &D = c->d;
     hipStream_t st = c->stream;
+    int nshort = blocks_for(c->N);
+    int nlongb = (c->n_long + BLOCK / TILE - 1) / (BLOCK / TILE);
     prof_begin(c, IPC_K_SPMV);
-    hipLaunchKernelGGL(k_spmv, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.row_ptr.p, D.col.p, D.val.p, v, D.node_scene.p,
-                       active, out, partials ? D.part_node.p : nullptr);
-    prof_end(c, IPC_K_SPMV, 76.0 * c->nnzb + 4.0 * (c->N + 1) + 48.0 * c->NFEM);
-    if (c->NB)
-        hipLaunchKernelGGL(k_body_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.body_scene.p, D.Hb.p,
-                           active, v, out, partials ? D.body_part.p : nullptr);
-    launch_spring_apply(c, v, out, active, partials ? D.sp_part.p : nullptr, D.h2s.p);
-    D.pair_part.alloc(c->n_pt + c->n_ee + 1);
-    D.fr_part.alloc(c->n_lag + 1);
+    hipLaunchKernelGGL(k_spmv, dim3(nshort + nlongb), dim3(BLOCK), 0, st, c->N, nshort, c->n_long, D.long_rows.p, D.row_ptr.p, D.col.p,
+                       D.val.p, v, D.node_scene.p, active, out);
+    prof_end(c, IPC_K_SPMV, 76.0 * c->nnzb + 4.0 * (c->N + 1) + 48.0 * (c->NFEM + 4.0 * c->NB));
     prof_begin(c, IPC_K_CONTACT_APPLY);
-    launch_contact_apply(c, v, out, active, partials ? D.pair_part.p : nullptr, partials ? D.fr_part.p : nullptr);
+    launch_contact_apply(c, v, out, active, nullptr, nullptr);
     prof_end(c, IPC_K_CONTACT_APPLY, 0.0);
-    if (partials) {
+    if (pap) {
+        hipLaunchKernelGGL(k_dot, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, active, v, out, D.part_node.p);
         RedArgs a{};
-        a.nsrc = 0;
         a.src[a.nsrc++] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0);
-        a.src[a.nsrc++] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0);
-        a.src[a.nsrc++] = src(c->NS ? D.sp_part.p : nullptr, seg_ptr(c, R_SP), 0, 0);
-        a.src[a.nsrc++] = src(c->n_pt ? D.pair_part.p : nullptr, seg_ptr(c, R_PT), 0, 0);
-        a.src[a.nsrc++] = src(c->n_ee ? D.pair_part.p : nullptr, seg_ptr(c, R_EE), (int)c->n_pt, 0);
-        if (c->fr_on) {
-            a.src[a.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
-            a.src[a.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
-        }
         a.slot = S_PAP;
-        a.acc = 0;
-        reduce(c, a);
+        reduce_post(c, a, POST_ALPHA);
     }
 }
 
 // ---------------------------------------------------------------------------
-// block-Jacobi preconditioner
+// block-Jacobi preconditioner: diagonal blocks of the matrix plus the
+// diagonal blocks of the pair-local contact terms
 // ---------------------------------------------------------------------------
 __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__restrict__ diag_slot, const double *__restrict__ val,
-                           const double *__restrict__ spd, const double *__restrict__ diagF, double *__restrict__ dinv)
+                           const double *__restrict__ diagF, double *__restrict__ dinv)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -160,7 +168,7 @@ __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__res
     if (kind[n] != 0) { for (int q = 0; q < 9; ++q) o[q] = 0.0; return; }
     double a[9];
     const double *B = val + 9 * (size_t)diag_slot[n];
-    for (int q = 0; q < 9; ++q) a[q] = B[q] + spd[9 * (size_t)n + q] + diagF[9 * (size_t)n + q];
+    for (int q = 0; q < 9; ++q) a[q] = B[q] + diagF[9 * (size_t)n + q];
     double c0 = a[4] * a[8] - a[5] * a[7], c1 = a[5] * a[6] - a[3] * a[8], c2 = a[3] * a[7] - a[4] * a[6];
     double det = a[0] * c0 + a[1] * c1 + a[2] * c2;
     double id = 1.0 / det;
@@ -170,13 +178,21 @@ __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__res
 }
 
 // 12x12 SPD inverse by Cholesky (one thread per body)
-__global__ void k_prec_body(int NB, const double *__restrict__ Hb, const double *__restrict__ spd, const double *__restrict__ diagB,
+__global__ void k_prec_body(int NB, const int *__restrict__ bslot, const double *__restrict__ val, const double *__restrict__ diagB,
                             double *__restrict__ dinvB)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= NB) return;
     double L[144];
-    for (int q = 0; q < 144; ++q) L[q] = Hb[144 * (size_t)b + q] + spd[144 * (size_t)b + q] + diagB[144 * (size_t)b + q];
+    for (int ca = 0; ca < 4; ++ca)
+        for (int cb = 0; cb < 4; ++cb) {
+            const double *B = val + 9 * (size_t)bslot[16 * (size_t)b + 4 * ca + cb];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    int r = 3 * ca + i, cc = 3 * cb + j;
+                    L[12 * r + cc] = B[3 * i + j] + diagB[144 * (size_t)b + 12 * r + cc];
+                }
+        }
     for (int j = 0; j < 12; ++j) {
         double s = L[12 * j + j];
         for (int k = 0; k < j; ++k) s -= L[12 * j + k] * L[12 * j + k];
@@ -188,7 +204,6 @@ __global__ void k_prec_body(int NB, const double *__restrict__ Hb, const double 
             L[12 * i + j] = t / dj;
         }
     }
-    // inverse = L^-T L^-1, column by column
     double *o = dinvB + 144 * (size_t)b;
     for (int cidx = 0; cidx < 12; ++cidx) {
         double y[12];
@@ -210,16 +225,16 @@ void build_preconditioner(ipc_ctx *c)
 {
     Dev &D = c->d;
     hipLaunchKernelGGL(k_prec_fem, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, D.node_kind.p, D.diag_slot.p, D.val.p,
-                       D.fem_sp_diag.p, D.diagF.p, D.dinv.p);
+                       D.diagF.p, D.dinv.p);
     if (c->NB)
-        hipLaunchKernelGGL(k_prec_body, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.Hb.p, D.body_sp_diag.p, D.diagB.p,
+        hipLaunchKernelGGL(k_prec_body, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.bslot.p, D.val.p, D.diagB.p,
                            D.dinvB.p);
 }
 
 // ---------------------------------------------------------------------------
 // PCG kernels
 // ---------------------------------------------------------------------------
-// x = 0, r = b, z = M^-1 r (FEM nodes), p = z; partials of b.b and r.z
+// x = 0, r = b, z = M^-1 r (FEM nodes); partials of b.b and r.z
 __global__ void k_pcg_init(int N, const int *__restrict__ kind, const double *__restrict__ b, const double *__restrict__ dinv,
                            double *__restrict__ x, double *__restrict__ r, double *__restrict__ z, double *__restrict__ part_bb,
                            double *__restrict__ part_rz)
@@ -264,7 +279,7 @@ __global__ void k_body_prec_apply(int NB, const int *__restrict__ node0, const i
     part[b] = rz;
 }
 
-// alpha = rz / pAp; x += alpha p; r -= alpha Ap; z = M^-1 r (FEM); partials r.z, r.r
+// x += alpha p; r -= alpha Ap; z = M^-1 r (FEM); partials r.z, r.r
 __global__ void k_pcg_update(int N, const int *__restrict__ kind, const int *__restrict__ node_scene, const int *__restrict__ active,
                              const double *__restrict__ scal, const double *__restrict__ dinv, const double *__restrict__ p,
                              const double *__restrict__ Ap, double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
@@ -275,8 +290,7 @@ __global__ void k_pcg_update(int N, const int *__restrict__ kind, const int *__r
     if (n < N) {
         int s = node_scene[n];
         if (active[s]) {
-            const double *S = scal + (size_t)s * NSLOT;
-            double al = S[S_RZ] / S[S_PAP];
+            double al = scal[(size_t)s * NSLOT + S_ALPHA];
             d3 pv = ld3(p, n), av = ld3(Ap, n), xv = ld3(x, n), rv = ld3(r, n);
             xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
             rv = {rv.x - al * av.x, rv.y - al * av.y, rv.z - al * av.z};
@@ -294,18 +308,6 @@ __global__ void k_pcg_update(int N, const int *__restrict__ kind, const int *__r
     }
     rz = wave_sum(rz); rr = wave_sum(rr);
     if ((threadIdx.x & (TILE - 1)) == 0 && n < N) { part_rz[n / TILE] = rz; part_rr[n / TILE] = rr; }
-}
-
-// per scene: convergence test and beta
-__global__ void k_pcg_scalars(int ns, double *__restrict__ scal, int *__restrict__ active, int *__restrict__ iters, int maxit_dummy)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= ns || !active[s]) return;
-    double *S = scal + (size_t)s * NSLOT;
-    iters[s] += 1;
-    if (S[S_RR] <= S[S_ALPHA] || iters[s] >= (int)S[S_ACTIVE]) { active[s] = 0; return; }   // S_ALPHA: eta^2 b.b, S_ACTIVE: cap
-    S[S_BETA] = S[S_RZ_NEW] / S[S_RZ];
-    S[S_RZ] = S[S_RZ_NEW];
 }
 
 __global__ void k_pcg_p(int N, const int *__restrict__ node_scene, const int *__restrict__ active, const double *__restrict__ scal,
@@ -328,8 +330,8 @@ __global__ void k_pcg_start(int ns, double *__restrict__ scal, int *__restrict__
     double *S = scal + (size_t)s * NSLOT;
     iters[s] = 0;
     double e = eta > 0.0 ? eta : S[S_ETA];
-    S[S_ALPHA] = e * e * S[S_BB];
-    S[S_ACTIVE] = (double)maxit[s];
+    S[S_ETA2] = e * e * S[S_BB];
+    S[S_MAXIT] = (double)maxit[s];
     active[s] = (want ? want[s] : 1) && S[S_BB] > 0.0 ? 1 : 0;
 }
 
@@ -348,13 +350,12 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                            D.dinvB.p, nullptr, r, z, D.body_part.p);
     {
         RedArgs a{};
-        a.src[a.nsrc++] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0);
-        a.slot = S_BB; a.acc = 0;
+        a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = S_BB;
         reduce(c, a);
         RedArgs b2{};
         b2.src[b2.nsrc++] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0);
         b2.src[b2.nsrc++] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0);
-        b2.slot = S_RZ; b2.acc = 0;
+        b2.slot = S_RZ;
         reduce(c, b2);
     }
     IPC_HIP(hipMemcpyAsync(p, z, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -373,15 +374,13 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
             hipLaunchKernelGGL(k_body_prec_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.body_scene.p,
                                D.dinvB.p, active, r, z, D.body_part.p);
         RedArgs a{};
-        a.src[a.nsrc++] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0);
-        a.src[a.nsrc++] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0);
-        a.slot = S_RZ_NEW; a.acc = 0;
-        reduce(c, a);
-        RedArgs b2{};
-        b2.src[b2.nsrc++] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0);
-        b2.slot = S_RR; b2.acc = 0;
-        reduce(c, b2);
-        hipLaunchKernelGGL(k_pcg_scalars, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.scal.p, active, iters, 0);
+        a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = -1;
+        a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = -1;
+        a.slot = S_RZ_NEW;
+        a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = S_RR;
+        // total of the first two sources is r.z; the third source is r.r
+        a.split = 2;
+        reduce_post(c, a, POST_PCG);
         hipLaunchKernelGGL(k_pcg_p, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, active, D.scal.p, z, p);
         if ((it + 1) % check_every == 0 || it + 1 == maxit) {
             IPC_HIP(hipMemcpyAsync(hact.data(), active, ns * sizeof(int), hipMemcpyDeviceToHost, st));
