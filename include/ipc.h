@@ -125,7 +125,11 @@ enum {
     IPC_Q_NTRI = 3,       /* contact triangles of all scenes                   */
     IPC_Q_NEDGE = 4,
     IPC_Q_NNODES = 5,     /* internal padded node count                        */
-    IPC_Q_NTETS = 6       /* internal padded tetrahedron count                 */
+    IPC_Q_NTETS = 6,      /* internal padded tetrahedron count                 */
+    IPC_Q_NLOCAL = 7,     /* contact entries (barrier + friction) of the last
+                             assembly that stay pair-local, i.e. whose blocks
+                             did not fit the matrix pattern                      */
+    IPC_Q_NPAIRS = 8      /* active barrier pairs of the last assembly         */
 };
 
 /* Flags of ipc_energy_grad_hess. */
@@ -208,6 +212,12 @@ enum {
 };
 int ipc_profile(ipc_ctx *ctx, int enable);
 int ipc_kernel_time(ipc_ctx *ctx, int kernel, double *total_ms, int64_t *launches, double *bytes);
+/* Duration of one launch of a timed kernel on the matrix of the last
+ * assembly, from `reps` back-to-back launches between two HIP events on the
+ * context's stream (so no host gap enters the figure).  Supported kernels:
+ * IPC_K_SPMV.  avg_us and bytes (algorithmic bytes of one launch) are
+ * written on success.  Uses the context's solver scratch vectors. */
+int ipc_time_kernel(ipc_ctx *ctx, int kernel, int reps, double *avg_us, double *bytes);
 
 #ifdef __cplusplus
 }

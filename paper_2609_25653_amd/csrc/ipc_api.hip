@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -192,6 +193,9 @@ void setup_after_create(ipc_ctx *c)
     D.is_trans.upload(is_trans, c->stream);
     for (auto *b : {&D.inf_flag, &D.ls_active, &D.pcg_active, &D.pcg_iters, &D.newton_on}) b->alloc(ns);
     D.part_node2.alloc(c->N / TILE + 1);
+    D.body_part2.alloc(std::max(c->NB, 1));
+    D.tickets.alloc(4);
+    D.tickets.zero(c->stream, 4);
     D.segs.alloc((size_t)NREGION * (ns + 1));
     D.segs.zero(c->stream, (size_t)NREGION * (ns + 1));
     std::vector<int> nodew(ns + 1), tetw(ns + 1);
@@ -272,6 +276,7 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     launch_spring(c, 1, y, g, D.sp_part.p, D.h2s.p);
     launch_barrier(c, hess ? 2 : 1, false, D.xw.p, g, project);
     if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p, g);
+    if (hess) build_local_list(c);
 }
 
 // Active pairs at internal y from a static broad phase.
@@ -360,6 +365,11 @@ extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_
     if (!scenes || n_scenes < 1) { g_create_error = "need at least one scene"; return IPC_E_INVALID; }
     ipc_ctx *c = new ipc_ctx;
     c->stream = (hipStream_t)hip_stream;
+    {
+        const char *ng = std::getenv("IPC_NO_GRAPH");
+        c->use_graphs = !(ng && ng[0] == '1');
+        if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
+    }
     int rc = guard(c, [&] {
         create_context(c, scenes, n_scenes);
         setup_after_create(c);
@@ -394,6 +404,8 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_NEDGE: *v = c->EDGE; return IPC_OK;
     case IPC_Q_NNODES: *v = c->N; return IPC_OK;
     case IPC_Q_NTETS: *v = c->T; return IPC_OK;
+    case IPC_Q_NLOCAL: *v = c->n_local; return IPC_OK;
+    case IPC_Q_NPAIRS: *v = c->n_pt + c->n_ee; return IPC_OK;
     }
     return IPC_E_INVALID;
 }
@@ -793,6 +805,7 @@ ipc_ctx::~ipc_ctx()
         for (auto e : T.ev) (void)hipEventDestroy(e);
         for (auto e : T.pool) (void)hipEventDestroy(e);
     }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 
 extern "C" int ipc_profile(ipc_ctx *c, int enable)
@@ -815,5 +828,31 @@ extern "C" int ipc_kernel_time(ipc_ctx *c, int kernel, double *total_ms, int64_t
         if (total_ms) *total_ms = c->timers[kernel].total_ms;
         if (launches) *launches = c->timers[kernel].launches;
         if (bytes) *bytes = c->timers[kernel].bytes;
+    });
+}
+
+extern "C" int ipc_time_kernel(ipc_ctx *c, int kernel, int reps, double *avg_us, double *bytes)
+{
+    if (!c || reps < 1 || !avg_us || kernel != IPC_K_SPMV) return IPC_E_INVALID;
+    return guard(c, [&] {
+        Dev &D = c->d;
+        hipEvent_t e0, e1;
+        IPC_HIP(hipEventCreate(&e0));
+        IPC_HIP(hipEventCreate(&e1));
+        bool prof = c->prof;
+        c->prof = false;
+        // one warm launch, then the timed batch: q = H p on the current matrix
+        spmv_only(c, D.p.p, D.q.p);
+        IPC_HIP(hipEventRecord(e0, c->stream));
+        for (int k = 0; k < reps; ++k) spmv_only(c, D.p.p, D.q.p);
+        IPC_HIP(hipEventRecord(e1, c->stream));
+        IPC_HIP(hipEventSynchronize(e1));
+        c->prof = prof;
+        float ms = 0.0f;
+        IPC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_us = 1e3 * ms / reps;
+        if (bytes) *bytes = spmv_bytes(c);
     });
 }

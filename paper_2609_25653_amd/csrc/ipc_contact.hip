@@ -871,13 +871,13 @@ __global__ void k_contact_apply(int nb, int nf, const int4 *__restrict__ pcv, co
                                 const int *__restrict__ cv_scene, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
                                 const double *__restrict__ cv_x, const int *__restrict__ body_node0, const int *__restrict__ active,
                                 const double *__restrict__ v, double *__restrict__ out, double *__restrict__ part_b,
-                                double *__restrict__ part_f, const int *__restrict__ pflag, const int *__restrict__ lflag)
+                                double *__restrict__ part_f, const int *__restrict__ local, int nlocal)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb + nf) return;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlocal) return;
+    int i = local[t];   // pair-local entries only: the rest were merged into the matrix
     bool fr = i >= nb;
     int j = fr ? i - nb : i;
-    if ((fr ? lflag[j] : pflag[j]) != 0) { double *pp = fr ? part_f : part_b; if (pp) pp[j] = 0.0; return; }   // merged into the matrix
     int4 c4 = fr ? lcv[j] : pcv[j];
     int cv[4] = {c4.x, c4.y, c4.z, c4.w};
     int s = cv_scene[cv[0]];
@@ -926,10 +926,53 @@ void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *a
 {
     Dev &D = c->d;
     int64_t nb = c->n_pt + c->n_ee, nf = c->fr_on ? c->n_lag : 0;
-    if (nb + nf == 0) return;
-    hipLaunchKernelGGL(k_contact_apply, dim3(blocks_for(nb + nf)), dim3(BLOCK), 0, c->stream, (int)nb, (int)nf, D.pair_cv.p,
+    if (c->n_local == 0) return;
+    hipLaunchKernelGGL(k_contact_apply, dim3(blocks_for(c->n_local)), dim3(BLOCK), 0, c->stream, (int)nb, (int)nf, D.pair_cv.p,
                        D.pair_H.p, D.lag_cv.p, D.lag_beta.p, D.lag_M.p, D.cv_scene.p, D.cv_node.p, D.cv_body.p, D.cv_x.p,
-                       D.body_node0.p, active, v, out, part_b, part_f, D.pair_flag.p, D.lag_flag.p);
+                       D.body_node0.p, active, v, out, part_b, part_f, D.local_idx.p, (int)c->n_local);
+}
+
+// List of the pair-local entries (barrier pairs then friction pairs whose
+// blocks were not merged into the matrix): ballot per wavefront, scan of the
+// wavefront counts, write.
+template <bool WRITE>
+__global__ void k_local(int nb, int nf, const int *__restrict__ pflag, const int *__restrict__ lflag,
+                        unsigned long long *__restrict__ mask, int *__restrict__ wcount, const int *__restrict__ woff,
+                        int *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int wave = i / TILE, lane = threadIdx.x & (TILE - 1);
+    if (!WRITE) {
+        bool loc = false;
+        if (i < nb + nf) loc = (i < nb ? pflag[i] : lflag[i - nb]) == 0;
+        unsigned long long m = __ballot(loc);
+        if (lane == 0 && wave * TILE < nb + nf) { mask[wave] = m; wcount[wave] = __popcll(m); }
+    } else {
+        if (i >= nb + nf) return;
+        unsigned long long m = mask[wave];
+        if ((m >> lane) & 1ull) out[woff[wave] + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    }
+}
+
+void build_local_list(ipc_ctx *c)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    int64_t nb = c->n_pt + c->n_ee, nf = c->fr_on ? c->n_lag : 0, n = nb + nf;
+    c->n_local = 0;
+    if (n == 0) return;
+    int nw = (int)((n + TILE - 1) / TILE);
+    D.mkey.alloc(nw);
+    D.wcount.alloc(nw + 1); D.woff.alloc(nw + 1);
+    D.local_idx.alloc(n);
+    hipLaunchKernelGGL(k_local<false>, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.pair_flag.p, D.lag_flag.p, D.mkey.p,
+                       D.wcount.p, nullptr, nullptr);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.wcount.p + nw, 0);
+    exclusive_scan(c, D.wcount.p, D.woff.p, nw);
+    c->n_local = read_int(c, D.woff.p + nw);
+    if (c->n_local)
+        hipLaunchKernelGGL(k_local<true>, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.pair_flag.p, D.lag_flag.p,
+                           D.mkey.p, D.wcount.p, D.woff.p, D.local_idx.p);
 }
 
 // ---------------------------------------------------------------------------

@@ -205,6 +205,9 @@ struct Dev {
     DBuf<int> inf_flag, ls_active, pcg_active, pcg_iters, maxpcg, newton_on;
     DBuf<int> leafpar, is_trans;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
+    DBuf<int> local_idx;                   // pair-local entries (barrier pairs, then friction pairs)
+    DBuf<int> tickets;                     // last-workgroup counters
+    DBuf<double> body_part2;
     DBuf<double> grav;
     DBuf<double> red_tmp;
 };
@@ -229,7 +232,9 @@ struct ipc_ctx {
     ipc::Dev d;
     bool step_ready = false;
     bool fr_on = true;
-    int64_t n_lag_pt = 0;
+    bool use_graphs = true;              // PCG iterations replayed from a captured graph
+    hipStream_t cap_stream = nullptr;    // private stream used only for graph capture
+    int64_t n_lag_pt = 0, n_local = 0;
     int last_status = 0;
     // host staging for small uploads (kept alive until the copy has completed)
     std::vector<double> h_scal_stage;
@@ -261,6 +266,8 @@ void prof_end(ipc_ctx *c, int k, double bytes);
 void store_pair_segs(ipc_ctx *c);
 __global__ void k_fill_int_api(int n, int *p, int v);
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool partials);
+void spmv_only(ipc_ctx *c, const double *v, double *out);
+double spmv_bytes(const ipc_ctx *c);
 void build_preconditioner(ipc_ctx *c);
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
 

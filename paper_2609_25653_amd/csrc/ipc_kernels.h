@@ -34,6 +34,7 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, dou
 void launch_lag(ipc_ctx *c, const double *xw);
 void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g);
 void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part_b, double *part_f);
+void build_local_list(ipc_ctx *c);
 void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1);
 
 // per-scene scalars (ipc_solver.hip)

@@ -22,7 +22,7 @@ __global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post,
 {
     int s = blockIdx.x;
     __shared__ double sh[256];
-    double total = 0.0;
+    double total = 0.0, rest = 0.0;
     for (int k = 0; k < a.nsrc; ++k) {
         const RedSrc &r = a.src[k];
         double part = 0.0;
@@ -43,6 +43,7 @@ __global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post,
         __syncthreads();
         if (threadIdx.x == 0 && a.slots[k] >= 0) scal[(size_t)s * NSLOT + a.slots[k]] = v;
         if (a.split == 0 || k < a.split) total = a.op ? fmax(total, v) : total + v;
+        else rest += v;
     }
     if (threadIdx.x != 0) return;
     double *S = scal + (size_t)s * NSLOT;
@@ -50,6 +51,7 @@ __global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post,
     if (post == POST_ALPHA) {
         S[S_ALPHA] = S[S_RZ] / S[S_PAP];
     } else if (post == POST_PCG && active[s]) {
+        S[S_RR] = rest;   // the sources after `split` carry r.r
         iters[s] += 1;
         if (S[S_RR] <= S[S_ETA2] || iters[s] >= (int)S[S_MAXIT]) { active[s] = 0; return; }
         S[S_BETA] = S[S_RZ_NEW] / S[S_RZ];
@@ -122,15 +124,32 @@ __global__ void __launch_bounds__(256) k_spmv(int N, int nshort_blocks, int nlon
     if (lane == 0) st3(out, n, {ax, ay, az});
 }
 
-// p.Ap per wavefront of nodes
+// p.Ap per wavefront of nodes (the per-scene sum and alpha follow in k_reduce;
+// summing in the producer's last workgroup would need a device-scope release
+// fence per workgroup, which writes back the XCD's L2 and costs more than the
+// extra launch)
 __global__ void k_dot(int N, const int *__restrict__ node_scene, const int *__restrict__ active, const double *__restrict__ a,
                       const double *__restrict__ b, double *__restrict__ part)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
-    if (n < N && (!active || active[node_scene[n]])) s = dt(ld3(a, n), ld3(b, n));
+    if (n < N && active[node_scene[n]]) s = dt(ld3(a, n), ld3(b, n));
     s = wave_sum(s);
     if ((threadIdx.x & (TILE - 1)) == 0 && n < N) part[n / TILE] = s;
+}
+
+// Algorithmic bytes of one block-CSR product: 76 per stored block (9 doubles
+// + column index), 4 per row pointer, and 24 read plus 24 written per
+// non-padding node.
+double spmv_bytes(const ipc_ctx *c) { return 76.0 * c->nnzb + 4.0 * (c->N + 1) + 48.0 * (c->NFEM + 4.0 * c->NB); }
+
+void spmv_only(ipc_ctx *c, const double *v, double *out)
+{
+    Dev &D = c->d;
+    int nshort = blocks_for(c->N);
+    int nlongb = (c->n_long + BLOCK / TILE - 1) / (BLOCK / TILE);
+    hipLaunchKernelGGL(k_spmv, dim3(nshort + nlongb), dim3(BLOCK), 0, c->stream, c->N, nshort, c->n_long, D.long_rows.p, D.row_ptr.p,
+                       D.col.p, D.val.p, v, D.node_scene.p, nullptr, out);
 }
 
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool pap)
@@ -142,7 +161,7 @@ void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, boo
     prof_begin(c, IPC_K_SPMV);
     hipLaunchKernelGGL(k_spmv, dim3(nshort + nlongb), dim3(BLOCK), 0, st, c->N, nshort, c->n_long, D.long_rows.p, D.row_ptr.p, D.col.p,
                        D.val.p, v, D.node_scene.p, active, out);
-    prof_end(c, IPC_K_SPMV, 76.0 * c->nnzb + 4.0 * (c->N + 1) + 48.0 * (c->NFEM + 4.0 * c->NB));
+    prof_end(c, IPC_K_SPMV, spmv_bytes(c));
     prof_begin(c, IPC_K_CONTACT_APPLY);
     launch_contact_apply(c, v, out, active, nullptr, nullptr);
     prof_end(c, IPC_K_CONTACT_APPLY, 0.0);
@@ -279,35 +298,69 @@ __global__ void k_body_prec_apply(int NB, const int *__restrict__ node0, const i
     part[b] = rz;
 }
 
-// x += alpha p; r -= alpha Ap; z = M^-1 r (FEM); partials r.z, r.r
-__global__ void k_pcg_update(int N, const int *__restrict__ kind, const int *__restrict__ node_scene, const int *__restrict__ active,
-                             const double *__restrict__ scal, const double *__restrict__ dinv, const double *__restrict__ p,
-                             const double *__restrict__ Ap, double *__restrict__ x, double *__restrict__ r, double *__restrict__ z,
-                             double *__restrict__ part_rz, double *__restrict__ part_rr)
+// x += alpha p; r -= alpha Ap; z = M^-1 r with partials of r.z and r.r.
+// Workgroups [0, nnode_blocks) take FEM and padding nodes, one thread per
+// node; the rest take one affine body per thread (its 4 nodes and its 12x12
+// inverse block).  The last workgroup tests convergence and forms beta.
+__global__ void k_pcg_update2(int N, int nnode_blocks, int NB, const int *__restrict__ kind, const int *__restrict__ node_scene,
+                              int *__restrict__ active, double *__restrict__ scal, const double *__restrict__ dinv,
+                              const double *__restrict__ dinvB, const int *__restrict__ body_node0, const int *__restrict__ body_scene,
+                              const double *__restrict__ p, const double *__restrict__ Ap, double *__restrict__ x, double *__restrict__ r,
+                              double *__restrict__ z, double *__restrict__ part_rz, double *__restrict__ part_rr,
+                              double *__restrict__ bpart_rz, double *__restrict__ bpart_rr)
 {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    double rz = 0.0, rr = 0.0;
-    if (n < N) {
-        int s = node_scene[n];
-        if (active[s]) {
-            double al = scal[(size_t)s * NSLOT + S_ALPHA];
-            d3 pv = ld3(p, n), av = ld3(Ap, n), xv = ld3(x, n), rv = ld3(r, n);
-            xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
-            rv = {rv.x - al * av.x, rv.y - al * av.y, rv.z - al * av.z};
-            st3(x, n, xv);
-            st3(r, n, rv);
-            rr = dt(rv, rv);
-            if (kind[n] == 0) {
-                const double *M = dinv + 9 * (size_t)n;
-                d3 zv = {M[0] * rv.x + M[1] * rv.y + M[2] * rv.z, M[3] * rv.x + M[4] * rv.y + M[5] * rv.z,
-                         M[6] * rv.x + M[7] * rv.y + M[8] * rv.z};
-                st3(z, n, zv);
-                rz = dt(rv, zv);
+    if ((int)blockIdx.x < nnode_blocks) {
+        int n = blockIdx.x * blockDim.x + threadIdx.x;
+        double rz = 0.0, rr = 0.0;
+        if (n < N && kind[n] != 1) {
+            int s = node_scene[n];
+            if (active[s]) {
+                double al = scal[(size_t)s * NSLOT + S_ALPHA];
+                d3 pv = ld3(p, n), av = ld3(Ap, n), xv = ld3(x, n), rv = ld3(r, n);
+                xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
+                rv = {rv.x - al * av.x, rv.y - al * av.y, rv.z - al * av.z};
+                st3(x, n, xv);
+                st3(r, n, rv);
+                rr = dt(rv, rv);
+                if (kind[n] == 0) {
+                    const double *M = dinv + 9 * (size_t)n;
+                    d3 zv = {M[0] * rv.x + M[1] * rv.y + M[2] * rv.z, M[3] * rv.x + M[4] * rv.y + M[5] * rv.z,
+                             M[6] * rv.x + M[7] * rv.y + M[8] * rv.z};
+                    st3(z, n, zv);
+                    rz = dt(rv, zv);
+                }
             }
         }
+        rz = wave_sum(rz); rr = wave_sum(rr);
+        if ((threadIdx.x & (TILE - 1)) == 0 && n < N) { part_rz[n / TILE] = rz; part_rr[n / TILE] = rr; }
+    } else {
+        int b = (blockIdx.x - nnode_blocks) * blockDim.x + threadIdx.x;
+        if (b < NB) {
+            double rz = 0.0, rr = 0.0;
+            int s = body_scene[b];
+            if (active[s]) {
+                double al = scal[(size_t)s * NSLOT + S_ALPHA];
+                int n0 = body_node0[b];
+                double rv[12];
+                for (int i = 0; i < 12; ++i) {
+                    size_t q = 3 * (size_t)n0 + i;
+                    x[q] += al * p[q];
+                    rv[i] = r[q] - al * Ap[q];
+                    r[q] = rv[i];
+                    rr += rv[i] * rv[i];
+                }
+                const double *M = dinvB + 144 * (size_t)b;
+                for (int i = 0; i < 12; ++i) {
+                    double acc = 0.0;
+                    for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rv[j];
+                    z[3 * (size_t)n0 + i] = acc;
+                    rz += rv[i] * acc;
+                }
+            }
+            bpart_rz[b] = rz;
+            bpart_rr[b] = rr;
+        }
     }
-    rz = wave_sum(rz); rr = wave_sum(rr);
-    if ((threadIdx.x & (TILE - 1)) == 0 && n < N) { part_rz[n / TILE] = rz; part_rr[n / TILE] = rr; }
 }
 
 __global__ void k_pcg_p(int N, const int *__restrict__ node_scene, const int *__restrict__ active, const double *__restrict__ scal,
@@ -363,32 +416,66 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
     int maxit = 0;
     for (auto &S : c->sc) maxit = std::max(maxit, S.max_pcg);
     std::vector<int> hact(ns);
-    const int check_every = 8;
-    for (int it = 0; it < maxit; ++it) {
+    // one PCG iteration; every kernel skips scenes whose flag is down, so extra
+    // iterations after convergence change nothing
+    auto iteration = [&]() {
+        hipStream_t s2 = c->stream;
         hess_apply(c, p, Ap, active, true);
+        int nnb = blocks_for(c->N), nbb = blocks_for(c->NB);
         prof_begin(c, IPC_K_PCG_UPDATE);
-        hipLaunchKernelGGL(k_pcg_update, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.node_scene.p, active,
-                           D.scal.p, D.dinv.p, p, Ap, x, r, z, D.part_node.p, D.part_node2.p);
+        hipLaunchKernelGGL(k_pcg_update2, dim3(nnb + nbb), dim3(BLOCK), 0, s2, c->N, nnb, c->NB, D.node_kind.p, D.node_scene.p, active,
+                           D.scal.p, D.dinv.p, D.dinvB.p, D.body_node0.p, D.body_scene.p, p, Ap, x, r, z, D.part_node.p,
+                           D.part_node2.p, D.body_part.p, D.body_part2.p);
         prof_end(c, IPC_K_PCG_UPDATE, 240.0 * c->NFEM);
-        if (c->NB)
-            hipLaunchKernelGGL(k_body_prec_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.body_scene.p,
-                               D.dinvB.p, active, r, z, D.body_part.p);
         RedArgs a{};
         a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = -1;
         a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = -1;
         a.slot = S_RZ_NEW;
-        a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = S_RR;
-        // total of the first two sources is r.z; the third source is r.r
-        a.split = 2;
+        a.split = 2;   // r.z = the first two sources; r.r = the last two
+        a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = -1;
+        a.src[a.nsrc] = src(c->NB ? D.body_part2.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = -1;
         reduce_post(c, a, POST_PCG);
-        hipLaunchKernelGGL(k_pcg_p, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, active, D.scal.p, z, p);
-        if ((it + 1) % check_every == 0 || it + 1 == maxit) {
-            IPC_HIP(hipMemcpyAsync(hact.data(), active, ns * sizeof(int), hipMemcpyDeviceToHost, st));
-            IPC_HIP(hipStreamSynchronize(st));
-            bool any = false;
-            for (int s = 0; s < ns; ++s) any |= hact[s] != 0;
-            if (!any) break;
+        hipLaunchKernelGGL(k_pcg_p, dim3(blocks_for(c->N)), dim3(BLOCK), 0, s2, c->N, D.node_scene.p, active, D.scal.p, z, p);
+    };
+    auto any_active = [&]() {
+        IPC_HIP(hipMemcpyAsync(hact.data(), active, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int s = 0; s < ns; ++s) any |= hact[s] != 0;
+        return any;
+    };
+    const int K = 8;   // iterations per convergence check
+    if (c->use_graphs && !c->prof) {
+        // Capture K iterations once per solve on the context's capture stream
+        // (the caller's stream may be the null stream, which cannot capture)
+        // and replay the graph on the context's stream.
+        IPC_HIP(hipStreamSynchronize(st));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        c->stream = c->cap_stream;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < K; ++k) iteration();
+            e = hipStreamEndCapture(c->cap_stream, &graph);
         }
+        c->stream = st;
+        IPC_HIP(e);
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        IPC_HIP(e);
+        hipError_t le = hipSuccess;
+        for (int it = 0; it < maxit; it += K) {
+            le = hipGraphLaunch(exec, st);
+            if (le != hipSuccess) break;
+            if (!any_active()) break;
+        }
+        (void)hipGraphExecDestroy(exec);
+        IPC_HIP(le);
+        return;
+    }
+    for (int it = 0; it < maxit; ++it) {
+        iteration();
+        if (((it + 1) % K == 0 || it + 1 == maxit) && !any_active()) break;
     }
 }
 

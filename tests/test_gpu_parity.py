@@ -123,3 +123,21 @@ def test_trajectory(name, n):
         yo, _ = o.state()
         err = np.abs(y - yo).max()
         assert err <= 1e-6 * L, (name, k, err / L, stats[0], so)
+
+
+def test_graph_replay_matches_eager(monkeypatch):
+    """PCG iterations replayed from a captured HIP graph (several replays per
+    solve, eager work and host reads in between) match eager launches."""
+    from paper_2609_25653_amd import Sim
+    sc = S.tiny_scene("pad_box", h=0.01, n_steps=30)
+    monkeypatch.setenv("IPC_NO_GRAPH", "0")
+    g = Sim(sc)
+    monkeypatch.setenv("IPC_NO_GRAPH", "1")
+    e = Sim(sc)
+    L = O.Oracle(sc).L
+    for k in range(30):
+        rg, sg = g.step()
+        re, se = e.step()
+        assert rg == 0 and re == 0
+        yg, ye = to_np(g.state()[0]), to_np(e.state()[0])
+        assert np.abs(yg - ye).max() <= 1e-9 * L, (k, sg, se)
