@@ -456,6 +456,13 @@ def tiny_scene(kind="tet", seed=0, **kw):
         X = X + rng.uniform(-1e-4, 1e-4, size=X.shape)
         b.add_fem(X, orient(X, hex_tets(2, 2, 2)), 1e5, 0.45, 1000.0)
         b.add_static(*ground_quad())
+    elif kind == "edge_tet":
+        # one tetrahedron resting on an edge 0.6 mm above the ground's diagonal
+        # edge and about 1 degree off parallel to it
+        X = np.array([[0.005, -0.005, 0.0], [-0.005, 0.005 + 2.5e-4, 0.0],
+                      [0.005, 0.005, 0.008], [-0.005, -0.005, 0.008]], np.float64) + [0.0, 0.0, 6e-4]
+        b.add_fem(X, orient(X, np.array([[0, 1, 2, 3]], np.int32)), 1e5, 0.4, 1000.0)
+        b.add_static(*ground_quad())
     elif kind == "pad_box":
         b.add_body((0.3, 0.3, 0.01 + 5e-4), (0.02, 0.02, 0.02), 0.05, contact=True)
         drive, _, _ = _add_gripper(b, rng, center_xy=(0.3, 0.3), z_mid=0.01 + 5e-4, inner_half_gap=0.0115,

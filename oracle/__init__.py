@@ -81,6 +81,12 @@ def lib():
         L.or_snh.argtypes = [D, ctypes.c_double, ctypes.c_double, D, D]
         L.or_psd_project.argtypes = [D, ctypes.c_int]
         L.or_barrier3.argtypes = [ctypes.c_double, ctypes.c_double, D]
+        L.or_set_params.argtypes = [P, D, ctypes.c_double]
+        L.or_dG_dyn_T.argtypes = [P, D, D, D, D, D, D]
+        L.or_dG_dtheta_T.restype = ctypes.c_double
+        L.or_dG_dtheta_T.argtypes = [P, D, D, D, D, D, D]
+        L.or_step_vjp.restype = ctypes.c_int
+        L.or_step_vjp.argtypes = [P, D, D, D, D, D, D, D, D, D, D, ctypes.c_double, I]
         _lib = L
     return _lib
 
@@ -245,6 +251,83 @@ class Oracle:
         rc = lib().or_step(self._h, _d(t) if t is not None else None, ctypes.byref(st))
         self.step_index += 1
         return rc, st.as_dict()
+
+    # adjoint (one converged step n: y_prev -> y_next)
+    def set_params(self, E=None, mu=None):
+        """Replace the per-tet Young's moduli and/or the friction coefficient."""
+        e = _f64(E) if E is not None else None
+        lib().or_set_params(self._h, _d(e) if e is not None else None, -1.0 if mu is None else float(mu))
+
+    def _t(self, n):
+        t = self.targets(n)
+        return _d(t) if t is not None else None
+
+    def dG_dyn_T(self, y_prev, yd_prev, n, y_next, w):
+        a = [_f64(v) for v in (y_prev, yd_prev, y_next, w)]
+        out = np.zeros(self.ndof)
+        lib().or_dG_dyn_T(self._h, _d(a[0]), _d(a[1]), self._t(n), _d(a[2]), _d(a[3]), _d(out))
+        return out
+
+    def dG_dtheta_T(self, y_prev, yd_prev, n, y_next, w):
+        a = [_f64(v) for v in (y_prev, yd_prev, y_next, w)]
+        eb = np.zeros(len(self.scene["tets"]))
+        mb = lib().or_dG_dtheta_T(self._h, _d(a[0]), _d(a[1]), self._t(n), _d(a[2]), _d(a[3]), _d(eb))
+        return eb, mb
+
+    def step_vjp(self, y_prev, yd_prev, n, y_next, ybar_next, vbar_next, eta=1e-12):
+        """Returns (status, ybar_prev, vbar_prev, Ebar, mubar, pcg_iters) for
+        one step, with Ebar and mubar the parameter adjoints of this step alone."""
+        a = [_f64(v) for v in (y_prev, yd_prev, y_next, ybar_next, vbar_next)]
+        yb = np.zeros(self.ndof); vb = np.zeros(self.ndof)
+        eb = np.zeros(len(self.scene["tets"])); mb = np.zeros(1); it = ctypes.c_int()
+        rc = lib().or_step_vjp(self._h, _d(a[0]), _d(a[1]), self._t(n), _d(a[2]), _d(a[3]), _d(a[4]),
+                               _d(yb), _d(vb), _d(eb), _d(mb), float(eta), ctypes.byref(it))
+        return rc, yb, vb, eb, float(mb[0]), it.value
+
+
+def rollout_loss(scene, y0, yd0, first_step, n_steps, tracked, target, E=None, mu=None, grad=False,
+                 checkpoint_every=10, eta=1e-12):
+    """Roll the scene from (y0, yd0) at step first_step over n_steps steps with
+    parameters (E, mu) and return the loss sum_i |x_i - target_i|^2 over the
+    tracked FEM vertices at the last step; with grad=True also dL/dE (per tet)
+    and dL/dmu by the per-step adjoint, recomputing each checkpoint segment."""
+    o = Oracle(scene)
+    o.set_params(E, mu)
+    y0 = _f64(y0); yd0 = _f64(yd0)
+    idx = (3 * np.asarray(tracked)[:, None] + np.arange(3)[None, :]).ravel()
+    ckpt = {}
+    o.set_state(y0, yd0)
+    for k in range(n_steps):
+        if k % checkpoint_every == 0:
+            ckpt[k] = o.state()
+        o.step_index = first_step + k
+        rc, _ = o.step()
+        if rc != 0:
+            raise RuntimeError(f"oracle step {first_step + k} returned {rc}")
+    y, _ = o.state()
+    diff = y[idx] - np.asarray(target, np.float64).ravel()
+    loss = float(diff @ diff)
+    if not grad:
+        return loss
+    ybar = np.zeros(o.ndof); ybar[idx] = 2.0 * diff
+    vbar = np.zeros(o.ndof)
+    Ebar = np.zeros(len(scene["tets"])); mubar = 0.0
+    for c0 in sorted(ckpt, reverse=True):
+        c1 = min(c0 + checkpoint_every, n_steps)
+        states = [ckpt[c0]]
+        o.set_state(*ckpt[c0])
+        for k in range(c0, c1):
+            o.step_index = first_step + k
+            o.step()
+            states.append(o.state())
+        for k in range(c1 - 1, c0 - 1, -1):
+            yp, vp = states[k - c0]
+            yn, _ = states[k - c0 + 1]
+            rc, ybar, vbar, eb, mb, _ = o.step_vjp(yp, vp, first_step + k, yn, ybar, vbar, eta)
+            if rc != 0:
+                raise RuntimeError(f"oracle adjoint of step {first_step + k} returned {rc}")
+            Ebar += eb; mubar += mb
+    return loss, Ebar, mubar
 
 
 # single-pair helpers for unit pins

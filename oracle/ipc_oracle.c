@@ -147,6 +147,9 @@ typedef struct {       /* friction data lagged at y^n (C10) */
     double nrm[3];
     double lam;
     double rn[3];      /* sum_i beta_i x_i^n */
+    int kind;          /* 0 point-triangle, 1 edge-edge */
+    int type;          /* distance type at y^n */
+    double ex;         /* edge-edge mollifier threshold */
 } OLag;
 
 struct OScene {
@@ -1361,8 +1364,12 @@ static void compute_lag(OScene *s)
             double rn = sqrt(dot3(r, r));
             for (int c = 0; c < 3; ++c) { lg->nrm[c] = r[c] / rn; lg->rn[c] = r[c]; }
             double m = 1.0;
+            lg->kind = kind;
+            lg->type = t;
+            lg->ex = 0.0;
             if (kind == 1) {
                 double ex = pair_eps_x(s, i, j), c = cross2_derivs(x, NULL, NULL);
+                lg->ex = ex;
                 if (c < ex) m = (2.0 - c / ex) * (c / ex);
             }
             lg->lam = -s->kappa * m * barrier_d1(d, s->dhat);
@@ -1435,7 +1442,9 @@ static int group_of(const OScene *s, int node, int *local)
     return s->nv + (node - s->nv) / 4;
 }
 
-static int pcg_terms(OScene *s, const Terms *T, const double *b, double *x, double eta, int maxit)
+/* PCG on the terms T with their block-Jacobi preconditioner.  Returns the
+ * iterations; *indef (nullable) is set when some p^T A p <= 0 stopped it. */
+static int pcg_terms(OScene *s, const Terms *T, const double *b, double *x, double eta, int maxit, int *indef)
 {
     int n = s->ndof;
     /* block diagonal: 3x3 per FEM vertex, 12x12 per body */
@@ -1477,6 +1486,7 @@ static int pcg_terms(OScene *s, const Terms *T, const double *b, double *x, doub
     for (int i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; bn += b[i] * b[i]; }
     bn = sqrt(bn);
     int it = 0;
+    if (indef) *indef = 0;
     if (bn > 0.0) {
         PREC(r, z);
         double rz = 0.0;
@@ -1485,6 +1495,7 @@ static int pcg_terms(OScene *s, const Terms *T, const double *b, double *x, doub
             terms_matvec(s, T, p, Ap);
             double pAp = 0.0;
             for (int i = 0; i < n; ++i) pAp += p[i] * Ap[i];
+            if (!(pAp > 0.0)) { if (indef) *indef = 1; break; }
             double al = rz / pAp, rn = 0.0;
             for (int i = 0; i < n; ++i) { x[i] += al * p[i]; r[i] -= al * Ap[i]; rn += r[i] * r[i]; }
             if (sqrt(rn) <= eta * bn) break;
@@ -1509,7 +1520,7 @@ int or_pcg(OScene *s, const double *y, const double *b, double *x, double eta)
     Terms T = {0};
     double *g = xmalloc(sizeof(double) * s->ndof);
     eval_ip(s, y, &apt, &aee, NULL, g, NULL, &T, 1, 1);
-    int it = pcg_terms(s, &T, b, x, eta, s->max_pcg);
+    int it = pcg_terms(s, &T, b, x, eta, s->max_pcg, NULL);
     free(g); free(T.t); free(apt.v); free(aee.v);
     return it;
 }
@@ -1614,7 +1625,7 @@ int or_step(OScene *s, const double *targets, OStats *st)
         Terms T = {0};
         double E0 = eval_ip(s, y, &apt, &aee, NULL, g, NULL, &T, 1, 1);
         for (int i = 0; i < n; ++i) b[i] = -g[i];
-        int it = pcg_terms(s, &T, b, p, s->pcg_tol, s->max_pcg);
+        int it = pcg_terms(s, &T, b, p, s->pcg_tol, s->max_pcg, NULL);
         free(T.t); free(apt.v); free(aee.v);
         loc.pcg_iters_total += it;
         if (it > loc.pcg_iters_max) loc.pcg_iters_max = it;
@@ -1652,5 +1663,222 @@ int or_step(OScene *s, const double *targets, OStats *st)
     loc.status = status;
     if (st) *st = loc;
     free(y); free(g); free(p); free(b); free(yt);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* adjoint of one converged step (C15)                                      */
+/* ------------------------------------------------------------------------ */
+/* The step solves G(y^{n+1}; y^n, ydot^n, theta) = grad E_n = 0 with
+ * theta = (E_e per tet, mu).  By the implicit function theorem, for an
+ * upstream adjoint a = dL/dy^{n+1} the sensitivities are -(dG/dq)^T w with
+ * H w = a, H the unprojected Hessian at y^{n+1} and the lagged friction data
+ * held as functions of y^n. */
+void or_set_params(OScene *s, const double *E, double mu)
+{
+    if (E)
+        for (int e = 0; e < s->nt; ++e) {
+            double nu = s->nu[e];
+            s->E[e] = E[e];
+            s->lmu[e] = E[e] / (2.0 * (1.0 + nu));
+            s->llam[e] = E[e] * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        }
+    if (mu >= 0.0) s->mu = mu;
+}
+
+/* out = M v with M the mass matrix of the inertia term (lumped FEM masses,
+ * per body the 4x4 generalised mass [m 0; 0 S] times I3) */
+static void mass_apply(const OScene *s, const double *v, double *out)
+{
+    for (int i = 0; i < s->nv; ++i)
+        for (int k = 0; k < 3; ++k) out[3 * i + k] = s->mass[i] * v[3 * i + k];
+    for (int b = 0; b < s->nb; ++b) {
+        int n0 = s->nv + 4 * b;
+        double Mh[4][4] = {{0}};
+        Mh[0][0] = s->bmass[b];
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) Mh[1 + i][1 + j] = s->bS[9 * b + 3 * i + j];
+        for (int c = 0; c < 4; ++c)
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+                for (int c2 = 0; c2 < 4; ++c2) acc += Mh[c][c2] * v[3 * (size_t)(n0 + c2) + k];
+                out[3 * (size_t)(n0 + c) + k] = acc;
+            }
+    }
+}
+
+/* Friction part of (dG/dy^n)^T w, accumulated into out.  Each lagged pair
+ * contributes phi = mu lam f1(|u|)/|u| (W . u), W = sum_a beta_a w_a, and
+ * phi depends on the positions x^n of the pair's vertices through the
+ * closest-point weights beta (the minimiser s* of |r(s)|^2 moves with x^n),
+ * the offset r = sum beta x^n, the normal n = r/|r|, the normal force
+ * lam = -kappa m(c) b'(|r|), and the -x^n inside u = P (sum beta (x - x^n)).
+ * Returns sum_k lam_k f1_k/|u_k| (W_k . u_k) = w^T dG/dmu. */
+static double friction_lag_vjp(const OScene *s, const double *xw, const double *xwn, const double *w, double *out)
+{
+    double ea = s->eps_v * s->h, dh = s->dhat, wgf = 0.0;
+    for (int k = 0; k < s->nlag; ++k) {
+        const OLag *L = s->lag + k;
+        double x[12], xn[12], wv[12];
+        OPt pts[4];
+        for (int a = 0; a < 4; ++a) {
+            memcpy(x + 3 * a, P3(xw, L->cv[a]), 3 * sizeof(double));
+            memcpy(xn + 3 * a, P3(xwn, L->cv[a]), 3 * sizeof(double));
+            pts[a] = cv_point(s, L->cv[a]);
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int q = 0; q < pts[a].n; ++q) acc += pts[a].w[q] * w[3 * (size_t)pts[a].node[q] + c];
+                wv[3 * a + c] = acc;
+            }
+        }
+        Param P = type_param(L->kind, L->type);
+        double beta[4], r[3], Dm[6];
+        closest(&P, xn, beta, r, Dm);
+        double d = sqrt(dot3(r, r)), n[3] = {r[0] / d, r[1] / d, r[2] / d};
+        double m = 1.0, m1 = 0.0, gc[12] = {0}, Hc[144];
+        if (L->kind == 1) {
+            double c = cross2_derivs(xn, gc, Hc);
+            if (c < L->ex) { m = (2.0 - c / L->ex) * (c / L->ex); m1 = 2.0 / L->ex - 2.0 * c / (L->ex * L->ex); }
+        }
+        double b1 = barrier_d1(d, dh), b2 = barrier_d2(d, dh);
+        double lam = -s->kappa * m * b1;
+        double D[3] = {0, 0, 0}, W[3] = {0, 0, 0};
+        for (int a = 0; a < 4; ++a)
+            for (int c = 0; c < 3; ++c) { D[c] += beta[a] * (x[3 * a + c] - xn[3 * a + c]); W[c] += beta[a] * wv[3 * a + c]; }
+        double nD = dot3(n, D), u[3];
+        for (int c = 0; c < 3; ++c) u[c] = D[c] - n[c] * nD;
+        double sg = sqrt(dot3(u, u));
+        double f1s = sg < ea ? 2.0 / ea - sg / (ea * ea) : 1.0 / sg;
+        double df1s = sg < ea ? -1.0 / (ea * ea) : -1.0 / (sg * sg);   /* d(f1/s)/ds */
+        double Wu = dot3(W, u), psi = f1s * Wu, dpsi_du[3];
+        for (int c = 0; c < 3; ++c) dpsi_du[c] = f1s * W[c] + (sg > 0.0 ? Wu * df1s * u[c] / sg : 0.0);
+        wgf += lam * psi;
+        /* s* sensitivity: ds = -F_ss^{-1} F_sx, F = |r(s)|^2 */
+        double Fi[2][2] = {{0, 0}, {0, 0}};
+        if (P.npar == 1) Fi[0][0] = 1.0 / (2.0 * dot3(Dm, Dm));
+        else if (P.npar == 2) {
+            double a00 = 2.0 * dot3(Dm, Dm), a01 = 2.0 * dot3(Dm, Dm + 3), a11 = 2.0 * dot3(Dm + 3, Dm + 3);
+            double det = a00 * a11 - a01 * a01;
+            Fi[0][0] = a11 / det; Fi[1][1] = a00 / det; Fi[0][1] = Fi[1][0] = -a01 / det;
+        }
+        for (int j = 0; j < 4; ++j) {
+            if (pts[j].n == 0) continue;
+            for (int c = 0; c < 3; ++c) {
+                double Fsx[2] = {0, 0}, ds[2] = {0, 0};
+                for (int q = 0; q < P.npar; ++q) Fsx[q] = 2.0 * P.a[q][j] * r[c] + 2.0 * beta[j] * Dm[3 * q + c];
+                for (int q = 0; q < P.npar; ++q)
+                    for (int q2 = 0; q2 < P.npar; ++q2) ds[q] -= Fi[q][q2] * Fsx[q2];
+                double db[4], dr[3], dn[3], dD[3], du[3];
+                for (int a = 0; a < 4; ++a) {
+                    db[a] = 0.0;
+                    for (int q = 0; q < P.npar; ++q) db[a] += P.a[q][a] * ds[q];
+                }
+                for (int i = 0; i < 3; ++i) {
+                    dr[i] = (i == c ? beta[j] : 0.0);
+                    for (int q = 0; q < P.npar; ++q) dr[i] += Dm[3 * q + i] * ds[q];
+                }
+                double dd = dot3(n, dr);
+                for (int i = 0; i < 3; ++i) dn[i] = (dr[i] - n[i] * dd) / d;
+                for (int i = 0; i < 3; ++i) {
+                    dD[i] = -(i == c ? beta[j] : 0.0);
+                    for (int a = 0; a < 4; ++a) dD[i] += db[a] * (x[3 * a + i] - xn[3 * a + i]);
+                }
+                double dnD = dot3(dn, D) + dot3(n, dD);
+                for (int i = 0; i < 3; ++i) du[i] = dD[i] - dn[i] * nD - n[i] * dnD;
+                double dWu = 0.0;
+                for (int a = 0; a < 4; ++a) dWu += db[a] * dot3(wv + 3 * a, u);
+                double dlam = -s->kappa * (m1 * gc[3 * j + c] * b1 + m * b2 * dd);
+                double dpsi = dot3(dpsi_du, du) + f1s * dWu;
+                double dphi = s->mu * (dlam * psi + lam * dpsi);
+                for (int q = 0; q < pts[j].n; ++q) out[3 * (size_t)pts[j].node[q] + c] += pts[j].w[q] * dphi;
+            }
+        }
+    }
+    return wgf;
+}
+
+/* Set up step n at (y_prev, yd_prev, targets): state, predictor, lag. */
+static void adjoint_setup(OScene *s, const double *y_prev, const double *yd_prev, const double *targets)
+{
+    or_set_state(s, y_prev, yd_prev);
+    or_begin_step(s, targets);
+}
+
+void or_dG_dyn_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
+                 const double *y_next, const double *w, double *out)
+{
+    adjoint_setup(s, y_prev, yd_prev, targets);
+    int n = s->ndof;
+    mass_apply(s, w, out);
+    for (int i = 0; i < n; ++i) out[i] = -out[i];
+    double *xw = world_alloc(s, y_next), *xwn = world_alloc(s, y_prev);
+    friction_lag_vjp(s, xw, xwn, w, out);
+    free(xw); free(xwn);
+}
+
+/* Ebar[e] = w . dG/dE_e = (w_e . g_e)/E_e, g_e the tet's own gradient
+ * contribution (Psi_e is linear in E_e at fixed nu); returns w . dG/dmu. */
+double or_dG_dtheta_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
+                      const double *y_next, const double *w, double *Ebar)
+{
+    adjoint_setup(s, y_prev, yd_prev, targets);
+    double h2 = s->h * s->h;
+    if (Ebar)
+        for (int e = 0; e < s->nt; ++e) {
+            double F[9], c[4][3], P[9];
+            tet_F(s, y_next, e, F, c);
+            or_snh(F, s->lmu[e], s->llam[e], P, NULL);
+            double acc = 0.0;
+            for (int a = 0; a < 4; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    double ga = 0.0;
+                    for (int j = 0; j < 3; ++j) ga += c[a][j] * P[3 * j + r];
+                    acc += h2 * s->vol[e] * ga * w[3 * (size_t)s->tets[4 * e + a] + r];
+                }
+            Ebar[e] = acc / s->E[e];
+        }
+    double *xw = world_alloc(s, y_next), *xwn = world_alloc(s, y_prev);
+    double *tmp = xcalloc((size_t)s->ndof, sizeof(double));
+    double wgf = friction_lag_vjp(s, xw, xwn, w, tmp);
+    free(tmp); free(xw); free(xwn);
+    return wgf;
+}
+
+int or_step_vjp(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
+                const double *y_next, const double *ybar_next, const double *vbar_next,
+                double *ybar_prev, double *vbar_prev, double *Ebar, double *mubar, double eta, int *pcg_iters)
+{
+    int n = s->ndof;
+    double h = s->h;
+    adjoint_setup(s, y_prev, yd_prev, targets);
+    IVec apt = {0}, aee = {0};
+    pairs_at(s, y_next, &apt, &aee);
+    Terms T = {0};
+    double *g = xmalloc(sizeof(double) * n), *a = xmalloc(sizeof(double) * n), *w = xmalloc(sizeof(double) * n),
+           *Mw = xmalloc(sizeof(double) * n), *lv = xcalloc((size_t)n, sizeof(double));
+    eval_ip(s, y_next, &apt, &aee, NULL, g, NULL, &T, 0, 1);
+    for (int i = 0; i < n; ++i) a[i] = ybar_next[i] + vbar_next[i] / h;
+    int indef = 0;
+    int it = pcg_terms(s, &T, a, w, eta, s->max_pcg, &indef);
+    if (pcg_iters) *pcg_iters = it;
+    free(T.t); free(apt.v); free(aee.v);
+    int status = indef ? 6 : 0;
+    if (!indef) {
+        mass_apply(s, w, Mw);
+        double *xw = world_alloc(s, y_next), *xwn = world_alloc(s, y_prev);
+        double wgf = friction_lag_vjp(s, xw, xwn, w, lv);
+        free(xw); free(xwn);
+        for (int i = 0; i < n; ++i) {
+            vbar_prev[i] = h * Mw[i];
+            ybar_prev[i] = Mw[i] - lv[i] - vbar_next[i] / h;
+        }
+        if (mubar) *mubar -= wgf;
+        if (Ebar) {
+            double *eb = xmalloc(sizeof(double) * (size_t)(s->nt ? s->nt : 1));
+            or_dG_dtheta_T(s, y_prev, yd_prev, targets, y_next, w, eb);
+            for (int e = 0; e < s->nt; ++e) Ebar[e] -= eb[e];
+            free(eb);
+        }
+    }
+    free(g); free(a); free(w); free(Mw); free(lv);
     return status;
 }

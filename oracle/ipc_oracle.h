@@ -88,6 +88,29 @@ void    or_barrier3(double d, double dh, double *b3);
 /* Symmetric PSD projection of an n x n matrix in place (n <= 12). */
 void    or_psd_project(double *A, int n);
 
+/* Adjoint of one converged step (Eq. (3) by the implicit function theorem).
+ * Parameters theta = (E per tet, mu): or_set_params replaces them (E may be
+ * NULL; mu < 0 keeps mu).  The calls below set the state to (y_prev, yd_prev)
+ * and redo the step set-up there (predictor, lag) with the given drive
+ * targets, so that the lag data are the functions of y_prev they are in the
+ * forward step.
+ *   or_dG_dyn_T:    out = (dG/dy^n)^T w  (inertia and the friction lag).
+ *   or_dG_dtheta_T: Ebar[e] = w . dG/dE_e; returns w . dG/dmu.
+ *   or_step_vjp:    solves H w = ybar_next + vbar_next/h (H unprojected at
+ *                   y_next, PCG to relative residual eta) and writes
+ *                   ybar_prev, vbar_prev; Ebar (nt) and *mubar are
+ *                   accumulated (-=) when non-NULL.  Returns 0, or 6 when the
+ *                   PCG met p^T H p <= 0. */
+void    or_set_params(OScene *s, const double *E, double mu);
+void    or_dG_dyn_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
+                    const double *y_next, const double *w, double *out);
+double  or_dG_dtheta_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
+                       const double *y_next, const double *w, double *Ebar);
+int     or_step_vjp(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
+                    const double *y_next, const double *ybar_next, const double *vbar_next,
+                    double *ybar_prev, double *vbar_prev, double *Ebar, double *mubar, double eta,
+                    int *pcg_iters);
+
 #ifdef __cplusplus
 }
 #endif
