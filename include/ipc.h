@@ -129,7 +129,8 @@ enum {
     IPC_Q_NLOCAL = 7,     /* contact entries (barrier + friction) of the last
                              assembly that stay pair-local, i.e. whose blocks
                              did not fit the matrix pattern                      */
-    IPC_Q_NPAIRS = 8      /* active barrier pairs of the last assembly         */
+    IPC_Q_NPAIRS = 8,     /* active barrier pairs of the last assembly         */
+    IPC_Q_NTETS_EXT = 9   /* tetrahedra of all scenes (external numbering)     */
 };
 
 /* Flags of ipc_energy_grad_hess. */
@@ -190,6 +191,35 @@ int ipc_pcg(ipc_ctx *ctx, const double *y_dev, const double *b_dev, double *x_de
  * (nullable) receives n_scenes records.  Returns IPC_OK, or the first non-OK
  * scene status (IPC_E_NOT_CONVERGED leaves that scene at its last iterate). */
 int ipc_step(ipc_ctx *ctx, const double *targets_dev, ipc_stats *stats_host);
+
+/* Differentiable parameters theta: the Young's modulus of every tetrahedron
+ * (tet_E_dev: all scenes' tets concatenated in creation order, > 0; NULL
+ * keeps them) and the friction coefficient of every scene (mu_host[n_scenes],
+ * >= 0; NULL keeps them).  Lame parameters follow from E with the scene's
+ * Poisson ratios.  The barrier stiffness does not depend on theta. */
+int ipc_set_params(ipc_ctx *ctx, const double *tet_E_dev, const double *mu_host);
+
+/* Adjoint of one converged step (the implicit function theorem applied to
+ * the stationarity of Eq. (3)'s incremental potential).  The step went from
+ * (y_prev, ydot_prev) with drive targets targets_dev (as for ipc_step) to
+ * y_next; ybar_next and vbar_next are the adjoints of the loss with respect
+ * to y_next and ydot_next = (y_next - y_prev)/h (all external layout, ndof).
+ * The call sets the context's state to (y_prev, ydot_prev), redoes the step
+ * set-up there (predictor, friction lag), assembles the Hessian at y_next
+ * WITHOUT PSD projection, solves H w = ybar_next + vbar_next/h by block-Jacobi
+ * PCG to relative residual eta (each scene's max_pcg caps it), and writes
+ *   vbar_prev = h M w,
+ *   ybar_prev = M w - (dG_F/dy_prev)^T w - vbar_next/h
+ * (G_F: friction gradient, whose lagged normals, weights and normal forces are
+ * functions of y_prev).  It accumulates the parameter adjoints
+ *   Ebar_dev[e] -= w . dG/dE_e   (external tets, nullable),
+ *   mubar_dev[s] -= w . dG/dmu_s (n_scenes, nullable).
+ * iters_host[n_scenes] (nullable) receives the PCG iterations.  Returns
+ * IPC_E_INDEFINITE when the PCG met p^T H p <= 0 in some scene (outputs are
+ * then not written). */
+int ipc_step_vjp(ipc_ctx *ctx, const double *y_prev_dev, const double *ydot_prev_dev, const double *targets_dev,
+                 const double *y_next_dev, const double *ybar_next_dev, const double *vbar_next_dev, double *ybar_prev_dev,
+                 double *vbar_prev_dev, double *Ebar_dev, double *mubar_dev, double eta, int32_t *iters_host);
 
 /* Kernel timing for measurement.  ipc_profile(ctx, 1) resets the counters
  * and starts recording HIP events on the context's stream around the timed

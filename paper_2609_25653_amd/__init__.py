@@ -28,7 +28,11 @@ def _torch():
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    if t is None:
+        return None
+    if t.dtype != _torch().float64 or not t.is_contiguous():
+        raise TypeError("device buffers must be contiguous float64 tensors")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 class Sim:
@@ -154,3 +158,30 @@ class Sim:
         self._check(rc, allow=allow_status)
         self.step_index += 1
         return rc, [s.as_dict() for s in st]
+
+    # ---- adjoint --------------------------------------------------------------
+    @property
+    def n_tets(self):
+        return self._query(_lib.Q_NTETS_EXT)
+
+    def set_params(self, E=None, mu=None):
+        """Young's moduli of all tets (scenes concatenated) and/or the friction
+        coefficient of every scene (a scalar applies to all)."""
+        e = self._as_dev(E, self.n_tets) if E is not None else None
+        m = None
+        if mu is not None:
+            m = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, np.float64), (self.n_scenes,)))
+        self._check(lib().ipc_set_params(self._h, _ptr(e), m.ctypes.data_as(_lib._D) if m is not None else None))
+
+    def step_vjp(self, y_prev, ydot_prev, n, y_next, ybar_next, vbar_next, Ebar=None, mubar=None, eta=1e-12):
+        """Adjoint of step n (from (y_prev, ydot_prev) to y_next).  Returns
+        (ybar_prev, vbar_prev, pcg_iters); Ebar (n_tets) and mubar (n_scenes)
+        tensors, when given, are accumulated in place."""
+        a = [self._as_dev(v, self.ndof) for v in (y_prev, ydot_prev, y_next, ybar_next, vbar_next)]
+        t = self.targets(n)
+        yb, vb = self._vec(), self._vec()
+        it = np.zeros(self.n_scenes, np.int32)
+        self._check(lib().ipc_step_vjp(self._h, _ptr(a[0]), _ptr(a[1]), _ptr(t), _ptr(a[2]), _ptr(a[3]), _ptr(a[4]),
+                                       _ptr(yb), _ptr(vb), _ptr(Ebar), _ptr(mubar), float(eta),
+                                       it.ctypes.data_as(_lib._I)))
+        return yb, vb, it

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "NOT_CONVERGED", 4: "LI
 IPC_PSD_PROJECT = 1
 IPC_WITH_FRICTION = 2
 
-Q_NDOF, Q_NSCENES, Q_NDRIVEN, Q_NTRI, Q_NEDGE, Q_NNODES, Q_NTETS = range(7)
+Q_NDOF, Q_NSCENES, Q_NDRIVEN, Q_NTRI, Q_NEDGE, Q_NNODES, Q_NTETS, Q_NLOCAL, Q_NPAIRS, Q_NTETS_EXT = range(10)
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int32)
@@ -82,23 +82,17 @@ def lib():
         L.ipc_ccd.argtypes = [P, P, P, P]
         L.ipc_pcg.argtypes = [P, P, P, P, ctypes.c_double, _I]
         L.ipc_step.argtypes = [P, P, ctypes.POINTER(Stats)]
+        L.ipc_set_params.argtypes = [P, P, _D]
+        L.ipc_step_vjp.argtypes = [P, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, _I]
+        L.ipc_profile.argtypes = [P, ctypes.c_int]
+        L.ipc_kernel_time.argtypes = [P, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int64), _D]
+        L.ipc_time_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, _D, _D]
         for n in ("ipc_create", "ipc_destroy", "ipc_query", "ipc_scene_scalars", "ipc_get_state", "ipc_set_state",
-                  "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg", "ipc_step"):
+                  "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg", "ipc_step",
+                  "ipc_set_params", "ipc_step_vjp", "ipc_profile", "ipc_kernel_time", "ipc_time_kernel"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
-
-
-def exported_symbols():
-    """Names of the ipc_* functions the library exports (checked against include/ipc.h)."""
-    L = lib()
-    names = []
-    for n in ("ipc_create", "ipc_destroy", "ipc_last_error", "ipc_query", "ipc_scene_scalars", "ipc_get_state",
-              "ipc_set_state", "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg",
-              "ipc_step"):
-        if hasattr(L, n):
-            names.append(n)
-    return names
 
 
 def make_desc(sc, keep):

@@ -117,6 +117,11 @@ __global__ void k_copy_int(int n, const int *a, int *b)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
 }
+__global__ void k_sub_slot(int ns, const double *scal, int slot, double *out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) out[s] -= scal[(size_t)s * NSLOT + slot];
+}
 __global__ void k_inf_to_scal(int ns, int *flag, double *scal)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -150,21 +155,35 @@ void upload_seg_region(ipc_ctx *c, int region, const std::vector<int> &h)
     sync(c);
 }
 
-void setup_after_create(ipc_ctx *c)
+// per-scene parameters (8 per scene) from the host scene records
+void upload_sparam(ipc_ctx *c)
 {
-    Dev &D = c->d;
     int ns = c->n_scenes;
-    std::vector<double> sp(8 * (size_t)ns, 0.0), h2(ns), grav(3 * (size_t)ns), lo(6 * (size_t)ns);
-    std::vector<int> maxpcg(ns);
+    std::vector<double> &sp = c->h_scal_stage;
+    sp.assign(8 * (size_t)ns, 0.0);
     for (int s = 0; s < ns; ++s) {
         SceneInfo &S = c->sc[s];
         sp[8 * s + P_H2] = S.h * S.h; sp[8 * s + P_KAPPA] = S.kappa; sp[8 * s + P_DHAT] = S.dhat; sp[8 * s + P_MU] = S.mu;
         sp[8 * s + P_EPSH] = S.eps_v * S.h; sp[8 * s + P_CCDS] = S.ccd_s; sp[8 * s + P_H] = S.h;
+    }
+    c->d.sparam.upload(sp, c->stream);
+    sync(c);
+}
+
+void setup_after_create(ipc_ctx *c)
+{
+    Dev &D = c->d;
+    int ns = c->n_scenes;
+    std::vector<double> h2(ns), grav(3 * (size_t)ns), lo(6 * (size_t)ns);
+    std::vector<int> maxpcg(ns);
+    for (int s = 0; s < ns; ++s) {
+        SceneInfo &S = c->sc[s];
         h2[s] = S.h * S.h;
         for (int k = 0; k < 3; ++k) grav[3 * s + k] = S.g[k];
         maxpcg[s] = S.max_pcg;
     }
-    D.sparam.upload(sp, c->stream); D.h2s.upload(h2, c->stream); D.grav.upload(grav, c->stream); D.maxpcg.upload(maxpcg, c->stream);
+    upload_sparam(c);
+    D.h2s.upload(h2, c->stream); D.grav.upload(grav, c->stream); D.maxpcg.upload(maxpcg, c->stream);
     // Morton boxes: initial world bounds of each scene's contact vertices, enlarged
     {
         launch_world(c, D.y.p, D.xw.p);
@@ -406,6 +425,7 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_NTETS: *v = c->T; return IPC_OK;
     case IPC_Q_NLOCAL: *v = c->n_local; return IPC_OK;
     case IPC_Q_NPAIRS: *v = c->n_pt + c->n_ee; return IPC_OK;
+    case IPC_Q_NTETS_EXT: *v = c->ext_tets; return IPC_OK;
     }
     return IPC_E_INVALID;
 }
@@ -574,6 +594,97 @@ extern "C" int ipc_pcg(ipc_ctx *c, const double *y_dev, const double *b_dev, dou
         if (iters_host) IPC_HIP(hipMemcpyAsync(iters_host, D.pcg_iters.p, c->n_scenes * sizeof(int), hipMemcpyDeviceToHost, st));
         IPC_HIP(hipStreamSynchronize(st));
     });
+}
+
+extern "C" int ipc_set_params(ipc_ctx *c, const double *tet_E_dev, const double *mu_host)
+{
+    if (!c) return IPC_E_INVALID;
+    if (mu_host)
+        for (int s = 0; s < c->n_scenes; ++s)
+            if (!(mu_host[s] >= 0.0) || !std::isfinite(mu_host[s])) { c->err = "mu must be finite and >= 0"; return IPC_E_INVALID; }
+    return guard(c, [&] {
+        hipStream_t st = c->stream;
+        if (tet_E_dev && c->ext_tets) {
+            std::vector<double> E((size_t)c->ext_tets);
+            IPC_HIP(hipMemcpyAsync(E.data(), tet_E_dev, E.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync(c);
+            for (size_t i = 0; i < E.size(); ++i)
+                if (!(E[i] > 0.0) || !std::isfinite(E[i])) throw Error(IPC_E_INVALID, "Young's modulus must be finite and > 0 (tet " + std::to_string(i) + ")");
+            launch_set_E(c, tet_E_dev);
+        }
+        if (mu_host) {
+            for (int s = 0; s < c->n_scenes; ++s) c->sc[s].mu = mu_host[s];
+            upload_sparam(c);
+        }
+        IPC_HIP(hipGetLastError());
+        sync(c);
+    });
+}
+
+extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *ydot_prev_dev, const double *targets_dev,
+                            const double *y_next_dev, const double *ybar_next_dev, const double *vbar_next_dev, double *ybar_prev_dev,
+                            double *vbar_prev_dev, double *Ebar_dev, double *mubar_dev, double eta, int32_t *iters_host)
+{
+    if (!c || !y_prev_dev || !ydot_prev_dev || !y_next_dev || !ybar_next_dev || !vbar_next_dev || !ybar_prev_dev || !vbar_prev_dev)
+        return IPC_E_INVALID;
+    if (c->ND && !targets_dev) { c->err = "targets required: the scenes have driven links"; return IPC_E_INVALID; }
+    if (!(eta > 0.0)) { c->err = "eta must be > 0"; return IPC_E_INVALID; }
+    int status = IPC_OK;
+    int rc = guard(c, [&] {
+        Dev &D = c->d;
+        hipStream_t st = c->stream;
+        int64_t n3 = 3 * (int64_t)c->N;
+        auto to_int = [&](const double *ext, double *v) {
+            hipLaunchKernelGGL(k_zero, dim3(blocks_for(n3)), dim3(BLOCK), 0, st, n3, v);
+            hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, ext, v);
+        };
+        // the step's set-up at (y^n, ydot^n): predictor and friction lag
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, y_prev_dev,
+                           D.y.p);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p,
+                           ydot_prev_dev, D.ydot.p);
+        begin_step_impl(c, targets_dev);
+        if (c->CV) IPC_HIP(hipMemcpyAsync(D.xw1.p, D.xw.p, 3 * (size_t)c->CV * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // y^{n+1}, the upstream adjoints and the right-hand side
+        to_int(y_next_dev, D.yt.p);
+        to_int(vbar_next_dev, D.y0.p);
+        to_int(ybar_next_dev, D.v2.p);
+        launch_adj_rhs(c, D.v2.p, D.y0.p, D.v1.p);
+        // unprojected Hessian at y^{n+1} and H w = rhs
+        c->fr_on = true;
+        pairs_from_scratch(c, D.yt.p);
+        eval_grad_hess(c, D.yt.p, D.g.p, true, false);
+        build_preconditioner(c);
+        pcg_solve(c, D.v1.p, D.x.p, eta, nullptr);
+        std::vector<double> sc = read_scal(c);
+        for (int s = 0; s < c->n_scenes; ++s)
+            if (sc[(size_t)s * NSLOT + S_INDEF] != 0.0) status = IPC_E_INDEFINITE;
+        if (iters_host) IPC_HIP(hipMemcpyAsync(iters_host, D.pcg_iters.p, c->n_scenes * sizeof(int), hipMemcpyDeviceToHost, st));
+        if (status != IPC_OK) {
+            c->err = "the Hessian at y_next is not positive definite along a PCG direction";
+            sync(c);
+            return;
+        }
+        // state adjoints: inertia, then the friction lag at x^n (D.xw1) and x^{n+1}
+        launch_adj_mass(c, D.x.p, D.y0.p, D.v2.p, D.r.p);
+        launch_world(c, D.yt.p, D.xw.p);
+        launch_lag_vjp(c, D.xw.p, D.xw1.p, D.x.p, D.v2.p);
+        RedArgs f{};
+        f.src[f.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
+        f.src[f.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
+        f.slot = S_MUBAR;
+        reduce(c, f);
+        if (mubar_dev)
+            hipLaunchKernelGGL(k_sub_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_MUBAR, mubar_dev);
+        if (Ebar_dev) launch_adj_E(c, D.yt.p, D.x.p, Ebar_dev);
+        hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, D.v2.p,
+                           ybar_prev_dev);
+        hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, D.r.p,
+                           vbar_prev_dev);
+        IPC_HIP(hipGetLastError());
+        sync(c);
+    });
+    return rc != IPC_OK ? rc : status;
 }
 
 // ---------------------------------------------------------------------------------

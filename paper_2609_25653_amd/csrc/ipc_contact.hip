@@ -737,7 +737,8 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, dou
 __global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee, const int4 *__restrict__ tri,
                       const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
                       const double *__restrict__ sparam, const double *__restrict__ rest2, int4 *__restrict__ lcv,
-                      double *__restrict__ lbeta, double *__restrict__ lnrm, double *__restrict__ llam, double *__restrict__ lrn)
+                      double *__restrict__ lbeta, double *__restrict__ lnrm, double *__restrict__ llam, double *__restrict__ lrn,
+                      int *__restrict__ ltype, double *__restrict__ lex)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npt + nee) return;
@@ -756,13 +757,16 @@ __global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 
     d3 r, D0, D1;
     closest_point(P, x, beta, r, D0, D1);
     double rn = sqrt(dt(r, r));
-    double m = 1.0;
+    double m = 1.0, ex = 0.0;
     if (kind == 1) {
         d3 u = {x[1].x - x[0].x, x[1].y - x[0].y, x[1].z - x[0].z}, v = {x[3].x - x[2].x, x[3].y - x[2].y, x[3].z - x[2].z};
         d3 nn = cr(u, v);
-        double cval = dt(nn, nn), ex = 1e-3 * rest2[pr.x] * rest2[pr.y];
+        double cval = dt(nn, nn);
+        ex = 1e-3 * rest2[pr.x] * rest2[pr.y];
         if (cval < ex) m = (2.0 - cval / ex) * (cval / ex);
     }
+    ltype[i] = type;
+    lex[i] = ex;
     lcv[i] = make_int4(cv[0], cv[1], cv[2], cv[3]);
     for (int k = 0; k < 4; ++k) lbeta[4 * (size_t)i + k] = beta[k];
     lnrm[3 * (size_t)i] = r.x / rn; lnrm[3 * (size_t)i + 1] = r.y / rn; lnrm[3 * (size_t)i + 2] = r.z / rn;
@@ -778,7 +782,7 @@ void launch_lag(ipc_ctx *c, const double *xw)
         c->cap_lag = (int64_t)(n * 1.5) + 1024;
         D.lag_cv.alloc(c->cap_lag); D.lag_beta.alloc(4 * c->cap_lag); D.lag_nrm.alloc(3 * c->cap_lag);
         D.lag_lam.alloc(c->cap_lag); D.lag_rn.alloc(3 * c->cap_lag); D.lag_M.alloc(6 * c->cap_lag);
-        D.lag_flag.alloc(c->cap_lag);
+        D.lag_flag.alloc(c->cap_lag); D.lag_type.alloc(c->cap_lag); D.lag_ex.alloc(c->cap_lag);
     }
     c->n_lag = n;
     c->h_lag_seg.assign(c->n_scenes + 1, 0);
@@ -786,7 +790,7 @@ void launch_lag(ipc_ctx *c, const double *xw)
     if (n == 0) return;
     hipLaunchKernelGGL(k_lag, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,
                        D.edge.p, xw, D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p, D.lag_lam.p,
-                       D.lag_rn.p);
+                       D.lag_rn.p, D.lag_type.p, D.lag_ex.p);
 }
 
 template <int MODE>
@@ -859,6 +863,127 @@ void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
     if (mode == 0) go(k_friction<0>);
     else if (mode == 1) go(k_friction<1>);
     else go(k_friction<2>);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the friction lag.  For the adjoint vector w, a lagged pair adds
+// phi = mu lam (f1(s)/s) (W . u) to w^T G, with W = sum_k beta_k w_k and u the
+// tangential relative displacement.  phi depends on the lag positions x^n of
+// its four vertices through beta (the closest-point parameters s* minimise
+// |r(s)|^2, so ds* = -F_ss^-1 F_sx dx^n), the offset r, the normal n = r/|r|,
+// the normal force lam = -kappa m(c) b'(|r|) and the -x^n inside u.  One
+// thread per pair: ybar -= d phi / d y^n (through the contact-vertex maps) and
+// part[i] = lam (f1/s) (W . u), the pair's w . dG/dmu.
+// ---------------------------------------------------------------------------
+__global__ void k_lag_vjp(int n, int npt, const int4 *__restrict__ lcv, const int *__restrict__ ltype, const double *__restrict__ lex,
+                          const double *__restrict__ xw, const double *__restrict__ xwn, const int *__restrict__ cv_scene,
+                          const double *__restrict__ sparam, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
+                          const double *__restrict__ cv_x, const int *__restrict__ body_node0, const double *__restrict__ w,
+                          double *__restrict__ ybar, double *__restrict__ part)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int kind = i < npt ? 0 : 1;
+    int4 c4 = lcv[i];
+    int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+    int s = cv_scene[cv[0]];
+    const double *sp = sparam + 8 * (size_t)s;
+    double kappa = sp[P_KAPPA], dh = sp[P_DHAT], mu = sp[P_MU], ea = sp[P_EPSH];
+    Map mp[4];
+    d3 x[4], xn[4], wv[4];
+    for (int k = 0; k < 4; ++k) {
+        mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
+        x[k] = ld3(xw, cv[k]);
+        xn[k] = ld3(xwn, cv[k]);
+        wv[k] = gather_cv(mp[k], w);
+    }
+    TypeParam P = type_param(kind, ltype[i]);
+    double beta[4];
+    d3 r, D0, D1;
+    closest_point(P, xn, beta, r, D0, D1);
+    double d = sqrt(dt(r, r));
+    d3 nr = {r.x / d, r.y / d, r.z / d};
+    // normal force with the edge-edge mollifier m(c), c = |u x v|^2 at x^n
+    double m = 1.0, m1 = 0.0;
+    d3 gu = {0, 0, 0}, gv = {0, 0, 0};
+    if (kind == 1) {
+        d3 ue = {xn[1].x - xn[0].x, xn[1].y - xn[0].y, xn[1].z - xn[0].z}, ve = {xn[3].x - xn[2].x, xn[3].y - xn[2].y, xn[3].z - xn[2].z};
+        d3 nn = cr(ue, ve);
+        double cval = dt(nn, nn), ex = lex[i];
+        if (cval < ex) {
+            m = (2.0 - cval / ex) * (cval / ex);
+            m1 = 2.0 / ex - 2.0 * cval / (ex * ex);
+            gu = cr(ve, nn); gu = {2.0 * gu.x, 2.0 * gu.y, 2.0 * gu.z};   // dc/du
+            gv = cr(nn, ue); gv = {2.0 * gv.x, 2.0 * gv.y, 2.0 * gv.z};   // dc/dv
+        }
+    }
+    double b1 = barrier1(d, dh), b2 = barrier2(d, dh);
+    double lam = -kappa * m * b1;
+    d3 Dv = {0, 0, 0}, W = {0, 0, 0}, dx[4];
+    for (int k = 0; k < 4; ++k) {
+        dx[k] = {x[k].x - xn[k].x, x[k].y - xn[k].y, x[k].z - xn[k].z};
+        Dv.x += beta[k] * dx[k].x; Dv.y += beta[k] * dx[k].y; Dv.z += beta[k] * dx[k].z;
+        W.x += beta[k] * wv[k].x; W.y += beta[k] * wv[k].y; W.z += beta[k] * wv[k].z;
+    }
+    double nD = dt(nr, Dv);
+    d3 u = {Dv.x - nr.x * nD, Dv.y - nr.y * nD, Dv.z - nr.z * nD};
+    double sg = sqrt(dt(u, u));
+    double f1s = sg < ea ? 2.0 / ea - sg / (ea * ea) : 1.0 / sg;
+    double df1s = sg < ea ? -1.0 / (ea * ea) : -1.0 / (sg * sg);
+    double Wu = dt(W, u), psi = f1s * Wu;
+    double cq = sg > 0.0 ? Wu * df1s / sg : 0.0;
+    d3 gpsi = {f1s * W.x + cq * u.x, f1s * W.y + cq * u.y, f1s * W.z + cq * u.z};   // d psi / d u
+    part[i] = lam * psi;
+    double wu[4];
+    for (int k = 0; k < 4; ++k) wu[k] = dt(wv[k], u);
+    // inverse of F_ss = 2 [D_a . D_b]
+    double i00 = 0.0, i01 = 0.0, i11 = 0.0;
+    if (P.npar == 1) i00 = 1.0 / (2.0 * dt(D0, D0));
+    else if (P.npar == 2) {
+        double a00 = 2.0 * dt(D0, D0), a01 = 2.0 * dt(D0, D1), a11 = 2.0 * dt(D1, D1), det = a00 * a11 - a01 * a01;
+        i00 = a11 / det; i01 = -a01 / det; i11 = a00 / det;
+    }
+    const double su[4] = {-1.0, 1.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, -1.0, 1.0};
+    for (int j = 0; j < 4; ++j) {
+        if (mp[j].node < 0 && mp[j].body < 0) continue;
+        double res[3];
+        for (int c = 0; c < 3; ++c) {
+            double rc = comp(r, c);
+            double F0 = 2.0 * P.a1[j] * rc + 2.0 * beta[j] * comp(D0, c);
+            double F1 = 2.0 * P.a2[j] * rc + 2.0 * beta[j] * comp(D1, c);
+            double ds0 = -(i00 * F0 + i01 * F1), ds1 = -(i01 * F0 + i11 * F1);
+            double db[4];
+            for (int k = 0; k < 4; ++k) db[k] = P.a1[k] * ds0 + P.a2[k] * ds1;
+            d3 dr = {D0.x * ds0 + D1.x * ds1, D0.y * ds0 + D1.y * ds1, D0.z * ds0 + D1.z * ds1};
+            d3 dD = {0, 0, 0};
+            for (int k = 0; k < 4; ++k) { dD.x += db[k] * dx[k].x; dD.y += db[k] * dx[k].y; dD.z += db[k] * dx[k].z; }
+            if (c == 0) { dr.x += beta[j]; dD.x -= beta[j]; }
+            else if (c == 1) { dr.y += beta[j]; dD.y -= beta[j]; }
+            else { dr.z += beta[j]; dD.z -= beta[j]; }
+            double dd = dt(nr, dr);
+            d3 dn = {(dr.x - nr.x * dd) / d, (dr.y - nr.y * dd) / d, (dr.z - nr.z * dd) / d};
+            double dnD = dt(dn, Dv) + dt(nr, dD);
+            d3 du = {dD.x - dn.x * nD - nr.x * dnD, dD.y - dn.y * nD - nr.y * dnD, dD.z - dn.z * nD - nr.z * dnD};
+            double dWu = 0.0;
+            for (int k = 0; k < 4; ++k) dWu += db[k] * wu[k];
+            double dc = su[j] * comp(gu, c) + sv[j] * comp(gv, c);
+            double dlam = -kappa * (m1 * dc * b1 + m * b2 * dd);
+            double dpsi = dt(gpsi, du) + f1s * dWu;
+            res[c] = -mu * (dlam * psi + lam * dpsi);
+        }
+        scatter_cv(mp[j], ybar, {res[0], res[1], res[2]});
+    }
+}
+
+void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const double *w, double *ybar)
+{
+    Dev &D = c->d;
+    int64_t n = c->n_lag;
+    D.fr_part.alloc(n + 1);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_lag_vjp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, (int)c->n_lag_pt, D.lag_cv.p, D.lag_type.p,
+                       D.lag_ex.p, xw, xwn, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, w, ybar,
+                       D.fr_part.p);
 }
 
 // ---------------------------------------------------------------------------

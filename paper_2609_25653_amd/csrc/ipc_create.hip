@@ -298,6 +298,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     std::vector<int4> tv(tet);
     std::vector<int> tvalid(tet, 0);
     std::vector<double> tE(tet, 1.0), tnu(tet, 0.25), trho(tet, 0.0);
+    std::vector<int> ext2tet;
     std::vector<double> bM(16 * (size_t)std::max(body, 1), 0.0), bvol(body), bkappa(body), bext(3 * (size_t)body);
     std::vector<int> body_node0(body), body_scene(body);
     std::vector<int> ska(sp), sia(sp), skb(sp), sib(sp), sscene(sp);
@@ -335,6 +336,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
             if (e < d.nt) {
                 tv[g] = make_int4(S.node0 + d.tets[4 * e], S.node0 + d.tets[4 * e + 1], S.node0 + d.tets[4 * e + 2], S.node0 + d.tets[4 * e + 3]);
                 tvalid[g] = 1; tE[g] = d.tet_E[e]; tnu[g] = d.tet_nu[e]; trho[g] = d.tet_rho[e];
+                ext2tet.push_back(g);
             } else {
                 tv[g] = make_int4(S.node0, S.node0, S.node0, S.node0);
             }
@@ -518,12 +520,14 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
 
     // ---- device precompute
     {
-        DBuf<double> dE, dnu, drho;
+        DBuf<double> drho;
         DBuf<int> dvalid, dadjp, dadj;
-        dE.upload(tE, st); dnu.upload(tnu, st); drho.upload(trho, st); dvalid.upload(tvalid, st);
+        D.tE.upload(tE, st); D.tnu.upload(tnu, st); drho.upload(trho, st); dvalid.upload(tvalid, st);
+        c->ext_tets = (int64_t)ext2tet.size();
+        D.ext2tet.upload(ext2tet, st);
         dadjp.upload(adj_ptr, st); dadj.upload(adj, st);
         if (tet > 0)
-            hipLaunchKernelGGL(k_tet_precompute, dim3(blocks_for(tet)), dim3(BLOCK), 0, st, tet, D.tv.p, D.y.p, dE.p, dnu.p,
+            hipLaunchKernelGGL(k_tet_precompute, dim3(blocks_for(tet)), dim3(BLOCK), 0, st, tet, D.tv.p, D.y.p, D.tE.p, D.tnu.p,
                                D.Bm.p, D.vol.p, D.tmu.p, D.tlam.p, dvalid.p);
         hipLaunchKernelGGL(k_node_mass, dim3(blocks_for(node)), dim3(BLOCK), 0, st, node, dadjp.p, dadj.p, D.vol.p, drho.p, D.mass.p);
         std::vector<double> h2s(n);

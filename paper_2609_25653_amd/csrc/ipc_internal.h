@@ -43,6 +43,8 @@ enum Slot {
     S_NEWTON_ON,    // 1 while the scene's Newton loop runs
     S_ETA2,         // PCG stop: eta^2 b.b
     S_MAXIT,        // PCG iteration cap
+    S_INDEF,        // 1 when the scene's PCG met p.Ap <= 0
+    S_MUBAR,        // adjoint: w . dG/dmu of the last step
     NSLOT
 };
 
@@ -149,6 +151,8 @@ struct Dev {
     DBuf<int4> tv;
     DBuf<double> Bm;                       // 9 arrays of nT
     DBuf<double> vol, tmu, tlam;
+    DBuf<double> tE, tnu;                  // Young's modulus and Poisson ratio per tet
+    DBuf<int> ext2tet;                     // external tet (scenes concatenated) -> internal tet
     DBuf<int> tslot;                       // 16 BSR slots per tet (row-major a*4+b)
     // FEM matrix (block CSR, 3x3 blocks, rows = nodes)
     DBuf<int> row_ptr, col, diag_slot;
@@ -194,6 +198,8 @@ struct Dev {
     DBuf<int4> lag_cv;
     DBuf<double> lag_beta, lag_nrm, lag_lam, lag_rn;
     DBuf<double> lag_M;                    // 6 (symmetric 3x3) per lag pair, scaled
+    DBuf<int> lag_type;                    // distance type at the lag state
+    DBuf<double> lag_ex;                   // edge-edge mollifier threshold (0 for PT)
     // scalars and partials
     DBuf<double> scal;                     // n_scenes x NSLOT
     DBuf<double> part_node, part_tet;      // one partial per wavefront
@@ -223,6 +229,7 @@ struct ipc_ctx {
     int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
     int nnzb = 0, nnzb_fem = 0, n_long = 0;
     int64_t ext_nodes = 0;
+    int64_t ext_tets = 0;
     // host copies of segment tables
     std::vector<int> seg_surf, seg_tri, seg_edge, seg_sp, seg_body;
     // dynamic counts

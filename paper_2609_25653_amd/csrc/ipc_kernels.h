@@ -37,12 +37,15 @@ void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *a
 void build_local_list(ipc_ctx *c);
 void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1);
 
-// per-scene scalars (ipc_solver.hip)
-const double *scene_h2(ipc_ctx *c);
-const double *scene_param(ipc_ctx *c, int which);   // 0 kappa, 1 dhat, 2 mu, 3 eps_v*h, 4 ccd_s
-void seg_sum(ipc_ctx *c, const double *vals, const int *seg_dev, int slot, bool accumulate);
-void node_seg_sum(ipc_ctx *c, const double *part, int slot, bool accumulate);
-void tet_seg_sum(ipc_ctx *c, const double *part, int slot, bool accumulate);
+// adjoint of the friction lag: ybar -= (dG_F/dy^n)^T w; per-pair w . dG/dmu into fr_part
+void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const double *w, double *ybar);
+
+// adjoint of one step (ipc_adjoint.hip)
+void launch_set_E(ipc_ctx *c, const double *E_ext);
+void launch_adj_rhs(ipc_ctx *c, const double *ybar_next, const double *vbar_next, double *rhs);
+void launch_adj_mass(ipc_ctx *c, const double *w, const double *vbar_next, double *ybar_prev, double *vbar_prev);
+void launch_adj_E(ipc_ctx *c, const double *y, const double *w, double *Ebar_ext);
+
 int *upload_seg(ipc_ctx *c, const std::vector<int> &seg, int which);
 
 } // namespace ipc

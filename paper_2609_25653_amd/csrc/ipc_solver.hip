@@ -50,6 +50,11 @@ __global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post,
     if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], total) : S[a.slot] + total) : total;
     if (post == POST_ALPHA) {
         S[S_ALPHA] = S[S_RZ] / S[S_PAP];
+        if (active[s] && !(S[S_PAP] > 0.0)) {   // not positive definite along p: stop here
+            S[S_INDEF] = 1.0;
+            S[S_ALPHA] = 0.0;
+            active[s] = 0;
+        }
     } else if (post == POST_PCG && active[s]) {
         S[S_RR] = rest;   // the sources after `split` carry r.r
         iters[s] += 1;
@@ -385,6 +390,7 @@ __global__ void k_pcg_start(int ns, double *__restrict__ scal, int *__restrict__
     double e = eta > 0.0 ? eta : S[S_ETA];
     S[S_ETA2] = e * e * S[S_BB];
     S[S_MAXIT] = (double)maxit[s];
+    S[S_INDEF] = 0.0;
     active[s] = (want ? want[s] : 1) && S[S_BB] > 0.0 ? 1 : 0;
 }
 

@@ -1,0 +1,70 @@
+"""Differentiable rollouts: ``IPCRollout``, a torch.autograd.Function over K steps.
+
+Forward runs the library's steps from (y0, ydot0) with parameters (E per tet,
+mu per scene) and keeps (y, ydot) every ``checkpoint_every`` steps.  Backward
+walks the checkpoint segments in reverse: it recomputes a segment's states
+from its checkpoint, then calls the library's one-step adjoint for each step
+of the segment, newest first, accumulating dL/dE and dL/dmu and carrying the
+state adjoints (ybar, vbar) back to the segment start.  Memory: one (y, ydot)
+pair per checkpoint plus the states of one segment.
+"""
+import torch
+
+from . import IPCError, Sim  # noqa: F401
+
+
+class IPCRollout(torch.autograd.Function):
+    """(E, mu, y0, ydot0) -> (y_K, ydot_K) over steps first_step .. first_step+K-1.
+
+    ``sim`` is a ``Sim`` over the scene(s); E has one entry per tet of all
+    scenes, mu one per scene.  The Newton and adjoint solves use the scenes'
+    own tolerances; ``eta`` is the adjoint PCG's relative residual."""
+
+    @staticmethod
+    def forward(ctx, E, mu, y0, ydot0, sim, first_step, n_steps, checkpoint_every=10, eta=1e-12):
+        E = E.detach().contiguous()
+        mu = mu.detach().contiguous()
+        sim.set_params(E, mu.cpu().numpy())
+        y, v = y0.detach().contiguous().clone(), ydot0.detach().contiguous().clone()
+        sim.set_state(y, v)
+        ckpts = []
+        for k in range(n_steps):
+            if k % checkpoint_every == 0:
+                ckpts.append((k, y, v))
+            sim.step(first_step + k)
+            y, v = sim.state()
+        ctx.sim, ctx.first, ctx.n, ctx.every, ctx.eta = sim, first_step, n_steps, checkpoint_every, eta
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(E, mu)
+        return y, v
+
+    @staticmethod
+    def backward(ctx, ybar, vbar):
+        sim = ctx.sim
+        E, mu = ctx.saved_tensors
+        sim.set_params(E, mu.cpu().numpy())
+        ybar = torch.zeros(sim.ndof, dtype=torch.float64, device=sim.device) if ybar is None else ybar.contiguous().clone()
+        vbar = torch.zeros(sim.ndof, dtype=torch.float64, device=sim.device) if vbar is None else vbar.contiguous().clone()
+        Ebar = torch.zeros(sim.n_tets, dtype=torch.float64, device=sim.device)
+        mubar = torch.zeros(sim.n_scenes, dtype=torch.float64, device=sim.device)
+        for c0, y, v in reversed(ctx.ckpts):
+            c1 = min(c0 + ctx.every, ctx.n)
+            states = [(y, v)]
+            sim.set_state(y, v)
+            for k in range(c0, c1):
+                sim.step(ctx.first + k)
+                states.append(sim.state())
+            for k in range(c1 - 1, c0 - 1, -1):
+                yp, vp = states[k - c0]
+                yn = states[k - c0 + 1][0]
+                ybar, vbar, _ = sim.step_vjp(yp, vp, ctx.first + k, yn, ybar, vbar, Ebar, mubar, ctx.eta)
+        # the context's state is left at the start of the rollout
+        return Ebar, mubar.to(mu.dtype).reshape(mu.shape), ybar, vbar, None, None, None, None, None
+
+
+def rollout(sim, E, mu, y0, ydot0, first_step, n_steps, checkpoint_every=10, eta=1e-12):
+    """Differentiable (y_K, ydot_K) of a K-step rollout; see ``IPCRollout``."""
+    mu = torch.as_tensor(mu, dtype=torch.float64, device=sim.device).reshape(-1)
+    if mu.numel() == 1 and sim.n_scenes > 1:
+        mu = mu.expand(sim.n_scenes).contiguous()
+    return IPCRollout.apply(E, mu, y0, ydot0, sim, first_step, n_steps, checkpoint_every, eta)
