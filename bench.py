@@ -23,20 +23,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton iters/s & sim steps/s at 200k tets; batched scenes/s; adjoint/forward time"
 HBM_PEAK_GBS = 8000.0
-KERNELS = {0: "spmv_bsr", 1: "fem_grad_hess", 2: "barrier_grad_hess", 3: "contact_apply", 4: "pcg_update",
-           5: "broad_phase", 6: "ccd", 7: "fem_energy"}
-
-
-def kernel_times(sim):
-    from paper_2609_25653_amd import lib
-    out = {}
-    for k, name in KERNELS.items():
-        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-        rc = lib().ipc_kernel_time(sim._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
-        if rc == 0 and n.value > 0:
-            out[name] = dict(total_ms=ms.value, launches=n.value, avg_us=1e3 * ms.value / n.value,
-                             bytes_per_launch=b.value / n.value)
-    return out
 
 
 def cpu_baseline(scene, pcg_per_newton):
@@ -75,6 +61,23 @@ def cpu_baseline(scene, pcg_per_newton):
                        f"iteration; CPU {model}")}
 
 
+def probe_spmv(sim):
+    """One assembly, one plain copy of known size, then 20 timed products."""
+    import torch
+    from paper_2609_25653_amd import lib
+    y, _ = sim.state()
+    sim.begin_step(0)
+    sim.energy_grad_hess(y, torch.ones_like(y), energy=False, grad=False)
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    us, by = ctypes.c_double(), ctypes.c_double()
+    sim._check(lib().ipc_time_kernel(sim._h, 0, 20, ctypes.byref(us), ctypes.byref(by)))
+    print(json.dumps({"probe": "spmv", "copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                      "spmv_launches": 20, "spmv_avg_us": us.value, "spmv_algorithmic_bytes": by.value}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +85,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=1e-3, help="ground patch spacing (m)")
+    ap.add_argument("--probe", choices=["spmv"], default=None,
+                    help="spmv: assemble the Hessian of the 200k-tet scene once, then run a plain 256 MiB device copy "
+                         "and 20 back-to-back block-CSR products (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (scenes would shard without "
@@ -96,6 +102,8 @@ def main():
     n_total = args.warmup + args.steps
     scene = ipcscenes.contact_rich(n_steps=n_total, s_g=args.s_g)
     sim = Sim(scene)
+    if args.probe == "spmv":
+        return probe_spmv(sim)
     for _ in range(args.warmup):
         sim.step(allow_status=(3,))
     torch.cuda.synchronize()
