@@ -72,9 +72,10 @@ def probe_spmv(sim):
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
+    lanes, times = sim.autotune(20)
     us, by = ctypes.c_double(), ctypes.c_double()
     sim._check(lib().ipc_time_kernel(sim._h, 0, 20, ctypes.byref(us), ctypes.byref(by)))
-    print(json.dumps({"probe": "spmv", "copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+    print(json.dumps({"probe": "spmv", "lanes_per_row": lanes, "autotune_us": times, "copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
                       "spmv_launches": 20, "spmv_avg_us": us.value, "spmv_algorithmic_bytes": by.value}))
 
 
@@ -106,6 +107,9 @@ def main():
         return probe_spmv(sim)
     for _ in range(args.warmup):
         sim.step(allow_status=(3,))
+    # autotune the product's lanes per row on the last warm-up matrix
+    lanes, tune_us = sim.autotune(20)
+    print(f"# autotune: {lanes} lanes per row; us per product {tune_us}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     newton = pcg = 0
     pairs = []
@@ -127,7 +131,7 @@ def main():
     sim._check(lib().ipc_time_kernel(sim._h, 0, 200, ctypes.byref(us), ctypes.byref(by)))
     achieved = by.value / (us.value * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "k_spmv (block-CSR Hessian product)", "bytes_per_launch": by.value,
+            "traffic": None, "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)", "bytes_per_launch": by.value,
             "avg_us": us.value}
     kt = {}
     line = {
@@ -142,6 +146,7 @@ def main():
         "pcg_per_newton": pcg / max(newton, 1),
         "active_pairs": {"min": int(min(pairs)), "median": float(np.median(pairs)), "max": int(max(pairs))},
         "roofline": roof,
+        "spmv_lanes_per_row": lanes,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, pcg / max(newton, 1))

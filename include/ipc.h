@@ -227,13 +227,15 @@ int ipc_step_vjp(ipc_ctx *ctx, const double *y_prev_dev, const double *ydot_prev
  * timed kernel, the summed duration of its launches since the reset, the
  * launch count and the summed algorithmic bytes of those launches (the bytes
  * the operation must move at minimum for its storage format: for IPC_K_SPMV,
- * 76 per stored 3x3 block (9 doubles + column index), 4 per row pointer, and
- * 24 read plus 24 written per FEM vertex). */
+ * 76 per stored 3x3 block (9 doubles + column index) of the matrix and of the
+ * row-sorted pair-local contact blocks, 4 per row pointer of each, and 24 read
+ * plus 24 written per FEM vertex and per body node). */
 enum {
-    IPC_K_SPMV = 0,          /* block-CSR product of the FEM Hessian            */
+    IPC_K_SPMV = 0,          /* Hessian product (block CSR + pair-local blocks) */
     IPC_K_FEM_HESS = 1,      /* FEM gradient + projected Hessian assembly        */
     IPC_K_BARRIER_HESS = 2,  /* barrier gradient + projected Hessian per pair    */
-    IPC_K_CONTACT_APPLY = 3, /* contact / friction Hessian product               */
+    IPC_K_CONTACT_APPLY = 3, /* unused: pair-local contact blocks are part of
+                                the IPC_K_SPMV product (records nothing)         */
     IPC_K_PCG_UPDATE = 4,    /* PCG vector update + preconditioner               */
     IPC_K_BROAD = 5,         /* LBVH build + traversal (both primitive kinds)    */
     IPC_K_CCD = 6,           /* additive CCD over candidates                     */
@@ -248,6 +250,14 @@ int ipc_kernel_time(ipc_ctx *ctx, int kernel, double *total_ms, int64_t *launche
  * IPC_K_SPMV.  avg_us and bytes (algorithmic bytes of one launch) are
  * written on success.  Uses the context's solver scratch vectors. */
 int ipc_time_kernel(ipc_ctx *ctx, int kernel, int reps, double *avg_us, double *bytes);
+/* Autotuner: times the Hessian product on the matrix of the last assembly
+ * with 1, 2, 4, 8 and 16 lanes per row (reps back-to-back launches each,
+ * HIP events on the context's stream) and keeps the fastest for all later
+ * products.  us_host[5] (nullable) receives the five times in microseconds,
+ * lanes_host (nullable) the choice.  The default before any call is 8 lanes
+ * (the environment variable IPC_SPMV_LANES, read at ipc_create, overrides
+ * it).  Uses the context's solver scratch vectors. */
+int ipc_autotune(ipc_ctx *ctx, int reps, double *us_host, int32_t *lanes_host);
 
 #ifdef __cplusplus
 }

@@ -159,6 +159,14 @@ class Sim:
         self.step_index += 1
         return rc, [s.as_dict() for s in st]
 
+    def autotune(self, reps=20):
+        """Pick the product's lanes per row on the current matrix; returns
+        (lanes, {lanes: microseconds})."""
+        us = np.zeros(5)
+        L = ctypes.c_int32()
+        self._check(lib().ipc_autotune(self._h, int(reps), us.ctypes.data_as(_lib._D), ctypes.byref(L)))
+        return L.value, dict(zip((1, 2, 4, 8, 16), us.tolist()))
+
     # ---- adjoint --------------------------------------------------------------
     @property
     def n_tets(self):

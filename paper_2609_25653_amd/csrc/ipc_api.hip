@@ -227,6 +227,7 @@ void setup_after_create(ipc_ctx *c)
     upload_seg_region(c, R_SURF, c->seg_surf);
     upload_seg_region(c, R_TRI, c->seg_tri);
     upload_seg_region(c, R_EDGE, c->seg_edge);
+    build_dyn_blocks(c);   // no pairs yet: row pointers and the long rows of the static pattern
     sync(c);
 }
 
@@ -295,7 +296,7 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     launch_spring(c, 1, y, g, D.sp_part.p, D.h2s.p);
     launch_barrier(c, hess ? 2 : 1, false, D.xw.p, g, project);
     if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p, g);
-    if (hess) build_local_list(c);
+    if (hess) build_dyn_blocks(c);
 }
 
 // Active pairs at internal y from a static broad phase.
@@ -387,6 +388,11 @@ extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_
     {
         const char *ng = std::getenv("IPC_NO_GRAPH");
         c->use_graphs = !(ng && ng[0] == '1');
+        const char *nl = std::getenv("IPC_SPMV_LANES");
+        if (nl) {
+            int L = std::atoi(nl);
+            if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) c->spmv_lanes = L;
+        }
         if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
     }
     int rc = guard(c, [&] {
@@ -500,7 +506,7 @@ extern "C" int ipc_energy_grad_hess(ipc_ctx *c, const double *y_dev, double *E_d
         if (hv) {
             hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.v1.p);
             hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, v_dev, D.v1.p);
-            hess_apply(c, D.v1.p, D.q.p, nullptr, false);
+            hess_apply(c, D.v1.p, D.q.p, nullptr, nullptr);
             hipLaunchKernelGGL(k_to_external, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, D.q.p, Hv_dev);
         }
         std::vector<int> inf(c->n_scenes);
@@ -942,6 +948,18 @@ extern "C" int ipc_kernel_time(ipc_ctx *c, int kernel, double *total_ms, int64_t
     });
 }
 
+extern "C" int ipc_autotune(ipc_ctx *c, int reps, double *us_host, int32_t *lanes_host)
+{
+    if (!c || reps < 1) return IPC_E_INVALID;
+    return guard(c, [&] {
+        bool prof = c->prof;
+        c->prof = false;
+        autotune_spmv(c, reps, us_host);
+        c->prof = prof;
+        if (lanes_host) *lanes_host = c->spmv_lanes;
+    });
+}
+
 extern "C" int ipc_time_kernel(ipc_ctx *c, int kernel, int reps, double *avg_us, double *bytes)
 {
     if (!c || reps < 1 || !avg_us || kernel != IPC_K_SPMV) return IPC_E_INVALID;
@@ -953,9 +971,9 @@ extern "C" int ipc_time_kernel(ipc_ctx *c, int kernel, int reps, double *avg_us,
         bool prof = c->prof;
         c->prof = false;
         // one warm launch, then the timed batch: q = H p on the current matrix
-        spmv_only(c, D.p.p, D.q.p);
+        hess_apply(c, D.p.p, D.q.p, nullptr, nullptr);
         IPC_HIP(hipEventRecord(e0, c->stream));
-        for (int k = 0; k < reps; ++k) spmv_only(c, D.p.p, D.q.p);
+        for (int k = 0; k < reps; ++k) hess_apply(c, D.p.p, D.q.p, nullptr, nullptr);
         IPC_HIP(hipEventRecord(e1, c->stream));
         IPC_HIP(hipEventSynchronize(e1));
         c->prof = prof;

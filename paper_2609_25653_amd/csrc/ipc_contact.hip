@@ -987,117 +987,248 @@ void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// contact Hessian product: out += sum_pairs J^T H J v (barrier pairs through the
-// reduced 9x9 blocks, friction pairs through beta and the 3x3 blocks), with the
-// local quadratic forms v^T H v per pair
+// Pair-local contact blocks as extra rows of the product.  A barrier or
+// friction pair whose blocks did not fit the matrix pattern couples the DOF
+// nodes of its vertices: a FEM vertex is one node, and the vertices of one
+// affine body share that body's 4 nodes with weights (1, xb).  The pair's
+// vertices are grouped by owner, and the pair emits one 3x3 block per
+// (node, node) of its groups, B = sum_{k in g, l in h} w_k w_l H_kl with H_kl
+// the world-vertex blocks.  Blocks are written per pair in a fixed order,
+// stably radix-sorted by row and gathered, so the product reads them per row
+// without atomics and in a run-to-run fixed order.
 // ---------------------------------------------------------------------------
-__global__ void k_contact_apply(int nb, int nf, const int4 *__restrict__ pcv, const double *__restrict__ pH,
-                                const int4 *__restrict__ lcv, const double *__restrict__ lbeta, const double *__restrict__ lM,
-                                const int *__restrict__ cv_scene, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
-                                const double *__restrict__ cv_x, const int *__restrict__ body_node0, const int *__restrict__ active,
-                                const double *__restrict__ v, double *__restrict__ out, double *__restrict__ part_b,
-                                double *__restrict__ part_f, const int *__restrict__ local, int nlocal)
+struct PairNodes {
+    int ng;          // owner groups (distinct FEM nodes / bodies)
+    int first[4];    // first DOF node of each group
+    int nn[4];       // nodes per group (1 FEM, 4 body)
+    int g[4];        // group of each vertex (-1: static)
+    int total;       // sum of nn
+};
+
+__device__ __forceinline__ PairNodes pair_nodes(const Map *mp)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nlocal) return;
-    int i = local[t];   // pair-local entries only: the rest were merged into the matrix
-    bool fr = i >= nb;
-    int j = fr ? i - nb : i;
-    int4 c4 = fr ? lcv[j] : pcv[j];
-    int cv[4] = {c4.x, c4.y, c4.z, c4.w};
-    int s = cv_scene[cv[0]];
-    double *part = fr ? part_f : part_b;
-    if (active && !active[s]) { if (part) part[j] = 0.0; return; }
-    Map mp[4];
-    d3 vw[4];
-    for (int k = 0; k < 4; ++k) { mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0); vw[k] = gather_cv(mp[k], v); }
-    if (!fr) {
-        double z[9], yv[9];
-        for (int ii = 0; ii < 3; ++ii) {
-            double a = 0, b = 0, cc = 0;
-            for (int k = 0; k < 4; ++k) { double U = helmert(k, ii); a += U * vw[k].x; b += U * vw[k].y; cc += U * vw[k].z; }
-            z[3 * ii] = a; z[3 * ii + 1] = b; z[3 * ii + 2] = cc;
+    PairNodes P;
+    P.ng = 0; P.total = 0;
+    for (int k = 0; k < 4; ++k) {
+        P.g[k] = -1;
+        int f = mp[k].node >= 0 ? mp[k].node : mp[k].body;
+        if (f < 0) continue;
+        int gi = -1;
+        for (int q = 0; q < P.ng; ++q) if (P.first[q] == f) gi = q;
+        if (gi < 0) {
+            gi = P.ng++;
+            P.first[gi] = f;
+            P.nn[gi] = mp[k].node >= 0 ? 1 : 4;
+            P.total += P.nn[gi];
         }
-        const double *H = pH + 45 * (size_t)j;
-        double qf = 0.0;
-        for (int R = 0; R < 9; ++R) {
-            double acc = 0.0;
-            for (int C = 0; C < 9; ++C) acc += H[pk9(R, C)] * z[C];
-            yv[R] = acc;
-            qf += z[R] * acc;
-        }
-        if (part) part[j] = qf;
-        for (int k = 0; k < 4; ++k) {
-            d3 o = {0, 0, 0};
-            for (int ii = 0; ii < 3; ++ii) {
-                double U = helmert(k, ii);
-                o.x += U * yv[3 * ii]; o.y += U * yv[3 * ii + 1]; o.z += U * yv[3 * ii + 2];
+        P.g[k] = gi;
+    }
+    return P;
+}
+
+__device__ __forceinline__ double map_weight(const Map &m, int q)
+{
+    if (m.node >= 0) return 1.0;
+    return q == 0 ? 1.0 : (q == 1 ? m.xb.x : (q == 2 ? m.xb.y : m.xb.z));
+}
+
+// world-vertex block (k, l) of pair entry i: barrier pairs (i < nb) from the
+// reduced 9x9 Hessian through the Helmert basis, friction pairs from beta and M
+__device__ __forceinline__ void pair_block(int i, int nb, const double *pH, const double *lbeta, const double *lM, int k, int l,
+                                           double *B)
+{
+    if (i < nb) {
+        const double *H = pH + 45 * (size_t)i;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0.0;
+                for (int ii = 0; ii < 3; ++ii)
+                    for (int jj = 0; jj < 3; ++jj) acc += helmert(k, ii) * helmert(l, jj) * H[pk9(3 * ii + a, 3 * jj + b)];
+                B[3 * a + b] = acc;
             }
-            scatter_cv(mp[k], out, o);
-        }
     } else {
-        double be[4];
-        for (int k = 0; k < 4; ++k) be[k] = lbeta[4 * (size_t)j + k];
-        d3 z = {0, 0, 0};
-        for (int k = 0; k < 4; ++k) { z.x += be[k] * vw[k].x; z.y += be[k] * vw[k].y; z.z += be[k] * vw[k].z; }
+        int j = i - nb;
         const double *M = lM + 6 * (size_t)j;
-        d3 yv = {M[0] * z.x + M[1] * z.y + M[2] * z.z, M[1] * z.x + M[3] * z.y + M[4] * z.z, M[2] * z.x + M[4] * z.y + M[5] * z.z};
-        if (part) part[j] = dt(z, yv);
-        for (int k = 0; k < 4; ++k) scatter_cv(mp[k], out, {be[k] * yv.x, be[k] * yv.y, be[k] * yv.z});
+        double bb = lbeta[4 * (size_t)j + k] * lbeta[4 * (size_t)j + l];
+        double Mf[9] = {M[0], M[1], M[2], M[1], M[3], M[4], M[2], M[4], M[5]};
+        for (int q = 0; q < 9; ++q) B[q] = bb * Mf[q];
     }
 }
 
-void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part_b, double *part_f)
+__device__ __forceinline__ void pair_maps(int i, int nb, const int4 *pcv, const int4 *lcv, const int *cv_node, const int *cv_body,
+                                          const double *cv_x, const int *body_node0, Map *mp)
 {
-    Dev &D = c->d;
-    int64_t nb = c->n_pt + c->n_ee, nf = c->fr_on ? c->n_lag : 0;
-    if (c->n_local == 0) return;
-    hipLaunchKernelGGL(k_contact_apply, dim3(blocks_for(c->n_local)), dim3(BLOCK), 0, c->stream, (int)nb, (int)nf, D.pair_cv.p,
-                       D.pair_H.p, D.lag_cv.p, D.lag_beta.p, D.lag_M.p, D.cv_scene.p, D.cv_node.p, D.cv_body.p, D.cv_x.p,
-                       D.body_node0.p, active, v, out, part_b, part_f, D.local_idx.p, (int)c->n_local);
+    int4 c4 = i < nb ? pcv[i] : lcv[i - nb];
+    int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+    for (int k = 0; k < 4; ++k) mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
 }
 
-// List of the pair-local entries (barrier pairs then friction pairs whose
-// blocks were not merged into the matrix): ballot per wavefront, scan of the
-// wavefront counts, write.
-template <bool WRITE>
-__global__ void k_local(int nb, int nf, const int *__restrict__ pflag, const int *__restrict__ lflag,
-                        unsigned long long *__restrict__ mask, int *__restrict__ wcount, const int *__restrict__ woff,
-                        int *__restrict__ out)
+// blocks per pair entry (0 when merged into the matrix)
+__global__ void k_dyn_count(int nb, int nf, const int *__restrict__ pflag, const int *__restrict__ lflag, const int4 *__restrict__ pcv,
+                            const int4 *__restrict__ lcv, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
+                            const double *__restrict__ cv_x, const int *__restrict__ body_node0, int *__restrict__ cnt,
+                            int *__restrict__ nlocal)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int wave = i / TILE, lane = threadIdx.x & (TILE - 1);
+    if (i >= nb + nf) return;
+    bool local = (i < nb ? pflag[i] : lflag[i - nb]) == 0;
+    int n = 0;
+    if (local) {
+        Map mp[4];
+        pair_maps(i, nb, pcv, lcv, cv_node, cv_body, cv_x, body_node0, mp);
+        PairNodes P = pair_nodes(mp);
+        n = P.total * P.total;
+        atomicAdd(nlocal, 1);
+    }
+    cnt[i] = n;
+}
+
+__global__ void k_dyn_write(int nb, int nf, const int *__restrict__ off, const int4 *__restrict__ pcv, const int4 *__restrict__ lcv,
+                            const double *__restrict__ pH, const double *__restrict__ lbeta, const double *__restrict__ lM,
+                            const int *__restrict__ cv_node, const int *__restrict__ cv_body, const double *__restrict__ cv_x,
+                            const int *__restrict__ body_node0, int *__restrict__ key, int *__restrict__ idx, int *__restrict__ colc,
+                            double *__restrict__ valc)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb + nf) return;
+    int o = off[i];
+    if (off[i + 1] == o) return;
+    Map mp[4];
+    pair_maps(i, nb, pcv, lcv, cv_node, cv_body, cv_x, body_node0, mp);
+    PairNodes P = pair_nodes(mp);
+    double B[9], S[9];
+    for (int ga = 0; ga < P.ng; ++ga)
+        for (int qa = 0; qa < P.nn[ga]; ++qa)
+            for (int gb = 0; gb < P.ng; ++gb)
+                for (int qb = 0; qb < P.nn[gb]; ++qb) {
+                    for (int q = 0; q < 9; ++q) S[q] = 0.0;
+                    for (int k = 0; k < 4; ++k) {
+                        if (P.g[k] != ga) continue;
+                        double wk = map_weight(mp[k], qa);
+                        for (int l = 0; l < 4; ++l) {
+                            if (P.g[l] != gb) continue;
+                            double w = wk * map_weight(mp[l], qb);
+                            pair_block(i, nb, pH, lbeta, lM, k, l, B);
+                            for (int q = 0; q < 9; ++q) S[q] += w * B[q];
+                        }
+                    }
+                    key[o] = P.first[ga] + qa;
+                    idx[o] = o;
+                    colc[o] = P.first[gb] + qb;
+                    for (int q = 0; q < 9; ++q) valc[9 * (size_t)o + q] = S[q];
+                    ++o;
+                }
+}
+
+__global__ void k_dyn_gather(int n, const int *__restrict__ idx, const int *__restrict__ colc, const double *__restrict__ valc,
+                             int *__restrict__ col, double *__restrict__ val)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int e = idx[p];
+    col[p] = colc[e];
+    for (int q = 0; q < 9; ++q) val[9 * (size_t)p + q] = valc[9 * (size_t)e + q];
+}
+
+// row pointers from the sorted row keys: every row start written exactly once
+__global__ void k_dyn_ptr(int n, int N, const int *__restrict__ key, int *__restrict__ ptr)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n) return;
+    int r = p < n ? key[p] : N;
+    int rp = p > 0 ? key[p - 1] : -1;
+    for (int q = rp + 1; q <= r; ++q) ptr[q] = p;
+}
+
+// rows whose static plus pair-local blocks exceed LONG_ROW, in node order
+template <bool WRITE>
+__global__ void k_long(int N, const int *__restrict__ row_ptr, const int *__restrict__ dyn_ptr, unsigned long long *__restrict__ mask,
+                       int *__restrict__ wcount, const int *__restrict__ woff, int *__restrict__ out)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    int wave = n / TILE, lane = threadIdx.x & (TILE - 1);
     if (!WRITE) {
-        bool loc = false;
-        if (i < nb + nf) loc = (i < nb ? pflag[i] : lflag[i - nb]) == 0;
-        unsigned long long m = __ballot(loc);
-        if (lane == 0 && wave * TILE < nb + nf) { mask[wave] = m; wcount[wave] = __popcll(m); }
+        bool lg = n < N && (row_ptr[n + 1] - row_ptr[n]) + (dyn_ptr[n + 1] - dyn_ptr[n]) > LONG_ROW;
+        unsigned long long m = __ballot(lg);
+        if (lane == 0 && wave * TILE < N) { mask[wave] = m; wcount[wave] = __popcll(m); }
     } else {
-        if (i >= nb + nf) return;
+        if (n >= N) return;
         unsigned long long m = mask[wave];
-        if ((m >> lane) & 1ull) out[woff[wave] + __popcll(m & ((1ull << lane) - 1ull))] = i;
+        if ((m >> lane) & 1ull) out[woff[wave] + __popcll(m & ((1ull << lane) - 1ull))] = n;
     }
 }
 
-void build_local_list(ipc_ctx *c)
+// per-scene segments of the long-row list (node ranges of scenes are tiles)
+__global__ void k_long_seg(int ns, const int *__restrict__ nodew, const int *__restrict__ rows, int nlong, int *__restrict__ seg)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > ns) return;
+    int start = nodew[s] * TILE, lo = 0, hi = nlong;
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (rows[m] < start) lo = m + 1; else hi = m;
+    }
+    seg[s] = lo;
+}
+
+void build_dyn_blocks(ipc_ctx *c)
 {
     Dev &D = c->d;
     hipStream_t st = c->stream;
     int64_t nb = c->n_pt + c->n_ee, nf = c->fr_on ? c->n_lag : 0, n = nb + nf;
+    int N = c->N;
+    D.dyn_ptr.alloc(N + 1);
     c->n_local = 0;
-    if (n == 0) return;
-    int nw = (int)((n + TILE - 1) / TILE);
-    D.mkey.alloc(nw);
-    D.wcount.alloc(nw + 1); D.woff.alloc(nw + 1);
-    D.local_idx.alloc(n);
-    hipLaunchKernelGGL(k_local<false>, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.pair_flag.p, D.lag_flag.p, D.mkey.p,
-                       D.wcount.p, nullptr, nullptr);
+    c->n_dyn = 0;
+    if (n > 0) {
+        D.dyn_cnt.alloc(n + 1); D.dyn_off.alloc(n + 1);
+        D.tickets.alloc(4);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.tickets.p, 0);
+        hipLaunchKernelGGL(k_dyn_count, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.pair_flag.p, D.lag_flag.p,
+                           D.pair_cv.p, D.lag_cv.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_cnt.p, D.tickets.p);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.dyn_cnt.p + n, 0);
+        exclusive_scan(c, D.dyn_cnt.p, D.dyn_off.p, (int)n);
+        c->n_dyn = read_int(c, D.dyn_off.p + n);
+        c->n_local = read_int(c, D.tickets.p);
+    }
+    int64_t E = c->n_dyn;
+    if (E > 0) {
+        if (E > c->cap_dyn) {
+            c->cap_dyn = E + E / 2 + 1024;
+            for (auto *b : {&D.dyn_key, &D.dyn_key2, &D.dyn_idx, &D.dyn_idx2, &D.dyn_col_coo, &D.dyn_col}) b->alloc(c->cap_dyn);
+            D.dyn_val.alloc(9 * (size_t)c->cap_dyn); D.dyn_val_coo.alloc(9 * (size_t)c->cap_dyn);
+        }
+        hipLaunchKernelGGL(k_dyn_write, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.dyn_off.p, D.pair_cv.p, D.lag_cv.p,
+                           D.pair_H.p, D.lag_beta.p, D.lag_M.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_key.p,
+                           D.dyn_idx.p, D.dyn_col_coo.p, D.dyn_val_coo.p);
+        int end_bit = 1;
+        while ((1ll << end_bit) <= N) ++end_bit;
+        size_t bytes = 0;
+        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.dyn_key.p, D.dyn_key2.p, D.dyn_idx.p, D.dyn_idx2.p, (int)E, 0,
+                                                   end_bit, st));
+        D.sort_tmp.alloc(bytes + 16);
+        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.sort_tmp.p, bytes, D.dyn_key.p, D.dyn_key2.p, D.dyn_idx.p, D.dyn_idx2.p, (int)E, 0,
+                                                   end_bit, st));
+        hipLaunchKernelGGL(k_dyn_gather, dim3(blocks_for(E)), dim3(BLOCK), 0, st, (int)E, D.dyn_idx2.p, D.dyn_col_coo.p,
+                           D.dyn_val_coo.p, D.dyn_col.p, D.dyn_val.p);
+        hipLaunchKernelGGL(k_dyn_ptr, dim3(blocks_for(E + 1)), dim3(BLOCK), 0, st, (int)E, N, D.dyn_key2.p, D.dyn_ptr.p);
+    } else {
+        hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(N + 1)), dim3(BLOCK), 0, st, N + 1, D.dyn_ptr.p, 0);
+    }
+    // long rows of the product
+    int nw = (N + TILE - 1) / TILE;
+    D.mkey.alloc(nw); D.wcount.alloc(nw + 1); D.woff.alloc(nw + 1); D.long_rows.alloc(N + 1);
+    hipLaunchKernelGGL(k_long<false>, dim3(blocks_for(N)), dim3(BLOCK), 0, st, N, D.row_ptr.p, D.dyn_ptr.p, D.mkey.p, D.wcount.p,
+                       nullptr, nullptr);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.wcount.p + nw, 0);
     exclusive_scan(c, D.wcount.p, D.woff.p, nw);
-    c->n_local = read_int(c, D.woff.p + nw);
-    if (c->n_local)
-        hipLaunchKernelGGL(k_local<true>, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.pair_flag.p, D.lag_flag.p,
-                           D.mkey.p, D.wcount.p, D.woff.p, D.local_idx.p);
+    c->n_long = read_int(c, D.woff.p + nw);
+    if (c->n_long)
+        hipLaunchKernelGGL(k_long<true>, dim3(blocks_for(N)), dim3(BLOCK), 0, st, N, D.row_ptr.p, D.dyn_ptr.p, D.mkey.p, D.wcount.p,
+                           D.woff.p, D.long_rows.p);
+    D.part_long.alloc(c->n_long + 1);
+    hipLaunchKernelGGL(k_long_seg, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes, seg_ptr(c, R_NODEW),
+                       D.long_rows.p, c->n_long, seg_ptr(c, R_LONG));
 }
 
 // ---------------------------------------------------------------------------

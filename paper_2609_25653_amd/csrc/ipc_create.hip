@@ -459,7 +459,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     }
     c->nnzb = row_ptr[node];
     c->nnzb_fem = 0;
-    std::vector<int> tslot(16 * (size_t)tet, 0), diag_slot(node, -1), bslot(16 * (size_t)std::max(body, 1), 0), long_rows;
+    std::vector<int> tslot(16 * (size_t)tet, 0), diag_slot(node, -1), bslot(16 * (size_t)std::max(body, 1), 0);
     auto find_slot = [&](int r, int cc) {
         auto b = col.begin() + row_ptr[r], e = col.begin() + row_ptr[r + 1];
         return (int)(std::lower_bound(b, e, cc) - col.begin());
@@ -472,11 +472,9 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     for (int i = 0; i < node; ++i) {
         if (node_kind[i] != 2) diag_slot[i] = find_slot(i, i);
         if (node_kind[i] == 0) c->nnzb_fem += row_ptr[i + 1] - row_ptr[i];
-        if (row_ptr[i + 1] - row_ptr[i] > LONG_ROW) long_rows.push_back(i);
     }
     for (int b = 0; b < body; ++b)
         for (int k = 0; k < 4; ++k) for (int m = 0; m < 4; ++m) bslot[16 * b + 4 * k + m] = find_slot(body_node0[b] + k, body_node0[b] + m);
-    c->n_long = (int)long_rows.size();
     // segment tables (per-scene ranges) used by the segmented reductions
     c->seg_surf.resize(n + 1); c->seg_tri.resize(n + 1); c->seg_edge.resize(n + 1); c->seg_sp.resize(n + 1); c->seg_body.resize(n + 1);
     for (int s = 0; s < n; ++s) {
@@ -488,7 +486,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     // ---- upload
     Dev &D = c->d;
     D.y.upload(X, st); D.ydot.upload(V, st);
-    for (auto *b : {&D.xt, &D.y0, &D.yt, &D.g, &D.p, &D.r, &D.z, &D.q, &D.x, &D.v1, &D.v2}) b->alloc(3 * (size_t)node);
+    for (auto *b : {&D.xt, &D.y0, &D.yt, &D.g, &D.p, &D.r, &D.z, &D.q, &D.w, &D.x, &D.v1, &D.v2}) b->alloc(3 * (size_t)node);
     IPC_HIP(hipMemcpyAsync(D.xt.p, D.y.p, 3 * (size_t)node * sizeof(double), hipMemcpyDeviceToDevice, st));
     D.node_scene.upload(node_scene, st); D.node_kind.upload(node_kind, st); D.ext2node.upload(ext2node, st);
     D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node); D.diagF.alloc(9 * (size_t)node);
@@ -498,7 +496,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     D.row_ptr.upload(row_ptr, st); D.col.upload(col, st); D.diag_slot.upload(diag_slot, st);
     D.val.alloc(9 * (size_t)std::max(c->nnzb, 1));
     D.val_const.alloc(9 * (size_t)std::max(c->nnzb, 1)); D.val_const.zero(st, 9 * (size_t)std::max(c->nnzb, 1));
-    D.bslot.upload(bslot, st); D.long_rows.upload(long_rows, st);
+    D.bslot.upload(bslot, st);
     D.bM.upload(bM, st); D.bvol.upload(bvol, st); D.bkappa.upload(bkappa, st); D.bext.upload(bext, st);
     D.body_node0.upload(body_node0, st); D.body_scene.upload(body_scene, st);
     D.diagB.alloc(144 * (size_t)std::max(body, 1));

@@ -19,7 +19,7 @@ namespace ipc {
 
 constexpr int TILE = 64;      // wavefront size on CDNA
 constexpr int BLOCK = 256;    // default workgroup: 4 wavefronts
-constexpr int LONG_ROW = 48;  // rows with more blocks go to the wavefront-per-row path
+constexpr int LONG_ROW = 64;  // rows with more blocks go to the wavefront-per-row path
 
 // per-scene device scalar slots
 enum Slot {
@@ -57,6 +57,7 @@ enum Region {
     R_PT, R_EE,     // active pairs
     R_LPT, R_LEE,   // friction lag lists
     R_QSEG, R_PSEG, R_TMP,
+    R_LONG,         // rows of the product handled one wavefront per row
     NREGION
 };
 
@@ -69,14 +70,19 @@ struct RedSrc {
     int off;
     int base;
 };
+// Per-scene reduction of up to 8 sources.  Each source's sum can be stored in
+// its own slot; the sources of group g (grp[k] = g) are combined in source
+// order into the slot of that group (slot, slot1, slot2).
 struct RedArgs {
     RedSrc src[8];
     int nsrc = 0;
-    int slot = -1;          // total goes here (-1: none)
-    int acc = 0;            // accumulate into the total slot
+    int slot = -1;          // total of group 0 (-1: none)
+    int slot1 = -1;         // total of group 1
+    int slot2 = -1;         // total of group 2
+    int acc = 0;            // accumulate into the group-0 slot
     int slots[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // per-source sums (-1: none)
+    int grp[8] = {0, 0, 0, 0, 0, 0, 0, 0};             // group of each source
     int op = 0;             // 0 sum, 1 max
-    int split = 0;          // > 0: only the first `split` sources enter the total
 };
 
 #define IPC_HIP(call)                                                           \
@@ -141,7 +147,7 @@ struct SceneInfo {
 
 struct Dev {
     // nodes
-    DBuf<double> y, ydot, xt, y0, yt, g, p, r, z, q, x, v1, v2;
+    DBuf<double> y, ydot, xt, y0, yt, g, p, r, z, q, w, x, v1, v2;
     DBuf<int> node_scene, node_kind;       // kind: 0 FEM, 1 body node, 2 padding
     DBuf<double> mass;                     // lumped FEM vertex mass (0 elsewhere)
     DBuf<double> dinv;                     // 3x3 inverse diagonal block per node
@@ -157,7 +163,11 @@ struct Dev {
     // FEM matrix (block CSR, 3x3 blocks, rows = nodes)
     DBuf<int> row_ptr, col, diag_slot;
     DBuf<double> val, val_const;           // assembled values; constant part (mass, springs)
-    DBuf<int> bslot, long_rows;            // 16 body-block slots per body; rows with > LONG_ROW blocks
+    DBuf<int> bslot, long_rows;            // 16 body-block slots per body; rows with > LONG_ROW blocks in all
+    // pair-local contact blocks, sorted by row: extra blocks of the product
+    DBuf<int> dyn_ptr, dyn_col, dyn_cnt, dyn_off, dyn_key, dyn_key2, dyn_idx, dyn_idx2, dyn_col_coo;
+    DBuf<double> dyn_val, dyn_val_coo;
+    DBuf<double> part_node3, part_long;    // product dot partials (per wavefront of nodes / per long row)
     // bodies
     DBuf<double> bM;                       // 4x4 mass matrix per body
     DBuf<double> bvol, bkappa, bext;
@@ -211,8 +221,7 @@ struct Dev {
     DBuf<int> inf_flag, ls_active, pcg_active, pcg_iters, maxpcg, newton_on;
     DBuf<int> leafpar, is_trans;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
-    DBuf<int> local_idx;                   // pair-local entries (barrier pairs, then friction pairs)
-    DBuf<int> tickets;                     // last-workgroup counters
+    DBuf<int> tickets;                     // small device counters
     DBuf<double> body_part2;
     DBuf<double> grav;
     DBuf<double> red_tmp;
@@ -228,6 +237,8 @@ struct ipc_ctx {
     int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
     int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
     int nnzb = 0, nnzb_fem = 0, n_long = 0;
+    int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly
+    int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
     int64_t ext_nodes = 0;
     int64_t ext_tets = 0;
     // host copies of segment tables
@@ -272,8 +283,8 @@ void prof_begin(ipc_ctx *c, int k);
 void prof_end(ipc_ctx *c, int k, double bytes);
 void store_pair_segs(ipc_ctx *c);
 __global__ void k_fill_int_api(int n, int *p, int v);
-void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool partials);
-void spmv_only(ipc_ctx *c, const double *v, double *out);
+void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part);
+void autotune_spmv(ipc_ctx *c, int reps, double *us);
 double spmv_bytes(const ipc_ctx *c);
 void build_preconditioner(ipc_ctx *c);
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);

@@ -33,8 +33,9 @@ void narrow_phase(ipc_ctx *c, const double *xw);
 void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project);
 void launch_lag(ipc_ctx *c, const double *xw);
 void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g);
-void launch_contact_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part_b, double *part_f);
-void build_local_list(ipc_ctx *c);
+// pair-local contact blocks as row-sorted extra blocks of the product, and the
+// rows the product takes one wavefront per row
+void build_dyn_blocks(ipc_ctx *c);
 void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1);
 
 // adjoint of the friction lag: ybar -= (dG_F/dy^n)^T w; per-pair w . dG/dmu into fr_part

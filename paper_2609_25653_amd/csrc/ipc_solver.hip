@@ -13,60 +13,73 @@
 namespace ipc {
 
 // ---------------------------------------------------------------------------
-// reductions: one workgroup per scene, fixed-order strided sums and a tree.
-// The post step runs in the same workgroup once the sums are known.
+// reductions: one workgroup per scene.  Each thread sums a fixed strided
+// subset of a source's partials, wavefront shuffles and a 4-entry LDS step
+// combine them in a fixed order, and the post step runs in the same
+// workgroup once the sums are known.
 // ---------------------------------------------------------------------------
-enum Post { POST_NONE = 0, POST_ALPHA = 1, POST_PCG = 2 };
+enum Post { POST_NONE = 0, POST_CG_FIRST = 1, POST_CG = 2 };
 
-__global__ void k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post, int *__restrict__ active, int *__restrict__ iters)
+__global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post, int *__restrict__ active,
+                                                int *__restrict__ iters)
 {
     int s = blockIdx.x;
-    __shared__ double sh[256];
-    double total = 0.0, rest = 0.0;
-    for (int k = 0; k < a.nsrc; ++k) {
+    __shared__ double sh[8][BLOCK / TILE];
+    int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k >= a.nsrc) break;
         const RedSrc &r = a.src[k];
         double part = 0.0;
         if (r.v) {
             int lo = r.seg[s] - r.base, hi = r.seg[s + 1] - r.base;
-            for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+            for (int i = lo + (int)threadIdx.x; i < hi; i += BLOCK) {
                 double v = r.v[r.off + i];
                 part = a.op ? fmax(part, v) : part + v;
             }
         }
-        sh[threadIdx.x] = part;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) sh[threadIdx.x] = a.op ? fmax(sh[threadIdx.x], sh[threadIdx.x + o]) : sh[threadIdx.x] + sh[threadIdx.x + o];
-            __syncthreads();
-        }
-        double v = sh[0];
-        __syncthreads();
-        if (threadIdx.x == 0 && a.slots[k] >= 0) scal[(size_t)s * NSLOT + a.slots[k]] = v;
-        if (a.split == 0 || k < a.split) total = a.op ? fmax(total, v) : total + v;
-        else rest += v;
+        part = a.op ? wave_max(part) : wave_sum(part);
+        if (lane == 0) sh[k][wave] = part;
     }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double *S = scal + (size_t)s * NSLOT;
-    if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], total) : S[a.slot] + total) : total;
-    if (post == POST_ALPHA) {
-        S[S_ALPHA] = S[S_RZ] / S[S_PAP];
-        if (active[s] && !(S[S_PAP] > 0.0)) {   // not positive definite along p: stop here
-            S[S_INDEF] = 1.0;
-            S[S_ALPHA] = 0.0;
-            active[s] = 0;
-        }
-    } else if (post == POST_PCG && active[s]) {
-        S[S_RR] = rest;   // the sources after `split` carry r.r
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < a.nsrc; ++k) {
+        double v = sh[k][0];
+        for (int w = 1; w < BLOCK / TILE; ++w) v = a.op ? fmax(v, sh[k][w]) : v + sh[k][w];
+        if (a.slots[k] >= 0) S[a.slots[k]] = v;
+        int g = a.grp[k];
+        if (g >= 0) tot[g] = a.op ? fmax(tot[g], v) : tot[g] + v;
+    }
+    if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], tot[0]) : S[a.slot] + tot[0]) : tot[0];
+    if (a.slot1 >= 0) S[a.slot1] = tot[1];
+    if (a.slot2 >= 0) S[a.slot2] = tot[2];
+    if (post == POST_NONE || !active[s]) return;
+    // Conjugate gradients with one reduction per iteration (Chronopoulos and
+    // Gear): with gamma = r.z and delta = z.Az of the current residual,
+    //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
+    //   alpha = gamma / p.Ap.
+    double gam = S[S_RZ_NEW], del = S[S_PAP], be = 0.0;
+    if (post == POST_CG) {
         iters[s] += 1;
         if (S[S_RR] <= S[S_ETA2] || iters[s] >= (int)S[S_MAXIT]) { active[s] = 0; return; }
-        S[S_BETA] = S[S_RZ_NEW] / S[S_RZ];
-        S[S_RZ] = S[S_RZ_NEW];
+        be = gam / S[S_RZ];
+        del -= be * gam / S[S_ALPHA];
     }
+    if (!(del > 0.0)) {   // not positive definite along the search direction: stop here
+        S[S_INDEF] = 1.0;
+        active[s] = 0;
+        return;
+    }
+    S[S_BETA] = be;
+    S[S_ALPHA] = gam / del;
+    S[S_RZ] = gam;
 }
 
 void reduce_post(ipc_ctx *c, const RedArgs &a, int post)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(c->n_scenes), dim3(256), 0, c->stream, c->n_scenes, a, c->d.scal.p, post, c->d.pcg_active.p,
+    hipLaunchKernelGGL(k_reduce, dim3(c->n_scenes), dim3(BLOCK), 0, c->stream, c->n_scenes, a, c->d.scal.p, post, c->d.pcg_active.p,
                        c->d.pcg_iters.p);
 }
 
@@ -82,101 +95,154 @@ RedSrc src(const double *v, const int *seg, int off, int base)
 int *seg_ptr(ipc_ctx *c, int region) { return c->d.segs.p + (size_t)region * (c->n_scenes + 1); }
 
 // ---------------------------------------------------------------------------
-// Hessian product
+// Hessian product out = H v: the block-CSR matrix (elasticity, inertia,
+// orthogonality, springs and the contact blocks merged at assembly) plus the
+// row-sorted pair-local contact blocks.
+//
+// One workgroup per tile of 64 rows, L lanes per row (workgroup 64 L): the L
+// lanes of a row read consecutive blocks (coalesced 72 B runs), and a 44k-row
+// matrix still yields L x 700 wavefronts, enough to hide the gather latency
+// of v.  The row's partial sums meet through shuffles inside the lane group.
+// Rows with more than LONG_ROW blocks in all (affine-body nodes with many
+// springs or contacts) go to extra workgroups, one wavefront per row.  With
+// `part`, also v . out per tile (long rows into part_long): the dot product
+// the conjugate-gradient step needs, in the same pass.  L is chosen by the
+// autotuner among 1, 2, 4, 8 and 16.
 // ---------------------------------------------------------------------------
-// Rows with at most LONG_ROW blocks: one thread per row.  Longer rows (affine
-// body nodes carrying many springs): one wavefront per row, lanes striding
-// over the blocks, then a wavefront reduction.  Same launch.
-__global__ void __launch_bounds__(256) k_spmv(int N, int nshort_blocks, int nlong, const int *__restrict__ long_rows,
-                                              const int *__restrict__ row_ptr, const int *__restrict__ col,
-                                              const double *__restrict__ val, const double *__restrict__ v,
-                                              const int *__restrict__ node_scene, const int *__restrict__ active,
-                                              double *__restrict__ out)
+__device__ __forceinline__ void acc_block(const double *__restrict__ B, d3 w, double &ax, double &ay, double &az)
 {
-    if ((int)blockIdx.x < nshort_blocks) {
-        int n = blockIdx.x * blockDim.x + threadIdx.x;
-        if (n >= N) return;
-        int k0 = row_ptr[n], k1 = row_ptr[n + 1];
-        if (k1 - k0 > LONG_ROW) return;
+    ax += B[0] * w.x + B[1] * w.y + B[2] * w.z;
+    ay += B[3] * w.x + B[4] * w.y + B[5] * w.z;
+    az += B[6] * w.x + B[7] * w.y + B[8] * w.z;
+}
+
+template <int L>
+__global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, int nlong, const int *__restrict__ long_rows,
+                                                 const int *__restrict__ row_ptr, const int *__restrict__ col,
+                                                 const double *__restrict__ val, const int *__restrict__ dptr,
+                                                 const int *__restrict__ dcol, const double *__restrict__ dval,
+                                                 const double *__restrict__ v, const int *__restrict__ node_scene,
+                                                 const int *__restrict__ active, double *__restrict__ out,
+                                                 double *__restrict__ part, double *__restrict__ part_long)
+{
+    constexpr int NW = L;   // wavefronts per workgroup
+    int lane = threadIdx.x & (TILE - 1);
+    if ((int)blockIdx.x < ntiles) {
+        __shared__ double sh[NW];
+        int sub = threadIdx.x % L;
+        int n = blockIdx.x * TILE + threadIdx.x / L;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        if (!active || active[node_scene[n]]) {
-            for (int k = k0; k < k1; ++k) {
-                const double *B = val + 9 * (size_t)k;
-                d3 w = ld3(v, col[k]);
-                ax += B[0] * w.x + B[1] * w.y + B[2] * w.z;
-                ay += B[3] * w.x + B[4] * w.y + B[5] * w.z;
-                az += B[6] * w.x + B[7] * w.y + B[8] * w.z;
+        bool mine = false, on = false;
+        if (n < N) {
+            int k0 = row_ptr[n], k1 = row_ptr[n + 1], d0 = dptr[n], d1 = dptr[n + 1];
+            if ((k1 - k0) + (d1 - d0) <= LONG_ROW) {
+                mine = true;
+                on = !active || active[node_scene[n]];
+                if (on) {
+                    for (int k = k0 + sub; k < k1; k += L) acc_block(val + 9 * (size_t)k, ld3(v, col[k]), ax, ay, az);
+                    for (int k = d0 + sub; k < d1; k += L) acc_block(dval + 9 * (size_t)k, ld3(v, dcol[k]), ax, ay, az);
+                }
             }
         }
-        st3(out, n, {ax, ay, az});
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) {
+            ax += __shfl_xor(ax, o, TILE);
+            ay += __shfl_xor(ay, o, TILE);
+            az += __shfl_xor(az, o, TILE);
+        }
+        double dot = 0.0;
+        if (mine && sub == 0) {
+            st3(out, n, {ax, ay, az});
+            if (part && on) dot = dt(ld3(v, n), {ax, ay, az});
+        }
+        if (part) {
+            dot = wave_sum(dot);
+            if (lane == 0) sh[threadIdx.x / TILE] = dot;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = sh[0];
+                for (int q = 1; q < NW; ++q) t += sh[q];
+                part[blockIdx.x] = t;
+            }
+        }
         return;
     }
-    int w = (blockIdx.x - nshort_blocks) * (blockDim.x / TILE) + threadIdx.x / TILE;
-    int lane = threadIdx.x & (TILE - 1);
+    int w = ((int)blockIdx.x - ntiles) * NW + threadIdx.x / TILE;
     if (w >= nlong) return;
     int n = long_rows[w];
     double ax = 0.0, ay = 0.0, az = 0.0;
-    if (!active || active[node_scene[n]]) {
-        for (int k = row_ptr[n] + lane; k < row_ptr[n + 1]; k += TILE) {
-            const double *B = val + 9 * (size_t)k;
-            d3 x = ld3(v, col[k]);
-            ax += B[0] * x.x + B[1] * x.y + B[2] * x.z;
-            ay += B[3] * x.x + B[4] * x.y + B[5] * x.z;
-            az += B[6] * x.x + B[7] * x.y + B[8] * x.z;
-        }
+    bool on = !active || active[node_scene[n]];
+    if (on) {
+        for (int k = row_ptr[n] + lane; k < row_ptr[n + 1]; k += TILE) acc_block(val + 9 * (size_t)k, ld3(v, col[k]), ax, ay, az);
+        for (int k = dptr[n] + lane; k < dptr[n + 1]; k += TILE) acc_block(dval + 9 * (size_t)k, ld3(v, dcol[k]), ax, ay, az);
     }
     ax = wave_sum(ax); ay = wave_sum(ay); az = wave_sum(az);
-    if (lane == 0) st3(out, n, {ax, ay, az});
-}
-
-// p.Ap per wavefront of nodes (the per-scene sum and alpha follow in k_reduce;
-// summing in the producer's last workgroup would need a device-scope release
-// fence per workgroup, which writes back the XCD's L2 and costs more than the
-// extra launch)
-__global__ void k_dot(int N, const int *__restrict__ node_scene, const int *__restrict__ active, const double *__restrict__ a,
-                      const double *__restrict__ b, double *__restrict__ part)
-{
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (n < N && active[node_scene[n]]) s = dt(ld3(a, n), ld3(b, n));
-    s = wave_sum(s);
-    if ((threadIdx.x & (TILE - 1)) == 0 && n < N) part[n / TILE] = s;
-}
-
-// Algorithmic bytes of one block-CSR product: 76 per stored block (9 doubles
-// + column index), 4 per row pointer, and 24 read plus 24 written per
-// non-padding node.
-double spmv_bytes(const ipc_ctx *c) { return 76.0 * c->nnzb + 4.0 * (c->N + 1) + 48.0 * (c->NFEM + 4.0 * c->NB); }
-
-void spmv_only(ipc_ctx *c, const double *v, double *out)
-{
-    Dev &D = c->d;
-    int nshort = blocks_for(c->N);
-    int nlongb = (c->n_long + BLOCK / TILE - 1) / (BLOCK / TILE);
-    hipLaunchKernelGGL(k_spmv, dim3(nshort + nlongb), dim3(BLOCK), 0, c->stream, c->N, nshort, c->n_long, D.long_rows.p, D.row_ptr.p,
-                       D.col.p, D.val.p, v, D.node_scene.p, nullptr, out);
-}
-
-void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, bool pap)
-{
-    Dev &D = c->d;
-    hipStream_t st = c->stream;
-    int nshort = blocks_for(c->N);
-    int nlongb = (c->n_long + BLOCK / TILE - 1) / (BLOCK / TILE);
-    prof_begin(c, IPC_K_SPMV);
-    hipLaunchKernelGGL(k_spmv, dim3(nshort + nlongb), dim3(BLOCK), 0, st, c->N, nshort, c->n_long, D.long_rows.p, D.row_ptr.p, D.col.p,
-                       D.val.p, v, D.node_scene.p, active, out);
-    prof_end(c, IPC_K_SPMV, spmv_bytes(c));
-    prof_begin(c, IPC_K_CONTACT_APPLY);
-    launch_contact_apply(c, v, out, active, nullptr, nullptr);
-    prof_end(c, IPC_K_CONTACT_APPLY, 0.0);
-    if (pap) {
-        hipLaunchKernelGGL(k_dot, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, active, v, out, D.part_node.p);
-        RedArgs a{};
-        a.src[a.nsrc++] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0);
-        a.slot = S_PAP;
-        reduce_post(c, a, POST_ALPHA);
+    if (lane == 0) {
+        st3(out, n, {ax, ay, az});
+        if (part_long) part_long[w] = on ? dt(ld3(v, n), {ax, ay, az}) : 0.0;
     }
+}
+
+// Algorithmic bytes of one product: 76 per stored block (9 doubles + column
+// index) of the matrix and of the pair-local list, 4 per row pointer of each,
+// and 24 read plus 24 written per non-padding node.
+double spmv_bytes(const ipc_ctx *c)
+{
+    return 76.0 * ((double)c->nnzb + (double)c->n_dyn) + 8.0 * (c->N + 1) + 48.0 * (c->NFEM + 4.0 * c->NB);
+}
+
+static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const int *active, double *part)
+{
+    Dev &D = c->d;
+    int ntiles = (c->N + TILE - 1) / TILE;
+    int nlongb = (c->n_long + L - 1) / L;
+    dim3 grid(ntiles + nlongb), blk(64 * L);
+    double *pl = part ? D.part_long.p : nullptr;
+#define IPC_SPMV(LL) hipLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, c->N, ntiles, c->n_long, D.long_rows.p, D.row_ptr.p, D.col.p, \
+                                        D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, v, D.node_scene.p, active, out, part, pl)
+    switch (L) {
+    case 1: IPC_SPMV(1); break;
+    case 2: IPC_SPMV(2); break;
+    case 4: IPC_SPMV(4); break;
+    case 8: IPC_SPMV(8); break;
+    default: IPC_SPMV(16); break;
+    }
+#undef IPC_SPMV
+}
+
+void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part)
+{
+    prof_begin(c, IPC_K_SPMV);
+    spmv_launch(c, c->spmv_lanes, v, out, active, part);
+    prof_end(c, IPC_K_SPMV, spmv_bytes(c));
+}
+
+// Time every lane count on the current matrix (reps back-to-back launches
+// each, HIP events on the context's stream) and keep the fastest.
+void autotune_spmv(ipc_ctx *c, int reps, double *us)
+{
+    Dev &D = c->d;
+    const int Ls[5] = {1, 2, 4, 8, 16};
+    hipEvent_t e0, e1;
+    IPC_HIP(hipEventCreate(&e0));
+    IPC_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int bestL = c->spmv_lanes;
+    for (int i = 0; i < 5; ++i) {
+        spmv_launch(c, Ls[i], D.p.p, D.q.p, nullptr, nullptr);
+        IPC_HIP(hipEventRecord(e0, c->stream));
+        for (int k = 0; k < reps; ++k) spmv_launch(c, Ls[i], D.p.p, D.q.p, nullptr, nullptr);
+        IPC_HIP(hipEventRecord(e1, c->stream));
+        IPC_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        IPC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        double t = 1e3 * ms / reps;
+        if (us) us[i] = t;
+        if (t < best) { best = t; bestL = Ls[i]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->spmv_lanes = bestL;
 }
 
 // ---------------------------------------------------------------------------
@@ -256,18 +322,22 @@ void build_preconditioner(ipc_ctx *c)
 }
 
 // ---------------------------------------------------------------------------
-// PCG kernels
+// PCG kernels (preconditioned conjugate gradients in the single-reduction
+// form of Chronopoulos and Gear: besides p it carries s = A p, so that one
+// product w = A z and one per-scene reduction per iteration suffice)
 // ---------------------------------------------------------------------------
-// x = 0, r = b, z = M^-1 r (FEM nodes); partials of b.b and r.z
+// x = 0, r = b, p = s = 0, z = M^-1 r (FEM nodes); partials of b.b and r.z
 __global__ void k_pcg_init(int N, const int *__restrict__ kind, const double *__restrict__ b, const double *__restrict__ dinv,
-                           double *__restrict__ x, double *__restrict__ r, double *__restrict__ z, double *__restrict__ part_bb,
-                           double *__restrict__ part_rz)
+                           double *__restrict__ x, double *__restrict__ r, double *__restrict__ z, double *__restrict__ p,
+                           double *__restrict__ s, double *__restrict__ part_bb, double *__restrict__ part_rz)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     double bb = 0.0, rz = 0.0;
     if (n < N) {
         d3 bv = ld3(b, n);
         st3(x, n, {0.0, 0.0, 0.0});
+        st3(p, n, {0.0, 0.0, 0.0});
+        st3(s, n, {0.0, 0.0, 0.0});
         st3(r, n, bv);
         bb = dt(bv, bv);
         d3 zv = {0, 0, 0};
@@ -283,13 +353,11 @@ __global__ void k_pcg_init(int N, const int *__restrict__ kind, const double *__
 }
 
 // z = M^-1 r on body nodes; partial r.z per body
-__global__ void k_body_prec_apply(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ dinvB,
-                                  const int *__restrict__ active, const double *__restrict__ r, double *__restrict__ z,
-                                  double *__restrict__ part)
+__global__ void k_body_prec_apply(int NB, const int *__restrict__ node0, const double *__restrict__ dinvB, const double *__restrict__ r,
+                                  double *__restrict__ z, double *__restrict__ part)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= NB) return;
-    if (active && !active[bscene[b]]) { part[b] = 0.0; return; }
     int n0 = node0[b];
     const double *rv = r + 3 * (size_t)n0;
     const double *M = dinvB + 144 * (size_t)b;
@@ -303,81 +371,70 @@ __global__ void k_body_prec_apply(int NB, const int *__restrict__ node0, const i
     part[b] = rz;
 }
 
-// x += alpha p; r -= alpha Ap; z = M^-1 r with partials of r.z and r.r.
-// Workgroups [0, nnode_blocks) take FEM and padding nodes, one thread per
-// node; the rest take one affine body per thread (its 4 nodes and its 12x12
-// inverse block).  The last workgroup tests convergence and forms beta.
-__global__ void k_pcg_update2(int N, int nnode_blocks, int NB, const int *__restrict__ kind, const int *__restrict__ node_scene,
-                              int *__restrict__ active, double *__restrict__ scal, const double *__restrict__ dinv,
-                              const double *__restrict__ dinvB, const int *__restrict__ body_node0, const int *__restrict__ body_scene,
-                              const double *__restrict__ p, const double *__restrict__ Ap, double *__restrict__ x, double *__restrict__ r,
-                              double *__restrict__ z, double *__restrict__ part_rz, double *__restrict__ part_rr,
-                              double *__restrict__ bpart_rz, double *__restrict__ bpart_rr)
+// p = z + beta p; s = w + beta s; x += alpha p; r -= alpha s; z = M^-1 r,
+// with partials of r.z and r.r.  Workgroups [0, nnode_blocks) take FEM and
+// padding nodes, one thread per node; the rest take one affine body per
+// thread (its 4 nodes and its 12x12 inverse block).
+__global__ void k_pcg_update(int N, int nnode_blocks, int NB, const int *__restrict__ kind, const int *__restrict__ node_scene,
+                             const int *__restrict__ active, const double *__restrict__ scal, const double *__restrict__ dinv,
+                             const double *__restrict__ dinvB, const int *__restrict__ body_node0, const int *__restrict__ body_scene,
+                             const double *__restrict__ w, double *__restrict__ p, double *__restrict__ s, double *__restrict__ x,
+                             double *__restrict__ r, double *__restrict__ z, double *__restrict__ part_rz, double *__restrict__ part_rr,
+                             double *__restrict__ bpart_rz, double *__restrict__ bpart_rr)
 {
     if ((int)blockIdx.x < nnode_blocks) {
         int n = blockIdx.x * blockDim.x + threadIdx.x;
         double rz = 0.0, rr = 0.0;
-        if (n < N && kind[n] != 1) {
-            int s = node_scene[n];
-            if (active[s]) {
-                double al = scal[(size_t)s * NSLOT + S_ALPHA];
-                d3 pv = ld3(p, n), av = ld3(Ap, n), xv = ld3(x, n), rv = ld3(r, n);
+        if (n < N && kind[n] == 0) {
+            int sc = node_scene[n];
+            if (active[sc]) {
+                const double *S = scal + (size_t)sc * NSLOT;
+                double al = S[S_ALPHA], be = S[S_BETA];
+                d3 zv = ld3(z, n), pv = ld3(p, n), wv = ld3(w, n), sv = ld3(s, n), xv = ld3(x, n), rv = ld3(r, n);
+                pv = {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z};
+                sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
                 xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
-                rv = {rv.x - al * av.x, rv.y - al * av.y, rv.z - al * av.z};
-                st3(x, n, xv);
-                st3(r, n, rv);
+                rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
+                const double *M = dinv + 9 * (size_t)n;
+                zv = {M[0] * rv.x + M[1] * rv.y + M[2] * rv.z, M[3] * rv.x + M[4] * rv.y + M[5] * rv.z, M[6] * rv.x + M[7] * rv.y + M[8] * rv.z};
+                st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv); st3(z, n, zv);
                 rr = dt(rv, rv);
-                if (kind[n] == 0) {
-                    const double *M = dinv + 9 * (size_t)n;
-                    d3 zv = {M[0] * rv.x + M[1] * rv.y + M[2] * rv.z, M[3] * rv.x + M[4] * rv.y + M[5] * rv.z,
-                             M[6] * rv.x + M[7] * rv.y + M[8] * rv.z};
-                    st3(z, n, zv);
-                    rz = dt(rv, zv);
-                }
+                rz = dt(rv, zv);
             }
         }
         rz = wave_sum(rz); rr = wave_sum(rr);
         if ((threadIdx.x & (TILE - 1)) == 0 && n < N) { part_rz[n / TILE] = rz; part_rr[n / TILE] = rr; }
     } else {
         int b = (blockIdx.x - nnode_blocks) * blockDim.x + threadIdx.x;
-        if (b < NB) {
-            double rz = 0.0, rr = 0.0;
-            int s = body_scene[b];
-            if (active[s]) {
-                double al = scal[(size_t)s * NSLOT + S_ALPHA];
-                int n0 = body_node0[b];
-                double rv[12];
-                for (int i = 0; i < 12; ++i) {
-                    size_t q = 3 * (size_t)n0 + i;
-                    x[q] += al * p[q];
-                    rv[i] = r[q] - al * Ap[q];
-                    r[q] = rv[i];
-                    rr += rv[i] * rv[i];
-                }
-                const double *M = dinvB + 144 * (size_t)b;
-                for (int i = 0; i < 12; ++i) {
-                    double acc = 0.0;
-                    for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rv[j];
-                    z[3 * (size_t)n0 + i] = acc;
-                    rz += rv[i] * acc;
-                }
+        if (b >= NB) return;
+        double rz = 0.0, rr = 0.0;
+        int sc = body_scene[b];
+        if (active[sc]) {
+            const double *S = scal + (size_t)sc * NSLOT;
+            double al = S[S_ALPHA], be = S[S_BETA];
+            size_t o = 3 * (size_t)body_node0[b];
+            double rv[12];
+            for (int i = 0; i < 12; ++i) {
+                double pi = z[o + i] + be * p[o + i];
+                double si = w[o + i] + be * s[o + i];
+                p[o + i] = pi;
+                s[o + i] = si;
+                x[o + i] += al * pi;
+                rv[i] = r[o + i] - al * si;
+                r[o + i] = rv[i];
+                rr += rv[i] * rv[i];
             }
-            bpart_rz[b] = rz;
-            bpart_rr[b] = rr;
+            const double *M = dinvB + 144 * (size_t)b;
+            for (int i = 0; i < 12; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rv[j];
+                z[o + i] = acc;
+                rz += rv[i] * acc;
+            }
         }
+        bpart_rz[b] = rz;
+        bpart_rr[b] = rr;
     }
-}
-
-__global__ void k_pcg_p(int N, const int *__restrict__ node_scene, const int *__restrict__ active, const double *__restrict__ scal,
-                        const double *__restrict__ z, double *__restrict__ p)
-{
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    int s = node_scene[n];
-    if (!active[s]) return;
-    double be = scal[(size_t)s * NSLOT + S_BETA];
-    d3 zv = ld3(z, n), pv = ld3(p, n);
-    st3(p, n, {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z});
 }
 
 __global__ void k_pcg_start(int ns, double *__restrict__ scal, int *__restrict__ active, int *__restrict__ iters, double eta,
@@ -394,60 +451,72 @@ __global__ void k_pcg_start(int ns, double *__restrict__ scal, int *__restrict__
     active[s] = (want ? want[s] : 1) && S[S_BB] > 0.0 ? 1 : 0;
 }
 
+// Bytes one update pass moves: 6 node vectors read and 5 written (24 B
+// each) plus the 3x3 inverse block per FEM vertex; 12x12 blocks per body.
+static double update_bytes(const ipc_ctx *c) { return (264.0 + 72.0) * c->NFEM + (4 * 264.0 + 1152.0) * c->NB; }
+
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want)
 {
     Dev &D = c->d;
     hipStream_t st = c->stream;
     int ns = c->n_scenes;
     int *active = D.pcg_active.p;
-    int *iters = D.pcg_iters.p;
-    double *r = D.r.p, *z = D.z.p, *p = D.p.p, *Ap = D.q.p;
-    hipLaunchKernelGGL(k_pcg_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, b, D.dinv.p, x, r, z,
+    double *r = D.r.p, *z = D.z.p, *p = D.p.p, *s = D.q.p, *w = D.w.p;
+    D.part_node3.alloc(c->N / TILE + 1);
+    D.part_long.alloc(c->n_long + 1);
+    hipLaunchKernelGGL(k_pcg_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, b, D.dinv.p, x, r, z, p, s,
                        D.part_node.p, D.part_node2.p);
     if (c->NB)
-        hipLaunchKernelGGL(k_body_prec_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.body_scene.p,
-                           D.dinvB.p, nullptr, r, z, D.body_part.p);
+        hipLaunchKernelGGL(k_body_prec_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.dinvB.p, r, z,
+                           D.body_part.p);
     {
         RedArgs a{};
-        a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = S_BB;
+        a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 0;
+        a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 1;
+        a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.grp[a.nsrc++] = 1;
+        a.slot = S_BB;
+        a.slot1 = S_RZ_NEW;
         reduce(c, a);
-        RedArgs b2{};
-        b2.src[b2.nsrc++] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0);
-        b2.src[b2.nsrc++] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0);
-        b2.slot = S_RZ;
-        reduce(c, b2);
     }
-    IPC_HIP(hipMemcpyAsync(p, z, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_pcg_start, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.scal.p, active, iters, eta, D.maxpcg.p, want);
+    hipLaunchKernelGGL(k_pcg_start, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.scal.p, active, D.pcg_iters.p, eta, D.maxpcg.p,
+                       want);
+    // first product and step length
+    auto product = [&](int post) {
+        hess_apply(c, z, w, active, D.part_node3.p);
+        RedArgs a{};
+        if (post == POST_CG) {
+            a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 0;
+            a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.grp[a.nsrc++] = 0;
+            a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 2;
+            a.src[a.nsrc] = src(c->NB ? D.body_part2.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.grp[a.nsrc++] = 2;
+            a.slot = S_RZ_NEW;
+            a.slot2 = S_RR;
+        }
+        a.src[a.nsrc] = src(D.part_node3.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 1;
+        a.src[a.nsrc] = src(c->n_long ? D.part_long.p : nullptr, seg_ptr(c, R_LONG), 0, 0); a.grp[a.nsrc++] = 1;
+        a.slot1 = S_PAP;
+        reduce_post(c, a, post);
+    };
+    product(POST_CG_FIRST);
     int maxit = 0;
     for (auto &S : c->sc) maxit = std::max(maxit, S.max_pcg);
     std::vector<int> hact(ns);
-    // one PCG iteration; every kernel skips scenes whose flag is down, so extra
+    // one iteration; every kernel skips scenes whose flag is down, so extra
     // iterations after convergence change nothing
     auto iteration = [&]() {
-        hipStream_t s2 = c->stream;
-        hess_apply(c, p, Ap, active, true);
         int nnb = blocks_for(c->N), nbb = blocks_for(c->NB);
         prof_begin(c, IPC_K_PCG_UPDATE);
-        hipLaunchKernelGGL(k_pcg_update2, dim3(nnb + nbb), dim3(BLOCK), 0, s2, c->N, nnb, c->NB, D.node_kind.p, D.node_scene.p, active,
-                           D.scal.p, D.dinv.p, D.dinvB.p, D.body_node0.p, D.body_scene.p, p, Ap, x, r, z, D.part_node.p,
+        hipLaunchKernelGGL(k_pcg_update, dim3(nnb + nbb), dim3(BLOCK), 0, c->stream, c->N, nnb, c->NB, D.node_kind.p, D.node_scene.p,
+                           active, D.scal.p, D.dinv.p, D.dinvB.p, D.body_node0.p, D.body_scene.p, w, p, s, x, r, z, D.part_node.p,
                            D.part_node2.p, D.body_part.p, D.body_part2.p);
-        prof_end(c, IPC_K_PCG_UPDATE, 240.0 * c->NFEM);
-        RedArgs a{};
-        a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = -1;
-        a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = -1;
-        a.slot = S_RZ_NEW;
-        a.split = 2;   // r.z = the first two sources; r.r = the last two
-        a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = -1;
-        a.src[a.nsrc] = src(c->NB ? D.body_part2.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = -1;
-        reduce_post(c, a, POST_PCG);
-        hipLaunchKernelGGL(k_pcg_p, dim3(blocks_for(c->N)), dim3(BLOCK), 0, s2, c->N, D.node_scene.p, active, D.scal.p, z, p);
+        prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
+        product(POST_CG);
     };
     auto any_active = [&]() {
         IPC_HIP(hipMemcpyAsync(hact.data(), active, ns * sizeof(int), hipMemcpyDeviceToHost, st));
         IPC_HIP(hipStreamSynchronize(st));
         bool any = false;
-        for (int s = 0; s < ns; ++s) any |= hact[s] != 0;
+        for (int q = 0; q < ns; ++q) any |= hact[q] != 0;
         return any;
     };
     const int K = 8;   // iterations per convergence check
