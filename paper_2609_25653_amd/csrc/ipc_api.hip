@@ -287,12 +287,13 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     if (hess) {
         hipLaunchKernelGGL(k_zero, dim3(blocks_for(9 * (int64_t)c->N)), dim3(BLOCK), 0, st, 9 * (int64_t)c->N, D.diagF.p);
         if (c->NB) hipLaunchKernelGGL(k_zero, dim3(blocks_for(144 * (int64_t)c->NB)), dim3(BLOCK), 0, st, 144 * (int64_t)c->NB, D.diagB.p);
-        launch_bsr_init(c);
     }
     hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
+    // inertia writes g; the FEM gathers then write the matrix values (constant
+    // part + tets) and add the tets' gradients; every later term adds atomically
     launch_node_inertia(c, y, g, D.part_node.p);
-    launch_body(c, hess ? 2 : 1, y, g, project, D.body_part.p, D.h2s.p);
     launch_fem(c, hess ? 2 : 1, y, g, project, D.part_tet.p, D.h2s.p);
+    launch_body(c, hess ? 2 : 1, y, g, project, D.body_part.p, D.h2s.p);
     launch_spring(c, 1, y, g, D.sp_part.p, D.h2s.p);
     launch_barrier(c, hess ? 2 : 1, false, D.xw.p, g, project);
     if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p, g);

@@ -1130,14 +1130,17 @@ __global__ void k_dyn_gather(int n, const int *__restrict__ idx, const int *__re
     for (int q = 0; q < 9; ++q) val[9 * (size_t)p + q] = valc[9 * (size_t)e + q];
 }
 
-// row pointers from the sorted row keys: every row start written exactly once
+// row pointers from the sorted row keys: ptr[n] = first position with key >= n
 __global__ void k_dyn_ptr(int n, int N, const int *__restrict__ key, int *__restrict__ ptr)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > n) return;
-    int r = p < n ? key[p] : N;
-    int rp = p > 0 ? key[p - 1] : -1;
-    for (int q = rp + 1; q <= r; ++q) ptr[q] = p;
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > N) return;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (key[m] < r) lo = m + 1; else hi = m;
+    }
+    ptr[r] = lo;
 }
 
 // rows whose static plus pair-local blocks exceed LONG_ROW, in node order
@@ -1211,7 +1214,7 @@ void build_dyn_blocks(ipc_ctx *c)
                                                    end_bit, st));
         hipLaunchKernelGGL(k_dyn_gather, dim3(blocks_for(E)), dim3(BLOCK), 0, st, (int)E, D.dyn_idx2.p, D.dyn_col_coo.p,
                            D.dyn_val_coo.p, D.dyn_col.p, D.dyn_val.p);
-        hipLaunchKernelGGL(k_dyn_ptr, dim3(blocks_for(E + 1)), dim3(BLOCK), 0, st, (int)E, N, D.dyn_key2.p, D.dyn_ptr.p);
+        hipLaunchKernelGGL(k_dyn_ptr, dim3(blocks_for(N + 1)), dim3(BLOCK), 0, st, (int)E, N, D.dyn_key2.p, D.dyn_ptr.p);
     } else {
         hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(N + 1)), dim3(BLOCK), 0, st, N + 1, D.dyn_ptr.p, 0);
     }

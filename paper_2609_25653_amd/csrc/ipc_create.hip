@@ -69,7 +69,7 @@ __global__ void k_node_mass(int N, const int *__restrict__ adj_ptr, const int *_
     if (n >= N) return;
     double m = 0.0;
     for (int k = adj_ptr[n]; k < adj_ptr[n + 1]; ++k) {
-        int e = adj[k];
+        int e = adj[k] >> 2;
         m += rho[e] * vol[e] / 4.0;
     }
     mass[n] = m;
@@ -414,7 +414,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         S.L = std::sqrt(dd);
         S.thr = S.newton_tol * S.h * S.L;
     }
-    // node -> incident tets (fixed order) for the lumped mass
+    // node -> incident tets (fixed order), as codes 4 tet + local vertex, for
+    // the lumped mass and the gradient gather
     for (int e = 0; e < tet; ++e)
         if (tvalid[e]) { adj_ptr[tv[e].x + 1]++; adj_ptr[tv[e].y + 1]++; adj_ptr[tv[e].z + 1]++; adj_ptr[tv[e].w + 1]++; }
     for (int i = 0; i < node; ++i) adj_ptr[i + 1] += adj_ptr[i];
@@ -422,7 +423,10 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     {
         std::vector<int> fill(adj_ptr.begin(), adj_ptr.end() - 1);
         for (int e = 0; e < tet; ++e)
-            if (tvalid[e]) { adj[fill[tv[e].x]++] = e; adj[fill[tv[e].y]++] = e; adj[fill[tv[e].z]++] = e; adj[fill[tv[e].w]++] = e; }
+            if (tvalid[e]) {
+                adj[fill[tv[e].x]++] = 4 * e; adj[fill[tv[e].y]++] = 4 * e + 1;
+                adj[fill[tv[e].z]++] = 4 * e + 2; adj[fill[tv[e].w]++] = 4 * e + 3;
+            }
     }
     // Block-CSR pattern over all node rows: tetrahedra, the 4x4 node blocks of
     // every affine body, and the (constant) spring couplings between the nodes
@@ -475,6 +479,17 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     }
     for (int b = 0; b < body; ++b)
         for (int k = 0; k < 4; ++k) for (int m = 0; m < 4; ++m) bslot[16 * b + 4 * k + m] = find_slot(body_node0[b] + k, body_node0[b] + m);
+    // matrix slot -> tet blocks that land in it (tet order)
+    std::vector<int> sc_ptr(c->nnzb + 1, 0), sc_list;
+    for (int e = 0; e < tet; ++e)
+        if (tvalid[e]) for (int q = 0; q < 16; ++q) sc_ptr[tslot[16 * (size_t)e + q] + 1]++;
+    for (int i = 0; i < c->nnzb; ++i) sc_ptr[i + 1] += sc_ptr[i];
+    sc_list.resize(sc_ptr[c->nnzb]);
+    {
+        std::vector<int> fill(sc_ptr.begin(), sc_ptr.end() - 1);
+        for (int e = 0; e < tet; ++e)
+            if (tvalid[e]) for (int q = 0; q < 16; ++q) sc_list[fill[tslot[16 * (size_t)e + q]]++] = 16 * e + q;
+    }
     // segment tables (per-scene ranges) used by the segmented reductions
     c->seg_surf.resize(n + 1); c->seg_tri.resize(n + 1); c->seg_edge.resize(n + 1); c->seg_sp.resize(n + 1); c->seg_body.resize(n + 1);
     for (int s = 0; s < n; ++s) {
@@ -492,7 +507,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node); D.diagF.alloc(9 * (size_t)node);
     D.tv.upload(tv, st);
     D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);
-    D.tslot.upload(tslot, st);
+    D.sc_ptr.upload(sc_ptr, st); D.sc_list.upload(sc_list, st);
+    D.tgrad.alloc(12 * (size_t)std::max(tet, 1)); D.telem.alloc(144 * (size_t)std::max(tet, 1));
     D.row_ptr.upload(row_ptr, st); D.col.upload(col, st); D.diag_slot.upload(diag_slot, st);
     D.val.alloc(9 * (size_t)std::max(c->nnzb, 1));
     D.val_const.alloc(9 * (size_t)std::max(c->nnzb, 1)); D.val_const.zero(st, 9 * (size_t)std::max(c->nnzb, 1));
@@ -519,15 +535,15 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     // ---- device precompute
     {
         DBuf<double> drho;
-        DBuf<int> dvalid, dadjp, dadj;
+        DBuf<int> dvalid;
         D.tE.upload(tE, st); D.tnu.upload(tnu, st); drho.upload(trho, st); dvalid.upload(tvalid, st);
         c->ext_tets = (int64_t)ext2tet.size();
         D.ext2tet.upload(ext2tet, st);
-        dadjp.upload(adj_ptr, st); dadj.upload(adj, st);
+        D.fadj_ptr.upload(adj_ptr, st); D.fadj.upload(adj, st);
         if (tet > 0)
             hipLaunchKernelGGL(k_tet_precompute, dim3(blocks_for(tet)), dim3(BLOCK), 0, st, tet, D.tv.p, D.y.p, D.tE.p, D.tnu.p,
                                D.Bm.p, D.vol.p, D.tmu.p, D.tlam.p, dvalid.p);
-        hipLaunchKernelGGL(k_node_mass, dim3(blocks_for(node)), dim3(BLOCK), 0, st, node, dadjp.p, dadj.p, D.vol.p, drho.p, D.mass.p);
+        hipLaunchKernelGGL(k_node_mass, dim3(blocks_for(node)), dim3(BLOCK), 0, st, node, D.fadj_ptr.p, D.fadj.p, D.vol.p, drho.p, D.mass.p);
         std::vector<double> h2s(n);
         for (int s = 0; s < n; ++s) h2s[s] = c->sc[s].h * c->sc[s].h;
         DBuf<double> dh2; dh2.upload(h2s, st);

@@ -3,9 +3,10 @@
 //
 // One thread per tetrahedron / body / spring.  The FEM kernel forms the 9x9
 // Hessian of the energy density in F, projects it to PSD in registers, maps it
-// to the 16 3x3 blocks of the element and adds them into the block-CSR matrix
-// through precomputed slots; gradients go out through FP64 atomics.  Energies
-// are reduced per wavefront (scene-aligned tiles) for a deterministic sum.
+// to the 16 3x3 blocks of the element and writes them, with its 12 gradient
+// entries, to per-tet arrays; two gather kernels then sum them per matrix slot
+// and per node in a fixed order (no atomics, deterministic).  Energies are
+// reduced per wavefront (scene-aligned tiles) for a deterministic sum.
 #include "ipc_device.h"
 #include "ipc_internal.h"
 #include "ipc_kernels.h"
@@ -42,8 +43,8 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                                              const double *__restrict__ vol, const double *__restrict__ tmu,
                                              const double *__restrict__ tlam, const double *__restrict__ y,
                                              const int *__restrict__ tile_scene, const double *__restrict__ h2s,
-                                             double *__restrict__ g, double *__restrict__ val, const int *__restrict__ tslot,
-                                             int project, double *__restrict__ part)
+                                             double *__restrict__ tgrad, double *__restrict__ telem, int project,
+                                             double *__restrict__ part)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     double energy = 0.0;
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                 d3 ga = {w * (c[a][0] * P[0].x + c[a][1] * P[1].x + c[a][2] * P[2].x),
                          w * (c[a][0] * P[0].y + c[a][1] * P[1].y + c[a][2] * P[2].y),
                          w * (c[a][0] * P[0].z + c[a][1] * P[1].z + c[a][2] * P[2].z)};
-                atomic_add3(g, vi[a], ga);
+                st3(tgrad, a * T + e, ga);
             }
         }
         if (MODE == 2) {
@@ -107,7 +108,6 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                             H[pk9(R, C)] = v;
                         }
             if (project) psd_project9(H);
-            const int *sl = tslot + 16 * (size_t)e;
 #pragma unroll
             for (int B = 0; B < 4; ++B) {
                 double Tm[9][3];   // Tm[(j,r)][q] = sum_l c[B][l] H[(j,r),(l,q)]
@@ -118,12 +118,12 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                         Tm[R][q] = c[B][0] * H[pk9(R, q)] + c[B][1] * H[pk9(R, 3 + q)] + c[B][2] * H[pk9(R, 6 + q)];
 #pragma unroll
                 for (int A = 0; A < 4; ++A) {
-                    double *blk = val + 9 * (size_t)sl[4 * A + B];
+                    double *blk = telem + 9 * ((size_t)(4 * A + B) * T + e);
 #pragma unroll
                     for (int r = 0; r < 3; ++r)
 #pragma unroll
                         for (int q = 0; q < 3; ++q)
-                            atomicAdd(blk + 3 * r + q, w * (c[A][0] * Tm[r][q] + c[A][1] * Tm[3 + r][q] + c[A][2] * Tm[6 + r][q]));
+                            blk[3 * r + q] = w * (c[A][0] * Tm[r][q] + c[A][1] * Tm[3 + r][q] + c[A][2] * Tm[6 + r][q]);
                 }
             }
         }
@@ -132,11 +132,37 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
     if (part && (threadIdx.x & (TILE - 1)) == 0 && e < T) part[e / TILE] = energy;
 }
 
-// block-CSR init: the constant part (lumped mass, springs)
-__global__ void k_bsr_init(int64_t n, const double *__restrict__ vc, double *__restrict__ val)
+// matrix values: the constant part (lumped mass, springs) plus the tet blocks
+// of each slot, summed in tet order; one thread per (slot, entry)
+__global__ void k_bsr_assemble(int64_t n9, int T, const int *__restrict__ sc_ptr, const int *__restrict__ sc_list,
+                               const double *__restrict__ telem, const double *__restrict__ vc, double *__restrict__ val)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) val[i] = vc[i];
+    if (i >= n9) return;
+    int k = (int)(i / 9), q = (int)(i % 9);
+    double acc = vc[i];
+    for (int j = sc_ptr[k]; j < sc_ptr[k + 1]; ++j) {
+        int code = sc_list[j];
+        acc += telem[9 * ((size_t)(code & 15) * T + (code >> 4)) + q];
+    }
+    val[i] = acc;
+}
+
+// node gradients of the tets: g[n] += sum over incident (tet, vertex), in order
+__global__ void k_fem_grad_gather(int N, int T, const int *__restrict__ adj_ptr, const int *__restrict__ adj,
+                                  const double *__restrict__ tgrad, double *__restrict__ g)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    int k0 = adj_ptr[n], k1 = adj_ptr[n + 1];
+    if (k0 == k1) return;
+    d3 acc = ld3(g, n);
+    for (int k = k0; k < k1; ++k) {
+        int code = adj[k];
+        d3 v = ld3(tgrad, (code & 3) * T + (code >> 2));
+        acc.x += v.x; acc.y += v.y; acc.z += v.z;
+    }
+    st3(g, n, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,24 +324,33 @@ void launch_node_inertia(ipc_ctx *c, const double *y, double *g, double *part)
 
 void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)
 {
-    if (c->T == 0) return;
     Dev &D = c->d;
+    int64_t n9 = 9 * (int64_t)c->nnzb;
+    if (c->T == 0) {
+        if (mode == 2) hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, 1, D.sc_ptr.p,
+                                          D.sc_list.p, D.telem.p, D.val_const.p, D.val.p);
+        return;
+    }
     auto args = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(c->T)), dim3(BLOCK), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p, D.tmu.p,
-                           D.tlam.p, y, D.tile_scene_tet.p, h2s, g, D.val.p, D.tslot.p, (int)project, part);
+                           D.tlam.p, y, D.tile_scene_tet.p, h2s, D.tgrad.p, D.telem.p, (int)project, part);
     };
     int k = mode == 2 ? IPC_K_FEM_HESS : (mode == 0 ? IPC_K_FEM_ENERGY : -1);
     if (k >= 0) prof_begin(c, k);
     if (mode == 0) args(k_fem<0>);
     else if (mode == 1) args(k_fem<1>);
     else args(k_fem<2>);
-    if (k >= 0) prof_end(c, k, mode == 2 ? 112.0 * c->TREAL + 48.0 * c->NFEM + 72.0 * c->nnzb : 112.0 * c->TREAL + 24.0 * c->NFEM);
-}
-
-void launch_bsr_init(ipc_ctx *c)
-{
-    int64_t n = 9 * (int64_t)c->nnzb;
-    hipLaunchKernelGGL(k_bsr_init, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n, c->d.val_const.p, c->d.val.p);
+    if (mode >= 1)
+        hipLaunchKernelGGL(k_fem_grad_gather, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, c->T, D.fadj_ptr.p, D.fadj.p,
+                           D.tgrad.p, g);
+    if (mode == 2)
+        hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, c->T, D.sc_ptr.p, D.sc_list.p,
+                           D.telem.p, D.val_const.p, D.val.p);
+    // algorithmic bytes: tet data in (112), per-tet gradient and blocks out and
+    // back in (96 and 1152, twice), node gradient in and out (48), matrix out
+    // and its constant part in (2 x 72 per block)
+    if (k >= 0)
+        prof_end(c, k, mode == 2 ? (112.0 + 2 * 1248.0) * c->TREAL + 48.0 * c->NFEM + 144.0 * c->nnzb : 112.0 * c->TREAL + 24.0 * c->NFEM);
 }
 
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)

@@ -159,7 +159,12 @@ struct Dev {
     DBuf<double> vol, tmu, tlam;
     DBuf<double> tE, tnu;                  // Young's modulus and Poisson ratio per tet
     DBuf<int> ext2tet;                     // external tet (scenes concatenated) -> internal tet
-    DBuf<int> tslot;                       // 16 BSR slots per tet (row-major a*4+b)
+    // FEM assembly by gathering: each tet writes its gradient ([a][tet][3]) and
+    // its 16 3x3 blocks ([a*4+b][tet][9]); nodes and matrix slots then sum
+    // their contributions in a fixed order
+    DBuf<double> tgrad, telem;
+    DBuf<int> fadj_ptr, fadj;              // node -> incident (tet, local vertex) codes 4 tet + a
+    DBuf<int> sc_ptr, sc_list;             // matrix slot -> contributing codes 16 tet + 4 a + b
     // FEM matrix (block CSR, 3x3 blocks, rows = nodes)
     DBuf<int> row_ptr, col, diag_slot;
     DBuf<double> val, val_const;           // assembled values; constant part (mass, springs)

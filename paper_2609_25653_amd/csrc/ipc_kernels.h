@@ -20,7 +20,6 @@ __device__ __forceinline__ double wave_max(double v)
 // elastic terms (ipc_elastic.hip)
 void launch_node_inertia(ipc_ctx *c, const double *y, double *g, double *part);
 void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s);
-void launch_bsr_init(ipc_ctx *c);
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s);
 void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *part, const double *h2s);
 

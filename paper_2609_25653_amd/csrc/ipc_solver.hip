@@ -26,20 +26,25 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
     int s = blockIdx.x;
     __shared__ double sh[8][BLOCK / TILE];
     int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
+    // all loads first (independent, in flight together), then the shuffles
+    double part[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        part[k] = 0.0;
+        if (k >= a.nsrc) continue;
+        const RedSrc &r = a.src[k];
+        if (!r.v) continue;
+        int lo = r.seg[s] - r.base, hi = r.seg[s + 1] - r.base;
+        for (int i = lo + (int)threadIdx.x; i < hi; i += BLOCK) {
+            double v = r.v[r.off + i];
+            part[k] = a.op ? fmax(part[k], v) : part[k] + v;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if (k >= a.nsrc) break;
-        const RedSrc &r = a.src[k];
-        double part = 0.0;
-        if (r.v) {
-            int lo = r.seg[s] - r.base, hi = r.seg[s + 1] - r.base;
-            for (int i = lo + (int)threadIdx.x; i < hi; i += BLOCK) {
-                double v = r.v[r.off + i];
-                part = a.op ? fmax(part, v) : part + v;
-            }
-        }
-        part = a.op ? wave_max(part) : wave_sum(part);
-        if (lane == 0) sh[k][wave] = part;
+        double v = a.op ? wave_max(part[k]) : wave_sum(part[k]);
+        if (lane == 0) sh[k][wave] = v;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -512,45 +517,72 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
         product(POST_CG);
     };
-    auto any_active = [&]() {
+    // Host view after a batch: the active flags and, per active scene, an
+    // estimate of the iterations left from the residual's geometric decay
+    // since the previous check (capped; unknown on the first check).
+    std::vector<double> hs((size_t)ns * NSLOT), prev_rr(ns, -1.0);
+    auto check = [&](int done_since) {
         IPC_HIP(hipMemcpyAsync(hact.data(), active, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipMemcpyAsync(hs.data(), D.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         IPC_HIP(hipStreamSynchronize(st));
+        int left = 0;
         bool any = false;
-        for (int q = 0; q < ns; ++q) any |= hact[q] != 0;
-        return any;
+        for (int q = 0; q < ns; ++q) {
+            if (!hact[q]) continue;
+            any = true;
+            double rr = hs[(size_t)q * NSLOT + S_RR], e2 = hs[(size_t)q * NSLOT + S_ETA2];
+            int est = 1 << 20;
+            if (prev_rr[q] > 0.0 && rr > 0.0 && rr < prev_rr[q] && done_since > 0) {
+                double rate = std::log(prev_rr[q] / rr) / done_since;
+                est = (int)std::ceil(std::log(rr / e2) / rate);
+            }
+            prev_rr[q] = rr;
+            left = std::max(left, est);
+        }
+        return any ? std::max(left, 1) : 0;
     };
-    const int K = 8;   // iterations per convergence check
+    const int KB = 16, KS = 4;   // iterations per batch: far from and near convergence
     if (c->use_graphs && !c->prof) {
-        // Capture K iterations once per solve on the context's capture stream
-        // (the caller's stream may be the null stream, which cannot capture)
-        // and replay the graph on the context's stream.
+        // Capture a long and a short batch of iterations once per solve on the
+        // context's capture stream (the caller's stream may be the null
+        // stream, which cannot capture) and replay them on the context's
+        // stream, the short one once few iterations are predicted to remain.
         IPC_HIP(hipStreamSynchronize(st));
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        c->stream = c->cap_stream;
-        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            for (int k = 0; k < K; ++k) iteration();
-            e = hipStreamEndCapture(c->cap_stream, &graph);
+        hipGraphExec_t exec[2] = {nullptr, nullptr};
+        const int Ks[2] = {KB, KS};
+        hipError_t e = hipSuccess;
+        for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+            hipGraph_t graph = nullptr;
+            c->stream = c->cap_stream;
+            e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (int k = 0; k < Ks[g]; ++k) iteration();
+                e = hipStreamEndCapture(c->cap_stream, &graph);
+            }
+            c->stream = st;
+            if (e == hipSuccess) {
+                e = hipGraphInstantiate(&exec[g], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+            }
         }
-        c->stream = st;
-        IPC_HIP(e);
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        IPC_HIP(e);
-        hipError_t le = hipSuccess;
-        for (int it = 0; it < maxit; it += K) {
-            le = hipGraphLaunch(exec, st);
+        hipError_t le = e;
+        int it = 0, left = 1 << 20;
+        while (le == hipSuccess && it < maxit && left > 0) {
+            int g = left > KB ? 0 : 1;
+            le = hipGraphLaunch(exec[g], st);
             if (le != hipSuccess) break;
-            if (!any_active()) break;
+            it += Ks[g];
+            left = check(Ks[g]);
         }
-        (void)hipGraphExecDestroy(exec);
+        for (auto &x : exec) if (x) (void)hipGraphExecDestroy(x);
         IPC_HIP(le);
         return;
     }
-    for (int it = 0; it < maxit; ++it) {
+    for (int it = 0, since = 0; it < maxit; ++it) {
         iteration();
-        if (((it + 1) % K == 0 || it + 1 == maxit) && !any_active()) break;
+        ++since;
+        if ((since == KS || it + 1 == maxit) && !check(since)) break;
+        if (since == KS) since = 0;
     }
 }
 
