@@ -387,7 +387,7 @@ def gripper_squeeze(seed=0, n_steps=200, pad_cells=(20, 10, 10), pad_E=2e5, mu=0
     return b.finish(p, drive)
 
 
-def contact_rich(seed=0, n_steps=100, s_g=1e-3, n_disk=30, n_layers=40):
+def contact_rich(seed=0, n_steps=100, s_g=8e-4, n_disk=30, n_layers=40):
     """Two pads squeezing a ~180k-tet soft cylinder that rests on a finely meshed ground patch."""
     rng = np.random.Generator(np.random.PCG64(seed))
     b = _Builder()
@@ -438,6 +438,8 @@ def tiny_scene(kind="tet", seed=0, **kw):
     tet      one tetrahedron, free (no contact geometry besides its own surface)
     two_tets two tetrahedra sharing a face
     cube     a 2x2x2-cell block resting above the 2-triangle ground
+    edge_tet one tetrahedron on an edge nearly parallel to the ground's diagonal
+             edge (an active edge-edge mollifier)
     pad_box  a 2x1x1-cell pad squeezing a small affine box (springs, bodies, contact)
     """
     rng = np.random.Generator(np.random.PCG64(seed))
