@@ -79,6 +79,116 @@ def probe_spmv(sim):
                       "spmv_launches": 20, "spmv_avg_us": us.value, "spmv_algorithmic_bytes": by.value}))
 
 
+def bench_batched(args):
+    """256 squeeze scenes of 1k-40k tets stepped together, against the same
+    scenes stepped one at a time (a stratified sample, scaled to all)."""
+    import numpy as np
+    import torch
+    import ipcscenes
+    from paper_2609_25653_amd import Sim
+    n_total = args.warmup + args.steps
+    scenes = ipcscenes.batched_squeeze(n_scenes=args.scenes, n_steps=n_total)
+    tets = np.array([len(s["tets"]) for s in scenes])
+    t0 = time.perf_counter()
+    sim = Sim(scenes)
+    t_create = time.perf_counter() - t0
+    print(f"# batched: {len(scenes)} scenes, {tets.sum()} tets, created in {t_create:.1f} s", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        sim.step(allow_status=(3,))
+    lanes, _ = sim.autotune(10)
+    torch.cuda.synchronize()
+    newton = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, st = sim.step(allow_status=(3,))
+        newton.append(max(s["newton_iters"] for s in st))
+        print(f"# step {sim.step_index}: rc={rc} max newton={newton[-1]} "
+              f"pairs={sum(s['n_pt_max'] + s['n_ee_max'] for s in st)}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # one at a time: a sample spread over the size range, same steps
+    order = np.argsort(tets)
+    pick = order[np.linspace(0, len(scenes) - 1, min(args.single_sample, len(scenes))).round().astype(int)]
+    t_single = 0.0
+    for i in pick:
+        s1 = Sim(scenes[i])
+        for _ in range(args.warmup):
+            s1.step(allow_status=(3,))
+        s1.autotune(5)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            s1.step(allow_status=(3,))
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - a
+        del s1
+    t_single_all = t_single * len(scenes) / len(pick)
+    line = {
+        "metric": "batched scene-steps/s", "value": len(scenes) * args.steps / t, "unit": "scene-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{len(scenes)} uneven squeeze scenes stepped together", "tets": int(tets.sum()),
+                   "tets_min": int(tets.min()), "tets_max": int(tets.max()), "parallelism": "single GPU"},
+        "one_at_a_time": {"value": len(scenes) * args.steps / t_single_all, "unit": "scene-steps/s",
+                          "sample": f"{len(pick)} scenes spread over the size range, scaled by {len(scenes)}/{len(pick)}"},
+        "speedup_vs_one_at_a_time": t_single_all / t,
+        "max_newton_per_step": newton, "spmv_lanes_per_row": lanes,
+    }
+    print(json.dumps(line))
+
+
+def bench_adjoint(args):
+    """Squeeze steps 40-89 with theta = (E per pad tet, mu): forward rollout
+    with checkpoints every 10 steps, then the backward pass (recompute + one
+    adjoint solve per step); loss = squared distance of the 64 tracked pad
+    vertices to targets from a run with perturbed theta, summed over steps."""
+    import numpy as np
+    import torch
+    import ipcscenes
+    from paper_2609_25653_amd import Sim
+    from paper_2609_25653_amd.rollout import rollout
+    sc, info = ipcscenes.adjoint_squeeze(0)
+    first, K, every = info["first_step"], info["n_steps"], info["checkpoint_every"]
+    sim = Sim(sc)
+    for k in range(first):
+        sim.step(k, allow_status=(3,))
+    lanes, _ = sim.autotune(10)
+    y0, v0 = sim.state()
+    y0, v0 = y0.clone(), v0.clone()
+    tr = torch.as_tensor(info["tracked"], device="cuda").long()
+    idx = (3 * tr[:, None] + torch.arange(3, device="cuda")[None, :]).reshape(-1)
+    E0 = torch.as_tensor(sc["tet_E"], device="cuda")
+    mu0 = float(sc["mu"])
+    # targets: the tracked vertices over the same window with perturbed parameters
+    with torch.no_grad():
+        Et = E0 * torch.as_tensor(info["target_E_scale"], device="cuda")
+        _, _, targets = rollout(sim, Et, mu0 * info["target_mu_scale"], y0, v0, first, K, every, observe=idx)
+    E = E0.clone().requires_grad_(True)
+    mu = torch.tensor([mu0], dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, Y = rollout(sim, E, mu, y0, v0, first, K, every, observe=idx)
+    loss = ((Y - targets) ** 2).sum()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    line = {
+        "metric": "adjoint/forward time", "value": t_bwd / t_fwd, "unit": "ratio", "n_gpus": 1, "steps": K, "warmup": first,
+        "ms_per_step": 1e3 * t_fwd / K, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "squeeze steps 40-89, theta = per-tet E (20k) and mu, 64 tracked vertices",
+                   "tets": int(len(sc["tets"])), "parallelism": "single GPU"},
+        "forward_s": t_fwd, "backward_s": t_bwd, "backward_ms_per_step": 1e3 * t_bwd / K,
+        "note": "backward = recompute of each 10-step segment from its checkpoint + one adjoint solve per step",
+        "loss": float(loss.detach()), "dL_dE_norm": float(E.grad.norm()), "dL_dmu": float(mu.grad[0]),
+        "spmv_lanes_per_row": lanes,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,13 +196,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=8e-4, help="ground patch spacing (m): 0.8 mm keeps the median active pairs inside 50k-300k")
+    ap.add_argument("--workload", choices=["contact", "batched", "adjoint"], default="contact",
+                    help="contact: the 200k-tet squeeze (default line); batched: 256 uneven squeeze scenes stepped "
+                         "together vs one at a time; adjoint: 50-step squeeze rollout, forward vs backward time")
+    ap.add_argument("--scenes", type=int, default=256, help="batched: number of scenes")
+    ap.add_argument("--single-sample", type=int, default=16, help="batched: scenes stepped one at a time for the baseline")
     ap.add_argument("--probe", choices=["spmv"], default=None,
                     help="spmv: assemble the Hessian of the 200k-tet scene once, then run a plain 256 MiB device copy "
                          "and 20 back-to-back block-CSR products (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (scenes would shard without "
-              f"communication, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -100,6 +214,10 @@ def main():
     import ipcscenes
     from paper_2609_25653_amd import Sim, lib
 
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     n_total = args.warmup + args.steps
     scene = ipcscenes.contact_rich(n_steps=n_total, s_g=args.s_g)
     sim = Sim(scene)

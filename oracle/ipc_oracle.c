@@ -548,7 +548,7 @@ static int ee_type(const double *a0, const double *a1, const double *b0, const d
     sub3(a1, a0, u); sub3(b1, b0, v); sub3(a0, b0, w);
     double A = dot3(u, u), B = dot3(u, v), C = dot3(v, v), D = dot3(u, w), E = dot3(v, w);
     double den = A * C - B * B;
-    if (den > 1e-20 * A * C) {
+    if (den > 1e-10 * A * C) {
         double sN = B * E - C * D, tN = A * E - B * D;
         if (sN > 0.0 && sN < den && tN > 0.0 && tN < den) return 8;
     }

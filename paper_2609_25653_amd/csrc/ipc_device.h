@@ -139,7 +139,7 @@ __device__ __forceinline__ int ee_type(d3 a0, d3 a1, d3 b0, d3 b1)
     d3 u = xsub(a1, a0), v = xsub(b1, b0), w = xsub(a0, b0);
     double A = xdot(u, u), B = xdot(u, v), C = xdot(v, v), D = xdot(u, w), E = xdot(v, w);
     double den = A * C - B * B;
-    if (den > 1e-20 * A * C) {
+    if (den > 1e-10 * A * C) {
         double sN = B * E - C * D, tN = A * E - B * D;
         if (sN > 0.0 && sN < den && tN > 0.0 && tN < den) return 8;
     }

@@ -1,50 +1,57 @@
 """Differentiable rollouts: ``IPCRollout``, a torch.autograd.Function over K steps.
 
 Forward runs the library's steps from (y0, ydot0) with parameters (E per tet,
-mu per scene) and keeps (y, ydot) every ``checkpoint_every`` steps.  Backward
-walks the checkpoint segments in reverse: it recomputes a segment's states
-from its checkpoint, then calls the library's one-step adjoint for each step
-of the segment, newest first, accumulating dL/dE and dL/dmu and carrying the
-state adjoints (ybar, vbar) back to the segment start.  Memory: one (y, ydot)
-pair per checkpoint plus the states of one segment.
+mu per scene) and keeps (y, ydot) every ``checkpoint_every`` steps, plus the
+observed DOFs of every step when ``observe`` is given (e.g. the tracked
+vertices of a loss summed over the trajectory).  Backward walks the
+checkpoint segments in reverse: it recomputes a segment's states from its
+checkpoint, then calls the library's one-step adjoint for each step of the
+segment, newest first, adding the observed DOFs' upstream gradients as it
+passes their step, accumulating dL/dE and dL/dmu and carrying the state
+adjoints (ybar, vbar) back to the start.  Memory: one (y, ydot) pair per
+checkpoint, the states of one segment and the observed trajectory.
 """
 import torch
 
-from . import IPCError, Sim  # noqa: F401
-
 
 class IPCRollout(torch.autograd.Function):
-    """(E, mu, y0, ydot0) -> (y_K, ydot_K) over steps first_step .. first_step+K-1.
+    """(E, mu, y0, ydot0) -> (y_K, ydot_K, Y_obs) over steps first_step .. first_step+K-1.
 
     ``sim`` is a ``Sim`` over the scene(s); E has one entry per tet of all
-    scenes, mu one per scene.  The Newton and adjoint solves use the scenes'
+    scenes, mu one per scene.  ``observe`` (a long tensor of DOF indices, or
+    None) selects the DOFs recorded after every step: Y_obs[k] = y_{k+1}[observe]
+    (an empty tensor when None).  The Newton and adjoint solves use the scenes'
     own tolerances; ``eta`` is the adjoint PCG's relative residual."""
 
     @staticmethod
-    def forward(ctx, E, mu, y0, ydot0, sim, first_step, n_steps, checkpoint_every=10, eta=1e-12):
+    def forward(ctx, E, mu, y0, ydot0, sim, first_step, n_steps, checkpoint_every, eta, observe):
         E = E.detach().contiguous()
         mu = mu.detach().contiguous()
         sim.set_params(E, mu.cpu().numpy())
         y, v = y0.detach().contiguous().clone(), ydot0.detach().contiguous().clone()
         sim.set_state(y, v)
-        ckpts = []
+        ckpts, obs = [], []
         for k in range(n_steps):
             if k % checkpoint_every == 0:
                 ckpts.append((k, y, v))
             sim.step(first_step + k)
             y, v = sim.state()
-        ctx.sim, ctx.first, ctx.n, ctx.every, ctx.eta = sim, first_step, n_steps, checkpoint_every, eta
+            if observe is not None:
+                obs.append(y[observe])
+        ctx.sim, ctx.first, ctx.n, ctx.every, ctx.eta, ctx.observe = sim, first_step, n_steps, checkpoint_every, eta, observe
         ctx.ckpts = ckpts
         ctx.save_for_backward(E, mu)
-        return y, v
+        Y = torch.stack(obs) if obs else torch.zeros(0, dtype=torch.float64, device=y.device)
+        return y, v, Y
 
     @staticmethod
-    def backward(ctx, ybar, vbar):
+    def backward(ctx, ybar, vbar, gobs):
         sim = ctx.sim
         E, mu = ctx.saved_tensors
         sim.set_params(E, mu.cpu().numpy())
-        ybar = torch.zeros(sim.ndof, dtype=torch.float64, device=sim.device) if ybar is None else ybar.contiguous().clone()
-        vbar = torch.zeros(sim.ndof, dtype=torch.float64, device=sim.device) if vbar is None else vbar.contiguous().clone()
+        zeros = lambda: torch.zeros(sim.ndof, dtype=torch.float64, device=sim.device)
+        ybar = zeros() if ybar is None else ybar.contiguous().clone()
+        vbar = zeros() if vbar is None else vbar.contiguous().clone()
         Ebar = torch.zeros(sim.n_tets, dtype=torch.float64, device=sim.device)
         mubar = torch.zeros(sim.n_scenes, dtype=torch.float64, device=sim.device)
         for c0, y, v in reversed(ctx.ckpts):
@@ -55,16 +62,22 @@ class IPCRollout(torch.autograd.Function):
                 sim.step(ctx.first + k)
                 states.append(sim.state())
             for k in range(c1 - 1, c0 - 1, -1):
+                if ctx.observe is not None and gobs is not None and gobs.numel():
+                    ybar = ybar.index_add(0, ctx.observe, gobs[k])
                 yp, vp = states[k - c0]
                 yn = states[k - c0 + 1][0]
                 ybar, vbar, _ = sim.step_vjp(yp, vp, ctx.first + k, yn, ybar, vbar, Ebar, mubar, ctx.eta)
         # the context's state is left at the start of the rollout
-        return Ebar, mubar.to(mu.dtype).reshape(mu.shape), ybar, vbar, None, None, None, None, None
+        return Ebar, mubar.to(mu.dtype).reshape(mu.shape), ybar, vbar, None, None, None, None, None, None
 
 
-def rollout(sim, E, mu, y0, ydot0, first_step, n_steps, checkpoint_every=10, eta=1e-12):
-    """Differentiable (y_K, ydot_K) of a K-step rollout; see ``IPCRollout``."""
+def rollout(sim, E, mu, y0, ydot0, first_step, n_steps, checkpoint_every=10, eta=1e-12, observe=None):
+    """Differentiable rollout; returns (y_K, ydot_K), or (y_K, ydot_K, Y_obs)
+    with Y_obs[k] = y_{k+1}[observe] when ``observe`` is given.  See ``IPCRollout``."""
     mu = torch.as_tensor(mu, dtype=torch.float64, device=sim.device).reshape(-1)
     if mu.numel() == 1 and sim.n_scenes > 1:
         mu = mu.expand(sim.n_scenes).contiguous()
-    return IPCRollout.apply(E, mu, y0, ydot0, sim, first_step, n_steps, checkpoint_every, eta)
+    if observe is not None:
+        observe = torch.as_tensor(observe, device=sim.device).long()
+    y, v, Y = IPCRollout.apply(E, mu, y0, ydot0, sim, first_step, n_steps, checkpoint_every, eta, observe)
+    return (y, v) if observe is None else (y, v, Y)

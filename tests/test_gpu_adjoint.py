@@ -163,3 +163,36 @@ def test_rollout_gradient_matches_oracle_and_fd():
     h = 1e-3
     fd = (loss_of(E0, mu0 * (1 + h), False) - loss_of(E0, mu0 * (1 - h), False)) / (2 * h * mu0)
     assert abs(fd - mb) <= 3e-5 * abs(mb), (fd, mb)
+
+
+def test_observed_trajectory_loss_matches_chained_steps():
+    """A loss over every step's tracked vertices through one checkpointed
+    rollout (observe=...) equals the same loss through one rollout per step."""
+    from paper_2609_25653_amd import Sim
+    from paper_2609_25653_amd.rollout import rollout
+    sc, first, y0, v0, tracked, target = _rollout_setup()
+    nst = 4
+    sim = Sim(sc)
+    idx = torch.as_tensor((3 * tracked[:, None] + np.arange(3)[None, :]).ravel(), device="cuda")
+    tgt = torch.as_tensor(target.ravel(), dtype=torch.float64, device="cuda")
+    y0t = torch.as_tensor(y0, device="cuda")
+    v0t = torch.as_tensor(v0, device="cuda")
+    E0 = torch.as_tensor(sc["tet_E"], dtype=torch.float64, device="cuda")
+    out = []
+    for chained in (False, True):
+        E = E0.clone().requires_grad_(True)
+        mu = torch.tensor([float(sc["mu"])], dtype=torch.float64, device="cuda", requires_grad=True)
+        if chained:
+            y, v, L = y0t, v0t, 0.0
+            for k in range(nst):
+                y, v = rollout(sim, E, mu, y, v, first + k, 1)
+                L = L + ((y[idx] - tgt) ** 2).sum()
+        else:
+            _, _, Y = rollout(sim, E, mu, y0t, v0t, first, nst, checkpoint_every=3, observe=idx)
+            L = ((Y - tgt) ** 2).sum()
+        L.backward()
+        out.append((float(L.detach()), to_np(E.grad), float(mu.grad[0])))
+    (La, Ea, ma), (Lb, Eb, mb) = out
+    assert abs(La - Lb) <= 1e-12 * abs(Lb)
+    _close(Ea, Eb, 1e-8)
+    assert abs(ma - mb) <= 1e-8 * abs(mb)

@@ -178,6 +178,47 @@ def test_distance_special_cases():
     assert d2 == pytest.approx(0.25, rel=1e-14)
 
 
+def test_distance_parallel_coplanar_edges_with_rounding():
+    """Parallel face diagonals on one face of a generated pad: their
+    coordinates are not exact in binary, so A C - B^2 is a rounding residue;
+    the edges must still be treated as parallel (distance from the
+    point-segment cases), not as crossing lines at distance 0."""
+    import ipcscenes
+    def seg_d2(p, a, b):
+        t = np.clip(np.dot(p - a, b - a) / np.dot(b - a, b - a), 0.0, 1.0)
+        q = a + t * (b - a)
+        return float(np.dot(p - q, p - q))
+    X = ipcscenes.scenes.grid_vertices(10, 5, 5, (0.28, 0.258, 0.0105), (0.004, 0.004, 0.004))
+    vid = lambda i, j, k: (i * 6 + j) * 6 + k
+    n_checked = 0
+    for j in range(4):
+        for k in range(4):
+            # diagonal (j,k+1)-(j+1,k) and its neighbour shifted by one cell in y and z
+            a0, a1 = X[vid(0, j, k + 1)], X[vid(0, j + 1, k)]
+            for dj, dk in ((1, 1), (1, 0), (0, 1)):
+                if j + 1 + dj > 5 or k + 1 + dk > 5:
+                    continue
+                b0, b1 = X[vid(0, j + dj, k + 1 + dk)], X[vid(0, j + 1 + dj, k + dk)]
+                if any(np.array_equal(p, q) for p in (a0, a1) for q in (b0, b1)):
+                    continue
+                d2, t = O.dist2_ee(np.concatenate([a0, a1, b0, b1]))
+                ref = min(seg_d2(a0, b0, b1), seg_d2(a1, b0, b1), seg_d2(b0, a0, a1), seg_d2(b1, a0, a1))
+                assert t != 8 and d2 == pytest.approx(ref, rel=1e-12), (j, k, dj, dk, d2, ref, t)
+                n_checked += 1
+    assert n_checked > 20
+
+
+def test_generated_squeeze_scenes_start_separated():
+    """Regression: the batched squeeze generator's scenes start with every
+    contact pair at a positive distance (finite energy)."""
+    import ipcscenes
+    for sc in ipcscenes.batched_squeeze(n_scenes=16, n_steps=2):
+        o = O.Oracle(sc)
+        o.begin_step(0)
+        y, _ = o.state()
+        assert np.isfinite(o.energy(y)[0])
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_distance_derivatives_fd(kind):
     f = O.dist2_pt if kind == 0 else O.dist2_ee
