@@ -62,8 +62,11 @@ class Sim:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().ipc_destroy(h)
             self._h = None
+            try:
+                lib().ipc_destroy(h)
+            except Exception:   # interpreter shutdown: the process releases the device anyway
+                pass
 
     def _query(self, what):
         v = ctypes.c_int64()

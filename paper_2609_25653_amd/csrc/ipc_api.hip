@@ -284,10 +284,6 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     Dev &D = c->d;
     hipStream_t st = c->stream;
     launch_world(c, y, D.xw.p);
-    if (hess) {
-        hipLaunchKernelGGL(k_zero, dim3(blocks_for(9 * (int64_t)c->N)), dim3(BLOCK), 0, st, 9 * (int64_t)c->N, D.diagF.p);
-        if (c->NB) hipLaunchKernelGGL(k_zero, dim3(blocks_for(144 * (int64_t)c->NB)), dim3(BLOCK), 0, st, 144 * (int64_t)c->NB, D.diagB.p);
-    }
     hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
     // inertia writes g; the FEM gathers then write the matrix values (constant
     // part + tets) and add the tets' gradients; every later term adds atomically

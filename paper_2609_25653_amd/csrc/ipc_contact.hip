@@ -199,8 +199,9 @@ __global__ void k_refit(int P, const int *__restrict__ sorted_id, const double *
 
 // Queries.  kind 0: surface vertex vs triangle tree; kind 1: edge vs edge tree.
 // WRITE = false counts, WRITE = true writes at off[q].
+constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64;
 template <bool WRITE>
-__global__ void k_traverse(int Q, int kind, const int2 *__restrict__ qedge, const int *__restrict__ cv_scene,
+__global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const int2 *__restrict__ qedge, const int *__restrict__ cv_scene,
                            const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_obj,
                            const int *__restrict__ okind, const int *__restrict__ excl, int nex, const double *__restrict__ xw0,
                            const double *__restrict__ xw1, const double *__restrict__ sparam, const int *__restrict__ seg,
@@ -219,35 +220,42 @@ __global__ void k_traverse(int Q, int kind, const int2 *__restrict__ qedge, cons
     int oq = cv_obj[qv[0]];
     int base = seg[s], n = seg[s + 1] - base;
     int cnt = 0, w = WRITE ? off[qi] : 0;
-    if (n > 0) {
-        int stack[64];
+    // traversal stack in LDS, one column per thread (a private array would
+    // live in scratch memory); children are tested before they are pushed
+    __shared__ int stk[TRAV_DEPTH * TRAV_BLOCK];
+    int *my = stk + threadIdx.x;
+    auto leaf = [&](int pid) {
+        if (!overlap(qb, pbox + 6 * (size_t)pid)) return;
+        bool ok;
+        int ob;
+        if (kind == 0) {
+            int4 t = tri[pid];
+            ok = qi != t.x && qi != t.y && qi != t.z;
+            ob = cv_obj[t.x];
+        } else {
+            int2 f = edge[pid];
+            ok = pid > qi && qv[0] != f.x && qv[0] != f.y && qv[1] != f.x && qv[1] != f.y;
+            ob = cv_obj[f.x];
+        }
+        if (ok && allowed(oq, ob, okind, excl, nex)) {
+            if (WRITE) out[w + cnt] = make_int2(qi, pid);
+            ++cnt;
+        }
+    };
+    if (n == 1) leaf(sorted_id[base]);
+    else if (n > 1 && overlap(qb, nbox + 6 * (size_t)base)) {
         int sp = 0;
-        stack[sp++] = (n == 1) ? -1 - base : base;
+        my[0] = base;
+        sp = 1;
         while (sp > 0) {
-            int node = stack[--sp];
-            if (node < 0) {
-                int pid = sorted_id[-1 - node];
-                if (!overlap(qb, pbox + 6 * (size_t)pid)) continue;
-                bool ok;
-                int ob;
-                if (kind == 0) {
-                    int4 t = tri[pid];
-                    ok = qi != t.x && qi != t.y && qi != t.z;
-                    ob = cv_obj[t.x];
-                } else {
-                    int2 f = edge[pid];
-                    ok = pid > qi && qv[0] != f.x && qv[0] != f.y && qv[1] != f.x && qv[1] != f.y;
-                    ob = cv_obj[f.x];
-                }
-                if (ok && allowed(oq, ob, okind, excl, nex)) {
-                    if (WRITE) out[w + cnt] = make_int2(qi, pid);
-                    ++cnt;
-                }
-            } else {
-                if (!overlap(qb, nbox + 6 * (size_t)node)) continue;
-                if (sp + 2 > 64) { atomicOr(overflow, 1); continue; }
-                stack[sp++] = left[node];
-                stack[sp++] = right[node];
+            int node = my[TRAV_BLOCK * --sp];
+            int ch[2] = {left[node], right[node]};
+            for (int c2 = 0; c2 < 2; ++c2) {
+                int x = ch[c2];
+                if (x < 0) { leaf(sorted_id[-1 - x]); continue; }
+                if (!overlap(qb, nbox + 6 * (size_t)x)) continue;
+                if (sp >= TRAV_DEPTH) { atomicOr(overflow, 1); continue; }
+                my[TRAV_BLOCK * sp++] = x;
             }
         }
     }
@@ -339,7 +347,7 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     ovf.alloc(2);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 2, ovf.p, 0);
     const int2 *qedge = D.edge.p;
-    hipLaunchKernelGGL(k_traverse<false>, dim3(blocks_for(Q, 128)), dim3(128), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
+    hipLaunchKernelGGL(k_traverse<false>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
                        D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
                        D.bvh_right.p, D.bvh_box.p, D.qcount.p, nullptr, nullptr, ovf.p);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.qcount.p + Q, 0);
@@ -351,7 +359,7 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
         outbuf.alloc(cap);
     }
     count = total;
-    hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, 128)), dim3(128), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
+    hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
                        D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
                        D.bvh_right.p, D.bvh_box.p, D.qcount.p, D.qoff.p, outbuf.p, ovf.p);
     int *sseg = D.seg.p + 2 * (ns + 1);
@@ -488,37 +496,6 @@ __device__ __forceinline__ d3 gather_cv(const Map &m, const double *v)
     return {0.0, 0.0, 0.0};
 }
 
-// body diagonal block: add (w_k w_l^T) (x) B into the body's 12x12 block
-__device__ __forceinline__ void body_diag_add(double *diagB, int bidx, d3 wk3, d3 wl3, const double *B)
-{
-    double wk[4] = {1.0, wk3.x, wk3.y, wk3.z}, wl[4] = {1.0, wl3.x, wl3.y, wl3.z};
-    double *D = diagB + 144 * (size_t)bidx;
-    for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b)
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) atomicAdd(D + (3 * a + i) * 12 + 3 * b + j, wk[a] * wl[b] * B[3 * i + j]);
-}
-
-// Add the diagonal-block contributions of a 4-vertex local Hessian given by
-// the function blk(k, l, B[9]) into the FEM / body diagonal accumulators.
-template <class F>
-__device__ __forceinline__ void diag_contrib(const Map *m, const int *cvb, double *diagF, double *diagB, F blk)
-{
-    double B[9];
-    for (int k = 0; k < 4; ++k) {
-        if (m[k].node >= 0) {
-            blk(k, k, B);
-            for (int q = 0; q < 9; ++q) atomicAdd(diagF + 9 * (size_t)m[k].node + q, B[q]);
-        } else if (m[k].body >= 0) {
-            for (int l = 0; l < 4; ++l) {
-                if (cvb[l] != cvb[k]) continue;
-                blk(k, l, B);
-                body_diag_add(diagB, cvb[k], m[k].xb, m[l].xb, B);
-            }
-        }
-    }
-}
-
 // When every dynamic vertex of a pair is a FEM node and each pair of them
 // already shares a block of the matrix (same tetrahedral mesh, adjacent - as
 // for a surface triangle or edge against static geometry), add the pair's
@@ -562,7 +539,7 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     const int4 *__restrict__ tri, const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
     const double *__restrict__ sparam, const double *__restrict__ rest2, const int *__restrict__ cv_node,
     const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ g,
-    int4 *__restrict__ pair_cv, double *__restrict__ pair_H, double *__restrict__ diagF, double *__restrict__ diagB,
+    int4 *__restrict__ pair_cv, double *__restrict__ pair_H,
     double *__restrict__ pe, int project, int *__restrict__ inf_flag, const int *__restrict__ row_ptr, const int *__restrict__ col, double *__restrict__ val, int *__restrict__ pair_flag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -621,8 +598,7 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
         cvv = {2.0 * t2.x, 2.0 * t2.y, 2.0 * t2.z};
     }
     Map mp[4];
-    int cvb[4];
-    for (int k = 0; k < 4; ++k) { mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0); cvb[k] = cv_body[cv[k]]; }
+    for (int k = 0; k < 4; ++k) mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
     // gradient in world coordinates
     const double su[4] = {-1.0, 1.0, 0.0, 0.0}, sv[4] = {0.0, 0.0, -1.0, 1.0};
     for (int k = 0; k < 4; ++k) {
@@ -706,7 +682,6 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     pair_flag[i] = 0;
     double *out = pair_H + 45 * (size_t)i;
     for (int q = 0; q < 45; ++q) out[q] = H[q];
-    diag_contrib(mp, cvb, diagF, diagB, blk);
 }
 
 void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project)
@@ -721,7 +696,7 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, dou
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)npt, (int)nee, pt, ee, D.tri.p, D.edge.p, xw,
                            D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, g,
-                           D.pair_cv.p, D.pair_H.p, D.diagF.p, D.diagB.p, D.pair_part.p, (int)project, D.inf_flag.p, D.row_ptr.p, D.col.p, D.val.p, D.pair_flag.p);
+                           D.pair_cv.p, D.pair_H.p, D.pair_part.p, (int)project, D.inf_flag.p, D.row_ptr.p, D.col.p, D.val.p, D.pair_flag.p);
     };
     if (mode == 2) prof_begin(c, IPC_K_BARRIER_HESS);
     if (mode == 0) go(k_barrier<0>);
@@ -798,7 +773,7 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
                            const double *__restrict__ llam, const double *__restrict__ lrn, const double *__restrict__ xw,
                            const int *__restrict__ cv_scene, const double *__restrict__ sparam, const int *__restrict__ cv_node,
                            const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
-                           double *__restrict__ g, double *__restrict__ lM, double *__restrict__ diagF, double *__restrict__ diagB,
+                           double *__restrict__ g, double *__restrict__ lM,
                            double *__restrict__ pe, const int *__restrict__ row_ptr, const int *__restrict__ col,
                            double *__restrict__ val, int *__restrict__ lflag)
 {
@@ -826,8 +801,7 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
     if (MODE == 0) return;
     double f1s = sn < ea ? 2.0 / ea - sn / (ea * ea) : 1.0 / sn;
     Map mp[4];
-    int cvb[4];
-    for (int k = 0; k < 4; ++k) { mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0); cvb[k] = cv_body[cv[k]]; }
+    for (int k = 0; k < 4; ++k) mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
     for (int k = 0; k < 4; ++k) {
         double cc = w * f1s * beta[k];
         scatter_cv(mp[k], g, {cc * u.x, cc * u.y, cc * u.z});
@@ -845,7 +819,6 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
     lflag[i] = 0;
     double *o = lM + 6 * (size_t)i;
     o[0] = M[0]; o[1] = M[1]; o[2] = M[2]; o[3] = M[4]; o[4] = M[5]; o[5] = M[8];
-    diag_contrib(mp, cvb, diagF, diagB, blk);
 }
 
 void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
@@ -857,7 +830,7 @@ void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p,
                            D.lag_lam.p, D.lag_rn.p, xw, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p,
-                           g, D.lag_M.p, D.diagF.p, D.diagB.p, D.fr_part.p, D.row_ptr.p, D.col.p, D.val.p, D.lag_flag.p);
+                           g, D.lag_M.p, D.fr_part.p, D.row_ptr.p, D.col.p, D.val.p, D.lag_flag.p);
     };
     D.fr_part.alloc(n + 1);
     if (mode == 0) go(k_friction<0>);
@@ -1086,7 +1059,7 @@ __global__ void k_dyn_count(int nb, int nf, const int *__restrict__ pflag, const
 __global__ void k_dyn_write(int nb, int nf, const int *__restrict__ off, const int4 *__restrict__ pcv, const int4 *__restrict__ lcv,
                             const double *__restrict__ pH, const double *__restrict__ lbeta, const double *__restrict__ lM,
                             const int *__restrict__ cv_node, const int *__restrict__ cv_body, const double *__restrict__ cv_x,
-                            const int *__restrict__ body_node0, int *__restrict__ key, int *__restrict__ idx, int *__restrict__ colc,
+                            const int *__restrict__ body_node0, unsigned long long *__restrict__ key, int *__restrict__ idx,
                             double *__restrict__ valc)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1112,30 +1085,61 @@ __global__ void k_dyn_write(int nb, int nf, const int *__restrict__ off, const i
                             for (int q = 0; q < 9; ++q) S[q] += w * B[q];
                         }
                     }
-                    key[o] = P.first[ga] + qa;
+                    key[o] = ((unsigned long long)(P.first[ga] + qa) << 32) | (unsigned)(P.first[gb] + qb);
                     idx[o] = o;
-                    colc[o] = P.first[gb] + qb;
                     for (int q = 0; q < 9; ++q) valc[9 * (size_t)o + q] = S[q];
                     ++o;
                 }
 }
 
-__global__ void k_dyn_gather(int n, const int *__restrict__ idx, const int *__restrict__ colc, const double *__restrict__ valc,
-                             int *__restrict__ col, double *__restrict__ val)
+// entries with the same (row, column) after the sort: one head per run
+__global__ void k_dyn_heads(int n, const unsigned long long *__restrict__ key, int *__restrict__ head)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    int e = idx[p];
-    col[p] = colc[e];
-    for (int q = 0; q < 9; ++q) val[9 * (size_t)p + q] = valc[9 * (size_t)e + q];
+    if (p > n) return;
+    head[p] = (p < n && (p == 0 || key[p] != key[p - 1])) ? 1 : 0;
 }
 
-// row pointers from the sorted row keys: ptr[n] = first position with key >= n
-__global__ void k_dyn_ptr(int n, int N, const int *__restrict__ key, int *__restrict__ ptr)
+// first sorted position of every run (and n after the last)
+__global__ void k_dyn_starts(int n, const int *__restrict__ head, const int *__restrict__ pos, int *__restrict__ start)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n) return;
+    if (p == n || head[p]) start[pos[p]] = p;
+}
+
+// one wavefront per run (a body's node blocks can collect thousands of
+// entries): lanes stride over the run's blocks, then shuffle-sum in a fixed
+// order into one block
+__global__ void k_dyn_merge(const int *__restrict__ nruns, const unsigned long long *__restrict__ key, const int *__restrict__ idx,
+                            const int *__restrict__ start, const double *__restrict__ valc, int *__restrict__ row,
+                            int *__restrict__ col, double *__restrict__ val)
+{
+    int w = (blockIdx.x * blockDim.x + threadIdx.x) / TILE, lane = threadIdx.x & (TILE - 1);
+    if (w >= *nruns) return;
+    int lo = start[w], hi = start[w + 1];
+    double acc[9];
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    for (int r = lo + lane; r < hi; r += TILE) {
+        const double *B = valc + 9 * (size_t)idx[r];
+        for (int q = 0; q < 9; ++q) acc[q] += B[q];
+    }
+    for (int q = 0; q < 9; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+        unsigned long long k = key[lo];
+        row[w] = (int)(k >> 32);
+        col[w] = (int)(k & 0xffffffffull);
+        for (int q = 0; q < 9; ++q) val[9 * (size_t)w + q] = acc[q];
+    }
+}
+
+// row pointers from the sorted rows of the *count entries: ptr[n] = first
+// position with row >= n
+__global__ void k_dyn_ptr(const int *__restrict__ count, int N, const int *__restrict__ key, int *__restrict__ ptr)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r > N) return;
-    int lo = 0, hi = n;
+    int lo = 0, hi = *count;
     while (lo < hi) {
         int m = (lo + hi) >> 1;
         if (key[m] < r) lo = m + 1; else hi = m;
@@ -1191,30 +1195,40 @@ void build_dyn_blocks(ipc_ctx *c)
                            D.pair_cv.p, D.lag_cv.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_cnt.p, D.tickets.p);
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.dyn_cnt.p + n, 0);
         exclusive_scan(c, D.dyn_cnt.p, D.dyn_off.p, (int)n);
-        c->n_dyn = read_int(c, D.dyn_off.p + n);
-        c->n_local = read_int(c, D.tickets.p);
+        int hv[2];
+        IPC_HIP(hipMemcpyAsync(&hv[0], D.dyn_off.p + n, sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipMemcpyAsync(&hv[1], D.tickets.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        c->n_dyn = hv[0];
+        c->n_local = hv[1];
     }
     int64_t E = c->n_dyn;
     if (E > 0) {
         if (E > c->cap_dyn) {
             c->cap_dyn = E + E / 2 + 1024;
-            for (auto *b : {&D.dyn_key, &D.dyn_key2, &D.dyn_idx, &D.dyn_idx2, &D.dyn_col_coo, &D.dyn_col}) b->alloc(c->cap_dyn);
+            D.dyn_key64.alloc(c->cap_dyn); D.dyn_key64b.alloc(c->cap_dyn);
+            for (auto *b : {&D.dyn_idx, &D.dyn_idx2, &D.dyn_head, &D.dyn_pos, &D.dyn_start, &D.dyn_row, &D.dyn_col}) b->alloc(c->cap_dyn + 1);
             D.dyn_val.alloc(9 * (size_t)c->cap_dyn); D.dyn_val_coo.alloc(9 * (size_t)c->cap_dyn);
         }
         hipLaunchKernelGGL(k_dyn_write, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.dyn_off.p, D.pair_cv.p, D.lag_cv.p,
-                           D.pair_H.p, D.lag_beta.p, D.lag_M.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_key.p,
-                           D.dyn_idx.p, D.dyn_col_coo.p, D.dyn_val_coo.p);
-        int end_bit = 1;
-        while ((1ll << end_bit) <= N) ++end_bit;
+                           D.pair_H.p, D.lag_beta.p, D.lag_M.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_key64.p,
+                           D.dyn_idx.p, D.dyn_val_coo.p);
+        int end_bit = 33;
+        while ((1ll << (end_bit - 32)) <= N) ++end_bit;
         size_t bytes = 0;
-        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.dyn_key.p, D.dyn_key2.p, D.dyn_idx.p, D.dyn_idx2.p, (int)E, 0,
-                                                   end_bit, st));
+        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.dyn_key64.p, D.dyn_key64b.p, D.dyn_idx.p, D.dyn_idx2.p, (int)E,
+                                                   0, end_bit, st));
         D.sort_tmp.alloc(bytes + 16);
-        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.sort_tmp.p, bytes, D.dyn_key.p, D.dyn_key2.p, D.dyn_idx.p, D.dyn_idx2.p, (int)E, 0,
-                                                   end_bit, st));
-        hipLaunchKernelGGL(k_dyn_gather, dim3(blocks_for(E)), dim3(BLOCK), 0, st, (int)E, D.dyn_idx2.p, D.dyn_col_coo.p,
-                           D.dyn_val_coo.p, D.dyn_col.p, D.dyn_val.p);
-        hipLaunchKernelGGL(k_dyn_ptr, dim3(blocks_for(N + 1)), dim3(BLOCK), 0, st, (int)E, N, D.dyn_key2.p, D.dyn_ptr.p);
+        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.sort_tmp.p, bytes, D.dyn_key64.p, D.dyn_key64b.p, D.dyn_idx.p, D.dyn_idx2.p,
+                                                   (int)E, 0, end_bit, st));
+        hipLaunchKernelGGL(k_dyn_heads, dim3(blocks_for(E + 1)), dim3(BLOCK), 0, st, (int)E, D.dyn_key64b.p, D.dyn_head.p);
+        exclusive_scan(c, D.dyn_head.p, D.dyn_pos.p, (int)E);
+        hipLaunchKernelGGL(k_dyn_starts, dim3(blocks_for(E + 1)), dim3(BLOCK), 0, st, (int)E, D.dyn_head.p, D.dyn_pos.p, D.dyn_start.p);
+        hipLaunchKernelGGL(k_dyn_merge, dim3(blocks_for(E * TILE)), dim3(BLOCK), 0, st, D.dyn_pos.p + E, D.dyn_key64b.p, D.dyn_idx2.p,
+                           D.dyn_start.p, D.dyn_val_coo.p, D.dyn_row.p, D.dyn_col.p, D.dyn_val.p);
+        // unique count: dyn_pos[E]; the row pointers search the sorted rows of
+        // the first dyn_pos[E] entries, read on the device
+        hipLaunchKernelGGL(k_dyn_ptr, dim3(blocks_for(N + 1)), dim3(BLOCK), 0, st, D.dyn_pos.p + E, N, D.dyn_row.p, D.dyn_ptr.p);
     } else {
         hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(N + 1)), dim3(BLOCK), 0, st, N + 1, D.dyn_ptr.p, 0);
     }
@@ -1225,7 +1239,14 @@ void build_dyn_blocks(ipc_ctx *c)
                        nullptr, nullptr);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.wcount.p + nw, 0);
     exclusive_scan(c, D.wcount.p, D.woff.p, nw);
-    c->n_long = read_int(c, D.woff.p + nw);
+    {
+        int hv[2] = {0, 0};
+        IPC_HIP(hipMemcpyAsync(&hv[0], D.woff.p + nw, sizeof(int), hipMemcpyDeviceToHost, st));
+        if (c->n_dyn > 0) IPC_HIP(hipMemcpyAsync(&hv[1], D.dyn_pos.p + c->n_dyn, sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        c->n_long = hv[0];
+        c->n_dyn = hv[1];   // blocks after merging equal (row, column) entries
+    }
     if (c->n_long)
         hipLaunchKernelGGL(k_long<true>, dim3(blocks_for(N)), dim3(BLOCK), 0, st, N, D.row_ptr.p, D.dyn_ptr.p, D.mkey.p, D.wcount.p,
                            D.woff.p, D.long_rows.p);

@@ -504,7 +504,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     for (auto *b : {&D.xt, &D.y0, &D.yt, &D.g, &D.p, &D.r, &D.z, &D.q, &D.w, &D.x, &D.v1, &D.v2}) b->alloc(3 * (size_t)node);
     IPC_HIP(hipMemcpyAsync(D.xt.p, D.y.p, 3 * (size_t)node * sizeof(double), hipMemcpyDeviceToDevice, st));
     D.node_scene.upload(node_scene, st); D.node_kind.upload(node_kind, st); D.ext2node.upload(ext2node, st);
-    D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node); D.diagF.alloc(9 * (size_t)node);
+    D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node);
     D.tv.upload(tv, st);
     D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);
     D.sc_ptr.upload(sc_ptr, st); D.sc_list.upload(sc_list, st);
@@ -515,7 +515,6 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     D.bslot.upload(bslot, st);
     D.bM.upload(bM, st); D.bvol.upload(bvol, st); D.bkappa.upload(bkappa, st); D.bext.upload(bext, st);
     D.body_node0.upload(body_node0, st); D.body_scene.upload(body_scene, st);
-    D.diagB.alloc(144 * (size_t)std::max(body, 1));
     D.dinvB.alloc(144 * (size_t)std::max(body, 1));
     D.body_part.alloc(std::max(body, 1));
     D.sp_ka.upload(ska, st); D.sp_ia.upload(sia, st); D.sp_kb.upload(skb, st); D.sp_ib.upload(sib, st);

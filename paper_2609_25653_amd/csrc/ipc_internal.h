@@ -151,7 +151,6 @@ struct Dev {
     DBuf<int> node_scene, node_kind;       // kind: 0 FEM, 1 body node, 2 padding
     DBuf<double> mass;                     // lumped FEM vertex mass (0 elsewhere)
     DBuf<double> dinv;                     // 3x3 inverse diagonal block per node
-    DBuf<double> diagF;                    // 3x3 diagonal block accumulators
     DBuf<int> ext2node;                    // external node -> internal node
     // tetrahedra (SoA over the padded tet range)
     DBuf<int4> tv;
@@ -170,14 +169,15 @@ struct Dev {
     DBuf<double> val, val_const;           // assembled values; constant part (mass, springs)
     DBuf<int> bslot, long_rows;            // 16 body-block slots per body; rows with > LONG_ROW blocks in all
     // pair-local contact blocks, sorted by row: extra blocks of the product
-    DBuf<int> dyn_ptr, dyn_col, dyn_cnt, dyn_off, dyn_key, dyn_key2, dyn_idx, dyn_idx2, dyn_col_coo;
+    DBuf<int> dyn_ptr, dyn_row, dyn_col, dyn_cnt, dyn_off, dyn_idx, dyn_idx2, dyn_head, dyn_pos, dyn_start;
+    DBuf<unsigned long long> dyn_key64, dyn_key64b;   // (row << 32 | column) before / after the sort
     DBuf<double> dyn_val, dyn_val_coo;
     DBuf<double> part_node3, part_long;    // product dot partials (per wavefront of nodes / per long row)
     // bodies
     DBuf<double> bM;                       // 4x4 mass matrix per body
     DBuf<double> bvol, bkappa, bext;
     DBuf<int> body_node0, body_scene;
-    DBuf<double> diagB, dinvB;
+    DBuf<double> dinvB;
     // springs
     DBuf<int> sp_ka, sp_ia, sp_kb, sp_ib, sp_scene;
     DBuf<double> sp_xa, sp_xb, sp_k;
@@ -242,7 +242,7 @@ struct ipc_ctx {
     int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
     int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
     int nnzb = 0, nnzb_fem = 0, n_long = 0;
-    int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly
+    int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
     int64_t ext_nodes = 0;
     int64_t ext_tets = 0;

@@ -109,7 +109,7 @@ int *seg_ptr(ipc_ctx *c, int region) { return c->d.segs.p + (size_t)region * (c-
 // matrix still yields L x 700 wavefronts, enough to hide the gather latency
 // of v.  The row's partial sums meet through shuffles inside the lane group.
 // Rows with more than LONG_ROW blocks in all (affine-body nodes with many
-// springs or contacts) go to extra workgroups, one wavefront per row.  With
+// springs or contacts) go to extra workgroups, one workgroup per row.  With
 // `part`, also v . out per tile (long rows into part_long): the dot product
 // the conjugate-gradient step needs, in the same pass.  L is chosen by the
 // autotuner among 1, 2, 4, 8 and 16.
@@ -172,17 +172,22 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, int nlong, c
         }
         return;
     }
-    int w = ((int)blockIdx.x - ntiles) * NW + threadIdx.x / TILE;
+    // one workgroup per long row: all 64 L lanes stride over its blocks
+    __shared__ double shl[3][NW];
+    int w = (int)blockIdx.x - ntiles;
     if (w >= nlong) return;
     int n = long_rows[w];
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool on = !active || active[node_scene[n]];
     if (on) {
-        for (int k = row_ptr[n] + lane; k < row_ptr[n + 1]; k += TILE) acc_block(val + 9 * (size_t)k, ld3(v, col[k]), ax, ay, az);
-        for (int k = dptr[n] + lane; k < dptr[n + 1]; k += TILE) acc_block(dval + 9 * (size_t)k, ld3(v, dcol[k]), ax, ay, az);
+        for (int k = row_ptr[n] + (int)threadIdx.x; k < row_ptr[n + 1]; k += 64 * L) acc_block(val + 9 * (size_t)k, ld3(v, col[k]), ax, ay, az);
+        for (int k = dptr[n] + (int)threadIdx.x; k < dptr[n + 1]; k += 64 * L) acc_block(dval + 9 * (size_t)k, ld3(v, dcol[k]), ax, ay, az);
     }
     ax = wave_sum(ax); ay = wave_sum(ay); az = wave_sum(az);
-    if (lane == 0) {
+    if (lane == 0) { shl[0][threadIdx.x / TILE] = ax; shl[1][threadIdx.x / TILE] = ay; shl[2][threadIdx.x / TILE] = az; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < NW; ++q) { ax += shl[0][q]; ay += shl[1][q]; az += shl[2][q]; }
         st3(out, n, {ax, ay, az});
         if (part_long) part_long[w] = on ? dt(ld3(v, n), {ax, ay, az}) : 0.0;
     }
@@ -200,8 +205,7 @@ static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const i
 {
     Dev &D = c->d;
     int ntiles = (c->N + TILE - 1) / TILE;
-    int nlongb = (c->n_long + L - 1) / L;
-    dim3 grid(ntiles + nlongb), blk(64 * L);
+    dim3 grid(ntiles + c->n_long), blk(64 * L);
     double *pl = part ? D.part_long.p : nullptr;
 #define IPC_SPMV(LL) hipLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, c->N, ntiles, c->n_long, D.long_rows.p, D.row_ptr.p, D.col.p, \
                                         D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, v, D.node_scene.p, active, out, part, pl)
@@ -252,10 +256,21 @@ void autotune_spmv(ipc_ctx *c, int reps, double *us)
 
 // ---------------------------------------------------------------------------
 // block-Jacobi preconditioner: diagonal blocks of the matrix plus the
-// diagonal blocks of the pair-local contact terms
+// pair-local contact blocks on the diagonal (found in the row-sorted list)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int dyn_find(const int *__restrict__ dptr, const int *__restrict__ dcol, int r, int cc)
+{
+    int lo = dptr[r], hi = dptr[r + 1];
+    while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (dcol[m] < cc) lo = m + 1; else hi = m;
+    }
+    return (lo < dptr[r + 1] && dcol[lo] == cc) ? lo : -1;
+}
+
 __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__restrict__ diag_slot, const double *__restrict__ val,
-                           const double *__restrict__ diagF, double *__restrict__ dinv)
+                           const int *__restrict__ dptr, const int *__restrict__ dcol, const double *__restrict__ dval,
+                           double *__restrict__ dinv)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -263,7 +278,9 @@ __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__res
     if (kind[n] != 0) { for (int q = 0; q < 9; ++q) o[q] = 0.0; return; }
     double a[9];
     const double *B = val + 9 * (size_t)diag_slot[n];
-    for (int q = 0; q < 9; ++q) a[q] = B[q] + diagF[9 * (size_t)n + q];
+    for (int q = 0; q < 9; ++q) a[q] = B[q];
+    int k = dyn_find(dptr, dcol, n, n);
+    if (k >= 0) for (int q = 0; q < 9; ++q) a[q] += dval[9 * (size_t)k + q];
     double c0 = a[4] * a[8] - a[5] * a[7], c1 = a[5] * a[6] - a[3] * a[8], c2 = a[3] * a[7] - a[4] * a[6];
     double det = a[0] * c0 + a[1] * c1 + a[2] * c2;
     double id = 1.0 / det;
@@ -273,19 +290,23 @@ __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__res
 }
 
 // 12x12 SPD inverse by Cholesky (one thread per body)
-__global__ void k_prec_body(int NB, const int *__restrict__ bslot, const double *__restrict__ val, const double *__restrict__ diagB,
+__global__ void k_prec_body(int NB, const int *__restrict__ bslot, const int *__restrict__ node0, const double *__restrict__ val,
+                            const int *__restrict__ dptr, const int *__restrict__ dcol, const double *__restrict__ dval,
                             double *__restrict__ dinvB)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= NB) return;
     double L[144];
+    int n0 = node0[b];
     for (int ca = 0; ca < 4; ++ca)
         for (int cb = 0; cb < 4; ++cb) {
             const double *B = val + 9 * (size_t)bslot[16 * (size_t)b + 4 * ca + cb];
+            int k = dyn_find(dptr, dcol, n0 + ca, n0 + cb);
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
-                    int r = 3 * ca + i, cc = 3 * cb + j;
-                    L[12 * r + cc] = B[3 * i + j] + diagB[144 * (size_t)b + 12 * r + cc];
+                    double v = B[3 * i + j];
+                    if (k >= 0) v += dval[9 * (size_t)k + 3 * i + j];
+                    L[12 * (3 * ca + i) + 3 * cb + j] = v;
                 }
         }
     for (int j = 0; j < 12; ++j) {
@@ -320,9 +341,10 @@ void build_preconditioner(ipc_ctx *c)
 {
     Dev &D = c->d;
     hipLaunchKernelGGL(k_prec_fem, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, D.node_kind.p, D.diag_slot.p, D.val.p,
-                       D.diagF.p, D.dinv.p);
+                       D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.dinv.p);
     if (c->NB)
-        hipLaunchKernelGGL(k_prec_body, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.bslot.p, D.val.p, D.diagB.p,
+        hipLaunchKernelGGL(k_prec_body, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.bslot.p, D.body_node0.p, D.val.p,
+                           D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p,
                            D.dinvB.p);
 }
 

@@ -25,7 +25,8 @@ def test_library_exports_every_declared_symbol():
     from paper_2609_25653_amd import _lib
     if not os.path.exists(_lib.SO_PATH):
         pytest.skip("library not built")
-    L = ctypes.CDLL(_lib.SO_PATH)
+    # RTLD_NOW: every symbol the library needs must resolve at load time
+    L = ctypes.CDLL(_lib.SO_PATH, mode=os.RTLD_NOW)
     missing = [n for n in declared() if not hasattr(L, n)]
     assert not missing, missing
 
