@@ -23,6 +23,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton iters/s & sim steps/s at 200k tets; batched scenes/s; adjoint/forward time"
 HBM_PEAK_GBS = 8000.0
+# calibrated hardware traffic of the product, valid while its source is unchanged
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_traffic.json")
+PRODUCT_SRC = os.path.join(ROOT, "paper_2609_25653_amd", "csrc", "ipc_solver.hip")
+
+
+def product_traffic():
+    """Per-launch HBM bytes of the product from the committed counter runs, or
+    None when the product's source file changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(PRODUCT_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec.get("bytes_per_launch") if rec.get("source_sha256") == sha else None
 
 
 def cpu_baseline(scene, pcg_per_newton):
@@ -61,6 +76,34 @@ def cpu_baseline(scene, pcg_per_newton):
                        f"iteration; CPU {model}")}
 
 
+def write_traffic(fetch_csv, write_csv):
+    """Calibrate FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the probe's
+    256 MiB device copy and store the product's bytes per launch."""
+    import csv
+    import hashlib
+
+    def per_kernel(path):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy = [k for k in f if "copyBuffer" in k]
+    spmv = [k for k in f if "k_spmv" in k]
+    kib = 256 * 1024   # the probe copies 256 MiB
+    fac_f = kib / max(max(f[k]) for k in copy)
+    fac_w = kib / max(max(w[k]) for k in copy)
+    sf = [v for k in spmv for v in f[k]]
+    sw = [v for k in spmv for v in w[k]]
+    traffic = 1024.0 * (fac_f * sum(sf) / len(sf) + fac_w * sum(sw) / len(sw))
+    rec = {"kernel": "k_spmv", "bytes_per_launch": traffic, "fetch_kib": sum(sf) / len(sf), "write_kib": sum(sw) / len(sw),
+           "fetch_scale": fac_f, "write_scale": fac_w, "launches": len(sf),
+           "source_sha256": hashlib.sha256(open(PRODUCT_SRC, "rb").read()).hexdigest()}
+    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(rec))
+
+
 def probe_spmv(sim):
     """One assembly, one plain copy of known size, then 20 timed products."""
     import torch
@@ -93,14 +136,19 @@ def bench_batched(args):
     sim = Sim(scenes)
     t_create = time.perf_counter() - t0
     print(f"# batched: {len(scenes)} scenes, {tets.sum()} tets, created in {t_create:.1f} s", file=sys.stderr, flush=True)
+    # a scene whose Newton loop ends without convergence (3) or without a
+    # decreasing line-search step (4) stays at its last iterate and continues
+    ok_codes = (3, 4)
+    not_ok = 0
     for _ in range(args.warmup):
-        sim.step(allow_status=(3,))
+        sim.step(allow_status=ok_codes)
     lanes, _ = sim.autotune(10)
     torch.cuda.synchronize()
     newton = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rc, st = sim.step(allow_status=(3,))
+        rc, st = sim.step(allow_status=ok_codes)
+        not_ok += sum(1 for s in st if s["status"] != 0)
         newton.append(max(s["newton_iters"] for s in st))
         print(f"# step {sim.step_index}: rc={rc} max newton={newton[-1]} "
               f"pairs={sum(s['n_pt_max'] + s['n_ee_max'] for s in st)}", file=sys.stderr, flush=True)
@@ -113,12 +161,12 @@ def bench_batched(args):
     for i in pick:
         s1 = Sim(scenes[i])
         for _ in range(args.warmup):
-            s1.step(allow_status=(3,))
+            s1.step(allow_status=ok_codes)
         s1.autotune(5)
         torch.cuda.synchronize()
         a = time.perf_counter()
         for _ in range(args.steps):
-            s1.step(allow_status=(3,))
+            s1.step(allow_status=ok_codes)
         torch.cuda.synchronize()
         t_single += time.perf_counter() - a
         del s1
@@ -133,6 +181,7 @@ def bench_batched(args):
                           "sample": f"{len(pick)} scenes spread over the size range, scaled by {len(scenes)}/{len(pick)}"},
         "speedup_vs_one_at_a_time": t_single_all / t,
         "max_newton_per_step": newton, "spmv_lanes_per_row": lanes,
+        "scene_steps_not_converged": not_ok,
     }
     print(json.dumps(line))
 
@@ -201,10 +250,15 @@ def main():
                          "together vs one at a time; adjoint: 50-step squeeze rollout, forward vs backward time")
     ap.add_argument("--scenes", type=int, default=256, help="batched: number of scenes")
     ap.add_argument("--single-sample", type=int, default=16, help="batched: scenes stepped one at a time for the baseline")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="write the product's calibrated per-launch HBM traffic from the counter files of two "
+                         "'rocprofv3 --pmc FETCH_SIZE' / '--pmc WRITE_SIZE' runs of --probe spmv, then exit")
     ap.add_argument("--probe", choices=["spmv"], default=None,
                     help="spmv: assemble the Hessian of the 200k-tet scene once, then run a plain 256 MiB device copy "
                          "and 20 back-to-back block-CSR products (for hardware-counter runs)")
     args = ap.parse_args()
+    if args.traffic_from:
+        return write_traffic(*args.traffic_from)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -249,7 +303,7 @@ def main():
     sim._check(lib().ipc_time_kernel(sim._h, 0, 200, ctypes.byref(us), ctypes.byref(by)))
     achieved = by.value / (us.value * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)", "bytes_per_launch": by.value,
+            "traffic": product_traffic(), "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)", "bytes_per_launch": by.value,
             "avg_us": us.value}
     kt = {}
     line = {

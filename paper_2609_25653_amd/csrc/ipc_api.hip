@@ -140,12 +140,13 @@ std::vector<double> read_scal(ipc_ctx *c)
     sync(c);
     return h;
 }
+// Staged through a context-owned buffer so the source outlives the copy.  No
+// synchronisation: every caller reads the scalars back (synchronising)
+// before it writes them again, so the staged copy has completed by then.
 void write_scal(ipc_ctx *c, const std::vector<double> &h)
 {
-    // staged through a context-owned buffer so the source outlives the copy
     c->h_scal_stage = h;
     IPC_HIP(hipMemcpyAsync(c->d.scal.p, c->h_scal_stage.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    sync(c);
 }
 
 void upload_seg_region(ipc_ctx *c, int region, const std::vector<int> &h)
@@ -301,9 +302,7 @@ void pairs_from_scratch(ipc_ctx *c, const double *y)
 {
     launch_world(c, y, c->d.xw.p);
     broad_phase(c, c->d.xw.p, nullptr);
-    store_cand_segs(c);
     narrow_phase(c, c->d.xw.p);
-    store_pair_segs(c);
 }
 
 void begin_step_impl(ipc_ctx *c, const double *targets_dev)
@@ -323,26 +322,6 @@ void begin_step_impl(ipc_ctx *c, const double *targets_dev)
 }
 
 } // namespace
-
-// segment tables computed by the broad / narrow phase live in host vectors;
-// mirror them into the device regions used by the reductions
-void store_cand_segs(ipc_ctx *c)
-{
-    upload_seg_region(c, R_CPT, c->h_cand_pt_seg);
-    upload_seg_region(c, R_CEE, c->h_cand_ee_seg);
-}
-void store_pair_segs(ipc_ctx *c)
-{
-    upload_seg_region(c, R_PT, c->h_pt_seg);
-    upload_seg_region(c, R_EE, c->h_ee_seg);
-}
-
-int *upload_seg(ipc_ctx *c, const std::vector<int> &seg, int which)
-{
-    int region = which == 0 ? R_PSEG : R_QSEG;
-    upload_seg_region(c, region, seg);
-    return seg_ptr(c, region);
-}
 
 __global__ void k_fill_int_api(int n, int *p, int v)
 {
@@ -568,7 +547,6 @@ extern "C" int ipc_ccd(ipc_ctx *c, const double *y_dev, const double *p_dev, dou
         launch_world(c, D.v2.p, D.xw.p);
         launch_world(c, D.yt.p, D.xw1.p);
         broad_phase(c, D.xw.p, D.xw1.p);
-        store_cand_segs(c);
         hipLaunchKernelGGL(k_set_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_CCD, 1.0);
         hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.ls_active.p, 1);
         launch_ccd(c, D.xw.p, D.xw1.p);
@@ -785,7 +763,6 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         launch_world(c, D.y.p, D.xw.p);
         launch_world(c, D.yt.p, D.xw1.p);
         broad_phase(c, D.xw.p, D.xw1.p);
-        store_cand_segs(c);
         for (int s = 0; s < ns; ++s) S[s].n_cand_max = std::max(S[s].n_cand_max, (c->h_cand_pt_seg[s + 1] - c->h_cand_pt_seg[s]) +
                                                                              (c->h_cand_ee_seg[s + 1] - c->h_cand_ee_seg[s]));
         c->h_int_stage = on;
@@ -837,7 +814,6 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         // pairs at the new iterate from the swept candidates (a superset)
         launch_world(c, D.y.p, D.xw.p);
         narrow_phase(c, D.xw.p);
-        store_pair_segs(c);
     }
     hipLaunchKernelGGL(k_velocity, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.sparam.p, D.y.p, D.y0.p, D.ydot.p);
     IPC_HIP(hipStreamSynchronize(st));

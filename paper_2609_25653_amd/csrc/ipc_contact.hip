@@ -274,14 +274,38 @@ __global__ void k_fill_int(int n, int *p, int v)
     if (i < n) p[i] = v;
 }
 
-// per-scene segment offsets of a query-ordered output from its exclusive scan
-__global__ void k_seg_from_scan(int n_scenes, const int *__restrict__ qseg, const int *__restrict__ off, int total, int *__restrict__ seg)
+// per-scene segment offsets of a query-ordered output from its exclusive
+// scan (qseg[n_scenes] = number of queries, off[that] = total)
+__global__ void k_seg_from_scan(int n_scenes, const int *__restrict__ qseg, const int *__restrict__ off, int *__restrict__ seg)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s > n_scenes) return;
-    int q = qseg[s];
-    seg[s] = (s == n_scenes) ? total : off[q];
+    seg[s] = off[qseg[s]];
 }
+
+// per-scene segments of a ballot-compacted list: survivors before each
+// scene's first candidate (cseg), from the wavefront masks and their scan
+__global__ void k_compact_seg(int n_scenes, int ncand, const int *__restrict__ cseg, const unsigned long long *__restrict__ mask,
+                              const int *__restrict__ woff, int nw, int *__restrict__ seg)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > n_scenes) return;
+    int q = cseg[s];
+    if (q >= ncand) { seg[s] = woff[nw]; return; }
+    int w = q / TILE, l = q % TILE;
+    seg[s] = woff[w] + (l ? __popcll(mask[w] & ((1ull << l) - 1ull)) : 0);
+}
+
+// several device values to the host with one synchronisation
+struct HostReads {
+    ipc_ctx *c;
+    explicit HostReads(ipc_ctx *cc) : c(cc) {}
+    void add(void *dst, const void *src, size_t bytes)
+    {
+        IPC_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    }
+    void wait() { IPC_HIP(hipStreamSynchronize(c->stream)); }
+};
 
 // exclusive scan helper (count[n] -> off[n + 1], off[n] = total)
 static void exclusive_scan(ipc_ctx *c, const int *in, int *out, int n)
@@ -315,12 +339,13 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     hipStream_t st = c->stream;
     int P = kind == 0 ? c->TRI : c->EDGE;
     int Q = kind == 0 ? c->NSURF : c->EDGE;
-    const std::vector<int> &pseg = kind == 0 ? c->seg_tri : c->seg_edge;
-    const std::vector<int> &qseg = kind == 0 ? c->seg_surf : c->seg_edge;
     int ns = c->n_scenes;
     hseg.assign(ns + 1, 0);
     count = 0;
-    if (P == 0 || Q == 0) return;
+    if (P == 0 || Q == 0) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, ns + 1, seg_ptr(c, kind == 0 ? R_CPT : R_CEE), 0);
+        return;
+    }
     D.box.alloc(6 * (size_t)P); D.mkey.alloc(P); D.mkey2.alloc(P); D.mid.alloc(P); D.mid2.alloc(P);
     D.bvh_left.alloc(P); D.bvh_right.alloc(P); D.bvh_parent.alloc(P); D.bvh_flag.alloc(2 * (size_t)P); D.bvh_box.alloc(6 * (size_t)P);
     D.qcount.alloc(Q + 1); D.qoff.alloc(Q + 1);
@@ -332,8 +357,9 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.mkey.p, D.mkey2.p, D.mid.p, D.mid2.p, P, 0, end_bit, st));
     D.sort_tmp.alloc(bytes + 16);
     IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.sort_tmp.p, bytes, D.mkey.p, D.mkey2.p, D.mid.p, D.mid2.p, P, 0, end_bit, st));
-    int *pseg_d = upload_seg(c, pseg, 0);
-    int *qseg_d = upload_seg(c, qseg, 1);
+    int *pseg_d = seg_ptr(c, kind == 0 ? R_TRI : R_EDGE);
+    int *qseg_d = seg_ptr(c, kind == 0 ? R_SURF : R_EDGE);
+    int *sseg = seg_ptr(c, kind == 0 ? R_CPT : R_CEE);
     int *scene_sorted = D.bvh_flag.p + P;   // scratch: scene of each sorted leaf
     hipLaunchKernelGGL(k_scene_of_sorted, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mkey2.p, scene_sorted);
     DBuf<int> &leafpar = D.leafpar;
@@ -352,8 +378,17 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
                        D.bvh_right.p, D.bvh_box.p, D.qcount.p, nullptr, nullptr, ovf.p);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.qcount.p + Q, 0);
     exclusive_scan(c, D.qcount.p, D.qoff.p, Q);
-    int total = read_int(c, D.qoff.p + Q);
-    if (read_int(c, ovf.p)) throw Error(IPC_E_CAPACITY, "BVH traversal stack overflow");
+    // the candidates' per-scene segments go straight to the device table
+    hipLaunchKernelGGL(k_seg_from_scan, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns, qseg_d, D.qoff.p, sseg);
+    int total = 0, of = 0;
+    {
+        HostReads r(c);
+        r.add(&total, D.qoff.p + Q, sizeof(int));
+        r.add(&of, ovf.p, sizeof(int));
+        r.add(hseg.data(), sseg, (ns + 1) * sizeof(int));
+        r.wait();
+    }
+    if (of) throw Error(IPC_E_CAPACITY, "BVH traversal stack overflow");
     if (total > cap) {
         cap = (int64_t)(total * 1.5) + 1024;
         outbuf.alloc(cap);
@@ -362,9 +397,6 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
                        D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
                        D.bvh_right.p, D.bvh_box.p, D.qcount.p, D.qoff.p, outbuf.p, ovf.p);
-    int *sseg = D.seg.p + 2 * (ns + 1);
-    hipLaunchKernelGGL(k_seg_from_scan, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns, qseg_d, D.qoff.p, total, sseg);
-    read_ints(c, sseg, hseg, ns + 1);
 }
 
 void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1)
@@ -415,7 +447,7 @@ __global__ void k_narrow(int n, int kind, const int2 *__restrict__ cand, const i
     }
 }
 
-static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &cand, int64_t ncand, const std::vector<int> &cseg,
+static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &cand, int64_t ncand, int cseg_region, int pseg_region,
                     DBuf<int2> &out, int64_t &cap, int64_t &count, std::vector<int> &hseg)
 {
     Dev &D = c->d;
@@ -423,7 +455,11 @@ static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &ca
     int ns = c->n_scenes;
     hseg.assign(ns + 1, 0);
     count = 0;
-    if (ncand == 0) return;
+    int *sseg = seg_ptr(c, pseg_region);
+    if (ncand == 0) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, ns + 1, sseg, 0);
+        return;
+    }
     int nw = (int)((ncand + TILE - 1) / TILE);
     DBuf<unsigned long long> &mask = D.mkey;   // scratch reuse
     mask.alloc(nw);
@@ -432,30 +468,27 @@ static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &ca
                        D.cv_scene.p, xw, D.sparam.p, mask.p, D.wcount.p, nullptr, nullptr);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.wcount.p + nw, 0);
     exclusive_scan(c, D.wcount.p, D.woff.p, nw);
-    int total = read_int(c, D.woff.p + nw);
+    // candidates are grouped by scene and the order is kept, so each scene's
+    // first survivor is the number of survivors before its first candidate
+    hipLaunchKernelGGL(k_compact_seg, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns, (int)ncand, seg_ptr(c, cseg_region), mask.p,
+                       D.woff.p, nw, sseg);
+    int total = 0;
+    {
+        HostReads r(c);
+        r.add(&total, D.woff.p + nw, sizeof(int));
+        r.add(hseg.data(), sseg, (ns + 1) * sizeof(int));
+        r.wait();
+    }
     if (total > cap) { cap = (int64_t)(total * 1.5) + 1024; out.alloc(cap); }
     count = total;
     hipLaunchKernelGGL(k_narrow<true>, dim3(blocks_for(ncand)), dim3(BLOCK), 0, st, (int)ncand, kind, cand.p, D.tri.p, D.edge.p,
                        D.cv_scene.p, xw, D.sparam.p, mask.p, D.wcount.p, D.woff.p, out.p);
-    // per-scene segments: candidates are grouped by scene and the order is kept, so
-    // each scene's first survivor index is the prefix count before its first candidate
-    std::vector<int> hoff;
-    read_ints(c, D.woff.p, hoff, nw + 1);
-    std::vector<unsigned long long> hm(nw);
-    IPC_HIP(hipMemcpyAsync(hm.data(), mask.p, nw * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    IPC_HIP(hipStreamSynchronize(st));
-    for (int s = 0; s <= ns; ++s) {
-        int q = cseg[s];
-        if (q >= ncand) { hseg[s] = total; continue; }
-        int w = q / TILE, l = q % TILE;
-        hseg[s] = hoff[w] + (l ? __builtin_popcountll(hm[w] & ((1ull << l) - 1ull)) : 0);
-    }
 }
 
 void narrow_phase(ipc_ctx *c, const double *xw)
 {
-    compact(c, 0, xw, c->d.cand_pt, c->n_cand_pt, c->h_cand_pt_seg, c->d.pt, c->cap_pt, c->n_pt, c->h_pt_seg);
-    compact(c, 1, xw, c->d.cand_ee, c->n_cand_ee, c->h_cand_ee_seg, c->d.ee, c->cap_ee, c->n_ee, c->h_ee_seg);
+    compact(c, 0, xw, c->d.cand_pt, c->n_cand_pt, R_CPT, R_PT, c->d.pt, c->cap_pt, c->n_pt, c->h_pt_seg);
+    compact(c, 1, xw, c->d.cand_ee, c->n_cand_ee, R_CEE, R_EE, c->d.ee, c->cap_ee, c->n_ee, c->h_ee_seg);
 }
 
 // ---------------------------------------------------------------------------

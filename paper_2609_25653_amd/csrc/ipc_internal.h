@@ -56,7 +56,6 @@ enum Region {
     R_CPT, R_CEE,   // candidates
     R_PT, R_EE,     // active pairs
     R_LPT, R_LEE,   // friction lag lists
-    R_QSEG, R_PSEG, R_TMP,
     R_LONG,         // rows of the product handled one wavefront per row
     NREGION
 };
@@ -283,10 +282,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n);
 void reduce(ipc_ctx *c, const RedArgs &a);
 RedSrc src(const double *v, const int *seg, int off, int base);
 int *seg_ptr(ipc_ctx *c, int region);
-void store_cand_segs(ipc_ctx *c);
 void prof_begin(ipc_ctx *c, int k);
 void prof_end(ipc_ctx *c, int k, double bytes);
-void store_pair_segs(ipc_ctx *c);
 __global__ void k_fill_int_api(int n, int *p, int v);
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part);
 void autotune_spmv(ipc_ctx *c, int reps, double *us);

@@ -46,6 +46,5 @@ void launch_adj_rhs(ipc_ctx *c, const double *ybar_next, const double *vbar_next
 void launch_adj_mass(ipc_ctx *c, const double *w, const double *vbar_next, double *ybar_prev, double *vbar_prev);
 void launch_adj_E(ipc_ctx *c, const double *y, const double *w, double *Ebar_ext);
 
-int *upload_seg(ipc_ctx *c, const std::vector<int> &seg, int which);
 
 } // namespace ipc
