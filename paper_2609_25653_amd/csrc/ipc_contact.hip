@@ -140,16 +140,14 @@ __device__ __forceinline__ int lcp(const unsigned long long *key, int base, int 
 // Child encoding: >= 0 internal node, < 0 leaf -1-k (k = sorted position).
 __global__ void k_karras(int P, const int *__restrict__ prim_scene_of_sorted, const int *__restrict__ seg,
                          const unsigned long long *__restrict__ key, int *__restrict__ left, int *__restrict__ right,
-                         int *__restrict__ parent, int *__restrict__ leaf_parent)
+                         int2 *__restrict__ range)
 {
     int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= P) return;
     int s = prim_scene_of_sorted[gi];
     int base = seg[s], n = seg[s + 1] - base;
     int i = gi - base;
-    if (i == 0) parent[gi] = -1;
-    if (n == 1) leaf_parent[gi] = -1;
-    if (i >= n - 1) return;
+    if (i >= n - 1) { range[gi] = make_int2(-1, -1); return; }
     int d = (lcp(key, base, n, i, i + 1) - lcp(key, base, n, i, i - 1)) >= 0 ? 1 : -1;
     int dmin = lcp(key, base, n, i, i - d);
     int lmax = 2;
@@ -170,31 +168,75 @@ __global__ void k_karras(int P, const int *__restrict__ prim_scene_of_sorted, co
     int R = (hi == gamma + 1) ? -1 - (base + gamma + 1) : base + gamma + 1;
     left[gi] = L;
     right[gi] = R;
-    if (L < 0) leaf_parent[-1 - L] = gi; else parent[L] = gi;
-    if (R < 0) leaf_parent[-1 - R] = gi; else parent[R] = gi;
+    range[gi] = make_int2(base + lo, base + hi);   // sorted leaves covered by the node
 }
 
-__global__ void k_refit(int P, const int *__restrict__ sorted_id, const double *__restrict__ pbox, const int *__restrict__ left,
-                        const int *__restrict__ right, const int *__restrict__ parent, const int *__restrict__ leaf_parent,
-                        int *__restrict__ flag, double *__restrict__ nbox)
+// Node boxes.  A Karras node covers a contiguous range of sorted leaves, so
+// its box is a range union.  A perfect binary tree of unions over the sorted
+// leaf boxes (levels built 8 at a time in LDS, one workgroup per 256 inputs)
+// answers every node's range with O(log P) independent loads, and no
+// workgroup waits on another (a bottom-up refit would need device-scope
+// fences, which write back the XCD's L2 at every level).
+struct SegLevels { int n; int off[32]; int size[32]; };
+
+__device__ __forceinline__ void box_union(double *a, const double *b)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P) return;
-    int node = leaf_parent[k];
-    while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(flag + node, 1) == 0) return;   // the second arrival merges
-        __threadfence();
+    for (int m = 0; m < 3; ++m) { a[m] = fmin(a[m], b[m]); a[3 + m] = fmax(a[3 + m], b[3 + m]); }
+}
+__device__ __forceinline__ void box_empty(double *a)
+{
+    for (int m = 0; m < 3; ++m) { a[m] = INFINITY; a[3 + m] = -INFINITY; }
+}
+
+// level 0: the leaf boxes in sorted order
+__global__ void k_seg_leaves(int P, const int *__restrict__ sorted_id, const double *__restrict__ pbox, double *__restrict__ lev)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const double *b = pbox + 6 * (size_t)sorted_id[i];
+    for (int m = 0; m < 6; ++m) lev[6 * (size_t)i + m] = b[m];
+}
+
+// levels j0+1 .. j0+8 from level j0 (256 inputs per workgroup)
+__global__ void __launch_bounds__(256) k_seg_up(SegLevels L, int j0, double *__restrict__ lev)
+{
+    __shared__ double sh[256][6];
+    int t = threadIdx.x, i = blockIdx.x * 256 + t;
+    if (i < L.size[j0]) for (int m = 0; m < 6; ++m) sh[t][m] = lev[6 * ((size_t)L.off[j0] + i) + m];
+    else box_empty(sh[t]);
+    __syncthreads();
+    for (int step = 1; step <= 8 && j0 + step < L.n; ++step) {
+        int w = 256 >> step;
         double b[6];
-        int ch[2] = {left[node], right[node]};
-        for (int m = 0; m < 6; ++m) b[m] = (m < 3) ? INFINITY : -INFINITY;
-        for (int c2 = 0; c2 < 2; ++c2) {
-            const double *cb = ch[c2] < 0 ? pbox + 6 * (size_t)sorted_id[-1 - ch[c2]] : nbox + 6 * (size_t)ch[c2];
-            for (int m = 0; m < 3; ++m) { b[m] = fmin(b[m], cb[m]); b[3 + m] = fmax(b[3 + m], cb[3 + m]); }
+        if (t < w) {
+            for (int m = 0; m < 6; ++m) b[m] = sh[2 * t][m];
+            box_union(b, sh[2 * t + 1]);
         }
-        for (int m = 0; m < 6; ++m) nbox[6 * (size_t)node + m] = b[m];
-        node = parent[node];
+        __syncthreads();
+        if (t < w) {
+            for (int m = 0; m < 6; ++m) sh[t][m] = b[m];
+            int j = j0 + step, k = blockIdx.x * w + t;
+            if (k < L.size[j]) for (int m = 0; m < 6; ++m) lev[6 * ((size_t)L.off[j] + k) + m] = b[m];
+        }
+        __syncthreads();
     }
+}
+
+// every internal node: the union over its leaf range [lo, hi]
+__global__ void k_node_box(int P, SegLevels L, const double *__restrict__ lev, const int2 *__restrict__ range, double *__restrict__ nbox)
+{
+    int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= P) return;
+    int2 rg = range[gi];
+    if (rg.x < 0) return;
+    double acc[6];
+    box_empty(acc);
+    int l = rg.x, r = rg.y + 1;
+    for (int j = 0; j < L.n && l < r; ++j, l >>= 1, r >>= 1) {
+        if (l & 1) { box_union(acc, lev + 6 * ((size_t)L.off[j] + l)); ++l; }
+        if (r & 1) { --r; box_union(acc, lev + 6 * ((size_t)L.off[j] + r)); }
+    }
+    for (int m = 0; m < 6; ++m) nbox[6 * (size_t)gi + m] = acc[m];
 }
 
 // Queries.  kind 0: surface vertex vs triangle tree; kind 1: edge vs edge tree.
@@ -347,7 +389,7 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
         return;
     }
     D.box.alloc(6 * (size_t)P); D.mkey.alloc(P); D.mkey2.alloc(P); D.mid.alloc(P); D.mid2.alloc(P);
-    D.bvh_left.alloc(P); D.bvh_right.alloc(P); D.bvh_parent.alloc(P); D.bvh_flag.alloc(2 * (size_t)P); D.bvh_box.alloc(6 * (size_t)P);
+    D.bvh_left.alloc(P); D.bvh_right.alloc(P); D.bvh_range.alloc(P); D.bvh_flag.alloc(P); D.bvh_box.alloc(6 * (size_t)P);
     D.qcount.alloc(Q + 1); D.qoff.alloc(Q + 1);
     hipLaunchKernelGGL(k_prim_box, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, kind, D.tri.p, D.edge.p, D.cv_scene.p, xw0, xw1,
                        D.sparam.p, D.scene_lo.p, D.box.p, D.mkey.p, D.mid.p);
@@ -360,15 +402,28 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     int *pseg_d = seg_ptr(c, kind == 0 ? R_TRI : R_EDGE);
     int *qseg_d = seg_ptr(c, kind == 0 ? R_SURF : R_EDGE);
     int *sseg = seg_ptr(c, kind == 0 ? R_CPT : R_CEE);
-    int *scene_sorted = D.bvh_flag.p + P;   // scratch: scene of each sorted leaf
+    int *scene_sorted = D.bvh_flag.p;   // scratch: scene of each sorted leaf
     hipLaunchKernelGGL(k_scene_of_sorted, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mkey2.p, scene_sorted);
-    DBuf<int> &leafpar = D.leafpar;
-    leafpar.alloc(P);
     hipLaunchKernelGGL(k_karras, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, scene_sorted, pseg_d, D.mkey2.p, D.bvh_left.p,
-                       D.bvh_right.p, D.bvh_parent.p, leafpar.p);
-    hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.bvh_flag.p, 0);
-    hipLaunchKernelGGL(k_refit, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mid2.p, D.box.p, D.bvh_left.p, D.bvh_right.p,
-                       D.bvh_parent.p, leafpar.p, D.bvh_flag.p, D.bvh_box.p);
+                       D.bvh_right.p, D.bvh_range.p);
+    // node boxes from the union tree over the sorted leaf boxes
+    SegLevels SL{};
+    {
+        int64_t total = 0;
+        int sz = P;
+        for (SL.n = 0; SL.n < 32; ++SL.n) {
+            SL.off[SL.n] = (int)total;
+            SL.size[SL.n] = sz;
+            total += sz;
+            if (sz == 1) { ++SL.n; break; }
+            sz = (sz + 1) / 2;
+        }
+        D.bvh_lev.alloc(6 * (size_t)total);
+    }
+    hipLaunchKernelGGL(k_seg_leaves, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mid2.p, D.box.p, D.bvh_lev.p);
+    for (int j0 = 0; j0 + 1 < SL.n; j0 += 8)
+        hipLaunchKernelGGL(k_seg_up, dim3(blocks_for(SL.size[j0], 256)), dim3(256), 0, st, SL, j0, D.bvh_lev.p);
+    hipLaunchKernelGGL(k_node_box, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, SL, D.bvh_lev.p, D.bvh_range.p, D.bvh_box.p);
     DBuf<int> &ovf = D.woff;
     ovf.alloc(2);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 2, ovf.p, 0);

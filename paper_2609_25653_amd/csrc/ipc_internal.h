@@ -196,8 +196,9 @@ struct Dev {
     DBuf<double> box;                      // 6 per primitive (lo, hi)
     DBuf<unsigned long long> mkey, mkey2;
     DBuf<int> mid, mid2;
-    DBuf<int> bvh_left, bvh_right, bvh_parent, bvh_flag;
-    DBuf<double> bvh_box;
+    DBuf<int> bvh_left, bvh_right, bvh_flag;
+    DBuf<int2> bvh_range;                  // sorted-leaf range of every internal node
+    DBuf<double> bvh_box, bvh_lev;         // node boxes; union tree over the sorted leaf boxes
     DBuf<int> qcount, qoff;                // per-query candidate counts and offsets
     DBuf<unsigned char> sort_tmp;
     DBuf<double> scene_lo;                 // Morton quantisation box per scene (6)
@@ -223,7 +224,7 @@ struct Dev {
     DBuf<double> part_node2, fr_part;
     DBuf<double> sparam, h2s;              // per-scene parameters
     DBuf<int> inf_flag, ls_active, pcg_active, pcg_iters, maxpcg, newton_on;
-    DBuf<int> leafpar, is_trans;
+    DBuf<int> is_trans;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
     DBuf<int> tickets;                     // small device counters
     DBuf<double> body_part2;

@@ -26,8 +26,18 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
     int s = blockIdx.x;
     __shared__ double sh[8][BLOCK / TILE];
     int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
-    // all loads first (independent, in flight together), then the shuffles
+    // all loads first (independent, in flight together), then the shuffles:
+    // the first 4 strided partials of every source are loaded unconditionally
+    // (predicated), the rest (scenes with more than 1024 partials) in a loop
     double part[8];
+    // the post step's inputs, fetched while the partials are in flight
+    double S0 = 0.0, S1 = 0.0, Sg = 0.0, Se = 0.0, Sm = 0.0;
+    int act = 0, it0 = 0;
+    if (threadIdx.x == 0 && post != POST_NONE) {
+        const double *Sp = scal + (size_t)s * NSLOT;
+        S0 = Sp[S_RZ]; S1 = Sp[S_ALPHA]; Sg = Sp[S_RZ_NEW]; Se = Sp[S_ETA2]; Sm = Sp[S_MAXIT];
+        act = active[s]; it0 = iters[s];
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         part[k] = 0.0;
@@ -35,10 +45,18 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
         const RedSrc &r = a.src[k];
         if (!r.v) continue;
         int lo = r.seg[s] - r.base, hi = r.seg[s + 1] - r.base;
-        for (int i = lo + (int)threadIdx.x; i < hi; i += BLOCK) {
-            double v = r.v[r.off + i];
-            part[k] = a.op ? fmax(part[k], v) : part[k] + v;
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int i = lo + (int)threadIdx.x + u * BLOCK;
+            v[u] = i < hi ? r.v[r.off + i] : (a.op ? -INFINITY : 0.0);
         }
+        double acc = a.op ? fmax(fmax(v[0], v[1]), fmax(v[2], v[3])) : (v[0] + v[1]) + (v[2] + v[3]);
+        for (int i = lo + (int)threadIdx.x + 4 * BLOCK; i < hi; i += BLOCK) {
+            double x = r.v[r.off + i];
+            acc = a.op ? fmax(acc, x) : acc + x;
+        }
+        part[k] = a.op ? fmax(acc, 0.0) : acc;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -60,17 +78,19 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
     if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], tot[0]) : S[a.slot] + tot[0]) : tot[0];
     if (a.slot1 >= 0) S[a.slot1] = tot[1];
     if (a.slot2 >= 0) S[a.slot2] = tot[2];
-    if (post == POST_NONE || !active[s]) return;
+    if (post == POST_NONE || !act) return;
     // Conjugate gradients with one reduction per iteration (Chronopoulos and
     // Gear): with gamma = r.z and delta = z.Az of the current residual,
     //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
     //   alpha = gamma / p.Ap.
-    double gam = S[S_RZ_NEW], del = S[S_PAP], be = 0.0;
+    // POST_CG: group 0 = gamma, 1 = delta, 2 = r.r; POST_CG_FIRST: group 1 =
+    // delta, gamma from the set-up reduction.
+    double gam = post == POST_CG ? tot[0] : Sg, del = tot[1], be = 0.0;
     if (post == POST_CG) {
-        iters[s] += 1;
-        if (S[S_RR] <= S[S_ETA2] || iters[s] >= (int)S[S_MAXIT]) { active[s] = 0; return; }
-        be = gam / S[S_RZ];
-        del -= be * gam / S[S_ALPHA];
+        iters[s] = it0 + 1;
+        if (tot[2] <= Se || it0 + 1 >= (int)Sm) { active[s] = 0; return; }
+        be = gam / S0;
+        del -= be * gam / S1;
     }
     if (!(del > 0.0)) {   // not positive definite along the search direction: stop here
         S[S_INDEF] = 1.0;
