@@ -240,8 +240,11 @@ __global__ void k_node_box(int P, SegLevels L, const double *__restrict__ lev, c
 }
 
 // Queries.  kind 0: surface vertex vs triangle tree; kind 1: edge vs edge tree.
-// WRITE = false counts, WRITE = true writes at off[q].
-constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64;
+// WRITE = false counts and stashes the first TRAV_STASH candidates of each
+// query (the common case needs no second traversal: a compaction copies the
+// stash); WRITE = true writes every candidate at off[q] when some query had
+// more.
+constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64, TRAV_STASH = 8;
 template <bool WRITE>
 __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const int2 *__restrict__ qedge, const int *__restrict__ cv_scene,
                            const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_obj,
@@ -249,7 +252,7 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
                            const double *__restrict__ xw1, const double *__restrict__ sparam, const int *__restrict__ seg,
                            const int *__restrict__ sorted_id, const double *__restrict__ pbox, const int *__restrict__ left,
                            const int *__restrict__ right, const double *__restrict__ nbox, int *__restrict__ count,
-                           const int *__restrict__ off, int2 *__restrict__ out, int *__restrict__ overflow)
+                           const int *__restrict__ off, int2 *__restrict__ out, int *__restrict__ overflow, int2 *__restrict__ stash)
 {
     int qi = blockIdx.x * blockDim.x + threadIdx.x;
     if (qi >= Q) return;
@@ -281,6 +284,7 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
         }
         if (ok && allowed(oq, ob, okind, excl, nex)) {
             if (WRITE) out[w + cnt] = make_int2(qi, pid);
+            else if (cnt < TRAV_STASH) stash[(size_t)qi * TRAV_STASH + cnt] = make_int2(qi, pid);
             ++cnt;
         }
     };
@@ -301,7 +305,20 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
             }
         }
     }
-    if (!WRITE) count[qi] = cnt;
+    if (!WRITE) {
+        count[qi] = cnt;
+        if (cnt > TRAV_STASH) atomicOr(overflow + 1, 1);
+    }
+}
+
+// candidates of every query from its stash, at its scanned offset
+__global__ void k_unstash(int Q, const int *__restrict__ count, const int *__restrict__ off, const int2 *__restrict__ stash,
+                          int2 *__restrict__ out)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q) return;
+    int n = count[q], o = off[q];
+    for (int c = 0; c < n; ++c) out[o + c] = stash[(size_t)q * TRAV_STASH + c];
 }
 
 __global__ void k_scene_of_sorted(int P, const unsigned long long *__restrict__ key, int *__restrict__ sc)
@@ -390,7 +407,7 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     }
     D.box.alloc(6 * (size_t)P); D.mkey.alloc(P); D.mkey2.alloc(P); D.mid.alloc(P); D.mid2.alloc(P);
     D.bvh_left.alloc(P); D.bvh_right.alloc(P); D.bvh_range.alloc(P); D.bvh_flag.alloc(P); D.bvh_box.alloc(6 * (size_t)P);
-    D.qcount.alloc(Q + 1); D.qoff.alloc(Q + 1);
+    D.qcount.alloc(Q + 1); D.qoff.alloc(Q + 1); D.qstash.alloc((size_t)Q * TRAV_STASH);
     hipLaunchKernelGGL(k_prim_box, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, kind, D.tri.p, D.edge.p, D.cv_scene.p, xw0, xw1,
                        D.sparam.p, D.scene_lo.p, D.box.p, D.mkey.p, D.mid.p);
     size_t bytes = 0;
@@ -430,28 +447,31 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     const int2 *qedge = D.edge.p;
     hipLaunchKernelGGL(k_traverse<false>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
                        D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
-                       D.bvh_right.p, D.bvh_box.p, D.qcount.p, nullptr, nullptr, ovf.p);
+                       D.bvh_right.p, D.bvh_box.p, D.qcount.p, nullptr, nullptr, ovf.p, D.qstash.p);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.qcount.p + Q, 0);
     exclusive_scan(c, D.qcount.p, D.qoff.p, Q);
     // the candidates' per-scene segments go straight to the device table
     hipLaunchKernelGGL(k_seg_from_scan, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns, qseg_d, D.qoff.p, sseg);
-    int total = 0, of = 0;
+    int total = 0, of[2] = {0, 0};
     {
         HostReads r(c);
         r.add(&total, D.qoff.p + Q, sizeof(int));
-        r.add(&of, ovf.p, sizeof(int));
+        r.add(of, ovf.p, 2 * sizeof(int));
         r.add(hseg.data(), sseg, (ns + 1) * sizeof(int));
         r.wait();
     }
-    if (of) throw Error(IPC_E_CAPACITY, "BVH traversal stack overflow");
+    if (of[0]) throw Error(IPC_E_CAPACITY, "BVH traversal stack overflow");
     if (total > cap) {
         cap = (int64_t)(total * 1.5) + 1024;
         outbuf.alloc(cap);
     }
     count = total;
-    hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
-                       D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
-                       D.bvh_right.p, D.bvh_box.p, D.qcount.p, D.qoff.p, outbuf.p, ovf.p);
+    if (!of[1])
+        hipLaunchKernelGGL(k_unstash, dim3(blocks_for(Q)), dim3(BLOCK), 0, st, Q, D.qcount.p, D.qoff.p, D.qstash.p, outbuf.p);
+    else
+        hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p,
+                           D.tri.p, D.edge.p, D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p,
+                           D.box.p, D.bvh_left.p, D.bvh_right.p, D.bvh_box.p, D.qcount.p, D.qoff.p, outbuf.p, ovf.p, nullptr);
 }
 
 void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1)

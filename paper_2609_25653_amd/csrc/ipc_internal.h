@@ -200,6 +200,7 @@ struct Dev {
     DBuf<int2> bvh_range;                  // sorted-leaf range of every internal node
     DBuf<double> bvh_box, bvh_lev;         // node boxes; union tree over the sorted leaf boxes
     DBuf<int> qcount, qoff;                // per-query candidate counts and offsets
+    DBuf<int2> qstash;                     // first candidates of every query from the counting pass
     DBuf<unsigned char> sort_tmp;
     DBuf<double> scene_lo;                 // Morton quantisation box per scene (6)
     // candidates and active pairs
