@@ -136,18 +136,13 @@ void sync(ipc_ctx *c) { IPC_HIP(hipStreamSynchronize(c->stream)); }
 std::vector<double> read_scal(ipc_ctx *c)
 {
     std::vector<double> h((size_t)c->n_scenes * NSLOT);
-    IPC_HIP(hipMemcpyAsync(h.data(), c->d.scal.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    sync(c);
+    HostReads r(c);
+    r.add(h.data(), c->d.scal.p, h.size() * sizeof(double));
+    r.wait();
     return h;
 }
-// Staged through a context-owned buffer so the source outlives the copy.  No
-// synchronisation: every caller reads the scalars back (synchronising)
-// before it writes them again, so the staged copy has completed by then.
-void write_scal(ipc_ctx *c, const std::vector<double> &h)
-{
-    c->h_scal_stage = h;
-    IPC_HIP(hipMemcpyAsync(c->d.scal.p, c->h_scal_stage.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-}
+
+void write_scal(ipc_ctx *c, const std::vector<double> &h) { upload_async(c, c->d.scal.p, h.data(), h.size() * sizeof(double)); }
 
 void upload_seg_region(ipc_ctx *c, int region, const std::vector<int> &h)
 {
@@ -166,6 +161,7 @@ void upload_sparam(ipc_ctx *c)
         SceneInfo &S = c->sc[s];
         sp[8 * s + P_H2] = S.h * S.h; sp[8 * s + P_KAPPA] = S.kappa; sp[8 * s + P_DHAT] = S.dhat; sp[8 * s + P_MU] = S.mu;
         sp[8 * s + P_EPSH] = S.eps_v * S.h; sp[8 * s + P_CCDS] = S.ccd_s; sp[8 * s + P_H] = S.h;
+        sp[8 * s + P_ETA] = S.pcg_tol;
     }
     c->d.sparam.upload(sp, c->stream);
     sync(c);
@@ -205,15 +201,17 @@ void setup_after_create(ipc_ctx *c)
         }
         D.scene_lo.upload(lo, c->stream);
     }
-    std::vector<int> is_trans(c->N, 0);
+    std::vector<int> is_trans(c->N, 0), node_body(c->N, -1);
     for (int s = 0; s < ns; ++s) {
         SceneInfo &S = c->sc[s];
-        for (int b = 0; b < S.nb; ++b) is_trans[S.node0 + S.nv + 4 * b] = 1;
+        for (int b = 0; b < S.nb; ++b) {
+            is_trans[S.node0 + S.nv + 4 * b] = 1;
+            node_body[S.node0 + S.nv + 4 * b] = S.body0 + b;
+        }
     }
     D.is_trans.upload(is_trans, c->stream);
-    for (auto *b : {&D.inf_flag, &D.ls_active, &D.pcg_active, &D.pcg_iters, &D.newton_on}) b->alloc(ns);
-    D.part_node2.alloc(c->N / TILE + 1);
-    D.body_part2.alloc(std::max(c->NB, 1));
+    D.node_body.upload(node_body, c->stream);
+    for (auto *b : {&D.inf_flag, &D.ls_active, &D.pcg_iters, &D.newton_on}) b->alloc(ns);
     D.tickets.alloc(4);
     D.tickets.zero(c->stream, 4);
     D.segs.alloc((size_t)NREGION * (ns + 1));
@@ -322,6 +320,61 @@ void begin_step_impl(ipc_ctx *c, const double *targets_dev)
 }
 
 } // namespace
+
+// pinned staging areas of the context (allocated on first use)
+constexpr size_t PIN_RD_BYTES = 1 << 20, PIN_WR_BYTES = 1 << 20;
+static void ensure_pinned(ipc_ctx *c)
+{
+    if (c->pin_rd) return;
+    IPC_HIP(hipHostMalloc((void **)&c->pin_rd, PIN_RD_BYTES, hipHostMallocDefault));
+    IPC_HIP(hipHostMalloc((void **)&c->pin_wr, PIN_WR_BYTES, hipHostMallocDefault));
+    c->pin_wr_off = 0;
+}
+
+HostReads::HostReads(ipc_ctx *cc) : c(cc) { ensure_pinned(c); }
+
+void HostReads::add(void *dst, const void *src, size_t bytes)
+{
+    if (!bytes) return;
+    size_t off = (used + 63) & ~(size_t)63;
+    if (off + bytes > PIN_RD_BYTES) {
+        IPC_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+        return;
+    }
+    IPC_HIP(hipMemcpyAsync(c->pin_rd + off, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    items.push_back({dst, off, bytes});
+    used = off + bytes;
+}
+
+void HostReads::wait()
+{
+    IPC_HIP(hipStreamSynchronize(c->stream));
+    for (auto &it : items) std::memcpy(it.dst, c->pin_rd + it.off, it.bytes);
+    items.clear();
+    used = 0;
+}
+
+// The ring wraps after a stream synchronisation, so no pending copy still
+// reads the part that is overwritten.
+void upload_async(ipc_ctx *c, void *dst_dev, const void *src, size_t bytes)
+{
+    if (!bytes) return;
+    ensure_pinned(c);
+    if (bytes > PIN_WR_BYTES) {
+        IPC_HIP(hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyHostToDevice, c->stream));
+        sync(c);
+        return;
+    }
+    size_t off = (c->pin_wr_off + 255) & ~(size_t)255;
+    if (off + bytes > PIN_WR_BYTES) {
+        sync(c);
+        off = 0;
+    }
+    std::memcpy(c->pin_wr + off, src, bytes);
+    IPC_HIP(hipMemcpyAsync(dst_dev, c->pin_wr + off, bytes, hipMemcpyHostToDevice, c->stream));
+    c->pin_wr_off = off + bytes;
+}
+
 
 __global__ void k_fill_int_api(int n, int *p, int v)
 {
@@ -718,16 +771,9 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         eval_grad_hess(c, D.y.p, D.g.p, true, true);
         build_preconditioner(c);
         hipLaunchKernelGGL(k_negate, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.g.p, D.v1.p);
-        c->h_int_stage = on;
-        IPC_HIP(hipMemcpyAsync(D.newton_on.p, c->h_int_stage.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
-        std::vector<double> eta(ns);
-        for (int s = 0; s < ns; ++s) eta[s] = c->sc[s].pcg_tol;
-        sc = read_scal(c);
-        for (int s = 0; s < ns; ++s) sc[(size_t)s * NSLOT + S_ETA] = eta[s];
-        write_scal(c, sc);
+        upload_async(c, D.newton_on.p, on.data(), ns * sizeof(int));
         pcg_solve(c, D.v1.p, D.x.p, -1.0, D.newton_on.p);
         std::vector<int> it(ns);
-        IPC_HIP(hipMemcpyAsync(it.data(), D.pcg_iters.p, ns * sizeof(int), hipMemcpyDeviceToHost, st));
         // Newton measure
         hipLaunchKernelGGL(k_measure_nodes, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.x.p, D.part_node.p);
         if (c->NB)
@@ -741,7 +787,12 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             a.slot = S_NEWTON_MAX;
             reduce(c, a);
         }
-        sc = read_scal(c);
+        {
+            HostReads rd(c);
+            rd.add(it.data(), D.pcg_iters.p, ns * sizeof(int));
+            rd.add(sc.data(), D.scal.p, sc.size() * sizeof(double));
+            rd.wait();
+        }
         any = false;
         for (int s = 0; s < ns; ++s) {
             if (!on[s]) continue;
@@ -765,8 +816,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         broad_phase(c, D.xw.p, D.xw1.p);
         for (int s = 0; s < ns; ++s) S[s].n_cand_max = std::max(S[s].n_cand_max, (c->h_cand_pt_seg[s + 1] - c->h_cand_pt_seg[s]) +
                                                                              (c->h_cand_ee_seg[s + 1] - c->h_cand_ee_seg[s]));
-        c->h_int_stage = on;
-        IPC_HIP(hipMemcpyAsync(D.ls_active.p, c->h_int_stage.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+        upload_async(c, D.ls_active.p, on.data(), ns * sizeof(int));
         launch_ccd(c, D.xw.p, D.xw1.p);
         sc = read_scal(c);
         std::vector<double> alpha(ns, 0.0);
@@ -895,6 +945,10 @@ ipc_ctx::~ipc_ctx()
         for (auto e : T.ev) (void)hipEventDestroy(e);
         for (auto e : T.pool) (void)hipEventDestroy(e);
     }
+    for (auto &x : pcg_exec) if (x) (void)hipGraphExecDestroy(x);
+    if (h_peek) (void)hipHostFree(h_peek);
+    if (pin_rd) (void)hipHostFree(pin_rd);
+    if (pin_wr) (void)hipHostFree(pin_wr);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
 }
 

@@ -355,17 +355,6 @@ __global__ void k_compact_seg(int n_scenes, int ncand, const int *__restrict__ c
     seg[s] = woff[w] + (l ? __popcll(mask[w] & ((1ull << l) - 1ull)) : 0);
 }
 
-// several device values to the host with one synchronisation
-struct HostReads {
-    ipc_ctx *c;
-    explicit HostReads(ipc_ctx *cc) : c(cc) {}
-    void add(void *dst, const void *src, size_t bytes)
-    {
-        IPC_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
-    }
-    void wait() { IPC_HIP(hipStreamSynchronize(c->stream)); }
-};
-
 // exclusive scan helper (count[n] -> off[n + 1], off[n] = total)
 static void exclusive_scan(ipc_ctx *c, const int *in, int *out, int n)
 {
@@ -373,21 +362,6 @@ static void exclusive_scan(ipc_ctx *c, const int *in, int *out, int n)
     IPC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n + 1, c->stream));
     c->d.sort_tmp.alloc(bytes + 16);
     IPC_HIP(hipcub::DeviceScan::ExclusiveSum(c->d.sort_tmp.p, bytes, in, out, n + 1, c->stream));
-}
-
-static int read_int(ipc_ctx *c, const int *p)
-{
-    int v = 0;
-    IPC_HIP(hipMemcpyAsync(&v, p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    IPC_HIP(hipStreamSynchronize(c->stream));
-    return v;
-}
-
-static void read_ints(ipc_ctx *c, const int *p, std::vector<int> &v, int n)
-{
-    v.resize(n);
-    IPC_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    IPC_HIP(hipStreamSynchronize(c->stream));
 }
 
 // Build the tree over one primitive kind and run one query kind against it.
@@ -1274,9 +1248,11 @@ __global__ void k_long(int N, const int *__restrict__ row_ptr, const int *__rest
 }
 
 // per-scene segments of the long-row list (node ranges of scenes are tiles)
-__global__ void k_long_seg(int ns, const int *__restrict__ nodew, const int *__restrict__ rows, int nlong, int *__restrict__ seg)
+__global__ void k_long_seg(int ns, const int *__restrict__ nodew, const int *__restrict__ rows, int nlong, int *__restrict__ seg,
+                           int *__restrict__ count)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) count[0] = nlong;
     if (s > ns) return;
     int start = nodew[s] * TILE, lo = 0, hi = nlong;
     while (lo < hi) {
@@ -1304,9 +1280,10 @@ void build_dyn_blocks(ipc_ctx *c)
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.dyn_cnt.p + n, 0);
         exclusive_scan(c, D.dyn_cnt.p, D.dyn_off.p, (int)n);
         int hv[2];
-        IPC_HIP(hipMemcpyAsync(&hv[0], D.dyn_off.p + n, sizeof(int), hipMemcpyDeviceToHost, st));
-        IPC_HIP(hipMemcpyAsync(&hv[1], D.tickets.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        IPC_HIP(hipStreamSynchronize(st));
+        HostReads rd(c);
+        rd.add(&hv[0], D.dyn_off.p + n, sizeof(int));
+        rd.add(&hv[1], D.tickets.p, sizeof(int));
+        rd.wait();
         c->n_dyn = hv[0];
         c->n_local = hv[1];
     }
@@ -1349,18 +1326,21 @@ void build_dyn_blocks(ipc_ctx *c)
     exclusive_scan(c, D.wcount.p, D.woff.p, nw);
     {
         int hv[2] = {0, 0};
-        IPC_HIP(hipMemcpyAsync(&hv[0], D.woff.p + nw, sizeof(int), hipMemcpyDeviceToHost, st));
-        if (c->n_dyn > 0) IPC_HIP(hipMemcpyAsync(&hv[1], D.dyn_pos.p + c->n_dyn, sizeof(int), hipMemcpyDeviceToHost, st));
-        IPC_HIP(hipStreamSynchronize(st));
+        HostReads rd(c);
+        rd.add(&hv[0], D.woff.p + nw, sizeof(int));
+        if (c->n_dyn > 0) rd.add(&hv[1], D.dyn_pos.p + c->n_dyn, sizeof(int));
+        rd.wait();
         c->n_long = hv[0];
         c->n_dyn = hv[1];   // blocks after merging equal (row, column) entries
     }
     if (c->n_long)
         hipLaunchKernelGGL(k_long<true>, dim3(blocks_for(N)), dim3(BLOCK), 0, st, N, D.row_ptr.p, D.dyn_ptr.p, D.mkey.p, D.wcount.p,
                            D.woff.p, D.long_rows.p);
-    D.part_long.alloc(c->n_long + 1);
+    if (c->n_long > c->long_cap) c->long_cap = (c->n_long + 63) / 64 * 64;
+    D.part_long.alloc(c->long_cap + 1);
+    D.long_count.alloc(1);
     hipLaunchKernelGGL(k_long_seg, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes, seg_ptr(c, R_NODEW),
-                       D.long_rows.p, c->n_long, seg_ptr(c, R_LONG));
+                       D.long_rows.p, c->n_long, seg_ptr(c, R_LONG), D.long_count.p);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,25 +24,14 @@ constexpr int LONG_ROW = 64;  // rows with more blocks go to the wavefront-per-r
 // per-scene device scalar slots
 enum Slot {
     S_E = 0,        // energy (sum over terms)
-    S_RZ,           // PCG r.z
-    S_RZ_NEW,
-    S_PAP,          // p.Ap
-    S_RR,           // r.r
-    S_BB,           // b.b
-    S_ALPHA,        // PCG alpha
-    S_BETA,         // PCG beta
-    S_ACTIVE,       // 1 while the scene's PCG iterates
     S_NEWTON_MAX,   // Newton measure (max world displacement of p)
     S_CCD,          // CCD step bound (stored through its bit pattern, atomic min)
     S_LS_ALPHA,     // line-search step of the scene
     S_LS_ON,        // 1 while the scene takes part in the current Newton iteration
     S_INF,          // 1 when some pair has d <= 0
     S_E_IN, S_E_FEM, S_E_ABD, S_E_SP, S_E_BAR, S_E_FR,
-    S_ETA,          // PCG relative tolerance of the scene
     S_E0,           // line search: energy at the current iterate
     S_NEWTON_ON,    // 1 while the scene's Newton loop runs
-    S_ETA2,         // PCG stop: eta^2 b.b
-    S_MAXIT,        // PCG iteration cap
     S_INDEF,        // 1 when the scene's PCG met p.Ap <= 0
     S_MUBAR,        // adjoint: w . dG/dmu of the last step
     NSLOT
@@ -61,7 +50,7 @@ enum Region {
 };
 
 // per-scene parameters (device, 8 per scene)
-enum Param { P_H2 = 0, P_KAPPA = 1, P_DHAT = 2, P_MU = 3, P_EPSH = 4, P_CCDS = 5, P_H = 6 };
+enum Param { P_H2 = 0, P_KAPPA = 1, P_DHAT = 2, P_MU = 3, P_EPSH = 4, P_CCDS = 5, P_H = 6, P_ETA = 7 };
 
 struct RedSrc {
     const double *v;
@@ -167,6 +156,7 @@ struct Dev {
     DBuf<int> row_ptr, col, diag_slot;
     DBuf<double> val, val_const;           // assembled values; constant part (mass, springs)
     DBuf<int> bslot, long_rows;            // 16 body-block slots per body; rows with > LONG_ROW blocks in all
+    DBuf<int> long_count;                  // number of long rows (read by the product's extra workgroups)
     // pair-local contact blocks, sorted by row: extra blocks of the product
     DBuf<int> dyn_ptr, dyn_row, dyn_col, dyn_cnt, dyn_off, dyn_idx, dyn_idx2, dyn_head, dyn_pos, dyn_start;
     DBuf<unsigned long long> dyn_key64, dyn_key64b;   // (row << 32 | column) before / after the sort
@@ -222,13 +212,17 @@ struct Dev {
     DBuf<int> seg;                         // scratch segment offsets (broad phase)
     DBuf<int> segs;                        // NREGION tables of n_scenes + 1
     DBuf<int> tile_scene_node, tile_scene_tet;
-    DBuf<double> part_node2, fr_part;
+    DBuf<double> fr_part;
     DBuf<double> sparam, h2s;              // per-scene parameters
-    DBuf<int> inf_flag, ls_active, pcg_active, pcg_iters, maxpcg, newton_on;
-    DBuf<int> is_trans;
+    DBuf<int> inf_flag, ls_active, pcg_iters, maxpcg, newton_on;
+    DBuf<int> is_trans, node_body;         // first node of an affine body: 1 / the body's index (else 0 / -1)
+    // conjugate-gradient state, two parity buffers: per scene {gamma, alpha,
+    // eta^2 b.b, r.r}, running flag and update count; per-tile partials of
+    // r.z and r.r
+    DBuf<double> pcg_st, pcg_part, pcg_prev;   // pcg_prev: r.r at the previous peek
+    DBuf<int> pcg_act, pcg_it;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
     DBuf<int> tickets;                     // small device counters
-    DBuf<double> body_part2;
     DBuf<double> grav;
     DBuf<double> red_tmp;
 };
@@ -243,6 +237,7 @@ struct ipc_ctx {
     int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
     int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
     int nnzb = 0, nnzb_fem = 0, n_long = 0;
+    int long_cap = 0;                     // long-row workgroups the product launches (grows, multiple of 64)
     int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
     int64_t ext_nodes = 0;
@@ -258,6 +253,15 @@ struct ipc_ctx {
     bool fr_on = true;
     bool use_graphs = true;              // PCG iterations replayed from a captured graph
     hipStream_t cap_stream = nullptr;    // private stream used only for graph capture
+    // PCG batch graphs, reused while every launch argument they captured is unchanged
+    std::vector<uintptr_t> pcg_key;
+    hipGraphExec_t pcg_exec[4] = {nullptr, nullptr, nullptr, nullptr};   // [batch length][copy]
+    unsigned long long *h_peek = nullptr;       // pinned, coherent host memory: 2 slots of one word per scene
+    unsigned long long *h_peek_dev = nullptr;   // its device address
+    unsigned int peek_seq = 0;
+    // pinned host staging: a readback arena (one HostReads at a time) and an upload ring
+    char *pin_rd = nullptr, *pin_wr = nullptr;
+    size_t pin_wr_off = 0;
     int64_t n_lag_pt = 0, n_local = 0;
     int last_status = 0;
     // host staging for small uploads (kept alive until the copy has completed)
@@ -292,6 +296,22 @@ void autotune_spmv(ipc_ctx *c, int reps, double *us);
 double spmv_bytes(const ipc_ctx *c);
 void build_preconditioner(ipc_ctx *c);
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
+
+// Several device values to the host with one synchronisation, staged in the
+// context's pinned readback arena (asynchronous copies); reads that do not
+// fit go straight to their destination.  One instance at a time per context.
+struct HostReads {
+    ipc_ctx *c;
+    size_t used = 0;
+    struct Item { void *dst; size_t off, bytes; };
+    std::vector<Item> items;
+    explicit HostReads(ipc_ctx *cc);
+    void add(void *dst, const void *src, size_t bytes);
+    void wait();
+};
+// host -> device copy through the context's pinned upload ring (asynchronous;
+// the host data may be reused as soon as the call returns)
+void upload_async(ipc_ctx *c, void *dst_dev, const void *src, size_t bytes);
 
 // launch helper
 inline int blocks_for(int64_t n, int bs = BLOCK) { return (int)((n + bs - 1) / bs); }

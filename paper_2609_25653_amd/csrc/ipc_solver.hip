@@ -4,6 +4,7 @@
 // blocks that fit its pattern, plus pair-local contact blocks for the rest),
 // the block-Jacobi preconditioner (3x3 per FEM vertex, 12x12 per body) and a
 // PCG that runs all scenes at once with per-scene scalars and flags.
+#include <chrono>
 #include <cmath>
 
 #include "ipc_device.h"
@@ -14,14 +15,10 @@ namespace ipc {
 
 // ---------------------------------------------------------------------------
 // reductions: one workgroup per scene.  Each thread sums a fixed strided
-// subset of a source's partials, wavefront shuffles and a 4-entry LDS step
-// combine them in a fixed order, and the post step runs in the same
-// workgroup once the sums are known.
+// subset of a source's partials, and wavefront shuffles and a 4-entry LDS
+// step combine them in a fixed order.
 // ---------------------------------------------------------------------------
-enum Post { POST_NONE = 0, POST_CG_FIRST = 1, POST_CG = 2 };
-
-__global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__restrict__ scal, int post, int *__restrict__ active,
-                                                int *__restrict__ iters)
+__global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__restrict__ scal)
 {
     int s = blockIdx.x;
     __shared__ double sh[8][BLOCK / TILE];
@@ -30,14 +27,6 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
     // the first 4 strided partials of every source are loaded unconditionally
     // (predicated), the rest (scenes with more than 1024 partials) in a loop
     double part[8];
-    // the post step's inputs, fetched while the partials are in flight
-    double S0 = 0.0, S1 = 0.0, Sg = 0.0, Se = 0.0, Sm = 0.0;
-    int act = 0, it0 = 0;
-    if (threadIdx.x == 0 && post != POST_NONE) {
-        const double *Sp = scal + (size_t)s * NSLOT;
-        S0 = Sp[S_RZ]; S1 = Sp[S_ALPHA]; Sg = Sp[S_RZ_NEW]; Se = Sp[S_ETA2]; Sm = Sp[S_MAXIT];
-        act = active[s]; it0 = iters[s];
-    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         part[k] = 0.0;
@@ -78,37 +67,12 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
     if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], tot[0]) : S[a.slot] + tot[0]) : tot[0];
     if (a.slot1 >= 0) S[a.slot1] = tot[1];
     if (a.slot2 >= 0) S[a.slot2] = tot[2];
-    if (post == POST_NONE || !act) return;
-    // Conjugate gradients with one reduction per iteration (Chronopoulos and
-    // Gear): with gamma = r.z and delta = z.Az of the current residual,
-    //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
-    //   alpha = gamma / p.Ap.
-    // POST_CG: group 0 = gamma, 1 = delta, 2 = r.r; POST_CG_FIRST: group 1 =
-    // delta, gamma from the set-up reduction.
-    double gam = post == POST_CG ? tot[0] : Sg, del = tot[1], be = 0.0;
-    if (post == POST_CG) {
-        iters[s] = it0 + 1;
-        if (tot[2] <= Se || it0 + 1 >= (int)Sm) { active[s] = 0; return; }
-        be = gam / S0;
-        del -= be * gam / S1;
-    }
-    if (!(del > 0.0)) {   // not positive definite along the search direction: stop here
-        S[S_INDEF] = 1.0;
-        active[s] = 0;
-        return;
-    }
-    S[S_BETA] = be;
-    S[S_ALPHA] = gam / del;
-    S[S_RZ] = gam;
 }
 
-void reduce_post(ipc_ctx *c, const RedArgs &a, int post)
+void reduce(ipc_ctx *c, const RedArgs &a)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(c->n_scenes), dim3(BLOCK), 0, c->stream, c->n_scenes, a, c->d.scal.p, post, c->d.pcg_active.p,
-                       c->d.pcg_iters.p);
+    hipLaunchKernelGGL(k_reduce, dim3(c->n_scenes), dim3(BLOCK), 0, c->stream, c->n_scenes, a, c->d.scal.p);
 }
-
-void reduce(ipc_ctx *c, const RedArgs &a) { reduce_post(c, a, POST_NONE); }
 
 RedSrc src(const double *v, const int *seg, int off, int base)
 {
@@ -142,7 +106,7 @@ __device__ __forceinline__ void acc_block(const double *__restrict__ B, d3 w, do
 }
 
 template <int L>
-__global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, int nlong, const int *__restrict__ long_rows,
+__global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *__restrict__ nlong, const int *__restrict__ long_rows,
                                                  const int *__restrict__ row_ptr, const int *__restrict__ col,
                                                  const double *__restrict__ val, const int *__restrict__ dptr,
                                                  const int *__restrict__ dcol, const double *__restrict__ dval,
@@ -195,7 +159,7 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, int nlong, c
     // one workgroup per long row: all 64 L lanes stride over its blocks
     __shared__ double shl[3][NW];
     int w = (int)blockIdx.x - ntiles;
-    if (w >= nlong) return;
+    if (w >= nlong[0]) return;
     int n = long_rows[w];
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool on = !active || active[node_scene[n]];
@@ -225,9 +189,9 @@ static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const i
 {
     Dev &D = c->d;
     int ntiles = (c->N + TILE - 1) / TILE;
-    dim3 grid(ntiles + c->n_long), blk(64 * L);
+    dim3 grid(ntiles + c->long_cap), blk(64 * L);   // extra workgroups beyond the long-row count exit at once
     double *pl = part ? D.part_long.p : nullptr;
-#define IPC_SPMV(LL) hipLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, c->N, ntiles, c->n_long, D.long_rows.p, D.row_ptr.p, D.col.p, \
+#define IPC_SPMV(LL) hipLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, c->N, ntiles, D.long_count.p, D.long_rows.p, D.row_ptr.p, D.col.p, \
                                         D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, v, D.node_scene.p, active, out, part, pl)
     switch (L) {
     case 1: IPC_SPMV(1); break;
@@ -369,262 +333,401 @@ void build_preconditioner(ipc_ctx *c)
 }
 
 // ---------------------------------------------------------------------------
-// PCG kernels (preconditioned conjugate gradients in the single-reduction
-// form of Chronopoulos and Gear: besides p it carries s = A p, so that one
-// product w = A z and one per-scene reduction per iteration suffice)
+// PCG (preconditioned conjugate gradients in the single-reduction form of
+// Chronopoulos and Gear: besides p it carries s = A p, so that one product
+// w = A z and one per-scene reduction per iteration suffice).
+//
+// An iteration is two launches: k_pcg_step, whose workgroups first reduce
+// their scenes' partials of the previous iteration themselves (every
+// workgroup of a scene sums the same partials in the same order, so all of
+// them obtain bit-identical scalars) and then update p, s, x, r, z; and the
+// product w = A z with its partials of z . w.  The per-scene state (gamma,
+// alpha, eta^2 b.b, r.r, running flag, update count) and the partials of
+// r.z and r.r are double-buffered by iteration parity: the step of
+// iteration k reads buffer k & 1, and the workgroup holding the scene's
+// first tile writes buffer (k + 1) & 1, so no launch reads what it writes.
 // ---------------------------------------------------------------------------
-// x = 0, r = b, p = s = 0, z = M^-1 r (FEM nodes); partials of b.b and r.z
-__global__ void k_pcg_init(int N, const int *__restrict__ kind, const double *__restrict__ b, const double *__restrict__ dinv,
-                           double *__restrict__ x, double *__restrict__ r, double *__restrict__ z, double *__restrict__ p,
-                           double *__restrict__ s, double *__restrict__ part_bb, double *__restrict__ part_rz)
+constexpr int WG_TILES = BLOCK / TILE;   // node tiles per step workgroup
+
+// Sums of up to three per-tile sources and one per-long-row source over a
+// scene's ranges; every thread of the workgroup returns the same totals.
+__device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, const double *__restrict__ a, const double *__restrict__ b,
+                                           const double *__restrict__ c, const double *__restrict__ cl, double (*sh)[WG_TILES],
+                                           double &ta, double &tb, double &tc)
+{
+    double va = 0.0, vb = 0.0, vc = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += BLOCK) {
+        va += a[i];
+        vb += b[i];
+        if (c) vc += c[i];
+    }
+    if (cl)
+        for (int i = llo + (int)threadIdx.x; i < lhi; i += BLOCK) vc += cl[i];
+    va = wave_sum(va); vb = wave_sum(vb); vc = wave_sum(vc);
+    int wave = threadIdx.x / TILE;
+    if ((threadIdx.x & (TILE - 1)) == 0) { sh[0][wave] = va; sh[1][wave] = vb; sh[2][wave] = vc; }
+    __syncthreads();
+    ta = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    tb = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    tc = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
+    __syncthreads();
+}
+
+__device__ __forceinline__ d3 mat3v(const double *__restrict__ M, d3 v)
+{
+    return {M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z, M[6] * v.x + M[7] * v.y + M[8] * v.z};
+}
+
+// x = 0, r = b, p = s = 0, z = M^-1 r; partials of r.z and r.r per tile
+// (affine bodies: the thread of the body's first node applies its 12x12
+// block); each scene's first-tile thread sets the parity-0 state, with the
+// relative tolerance (eta, or the scene's own when eta <= 0) in the eta^2
+// b.b entry until the first step.
+__global__ void __launch_bounds__(BLOCK) k_pcg_init(int N, int ns, const int *__restrict__ kind, const int *__restrict__ node_body,
+                                                    const int *__restrict__ tile_scene, const int *__restrict__ seg_nodew,
+                                                    const double *__restrict__ b, const double *__restrict__ dinv,
+                                                    const double *__restrict__ dinvB, double *__restrict__ x, double *__restrict__ r,
+                                                    double *__restrict__ z, double *__restrict__ p, double *__restrict__ s,
+                                                    double *__restrict__ part, int ntile, const int *__restrict__ want,
+                                                    double eta, const double *__restrict__ sparam, double *__restrict__ st,
+                                                    double *__restrict__ prev_rr,
+                                                    int *__restrict__ act, int *__restrict__ it, int *__restrict__ iters,
+                                                    double *__restrict__ scal)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
-    double bb = 0.0, rz = 0.0;
+    double rz = 0.0, rr = 0.0;
     if (n < N) {
         d3 bv = ld3(b, n);
         st3(x, n, {0.0, 0.0, 0.0});
         st3(p, n, {0.0, 0.0, 0.0});
         st3(s, n, {0.0, 0.0, 0.0});
         st3(r, n, bv);
-        bb = dt(bv, bv);
-        d3 zv = {0, 0, 0};
-        if (kind[n] == 0) {
-            const double *M = dinv + 9 * (size_t)n;
-            zv = {M[0] * bv.x + M[1] * bv.y + M[2] * bv.z, M[3] * bv.x + M[4] * bv.y + M[5] * bv.z, M[6] * bv.x + M[7] * bv.y + M[8] * bv.z};
+        int k = kind[n];
+        if (k == 0) {
+            d3 zv = mat3v(dinv + 9 * (size_t)n, bv);
+            st3(z, n, zv);
             rz = dt(bv, zv);
-        }
-        st3(z, n, zv);
-    }
-    bb = wave_sum(bb); rz = wave_sum(rz);
-    if ((threadIdx.x & (TILE - 1)) == 0 && n < N) { part_bb[n / TILE] = bb; part_rz[n / TILE] = rz; }
-}
-
-// z = M^-1 r on body nodes; partial r.z per body
-__global__ void k_body_prec_apply(int NB, const int *__restrict__ node0, const double *__restrict__ dinvB, const double *__restrict__ r,
-                                  double *__restrict__ z, double *__restrict__ part)
-{
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= NB) return;
-    int n0 = node0[b];
-    const double *rv = r + 3 * (size_t)n0;
-    const double *M = dinvB + 144 * (size_t)b;
-    double rz = 0.0;
-    for (int i = 0; i < 12; ++i) {
-        double acc = 0.0;
-        for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rv[j];
-        z[3 * (size_t)n0 + i] = acc;
-        rz += rv[i] * acc;
-    }
-    part[b] = rz;
-}
-
-// p = z + beta p; s = w + beta s; x += alpha p; r -= alpha s; z = M^-1 r,
-// with partials of r.z and r.r.  Workgroups [0, nnode_blocks) take FEM and
-// padding nodes, one thread per node; the rest take one affine body per
-// thread (its 4 nodes and its 12x12 inverse block).
-__global__ void k_pcg_update(int N, int nnode_blocks, int NB, const int *__restrict__ kind, const int *__restrict__ node_scene,
-                             const int *__restrict__ active, const double *__restrict__ scal, const double *__restrict__ dinv,
-                             const double *__restrict__ dinvB, const int *__restrict__ body_node0, const int *__restrict__ body_scene,
-                             const double *__restrict__ w, double *__restrict__ p, double *__restrict__ s, double *__restrict__ x,
-                             double *__restrict__ r, double *__restrict__ z, double *__restrict__ part_rz, double *__restrict__ part_rr,
-                             double *__restrict__ bpart_rz, double *__restrict__ bpart_rr)
-{
-    if ((int)blockIdx.x < nnode_blocks) {
-        int n = blockIdx.x * blockDim.x + threadIdx.x;
-        double rz = 0.0, rr = 0.0;
-        if (n < N && kind[n] == 0) {
-            int sc = node_scene[n];
-            if (active[sc]) {
-                const double *S = scal + (size_t)sc * NSLOT;
-                double al = S[S_ALPHA], be = S[S_BETA];
-                d3 zv = ld3(z, n), pv = ld3(p, n), wv = ld3(w, n), sv = ld3(s, n), xv = ld3(x, n), rv = ld3(r, n);
-                pv = {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z};
-                sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
-                xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
-                rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
-                const double *M = dinv + 9 * (size_t)n;
-                zv = {M[0] * rv.x + M[1] * rv.y + M[2] * rv.z, M[3] * rv.x + M[4] * rv.y + M[5] * rv.z, M[6] * rv.x + M[7] * rv.y + M[8] * rv.z};
-                st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv); st3(z, n, zv);
-                rr = dt(rv, rv);
-                rz = dt(rv, zv);
-            }
-        }
-        rz = wave_sum(rz); rr = wave_sum(rr);
-        if ((threadIdx.x & (TILE - 1)) == 0 && n < N) { part_rz[n / TILE] = rz; part_rr[n / TILE] = rr; }
-    } else {
-        int b = (blockIdx.x - nnode_blocks) * blockDim.x + threadIdx.x;
-        if (b >= NB) return;
-        double rz = 0.0, rr = 0.0;
-        int sc = body_scene[b];
-        if (active[sc]) {
-            const double *S = scal + (size_t)sc * NSLOT;
-            double al = S[S_ALPHA], be = S[S_BETA];
-            size_t o = 3 * (size_t)body_node0[b];
-            double rv[12];
-            for (int i = 0; i < 12; ++i) {
-                double pi = z[o + i] + be * p[o + i];
-                double si = w[o + i] + be * s[o + i];
-                p[o + i] = pi;
-                s[o + i] = si;
-                x[o + i] += al * pi;
-                rv[i] = r[o + i] - al * si;
-                r[o + i] = rv[i];
-                rr += rv[i] * rv[i];
-            }
-            const double *M = dinvB + 144 * (size_t)b;
+            rr = dt(bv, bv);
+        } else if (k == 2) {
+            st3(z, n, {0.0, 0.0, 0.0});
+        } else if (node_body[n] >= 0) {
+            const double *bb = b + 3 * (size_t)n;
+            const double *M = dinvB + 144 * (size_t)node_body[n];
             for (int i = 0; i < 12; ++i) {
                 double acc = 0.0;
-                for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rv[j];
-                z[o + i] = acc;
-                rz += rv[i] * acc;
+                for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * bb[j];
+                z[3 * (size_t)n + i] = acc;
+                rz += bb[i] * acc;
+                rr += bb[i] * bb[i];
             }
         }
-        bpart_rz[b] = rz;
-        bpart_rr[b] = rr;
+    }
+    rz = wave_sum(rz); rr = wave_sum(rr);
+    if ((threadIdx.x & (TILE - 1)) == 0 && n < N) {
+        int t = n / TILE;
+        part[t] = rz;
+        part[ntile + t] = rr;
+        int sc = tile_scene[t];
+        if (seg_nodew[sc] == t) {
+            act[sc] = (!want || want[sc]) ? 2 : 0;
+            it[sc] = 0;
+            st[4 * (size_t)sc + 2] = eta > 0.0 ? eta : sparam[8 * (size_t)sc + P_ETA];   // the first step squares it and scales by b.b
+            prev_rr[sc] = -1.0;
+            iters[sc] = 0;
+            scal[(size_t)sc * NSLOT + S_INDEF] = 0.0;
+        }
     }
 }
 
-__global__ void k_pcg_start(int ns, double *__restrict__ scal, int *__restrict__ active, int *__restrict__ iters, double eta,
-                            const int *__restrict__ maxit, const int *__restrict__ want)
+// One iteration, parity q.  State per scene and parity: st[4] = {gamma,
+// alpha, eta^2 b.b, r.r}, act (0 stopped, 1 running, 2 first iteration), it
+// (updates done).  part holds [r.z | r.r] for parity 0 then parity 1.
+__global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const int *__restrict__ kind, const int *__restrict__ node_body,
+                                                    const int *__restrict__ tile_scene, const int *__restrict__ seg_nodew,
+                                                    const int *__restrict__ seg_long, const int *__restrict__ maxit,
+                                                    const double *__restrict__ dinv,
+                                                    const double *__restrict__ dinvB, const double *__restrict__ w, double *__restrict__ p,
+                                                    double *__restrict__ s, double *__restrict__ x, double *__restrict__ r,
+                                                    double *__restrict__ z, const double *__restrict__ part_zw,
+                                                    const double *__restrict__ part_long, double *__restrict__ part, int ntile,
+                                                    double *__restrict__ st, int *__restrict__ act, int *__restrict__ it,
+                                                    double *__restrict__ scal)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= ns) return;
-    double *S = scal + (size_t)s * NSLOT;
-    iters[s] = 0;
-    double e = eta > 0.0 ? eta : S[S_ETA];
-    S[S_ETA2] = e * e * S[S_BB];
-    S[S_MAXIT] = (double)maxit[s];
-    S[S_INDEF] = 0.0;
-    active[s] = (want ? want[s] : 1) && S[S_BB] > 0.0 ? 1 : 0;
+    __shared__ double sh[3][WG_TILES];
+    const int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
+    const int t0 = blockIdx.x * WG_TILES, t = t0 + wave;
+    const int n = t * TILE + lane;
+    // this node's operands first: their loads overlap the reductions below
+    int k = 2;
+    d3 zv{}, pv{}, wv{}, sv{}, xv{}, rv{};
+    if (n < N) {
+        k = kind[n];
+        if (k == 0) { zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n); }
+    }
+    const double *rz_in = part + (size_t)(2 * q) * ntile, *rr_in = rz_in + ntile;
+    double *rz_out = part + (size_t)(2 * (q ^ 1)) * ntile, *rr_out = rz_out + ntile;
+    const int sc_lo = tile_scene[t0], sc_hi = tile_scene[min(t0 + WG_TILES, ntile) - 1];
+    const int my_sc = t < ntile ? tile_scene[t] : -1;
+    double al = 0.0, be = 0.0;
+    bool on = false;
+    for (int sc = sc_lo; sc <= sc_hi; ++sc) {   // uniform over the workgroup
+        const int a = act[q * ns + sc], itc = it[q * ns + sc];
+        const double *S = st + ((size_t)q * ns + sc) * 4;
+        const bool writer = seg_nodew[sc] / WG_TILES == (int)blockIdx.x && threadIdx.x == 0;
+        double *So = st + ((size_t)(q ^ 1) * ns + sc) * 4;
+        if (!a) {
+            if (writer) {
+                So[0] = S[0]; So[1] = S[1]; So[2] = S[2]; So[3] = S[3];
+                act[(q ^ 1) * ns + sc] = 0;
+                it[(q ^ 1) * ns + sc] = itc;
+            }
+            continue;
+        }
+        double gam, rr, del;
+        block_sums(seg_nodew[sc], seg_nodew[sc + 1], seg_long[sc], seg_long[sc + 1], rz_in, rr_in, part_zw, part_long, sh, gam, rr, del);
+        // gamma = r.z, delta = z.Az of the current residual:
+        //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
+        //   alpha = gamma / p.Ap
+        double eta2, bs = 0.0;
+        int na = 1;
+        bool indef = false;
+        if (a == 2) {
+            eta2 = S[2] * S[2] * rr;
+            if (!(rr > 0.0)) na = 0;
+        } else {
+            eta2 = S[2];
+            if (rr <= eta2 || itc >= maxit[sc]) na = 0;
+            else {
+                bs = gam / S[0];
+                del -= bs * gam / S[1];
+            }
+        }
+        if (na && !(del > 0.0)) { na = 0; indef = true; }   // not positive definite along p: stop
+        const double as = na ? gam / del : 0.0;
+        if (writer) {
+            So[0] = gam; So[1] = as; So[2] = eta2; So[3] = rr;
+            act[(q ^ 1) * ns + sc] = na;
+            it[(q ^ 1) * ns + sc] = itc + na;
+            if (indef) scal[(size_t)sc * NSLOT + S_INDEF] = 1.0;
+        }
+        if (sc == my_sc) { on = na; al = as; be = bs; }
+    }
+    double rz = 0.0, rr = 0.0;
+    if (on && k == 0) {
+        pv = {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z};
+        sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
+        xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
+        rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
+        zv = mat3v(dinv + 9 * (size_t)n, rv);
+        st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv); st3(z, n, zv);
+        rr = dt(rv, rv);
+        rz = dt(rv, zv);
+    } else if (on && k == 1 && node_body[n] >= 0) {
+        // the body's 4 nodes (12 DOFs) and its 12x12 inverse block
+        size_t o = 3 * (size_t)n;
+        double rb[12];
+        for (int i = 0; i < 12; ++i) {
+            double pi = z[o + i] + be * p[o + i];
+            double si = w[o + i] + be * s[o + i];
+            p[o + i] = pi;
+            s[o + i] = si;
+            x[o + i] += al * pi;
+            rb[i] = r[o + i] - al * si;
+            r[o + i] = rb[i];
+            rr += rb[i] * rb[i];
+        }
+        const double *M = dinvB + 144 * (size_t)node_body[n];
+        for (int i = 0; i < 12; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rb[j];
+            z[o + i] = acc;
+            rz += rb[i] * acc;
+        }
+    }
+    rz = wave_sum(rz); rr = wave_sum(rr);
+    if (lane == 0 && t < ntile) { rz_out[t] = rz; rr_out[t] = rr; }
 }
 
-// Bytes one update pass moves: 6 node vectors read and 5 written (24 B
-// each) plus the 3x3 inverse block per FEM vertex; 12x12 blocks per body.
+// After a batch of iterations (parity q): per scene, whether the next step
+// would still iterate (the same sums and test as the step) and, if so, an
+// estimate of the iterations left from the residual's geometric decay over
+// the batch (n_since iterations; 2^20 when unknown), published to host memory
+// as one 64-bit word (seq << 32 | estimate, 0 = stopped) that the host polls;
+// also the update count.
+constexpr int PCG_EST_UNKNOWN = 1 << 20;
+__global__ void __launch_bounds__(BLOCK) k_pcg_peek(int ns, int q, const int *__restrict__ seg_nodew, const int *__restrict__ maxit,
+                                                    const double *__restrict__ part, int ntile, const double *__restrict__ st,
+                                                    const int *__restrict__ act, const int *__restrict__ it,
+                                                    double *__restrict__ prev_rr, int n_since, unsigned int seq,
+                                                    unsigned long long *__restrict__ out, int *__restrict__ iters)
+{
+    __shared__ double sh[3][WG_TILES];
+    int sc = blockIdx.x;
+    int a = act[q * ns + sc], itc = it[q * ns + sc];
+    double rr = 0.0;
+    bool live = false;
+    if (a) {
+        const double *rz_in = part + (size_t)(2 * q) * ntile;
+        double g, d;
+        block_sums(seg_nodew[sc], seg_nodew[sc + 1], 0, 0, rz_in, rz_in + ntile, nullptr, nullptr, sh, g, rr, d);
+        live = a == 2 || !(rr <= st[((size_t)q * ns + sc) * 4 + 2] || itc >= maxit[sc]);
+    }
+    if (threadIdx.x != 0) return;
+    iters[sc] = itc;
+    int est = 0;
+    if (live) {
+        est = PCG_EST_UNKNOWN;
+        double pr = prev_rr[sc], e2 = a == 2 ? 0.0 : st[((size_t)q * ns + sc) * 4 + 2];
+        if (pr > 0.0 && rr > 0.0 && e2 > 0.0 && rr < pr && n_since > 0) {
+            double rate = log(pr / rr) / n_since, k = ceil(log(rr / e2) / rate);
+            est = k < (double)PCG_EST_UNKNOWN ? (int)fmax(k, 1.0) : PCG_EST_UNKNOWN;
+        }
+        prev_rr[sc] = rr;
+    }
+    out[sc] = ((unsigned long long)seq << 32) | (unsigned int)est;
+}
+
+// Bytes one step pass moves: 6 node vectors read and 5 written (24 B each)
+// plus the 3x3 inverse block per FEM vertex; 12x12 blocks per body.
 static double update_bytes(const ipc_ctx *c) { return (264.0 + 72.0) * c->NFEM + (4 * 264.0 + 1152.0) * c->NB; }
 
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want)
 {
     Dev &D = c->d;
     hipStream_t st = c->stream;
-    int ns = c->n_scenes;
-    int *active = D.pcg_active.p;
+    const int ns = c->n_scenes, ntile = c->N / TILE;
     double *r = D.r.p, *z = D.z.p, *p = D.p.p, *s = D.q.p, *w = D.w.p;
-    D.part_node3.alloc(c->N / TILE + 1);
-    D.part_long.alloc(c->n_long + 1);
-    hipLaunchKernelGGL(k_pcg_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, b, D.dinv.p, x, r, z, p, s,
-                       D.part_node.p, D.part_node2.p);
-    if (c->NB)
-        hipLaunchKernelGGL(k_body_prec_apply, dim3(blocks_for(c->NB, 64)), dim3(64), 0, st, c->NB, D.body_node0.p, D.dinvB.p, r, z,
-                           D.body_part.p);
-    {
-        RedArgs a{};
-        a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 0;
-        a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 1;
-        a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.grp[a.nsrc++] = 1;
-        a.slot = S_BB;
-        a.slot1 = S_RZ_NEW;
-        reduce(c, a);
-    }
-    hipLaunchKernelGGL(k_pcg_start, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.scal.p, active, D.pcg_iters.p, eta, D.maxpcg.p,
-                       want);
-    // first product and step length
-    auto product = [&](int post) {
-        hess_apply(c, z, w, active, D.part_node3.p);
-        RedArgs a{};
-        if (post == POST_CG) {
-            a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 0;
-            a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.grp[a.nsrc++] = 0;
-            a.src[a.nsrc] = src(D.part_node2.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 2;
-            a.src[a.nsrc] = src(c->NB ? D.body_part2.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.grp[a.nsrc++] = 2;
-            a.slot = S_RZ_NEW;
-            a.slot2 = S_RR;
-        }
-        a.src[a.nsrc] = src(D.part_node3.p, seg_ptr(c, R_NODEW), 0, 0); a.grp[a.nsrc++] = 1;
-        a.src[a.nsrc] = src(c->n_long ? D.part_long.p : nullptr, seg_ptr(c, R_LONG), 0, 0); a.grp[a.nsrc++] = 1;
-        a.slot1 = S_PAP;
-        reduce_post(c, a, post);
-    };
-    product(POST_CG_FIRST);
+    D.part_node3.alloc(ntile + 1);
+    D.part_long.alloc(c->long_cap + 1);
+    D.pcg_part.alloc(4 * (size_t)ntile + 1);
+    D.pcg_st.alloc(8 * (size_t)ns);
+    D.pcg_act.alloc(2 * (size_t)ns);
+    D.pcg_it.alloc(2 * (size_t)ns);
+    D.pcg_prev.alloc(ns);
+    int *act = D.pcg_act.p;
+    hipLaunchKernelGGL(k_pcg_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, ns, D.node_kind.p, D.node_body.p,
+                       D.tile_scene_node.p, seg_ptr(c, R_NODEW), b, D.dinv.p, D.dinvB.p, x, r, z, p, s, D.pcg_part.p, ntile, want, eta,
+                       D.sparam.p, D.pcg_st.p, D.pcg_prev.p, act, D.pcg_it.p, D.pcg_iters.p, D.scal.p);
+    hess_apply(c, z, w, act, D.part_node3.p);   // w = A z and z . w for the first step
     int maxit = 0;
     for (auto &S : c->sc) maxit = std::max(maxit, S.max_pcg);
-    std::vector<int> hact(ns);
-    // one iteration; every kernel skips scenes whose flag is down, so extra
-    // iterations after convergence change nothing
-    auto iteration = [&]() {
-        int nnb = blocks_for(c->N), nbb = blocks_for(c->NB);
+    // one iteration of parity q; every kernel skips scenes that stopped, so
+    // extra iterations after convergence change nothing
+    auto iteration = [&](int q) {
         prof_begin(c, IPC_K_PCG_UPDATE);
-        hipLaunchKernelGGL(k_pcg_update, dim3(nnb + nbb), dim3(BLOCK), 0, c->stream, c->N, nnb, c->NB, D.node_kind.p, D.node_scene.p,
-                           active, D.scal.p, D.dinv.p, D.dinvB.p, D.body_node0.p, D.body_scene.p, w, p, s, x, r, z, D.part_node.p,
-                           D.part_node2.p, D.body_part.p, D.body_part2.p);
+        hipLaunchKernelGGL(k_pcg_step, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p, D.node_body.p,
+                           D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
+                           r, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
-        product(POST_CG);
+        hess_apply(c, z, w, act + (q ^ 1) * ns, D.part_node3.p);
     };
-    // Host view after a batch: the active flags and, per active scene, an
-    // estimate of the iterations left from the residual's geometric decay
-    // since the previous check (capped; unknown on the first check).
-    std::vector<double> hs((size_t)ns * NSLOT), prev_rr(ns, -1.0);
-    auto check = [&](int done_since) {
-        IPC_HIP(hipMemcpyAsync(hact.data(), active, ns * sizeof(int), hipMemcpyDeviceToHost, st));
-        IPC_HIP(hipMemcpyAsync(hs.data(), D.scal.p, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        IPC_HIP(hipStreamSynchronize(st));
-        int left = 0;
-        bool any = false;
-        for (int q = 0; q < ns; ++q) {
-            if (!hact[q]) continue;
-            any = true;
-            double rr = hs[(size_t)q * NSLOT + S_RR], e2 = hs[(size_t)q * NSLOT + S_ETA2];
-            int est = 1 << 20;
-            if (prev_rr[q] > 0.0 && rr > 0.0 && rr < prev_rr[q] && done_since > 0) {
-                double rate = std::log(prev_rr[q] / rr) / done_since;
-                est = (int)std::ceil(std::log(rr / e2) / rate);
-            }
-            prev_rr[q] = rr;
-            left = std::max(left, est);
-        }
-        return any ? std::max(left, 1) : 0;
-    };
-    const int KB = 16, KS = 4;   // iterations per batch: far from and near convergence
-    if (c->use_graphs && !c->prof) {
-        // Capture a long and a short batch of iterations once per solve on the
-        // context's capture stream (the caller's stream may be the null
-        // stream, which cannot capture) and replay them on the context's
-        // stream, the short one once few iterations are predicted to remain.
-        IPC_HIP(hipStreamSynchronize(st));
-        hipGraphExec_t exec[2] = {nullptr, nullptr};
-        const int Ks[2] = {KB, KS};
-        hipError_t e = hipSuccess;
-        for (int g = 0; g < 2 && e == hipSuccess; ++g) {
-            hipGraph_t graph = nullptr;
-            c->stream = c->cap_stream;
-            e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                for (int k = 0; k < Ks[g]; ++k) iteration();
-                e = hipStreamEndCapture(c->cap_stream, &graph);
-            }
-            c->stream = st;
-            if (e == hipSuccess) {
-                e = hipGraphInstantiate(&exec[g], graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-            }
-        }
-        hipError_t le = e;
-        int it = 0, left = 1 << 20;
-        while (le == hipSuccess && it < maxit && left > 0) {
-            int g = left > KB ? 0 : 1;
-            le = hipGraphLaunch(exec[g], st);
-            if (le != hipSuccess) break;
-            it += Ks[g];
-            left = check(Ks[g]);
-        }
-        for (auto &x : exec) if (x) (void)hipGraphExecDestroy(x);
-        IPC_HIP(le);
-        return;
+    // The peek kernel publishes one word per scene into pinned, coherent host
+    // memory, which the host polls: no event and no stream synchronisation
+    // per batch.  If the words do not appear within a second the host
+    // synchronises the stream (which also reports a failed launch) and reads
+    // them again.
+    if (!c->h_peek) {
+        IPC_HIP(hipHostMalloc((void **)&c->h_peek, 2 * (size_t)ns * sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent));
+        IPC_HIP(hipHostGetDevicePointer((void **)&c->h_peek_dev, c->h_peek, 0));
+        for (size_t i = 0; i < 2 * (size_t)ns; ++i) c->h_peek[i] = 0;
     }
-    for (int it = 0, since = 0; it < maxit; ++it) {
-        iteration();
-        ++since;
-        if ((since == KS || it + 1 == maxit) && !check(since)) break;
-        if (since == KS) since = 0;
+    auto peek = [&](int q, int slot, int n_since) {
+        unsigned int seq = ++c->peek_seq;
+        if (seq == 0) seq = ++c->peek_seq;   // 0 never names a peek
+        hipLaunchKernelGGL(k_pcg_peek, dim3(ns), dim3(BLOCK), 0, st, ns, q, seg_ptr(c, R_NODEW), D.maxpcg.p, D.pcg_part.p, ntile,
+                           D.pcg_st.p, act, D.pcg_it.p, D.pcg_prev.p, n_since, seq, c->h_peek_dev + (size_t)ns * slot,
+                           D.pcg_iters.p);
+        return seq;
+    };
+    // 0 when no scene iterates any more, else the largest estimate
+    auto await = [&](int slot, unsigned int seq) {
+        volatile unsigned long long *wv = c->h_peek + (size_t)ns * slot;
+        auto ready = [&]() {
+            for (int k = 0; k < ns; ++k)
+                if ((unsigned int)(wv[k] >> 32) != seq) return false;
+            return true;
+        };
+        auto t0 = std::chrono::steady_clock::now();
+        while (!ready()) {
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+                IPC_HIP(hipStreamSynchronize(st));
+                if (!ready()) throw Error(IPC_E_DEVICE, "PCG progress words did not reach host memory");
+                break;
+            }
+        }
+        int left = 0;
+        for (int k = 0; k < ns; ++k) left = std::max(left, (int)(unsigned int)(wv[k] & 0xffffffffull));
+        return left;
+    };
+    const int KB = 16, KS = 4;   // iterations per batch (even): far from and near convergence
+    const int Ks[2] = {KB, KS};
+    // Two copies of a long and of a short batch of iterations, captured on
+    // the context's capture stream (the caller's stream may be the null
+    // stream, which cannot capture) and kept while the arguments they were
+    // captured with stay the same; consecutive replays of one batch length
+    // alternate between the copies, so a replay never waits for the previous
+    // replay of the same executable.  Both lengths are even, so every replay
+    // starts at parity 0.
+    const bool graphs = c->use_graphs && !c->prof;
+    if (graphs) {
+        std::vector<uintptr_t> key = {(uintptr_t)c->N, (uintptr_t)ns, (uintptr_t)c->spmv_lanes, (uintptr_t)c->long_cap,
+                                      (uintptr_t)D.node_kind.p, (uintptr_t)D.node_body.p, (uintptr_t)D.tile_scene_node.p,
+                                      (uintptr_t)D.segs.p, (uintptr_t)D.maxpcg.p, (uintptr_t)D.dinv.p, (uintptr_t)D.dinvB.p, (uintptr_t)w,
+                                      (uintptr_t)p, (uintptr_t)s, (uintptr_t)x, (uintptr_t)r, (uintptr_t)z, (uintptr_t)D.part_node3.p,
+                                      (uintptr_t)D.part_long.p, (uintptr_t)D.pcg_part.p, (uintptr_t)D.pcg_st.p, (uintptr_t)act,
+                                      (uintptr_t)D.pcg_it.p, (uintptr_t)D.scal.p, (uintptr_t)D.long_count.p, (uintptr_t)D.long_rows.p,
+                                      (uintptr_t)D.row_ptr.p, (uintptr_t)D.col.p, (uintptr_t)D.val.p, (uintptr_t)D.dyn_ptr.p,
+                                      (uintptr_t)D.dyn_col.p, (uintptr_t)D.dyn_val.p, (uintptr_t)D.node_scene.p};
+        bool have = key == c->pcg_key;
+        for (auto xg : c->pcg_exec) have = have && xg;
+        if (!have) {
+            for (auto &xg : c->pcg_exec) if (xg) { (void)hipGraphExecDestroy(xg); xg = nullptr; }
+            c->pcg_key.clear();
+            hipError_t e = hipSuccess;
+            for (int g = 0; g < 4 && e == hipSuccess; ++g) {
+                hipGraph_t graph = nullptr;
+                c->stream = c->cap_stream;
+                e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    for (int k = 0; k < Ks[g / 2]; ++k) iteration(k & 1);
+                    e = hipStreamEndCapture(c->cap_stream, &graph);
+                }
+                c->stream = st;
+                if (e == hipSuccess) {
+                    e = hipGraphInstantiate(&c->pcg_exec[g], graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                }
+            }
+            IPC_HIP(e);
+            c->pcg_key = key;
+        }
+    }
+    // Batches are pipelined: each batch is followed by a peek whose result
+    // lands in host memory behind an event, and while the estimate asks for
+    // more iterations than are already in flight, a second batch is queued
+    // before the host waits for the first one's peek.  A batch queued past
+    // convergence does nothing.
+    int launched = 0, nb = 0, k_done = 0, inflight = 0, size_of[2] = {0, 0}, replays[2] = {0, 0};
+    unsigned int seq_of[2] = {0, 0};
+    int left = PCG_EST_UNKNOWN;
+    auto launch_batch = [&](int g) {
+        if (graphs) IPC_HIP(hipGraphLaunch(c->pcg_exec[2 * g + (replays[g]++ & 1)], st));
+        else for (int k = 0; k < Ks[g]; ++k) iteration(k & 1);
+        int slot = nb & 1;
+        seq_of[slot] = peek(0, slot, Ks[g]);
+        size_of[slot] = Ks[g];
+        launched += Ks[g];
+        inflight += Ks[g];
+        ++nb;
+    };
+    while (true) {
+        if (nb - k_done < 2 && launched < maxit && left > inflight) launch_batch(left - inflight > KB ? 0 : 1);
+        if (k_done == nb) break;   // nothing in flight: the iteration cap is reached
+        int slot = k_done & 1;
+        left = await(slot, seq_of[slot]);
+        inflight -= size_of[slot];
+        ++k_done;
+        if (left == 0) break;
     }
 }
 
