@@ -127,6 +127,30 @@ __global__ void k_prim_box(int P, int kind, const int4 *__restrict__ tri, const 
     id[i] = i;
 }
 
+// Morton keys of the surface-vertex queries (centre of the swept point, or the
+// point itself when there is no end position: xw1 = nullptr), so that
+// neighbouring lanes of a wavefront traverse neighbouring parts of the tree;
+// the scene id sits above the code as for the leaves.
+__global__ void k_query_keys(int Q, const int *__restrict__ cv_scene, const double *__restrict__ xw0, const double *__restrict__ xw1,
+                             const double *__restrict__ sbox, unsigned long long *__restrict__ key, int *__restrict__ id)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q) return;
+    int s = cv_scene[i];
+    const double *sb = sbox + 6 * (size_t)s;
+    unsigned int q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double x0 = xw0[3 * (size_t)i + k], x1 = xw1 ? xw1[3 * (size_t)i + k] : x0;
+        double cc = (0.5 * (x0 + x1) - sb[k]) * sb[3 + k];
+        cc = fmin(fmax(cc, 0.0), 1023.0);
+        q[k] = (unsigned int)cc;
+    }
+    unsigned int m = (expand_bits(q[0]) << 2) | (expand_bits(q[1]) << 1) | expand_bits(q[2]);
+    key[i] = ((unsigned long long)s << 32) | m;
+    id[i] = i;
+}
+
 __device__ __forceinline__ int lcp(const unsigned long long *key, int base, int n, int a, int b)
 {
     if (b < 0 || b >= n) return -1;
@@ -188,13 +212,19 @@ __device__ __forceinline__ void box_empty(double *a)
     for (int m = 0; m < 3; ++m) { a[m] = INFINITY; a[3 + m] = -INFINITY; }
 }
 
-// level 0: the leaf boxes in sorted order
-__global__ void k_seg_leaves(int P, const int *__restrict__ sorted_id, const double *__restrict__ pbox, double *__restrict__ lev)
+// level 0: the leaf boxes in sorted order, and 1 for every sorted leaf whose
+// primitive is not static (its object moves)
+__global__ void k_seg_leaves(int P, int kind, const int *__restrict__ sorted_id, const double *__restrict__ pbox,
+                             const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_obj,
+                             const int *__restrict__ okind, double *__restrict__ lev, int *__restrict__ moving)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
-    const double *b = pbox + 6 * (size_t)sorted_id[i];
+    int pid = sorted_id[i];
+    const double *b = pbox + 6 * (size_t)pid;
     for (int m = 0; m < 6; ++m) lev[6 * (size_t)i + m] = b[m];
+    int o = cv_obj[kind == 0 ? tri[pid].x : edge[pid].x];
+    moving[i] = (o >= 0 ? okind[o] : 2) != 2 ? 1 : 0;
 }
 
 // levels j0+1 .. j0+8 from level j0 (256 inputs per workgroup)
@@ -222,13 +252,16 @@ __global__ void __launch_bounds__(256) k_seg_up(SegLevels L, int j0, double *__r
     }
 }
 
-// every internal node: the union over its leaf range [lo, hi]
-__global__ void k_node_box(int P, SegLevels L, const double *__restrict__ lev, const int2 *__restrict__ range, double *__restrict__ nbox)
+// every internal node: the union over its leaf range [lo, hi], and whether
+// the range holds a moving primitive (from the exclusive scan of the flags)
+__global__ void k_node_box(int P, SegLevels L, const double *__restrict__ lev, const int2 *__restrict__ range,
+                           const int *__restrict__ moving_scan, double *__restrict__ nbox, int *__restrict__ nmoving)
 {
     int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= P) return;
     int2 rg = range[gi];
     if (rg.x < 0) return;
+    nmoving[gi] = moving_scan[rg.y + 1] - moving_scan[rg.x] > 0 ? 1 : 0;
     double acc[6];
     box_empty(acc);
     int l = rg.x, r = rg.y + 1;
@@ -240,22 +273,33 @@ __global__ void k_node_box(int P, SegLevels L, const double *__restrict__ lev, c
 }
 
 // Queries.  kind 0: surface vertex vs triangle tree; kind 1: edge vs edge tree.
-// WRITE = false counts and stashes the first TRAV_STASH candidates of each
-// query (the common case needs no second traversal: a compaction copies the
-// stash); WRITE = true writes every candidate at off[q] when some query had
-// more.
-constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64, TRAV_STASH = 8;
+// Thread t takes query perm[t] (Morton order).  WRITE = false counts and
+// stashes the first TRAV_STASH candidates of each query; WRITE = true writes
+// every candidate at off[q]: from the stash when it held them all, else by
+// traversing again (with stash = nullptr: always traversing).
+constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64, TRAV_STASH = 16;
 template <bool WRITE>
 __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const int2 *__restrict__ qedge, const int *__restrict__ cv_scene,
                            const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_obj,
                            const int *__restrict__ okind, const int *__restrict__ excl, int nex, const double *__restrict__ xw0,
                            const double *__restrict__ xw1, const double *__restrict__ sparam, const int *__restrict__ seg,
                            const int *__restrict__ sorted_id, const double *__restrict__ pbox, const int *__restrict__ left,
-                           const int *__restrict__ right, const double *__restrict__ nbox, int *__restrict__ count,
-                           const int *__restrict__ off, int2 *__restrict__ out, int *__restrict__ overflow, int2 *__restrict__ stash)
+                           const int *__restrict__ right, const double *__restrict__ nbox, const int *__restrict__ nmoving,
+                           const int *__restrict__ perm,
+                           int *__restrict__ count, const int *__restrict__ off, int2 *__restrict__ out, int *__restrict__ overflow,
+                           int2 *__restrict__ stash)
 {
-    int qi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi >= Q) return;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Q) return;
+    int qi = perm[t];
+    if (WRITE && stash) {
+        int n = count[qi];
+        if (n <= TRAV_STASH) {
+            int o = off[qi];
+            for (int c = 0; c < n; ++c) out[o + c] = stash[(size_t)qi * TRAV_STASH + c];
+            return;
+        }
+    }
     int qv[2], nq, s;
     if (kind == 0) { qv[0] = qi; nq = 1; s = cv_scene[qi]; }
     else { int2 e = qedge[qi]; qv[0] = e.x; qv[1] = e.y; nq = 2; s = cv_scene[e.x]; }
@@ -263,6 +307,8 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
     double qb[6];
     box_of(xw0, xw1, qv, nq, r, qb);
     int oq = cv_obj[qv[0]];
+    // a static query pairs only with moving primitives: subtrees without one are skipped
+    const bool qstatic = (oq >= 0 ? okind[oq] : 2) == 2;
     int base = seg[s], n = seg[s + 1] - base;
     int cnt = 0, w = WRITE ? off[qi] : 0;
     // traversal stack in LDS, one column per thread (a private array would
@@ -289,7 +335,7 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
         }
     };
     if (n == 1) leaf(sorted_id[base]);
-    else if (n > 1 && overlap(qb, nbox + 6 * (size_t)base)) {
+    else if (n > 1 && !(qstatic && !nmoving[base]) && overlap(qb, nbox + 6 * (size_t)base)) {
         int sp = 0;
         my[0] = base;
         sp = 1;
@@ -299,6 +345,7 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
             for (int c2 = 0; c2 < 2; ++c2) {
                 int x = ch[c2];
                 if (x < 0) { leaf(sorted_id[-1 - x]); continue; }
+                if (qstatic && !nmoving[x]) continue;
                 if (!overlap(qb, nbox + 6 * (size_t)x)) continue;
                 if (sp >= TRAV_DEPTH) { atomicOr(overflow, 1); continue; }
                 my[TRAV_BLOCK * sp++] = x;
@@ -411,17 +458,33 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
         }
         D.bvh_lev.alloc(6 * (size_t)total);
     }
-    hipLaunchKernelGGL(k_seg_leaves, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, D.mid2.p, D.box.p, D.bvh_lev.p);
+    D.bvh_moving.alloc(P + 1); D.bvh_mscan.alloc(P + 1); D.bvh_nmoving.alloc(P);
+    hipLaunchKernelGGL(k_seg_leaves, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, kind, D.mid2.p, D.box.p, D.tri.p, D.edge.p, D.cv_obj.p,
+                       D.obj_kind.p, D.bvh_lev.p, D.bvh_moving.p);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.bvh_moving.p + P, 0);
+    exclusive_scan(c, D.bvh_moving.p, D.bvh_mscan.p, P);
     for (int j0 = 0; j0 + 1 < SL.n; j0 += 8)
         hipLaunchKernelGGL(k_seg_up, dim3(blocks_for(SL.size[j0], 256)), dim3(256), 0, st, SL, j0, D.bvh_lev.p);
-    hipLaunchKernelGGL(k_node_box, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, SL, D.bvh_lev.p, D.bvh_range.p, D.bvh_box.p);
+    hipLaunchKernelGGL(k_node_box, dim3(blocks_for(P)), dim3(BLOCK), 0, st, P, SL, D.bvh_lev.p, D.bvh_range.p, D.bvh_mscan.p,
+                       D.bvh_box.p, D.bvh_nmoving.p);
     DBuf<int> &ovf = D.woff;
     ovf.alloc(2);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 2, ovf.p, 0);
     const int2 *qedge = D.edge.p;
+    // query order: edges in their own tree's sorted order; surface vertices by their own Morton keys
+    const int *perm = D.mid2.p;
+    if (kind == 0) {
+        D.qkey.alloc(Q); D.qkey2.alloc(Q); D.qid.alloc(Q); D.qperm.alloc(Q);
+        hipLaunchKernelGGL(k_query_keys, dim3(blocks_for(Q)), dim3(BLOCK), 0, st, Q, D.cv_scene.p, xw0, xw1, D.scene_lo.p, D.qkey.p, D.qid.p);
+        size_t qb = 0;
+        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, qb, D.qkey.p, D.qkey2.p, D.qid.p, D.qperm.p, Q, 0, end_bit, st));
+        D.sort_tmp.alloc(qb + 16);
+        IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.sort_tmp.p, qb, D.qkey.p, D.qkey2.p, D.qid.p, D.qperm.p, Q, 0, end_bit, st));
+        perm = D.qperm.p;
+    }
     hipLaunchKernelGGL(k_traverse<false>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
                        D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
-                       D.bvh_right.p, D.bvh_box.p, D.qcount.p, nullptr, nullptr, ovf.p, D.qstash.p);
+                       D.bvh_right.p, D.bvh_box.p, D.bvh_nmoving.p, perm, D.qcount.p, nullptr, nullptr, ovf.p, D.qstash.p);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.qcount.p + Q, 0);
     exclusive_scan(c, D.qcount.p, D.qoff.p, Q);
     // the candidates' per-scene segments go straight to the device table
@@ -442,10 +505,10 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     count = total;
     if (!of[1])
         hipLaunchKernelGGL(k_unstash, dim3(blocks_for(Q)), dim3(BLOCK), 0, st, Q, D.qcount.p, D.qoff.p, D.qstash.p, outbuf.p);
-    else
+    else   // queries whose candidates did not fit the stash traverse again
         hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p,
                            D.tri.p, D.edge.p, D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p,
-                           D.box.p, D.bvh_left.p, D.bvh_right.p, D.bvh_box.p, D.qcount.p, D.qoff.p, outbuf.p, ovf.p, nullptr);
+                           D.box.p, D.bvh_left.p, D.bvh_right.p, D.bvh_box.p, D.bvh_nmoving.p, perm, D.qcount.p, D.qoff.p, outbuf.p, ovf.p, D.qstash.p);
 }
 
 void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1)
@@ -722,8 +785,10 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
         double det = s00 * s11 - s01 * s01;
         Fi00 = s11 / det; Fi11 = s00 / det; Fi01 = -s01 / det;
     }
-    double H[45];
+    double H[45];   // every index below is a compile-time constant, so H stays in registers
+#pragma unroll
     for (int R = 0; R < 9; ++R)
+#pragma unroll
         for (int C = R; C < 9; ++C) {
             int iR = R / 3, cR = R % 3, iC = C / 3, cC = C % 3;
             double hq = (cR == cC ? 2.0 * gam[iR] * gam[iC] : 0.0)
@@ -749,10 +814,14 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     if (project) psd_project9(H);
     // world-vertex block H12[k][l] = sum_ij U_ki U_lj H9[i][j]
     auto blk = [&](int k, int l, double *B) {
+#pragma unroll
         for (int a = 0; a < 3; ++a)
+#pragma unroll
             for (int bb = 0; bb < 3; ++bb) {
                 double acc = 0.0;
+#pragma unroll
                 for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
                     for (int jj = 0; jj < 3; ++jj) acc += helmert(k, ii) * helmert(l, jj) * H[pk9(3 * ii + a, 3 * jj + bb)];
                 B[3 * a + bb] = acc;
             }
@@ -763,6 +832,7 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     }
     pair_flag[i] = 0;
     double *out = pair_H + 45 * (size_t)i;
+#pragma unroll
     for (int q = 0; q < 45; ++q) out[q] = H[q];
 }
 

@@ -168,8 +168,8 @@ __global__ void k_fem_grad_gather(int N, int T, const int *__restrict__ adj_ptr,
 // ---------------------------------------------------------------------------
 // affine bodies: inertia (4x4 mass matrix (x) I3) + orthogonality kappa V |AA^T - I|^2
 // ---------------------------------------------------------------------------
-template <int MODE>
-__global__ void k_body(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ bM,
+template <int MODE>   // launched with 64 threads: the whole register file is available to one body's 9x9 projection
+__global__ void __launch_bounds__(64) k_body(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ bM,
                        const double *__restrict__ bvol, const double *__restrict__ bkappa, const double *__restrict__ h2s,
                        const double *__restrict__ y, const double *__restrict__ xt, double *__restrict__ g,
                        double *__restrict__ val, const int *__restrict__ bslot, int project, double *__restrict__ part)

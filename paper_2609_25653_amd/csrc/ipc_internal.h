@@ -189,8 +189,11 @@ struct Dev {
     DBuf<int> bvh_left, bvh_right, bvh_flag;
     DBuf<int2> bvh_range;                  // sorted-leaf range of every internal node
     DBuf<double> bvh_box, bvh_lev;         // node boxes; union tree over the sorted leaf boxes
+    DBuf<int> bvh_moving, bvh_mscan, bvh_nmoving;   // moving-primitive flag per sorted leaf, its scan; per node
     DBuf<int> qcount, qoff;                // per-query candidate counts and offsets
     DBuf<int2> qstash;                     // first candidates of every query from the counting pass
+    DBuf<unsigned long long> qkey, qkey2;  // surface-vertex query keys before / after the sort
+    DBuf<int> qid, qperm;                  // query order (Morton-sorted surface vertices)
     DBuf<unsigned char> sort_tmp;
     DBuf<double> scene_lo;                 // Morton quantisation box per scene (6)
     // candidates and active pairs

@@ -274,49 +274,68 @@ __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__res
 }
 
 // 12x12 SPD inverse by Cholesky (one thread per body)
-__global__ void k_prec_body(int NB, const int *__restrict__ bslot, const int *__restrict__ node0, const double *__restrict__ val,
-                            const int *__restrict__ dptr, const int *__restrict__ dcol, const double *__restrict__ dval,
-                            double *__restrict__ dinvB)
+// One thread per body (launched with 64 threads, so the register file holds
+// the 12x12 factor); every loop is unrolled, so no array needs scratch memory.
+__global__ void __launch_bounds__(64) k_prec_body(int NB, const int *__restrict__ bslot, const int *__restrict__ node0,
+                                                  const double *__restrict__ val, const int *__restrict__ dptr,
+                                                  const int *__restrict__ dcol, const double *__restrict__ dval,
+                                                  double *__restrict__ dinvB)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= NB) return;
     double L[144];
     int n0 = node0[b];
+#pragma unroll
     for (int ca = 0; ca < 4; ++ca)
+#pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const double *B = val + 9 * (size_t)bslot[16 * (size_t)b + 4 * ca + cb];
             int k = dyn_find(dptr, dcol, n0 + ca, n0 + cb);
+#pragma unroll
             for (int i = 0; i < 3; ++i)
+#pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     double v = B[3 * i + j];
                     if (k >= 0) v += dval[9 * (size_t)k + 3 * i + j];
                     L[12 * (3 * ca + i) + 3 * cb + j] = v;
                 }
         }
+    // Cholesky factor L L^T (lower triangle of L)
+#pragma unroll
     for (int j = 0; j < 12; ++j) {
         double s = L[12 * j + j];
+#pragma unroll
         for (int k = 0; k < j; ++k) s -= L[12 * j + k] * L[12 * j + k];
         double dj = sqrt(fmax(s, 1e-300));
         L[12 * j + j] = dj;
+#pragma unroll
         for (int i = j + 1; i < 12; ++i) {
             double t = L[12 * i + j];
+#pragma unroll
             for (int k = 0; k < j; ++k) t -= L[12 * i + k] * L[12 * j + k];
             L[12 * i + j] = t / dj;
         }
     }
+    // the inverse, one column at a time by forward and back substitution
     double *o = dinvB + 144 * (size_t)b;
+#pragma unroll
     for (int cidx = 0; cidx < 12; ++cidx) {
         double y[12];
+#pragma unroll
         for (int i = 0; i < 12; ++i) {
             double t = (i == cidx) ? 1.0 : 0.0;
+#pragma unroll
             for (int k = 0; k < i; ++k) t -= L[12 * i + k] * y[k];
             y[i] = t / L[12 * i + i];
         }
+#pragma unroll
         for (int i = 11; i >= 0; --i) {
             double t = y[i];
+#pragma unroll
             for (int k = i + 1; k < 12; ++k) t -= L[12 * k + i] * y[k];
             y[i] = t / L[12 * i + i];
         }
+#pragma unroll
         for (int i = 0; i < 12; ++i) o[12 * i + cidx] = y[i];
     }
 }
