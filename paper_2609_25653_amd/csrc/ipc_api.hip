@@ -246,32 +246,35 @@ void eval_energy(ipc_ctx *c, const double *y, bool from_candidates)
     launch_barrier(c, 0, from_candidates, D.xw.p, nullptr, false);
     if (c->fr_on) launch_friction(c, 0, D.xw.p, nullptr);
     int64_t npt = from_candidates ? c->n_cand_pt : c->n_pt, nee = from_candidates ? c->n_cand_ee : c->n_ee;
+    // the per-pair values are pre-summed in chunks of 64, so that a scene's
+    // reduction reads its chunk sums and at most 126 single entries
+    int64_t nlag = c->fr_on ? c->n_lag : 0;
+    D.pair_w64.alloc((npt + nee) / TILE + 1);
+    D.fr_w64.alloc(nlag / TILE + 1);
+    sum64(c, D.pair_part.p, npt + nee, D.pair_w64.p);
+    sum64(c, D.fr_part.p, nlag, D.fr_w64.p);
+    // one pass: every term in its slot, the barrier (group 1) and friction
+    // (group 2) totals, and the energy as the sum of all sources in order
     RedArgs a{};
-    a.src[a.nsrc] = src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0); a.slots[a.nsrc++] = S_E_IN;
-    a.src[a.nsrc] = src(c->T ? D.part_tet.p : nullptr, seg_ptr(c, R_TETW), 0, 0); a.slots[a.nsrc++] = S_E_FEM;
-    a.src[a.nsrc] = src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0); a.slots[a.nsrc++] = S_E_ABD;
-    a.src[a.nsrc] = src(c->NS ? D.sp_part.p : nullptr, seg_ptr(c, R_SP), 0, 0); a.slots[a.nsrc++] = S_E_SP;
-    a.src[a.nsrc++] = src(npt ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CPT : R_PT), 0, 0);
-    a.src[a.nsrc++] = src(nee ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CEE : R_EE), (int)npt, 0);
-    if (c->fr_on) {
-        a.src[a.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
-        a.src[a.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
-    }
-    a.slot = S_E;
+    auto add = [&](RedSrc r, int slot, int grp) { a.src[a.nsrc] = r; a.slots[a.nsrc] = slot; a.grp[a.nsrc++] = grp; };
+    add(src(D.part_node.p, seg_ptr(c, R_NODEW), 0, 0), S_E_IN, -1);
+    add(src(c->T ? D.part_tet.p : nullptr, seg_ptr(c, R_TETW), 0, 0), S_E_FEM, -1);
+    add(src(c->NB ? D.body_part.p : nullptr, seg_ptr(c, R_BODY), 0, 0), S_E_ABD, -1);
+    add(src(c->NS ? D.sp_part.p : nullptr, seg_ptr(c, R_SP), 0, 0), S_E_SP, -1);
+    RedSrc bp = src(npt ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CPT : R_PT), 0, 0);
+    RedSrc be = src(nee ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CEE : R_EE), (int)npt, 0);
+    bp.w64 = be.w64 = D.pair_w64.p;
+    add(bp, -1, 1);
+    add(be, -1, 1);
+    RedSrc fp = src(c->fr_on && c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
+    RedSrc fe = src(c->fr_on && c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
+    fp.w64 = fe.w64 = D.fr_w64.p;
+    add(fp, -1, 2);
+    add(fe, -1, 2);
+    a.slot1 = S_E_BAR;
+    a.slot2 = S_E_FR;
+    a.total = S_E;
     reduce(c, a);
-    // barrier and friction terms for reporting
-    RedArgs b{};
-    b.src[b.nsrc++] = src(npt ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CPT : R_PT), 0, 0);
-    b.src[b.nsrc++] = src(nee ? D.pair_part.p : nullptr, seg_ptr(c, from_candidates ? R_CEE : R_EE), (int)npt, 0);
-    b.slot = S_E_BAR;
-    reduce(c, b);
-    RedArgs f{};
-    if (c->fr_on) {
-        f.src[f.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
-        f.src[f.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
-    }
-    f.slot = S_E_FR;
-    reduce(c, f);
     hipLaunchKernelGGL(k_inf_to_scal, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.inf_flag.p, D.scal.p);
 }
 
@@ -703,9 +706,12 @@ extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *
         launch_adj_mass(c, D.x.p, D.y0.p, D.v2.p, D.r.p);
         launch_world(c, D.yt.p, D.xw.p);
         launch_lag_vjp(c, D.xw.p, D.xw1.p, D.x.p, D.v2.p);
+        D.fr_w64.alloc(c->n_lag / TILE + 1);
+        sum64(c, D.fr_part.p, c->n_lag, D.fr_w64.p);
         RedArgs f{};
         f.src[f.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
         f.src[f.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
+        f.src[0].w64 = f.src[1].w64 = D.fr_w64.p;
         f.slot = S_MUBAR;
         reduce(c, f);
         if (mubar_dev)

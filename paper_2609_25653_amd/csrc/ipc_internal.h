@@ -57,6 +57,7 @@ struct RedSrc {
     const int *seg;
     int off;
     int base;
+    const double *w64 = nullptr;   // optional sums of v[64 k .. 64 k + 63] (whole chunks are read from here)
 };
 // Per-scene reduction of up to 8 sources.  Each source's sum can be stored in
 // its own slot; the sources of group g (grp[k] = g) are combined in source
@@ -69,8 +70,9 @@ struct RedArgs {
     int slot2 = -1;         // total of group 2
     int acc = 0;            // accumulate into the group-0 slot
     int slots[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // per-source sums (-1: none)
-    int grp[8] = {0, 0, 0, 0, 0, 0, 0, 0};             // group of each source
+    int grp[8] = {0, 0, 0, 0, 0, 0, 0, 0};             // group of each source (-1: none)
     int op = 0;             // 0 sum, 1 max
+    int total = -1;         // slot of the combination of every source in source order (-1: none)
 };
 
 #define IPC_HIP(call)                                                           \
@@ -201,6 +203,7 @@ struct Dev {
     DBuf<int2> pt, ee;
     DBuf<int> wcount, woff;
     DBuf<double> pair_part;                // per-pair reduction values
+    DBuf<double> pair_w64, fr_w64;         // their sums over chunks of 64 (pairs; friction lag pairs)
     DBuf<int4> pair_cv;                    // 4 contact vertices per active pair (PT then EE)
     DBuf<double> pair_H;                   // 45 per pair: projected reduced Hessian
     // friction lag
@@ -289,6 +292,8 @@ namespace ipc {
 // ---- helpers implemented in the .hip files ---------------------------------
 void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n);
 void reduce(ipc_ctx *c, const RedArgs &a);
+// w[k] = sum of v[64 k .. 64 k + 63] (entries past n count as 0), k < ceil(n / 64)
+void sum64(ipc_ctx *c, const double *v, int64_t n, double *w);
 RedSrc src(const double *v, const int *seg, int off, int base);
 int *seg_ptr(ipc_ctx *c, int region);
 void prof_begin(ipc_ctx *c, int k);

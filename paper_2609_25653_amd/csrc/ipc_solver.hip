@@ -34,6 +34,19 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
         const RedSrc &r = a.src[k];
         if (!r.v) continue;
         int lo = r.seg[s] - r.base, hi = r.seg[s + 1] - r.base;
+        if (r.w64 && !a.op) {
+            // positions [off + lo, off + hi): the unaligned head and tail
+            // entries, the whole 64-entry chunks between them from w64
+            int plo = r.off + lo, phi = r.off + hi, c0 = (plo + 63) >> 6, c1 = phi >> 6;
+            if (c0 < c1) {
+                double acc = 0.0;
+                if ((int)threadIdx.x < 64 * c0 - plo) acc += r.v[plo + threadIdx.x];
+                for (int q = c0 + (int)threadIdx.x; q < c1; q += BLOCK) acc += r.w64[q];
+                if (64 * c1 + (int)threadIdx.x < phi) acc += r.v[64 * c1 + threadIdx.x];
+                part[k] = acc;
+                continue;
+            }
+        }
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -67,6 +80,28 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
     if (a.slot >= 0) S[a.slot] = a.acc ? (a.op ? fmax(S[a.slot], tot[0]) : S[a.slot] + tot[0]) : tot[0];
     if (a.slot1 >= 0) S[a.slot1] = tot[1];
     if (a.slot2 >= 0) S[a.slot2] = tot[2];
+    if (a.total >= 0) {
+        double t = 0.0;
+        for (int k = 0; k < a.nsrc; ++k) {
+            double v = sh[k][0];
+            for (int w = 1; w < BLOCK / TILE; ++w) v = a.op ? fmax(v, sh[k][w]) : v + sh[k][w];
+            t = a.op ? fmax(t, v) : t + v;
+        }
+        S[a.total] = t;
+    }
+}
+
+__global__ void k_sum64(int64_t n, const double *__restrict__ v, double *__restrict__ w)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double x = i < n ? v[i] : 0.0;
+    x = wave_sum(x);
+    if ((threadIdx.x & (TILE - 1)) == 0 && i < n) w[i / TILE] = x;
+}
+
+void sum64(ipc_ctx *c, const double *v, int64_t n, double *w)
+{
+    if (n > 0) hipLaunchKernelGGL(k_sum64, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, n, v, w);
 }
 
 void reduce(ipc_ctx *c, const RedArgs &a)
