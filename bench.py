@@ -293,7 +293,7 @@ def main():
         pairs.append(st[0]["n_pt_max"] + st[0]["n_ee_max"])
         nloc = sim._query(7)
         print(f"# step {sim.step_index}: rc={rc} newton={st[0]['newton_iters']} pcg={st[0]['pcg_iters_total']} "
-              f"pairs={pairs[-1]} pair_local={nloc} alpha_min={st[0]['alpha_min']:.3g}", file=sys.stderr, flush=True)
+              f"pairs={pairs[-1]} pair_local={nloc} cand_max={st[0]['n_cand_max']} alpha_min={st[0]['alpha_min']:.3g}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     # Dominant kernel: the block-CSR Hessian product inside PCG.  Its launch

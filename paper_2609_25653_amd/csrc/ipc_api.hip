@@ -63,6 +63,16 @@ __global__ void k_negate(int64_t n, const double *__restrict__ a, double *__rest
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) b[i] = -a[i];
 }
+// line search set-up: the scene takes part when on[s]; step 1; CCD bound 1
+__global__ void k_ls_begin(int ns, const int *__restrict__ on, double *__restrict__ scal)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    double *S = scal + (size_t)s * NSLOT;
+    S[S_LS_ON] = on[s] ? 1.0 : 0.0;
+    S[S_LS_ALPHA] = 1.0;
+    S[S_CCD] = 1.0;
+}
 // yt = y + alpha_s p (alpha from the scene's line-search slot, 0 when off)
 __global__ void k_trial(int N, const int *__restrict__ node_scene, const double *__restrict__ scal, const double *__restrict__ y,
                         const double *__restrict__ p, double *__restrict__ yt)
@@ -780,6 +790,18 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         upload_async(c, D.newton_on.p, on.data(), ns * sizeof(int));
         pcg_solve(c, D.v1.p, D.x.p, -1.0, D.newton_on.p);
         std::vector<int> it(ns);
+        // the trial point y + p (step 1) and world positions at both ends,
+        // and whether the kept candidates still cover that sweep; read
+        // together with the Newton measure
+        upload_async(c, D.ls_active.p, on.data(), ns * sizeof(int));
+        hipLaunchKernelGGL(k_ls_begin, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.ls_active.p, D.scal.p);
+        hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
+        launch_world(c, D.y.p, D.xw.p);
+        launch_world(c, D.yt.p, D.xw1.p);
+        const bool cached = c->cand_cached;
+        std::vector<int> stale(ns, 1);
+        D.cand_flag.alloc(ns);
+        if (cached) cand_check(c, D.xw.p, D.xw1.p, D.cand_flag.p);
         // Newton measure
         hipLaunchKernelGGL(k_measure_nodes, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.x.p, D.part_node.p);
         if (c->NB)
@@ -797,6 +819,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             HostReads rd(c);
             rd.add(it.data(), D.pcg_iters.p, ns * sizeof(int));
             rd.add(sc.data(), D.scal.p, sc.size() * sizeof(double));
+            if (cached) rd.add(stale.data(), D.cand_flag.p, ns * sizeof(int));
             rd.wait();
         }
         any = false;
@@ -809,20 +832,13 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             any |= on[s] != 0;
         }
         if (!any) break;
-        // CCD over the swept candidates of [y, y + p]
-        for (int s = 0; s < ns; ++s) {
-            sc[(size_t)s * NSLOT + S_LS_ON] = on[s] ? 1.0 : 0.0;
-            sc[(size_t)s * NSLOT + S_LS_ALPHA] = 1.0;
-            sc[(size_t)s * NSLOT + S_CCD] = 1.0;
-        }
-        write_scal(c, sc);
-        hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
-        launch_world(c, D.y.p, D.xw.p);
-        launch_world(c, D.yt.p, D.xw1.p);
-        broad_phase(c, D.xw.p, D.xw1.p);
+        // CCD over the swept candidates of [y, y + p]: the kept list while it
+        // still covers every iterating scene's sweep, else a new one
+        bool rebuild = !cached;
+        for (int s = 0; s < ns; ++s) rebuild = rebuild || (on[s] && stale[s]);
+        if (rebuild) broad_phase_cached(c, D.xw.p, D.xw1.p);
         for (int s = 0; s < ns; ++s) S[s].n_cand_max = std::max(S[s].n_cand_max, (c->h_cand_pt_seg[s + 1] - c->h_cand_pt_seg[s]) +
                                                                              (c->h_cand_ee_seg[s + 1] - c->h_cand_ee_seg[s]));
-        upload_async(c, D.ls_active.p, on.data(), ns * sizeof(int));
         launch_ccd(c, D.xw.p, D.xw1.p);
         sc = read_scal(c);
         std::vector<double> alpha(ns, 0.0);

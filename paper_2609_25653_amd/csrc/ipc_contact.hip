@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
                            const double *__restrict__ xw1, const double *__restrict__ sparam, const int *__restrict__ seg,
                            const int *__restrict__ sorted_id, const double *__restrict__ pbox, const int *__restrict__ left,
                            const int *__restrict__ right, const double *__restrict__ nbox, const int *__restrict__ nmoving,
-                           const int *__restrict__ perm,
+                           double grow, const int *__restrict__ perm,
                            int *__restrict__ count, const int *__restrict__ off, int2 *__restrict__ out, int *__restrict__ overflow,
                            int2 *__restrict__ stash)
 {
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const 
     int qv[2], nq, s;
     if (kind == 0) { qv[0] = qi; nq = 1; s = cv_scene[qi]; }
     else { int2 e = qedge[qi]; qv[0] = e.x; qv[1] = e.y; nq = 2; s = cv_scene[e.x]; }
-    double r = 1.01 * sparam[8 * s + 2] * (kind == 0 ? 1.0 : 0.5);
+    double r = 1.01 * sparam[8 * s + 2] * (kind == 0 ? 1.0 : 0.5) + grow * sparam[8 * s + 2];
     double qb[6];
     box_of(xw0, xw1, qv, nq, r, qb);
     int oq = cv_obj[qv[0]];
@@ -412,8 +412,8 @@ static void exclusive_scan(ipc_ctx *c, const int *in, int *out, int n)
 }
 
 // Build the tree over one primitive kind and run one query kind against it.
-static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1, DBuf<int2> &outbuf, int64_t &cap, int64_t &count,
-                      std::vector<int> &hseg)
+static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1, double grow, DBuf<int2> &outbuf, int64_t &cap,
+                      int64_t &count, std::vector<int> &hseg)
 {
     Dev &D = c->d;
     hipStream_t st = c->stream;
@@ -484,7 +484,7 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     }
     hipLaunchKernelGGL(k_traverse<false>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p, D.tri.p, D.edge.p,
                        D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p, D.box.p, D.bvh_left.p,
-                       D.bvh_right.p, D.bvh_box.p, D.bvh_nmoving.p, perm, D.qcount.p, nullptr, nullptr, ovf.p, D.qstash.p);
+                       D.bvh_right.p, D.bvh_box.p, D.bvh_nmoving.p, grow, perm, D.qcount.p, nullptr, nullptr, ovf.p, D.qstash.p);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.qcount.p + Q, 0);
     exclusive_scan(c, D.qcount.p, D.qoff.p, Q);
     // the candidates' per-scene segments go straight to the device table
@@ -508,15 +508,71 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     else   // queries whose candidates did not fit the stash traverse again
         hipLaunchKernelGGL(k_traverse<true>, dim3(blocks_for(Q, TRAV_BLOCK)), dim3(TRAV_BLOCK), 0, st, Q, kind, qedge, D.cv_scene.p,
                            D.tri.p, D.edge.p, D.cv_obj.p, D.obj_kind.p, D.excl.p, c->NEX, xw0, xw1, D.sparam.p, pseg_d, D.mid2.p,
-                           D.box.p, D.bvh_left.p, D.bvh_right.p, D.bvh_box.p, D.bvh_nmoving.p, perm, D.qcount.p, D.qoff.p, outbuf.p, ovf.p, D.qstash.p);
+                           D.box.p, D.bvh_left.p, D.bvh_right.p, D.bvh_box.p, D.bvh_nmoving.p, grow, perm, D.qcount.p, D.qoff.p, outbuf.p, ovf.p, D.qstash.p);
 }
 
-void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1)
+void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1, double grow)
 {
     prof_begin(c, IPC_K_BROAD);
-    bvh_query(c, 0, xw0, xw1, c->d.cand_pt, c->cap_cand_pt, c->n_cand_pt, c->h_cand_pt_seg);
-    bvh_query(c, 1, xw0, xw1, c->d.cand_ee, c->cap_cand_ee, c->n_cand_ee, c->h_cand_ee_seg);
+    c->cand_cached = false;
+    bvh_query(c, 0, xw0, xw1, grow, c->d.cand_pt, c->cap_cand_pt, c->n_cand_pt, c->h_cand_pt_seg);
+    bvh_query(c, 1, xw0, xw1, grow, c->d.cand_ee, c->cap_cand_ee, c->n_cand_ee, c->h_cand_ee_seg);
     prof_end(c, IPC_K_BROAD, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Candidates kept across Newton iterations.  The swept-box candidates are
+// built with query boxes grown by CAND_GROW dhat, and every contact vertex
+// keeps its swept box [min, max] of the two end positions.  Later sweeps
+// may reuse the list while no vertex's swept box leaves its kept box by more
+// than half the growth: each primitive box then grows by at most that much,
+// so every pair whose exact boxes overlap is still on the list (a
+// superset).  CCD skips listed pairs whose exact boxes do not overlap, so the
+// step bound is the one of the exact candidates; the pair set is exact for
+// any superset.
+// ---------------------------------------------------------------------------
+constexpr double CAND_GROW = 1.0;
+
+__global__ void k_cand_ref(int CV, const double *__restrict__ xw0, const double *__restrict__ xw1, double *__restrict__ ref)
+{
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= CV) return;
+    for (int k = 0; k < 3; ++k) {
+        double a = xw0[3 * (size_t)v + k], b = xw1[3 * (size_t)v + k];
+        ref[6 * (size_t)v + k] = fmin(a, b);
+        ref[6 * (size_t)v + 3 + k] = fmax(a, b);
+    }
+}
+
+__global__ void k_cand_check(int CV, const double *__restrict__ xw0, const double *__restrict__ xw1, const double *__restrict__ ref,
+                             const int *__restrict__ cv_scene, const double *__restrict__ sparam, double grow, int *__restrict__ flag)
+{
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= CV) return;
+    int s = cv_scene[v];
+    double m = 0.5 * grow * sparam[8 * (size_t)s + P_DHAT], ex = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double a = xw0[3 * (size_t)v + k], b = xw1[3 * (size_t)v + k];
+        ex = fmax(ex, fmax(ref[6 * (size_t)v + k] - fmin(a, b), fmax(a, b) - ref[6 * (size_t)v + 3 + k]));
+    }
+    if (ex > m) atomicOr(flag + s, 1);
+}
+
+void broad_phase_cached(ipc_ctx *c, const double *xw0, const double *xw1)
+{
+    broad_phase(c, xw0, xw1, CAND_GROW);
+    c->d.cand_ref.alloc(6 * (size_t)c->CV + 1);
+    if (c->CV)
+        hipLaunchKernelGGL(k_cand_ref, dim3(blocks_for(c->CV)), dim3(BLOCK), 0, c->stream, c->CV, xw0, xw1, c->d.cand_ref.p);
+    c->cand_cached = true;
+}
+
+void cand_check(ipc_ctx *c, const double *xw0, const double *xw1, int *flag)
+{
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(c->n_scenes)), dim3(BLOCK), 0, c->stream, c->n_scenes, flag, 0);
+    if (c->CV)
+        hipLaunchKernelGGL(k_cand_check, dim3(blocks_for(c->CV)), dim3(BLOCK), 0, c->stream, c->CV, xw0, xw1, c->d.cand_ref.p,
+                           c->d.cv_scene.p, c->d.sparam.p, CAND_GROW, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1458,11 +1514,29 @@ __global__ void k_ccd(int npt, int nee, const int2 *__restrict__ pt, const int2 
     pair_vertices(kind, pr, tri, edge, cv);
     int s = cv_scene[cv[0]];
     if (active && !active[s]) return;
-    d3 x0[4], p[4];
+    d3 x0[4], x1[4], p[4];
     for (int k = 0; k < 4; ++k) {
         x0[k] = ld3(xw0, cv[k]);
-        d3 x1 = ld3(xw1, cv[k]);
-        p[k] = {x1.x - x0[k].x, x1.y - x0[k].y, x1.z - x0[k].z};
+        x1[k] = ld3(xw1, cv[k]);
+        p[k] = {x1[k].x - x0[k].x, x1[k].y - x0[k].y, x1[k].z - x0[k].z};
+    }
+    // exact swept candidates only (the list may be a kept superset): the
+    // boxes of the two sides over both end positions, inflated as in the
+    // broad phase (vertex 1.01 dhat, triangle 0; each edge half of that)
+    {
+        double r = 1.01 * sparam[8 * s + 2];
+        double ra = kind == 0 ? r : 0.5 * r, rb = kind == 0 ? 0.0 : 0.5 * r;
+        int na = kind == 0 ? 1 : 2;
+        double A[6], B[6];
+        for (int k = 0; k < 3; ++k) { A[k] = B[k] = INFINITY; A[3 + k] = B[3 + k] = -INFINITY; }
+        for (int q = 0; q < 4; ++q) {
+            double *T = q < na ? A : B;
+            T[0] = fmin(T[0], fmin(x0[q].x, x1[q].x)); T[3] = fmax(T[3], fmax(x0[q].x, x1[q].x));
+            T[1] = fmin(T[1], fmin(x0[q].y, x1[q].y)); T[4] = fmax(T[4], fmax(x0[q].y, x1[q].y));
+            T[2] = fmin(T[2], fmin(x0[q].z, x1[q].z)); T[5] = fmax(T[5], fmax(x0[q].z, x1[q].z));
+        }
+        for (int k = 0; k < 3; ++k) { A[k] -= ra; A[3 + k] += ra; B[k] -= rb; B[3 + k] += rb; }
+        if (!overlap(A, B)) return;
     }
     double t = accd(kind, x0, p, sparam[8 * s + 5]);
     if (t < 1.0) atomicMin(amin + (size_t)stride * s, (unsigned long long)__double_as_longlong(t));

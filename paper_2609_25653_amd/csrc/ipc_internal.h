@@ -200,6 +200,8 @@ struct Dev {
     DBuf<double> scene_lo;                 // Morton quantisation box per scene (6)
     // candidates and active pairs
     DBuf<int2> cand_pt, cand_ee;
+    DBuf<double> cand_ref;                 // kept candidates: swept box of every contact vertex (lo, hi)
+    DBuf<int> cand_flag;                   // per scene: 1 when the kept candidates no longer cover the sweep
     DBuf<int2> pt, ee;
     DBuf<int> wcount, woff;
     DBuf<double> pair_part;                // per-pair reduction values
@@ -269,6 +271,7 @@ struct ipc_ctx {
     char *pin_rd = nullptr, *pin_wr = nullptr;
     size_t pin_wr_off = 0;
     int64_t n_lag_pt = 0, n_local = 0;
+    bool cand_cached = false;            // the candidate lists are a kept superset (valid while cand_check passes)
     int last_status = 0;
     // host staging for small uploads (kept alive until the copy has completed)
     std::vector<double> h_scal_stage;

@@ -26,7 +26,11 @@ void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *par
 // contact (ipc_contact.hip)
 void launch_world(ipc_ctx *c, const double *y, double *xw);
 // candidates from the LBVH over boxes at xw0 (and xw1 when swept)
-void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1);
+void broad_phase(ipc_ctx *c, const double *xw0, const double *xw1, double grow = 0.0);
+// swept candidates kept across Newton iterations (see ipc_contact.hip) and
+// the per-scene test (flag 1: rebuild) of whether they still cover [xw0, xw1]
+void broad_phase_cached(ipc_ctx *c, const double *xw0, const double *xw1);
+void cand_check(ipc_ctx *c, const double *xw0, const double *xw1, int *flag);
 // narrow phase: active pairs from the candidate lists at xw
 void narrow_phase(ipc_ctx *c, const double *xw);
 void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project);
