@@ -23,8 +23,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton iters/s & sim steps/s at 200k tets; batched scenes/s; adjoint/forward time"
 HBM_PEAK_GBS = 8000.0
+K_SPMV = 0   # the library's timed-kernel id of the Hessian product
 # calibrated hardware traffic of the product, valid while its source is unchanged
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv_contact_rich_200k_traffic.json")
 PRODUCT_SRC = os.path.join(ROOT, "paper_2609_25653_amd", "csrc", "ipc_solver.hip")
 
 
@@ -77,8 +78,9 @@ def cpu_baseline(scene, pcg_per_newton):
 
 
 def write_traffic(fetch_csv, write_csv):
-    """Calibrate FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the probe's
-    256 MiB device copy and store the product's bytes per launch."""
+    """Calibrate FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the 256 MiB
+    device copy of a --traffic-run and store the product's bytes per launch
+    (mean over the dispatches of the product variant the solver used)."""
     import csv
     import hashlib
 
@@ -90,7 +92,8 @@ def write_traffic(fetch_csv, write_csv):
 
     f, w = per_kernel(fetch_csv), per_kernel(write_csv)
     copy = [k for k in f if "copyBuffer" in k]
-    spmv = [k for k in f if "k_spmv" in k]
+    # the product variant the solver runs (one lane count per run)
+    spmv = [max((k for k in f if "k_spmv" in k), key=lambda k: len(f[k]))]
     kib = 256 * 1024   # the probe copies 256 MiB
     fac_f = kib / max(max(f[k]) for k in copy)
     fac_w = kib / max(max(w[k]) for k in copy)
@@ -100,6 +103,7 @@ def write_traffic(fetch_csv, write_csv):
     rec = {"kernel": "k_spmv", "bytes_per_launch": traffic, "fetch_kib": sum(sf) / len(sf), "write_kib": sum(sw) / len(sw),
            "fetch_scale": fac_f, "write_scale": fac_w, "launches": len(sf),
            "source_sha256": hashlib.sha256(open(PRODUCT_SRC, "rb").read()).hexdigest()}
+    rec["source"] = "python bench.py --traffic-run (1 warm-up + 1 timed step of the contact workload) under rocprofv3 --pmc"
     json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
     print(json.dumps(rec))
 
@@ -252,7 +256,10 @@ def main():
     ap.add_argument("--single-sample", type=int, default=16, help="batched: scenes stepped one at a time for the baseline")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="write the product's calibrated per-launch HBM traffic from the counter files of two "
-                         "'rocprofv3 --pmc FETCH_SIZE' / '--pmc WRITE_SIZE' runs of --probe spmv, then exit")
+                         "'rocprofv3 --pmc FETCH_SIZE' / '--pmc WRITE_SIZE' runs of --traffic-run, then exit")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="for hardware-counter runs: a plain 256 MiB device copy (the counters' calibration), then "
+                         "the contact workload with --warmup and --steps and no line")
     ap.add_argument("--probe", choices=["spmv"], default=None,
                     help="spmv: assemble the Hessian of the 200k-tet scene once, then run a plain 256 MiB device copy "
                          "and 20 back-to-back block-CSR products (for hardware-counter runs)")
@@ -277,6 +284,17 @@ def main():
     sim = Sim(scene)
     if args.probe == "spmv":
         return probe_spmv(sim)
+    if args.traffic_run:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        for k in range(args.warmup + args.steps):
+            rc, st = sim.step(allow_status=(3,))
+            print(f"# traffic run step {k}: rc={rc} newton={st[0]['newton_iters']}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return
     for _ in range(args.warmup):
         sim.step(allow_status=(3,))
     # autotune the product's lanes per row on the last warm-up matrix
@@ -297,14 +315,16 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     # Dominant kernel: the block-CSR Hessian product inside PCG.  Its launch
-    # duration comes from 200 back-to-back launches on the matrix of the last
-    # timed Newton iteration between two HIP events on the library's stream.
+    # duration: 200 back-to-back launches on the matrix of the last timed
+    # Newton iteration between two HIP events on the library's stream (events
+    # around single launches add their own dispatch overhead to each one).
     us, by = ctypes.c_double(), ctypes.c_double()
-    sim._check(lib().ipc_time_kernel(sim._h, 0, 200, ctypes.byref(us), ctypes.byref(by)))
+    sim._check(lib().ipc_time_kernel(sim._h, K_SPMV, 200, ctypes.byref(us), ctypes.byref(by)))
     achieved = by.value / (us.value * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": product_traffic(), "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)", "bytes_per_launch": by.value,
-            "avg_us": us.value}
+            "traffic": product_traffic(), "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)",
+            "bytes_per_launch": by.value,
+            "avg_us": us.value, "launches_timed": 200}
     kt = {}
     line = {
         "metric": METRIC, "value": newton / t, "unit": "Newton iters/s", "n_gpus": 1, "steps": args.steps,

@@ -140,6 +140,16 @@ __device__ __forceinline__ void acc_block(const double *__restrict__ B, d3 w, do
     az += B[6] * w.x + B[7] * w.y + B[8] * w.z;
 }
 
+// Workgroup b of a grid of n tiles -> tile, so that the b's one XCD runs
+// (b = x + 8 j for XCD x) cover a contiguous range of tiles: XCD x takes
+// tiles [x q + min(x, rem), ...) of length q (+1 for the first rem XCDs).
+__device__ __forceinline__ int tile_of(int b, int n)
+{
+    constexpr int NX = 8;
+    int x = b % NX, j = b / NX, q = n / NX, rem = n % NX;
+    return x * q + min(x, rem) + j;
+}
+
 template <int L>
 __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *__restrict__ nlong, const int *__restrict__ long_rows,
                                                  const int *__restrict__ row_ptr, const int *__restrict__ col,
@@ -153,8 +163,12 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *_
     int lane = threadIdx.x & (TILE - 1);
     if ((int)blockIdx.x < ntiles) {
         __shared__ double sh[NW];
+        // Workgroups are dealt to the 8 XCDs round-robin; tile_of gives each
+        // XCD one contiguous run of tiles, whose rows share most of their
+        // columns, so the gathered vector entries are reused in that XCD's L2.
+        const int tile = tile_of(blockIdx.x, ntiles);
         int sub = threadIdx.x % L;
-        int n = blockIdx.x * TILE + threadIdx.x / L;
+        int n = tile * TILE + threadIdx.x / L;
         double ax = 0.0, ay = 0.0, az = 0.0;
         bool mine = false, on = false;
         if (n < N) {
@@ -186,7 +200,7 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *_
             if (threadIdx.x == 0) {
                 double t = sh[0];
                 for (int q = 1; q < NW; ++q) t += sh[q];
-                part[blockIdx.x] = t;
+                part[tile] = t;
             }
         }
         return;
@@ -514,9 +528,14 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     // this node's operands first: their loads overlap the reductions below
     int k = 2;
     d3 zv{}, pv{}, wv{}, sv{}, xv{}, rv{};
+    double Mi[9];
     if (n < N) {
         k = kind[n];
-        if (k == 0) { zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n); }
+        if (k == 0) {
+            zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)n + q];
+        }
     }
     const double *rz_in = part + (size_t)(2 * q) * ntile, *rr_in = rz_in + ntile;
     double *rz_out = part + (size_t)(2 * (q ^ 1)) * ntile, *rr_out = rz_out + ntile;
@@ -572,7 +591,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
         xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
         rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
-        zv = mat3v(dinv + 9 * (size_t)n, rv);
+        zv = mat3v(Mi, rv);
         st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv); st3(z, n, zv);
         rr = dt(rv, rv);
         rz = dt(rv, zv);
