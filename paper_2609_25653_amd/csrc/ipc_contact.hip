@@ -1467,6 +1467,7 @@ void build_dyn_blocks(ipc_ctx *c)
     D.long_count.alloc(1);
     hipLaunchKernelGGL(k_long_seg, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes, seg_ptr(c, R_NODEW),
                        D.long_rows.p, c->n_long, seg_ptr(c, R_LONG), D.long_count.p);
+    pcg_wginfo(c);
 }
 
 // ---------------------------------------------------------------------------

@@ -228,6 +228,7 @@ struct Dev {
     // eta^2 b.b, r.r}, running flag and update count; per-tile partials of
     // r.z and r.r
     DBuf<double> pcg_st, pcg_part, pcg_prev;   // pcg_prev: r.r at the previous peek
+    DBuf<int> pcg_wginfo;                  // per step workgroup: scenes and the first scene's ranges (6 ints)
     DBuf<int> pcg_act, pcg_it;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
     DBuf<int> tickets;                     // small device counters
@@ -307,6 +308,7 @@ void autotune_spmv(ipc_ctx *c, int reps, double *us);
 double spmv_bytes(const ipc_ctx *c);
 void build_preconditioner(ipc_ctx *c);
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
+void pcg_wginfo(ipc_ctx *c);   // refresh the step workgroups' scene records (after the long rows change)
 
 // Several device values to the host with one synchronisation, staged in the
 // context's pinned readback arena (asynchronous copies); reads that do not
