@@ -100,6 +100,11 @@ typedef struct ipc_scene_desc {
     const int32_t *driven_body;
     double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
     int32_t max_newton, max_pcg;
+    /* joint-space drives (E_joint of Eq. (3)): nj springs whose b side is a
+     * body point that follows the joint reference; their b-side body-frame
+     * points arrive with every step's targets (see ipc_begin_step) */
+    int32_t nj;
+    const int32_t *joint_spring;   /* nj spring indices (b side of kind 1) */
 } ipc_scene_desc;
 
 /* Per-scene statistics of the last ipc_step(). */
@@ -154,9 +159,11 @@ int ipc_set_state(ipc_ctx *ctx, const double *y_dev, const double *ydot_dev);
 
 /* Step set-up at the current state: predictive positions x~ = x + h v + h^2 g
  * (bodies: q + h qdot + h^2 (g, 0, 0, 0)), the drive targets of this step
- * (targets_dev: 12 doubles per driven slot, all scenes concatenated; may be
- * NULL when there are no driven links) and the friction data lagged at the
- * current state.  ipc_step() calls it itself. */
+ * (targets_dev: 12 doubles per driven slot, all scenes concatenated, then 3
+ * per joint spring, all scenes concatenated: the spring's b-side body-frame
+ * point for this step; may be NULL when there are neither driven links nor
+ * joint springs) and the friction data lagged at the current state.
+ * ipc_step() calls it itself. */
 int ipc_begin_step(ipc_ctx *ctx, const double *targets_dev);
 
 /* Evaluate the potential of the step set up by ipc_begin_step() at any y_dev

@@ -9,6 +9,7 @@ from .scenes import (  # noqa: F401
     SCENE_KEYS,
     block_drop,
     gripper_squeeze,
+    arm_squeeze,
     contact_rich,
     batched_squeeze,
     adjoint_squeeze,

@@ -34,6 +34,10 @@ Springs, E = 1/2 k |a - b|^2 (times h^2 in the incremental potential)
 Drives
   driven_body (nd,) int32 body driven by slot d
   drive_q (n_steps, nd, 12) target affine state of every driven link at t_{n+1}
+Joint springs (joint-space drives: both sides body points, the b side's
+body-frame point follows the joint reference)
+  joint_spring (nj,) int32 spring index of every joint slot
+  joint_xbar (n_steps, nj, 3) the b-side body-frame point of slot j at t_{n+1}
 Scalars (0-d arrays): h, dhat, kappa (0 = automatic), mu, eps_v, newton_tol,
   max_newton, pcg_tol, max_pcg, ccd_s, n_steps; g (3,)
 """
@@ -46,13 +50,13 @@ SCENE_KEYS = (
     "bv_xbar", "bv_body", "btri", "sv_x", "stri",
     "obj_kind", "excl",
     "sp_ka", "sp_ia", "sp_xa", "sp_kb", "sp_ib", "sp_xb", "sp_k",
-    "driven_body", "drive_q",
+    "driven_body", "drive_q", "joint_spring", "joint_xbar",
     "h", "g", "dhat", "kappa", "mu", "eps_v", "newton_tol", "max_newton",
     "pcg_tol", "max_pcg", "ccd_s", "n_steps",
 )
 
 INT_KEYS = {"tets", "vobj", "body_obj", "bv_body", "btri", "stri", "obj_kind",
-            "excl", "sp_ka", "sp_ia", "sp_kb", "sp_ib", "driven_body"}
+            "excl", "sp_ka", "sp_ia", "sp_kb", "sp_ib", "driven_body", "joint_spring"}
 
 
 # --------------------------------------------------------------------------
@@ -160,6 +164,13 @@ def rotz(a):
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
 
 
+def rot_axis(u, a):
+    """Rotation by angle a about the unit axis u (Rodrigues' formula)."""
+    u = np.asarray(u, np.float64) / np.linalg.norm(u)
+    K = np.array([[0.0, -u[2], u[1]], [u[2], 0.0, -u[0]], [-u[1], u[0], 0.0]])
+    return np.eye(3) + np.sin(a) * K + (1.0 - np.cos(a)) * (K @ K)
+
+
 # --------------------------------------------------------------------------
 # builder
 # --------------------------------------------------------------------------
@@ -176,6 +187,7 @@ class _Builder:
         self.nsv = 0
         self.springs = []
         self.driven = []
+        self.joints = []   # (spring index, (n_steps, 3) b-side body-frame points)
 
     def add_fem(self, X, tets, E, nu, rho):
         obj = len(self.obj_kind)
@@ -222,6 +234,13 @@ class _Builder:
     def add_spring(self, a, b, k):
         self.springs.append((a, b, float(k)))
 
+    def add_joint_spring(self, child, parent_body, xbar_traj, k):
+        """A spring from a child side (kind, index, point) to a point of the
+        parent body whose body-frame coordinates follow xbar_traj[n] at step n."""
+        xbar_traj = np.asarray(xbar_traj, np.float64)
+        self.joints.append((len(self.springs), xbar_traj))
+        self.springs.append((child, (1, parent_body, xbar_traj[0]), float(k)))
+
     def add_driven(self, body):
         self.driven.append(body)
         return len(self.driven) - 1
@@ -263,6 +282,10 @@ class _Builder:
         d.update(sp_ka=ka, sp_ia=ia, sp_xa=xa, sp_kb=kb, sp_ib=ib, sp_xb=xb, sp_k=kk)
         d["driven_body"] = np.array(self.driven, np.int32)
         d["drive_q"] = np.asarray(drive_q, np.float64).reshape(int(params["n_steps"]), len(self.driven), 12)
+        nst = int(params["n_steps"])
+        d["joint_spring"] = np.array([j for j, _ in self.joints], np.int32)
+        d["joint_xbar"] = (np.stack([t[:nst] for _, t in self.joints], 1) if self.joints else np.zeros((nst, 0, 3))).astype(np.float64)
+        d["joint_xbar"] = np.ascontiguousarray(d["joint_xbar"])
         for k, v in params.items():
             d[k] = np.asarray(v, np.float64)
         validate_scene(d)
@@ -356,6 +379,94 @@ def _add_gripper(b, rng, *, center_xy, z_mid, inner_half_gap, pad_cells, pad_E, 
     return drive, [p[0] for p in pads], bases
 
 
+# vertices of a regular tetrahedron of circumradius 1 cm centred on the origin:
+# four spring points whose first moment vanishes and whose second moment is
+# isotropic
+TETRA_PTS = 0.01 / np.sqrt(3.0) * np.array([[1.0, 1.0, 1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]])
+
+
+def _add_arm_gripper(b, rng, *, center_xy, z_mid, inner_half_gap, pad_cells, pad_E, pad_nu,
+                     k_c=1e4, k_F=1e6, k_J=1e5, n_steps, h, t_close, v_close, v_lift, pert=True, link_len=0.1):
+    """The gripper of _add_gripper on a joint-space arm: the fingers ride on
+    prismatic joints of the hand, the hand on a revolute wrist of a 7-link
+    revolute chain whose top link is anchored to the world (the only drive
+    target).  Each revolute joint is two springs on its axis at +-1 cm from
+    the joint centre (k_F) and two springs at +-1 cm along a normal of the
+    axis whose parent-side points follow the joint angle (k_J); each prismatic
+    joint, the finger mounts and the anchor are four springs on a regular
+    tetrahedron centred on the body (TETRA_PTS), whose parent-side points
+    follow the joint offset.  Every point set is centred on its joint, so a
+    load through the joint centre moves the bodies without turning them.  The chain hangs above the hand (axes z, x, z, x, z,
+    x, z from the top); the lift bends joints 2, 4, 6 by phi, -2 phi, phi so
+    the hand rises without turning; joints 1, 3, 5, 7 carry seeded yaw
+    perturbations.  Returns the drive trajectory (anchor only)."""
+    cx, cy = center_xy
+    psize = np.array([0.04, 0.02, 0.02])
+    pads = []
+    for side in (-1, 1):
+        ylo = cy + inner_half_gap if side > 0 else cy - inner_half_gap - psize[1]
+        lo = (cx - psize[0] / 2, ylo, z_mid - psize[2] / 2)
+        X, T = _pad(pad_cells, psize, lo)
+        obj, off = b.add_fem(X, T, pad_E, pad_nu, 1000.0)
+        outer = np.isclose(X[:, 1], ylo + (0.0 if side < 0 else psize[1]))
+        pads.append((obj, off, X, np.nonzero(outer)[0], side, ylo))
+    fingers, bases = [], []
+    for obj, off, X, att, side, ylo in pads:
+        y_face = ylo + (0.0 if side < 0 else psize[1])
+        base_c = np.array([cx, y_face + side * 0.002, z_mid])
+        base = b.add_body(base_c, (0.04, 0.004, 0.02), 0.05)
+        for i in att:
+            b.add_spring((0, off + i, np.zeros(3)), (1, base, X[i] - base_c), k_c)
+        fing_c = np.array([cx, y_face + side * 0.009, z_mid + 0.01])
+        fing = b.add_body(fing_c, (0.02, 0.01, 0.04), 0.1)
+        for a in TETRA_PTS:
+            P = fing_c + a
+            b.add_spring((1, base, P - base_c), (1, fing, P - fing_c), k_F)
+        bases.append(base)
+        fingers.append((fing, fing_c, side))
+    hand_c = np.array([cx, cy, z_mid + 0.05])
+    hand = b.add_body(hand_c, (0.1, 0.04, 0.03), 0.5)
+    chain = [(b.add_body(hand_c + np.array([0.0, 0.0, link_len * (7 - k)]), (0.06, 0.06, 0.1), 1.0),
+              hand_c + np.array([0.0, 0.0, link_len * (7 - k)])) for k in range(7)] + [(hand, hand_c)]
+    ex, ey, ez = np.eye(3)
+    axes = [ez, ex, ez, ex, ez, ex, ez]
+    # joint references at t_{n+1}
+    t = (np.arange(n_steps) + 1) * h
+    dz = v_lift * np.maximum(0.0, t - t_close)
+    phi = np.arccos(np.clip(1.0 - dz / (4.0 * link_len), -1.0, 1.0))
+    theta = np.zeros((n_steps, 7))
+    theta[:, 1], theta[:, 3], theta[:, 5] = phi, -2.0 * phi, phi
+    amp = rng.uniform(0.0, np.deg2rad(0.5), size=(4, 3)) if pert else np.zeros((4, 3))
+    freq = rng.uniform(0.5, 2.0, size=(4, 3))
+    phase = rng.uniform(0.0, 2 * np.pi, size=(4, 3))
+    for i, j in enumerate((0, 2, 4, 6)):
+        theta[:, j] += np.sum(amp[i] * (np.sin(2 * np.pi * freq[i] * t[:, None] + phase[i]) - np.sin(phase[i])), 1)
+    for j in range(7):
+        (P, cP), (C, cC) = chain[j], chain[j + 1]
+        O = 0.5 * (cP + cC)
+        u = axes[j]
+        v = ey if u is not ey else ez
+        v = v - u * (v @ u); v = v / np.linalg.norm(v)
+        for a in (O + 0.01 * u, O - 0.01 * u):
+            b.add_spring((1, C, a - cC), (1, P, a - cP), k_F)
+        for a in (O + 0.01 * v, O - 0.01 * v):
+            traj = np.array([(O - cP) + rot_axis(u, th) @ (a - O) for th in theta[:, j]])
+            b.add_joint_spring((1, C, a - cC), P, traj, k_J)
+    d_close = v_close * np.minimum(t, t_close)
+    for fing, fing_c, side in fingers:
+        inward = -side * ey
+        for a in fing_c + TETRA_PTS:
+            traj = (a - hand_c)[None, :] + d_close[:, None] * inward[None, :]
+            b.add_joint_spring((1, fing, a - fing_c), hand, traj, k_J)
+    top, c_top = chain[0]
+    slot = b.add_driven(top)
+    for a in TETRA_PTS:
+        b.add_spring((1, top, a), (2, slot, a), k_J)
+    drive = np.zeros((n_steps, 1, 12))
+    drive[:, 0] = np.concatenate([c_top, np.eye(3).T.ravel()])
+    return drive, [p[0] for p in pads], bases
+
+
 # --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------
@@ -383,6 +494,22 @@ def gripper_squeeze(seed=0, n_steps=200, pad_cells=(20, 10, 10), pad_E=2e5, mu=0
                                t_close=0.5, v_close=0.01, v_lift=0.02)
     b.add_static(*ground_quad())
     del box
+    p = _params(h=h, dhat=1e-3, mu=mu, n_steps=n_steps)
+    return b.finish(p, drive)
+
+
+def arm_squeeze(seed=0, n_steps=200, pad_cells=(20, 10, 10), pad_E=2e5, mu=0.5, h=0.005):
+    """The squeeze of gripper_squeeze on a joint-space arm (see _add_arm_gripper):
+    the box is squeezed by fingers on prismatic joints and lifted by bending
+    the chain, whose top link alone is anchored."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = _Builder()
+    cxy = (0.3, 0.3)
+    b.add_body((cxy[0], cxy[1], 0.02 + 5e-4), (0.04, 0.04, 0.04), 0.2, contact=True)
+    drive, _, _ = _add_arm_gripper(b, rng, center_xy=cxy, z_mid=0.02 + 5e-4, inner_half_gap=0.022,
+                                   pad_cells=pad_cells, pad_E=pad_E, pad_nu=0.47, n_steps=n_steps, h=h,
+                                   t_close=0.5, v_close=0.01, v_lift=0.02)
+    b.add_static(*ground_quad())
     p = _params(h=h, dhat=1e-3, mu=mu, n_steps=n_steps)
     return b.finish(p, drive)
 
@@ -441,6 +568,7 @@ def tiny_scene(kind="tet", seed=0, **kw):
     edge_tet one tetrahedron on an edge nearly parallel to the ground's diagonal
              edge (an active edge-edge mollifier)
     pad_box  a 2x1x1-cell pad squeezing a small affine box (springs, bodies, contact)
+    arm_box  pad_box's squeeze on the joint-space arm (joint springs)
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     b = _Builder()
@@ -464,6 +592,12 @@ def tiny_scene(kind="tet", seed=0, **kw):
         X = np.array([[0.005, -0.005, 0.0], [-0.005, 0.005 + 2.5e-4, 0.0],
                       [0.005, 0.005, 0.008], [-0.005, -0.005, 0.008]], np.float64) + [0.0, 0.0, 6e-4]
         b.add_fem(X, orient(X, np.array([[0, 1, 2, 3]], np.int32)), 1e5, 0.4, 1000.0)
+        b.add_static(*ground_quad())
+    elif kind == "arm_box":
+        b.add_body((0.3, 0.3, 0.01 + 5e-4), (0.02, 0.02, 0.02), 0.05, contact=True)
+        drive, _, _ = _add_arm_gripper(b, rng, center_xy=(0.3, 0.3), z_mid=0.01 + 5e-4, inner_half_gap=0.0115,
+                                       pad_cells=(4, 2, 2), pad_E=1e5, pad_nu=0.45, n_steps=int(p["n_steps"]),
+                                       h=p["h"], t_close=0.5, v_close=0.01, v_lift=0.02)
         b.add_static(*ground_quad())
     elif kind == "pad_box":
         b.add_body((0.3, 0.3, 0.01 + 5e-4), (0.02, 0.02, 0.02), 0.05, contact=True)

@@ -18,16 +18,20 @@ PTR_KEYS = ("X", "V", "tets", "tet_E", "tet_nu", "tet_rho", "vobj",
             "body_q", "body_qdot", "body_mass", "body_S", "body_vol", "body_kappa",
             "body_ext", "body_obj", "bv_xbar", "bv_body", "btri", "sv_x", "stri",
             "obj_kind", "excl", "sp_ka", "sp_ia", "sp_xa", "sp_kb", "sp_ib", "sp_xb",
-            "sp_k", "driven_body")
+            "sp_k", "driven_body", "joint_spring")
 
 
 def build(force=True):
     """Compile the oracle with gcc (no FMA contraction, OpenMP over elements)."""
     if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= os.path.getmtime(_SRC):
         return _SO
+    # build under a private name, then rename: processes that build at the same
+    # time never load a half-written library
+    tmp = f"{_SO}.{os.getpid()}.tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
-           "-o", _SO, _SRC, "-lm"]
+           "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, _SO)
     return _SO
 
 
@@ -116,7 +120,7 @@ def _f64(a):
 def scene_sizes(sc):
     return [len(sc["X"]), len(sc["tets"]), len(sc["body_q"]), len(sc["bv_xbar"]), len(sc["btri"]),
             len(sc["sv_x"]), len(sc["stri"]), len(sc["obj_kind"]), len(sc["excl"]), len(sc["sp_k"]),
-            len(sc["driven_body"])]
+            len(sc["driven_body"]), len(sc["joint_spring"])]
 
 
 def scene_params(sc):
@@ -195,10 +199,11 @@ class Oracle:
         return x
 
     def targets(self, n):
-        dq = self.scene["drive_q"]
-        if dq.shape[1] == 0:
+        """Drive targets of step n (nd x 12) followed by the joint-spring points (nj x 3)."""
+        dq, jx = self.scene["drive_q"], self.scene["joint_xbar"]
+        if dq.shape[1] == 0 and jx.shape[1] == 0:
             return None
-        return np.ascontiguousarray(dq[n])
+        return np.ascontiguousarray(np.concatenate([dq[n].ravel(), jx[n].ravel()]))
 
     def begin_step(self, n=None):
         n = self.step_index if n is None else n

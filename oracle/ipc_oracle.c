@@ -153,7 +153,7 @@ typedef struct {       /* friction data lagged at y^n (C10) */
 } OLag;
 
 struct OScene {
-    int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd;
+    int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd, nj;
     double *X, *V, *E, *nu, *rho;
     int *tets, *vobj;
     double *bq, *bqd, *bmass, *bS, *bvol, *bkappa, *bext;
@@ -163,6 +163,7 @@ struct OScene {
     int *sp_ka, *sp_ia, *sp_kb, *sp_ib;
     double *sp_xa, *sp_xb, *sp_k;
     int *driven;
+    int *joint_spring;           /* joint slot -> spring whose b-side point follows the joint reference */
     double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
     int max_newton, max_pcg;
     /* precompute (C1) */
@@ -255,7 +256,7 @@ OScene *or_create(const int *sz, const void *const *pp, const double *prm)
 {
     OScene *s = xcalloc(1, sizeof(OScene));
     s->nv = sz[0]; s->nt = sz[1]; s->nb = sz[2]; s->nbv = sz[3]; s->nbt = sz[4];
-    s->nsv = sz[5]; s->nst = sz[6]; s->nobj = sz[7]; s->nex = sz[8]; s->ns = sz[9]; s->nd = sz[10];
+    s->nsv = sz[5]; s->nst = sz[6]; s->nobj = sz[7]; s->nex = sz[8]; s->ns = sz[9]; s->nd = sz[10]; s->nj = sz[11];
     size_t D = sizeof(double), I = sizeof(int);
     s->X = dupmem(pp[0], D * 3 * s->nv);      s->V = dupmem(pp[1], D * 3 * s->nv);
     s->tets = dupmem(pp[2], I * 4 * s->nt);
@@ -273,6 +274,7 @@ OScene *or_create(const int *sz, const void *const *pp, const double *prm)
     s->sp_kb = dupmem(pp[25], I * s->ns); s->sp_ib = dupmem(pp[26], I * s->ns); s->sp_xb = dupmem(pp[27], D * 3 * s->ns);
     s->sp_k = dupmem(pp[28], D * s->ns);
     s->driven = dupmem(pp[29], I * s->nd);
+    s->joint_spring = dupmem(pp[30], I * s->nj);
     s->h = prm[0]; s->g[0] = prm[1]; s->g[1] = prm[2]; s->g[2] = prm[3];
     s->dhat = prm[4]; s->kappa = prm[5]; s->mu = prm[6]; s->eps_v = prm[7];
     s->newton_tol = prm[8]; s->max_newton = (int)prm[9]; s->pcg_tol = prm[10];
@@ -415,7 +417,7 @@ void or_destroy(OScene *s)
     if (!s) return;
     void *p[] = {s->X, s->V, s->E, s->nu, s->rho, s->tets, s->vobj, s->bq, s->bqd, s->bmass, s->bS, s->bvol,
                  s->bkappa, s->bext, s->bobj, s->bv_xbar, s->sv_x, s->bv_body, s->btri, s->stri, s->obj_kind,
-                 s->excl, s->sp_ka, s->sp_ia, s->sp_kb, s->sp_ib, s->sp_xa, s->sp_xb, s->sp_k, s->driven,
+                 s->excl, s->sp_ka, s->sp_ia, s->sp_kb, s->sp_ib, s->sp_xa, s->sp_xb, s->sp_k, s->driven, s->joint_spring,
                  s->Bm, s->vol, s->lmu, s->llam, s->mass, s->tri, s->edge, s->edge_rest2, s->cv_obj,
                  s->surf_v, s->y, s->ydot, s->xtilde, s->targets, s->lag};
     for (size_t i = 0; i < sizeof p / sizeof p[0]; ++i) free(p[i]);
@@ -1389,6 +1391,9 @@ void or_begin_step(OScene *s, const double *targets)
         for (int i = 0; i < 12; ++i) s->xtilde[o + i] = s->y[o + i] + h * s->ydot[o + i] + (i < 3 ? h * h * s->g[i] : 0.0);
     }
     if (targets && s->nd) memcpy(s->targets, targets, sizeof(double) * 12 * s->nd);
+    /* joint references: the b-side body-frame point of every joint spring */
+    if (targets)
+        for (int j = 0; j < s->nj; ++j) memcpy(s->sp_xb + 3 * (size_t)s->joint_spring[j], targets + 12 * (size_t)s->nd + 3 * j, 3 * sizeof(double));
     compute_lag(s);
 }
 

@@ -7,12 +7,12 @@
  * product path may link or call it.
  *
  * Marshalling: or_create() takes three arrays.
- *   sizes[11]  = nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd
- *   ptrs[30]   = X, V, tets, tet_E, tet_nu, tet_rho, vobj,
+ *   sizes[12]  = nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd, nj
+ *   ptrs[31]   = X, V, tets, tet_E, tet_nu, tet_rho, vobj,
  *                body_q, body_qdot, body_mass, body_S, body_vol, body_kappa,
  *                body_ext, body_obj, bv_xbar, bv_body, btri, sv_x, stri,
  *                obj_kind, excl, sp_ka, sp_ia, sp_xa, sp_kb, sp_ib, sp_xb,
- *                sp_k, driven_body            (layouts as in the scene dict)
+ *                sp_k, driven_body, joint_spring (layouts as in the scene dict)
  *   params[13] = h, gx, gy, gz, dhat, kappa(0 = automatic), mu, eps_v,
  *                newton_tol, max_newton, pcg_tol, max_pcg, ccd_s
  * All inputs are copied.  The DOF vector is y = [FEM vertices xyz ; per body
@@ -54,7 +54,9 @@ void    or_set_state(OScene *s, const double *y, const double *ydot);
 void    or_world(const OScene *s, const double *y, double *xw);
 
 /* Step set-up at the current state: predictive positions, drive targets
- * (nd x 12, may be NULL when nd == 0) and the friction lag at y^n. */
+ * (nd x 12, then nj x 3 joint-spring points: the b-side body-frame point of
+ * each joint spring for this step; may be NULL when nd == nj == 0) and the
+ * friction lag at y^n. */
 void    or_begin_step(OScene *s, const double *targets);
 /* Incremental potential at y; terms[7] = inertia, fem, abd, spring,
  * barrier, friction, total.  Returns the total (inf if some pair has d <= 0). */

@@ -104,8 +104,10 @@ class Sim:
         self._check(lib().ipc_set_state(self._h, _ptr(y), _ptr(v)))
 
     def targets(self, n):
-        """Drive targets of step n for all scenes, concatenated (nd x 12)."""
-        parts = [s["drive_q"][n] for s in self.scenes if s["drive_q"].shape[1] > 0]
+        """Targets of step n: the drive targets of all scenes (nd x 12), then the
+        joint-spring points of all scenes (nj x 3), concatenated."""
+        parts = [s["drive_q"][n].ravel() for s in self.scenes if s["drive_q"].shape[1] > 0]
+        parts += [s["joint_xbar"][n].ravel() for s in self.scenes if s["joint_xbar"].shape[1] > 0]
         if not parts:
             return None
         return self._as_dev(np.concatenate(parts, 0))

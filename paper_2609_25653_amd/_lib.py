@@ -43,7 +43,7 @@ class SceneDesc(ctypes.Structure):
         ("h", ctypes.c_double), ("g", ctypes.c_double * 3), ("dhat", ctypes.c_double), ("kappa", ctypes.c_double),
         ("mu", ctypes.c_double), ("eps_v", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("pcg_tol", ctypes.c_double), ("ccd_s", ctypes.c_double), ("max_newton", ctypes.c_int32),
-        ("max_pcg", ctypes.c_int32)]
+        ("max_pcg", ctypes.c_int32), ("nj", ctypes.c_int32), ("joint_spring", _I)]
 
 
 class Stats(ctypes.Structure):
@@ -102,7 +102,7 @@ def make_desc(sc, keep):
     d = SceneDesc()
     sizes = dict(nv=len(sc["X"]), nt=len(sc["tets"]), nb=len(sc["body_q"]), nbv=len(sc["bv_xbar"]),
                  nbt=len(sc["btri"]), nsv=len(sc["sv_x"]), nst=len(sc["stri"]), nobj=len(sc["obj_kind"]),
-                 nex=len(sc["excl"]), ns=len(sc["sp_k"]), nd=len(sc["driven_body"]))
+                 nex=len(sc["excl"]), ns=len(sc["sp_k"]), nd=len(sc["driven_body"]), nj=len(sc["joint_spring"]))
     for k, v in sizes.items():
         setattr(d, k, int(v))
     for name, typ in SceneDesc._fields_:

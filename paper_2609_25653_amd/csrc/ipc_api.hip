@@ -63,6 +63,13 @@ __global__ void k_negate(int64_t n, const double *__restrict__ a, double *__rest
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) b[i] = -a[i];
 }
+// joint slot j: the b-side body-frame point of spring joint_sp[j]
+__global__ void k_joint_points(int nj, const double *__restrict__ pts, const int *__restrict__ joint_sp, double *__restrict__ sp_xb)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nj) return;
+    for (int k = 0; k < 3; ++k) sp_xb[3 * (size_t)joint_sp[j] + k] = pts[3 * (size_t)j + k];
+}
 // line search set-up: the scene takes part when on[s]; step 1; CCD bound 1
 __global__ void k_ls_begin(int ns, const int *__restrict__ on, double *__restrict__ scal)
 {
@@ -322,6 +329,13 @@ void begin_step_impl(ipc_ctx *c, const double *targets_dev)
     hipStream_t st = c->stream;
     if (targets_dev && c->ND)
         IPC_HIP(hipMemcpyAsync(D.targets.p, targets_dev, 12 * (size_t)c->ND * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (targets_dev && c->NJ) {
+        // joint references: the b-side body-frame point of every joint
+        // spring, then the constant matrix part for the new points
+        hipLaunchKernelGGL(k_joint_points, dim3(blocks_for(c->NJ)), dim3(BLOCK), 0, st, c->NJ, targets_dev + 12 * (size_t)c->ND,
+                           D.joint_sp.p, D.sp_xb.p);
+        build_const_part(c, D.h2s.p);
+    }
     hipLaunchKernelGGL(k_predict, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.node_scene.p, D.is_trans.p,
                        D.sparam.p, D.grav.p, D.y.p, D.ydot.p, D.xt.p);
     pairs_from_scratch(c, D.y.p);
@@ -516,7 +530,7 @@ extern "C" int ipc_set_state(ipc_ctx *c, const double *y_dev, const double *ydot
 extern "C" int ipc_begin_step(ipc_ctx *c, const double *targets_dev)
 {
     if (!c) return IPC_E_INVALID;
-    if (c->ND && !targets_dev) { c->err = "targets required: the scenes have driven links"; return IPC_E_INVALID; }
+    if ((c->ND || c->NJ) && !targets_dev) { c->err = "targets required: the scenes have driven links or joint springs"; return IPC_E_INVALID; }
     return guard(c, [&] { begin_step_impl(c, targets_dev); });
 }
 
@@ -674,7 +688,7 @@ extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *
 {
     if (!c || !y_prev_dev || !ydot_prev_dev || !y_next_dev || !ybar_next_dev || !vbar_next_dev || !ybar_prev_dev || !vbar_prev_dev)
         return IPC_E_INVALID;
-    if (c->ND && !targets_dev) { c->err = "targets required: the scenes have driven links"; return IPC_E_INVALID; }
+    if ((c->ND || c->NJ) && !targets_dev) { c->err = "targets required: the scenes have driven links or joint springs"; return IPC_E_INVALID; }
     if (!(eta > 0.0)) { c->err = "eta must be > 0"; return IPC_E_INVALID; }
     int status = IPC_OK;
     int rc = guard(c, [&] {
@@ -900,7 +914,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
 extern "C" int ipc_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats_host)
 {
     if (!c) return IPC_E_INVALID;
-    if (c->ND && !targets_dev) { c->err = "targets required: the scenes have driven links"; return IPC_E_INVALID; }
+    if ((c->ND || c->NJ) && !targets_dev) { c->err = "targets required: the scenes have driven links or joint springs"; return IPC_E_INVALID; }
     int rc = guard(c, [&] { newton_step(c, targets_dev, stats_host); });
     if (rc != IPC_OK) return rc;
     if (c->last_status != IPC_OK) c->err = "a scene did not finish its step cleanly (see ipc_stats.status)";

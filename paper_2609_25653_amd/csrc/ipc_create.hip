@@ -130,6 +130,12 @@ __global__ void k_const_springs(int NS, const int *__restrict__ ka, const int *_
         }
 }
 
+__global__ void k_zero_vals(int64_t n, double *__restrict__ v)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) v[i] = 0.0;
+}
+
 __global__ void k_sum_mass(int nv, const double *__restrict__ mass, int node0, double *out)
 {
     // one block; fixed-order strided sums then a tree
@@ -197,6 +203,10 @@ void validate(const ipc_scene_desc &s, int si)
         if (!(s.sp_k[k] >= 0)) fail(pre + "negative spring stiffness");
     }
     for (int d = 0; d < s.nd; ++d) if (s.driven_body[d] < 0 || s.driven_body[d] >= s.nb) fail(pre + "bad driven body");
+    if (s.nj < 0 || (s.nj > 0 && !s.joint_spring)) fail(pre + "bad joint-spring count");
+    for (int j = 0; j < s.nj; ++j)
+        if (s.joint_spring[j] < 0 || s.joint_spring[j] >= s.ns || s.sp_kb[s.joint_spring[j]] != 1)
+            fail(pre + "joint spring " + std::to_string(j) + " is not a spring with a body point on its b side");
 }
 
 int pad64(int n) { return (n + TILE - 1) / TILE * TILE; }
@@ -251,6 +261,21 @@ HostTopo topology(const ipc_scene_desc &s)
 
 } // namespace
 
+void build_const_part(ipc_ctx *c, const double *h2s)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    int64_t nv = 9 * (int64_t)std::max(c->nnzb, 1);
+    hipLaunchKernelGGL(k_zero_vals, dim3(blocks_for(nv)), dim3(BLOCK), 0, st, nv, D.val_const.p);
+    hipLaunchKernelGGL(k_const_mass, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.diag_slot.p, D.mass.p,
+                       D.val_const.p);
+    if (c->NS > 0)
+        hipLaunchKernelGGL(k_const_springs, dim3(blocks_for(c->NS)), dim3(BLOCK), 0, st, c->NS, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
+                           D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, D.body_node0.p, D.row_ptr.p, D.col.p,
+                           D.val_const.p);
+}
+
+
 void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
 {
     hipStream_t st = c->stream;
@@ -259,27 +284,27 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     for (int s = 0; s < n; ++s) validate(scenes[s], s);
 
     // ---- offsets
-    int node = 0, tet = 0, body = 0, drv = 0, sp = 0, cv = 0, tri = 0, edge = 0, obj = 0, ex = 0;
+    int node = 0, tet = 0, body = 0, drv = 0, sp = 0, jt = 0, cv = 0, tri = 0, edge = 0, obj = 0, ex = 0;
     int64_t dof = 0;
     std::vector<HostTopo> topo(n);
     for (int s = 0; s < n; ++s) {
         const ipc_scene_desc &d = scenes[s];
         SceneInfo &S = c->sc[s];
         S.nv = d.nv; S.nt = d.nt; S.nb = d.nb; S.nbv = d.nbv; S.nbt = d.nbt; S.nsv = d.nsv; S.nst = d.nst;
-        S.nobj = d.nobj; S.nex = d.nex; S.ns = d.ns; S.nd = d.nd;
+        S.nobj = d.nobj; S.nex = d.nex; S.ns = d.ns; S.nd = d.nd; S.nj = d.nj;
         S.h = d.h; S.g[0] = d.g[0]; S.g[1] = d.g[1]; S.g[2] = d.g[2]; S.dhat = d.dhat; S.kappa = d.kappa; S.mu = d.mu;
         S.eps_v = d.eps_v; S.newton_tol = d.newton_tol; S.pcg_tol = d.pcg_tol; S.ccd_s = d.ccd_s;
         S.max_newton = d.max_newton; S.max_pcg = d.max_pcg;
         topo[s] = topology(d);
         S.node0 = node; S.nnode = d.nv + 4 * d.nb; S.nnode_pad = pad64(S.nnode);
         S.tet0 = tet; S.nt_pad = pad64(d.nt);
-        S.body0 = body; S.drv0 = drv; S.sp0 = sp;
+        S.body0 = body; S.drv0 = drv; S.sp0 = sp; S.jt0 = jt;
         S.cv0 = cv; S.ncv = (int)topo[s].surf.size(); S.nsurf = S.ncv;
         S.tri0 = tri; S.ntri = (int)topo[s].tri.size();
         S.edge0 = edge; S.nedge = (int)topo[s].edge.size();
         S.obj0 = obj;
         S.dof0 = dof;
-        node += S.nnode_pad; tet += S.nt_pad; body += d.nb; drv += d.nd; sp += d.ns; cv += S.ncv;
+        node += S.nnode_pad; tet += S.nt_pad; body += d.nb; drv += d.nd; sp += d.ns; jt += d.nj; cv += S.ncv;
         tri += S.ntri; edge += S.nedge; obj += d.nobj; ex += d.nex;
         dof += 3 * (int64_t)S.nnode;
         S.surf_ext = topo[s].surf;
@@ -289,7 +314,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         for (int k = 0; k < S.nedge; ++k) for (int m = 0; m < 2; ++m) S.edge_ext[2 * k + m] = topo[s].edge[k][m];
     }
     for (int s = 0; s < n; ++s) { c->NFEM += scenes[s].nv; c->TREAL += scenes[s].nt; }
-    c->N = node; c->T = tet; c->NB = body; c->ND = drv; c->NS = sp; c->CV = cv; c->NSURF = cv; c->TRI = tri;
+    c->N = node; c->T = tet; c->NB = body; c->ND = drv; c->NJ = jt; c->NS = sp; c->CV = cv; c->NSURF = cv; c->TRI = tri;
     c->EDGE = edge; c->NOBJ = obj; c->NEX = ex; c->ndof = dof; c->ext_nodes = dof / 3;
 
     // ---- host arrays
@@ -304,7 +329,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     std::vector<int> ska(sp), sia(sp), skb(sp), sib(sp), sscene(sp);
     std::vector<double> sxa(3 * (size_t)sp), sxb(3 * (size_t)sp), sk(sp);
     std::vector<double> targets(12 * (size_t)std::max(drv, 1), 0.0);
-    std::vector<int> driven(drv);
+    std::vector<int> driven(drv), joint_sp(jt);
     std::vector<int> cv_node(cv, -1), cv_body(cv, -1), cv_obj(cv), cv_scene(cv);
     std::vector<double> cv_x(3 * (size_t)cv, 0.0);
     std::vector<int4> tri4(tri);
@@ -358,6 +383,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
             for (int m = 0; m < 3; ++m) { sxa[3 * (size_t)g + m] = d.sp_xa[3 * k + m]; sxb[3 * (size_t)g + m] = d.sp_xb[3 * k + m]; }
             sk[g] = d.sp_k[k]; sscene[g] = s;
         }
+        for (int j = 0; j < d.nj; ++j) joint_sp[S.jt0 + j] = S.sp0 + d.joint_spring[j];
         for (int k = 0; k < d.nd; ++k) {
             driven[S.drv0 + k] = S.body0 + d.driven_body[k];
             for (int m = 0; m < 12; ++m) targets[12 * (size_t)(S.drv0 + k) + m] = d.body_q[12 * d.driven_body[k] + m];
@@ -520,7 +546,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     D.sp_ka.upload(ska, st); D.sp_ia.upload(sia, st); D.sp_kb.upload(skb, st); D.sp_ib.upload(sib, st);
     D.sp_scene.upload(sscene, st); D.sp_xa.upload(sxa, st); D.sp_xb.upload(sxb, st); D.sp_k.upload(sk, st);
     D.sp_part.alloc(std::max(sp, 1));
-    D.targets.upload(targets, st); D.driven_body.upload(driven, st);
+    D.targets.upload(targets, st); D.driven_body.upload(driven, st); D.joint_sp.upload(joint_sp, st);
     D.cv_node.upload(cv_node, st); D.cv_body.upload(cv_body, st); D.cv_obj.upload(cv_obj, st); D.cv_scene.upload(cv_scene, st);
     D.cv_x.upload(cv_x, st);
     D.xw.alloc(3 * (size_t)std::max(cv, 1)); D.xw1.alloc(3 * (size_t)std::max(cv, 1));
@@ -546,12 +572,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
         std::vector<double> h2s(n);
         for (int s = 0; s < n; ++s) h2s[s] = c->sc[s].h * c->sc[s].h;
         DBuf<double> dh2; dh2.upload(h2s, st);
-        hipLaunchKernelGGL(k_const_mass, dim3(blocks_for(node)), dim3(BLOCK), 0, st, node, D.node_kind.p, D.diag_slot.p, D.mass.p,
-                           D.val_const.p);
-        if (sp > 0)
-            hipLaunchKernelGGL(k_const_springs, dim3(blocks_for(sp)), dim3(BLOCK), 0, st, sp, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
-                               D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, dh2.p, D.body_node0.p, D.row_ptr.p, D.col.p,
-                               D.val_const.p);
+        build_const_part(c, dh2.p);
         // kappa (automatic: 10 * mean FEM vertex mass * |g| * h^2 / dhat)
         DBuf<double> msum; msum.alloc(n);
         for (int s = 0; s < n; ++s)

@@ -118,11 +118,11 @@ struct DBuf {
 
 struct SceneInfo {
     // sizes
-    int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd;
+    int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd, nj;
     // offsets into the concatenated device arrays
     int node0, nnode, nnode_pad;     // nodes: FEM vertices then 4 per body
     int tet0, nt_pad;
-    int body0, drv0, sp0;
+    int body0, drv0, sp0, jt0;       // bodies, driven slots, springs, joint springs
     int cv0, ncv, nsurf;             // contact vertices; the first nsurf are PT query points
     int tri0, ntri, edge0, nedge;
     int obj0;
@@ -173,6 +173,7 @@ struct Dev {
     DBuf<int> sp_ka, sp_ia, sp_kb, sp_ib, sp_scene;
     DBuf<double> sp_xa, sp_xb, sp_k;
     DBuf<double> targets;                  // 12 per driven slot
+    DBuf<int> joint_sp;                    // spring of every joint slot (its b-side point follows the joint reference)
     DBuf<int> driven_body;
     DBuf<double> sp_part;                  // per-spring values for reductions
     DBuf<double> body_part;
@@ -243,7 +244,7 @@ struct ipc_ctx {
     int n_scenes = 0;
     std::vector<ipc::SceneInfo> sc;
     int64_t ndof = 0;
-    int N = 0, T = 0, NB = 0, NS = 0, ND = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
+    int N = 0, T = 0, NB = 0, NS = 0, ND = 0, NJ = 0, CV = 0, NSURF = 0, TRI = 0, EDGE = 0, NOBJ = 0, NEX = 0;
     int64_t NFEM = 0, TREAL = 0;   // real FEM vertices and tetrahedra over all scenes
     int nnzb = 0, nnzb_fem = 0, n_long = 0;
     int long_cap = 0;                     // long-row workgroups the product launches (grows, multiple of 64)
@@ -308,7 +309,10 @@ void autotune_spmv(ipc_ctx *c, int reps, double *us);
 double spmv_bytes(const ipc_ctx *c);
 void build_preconditioner(ipc_ctx *c);
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
-void pcg_wginfo(ipc_ctx *c);   // refresh the step workgroups' scene records (after the long rows change)
+void pcg_wginfo(ipc_ctx *c);
+// constant part of the matrix (lumped mass, spring blocks) from the current
+// spring points; h2s: h^2 per scene
+void build_const_part(ipc_ctx *c, const double *h2s);   // refresh the step workgroups' scene records (after the long rows change)
 
 // Several device values to the host with one synchronisation, staged in the
 // context's pinned readback arena (asynchronous copies); reads that do not

@@ -31,11 +31,30 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_struct_layout_matches_header():
+def test_struct_layout_matches_header(tmp_path):
+    """Every field offset and the size of the ctypes records equal the C
+    compiler's for include/ipc.h."""
+    import subprocess
     from paper_2609_25653_amd import _lib
-    # 11 int32 sizes, 30 pointers, 11 doubles (h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s), 2 int32
-    assert ctypes.sizeof(_lib.SceneDesc) == 11 * 4 + 4 + 30 * 8 + 11 * 8 + 2 * 4
-    assert ctypes.sizeof(_lib.Stats) == 8 * 4 + 2 * 8
+    recs = {"ipc_scene_desc": _lib.SceneDesc, "ipc_stats": _lib.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ipc.h"', "int main(void) {"]
+    for cname, cls in recs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        rec, name, val = line.split()
+        got[(rec, name)] = int(val)
+    for cname, cls in recs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -72,3 +72,27 @@ def test_batched_squeeze_generator_small():
             part = yb[batch.dof_offsets[i]:batch.dof_offsets[i + 1]]
             L = sim.scene_scalars(0)["L"]
             assert np.abs(part - y1).max() <= 1e-6 * L, (k, i)   # FP64 atomics make the sum order vary
+
+
+def test_batched_arms_match_single_and_oracle():
+    """Scenes with joint springs batched with one without: each scene's
+    joint points come from its own slice of the per-step targets."""
+    from paper_2609_25653_amd import Sim
+    n = 10
+    scenes = [S.tiny_scene("arm_box", h=0.01, n_steps=n),
+              S.tiny_scene("pad_box", h=0.01, n_steps=n),
+              S.tiny_scene("arm_box", seed=4, h=0.01, n_steps=n)]
+    batch = Sim(scenes)
+    singles = [Sim(s) for s in scenes]
+    oracles = [O.Oracle(s) for s in scenes]
+    offs = batch.dof_offsets
+    for k in range(n):
+        rc, st = batch.step()
+        assert rc == 0, st
+        yb = batch.state()[0].cpu().numpy()
+        for i, (sim, o) in enumerate(zip(singles, oracles)):
+            assert sim.step()[0] == 0
+            assert o.step()[0] == 0
+            part = yb[offs[i]:offs[i + 1]]
+            assert np.abs(part - sim.state()[0].cpu().numpy()).max() <= 1e-6 * o.L, (k, i)
+            assert np.abs(part - o.state()[0]).max() <= 1e-6 * o.L, (k, i)

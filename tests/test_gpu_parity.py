@@ -22,6 +22,7 @@ CASES = {
     "block": (lambda: S.block_drop(n_steps=8), [0, 2, 6]),
     "cube": (lambda: S.tiny_scene("cube", h=0.01, n_steps=8), [0, 6]),
     "pad_box": (lambda: S.tiny_scene("pad_box", h=0.01, n_steps=34), [0, 20, 32]),
+    "arm_box": (lambda: S.tiny_scene("arm_box", h=0.01, n_steps=17), [0, 8, 16]),
 }
 
 
@@ -93,7 +94,7 @@ def test_ccd(name, states):
             assert a == pytest.approx(a_or, rel=1e-12, abs=1e-15), (name, k, scale, a, a_or)
 
 
-@pytest.mark.parametrize("name", ["block", "pad_box"])
+@pytest.mark.parametrize("name", ["block", "pad_box", "arm_box"])
 def test_pcg(name, states):
     from paper_2609_25653_amd import Sim
     sc, st = states[name]
@@ -108,10 +109,10 @@ def test_pcg(name, states):
     assert abs(int(it[0]) - it_or) <= max(2, it_or // 20)
 
 
-@pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34)])
+@pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34), ("arm_box", 30)])
 def test_trajectory(name, n):
     from paper_2609_25653_amd import Sim
-    sc = S.block_drop(n_steps=n) if name == "block" else S.tiny_scene("pad_box", h=0.01, n_steps=n)
+    sc = S.block_drop(n_steps=n) if name == "block" else S.tiny_scene(name, h=0.01, n_steps=n)
     sim = Sim(sc)
     o = O.Oracle(sc)
     L = o.L
