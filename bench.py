@@ -242,6 +242,55 @@ def bench_adjoint(args):
     print(json.dumps(line))
 
 
+def bench_arm(args):
+    """The squeeze on the joint-space arm (joint springs, only the top link
+    anchored) against the same squeeze on link-space target drives: steps
+    [warmup, warmup + steps) of each, timed alike."""
+    import numpy as np
+    import torch
+    import ipcscenes
+    from paper_2609_25653_amd import Sim
+    n_total = args.warmup + args.steps
+    out = {}
+    for name, sc in (("arm", ipcscenes.arm_squeeze(n_steps=n_total)),
+                     ("fk_targets", ipcscenes.gripper_squeeze(n_steps=n_total))):
+        sim = Sim(sc)
+        for _ in range(args.warmup):
+            sim.step(allow_status=(3,))
+        lanes, _ = sim.autotune(10)
+        torch.cuda.synchronize()
+        newton, pcg, not_ok = [], [], 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rc, st = sim.step(allow_status=(3,))
+            not_ok += st[0]["status"] != 0
+            newton.append(st[0]["newton_iters"])
+            pcg.append(st[0]["pcg_iters_total"])
+            print(f"# {name} step {sim.step_index}: rc={rc} newton={newton[-1]} pcg={pcg[-1]} "
+                  f"pairs={st[0]['n_pt_max'] + st[0]['n_ee_max']}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = dict(t=t, newton=newton, pcg=pcg, not_ok=not_ok, lanes=lanes, tets=len(sc["tets"]),
+                         bodies=len(sc["body_q"]), joint_springs=len(sc["joint_spring"]), drive_slots=len(sc["driven_body"]))
+        del sim
+    a, f = out["arm"], out["fk_targets"]
+    line = {
+        "metric": "Newton iterations/s", "value": sum(a["newton"]) / a["t"], "unit": "Newton it/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * a["t"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"squeeze on the joint-space arm, steps {args.warmup}-{n_total - 1}", "tets": a["tets"],
+                   "bodies": a["bodies"], "joint_springs": a["joint_springs"], "drive_slots": a["drive_slots"],
+                   "parallelism": "single GPU"},
+        "steps_per_s": args.steps / a["t"], "newton_per_step": a["newton"], "pcg_per_step": a["pcg"],
+        "steps_not_converged": a["not_ok"], "spmv_lanes_per_row": a["lanes"],
+        "fk_targets": {"workload": "the same squeeze on link-space target drives", "tets": f["tets"],
+                       "newton_it_per_s": sum(f["newton"]) / f["t"], "steps_per_s": args.steps / f["t"],
+                       "ms_per_step": 1e3 * f["t"] / args.steps, "newton_per_step": f["newton"],
+                       "pcg_per_step": f["pcg"], "steps_not_converged": f["not_ok"]},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,9 +298,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=8e-4, help="ground patch spacing (m): 0.8 mm keeps the median active pairs inside 50k-300k")
-    ap.add_argument("--workload", choices=["contact", "batched", "adjoint"], default="contact",
+    ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm"], default="contact",
                     help="contact: the 200k-tet squeeze (default line); batched: 256 uneven squeeze scenes stepped "
-                         "together vs one at a time; adjoint: 50-step squeeze rollout, forward vs backward time")
+                         "together vs one at a time; adjoint: 50-step squeeze rollout, forward vs backward time; "
+                         "arm: the squeeze on the joint-space arm vs on link-space target drives")
     ap.add_argument("--scenes", type=int, default=256, help="batched: number of scenes")
     ap.add_argument("--single-sample", type=int, default=16, help="batched: scenes stepped one at a time for the baseline")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -279,6 +329,8 @@ def main():
         return bench_batched(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "arm":
+        return bench_arm(args)
     n_total = args.warmup + args.steps
     scene = ipcscenes.contact_rich(n_steps=n_total, s_g=args.s_g)
     sim = Sim(scene)
