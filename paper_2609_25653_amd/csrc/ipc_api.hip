@@ -243,6 +243,7 @@ void setup_after_create(ipc_ctx *c)
     upload_seg_region(c, R_SURF, c->seg_surf);
     upload_seg_region(c, R_TRI, c->seg_tri);
     upload_seg_region(c, R_EDGE, c->seg_edge);
+    upload_seg_region(c, R_CDOM, c->seg_cdom);
     build_dyn_blocks(c);   // no pairs yet: row pointers and the long rows of the static pattern
     sync(c);
 }
@@ -449,6 +450,8 @@ extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_
             int L = std::atoi(nl);
             if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) c->spmv_lanes = L;
         }
+        const char *nc = std::getenv("IPC_PCG_COARSE");
+        c->coarse = !(nc && nc[0] == '0');
         if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
     }
     int rc = guard(c, [&] {

@@ -530,6 +530,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     for (auto *b : {&D.xt, &D.y0, &D.yt, &D.g, &D.p, &D.r, &D.z, &D.q, &D.w, &D.x, &D.v1, &D.v2}) b->alloc(3 * (size_t)node);
     IPC_HIP(hipMemcpyAsync(D.xt.p, D.y.p, 3 * (size_t)node * sizeof(double), hipMemcpyDeviceToDevice, st));
     D.node_scene.upload(node_scene, st); D.node_kind.upload(node_kind, st); D.ext2node.upload(ext2node, st);
+    coarse_setup(c, X);   // groups and domains of the coarse preconditioner from the initial positions
     D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node);
     D.tv.upload(tv, st);
     D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);

@@ -19,6 +19,9 @@ namespace ipc {
 
 constexpr int TILE = 64;      // wavefront size on CDNA
 constexpr int BLOCK = 256;    // default workgroup: 4 wavefronts
+constexpr int CG_AGG = 32;    // coarse preconditioner: nodes per group
+constexpr int CG_DOM = 32;    // groups per coarse domain
+constexpr int CG_N = 3 * CG_DOM;   // coarse unknowns per domain
 constexpr int LONG_ROW = 64;  // rows with more blocks go to the wavefront-per-row path
 
 // per-scene device scalar slots
@@ -46,6 +49,7 @@ enum Region {
     R_PT, R_EE,     // active pairs
     R_LPT, R_LEE,   // friction lag lists
     R_LONG,         // rows of the product handled one wavefront per row
+    R_CDOM,         // domains of the coarse preconditioner
     NREGION
 };
 
@@ -229,7 +233,13 @@ struct Dev {
     // eta^2 b.b, r.r}, running flag and update count; per-tile partials of
     // r.z and r.r
     DBuf<double> pcg_st, pcg_part, pcg_prev;   // pcg_prev: r.r at the previous peek
-    DBuf<int> pcg_wginfo;                  // per step workgroup: scenes and the first scene's ranges (6 ints)
+    DBuf<int> pcg_wginfo;                  // per step workgroup: scenes and the first scene's ranges (8 ints)
+    // coarse preconditioner: per domain its entry range (ent, n_cdom + 1) into
+    // the node list (groups of CG_AGG consecutive entries), its scene, its
+    // inverse (CG_N x CG_N) and r . z partials of both parities; per node
+    // domain * CG_DOM + group, or -1 for nodes outside every group
+    DBuf<int> cg_ent, cg_nodes, cg_node_da, cg_dom_scene;
+    DBuf<double> cg_inv, cg_part;
     DBuf<int> pcg_act, pcg_it;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
     DBuf<int> tickets;                     // small device counters
@@ -250,6 +260,9 @@ struct ipc_ctx {
     int long_cap = 0;                     // long-row workgroups the product launches (grows, multiple of 64)
     int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
+    bool coarse = true;                   // coarse correction in the PCG preconditioner
+    int n_cdom = 0;                       // its domains over all scenes
+    std::vector<int> seg_cdom;            // per scene: first domain (n_scenes + 1)
     int64_t ext_nodes = 0;
     int64_t ext_tets = 0;
     // host copies of segment tables
@@ -308,6 +321,13 @@ void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, dou
 void autotune_spmv(ipc_ctx *c, int reps, double *us);
 double spmv_bytes(const ipc_ctx *c);
 void build_preconditioner(ipc_ctx *c);
+// coarse correction of the preconditioner: groups and domains from node
+// positions at creation; the domains' inverses after an assembly; z += its
+// correction of r for the scenes whose act entry is set, r . z partials into
+// the given parity
+void coarse_setup(ipc_ctx *c, const std::vector<double> &X);
+void coarse_build(ipc_ctx *c);
+void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int parity);
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
 void pcg_wginfo(ipc_ctx *c);
 // constant part of the matrix (lumped mass, spring blocks) from the current

@@ -402,6 +402,7 @@ void build_preconditioner(ipc_ctx *c)
         hipLaunchKernelGGL(k_prec_body, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.bslot.p, D.body_node0.p, D.val.p,
                            D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p,
                            D.dinvB.p);
+    coarse_build(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,8 +424,10 @@ constexpr int WG_TILES = BLOCK / TILE;   // node tiles per step workgroup
 
 // Sums of up to three per-tile sources and one per-long-row source over a
 // scene's ranges; every thread of the workgroup returns the same totals.
-__device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, const double *__restrict__ a, const double *__restrict__ b,
-                                           const double *__restrict__ c, const double *__restrict__ cl, double (*sh)[WG_TILES],
+// (ca: per-domain partials added to the first sum, over [clo, chi))
+__device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, int clo, int chi, const double *__restrict__ a,
+                                           const double *__restrict__ b, const double *__restrict__ c,
+                                           const double *__restrict__ cl, const double *__restrict__ ca, double (*sh)[WG_TILES],
                                            double &ta, double &tb, double &tc)
 {
     double va = 0.0, vb = 0.0, vc = 0.0;
@@ -435,6 +438,8 @@ __device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, con
     }
     if (cl)
         for (int i = llo + (int)threadIdx.x; i < lhi; i += BLOCK) vc += cl[i];
+    if (ca)
+        for (int i = clo + (int)threadIdx.x; i < chi; i += BLOCK) va += ca[i];
     va = wave_sum(va); vb = wave_sum(vb); vc = wave_sum(vc);
     int wave = threadIdx.x / TILE;
     if ((threadIdx.x & (TILE - 1)) == 0) { sh[0][wave] = va; sh[1][wave] = vb; sh[2][wave] = vc; }
@@ -450,26 +455,28 @@ __device__ __forceinline__ d3 mat3v(const double *__restrict__ M, d3 v)
     return {M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z, M[6] * v.x + M[7] * v.y + M[8] * v.z};
 }
 
-// Per step workgroup: its first and last scene and the first scene's tile
-// and long-row ranges (refreshed whenever the long rows change).
+// Per step workgroup: its first and last scene and the first scene's tile,
+// long-row and coarse-domain ranges (refreshed whenever the long rows change).
+constexpr int WGI = 8;
 __global__ void k_pcg_wginfo(int nwg, int ntile, const int *__restrict__ tile_scene, const int *__restrict__ seg_nodew,
-                             const int *__restrict__ seg_long, int *__restrict__ info)
+                             const int *__restrict__ seg_long, const int *__restrict__ seg_cdom, int *__restrict__ info)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nwg) return;
     int t0 = b * WG_TILES, lo = tile_scene[t0], hi = tile_scene[min(t0 + WG_TILES, ntile) - 1];
-    int *o = info + 6 * (size_t)b;
+    int *o = info + WGI * (size_t)b;
     o[0] = lo; o[1] = hi;
     o[2] = seg_nodew[lo]; o[3] = seg_nodew[lo + 1];
     o[4] = seg_long[lo]; o[5] = seg_long[lo + 1];
+    o[6] = seg_cdom[lo]; o[7] = seg_cdom[lo + 1];
 }
 
 void pcg_wginfo(ipc_ctx *c)
 {
     int ntile = c->N / TILE, nwg = blocks_for(c->N);
-    c->d.pcg_wginfo.alloc(6 * (size_t)nwg);
+    c->d.pcg_wginfo.alloc(WGI * (size_t)nwg);
     hipLaunchKernelGGL(k_pcg_wginfo, dim3(blocks_for(nwg)), dim3(BLOCK), 0, c->stream, nwg, ntile, c->d.tile_scene_node.p,
-                       seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), c->d.pcg_wginfo.p);
+                       seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM), c->d.pcg_wginfo.p);
 }
 
 // x = 0, r = b, p = s = 0, z = M^-1 r; partials of r.z and r.r per tile
@@ -538,7 +545,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_init(int N, int ns, const int *__
 // (updates done).  part holds [r.z | r.r] for parity 0 then parity 1.
 __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const int *__restrict__ kind, const int *__restrict__ node_body,
                                                     const int *__restrict__ tile_scene, const int *__restrict__ seg_nodew,
-                                                    const int *__restrict__ seg_long, const int *__restrict__ wginfo,
+                                                    const int *__restrict__ seg_long, const int *__restrict__ seg_cdom,
+                                                    const int *__restrict__ wginfo, const double *__restrict__ cg_part, int ncdom,
                                                     const int *__restrict__ maxit, const double *__restrict__ dinv,
                                                     const double *__restrict__ dinvB, const double *__restrict__ w, double *__restrict__ p,
                                                     double *__restrict__ s, double *__restrict__ x, double *__restrict__ r,
@@ -567,7 +575,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     double *rz_out = part + (size_t)(2 * (q ^ 1)) * ntile, *rr_out = rz_out + ntile;
     // the workgroup's scenes and the first one's tile and long-row ranges in
     // one record, so the partials' loads wait for a single load
-    const int *wi = wginfo + 6 * (size_t)blockIdx.x;
+    const int *wi = wginfo + WGI * (size_t)blockIdx.x;
+    const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction
     const int sc_lo = wi[0], sc_hi = wi[1];
     const int my_sc = t < ntile ? tile_scene[t] : -1;
     double al = 0.0, be = 0.0;
@@ -576,6 +585,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         const bool first = sc == sc_lo;
         const int tlo = first ? wi[2] : seg_nodew[sc], thi = first ? wi[3] : seg_nodew[sc + 1];
         const int llo = first ? wi[4] : seg_long[sc], lhi = first ? wi[5] : seg_long[sc + 1];
+        const int clo = first ? wi[6] : seg_cdom[sc], chi = first ? wi[7] : seg_cdom[sc + 1];
         const int a = act[q * ns + sc], itc = it[q * ns + sc];
         const double *S = st + ((size_t)q * ns + sc) * 4;
         const bool writer = tlo / WG_TILES == (int)blockIdx.x && threadIdx.x == 0;
@@ -589,7 +599,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
             continue;
         }
         double gam, rr, del;
-        block_sums(tlo, thi, llo, lhi, rz_in, rr_in, part_zw, part_long, sh, gam, rr, del);
+        block_sums(tlo, thi, llo, lhi, clo, chi, rz_in, rr_in, part_zw, part_long, cz_in, sh, gam, rr, del);
         // gamma = r.z, delta = z.Az of the current residual:
         //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
         //   alpha = gamma / p.Ap
@@ -674,7 +684,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_peek(int ns, int q, const int *__
     if (a) {
         const double *rz_in = part + (size_t)(2 * q) * ntile;
         double g, d;
-        block_sums(seg_nodew[sc], seg_nodew[sc + 1], 0, 0, rz_in, rz_in + ntile, nullptr, nullptr, sh, g, rr, d);
+        block_sums(seg_nodew[sc], seg_nodew[sc + 1], 0, 0, 0, 0, rz_in, rz_in + ntile, nullptr, nullptr, nullptr, sh, g, rr, d);
         live = a == 2 || !(rr <= st[((size_t)q * ns + sc) * 4 + 2] || itc >= maxit[sc]);
     }
     if (threadIdx.x != 0) return;
@@ -713,6 +723,7 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
     hipLaunchKernelGGL(k_pcg_init, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, ns, D.node_kind.p, D.node_body.p,
                        D.tile_scene_node.p, seg_ptr(c, R_NODEW), b, D.dinv.p, D.dinvB.p, x, r, z, p, s, D.pcg_part.p, ntile, want, eta,
                        D.sparam.p, D.pcg_st.p, D.pcg_prev.p, act, D.pcg_it.p, D.pcg_iters.p, D.scal.p);
+    coarse_apply(c, act, r, z, 0);              // z += the coarse correction of r, its r . z partials
     hess_apply(c, z, w, act, D.part_node3.p);   // w = A z and z . w for the first step
     int maxit = 0;
     for (auto &S : c->sc) maxit = std::max(maxit, S.max_pcg);
@@ -721,9 +732,11 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
     auto iteration = [&](int q) {
         prof_begin(c, IPC_K_PCG_UPDATE);
         hipLaunchKernelGGL(k_pcg_step, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p, D.node_body.p,
-                           D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), D.pcg_wginfo.p, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
+                           D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM), D.pcg_wginfo.p,
+                           D.cg_part.p, c->n_cdom, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
                            r, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
+        coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
         hess_apply(c, z, w, act + (q ^ 1) * ns, D.part_node3.p);
     };
     // The peek kernel publishes one word per scene into pinned, coherent host
@@ -783,7 +796,8 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                                       (uintptr_t)D.pcg_it.p, (uintptr_t)D.scal.p, (uintptr_t)D.long_count.p, (uintptr_t)D.long_rows.p,
                                       (uintptr_t)D.row_ptr.p, (uintptr_t)D.col.p, (uintptr_t)D.val.p, (uintptr_t)D.dyn_ptr.p,
                                       (uintptr_t)D.dyn_col.p, (uintptr_t)D.dyn_val.p, (uintptr_t)D.node_scene.p,
-                                      (uintptr_t)D.pcg_wginfo.p};
+                                      (uintptr_t)D.pcg_wginfo.p, (uintptr_t)c->n_cdom, (uintptr_t)D.cg_ent.p, (uintptr_t)D.cg_nodes.p,
+                                      (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p};
         bool have = key == c->pcg_key;
         for (auto xg : c->pcg_exec) have = have && xg;
         if (!have) {

@@ -94,9 +94,15 @@ def test_ccd(name, states):
             assert a == pytest.approx(a_or, rel=1e-12, abs=1e-15), (name, k, scale, a, a_or)
 
 
+@pytest.mark.parametrize("coarse", [False, True])
 @pytest.mark.parametrize("name", ["block", "pad_box", "arm_box"])
-def test_pcg(name, states):
+def test_pcg(name, coarse, states, monkeypatch):
+    """The solution of H x = b agrees with the oracle's PCG.  With the block-
+    Jacobi preconditioner alone (the coarse correction switched off) the
+    iteration counts agree too; with the coarse correction they may only
+    drop."""
     from paper_2609_25653_amd import Sim
+    monkeypatch.setenv("IPC_PCG_COARSE", "1" if coarse else "0")
     sc, st = states[name]
     sim = Sim(sc)
     o = O.Oracle(sc)
@@ -106,7 +112,10 @@ def test_pcg(name, states):
     x, it = sim.pcg(y, b, 1e-12)
     x_or, it_or = o.pcg(y, b, 1e-12)
     assert np.linalg.norm(to_np(x) - x_or) <= 1e-9 * np.linalg.norm(x_or)
-    assert abs(int(it[0]) - it_or) <= max(2, it_or // 20)
+    if coarse:
+        assert int(it[0]) <= it_or + 2, (int(it[0]), it_or)
+    else:
+        assert abs(int(it[0]) - it_or) <= max(2, it_or // 20)
 
 
 @pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34), ("arm_box", 30)])
