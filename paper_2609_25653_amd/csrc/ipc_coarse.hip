@@ -47,7 +47,7 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
 {
     const int ns = c->n_scenes;
     c->seg_cdom.assign(ns + 1, 0);
-    std::vector<int> ent, nodes, dom_scene, node_da(c->N, -1);
+    std::vector<int> ent, nodes, dom_scene, grp, node_da(c->N, -1);
     int ndom = 0;
     for (int s = 0; s < ns; ++s) {
         c->seg_cdom[s] = ndom;
@@ -81,61 +81,88 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
                 dom_scene.push_back(s);
                 ++ndom;
             }
-            node_da[part[ord[m]]] = (ndom - 1) * CG_DOM + (int)(m % per_dom) / CG_AGG;
+            const int g = (ndom - 1) * CG_DOM + (int)(m % per_dom) / CG_AGG;
+            if (m % CG_AGG == 0) grp.push_back(g);
+            node_da[part[ord[m]]] = g;
             nodes.push_back(part[ord[m]]);
         }
     }
     c->seg_cdom[ns] = ndom;
     ent.push_back((int)nodes.size());   // ndom + 1 offsets
     c->n_cdom = ndom;
+    c->n_cgrp = (int)grp.size();
     Dev &D = c->d;
+    D.cg_grp.upload(grp.empty() ? std::vector<int>(1, 0) : grp, c->stream);
     D.cg_ent.upload(ent, c->stream);
     D.cg_nodes.upload(nodes.empty() ? std::vector<int>(1, 0) : nodes, c->stream);
     D.cg_node_da.upload(node_da, c->stream);
     D.cg_dom_scene.upload(dom_scene.empty() ? std::vector<int>(1, 0) : dom_scene, c->stream);
+    // zero once: the entries past a short domain's n are never written and
+    // are read as 0 by the product with the inverse
     D.cg_inv.alloc((size_t)std::max(ndom, 1) * CG_N * CG_N);
+    D.cg_inv.zero(c->stream, (size_t)std::max(ndom, 1) * CG_N * CG_N);
     D.cg_part.alloc(2 * (size_t)std::max(ndom, 1));
 }
 
-// The domains' blocks of P^T A P, summed into cg_mat (zeroed before): one
-// thread per matrix row of a grouped node adds the 3x3 blocks whose column
-// node lies in a group of the same domain (block-CSR row and pair-local row).
-__global__ void k_coarse_assemble(int N, const int *__restrict__ node_da, const int *__restrict__ row_ptr,
-                                  const int *__restrict__ col, const double *__restrict__ val, const int *__restrict__ dptr,
-                                  const int *__restrict__ dcol, const double *__restrict__ dval, double *__restrict__ mat)
+// The domains' blocks of P^T A P: one workgroup per group (32 rows of 8
+// lanes) sums, in LDS, the 3x3 blocks of its nodes' rows (block-CSR and
+// pair-local) whose column node lies in a group of the same domain, then
+// stores the group's 3 rows of its domain's block (all CG_N columns; a
+// group owns its rows, so no other workgroup writes them).
+constexpr int CG_ASM = 256, CG_LPR = CG_ASM / CG_AGG;   // lanes per row
+__global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restrict__ grp, const int *__restrict__ ent,
+                                                            const int *__restrict__ nodes, const int *__restrict__ node_da,
+                                                            const int *__restrict__ row_ptr, const int *__restrict__ col,
+                                                            const double *__restrict__ val, const int *__restrict__ dptr,
+                                                            const int *__restrict__ dcol, const double *__restrict__ dval,
+                                                            double *__restrict__ mat)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int ti = node_da[i];
-    if (ti < 0) return;
-    const int d = ti / CG_DOM, a = ti % CG_DOM;
-    double *M = mat + (size_t)d * CG_N * CG_N + 3 * a * CG_N;
-    auto add = [&](int j, const double *__restrict__ B) {
-        const int tj = node_da[j];
-        if (tj < 0 || tj / CG_DOM != d) return;
-        double *o = M + 3 * (tj % CG_DOM);
+    __shared__ double S[3 * CG_N];
+    const int g = grp[blockIdx.x], d = g / CG_DOM, a = g % CG_DOM;
+    for (int q = threadIdx.x; q < 3 * CG_N; q += CG_ASM) S[q] = 0.0;
+    __syncthreads();
+    const int e = ent[d] + a * CG_AGG + (int)threadIdx.x / CG_LPR, sub = threadIdx.x % CG_LPR;
+    if (e < ent[d + 1]) {
+        const int i = nodes[e];
+        auto add = [&](int j, const double *__restrict__ B) {
+            const int tj = node_da[j];
+            if (tj < 0 || tj / CG_DOM != d) return;
+            double *o = S + 3 * (tj % CG_DOM);
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
+            for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) atomicAdd(&o[r * CG_N + k], B[3 * r + k]);
-    };
-    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) add(col[k], val + 9 * (size_t)k);
-    for (int k = dptr[i]; k < dptr[i + 1]; ++k) add(dcol[k], dval + 9 * (size_t)k);
+                for (int k = 0; k < 3; ++k) atomicAdd(&o[r * CG_N + k], B[3 * r + k]);
+        };
+        for (int k = row_ptr[i] + sub; k < row_ptr[i + 1]; k += CG_LPR) add(col[k], val + 9 * (size_t)k);
+        for (int k = dptr[i] + sub; k < dptr[i + 1]; k += CG_LPR) add(dcol[k], dval + 9 * (size_t)k);
+    }
+    __syncthreads();
+    double *G = mat + (size_t)d * CG_N * CG_N + (size_t)(3 * a) * CG_N;   // rows 3a .. 3a + 2, contiguous
+    for (int q = threadIdx.x; q < 3 * CG_N; q += CG_ASM) G[q] = S[q];
 }
 
 // One workgroup per domain: the inverse of its n x n block (n = 3 x groups)
 // by Gauss-Jordan elimination without pivoting in LDS (the pivots of an SPD
-// matrix are positive), written over the block.  A domain whose block shows
-// a pivot that is not positive (the unprojected Hessian of the adjoint can
-// be indefinite) gets a zero inverse: there the preconditioner is block-
-// Jacobi alone.
-constexpr int CG_INV = 512;
+// matrix are positive), written over the block.  The block is padded to
+// CG_N with the identity, which stays decoupled, so every thread keeps the
+// same CG_N^2 / CG_INV entries for all pivots.  A domain whose block shows a
+// pivot that is not positive (the unprojected Hessian of the adjoint can be
+// indefinite) gets a zero inverse: there the preconditioner is block-Jacobi
+// alone.
+constexpr int CG_INV = 1024, CG_PER = CG_N * CG_N / CG_INV;
+static_assert(CG_N * CG_N % CG_INV == 0, "whole entries per thread");
 __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict__ ent, double *__restrict__ mat)
 {
     __shared__ double A[CG_N * CG_N];
     const int d = blockIdx.x, ne = ent[d + 1] - ent[d], n = 3 * ((ne + CG_AGG - 1) / CG_AGG);
     double *G = mat + (size_t)d * CG_N * CG_N;
-    for (int q = threadIdx.x; q < n * n; q += CG_INV) A[(q / n) * CG_N + q % n] = G[(q / n) * CG_N + q % n];
+    int qi[CG_PER], qj[CG_PER];
+#pragma unroll
+    for (int m = 0; m < CG_PER; ++m) {
+        const int q = threadIdx.x + m * CG_INV;
+        qi[m] = q / CG_N; qj[m] = q % CG_N;
+        A[q] = (qi[m] < n && qj[m] < n) ? G[q] : (qi[m] == qj[m] ? 1.0 : 0.0);
+    }
     __syncthreads();
     bool bad = false;
     for (int k = 0; k < n; ++k) {
@@ -143,30 +170,29 @@ __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict_
         if (!(piv > 0.0)) { bad = true; break; }   // uniform: every thread reads the same pivot
         const double ip = 1.0 / piv;
         // A[i][j] -= A[i][k] A[k][j] / piv for i, j != k (row and column k are only read)
-        for (int q = threadIdx.x; q < n * n; q += CG_INV) {
-            const int i = q / n, j = q % n;
-            if (i != k && j != k) A[i * CG_N + j] -= A[i * CG_N + k] * A[k * CG_N + j] * ip;
-        }
+#pragma unroll
+        for (int m = 0; m < CG_PER; ++m)
+            if (qi[m] != k && qj[m] != k) A[qi[m] * CG_N + qj[m]] -= A[qi[m] * CG_N + k] * A[k * CG_N + qj[m]] * ip;
         __syncthreads();
-        if (threadIdx.x < n && (int)threadIdx.x != k) {
-            A[k * CG_N + threadIdx.x] *= ip;
-            A[threadIdx.x * CG_N + k] *= -ip;
-        } else if ((int)threadIdx.x == k) {
-            A[k * CG_N + k] = ip;
+        const int t = threadIdx.x;
+        if (t < n) {
+            if (t != k) { A[k * CG_N + t] *= ip; A[t * CG_N + k] *= -ip; }
+            else A[k * CG_N + k] = ip;
         }
         __syncthreads();
     }
-    for (int q = threadIdx.x; q < n * n; q += CG_INV) {
-        const int i = q / n, j = q % n;
-        G[i * CG_N + j] = bad ? 0.0 : A[i * CG_N + j];
-    }
+#pragma unroll
+    for (int m = 0; m < CG_PER; ++m)
+        if (qi[m] < n && qj[m] < n) G[threadIdx.x + m * CG_INV] = bad ? 0.0 : A[threadIdx.x + m * CG_INV];
 }
 
 // One workgroup per domain of a scene that updated its residual (act != 0):
 // rc = P^T r over the domain's groups, zc = C^-1 rc, z += P zc, and the
-// partial rc . zc (= r . P zc) into part[d].  Every stage spreads over the
-// whole workgroup: a group is 32 consecutive entries, i.e. half a wavefront
-// of one pass over the entries.
+// partial rc . zc (= r . P zc) into part[d].  The stages are latency-bound,
+// so every load that does not wait for another is issued first: the
+// inverse's columns (entries past a short domain's n are 0), the scene's
+// flag, then the entries' r and z.  A group is 32 consecutive entries, i.e.
+// half a wavefront of one pass over the entries.
 constexpr int CG_APPLY = 256;
 constexpr int CG_PASSES = CG_AGG * CG_DOM / CG_APPLY;
 __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict__ ent, const int *__restrict__ nodes,
@@ -175,21 +201,33 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict
                                                            double *__restrict__ z, double *__restrict__ part)
 {
     static_assert(CG_APPLY == 4 * TILE && CG_N == 96, "four wavefronts of 24 columns");
-    __shared__ double rc[CG_N], zc[CG_N], zp[CG_APPLY / TILE][CG_N], sh[CG_APPLY / TILE];
-    const int d = blockIdx.x;
-    if (!act[dom_scene[d]]) return;   // uniform over the workgroup
+    constexpr int KW = CG_N / (CG_APPLY / TILE);   // 24 columns per wavefront
+    __shared__ double rc[CG_N], zp[CG_APPLY / TILE][CG_N], zc[CG_N], sh[CG_APPLY / TILE];
+    const int d = blockIdx.x, t = threadIdx.x, lane = t & (TILE - 1), wave = t / TILE;
+    // wavefront w multiplies columns [KW w, KW w + KW) for rows lane and
+    // lane + 64 (the inverse is symmetric: row k is column k, read coalesced)
+    const double *M = inv + (size_t)d * CG_N * CG_N + (size_t)wave * KW * CG_N;
+    const int i1 = min(lane + TILE, CG_N - 1);
+    double m0[KW], m1[KW];
+#pragma unroll
+    for (int j = 0; j < KW; ++j) { m0[j] = M[(size_t)j * CG_N + lane]; m1[j] = M[(size_t)j * CG_N + i1]; }
+    const int on = act[dom_scene[d]];
     const int e0 = ent[d], ne = ent[d + 1] - e0, n = 3 * ((ne + CG_AGG - 1) / CG_AGG);
-    const int t = threadIdx.x, lane = t & (TILE - 1), wave = t / TILE;
-    // restriction: all entries' residuals in flight at once
     int nd[CG_PASSES];
-    d3 rv[CG_PASSES];
 #pragma unroll
     for (int j = 0; j < CG_PASSES; ++j) {
         const int e = t + j * CG_APPLY;
         nd[j] = e < ne ? nodes[e0 + e] : -1;
     }
+    d3 rv[CG_PASSES], zv[CG_PASSES];
 #pragma unroll
-    for (int j = 0; j < CG_PASSES; ++j) rv[j] = nd[j] >= 0 ? ld3(r, nd[j]) : d3{0.0, 0.0, 0.0};
+    for (int j = 0; j < CG_PASSES; ++j) {
+        rv[j] = nd[j] >= 0 ? ld3(r, nd[j]) : d3{0.0, 0.0, 0.0};
+        zv[j] = nd[j] >= 0 ? ld3(z, nd[j]) : d3{0.0, 0.0, 0.0};
+    }
+    if (!on) return;   // uniform over the workgroup; nothing written yet
+    if (t < CG_N) rc[t] = 0.0;
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < CG_PASSES; ++j) {
         double x = rv[j].x, y = rv[j].y, zz = rv[j].z;
@@ -203,60 +241,37 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict
         if ((lane & (CG_AGG - 1)) == 0 && 3 * g < n) { rc[3 * g] = x; rc[3 * g + 1] = y; rc[3 * g + 2] = zz; }
     }
     __syncthreads();
-    // zc = C^-1 rc: wavefront w sums the columns k in [KW w, KW w + KW) for
-    // the rows i = lane and lane + 64; all its loads are issued before the
-    // sums (the inverse is symmetric: row k is column k, read coalesced)
-    {
-        constexpr int KW = CG_N / (CG_APPLY / TILE);   // 24 columns per wavefront
-        const double *M = inv + (size_t)d * CG_N * CG_N;
-        const int i0 = lane, i1 = lane + TILE;
-        double m0[KW], m1[KW];
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int j = 0; j < KW; ++j) {
-            const int k = wave * KW + j;
-            m0[j] = (k < n && i0 < n) ? M[(size_t)k * CG_N + i0] : 0.0;
-            m1[j] = (k < n && i1 < n) ? M[(size_t)k * CG_N + i1] : 0.0;
-        }
-        double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-        for (int j = 0; j < KW; ++j) {
-            const int k = wave * KW + j;
-            const double rk = k < n ? rc[k] : 0.0;
-            a0 += m0[j] * rk;
-            a1 += m1[j] * rk;
-        }
-        zp[wave][i0] = a0;
-        if (i1 < CG_N) zp[wave][i1] = a1;
+    for (int j = 0; j < KW; ++j) {
+        const double rk = rc[wave * KW + j];
+        a0 += m0[j] * rk;
+        a1 += m1[j] * rk;
     }
+    zp[wave][lane] = a0;
+    if (lane + TILE < CG_N) zp[wave][lane + TILE] = a1;
     __syncthreads();
-    if (t < n) zc[t] = (zp[0][t] + zp[1][t]) + (zp[2][t] + zp[3][t]);
+    if (t < CG_N) zc[t] = t < n ? (zp[0][t] + zp[1][t]) + (zp[2][t] + zp[3][t]) : 0.0;
     __syncthreads();
     double dot = t < n ? rc[t] * zc[t] : 0.0;
     dot = wave_sum(dot);
     if (lane == 0) sh[wave] = dot;
-    // prolongation
 #pragma unroll
     for (int j = 0; j < CG_PASSES; ++j) {
         if (nd[j] < 0) continue;
         const int g = (t + j * CG_APPLY) / CG_AGG;
-        d3 zv = ld3(z, nd[j]);
-        st3(z, nd[j], {zv.x + zc[3 * g], zv.y + zc[3 * g + 1], zv.z + zc[3 * g + 2]});
+        st3(z, nd[j], {zv[j].x + zc[3 * g], zv[j].y + zc[3 * g + 1], zv[j].z + zc[3 * g + 2]});
     }
     __syncthreads();
-    if (t == 0) {
-        double s2 = 0.0;
-        for (int w = 0; w < CG_APPLY / TILE; ++w) s2 += sh[w];
-        part[d] = s2;
-    }
+    if (t == 0) part[d] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 void coarse_build(ipc_ctx *c)
 {
     if (!c->n_cdom) return;
     Dev &D = c->d;
-    D.cg_inv.zero(c->stream, (size_t)c->n_cdom * CG_N * CG_N);
-    hipLaunchKernelGGL(k_coarse_assemble, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, D.cg_node_da.p, D.row_ptr.p,
-                       D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.cg_inv.p);
+    hipLaunchKernelGGL(k_coarse_assemble, dim3(c->n_cgrp), dim3(CG_ASM), 0, c->stream, D.cg_grp.p, D.cg_ent.p, D.cg_nodes.p,
+                       D.cg_node_da.p, D.row_ptr.p, D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.cg_inv.p);
     hipLaunchKernelGGL(k_coarse_invert, dim3(c->n_cdom), dim3(CG_INV), 0, c->stream, D.cg_ent.p, D.cg_inv.p);
 }
 

@@ -239,6 +239,7 @@ struct Dev {
     // inverse (CG_N x CG_N) and r . z partials of both parities; per node
     // domain * CG_DOM + group, or -1 for nodes outside every group
     DBuf<int> cg_ent, cg_nodes, cg_node_da, cg_dom_scene;
+    DBuf<int> cg_grp;                      // per group: domain * CG_DOM + group in the domain
     DBuf<double> cg_inv, cg_part;
     DBuf<int> pcg_act, pcg_it;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
@@ -261,7 +262,7 @@ struct ipc_ctx {
     int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
     bool coarse = true;                   // coarse correction in the PCG preconditioner
-    int n_cdom = 0;                       // its domains over all scenes
+    int n_cdom = 0, n_cgrp = 0;           // its domains and groups over all scenes
     std::vector<int> seg_cdom;            // per scene: first domain (n_scenes + 1)
     int64_t ext_nodes = 0;
     int64_t ext_tets = 0;
