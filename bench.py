@@ -184,7 +184,7 @@ def bench_batched(args):
         "one_at_a_time": {"value": len(scenes) * args.steps / t_single_all, "unit": "scene-steps/s",
                           "sample": f"{len(pick)} scenes spread over the size range, scaled by {len(scenes)}/{len(pick)}"},
         "speedup_vs_one_at_a_time": t_single_all / t,
-        "max_newton_per_step": newton, "spmv_lanes_per_row": lanes,
+        "max_newton_per_step": newton, "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
         "scene_steps_not_converged": not_ok,
     }
     print(json.dumps(line))
@@ -237,7 +237,7 @@ def bench_adjoint(args):
         "forward_s": t_fwd, "backward_s": t_bwd, "backward_ms_per_step": 1e3 * t_bwd / K,
         "note": "backward = recompute of each 10-step segment from its checkpoint + one adjoint solve per step",
         "loss": float(loss.detach()), "dL_dE_norm": float(E.grad.norm()), "dL_dmu": float(mu.grad[0]),
-        "spmv_lanes_per_row": lanes,
+        "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
     }
     print(json.dumps(line))
 
@@ -270,7 +270,7 @@ def bench_arm(args):
                   f"pairs={st[0]['n_pt_max'] + st[0]['n_ee_max']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        out[name] = dict(t=t, newton=newton, pcg=pcg, not_ok=not_ok, lanes=lanes, tets=len(sc["tets"]),
+        out[name] = dict(t=t, newton=newton, pcg=pcg, not_ok=not_ok, lanes=lanes, coarse=sim.pcg_coarse, tets=len(sc["tets"]),
                          bodies=len(sc["body_q"]), joint_springs=len(sc["joint_spring"]), drive_slots=len(sc["driven_body"]))
         del sim
     a, f = out["arm"], out["fk_targets"]
@@ -282,11 +282,11 @@ def bench_arm(args):
                    "bodies": a["bodies"], "joint_springs": a["joint_springs"], "drive_slots": a["drive_slots"],
                    "parallelism": "single GPU"},
         "steps_per_s": args.steps / a["t"], "newton_per_step": a["newton"], "pcg_per_step": a["pcg"],
-        "steps_not_converged": a["not_ok"], "spmv_lanes_per_row": a["lanes"],
+        "steps_not_converged": a["not_ok"], "spmv_lanes_per_row": a["lanes"], "pcg_coarse": a["coarse"],
         "fk_targets": {"workload": "the same squeeze on link-space target drives", "tets": f["tets"],
                        "newton_it_per_s": sum(f["newton"]) / f["t"], "steps_per_s": args.steps / f["t"],
                        "ms_per_step": 1e3 * f["t"] / args.steps, "newton_per_step": f["newton"],
-                       "pcg_per_step": f["pcg"], "steps_not_converged": f["not_ok"]},
+                       "pcg_per_step": f["pcg"], "steps_not_converged": f["not_ok"], "pcg_coarse": f["coarse"]},
     }
     print(json.dumps(line))
 
@@ -390,7 +390,7 @@ def main():
         "pcg_per_newton": pcg / max(newton, 1),
         "active_pairs": {"min": int(min(pairs)), "median": float(np.median(pairs)), "max": int(max(pairs))},
         "roofline": roof,
-        "spmv_lanes_per_row": lanes,
+        "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, pcg / max(newton, 1))

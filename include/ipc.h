@@ -135,7 +135,13 @@ enum {
                              assembly that stay pair-local, i.e. whose blocks
                              did not fit the matrix pattern                      */
     IPC_Q_NPAIRS = 8,     /* active barrier pairs of the last assembly         */
-    IPC_Q_NTETS_EXT = 9   /* tetrahedra of all scenes (external numbering)     */
+    IPC_Q_NTETS_EXT = 9,  /* tetrahedra of all scenes (external numbering)     */
+    IPC_Q_COARSE = 10     /* 1 when the PCG preconditioner applies its coarse
+                             correction: for contexts of at least 32768 nodes
+                             (its cost per iteration is a fixed few
+                             microseconds); the environment variable
+                             IPC_PCG_COARSE = 0 or 1, read at ipc_create,
+                             switches it off or on whatever the size       */
 };
 
 /* Flags of ipc_energy_grad_hess. */
@@ -187,8 +193,9 @@ int ipc_get_pairs(ipc_ctx *ctx, const double *y_dev, int scene, int32_t *pt_host
  * swept candidates of [y, y + p] (external layout). */
 int ipc_ccd(ipc_ctx *ctx, const double *y_dev, const double *p_dev, double *alpha_dev);
 
-/* Solve H(y) x = b with the block-Jacobi PCG of the Newton step (projected
- * Hessian at y, relative tolerance eta); iters_host[n_scenes] (nullable). */
+/* Solve H(y) x = b with the PCG of the Newton step (projected Hessian at y,
+ * relative tolerance eta; block-Jacobi preconditioner, plus the coarse
+ * correction of IPC_Q_COARSE); iters_host[n_scenes] (nullable). */
 int ipc_pcg(ipc_ctx *ctx, const double *y_dev, const double *b_dev, double *x_dev, double eta,
             int32_t *iters_host);
 
@@ -213,8 +220,8 @@ int ipc_set_params(ipc_ctx *ctx, const double *tet_E_dev, const double *mu_host)
  * to y_next and ydot_next = (y_next - y_prev)/h (all external layout, ndof).
  * The call sets the context's state to (y_prev, ydot_prev), redoes the step
  * set-up there (predictor, friction lag), assembles the Hessian at y_next
- * WITHOUT PSD projection, solves H w = ybar_next + vbar_next/h by block-Jacobi
- * PCG to relative residual eta (each scene's max_pcg caps it), and writes
+ * WITHOUT PSD projection, solves H w = ybar_next + vbar_next/h by the Newton
+ * step's PCG to relative residual eta (each scene's max_pcg caps it), and writes
  *   vbar_prev = h M w,
  *   ybar_prev = M w - (dG_F/dy_prev)^T w - vbar_next/h
  * (G_F: friction gradient, whose lagged normals, weights and normal forces are

@@ -172,6 +172,11 @@ class Sim:
         self._check(lib().ipc_autotune(self._h, int(reps), us.ctypes.data_as(_lib._D), ctypes.byref(L)))
         return L.value, dict(zip((1, 2, 4, 8, 16), us.tolist()))
 
+    @property
+    def pcg_coarse(self):
+        """Whether the PCG preconditioner applies its coarse correction."""
+        return bool(self._query(_lib.Q_COARSE))
+
     # ---- adjoint --------------------------------------------------------------
     @property
     def n_tets(self):

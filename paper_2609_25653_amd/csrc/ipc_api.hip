@@ -450,8 +450,9 @@ extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_
             int L = std::atoi(nl);
             if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) c->spmv_lanes = L;
         }
-        const char *nc = std::getenv("IPC_PCG_COARSE");
+        const char *nc = std::getenv("IPC_PCG_COARSE");   // 0: never, 1: always, else by size and the autotuner
         c->coarse = !(nc && nc[0] == '0');
+        c->coarse_forced = nc && nc[0] == '1';
         if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
     }
     int rc = guard(c, [&] {
@@ -491,6 +492,7 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_NLOCAL: *v = c->n_local; return IPC_OK;
     case IPC_Q_NPAIRS: *v = c->n_pt + c->n_ee; return IPC_OK;
     case IPC_Q_NTETS_EXT: *v = c->ext_tets; return IPC_OK;
+    case IPC_Q_COARSE: *v = c->coarse_on ? 1 : 0; return IPC_OK;
     }
     return IPC_E_INVALID;
 }

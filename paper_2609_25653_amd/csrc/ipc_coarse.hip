@@ -90,6 +90,8 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
     c->seg_cdom[ns] = ndom;
     ent.push_back((int)nodes.size());   // ndom + 1 offsets
     c->n_cdom = ndom;
+    // a fixed cost per iteration (a few dependent stages): it pays on large contexts
+    c->coarse_on = ndom > 0 && (c->coarse_forced || c->N >= CG_MIN_NODES);
     c->n_cgrp = (int)grp.size();
     Dev &D = c->d;
     D.cg_grp.upload(grp.empty() ? std::vector<int>(1, 0) : grp, c->stream);
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict
 
 void coarse_build(ipc_ctx *c)
 {
-    if (!c->n_cdom) return;
+    if (!c->n_cdom || !c->coarse_on) return;
     Dev &D = c->d;
     hipLaunchKernelGGL(k_coarse_assemble, dim3(c->n_cgrp), dim3(CG_ASM), 0, c->stream, D.cg_grp.p, D.cg_ent.p, D.cg_nodes.p,
                        D.cg_node_da.p, D.row_ptr.p, D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.cg_inv.p);
@@ -277,7 +279,7 @@ void coarse_build(ipc_ctx *c)
 
 void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int parity)
 {
-    if (!c->n_cdom) return;
+    if (!c->n_cdom || !c->coarse_on) return;
     Dev &D = c->d;
     hipLaunchKernelGGL(k_coarse_apply, dim3(c->n_cdom), dim3(CG_APPLY), 0, c->stream, D.cg_ent.p, D.cg_nodes.p, D.cg_dom_scene.p,
                        act, D.cg_inv.p, r, z, D.cg_part.p + (size_t)parity * c->n_cdom);

@@ -22,6 +22,7 @@ constexpr int BLOCK = 256;    // default workgroup: 4 wavefronts
 constexpr int CG_AGG = 32;    // coarse preconditioner: nodes per group
 constexpr int CG_DOM = 32;    // groups per coarse domain
 constexpr int CG_N = 3 * CG_DOM;   // coarse unknowns per domain
+constexpr int CG_MIN_NODES = 32768;  // contexts from this size apply it by default
 constexpr int LONG_ROW = 64;  // rows with more blocks go to the wavefront-per-row path
 
 // per-scene device scalar slots
@@ -261,7 +262,9 @@ struct ipc_ctx {
     int long_cap = 0;                     // long-row workgroups the product launches (grows, multiple of 64)
     int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
-    bool coarse = true;                   // coarse correction in the PCG preconditioner
+    bool coarse = true;                   // coarse domains built (the PCG preconditioner's correction)
+    bool coarse_on = false;               // the PCG applies the coarse correction
+    bool coarse_forced = false;           // on by request, whatever the size
     int n_cdom = 0, n_cgrp = 0;           // its domains and groups over all scenes
     std::vector<int> seg_cdom;            // per scene: first domain (n_scenes + 1)
     int64_t ext_nodes = 0;
@@ -329,6 +332,7 @@ void build_preconditioner(ipc_ctx *c);
 void coarse_setup(ipc_ctx *c, const std::vector<double> &X);
 void coarse_build(ipc_ctx *c);
 void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int parity);
+
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
 void pcg_wginfo(ipc_ctx *c);
 // constant part of the matrix (lumped mass, spring blocks) from the current

@@ -733,7 +733,7 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
         prof_begin(c, IPC_K_PCG_UPDATE);
         hipLaunchKernelGGL(k_pcg_step, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p, D.node_body.p,
                            D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM), D.pcg_wginfo.p,
-                           D.cg_part.p, c->n_cdom, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
+                           D.cg_part.p, c->coarse_on ? c->n_cdom : 0, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
                            r, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
         coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
@@ -796,7 +796,7 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                                       (uintptr_t)D.pcg_it.p, (uintptr_t)D.scal.p, (uintptr_t)D.long_count.p, (uintptr_t)D.long_rows.p,
                                       (uintptr_t)D.row_ptr.p, (uintptr_t)D.col.p, (uintptr_t)D.val.p, (uintptr_t)D.dyn_ptr.p,
                                       (uintptr_t)D.dyn_col.p, (uintptr_t)D.dyn_val.p, (uintptr_t)D.node_scene.p,
-                                      (uintptr_t)D.pcg_wginfo.p, (uintptr_t)c->n_cdom, (uintptr_t)D.cg_ent.p, (uintptr_t)D.cg_nodes.p,
+                                      (uintptr_t)D.pcg_wginfo.p, (uintptr_t)(c->coarse_on ? c->n_cdom : 0), (uintptr_t)D.cg_ent.p, (uintptr_t)D.cg_nodes.p,
                                       (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p};
         bool have = key == c->pcg_key;
         for (auto xg : c->pcg_exec) have = have && xg;

@@ -118,11 +118,16 @@ def test_pcg(name, coarse, states, monkeypatch):
         assert abs(int(it[0]) - it_or) <= max(2, it_or // 20)
 
 
+@pytest.mark.parametrize("coarse", [False, True])
 @pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34), ("arm_box", 30)])
-def test_trajectory(name, n):
+def test_trajectory(name, n, coarse, monkeypatch):
+    """Steps agree with the oracle with the PCG's coarse correction switched
+    off and on (these small scenes leave it off by default)."""
     from paper_2609_25653_amd import Sim
+    monkeypatch.setenv("IPC_PCG_COARSE", "1" if coarse else "0")
     sc = S.block_drop(n_steps=n) if name == "block" else S.tiny_scene(name, h=0.01, n_steps=n)
     sim = Sim(sc)
+    assert sim.pcg_coarse == coarse
     o = O.Oracle(sc)
     L = o.L
     for k in range(n):
