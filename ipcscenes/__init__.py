@@ -1,7 +1,7 @@
 """Seeded synthetic scene generators shared by the HIP library tests and the oracle.
 
 This package only builds inputs: meshes, material parameters, body descriptions,
-spring anchors and drive trajectories.  It contains none of the method's
+spring anchors, drive trajectories and coarse render meshes with their frames.  It contains none of the method's
 arithmetic (no energies, no precompute, no contact, no solver).  Every scene is
 a plain ``dict`` of numpy arrays; see ``scenes.SCENE_KEYS`` for the layout.
 """
@@ -16,4 +16,6 @@ from .scenes import (  # noqa: F401
     tiny_scene,
     hex_tets,
     validate_scene,
+    tet_surface,
+    dualmesh_frames,
 )

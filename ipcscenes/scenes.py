@@ -610,3 +610,52 @@ def tiny_scene(kind="tet", seed=0, **kw):
     if drive is None:
         drive = np.zeros((int(p["n_steps"]), 0, 12))
     return b.finish(p, drive)
+
+
+def tet_surface(P, T):
+    """Boundary triangles of a tet mesh, oriented outward, on surface-local
+    vertex numbers: (surface positions, triangles, volume index of every
+    surface vertex)."""
+    P = np.asarray(P, np.float64)
+    T = np.asarray(T, np.int64).copy()
+    vol = np.einsum("ij,ij->i", np.cross(P[T[:, 1]] - P[T[:, 0]], P[T[:, 2]] - P[T[:, 0]]), P[T[:, 3]] - P[T[:, 0]])
+    neg = vol < 0
+    T[neg, 1], T[neg, 2] = T[neg, 2].copy(), T[neg, 1].copy()
+    a, b, c, d = T.T
+    faces = np.stack([np.stack(f, 1) for f in ((b, c, d), (a, d, c), (a, b, d), (a, c, b))], 1).reshape(-1, 3)
+    _, inv, cnt = np.unique(np.sort(faces, 1), axis=0, return_inverse=True, return_counts=True)
+    bnd = faces[cnt[inv.ravel()] == 1]
+    verts = np.unique(bnd.ravel())
+    local = np.full(len(P), -1, np.int64)
+    local[verts] = np.arange(len(verts))
+    tri = local[bnd].astype(np.int32)
+    return P[verts].copy(), tri, verts.astype(np.int32)
+
+
+def dualmesh_frames(seed=0, n_frames=100, n_disk=30, n_layers=40, radius=0.03, height=0.1):
+    """Coarse render input of the dual-mesh mapping: the surface of the soft
+    cylinder of contact_rich (6602 vertices, 13200 triangles at the default
+    resolution) and n_frames of its positions under a seeded smooth
+    deformation (a squeeze that varies along the height, a twist and a
+    sway), as a trajectory of simulated states would give them.  Returns
+    (triangles (m, 3) int32, frames (n_frames, n, 3) float64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P, T = cylinder_mesh(radius, height, n_disk, n_layers, (0.3, 0.3), 2.5e-4)
+    X0, tri, _ = tet_surface(P, T)
+    c = np.array([0.3, 0.3, 0.0])
+    rel = X0 - c
+    zeta = (X0[:, 2] - X0[:, 2].min()) / height
+    amp = rng.uniform(0.05, 0.15, size=3)
+    phase = rng.uniform(0.0, 2 * np.pi, size=3)
+    frames = np.empty((n_frames,) + X0.shape)
+    for f in range(n_frames):
+        s = f / max(n_frames - 1, 1)
+        sq = 1.0 - amp[0] * np.sin(np.pi * s + phase[0]) ** 2 * np.sin(np.pi * zeta)
+        tw = amp[1] * s * zeta
+        sway = amp[2] * 0.01 * np.sin(2 * np.pi * s + phase[2]) * zeta ** 2
+        x = rel[:, 0] * np.cos(tw) - rel[:, 1] * np.sin(tw)
+        y = rel[:, 0] * np.sin(tw) + rel[:, 1] * np.cos(tw)
+        frames[f, :, 0] = c[0] + sq * x + sway
+        frames[f, :, 1] = c[1] + sq * y
+        frames[f, :, 2] = X0[:, 2]
+    return tri, frames
