@@ -291,6 +291,104 @@ def bench_arm(args):
     print(json.dumps(line))
 
 
+DM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dm_apply_cylinder_L3_traffic.json")
+DM_SRC = os.path.join(ROOT, "paper_2609_25653_amd", "csrc", "ipc_dualmesh.hip")
+
+
+def bench_dualmesh(args):
+    """Dual-mesh mapping (Eq. (7)): the soft cylinder's surface (6602 coarse
+    vertices) subdivided 3 levels (422402 fine vertices), 100 frames of a
+    deformation trajectory per launch; a step is one launch."""
+    import hashlib
+    import numpy as np
+    import torch
+    import ipcscenes
+    from paper_2609_25653_amd.dualmesh import DualMesh
+    tri, frames = ipcscenes.dualmesh_frames(n_frames=args.frames)
+    dm = DualMesh(tri, frames.shape[1], 3)
+    xc = torch.as_tensor(frames, device="cuda")
+    xf = torch.empty((frames.shape[0], dm.n_fine, 3), dtype=torch.float64, device="cuda")
+    if args.traffic_run:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        for k in range(args.warmup + args.steps):
+            dm.apply(xc, xf)
+            print(f"# traffic run launch {k}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return
+    for _ in range(args.warmup):
+        dm.apply(xc, xf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dm.apply(xc, xf)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    us, by = dm.time(xc, xf, 50)
+    achieved = by / (us * 1e-6) / 1e9
+    traffic = None
+    try:
+        rec = json.load(open(DM_TRAFFIC_FILE))
+        if rec.get("source_sha256") == hashlib.sha256(open(DM_SRC, "rb").read()).hexdigest():
+            traffic = rec.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": "k_dm_apply (W X^c for every frame)", "bytes_per_launch": by, "avg_us": us,
+            "launches_timed": 50}
+    per_launch = frames.shape[0] * dm.n_fine
+    line = {
+        "metric": "fine vertex-frames/s", "value": args.steps * per_launch / t, "unit": "fine vertex-frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"dual-mesh mapping: cylinder surface {dm.n_coarse} -> {dm.n_fine} vertices (3 Loop levels), "
+                               f"{frames.shape[0]} frames per launch", "nnz_W": dm.nnz, "max_row": dm.max_row,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from oracle.loop_subdiv import loop_subdivide
+        t0 = time.perf_counter()
+        for f in (0, frames.shape[0] - 1):
+            loop_subdivide(frames[f], tri, 3)
+        tc = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 2 * dm.n_fine / tc, "unit": "fine vertex-frames/s", "cores": 1, "kind": "oracle",
+                                "sample": f"2 of the {frames.shape[0]} frames, level-by-level subdivision in Python ({tc:.1f} s)"}
+    print(json.dumps(line))
+
+
+def write_dm_traffic(fetch_csv, write_csv):
+    """As write_traffic, for the dual-mesh kernel of a --workload dualmesh
+    --traffic-run."""
+    import csv
+    import hashlib
+
+    def per_kernel(path):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy = [k for k in f if "copyBuffer" in k]
+    dmk = [k for k in f if "k_dm_apply" in k]
+    kib = 256 * 1024
+    fac_f = kib / max(max(f[k]) for k in copy)
+    fac_w = kib / max(max(w[k]) for k in copy)
+    sf = [v for k in dmk for v in f[k]]
+    sw = [v for k in dmk for v in w[k]]
+    traffic = 1024.0 * (fac_f * sum(sf) / len(sf) + fac_w * sum(sw) / len(sw))
+    rec = {"kernel": "k_dm_apply", "bytes_per_launch": traffic, "fetch_kib": sum(sf) / len(sf), "write_kib": sum(sw) / len(sw),
+           "fetch_scale": fac_f, "write_scale": fac_w, "launches": len(sf),
+           "source_sha256": hashlib.sha256(open(DM_SRC, "rb").read()).hexdigest(),
+           "source": "python bench.py --workload dualmesh --traffic-run under rocprofv3 --pmc"}
+    json.dump(rec, open(DM_TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,10 +396,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=8e-4, help="ground patch spacing (m): 0.8 mm keeps the median active pairs inside 50k-300k")
-    ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm"], default="contact",
+    ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm", "dualmesh"], default="contact",
                     help="contact: the 200k-tet squeeze (default line); batched: 256 uneven squeeze scenes stepped "
                          "together vs one at a time; adjoint: 50-step squeeze rollout, forward vs backward time; "
-                         "arm: the squeeze on the joint-space arm vs on link-space target drives")
+                         "arm: the squeeze on the joint-space arm vs on link-space target drives; "
+                         "dualmesh: the render mesh of the soft cylinder, 3 Loop levels, 100 frames per launch")
+    ap.add_argument("--frames", type=int, default=100, help="dualmesh: frames per launch")
     ap.add_argument("--scenes", type=int, default=256, help="batched: number of scenes")
     ap.add_argument("--single-sample", type=int, default=16, help="batched: scenes stepped one at a time for the baseline")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -315,6 +415,8 @@ def main():
                          "and 20 back-to-back block-CSR products (for hardware-counter runs)")
     args = ap.parse_args()
     if args.traffic_from:
+        if args.workload == "dualmesh":
+            return write_dm_traffic(*args.traffic_from)
         return write_traffic(*args.traffic_from)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -331,6 +433,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "arm":
         return bench_arm(args)
+    if args.workload == "dualmesh":
+        return bench_dualmesh(args)
     n_total = args.warmup + args.steps
     scene = ipcscenes.contact_rich(n_steps=n_total, s_g=args.s_g)
     sim = Sim(scene)

@@ -88,6 +88,19 @@ def lib():
         L.ipc_kernel_time.argtypes = [P, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int64), _D]
         L.ipc_time_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, _D, _D]
         L.ipc_autotune.argtypes = [P, ctypes.c_int, _D, _I]
+        L.ipc_dualmesh_create.argtypes = [_I, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)]
+        L.ipc_dualmesh_destroy.argtypes = [P]
+        L.ipc_dualmesh_destroy.restype = None
+        L.ipc_dualmesh_last_error.argtypes = [P]
+        L.ipc_dualmesh_last_error.restype = ctypes.c_char_p
+        L.ipc_dualmesh_query.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+        L.ipc_dualmesh_fine_tris.argtypes = [P, _I]
+        L.ipc_dualmesh_weights.argtypes = [P, _I, _I, _D]
+        L.ipc_dualmesh_apply.argtypes = [P, P, P, ctypes.c_int32]
+        L.ipc_dualmesh_time.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, _D, _D]
+        for n in ("ipc_dualmesh_create", "ipc_dualmesh_query", "ipc_dualmesh_fine_tris", "ipc_dualmesh_weights",
+                  "ipc_dualmesh_apply", "ipc_dualmesh_time"):
+            getattr(L, n).restype = ctypes.c_int
         for n in ("ipc_create", "ipc_destroy", "ipc_query", "ipc_scene_scalars", "ipc_get_state", "ipc_set_state",
                   "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg", "ipc_step",
                   "ipc_set_params", "ipc_step_vjp", "ipc_profile", "ipc_kernel_time", "ipc_time_kernel",

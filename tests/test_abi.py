@@ -1,5 +1,6 @@
 """C-ABI checks that need no GPU: the library loads and exports every entry
-point that include/ipc.h declares; the struct layouts match the binding."""
+point that the headers in include/ declare; the headers compile as C; the
+struct layouts match the binding."""
 import ctypes
 import os
 import re
@@ -10,15 +11,29 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared():
-    src = open(os.path.join(ROOT, "include", "ipc.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*\*?\s*(ipc_\w+)\s*\(", src, re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            names.update(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(ipc_\w+)\s*\(", src, re.M))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared()
     for n in ("ipc_create", "ipc_step", "ipc_energy_grad_hess", "ipc_destroy", "ipc_get_pairs", "ipc_ccd",
-              "ipc_pcg", "ipc_begin_step", "ipc_get_state", "ipc_set_state", "ipc_last_error"):
+              "ipc_pcg", "ipc_begin_step", "ipc_get_state", "ipc_set_state", "ipc_last_error",
+              "ipc_dualmesh_create", "ipc_dualmesh_apply", "ipc_dualmesh_weights", "ipc_dualmesh_destroy"):
         assert n in names
+
+
+def test_headers_compile_as_c(tmp_path):
+    import subprocess
+    src = tmp_path / "h.c"
+    src.write_text('#include "ipc.h"\n#include "ipc_dualmesh.h"\nint main(void) { return IPC_DM_NNZ - 3; }\n')
+    exe = tmp_path / "h"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    assert subprocess.run([str(exe)]).returncode == 0
 
 
 def test_library_exports_every_declared_symbol():

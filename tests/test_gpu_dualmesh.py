@@ -1,0 +1,89 @@
+"""Dual-mesh mapping on the GPU (Sec. IV, Eq. (6)-(7)): X^f = W X^c for many
+frames in one launch against the oracle's level-by-level Loop subdivision of
+each frame (needs a GPU).  Bar: every coordinate within 1e-13 of the
+coordinates' magnitude (a handful of weighted sums in FP64 in another
+order)."""
+import math
+
+import numpy as np
+import pytest
+
+import ipcscenes as S
+from oracle.loop_subdiv import loop_subdivide
+from test_oracle_loop import hexagon_fan, icosahedron, octahedron, torus
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a ROCm GPU")]
+
+
+def fan(n, seed=0):
+    """A planar disk of n triangles around one centre vertex of valence n:
+    its rows of W are n + 1 long after one level (the kernel's row-length
+    variants)."""
+    rng = np.random.default_rng(seed)
+    rim = [[math.cos(2 * math.pi * k / n), math.sin(2 * math.pi * k / n), 0.0] for k in range(n)]
+    V = np.array([[0.0, 0.0, 0.0]] + rim) + 0.02 * rng.standard_normal((n + 1, 3))
+    F = np.array([[0, 1 + k, 1 + (k + 1) % n] for k in range(n)])
+    return V, F
+
+
+def _check(V, F, levels, frames, seed):
+    from paper_2609_25653_amd.dualmesh import DualMesh
+    rng = np.random.default_rng(seed)
+    X = V[None] + 0.1 * rng.standard_normal((frames,) + V.shape)
+    dm = DualMesh(F, len(V), levels)
+    out = dm.apply(torch.as_tensor(X, device="cuda")).cpu().numpy()
+    for f in range(frames):
+        ref, _ = loop_subdivide(X[f], F, levels)
+        assert np.abs(out[f] - ref).max() <= 1e-13 * np.abs(X).max(), (levels, f)
+    return dm
+
+
+@pytest.mark.parametrize("mesh", [octahedron, icosahedron, lambda: torus(jitter=0.05), hexagon_fan])
+@pytest.mark.parametrize("levels", [0, 1, 2, 3])
+def test_small_meshes_match_the_oracle(mesh, levels):
+    V, F = mesh()
+    _check(V, F, levels, frames=3, seed=levels)
+
+
+@pytest.mark.parametrize("n,variant", [(12, 16), (40, 48), (60, 64), (70, 0)])
+def test_row_length_variants(n, variant):
+    """Rows of up to 16, 48, 64 and more than 64 nonzeros (the last one read
+    from memory on every frame instead of registers)."""
+    V, F = fan(n, seed=n)
+    dm = _check(V, F, 1, frames=5, seed=n)
+    assert dm.max_row == n + 1
+    assert (variant == 0 and dm.max_row > 64) or (variant > 0 and dm.max_row <= variant)
+
+
+def test_single_frame_and_rejections():
+    from paper_2609_25653_amd.dualmesh import DualMesh
+    V, F = icosahedron()
+    dm = DualMesh(F, len(V), 2)
+    x = torch.as_tensor(V, device="cuda")
+    ref, _ = loop_subdivide(V, F, 2)
+    assert np.abs(dm.apply(x).cpu().numpy() - ref).max() <= 1e-13 * np.abs(V).max()
+    with pytest.raises(ValueError):
+        dm.apply(torch.zeros((1, len(V) + 1, 3), dtype=torch.float64, device="cuda"))
+
+
+def test_cylinder_trajectory_at_full_size():
+    """The launch the bench times: the soft cylinder's surface (6602 coarse
+    vertices), three levels (422402 fine vertices), 100 frames at once;
+    frames 0, 41 and 99 against the oracle, every frame against the frame
+    before it run alone (a launch over many frames equals single-frame
+    launches)."""
+    from paper_2609_25653_amd.dualmesh import DualMesh
+    tri, frames = S.dualmesh_frames(n_frames=100)
+    dm = DualMesh(tri, frames.shape[1], 3)
+    xc = torch.as_tensor(frames, device="cuda")
+    out = dm.apply(xc)
+    torch.cuda.synchronize()
+    scale = np.abs(frames).max()
+    for f in (0, 41, 99):
+        ref, _ = loop_subdivide(frames[f], tri, 3)
+        assert np.abs(out[f].cpu().numpy() - ref).max() <= 1e-13 * scale, f
+    for f in (0, 57, 99):
+        one = dm.apply(xc[f].contiguous())
+        assert torch.equal(one, out[f])
