@@ -158,6 +158,14 @@ const char *ipc_last_error(const ipc_ctx *ctx);
 int ipc_query(const ipc_ctx *ctx, int what, int64_t *value);
 /* Per-scene scalars: kappa (as used), L, Newton threshold (newton_tol*h*L). */
 int ipc_scene_scalars(const ipc_ctx *ctx, int scene, double *kappa, double *L, double *newton_thr);
+/* Change the time step of every scene s with h_host[s] > 0 (entries <= 0
+ * keep the scene's step; a non-finite entry is IPC_E_INVALID).  The
+ * implicit step of Eq. (3) scales the elastic, spring and orthogonality
+ * terms by h^2, predicts y + h ydot + h^2 g and regularises friction by
+ * eps_v h; all of these follow, as does the Newton stop newton_tol h L.
+ * kappa keeps its creation value.  For retries of a step that did not
+ * converge: take it again as two steps of h/2 (host arrays; synchronous). */
+int ipc_set_timestep(ipc_ctx *ctx, const double *h_host);
 
 /* State in the external layout (ndof doubles each).  ydot may be NULL on get. */
 int ipc_get_state(ipc_ctx *ctx, double *y_dev, double *ydot_dev);

@@ -86,6 +86,8 @@ def lib():
         L.or_psd_project.argtypes = [D, ctypes.c_int]
         L.or_barrier3.argtypes = [ctypes.c_double, ctypes.c_double, D]
         L.or_set_params.argtypes = [P, D, ctypes.c_double]
+        L.or_set_timestep.argtypes = [P, ctypes.c_double]
+        L.or_set_timestep.restype = None
         L.or_dG_dyn_T.argtypes = [P, D, D, D, D, D, D]
         L.or_dG_dtheta_T.restype = ctypes.c_double
         L.or_dG_dtheta_T.argtypes = [P, D, D, D, D, D, D]
@@ -256,6 +258,49 @@ class Oracle:
         rc = lib().or_step(self._h, _d(t) if t is not None else None, ctypes.byref(st))
         self.step_index += 1
         return rc, st.as_dict()
+
+    def step_targets(self, t):
+        """One step towards explicit targets (the layout of targets(n))."""
+        st = OStats()
+        t = None if t is None else np.ascontiguousarray(t, dtype=np.float64)
+        rc = lib().or_step(self._h, _d(t) if t is not None else None, ctypes.byref(st))
+        return rc, st.as_dict()
+
+    def set_timestep(self, h):
+        lib().or_set_timestep(self._h, float(h))
+
+    def step_adaptive(self, max_depth=3):
+        """One step with sub-stepping on failure (the recovery policy of the
+        robustness variants): if the step ends without Newton convergence
+        (status 3), it is taken again from its start as two steps of h/2, the
+        first towards the mean of the previous and this step's targets, each
+        retried the same way down to h / 2^max_depth.  Returns (status of the
+        last piece, number of pieces)."""
+        n = self.step_index
+        h = float(self.scene["h"])
+        t1 = self.targets(n)
+        t0 = self.targets(n - 1 if n > 0 else 0)
+
+        def run(y, v, hh, ta, tb, depth):
+            self.set_state(y, v)
+            self.set_timestep(hh)
+            st = OStats()
+            rc = lib().or_step(self._h, _d(tb) if tb is not None else None, ctypes.byref(st))
+            if rc != 3 or depth >= max_depth:
+                return rc, 1
+            tm = None if tb is None else 0.5 * (ta + tb)
+            rc1, k1 = run(y, v, 0.5 * hh, ta, tm, depth + 1)
+            if rc1 != 0:
+                return rc1, k1
+            y2, v2 = self.state()
+            rc2, k2 = run(y2, v2, 0.5 * hh, tm, tb, depth + 1)
+            return rc2, k1 + k2
+
+        y, v = self.state()
+        rc, pieces = run(y, v, h, t0, t1, 0)
+        self.set_timestep(h)
+        self.step_index += 1
+        return rc, pieces
 
     # adjoint (one converged step n: y_prev -> y_next)
     def set_params(self, E=None, mu=None):

@@ -1679,6 +1679,13 @@ int or_step(OScene *s, const double *targets, OStats *st)
  * upstream adjoint a = dL/dy^{n+1} the sensitivities are -(dG/dq)^T w with
  * H w = a, H the unprojected Hessian at y^{n+1} and the lagged friction data
  * held as functions of y^n. */
+/* A new time step h > 0: every use of h (predictor, h^2 weights, friction
+ * regularisation eps_v h, Newton stop) reads s->h; kappa keeps its value. */
+void or_set_timestep(OScene *s, double h)
+{
+    if (h > 0.0) s->h = h;
+}
+
 void or_set_params(OScene *s, const double *E, double mu)
 {
     if (E)

@@ -104,6 +104,8 @@ void    or_psd_project(double *A, int n);
  *                   accumulated (-=) when non-NULL.  Returns 0, or 6 when the
  *                   PCG met p^T H p <= 0. */
 void    or_set_params(OScene *s, const double *E, double mu);
+/* New time step h > 0 (every use of h follows; kappa keeps its value). */
+void    or_set_timestep(OScene *s, double h);
 void    or_dG_dyn_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
                     const double *y_next, const double *w, double *out);
 double  or_dG_dtheta_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,

@@ -164,6 +164,56 @@ class Sim:
         self.step_index += 1
         return rc, [s.as_dict() for s in st]
 
+    def step_targets(self, targets, allow_status=()):
+        """One step towards explicit targets (the layout of targets(n)); the
+        step index does not move."""
+        t = None if targets is None else self._as_dev(targets)
+        st = (Stats * self.n_scenes)()
+        rc = lib().ipc_step(self._h, _ptr(t), st)
+        self._check(rc, allow=allow_status)
+        return rc, [s.as_dict() for s in st]
+
+    def set_timestep(self, h):
+        """New time step per scene (a scalar applies to every scene; entries
+        <= 0 keep a scene's step)."""
+        hh = np.broadcast_to(np.asarray(h, np.float64), (self.n_scenes,)).copy()
+        self._check(lib().ipc_set_timestep(self._h, hh.ctypes.data_as(_lib._D)))
+
+    def step_adaptive(self, max_depth=3):
+        """One step of a single-scene context with sub-stepping on failure:
+        if Newton does not converge (status 3) the step is taken again from
+        its start as two steps of h/2, the first towards the mean of the
+        previous and this step's targets, each retried the same way down to
+        h / 2^max_depth.  Returns (status of the last piece, pieces taken)."""
+        if self.n_scenes != 1:
+            raise ValueError("step_adaptive steps a single-scene context")
+        n = self.step_index
+        h = float(self.scenes[0]["h"])
+        t1 = self.targets(n)
+        t0 = self.targets(n - 1 if n > 0 else 0)
+        st = (Stats * 1)()
+
+        def run(y, v, hh, ta, tb, depth):
+            self.set_state(y, v)
+            self.set_timestep(hh)
+            rc = lib().ipc_step(self._h, _ptr(tb), st)
+            self._check(rc, allow=(3,))
+            if rc != 3 or depth >= max_depth:
+                return rc, 1
+            tm = None if tb is None else 0.5 * (ta + tb)
+            rc1, k1 = run(y, v, 0.5 * hh, ta, tm, depth + 1)
+            if rc1 != 0:
+                return rc1, k1
+            y2, v2 = self.state()
+            rc2, k2 = run(y2, v2, 0.5 * hh, tm, tb, depth + 1)
+            return rc2, k1 + k2
+
+        y, v = self.state()
+        rc, pieces = run(y, v, h, t0, t1, 0)
+        self.set_timestep(h)
+        self.step_index += 1
+        return rc, pieces
+
     def autotune(self, reps=20):
         """Pick the product's lanes per row on the current matrix; returns
         (lanes, {lanes: microseconds})."""

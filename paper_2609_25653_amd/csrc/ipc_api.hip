@@ -497,6 +497,29 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     return IPC_E_INVALID;
 }
 
+extern "C" int ipc_set_timestep(ipc_ctx *c, const double *h_host)
+{
+    if (!c || !h_host) return IPC_E_INVALID;
+    for (int s = 0; s < c->n_scenes; ++s)
+        if (!std::isfinite(h_host[s])) { c->err = "time step must be finite"; return IPC_E_INVALID; }
+    return guard(c, [&] {
+        std::vector<double> h2(c->n_scenes);
+        for (int s = 0; s < c->n_scenes; ++s) {
+            SceneInfo &S = c->sc[s];
+            if (h_host[s] > 0.0) {
+                S.h = h_host[s];
+                S.thr = S.newton_tol * S.h * S.L;   // the Newton stop scales with h
+            }
+            h2[s] = S.h * S.h;
+        }
+        upload_sparam(c);                 // h, h^2, eps_v h (kappa keeps its creation value)
+        c->d.h2s.upload(h2, c->stream);
+        build_const_part(c, c->d.h2s.p);  // the h^2-weighted spring blocks
+        sync(c);
+        c->step_ready = false;            // the predictor and the friction lag use h
+    });
+}
+
 extern "C" int ipc_scene_scalars(const ipc_ctx *c, int s, double *kappa, double *L, double *thr)
 {
     if (!c || s < 0 || s >= c->n_scenes) return IPC_E_INVALID;

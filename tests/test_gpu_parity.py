@@ -156,3 +156,57 @@ def test_graph_replay_matches_eager(monkeypatch):
         assert rg == 0 and re == 0
         yg, ye = to_np(g.state()[0]), to_np(e.state()[0])
         assert np.abs(yg - ye).max() <= 1e-9 * L, (k, sg, se)
+
+
+def test_half_steps_match_oracle():
+    """The pieces of a retried step: from the state after 12 steps of the
+    driven squeeze, two steps of h/2 towards the mean of steps 11 and 12's
+    targets and then step 12's, on both sides (1e-6 L)."""
+    from paper_2609_25653_amd import Sim
+    sc = S.tiny_scene("pad_box", h=0.01, n_steps=14)
+    sim = Sim(sc)
+    o = O.Oracle(sc)
+    for k in range(12):
+        assert sim.step()[0] == 0 and o.step()[0] == 0
+    tm = 0.5 * (o.targets(11) + o.targets(12))
+    sim.set_timestep(0.005)
+    o.set_timestep(0.005)
+    for t in (tm, o.targets(12)):
+        assert sim.step_targets(t)[0] == 0 and o.step_targets(t)[0] == 0
+        assert np.abs(to_np(sim.state()[0]) - o.state()[0]).max() <= 1e-6 * o.L
+    assert sim.scene_scalars()["newton_threshold"] == pytest.approx(o.newton_threshold, rel=1e-14)
+
+
+def test_step_adaptive_completes_and_conserves_momentum():
+    """Every one of 40 random velocity draws of two free tets completes 5
+    steps with the retry (11 of them end a plain step unconverged on the
+    oracle); linear momentum is conserved across every piece."""
+    from paper_2609_25653_amd import Sim
+    retried = 0
+    for seed in range(40):
+        sc = S.tiny_scene("two_tets", n_steps=5, h=0.01)
+        sc["g"] = np.zeros(3)
+        sc["V"] = 0.05 * np.random.default_rng(seed).standard_normal(sc["V"].shape)
+        sim = Sim(sc)
+        m = O.Oracle(sc).mass()
+        p0 = (m[:, None] * sc["V"]).sum(0)
+        for k in range(5):
+            rc, pieces = sim.step_adaptive()
+            assert rc == 0, (seed, k)
+            retried += pieces > 1
+            v = to_np(sim.state()[1]).reshape(-1, 3)
+            assert np.abs((m[:, None] * v).sum(0) - p0).max() <= 1e-6 * np.abs(m[:, None] * sc["V"]).sum(), (seed, k)
+    assert retried >= 1
+
+
+def test_changed_timestep_free_fall():
+    from paper_2609_25653_amd import Sim
+    sc = S.tiny_scene("tet", n_steps=6, h=0.01)
+    sim = Sim(sc)
+    sim.set_timestep(0.004)
+    x0 = sc["X"].copy()
+    L = sim.scene_scalars()["L"]
+    for n in range(1, 7):
+        assert sim.step()[0] == 0
+        ref = x0 + 0.004 ** 2 * sc["g"] * n * (n + 1) / 2
+        assert np.abs(to_np(sim.state()[0]).reshape(-1, 3) - ref).max() <= 1e-5 * 0.004 * L
