@@ -166,6 +166,13 @@ int ipc_scene_scalars(const ipc_ctx *ctx, int scene, double *kappa, double *L, d
  * kappa keeps its creation value.  For retries of a step that did not
  * converge: take it again as two steps of h/2 (host arrays; synchronous). */
 int ipc_set_timestep(ipc_ctx *ctx, const double *h_host);
+/* Friction lag passes per step, 1 <= passes <= 16 (default 1: friction
+ * lagged once at the step start, Sec. III-C).  With more, each scene whose
+ * Newton pass converged takes the lag again at its solution (closest-point
+ * weights, normals, normal forces and active pairs there; slips still
+ * measured from the step start) and runs Newton again from it; the stats
+ * count the iterations of all passes.  ipc_step_vjp needs 1 pass. */
+int ipc_set_friction_lag(ipc_ctx *ctx, int passes);
 
 /* State in the external layout (ndof doubles each).  ydot may be NULL on get. */
 int ipc_get_state(ipc_ctx *ctx, double *y_dev, double *ydot_dev);

@@ -88,6 +88,8 @@ def lib():
         L.or_set_params.argtypes = [P, D, ctypes.c_double]
         L.or_set_timestep.argtypes = [P, ctypes.c_double]
         L.or_set_timestep.restype = None
+        L.or_set_friction_lag.argtypes = [P, ctypes.c_int]
+        L.or_set_friction_lag.restype = None
         L.or_dG_dyn_T.argtypes = [P, D, D, D, D, D, D]
         L.or_dG_dtheta_T.restype = ctypes.c_double
         L.or_dG_dtheta_T.argtypes = [P, D, D, D, D, D, D]
@@ -268,6 +270,9 @@ class Oracle:
 
     def set_timestep(self, h):
         lib().or_set_timestep(self._h, float(h))
+
+    def set_friction_lag(self, passes):
+        lib().or_set_friction_lag(self._h, int(passes))
 
     def step_adaptive(self, max_depth=3):
         """One step with sub-stepping on failure (the recovery policy of the

@@ -164,6 +164,7 @@ struct OScene {
     double *sp_xa, *sp_xb, *sp_k;
     int *driven;
     int *joint_spring;           /* joint slot -> spring whose b-side point follows the joint reference */
+    int lag_passes;              /* friction lag passes per step (>= 1) */
     double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
     int max_newton, max_pcg;
     /* precompute (C1) */
@@ -278,6 +279,7 @@ OScene *or_create(const int *sz, const void *const *pp, const double *prm)
     s->h = prm[0]; s->g[0] = prm[1]; s->g[1] = prm[2]; s->g[2] = prm[3];
     s->dhat = prm[4]; s->kappa = prm[5]; s->mu = prm[6]; s->eps_v = prm[7];
     s->newton_tol = prm[8]; s->max_newton = (int)prm[9]; s->pcg_tol = prm[10];
+    s->lag_passes = 1;
     s->max_pcg = (int)prm[11]; s->ccd_s = prm[12];
 
     /* C1: per-tet inverse rest shape matrix, volume, Lame parameters, lumped mass */
@@ -1342,10 +1344,15 @@ static void terms_matvec(const OScene *s, const Terms *T, const double *v, doubl
 /* ------------------------------------------------------------------------ */
 /* friction lag (C10)                                                        */
 /* ------------------------------------------------------------------------ */
-static void compute_lag(OScene *s)
+/* The lag at state ylag (active pairs, closest-point weights, normals and
+ * normal forces there); the tangential displacement of a pair is measured
+ * from its weighted closest-point sum at state yref (NULL: ylag), i.e. from
+ * the step start whatever the state the lag was taken at. */
+static void compute_lag_at(OScene *s, const double *ylag, const double *yref)
 {
     free(s->lag); s->lag = NULL; s->nlag = 0;
-    double *xw = world_alloc(s, s->y);
+    double *xw = world_alloc(s, ylag);
+    double *xr = yref ? world_alloc(s, yref) : NULL;
     IVec cpt = {0}, cee = {0}, apt = {0}, aee = {0};
     candidates(s, xw, xw, &cpt, &cee);
     active_pairs(s, xw, &cpt, &cee, &apt, &aee);
@@ -1365,6 +1372,16 @@ static void compute_lag(OScene *s)
             closest(&P, x, lg->beta, r, Dm);
             double rn = sqrt(dot3(r, r));
             for (int c = 0; c < 3; ++c) { lg->nrm[c] = r[c] / rn; lg->rn[c] = r[c]; }
+            if (xr) {   /* the same weights on the reference positions */
+                double xref[12];
+                int cvr[4];
+                pair_x(s, xr, kind, i, j, cvr, xref);
+                for (int c = 0; c < 3; ++c) {
+                    double acc = 0.0;
+                    for (int q = 0; q < 4; ++q) acc += lg->beta[q] * xref[3 * q + c];
+                    lg->rn[c] = acc;
+                }
+            }
             double m = 1.0;
             lg->kind = kind;
             lg->type = t;
@@ -1378,8 +1395,10 @@ static void compute_lag(OScene *s)
             s->nlag++;
         }
     }
-    free(cpt.v); free(cee.v); free(apt.v); free(aee.v); free(xw);
+    free(cpt.v); free(cee.v); free(apt.v); free(aee.v); free(xw); free(xr);
 }
+
+static void compute_lag(OScene *s) { compute_lag_at(s, s->y, NULL); }
 
 void or_begin_step(OScene *s, const double *targets)
 {
@@ -1610,6 +1629,19 @@ static double newton_measure(const OScene *s, const double *p)
     return m;
 }
 
+/* A new time step h > 0: every use of h (predictor, h^2 weights, friction
+ * regularisation eps_v h, Newton stop) reads s->h; kappa keeps its value. */
+void or_set_timestep(OScene *s, double h)
+{
+    if (h > 0.0) s->h = h;
+}
+
+/* Friction lag passes per step (1: lagged once at the step start). */
+void or_set_friction_lag(OScene *s, int passes)
+{
+    if (passes >= 1) s->lag_passes = passes;
+}
+
 int or_step(OScene *s, const double *targets, OStats *st)
 {
     OStats loc; memset(&loc, 0, sizeof loc);
@@ -1622,6 +1654,15 @@ int or_step(OScene *s, const double *targets, OStats *st)
     memcpy(y, s->y, sizeof(double) * n);
     double thr = s->newton_tol * s->h * s->L;
     int status = 3;
+    /* friction lag passes: after a converged pass, the lag is taken again at
+     * the solution (displacements still from the step start) and Newton
+     * runs again from there */
+    for (int pass = 0; pass < s->lag_passes; ++pass) {
+    if (pass > 0) {
+        if (status != 0) break;
+        compute_lag_at(s, y, s->y);
+        status = 3;
+    }
     for (int j = 0; j < s->max_newton; ++j) {
         IVec apt = {0}, aee = {0};
         pairs_at(s, y, &apt, &aee);
@@ -1634,7 +1675,7 @@ int or_step(OScene *s, const double *targets, OStats *st)
         free(T.t); free(apt.v); free(aee.v);
         loc.pcg_iters_total += it;
         if (it > loc.pcg_iters_max) loc.pcg_iters_max = it;
-        loc.newton_iters = j + 1;
+        loc.newton_iters++;
         loc.energy = E0;
         if (newton_measure(s, p) <= thr) { status = 0; break; }
         /* CCD over the swept candidates, then backtracking on the energy */
@@ -1663,6 +1704,7 @@ int or_step(OScene *s, const double *targets, OStats *st)
         memcpy(y, yt, sizeof(double) * n);
         loc.energy = E1;
     }
+    }
     for (int i = 0; i < n; ++i) s->ydot[i] = (y[i] - s->y[i]) / s->h;
     memcpy(s->y, y, sizeof(double) * n);
     loc.status = status;
@@ -1679,13 +1721,6 @@ int or_step(OScene *s, const double *targets, OStats *st)
  * upstream adjoint a = dL/dy^{n+1} the sensitivities are -(dG/dq)^T w with
  * H w = a, H the unprojected Hessian at y^{n+1} and the lagged friction data
  * held as functions of y^n. */
-/* A new time step h > 0: every use of h (predictor, h^2 weights, friction
- * regularisation eps_v h, Newton stop) reads s->h; kappa keeps its value. */
-void or_set_timestep(OScene *s, double h)
-{
-    if (h > 0.0) s->h = h;
-}
-
 void or_set_params(OScene *s, const double *E, double mu)
 {
     if (E)

@@ -106,6 +106,9 @@ void    or_psd_project(double *A, int n);
 void    or_set_params(OScene *s, const double *E, double mu);
 /* New time step h > 0 (every use of h follows; kappa keeps its value). */
 void    or_set_timestep(OScene *s, double h);
+/* Friction lag passes per step (default 1): after a converged pass the lag
+ * is retaken at the solution, displacements still from the step start. */
+void    or_set_friction_lag(OScene *s, int passes);
 void    or_dG_dyn_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
                     const double *y_next, const double *w, double *out);
 double  or_dG_dtheta_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,

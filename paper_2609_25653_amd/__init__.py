@@ -179,6 +179,10 @@ class Sim:
         hh = np.broadcast_to(np.asarray(h, np.float64), (self.n_scenes,)).copy()
         self._check(lib().ipc_set_timestep(self._h, hh.ctypes.data_as(_lib._D)))
 
+    def set_friction_lag(self, passes):
+        """Friction lag passes per step (1: lagged once at the step start)."""
+        self._check(lib().ipc_set_friction_lag(self._h, int(passes)))
+
     def step_adaptive(self, max_depth=3):
         """One step of a single-scene context with sub-stepping on failure:
         if Newton does not converge (status 3) the step is taken again from

@@ -89,6 +89,7 @@ def lib():
         L.ipc_time_kernel.argtypes = [P, ctypes.c_int, ctypes.c_int, _D, _D]
         L.ipc_autotune.argtypes = [P, ctypes.c_int, _D, _I]
         L.ipc_set_timestep.argtypes = [P, _D]
+        L.ipc_set_friction_lag.argtypes = [P, ctypes.c_int]
         L.ipc_dualmesh_create.argtypes = [_I, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)]
         L.ipc_dualmesh_destroy.argtypes = [P]
         L.ipc_dualmesh_destroy.restype = None
@@ -105,7 +106,7 @@ def lib():
         for n in ("ipc_create", "ipc_destroy", "ipc_query", "ipc_scene_scalars", "ipc_get_state", "ipc_set_state",
                   "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg", "ipc_step",
                   "ipc_set_params", "ipc_step_vjp", "ipc_profile", "ipc_kernel_time", "ipc_time_kernel",
-                  "ipc_autotune", "ipc_set_timestep"):
+                  "ipc_autotune", "ipc_set_timestep", "ipc_set_friction_lag"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -520,6 +520,14 @@ extern "C" int ipc_set_timestep(ipc_ctx *c, const double *h_host)
     });
 }
 
+extern "C" int ipc_set_friction_lag(ipc_ctx *c, int passes)
+{
+    if (!c) return IPC_E_INVALID;
+    if (passes < 1 || passes > 16) { c->err = "friction lag passes must lie in [1, 16]"; return IPC_E_INVALID; }
+    c->lag_passes = passes;
+    return IPC_OK;
+}
+
 extern "C" int ipc_scene_scalars(const ipc_ctx *c, int s, double *kappa, double *L, double *thr)
 {
     if (!c || s < 0 || s >= c->n_scenes) return IPC_E_INVALID;
@@ -718,6 +726,7 @@ extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *
         return IPC_E_INVALID;
     if ((c->ND || c->NJ) && !targets_dev) { c->err = "targets required: the scenes have driven links or joint springs"; return IPC_E_INVALID; }
     if (!(eta > 0.0)) { c->err = "eta must be > 0"; return IPC_E_INVALID; }
+    if (c->lag_passes != 1) { c->err = "the adjoint differentiates steps lagged once at their start (ipc_set_friction_lag(ctx, 1))"; return IPC_E_INVALID; }
     int status = IPC_OK;
     int rc = guard(c, [&] {
         Dev &D = c->d;
@@ -814,6 +823,28 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
     int max_newton = 0;
     for (auto &si : c->sc) max_newton = std::max(max_newton, si.max_newton);
     std::vector<int> want(ns);
+    // friction lag passes: after a converged pass the lag is taken again at
+    // the solution (slips still measured from the step start) and Newton
+    // runs again from there, for the scenes that converged
+    for (int pass = 0; pass < c->lag_passes; ++pass) {
+    if (pass > 0) {
+        bool again = false;
+        for (int s = 0; s < ns; ++s) {
+            on[s] = S[s].status == IPC_OK;
+            if (on[s]) { S[s].status = IPC_E_NOT_CONVERGED; again = true; }
+        }
+        if (!again) break;
+        pairs_from_scratch(c, D.y.p);          // pairs and world positions at the solution
+        launch_world(c, D.y0.p, D.xw1.p);      // the step start
+        launch_lag(c, D.xw.p, D.xw1.p);
+        c->n_lag_pt = c->n_pt;
+        hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_PT), seg_ptr(c, R_LPT));
+        hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_EE), seg_ptr(c, R_LEE));
+        eval_energy(c, D.y.p, false);
+        sc = read_scal(c);
+        for (int s = 0; s < ns; ++s)
+            if (on[s]) { E0[s] = sc[(size_t)s * NSLOT + S_E]; S[s].energy = E0[s]; }
+    }
     for (int j = 0; j < max_newton; ++j) {
         bool any = false;
         for (int s = 0; s < ns; ++s) {
@@ -867,7 +898,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         any = false;
         for (int s = 0; s < ns; ++s) {
             if (!on[s]) continue;
-            S[s].newton_iters = j + 1;
+            S[s].newton_iters += 1;
             S[s].pcg_iters_total += it[s];
             S[s].pcg_iters_max = std::max(S[s].pcg_iters_max, it[s]);
             if (sc[(size_t)s * NSLOT + S_NEWTON_MAX] <= c->sc[s].thr) { on[s] = 0; S[s].status = IPC_OK; }
@@ -928,6 +959,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         // pairs at the new iterate from the swept candidates (a superset)
         launch_world(c, D.y.p, D.xw.p);
         narrow_phase(c, D.xw.p);
+    }
     }
     hipLaunchKernelGGL(k_velocity, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.sparam.p, D.y.p, D.y0.p, D.ydot.p);
     IPC_HIP(hipStreamSynchronize(st));

@@ -915,13 +915,15 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, dou
 
 // ---------------------------------------------------------------------------
 // friction, lagged at the step start (closest-point weights beta, normal n,
-// normal force lambda = -kappa m b'(d))
+// normal force lambda = -kappa m b'(d)); a later lag pass takes them at the
+// current solution but keeps measuring slip from the step start: lrn is the
+// weighted closest-point sum at the reference positions xref
 // ---------------------------------------------------------------------------
 __global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee, const int4 *__restrict__ tri,
                       const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
                       const double *__restrict__ sparam, const double *__restrict__ rest2, int4 *__restrict__ lcv,
                       double *__restrict__ lbeta, double *__restrict__ lnrm, double *__restrict__ llam, double *__restrict__ lrn,
-                      int *__restrict__ ltype, double *__restrict__ lex)
+                      int *__restrict__ ltype, double *__restrict__ lex, const double *__restrict__ xref)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npt + nee) return;
@@ -953,11 +955,18 @@ __global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 
     lcv[i] = make_int4(cv[0], cv[1], cv[2], cv[3]);
     for (int k = 0; k < 4; ++k) lbeta[4 * (size_t)i + k] = beta[k];
     lnrm[3 * (size_t)i] = r.x / rn; lnrm[3 * (size_t)i + 1] = r.y / rn; lnrm[3 * (size_t)i + 2] = r.z / rn;
+    if (xref) {   // the same weights on the reference positions
+        r = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 4; ++k) {
+            d3 p = ld3(xref, cv[k]);
+            r.x += beta[k] * p.x; r.y += beta[k] * p.y; r.z += beta[k] * p.z;
+        }
+    }
     lrn[3 * (size_t)i] = r.x; lrn[3 * (size_t)i + 1] = r.y; lrn[3 * (size_t)i + 2] = r.z;
     llam[i] = -kappa * m * barrier1(d, dh);
 }
 
-void launch_lag(ipc_ctx *c, const double *xw)
+void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
 {
     Dev &D = c->d;
     int64_t n = c->n_pt + c->n_ee;
@@ -973,7 +982,7 @@ void launch_lag(ipc_ctx *c, const double *xw)
     if (n == 0) return;
     hipLaunchKernelGGL(k_lag, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,
                        D.edge.p, xw, D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p, D.lag_lam.p,
-                       D.lag_rn.p, D.lag_type.p, D.lag_ex.p);
+                       D.lag_rn.p, D.lag_type.p, D.lag_ex.p, xref);
 }
 
 template <int MODE>

@@ -265,6 +265,7 @@ struct ipc_ctx {
     bool coarse = true;                   // coarse domains built (the PCG preconditioner's correction)
     bool coarse_on = false;               // the PCG applies the coarse correction
     bool coarse_forced = false;           // on by request, whatever the size
+    int lag_passes = 1;                   // friction lag passes per step
     int n_cdom = 0, n_cgrp = 0;           // its domains and groups over all scenes
     std::vector<int> seg_cdom;            // per scene: first domain (n_scenes + 1)
     int64_t ext_nodes = 0;

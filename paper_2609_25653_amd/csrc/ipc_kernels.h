@@ -34,7 +34,8 @@ void cand_check(ipc_ctx *c, const double *xw0, const double *xw1, int *flag);
 // narrow phase: active pairs from the candidate lists at xw
 void narrow_phase(ipc_ctx *c, const double *xw);
 void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project);
-void launch_lag(ipc_ctx *c, const double *xw);
+// the lag at world positions xw; slips measured from xref (nullptr: xw)
+void launch_lag(ipc_ctx *c, const double *xw, const double *xref = nullptr);
 void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g);
 // pair-local contact blocks as row-sorted extra blocks of the product, and the
 // rows the product takes one wavefront per row

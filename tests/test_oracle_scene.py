@@ -266,3 +266,25 @@ def test_no_interpenetration_exact():
             assert O.dist2_pt(x[r].ravel())[0] > 0
         for r in ee:
             assert O.dist2_ee(x[r].ravel())[0] > 0
+
+
+def test_coulomb_deceleration_with_lag_passes():
+    """Three friction lag passes per step: the block still loses mu g h of
+    speed per step.  The passes retake weights, normals and normal forces at
+    the solution but keep measuring the slip from the step start (measured
+    from the re-lag point, the second pass would see almost no slip and the
+    deceleration would collapse)."""
+    sc = S.block_drop(n_steps=60)
+    o = advanced(sc, 40)
+    o.set_friction_lag(3)
+    y, v = o.state()
+    v = v.reshape(-1, 3)
+    v[:, 0] = 0.1
+    o.set_state(y, v.ravel())
+    vx = []
+    for _ in range(3):
+        rc, st = o.step()
+        assert rc == 0 and st["newton_iters"] >= 3
+        vx.append(o.state()[1].reshape(-1, 3)[:, 0].mean())
+    dv = -np.diff([0.1] + vx)
+    assert np.allclose(dv, 0.3 * 9.81 * 0.01, rtol=2e-2)
