@@ -198,17 +198,30 @@ void setup_after_create(ipc_ctx *c)
     }
     upload_sparam(c);
     D.h2s.upload(h2, c->stream); D.grav.upload(grav, c->stream); D.maxpcg.upload(maxpcg, c->stream);
-    // Morton boxes: initial world bounds of each scene's contact vertices, enlarged
+    // Morton boxes: initial world bounds of each scene's moving contact
+    // vertices (FEM and body surfaces; all of them if there are none),
+    // enlarged.  Static geometry is left out: a large ground would otherwise
+    // set the quantisation and crowd the moving primitives into few codes
+    // (its primitives get codes clamped to the box, which any tree allows).
     {
         launch_world(c, D.y.p, D.xw.p);
         std::vector<double> xw(3 * (size_t)c->CV);
-        if (c->CV) IPC_HIP(hipMemcpyAsync(xw.data(), D.xw.p, xw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        std::vector<int> cvn(c->CV), cvb(c->CV);
+        if (c->CV) {
+            IPC_HIP(hipMemcpyAsync(xw.data(), D.xw.p, xw.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            IPC_HIP(hipMemcpyAsync(cvn.data(), D.cv_node.p, cvn.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            IPC_HIP(hipMemcpyAsync(cvb.data(), D.cv_body.p, cvb.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        }
         sync(c);
         for (int s = 0; s < ns; ++s) {
             SceneInfo &S = c->sc[s];
             double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
-            for (int i = S.cv0; i < S.cv0 + S.ncv; ++i)
+            bool any_moving = false;
+            for (int i = S.cv0; i < S.cv0 + S.ncv; ++i) any_moving = any_moving || cvn[i] >= 0 || cvb[i] >= 0;
+            for (int i = S.cv0; i < S.cv0 + S.ncv; ++i) {
+                if (any_moving && cvn[i] < 0 && cvb[i] < 0) continue;
                 for (int k = 0; k < 3; ++k) { l[k] = std::min(l[k], xw[3 * i + k]); h[k] = std::max(h[k], xw[3 * i + k]); }
+            }
             for (int k = 0; k < 3; ++k) {
                 if (!(h[k] >= l[k])) { l[k] = 0.0; h[k] = 1.0; }
                 double ext = std::max(h[k] - l[k], 1e-3), m = 0.25 * ext;
