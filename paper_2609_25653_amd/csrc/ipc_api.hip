@@ -821,7 +821,6 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         S[s].alpha_min = 1.0;
         S[s].n_lag = 0;
     }
-    for (int s = 0; s < ns; ++s) S[s].n_lag = c->h_lag_seg.empty() ? 0 : 0;
     std::vector<int> on(ns, 1);
     // energy at the start
     eval_energy(c, D.y.p, false);

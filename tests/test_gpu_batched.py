@@ -96,3 +96,29 @@ def test_batched_arms_match_single_and_oracle():
             part = yb[offs[i]:offs[i + 1]]
             assert np.abs(part - sim.state()[0].cpu().numpy()).max() <= 1e-6 * o.L, (k, i)
             assert np.abs(part - o.state()[0]).max() <= 1e-6 * o.L, (k, i)
+
+
+def test_batched_with_coarse_correction(monkeypatch):
+    """The PCG's coarse correction forced on in a batch of uneven scenes
+    (each scene its own groups and domains, several scenes per PCG-step
+    workgroup): batched equals one at a time (also corrected) and the
+    oracle."""
+    from paper_2609_25653_amd import Sim
+    monkeypatch.setenv("IPC_PCG_COARSE", "1")
+    n = 10
+    scenes = _mixed(n)
+    batch = Sim(scenes)
+    assert batch.pcg_coarse
+    singles = [Sim(s) for s in scenes]
+    oracles = [O.Oracle(s) for s in scenes]
+    offs = batch.dof_offsets
+    for k in range(n):
+        rc, st = batch.step()
+        assert rc == 0, st
+        yb = batch.state()[0].cpu().numpy()
+        for i, (sim, o) in enumerate(zip(singles, oracles)):
+            assert sim.step()[0] == 0
+            assert o.step()[0] == 0
+            part = yb[offs[i]:offs[i + 1]]
+            assert np.abs(part - sim.state()[0].cpu().numpy()).max() <= 1e-6 * o.L, (k, i)
+            assert np.abs(part - o.state()[0]).max() <= 1e-6 * o.L, (k, i)
