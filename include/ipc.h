@@ -282,10 +282,12 @@ int ipc_time_kernel(ipc_ctx *ctx, int kernel, int reps, double *avg_us, double *
 /* Autotuner: times the Hessian product on the matrix of the last assembly
  * with 1, 2, 4, 8 and 16 lanes per row (reps back-to-back launches each,
  * HIP events on the context's stream) and keeps the fastest for all later
- * products (8 lanes unless another count is more than 3 % faster).  us_host[5] (nullable) receives the five times in microseconds,
- * lanes_host (nullable) the choice.  The default before any call is 8 lanes
- * (the environment variable IPC_SPMV_LANES, read at ipc_create, overrides
- * it).  Uses the context's solver scratch vectors. */
+ * products (8 lanes unless another count is more than 3 % faster).
+ * us_host[5] (nullable) receives the five times in microseconds, lanes_host
+ * (nullable) the choice.  The default before any call is 8 lanes; the
+ * environment variable IPC_SPMV_LANES (1, 2, 4, 8 or 16), read at
+ * ipc_create, fixes the count instead: the autotuner still times every
+ * count but keeps that one.  Uses the context's solver scratch vectors. */
 int ipc_autotune(ipc_ctx *ctx, int reps, double *us_host, int32_t *lanes_host);
 
 #ifdef __cplusplus

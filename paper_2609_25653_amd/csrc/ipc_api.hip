@@ -461,7 +461,10 @@ extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_
         const char *nl = std::getenv("IPC_SPMV_LANES");
         if (nl) {
             int L = std::atoi(nl);
-            if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) c->spmv_lanes = L;
+            if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) {
+                c->spmv_lanes = L;
+                c->spmv_lanes_forced = true;
+            }
         }
         const char *nc = std::getenv("IPC_PCG_COARSE");   // 0: never, 1: always, else by size and the autotuner
         c->coarse = !(nc && nc[0] == '0');
@@ -1089,7 +1092,9 @@ extern "C" int ipc_autotune(ipc_ctx *c, int reps, double *us_host, int32_t *lane
     return guard(c, [&] {
         bool prof = c->prof;
         c->prof = false;
+        int keep = c->spmv_lanes;
         autotune_spmv(c, reps, us_host);
+        if (c->spmv_lanes_forced) c->spmv_lanes = keep;
         c->prof = prof;
         if (lanes_host) *lanes_host = c->spmv_lanes;
     });

@@ -2,7 +2,8 @@
 // terms of the incremental potential (Sec. III-C.1-2, Eq. (1)-(3)).
 //
 // One thread per tetrahedron / body / spring.  The FEM kernel forms the 9x9
-// Hessian of the energy density in F, projects it to PSD in registers, maps it
+// Hessian of the energy density in F, projects it to PSD in registers (the
+// energy's closed-form eigensystem: only negative modes are removed), maps it
 // to the 16 3x3 blocks of the element and writes them, with its 12 gradient
 // entries, to per-tet arrays; two gather kernels then sum them per matrix slot
 // and per node in a fixed order (no atomics, deterministic).  Energies are
@@ -10,6 +11,7 @@
 #include "ipc_device.h"
 #include "ipc_internal.h"
 #include "ipc_kernels.h"
+#include "ipc_eigsys.h"
 
 namespace ipc {
 
@@ -107,7 +109,16 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                             }
                             H[pk9(R, C)] = v;
                         }
-            if (project) psd_project9(H);
+            if (project) {
+                double Fm[3][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    Fm[0][a] = f[a].x;
+                    Fm[1][a] = f[a].y;
+                    Fm[2][a] = f[a].z;
+                }
+                iso::project_snh(H, Fm, mu, lh, sc);
+            }
 #pragma unroll
             for (int B = 0; B < 4; ++B) {
                 double Tm[9][3];   // Tm[(j,r)][q] = sum_l c[B][l] H[(j,r),(l,q)]
@@ -168,7 +179,7 @@ __global__ void k_fem_grad_gather(int N, int T, const int *__restrict__ adj_ptr,
 // ---------------------------------------------------------------------------
 // affine bodies: inertia (4x4 mass matrix (x) I3) + orthogonality kappa V |AA^T - I|^2
 // ---------------------------------------------------------------------------
-template <int MODE>   // launched with 64 threads: the whole register file is available to one body's 9x9 projection
+template <int MODE>   // launched with 64 threads (few bodies: short waves)
 __global__ void __launch_bounds__(64) k_body(int NB, const int *__restrict__ node0, const int *__restrict__ bscene, const double *__restrict__ bM,
                        const double *__restrict__ bvol, const double *__restrict__ bkappa, const double *__restrict__ h2s,
                        const double *__restrict__ y, const double *__restrict__ xt, double *__restrict__ g,
@@ -244,7 +255,7 @@ __global__ void __launch_bounds__(64) k_body(int NB, const int *__restrict__ nod
                     if (R > Cc) continue;
                     H[pk9(R, Cc)] = 4.0 * kv * ((a == cr_ ? AtA[bcol][dcol] : 0.0) + A[a][dcol] * A[cr_][bcol] + (bcol == dcol ? C[a][cr_] : 0.0));
                 }
-    if (project) psd_project9(H);
+    if (project) iso::project_ortho(H, A, kv);
     // add the 16 node blocks into the block-CSR values (the body's blocks are
     // touched by no other kernel during assembly)
     const int *sl = bslot + 16 * (size_t)b;

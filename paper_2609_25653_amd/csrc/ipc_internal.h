@@ -262,6 +262,7 @@ struct ipc_ctx {
     int long_cap = 0;                     // long-row workgroups the product launches (grows, multiple of 64)
     int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
+    bool spmv_lanes_forced = false;       // set by IPC_SPMV_LANES: the autotuner times but keeps it
     bool coarse = true;                   // coarse domains built (the PCG preconditioner's correction)
     bool coarse_on = false;               // the PCG applies the coarse correction
     bool coarse_forced = false;           // on by request, whatever the size
