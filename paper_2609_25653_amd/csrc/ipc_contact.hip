@@ -702,30 +702,76 @@ __device__ __forceinline__ d3 gather_cv(const Map &m, const double *v)
 // for a surface triangle or edge against static geometry), add the pair's
 // world-vertex blocks straight into the block-CSR values and report true; the
 // pair then costs nothing in the PCG products.
-__device__ __forceinline__ int find_block(const int *row_ptr, const int *col, int r, int cc)
+//
+// bsr_slots finds the blocks (slot -1 where a vertex is static); the up to
+// 16 look-ups are branchless lower-bound searches over the rows' sorted columns, advanced one halving step at a time all together, so
+// that a step issues all of its loads at once: a pair waits for about
+// log2(row length) + 1 rounds of loads instead of one round per probe.
+__device__ __forceinline__ bool bsr_slots(const Map *m, const int *row_ptr, const int *col, int slot[4][4])
 {
-    int lo = row_ptr[r], hi = row_ptr[r + 1];
-    while (lo < hi) {
-        int m = (lo + hi) >> 1;
-        if (col[m] < cc) lo = m + 1; else hi = m;
+    int nd[4], lo[4], len[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (m[k].body >= 0) return false;
+        nd[k] = m[k].node;
     }
-    return (lo < row_ptr[r + 1] && col[lo] == cc) ? lo : -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lo[k] = 0;
+        len[k] = 0;
+        if (nd[k] >= 0) {
+            lo[k] = row_ptr[nd[k]];
+            len[k] = row_ptr[nd[k] + 1] - lo[k];
+            if (len[k] <= 0) return false;
+        }
+    }
+    int base[4][4], n[4][4], most = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            bool on = nd[k] >= 0 && nd[l] >= 0;
+            base[k][l] = lo[k];
+            n[k][l] = on ? len[k] : 0;
+            most = max(most, n[k][l]);
+        }
+    // invariant: the first column >= nd[l] of row k lies in [base, base + n]
+    while (most > 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                int h = n[k][l] >> 1;
+                if (h > 0) {
+                    if (col[base[k][l] + h] < nd[l]) base[k][l] += h;
+                    n[k][l] -= h;
+                }
+            }
+        most -= most >> 1;
+    }
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            slot[k][l] = -1;
+            if (n[k][l] == 0) continue;
+            int b = base[k][l], end = lo[k] + len[k];
+            int c0 = col[b], c1 = b + 1 < end ? col[b + 1] : -1;
+            slot[k][l] = c0 == nd[l] ? b : (c0 < nd[l] && c1 == nd[l] ? b + 1 : -1);
+            all = all && slot[k][l] >= 0;
+        }
+    return all;
 }
 template <class F>
 __device__ __forceinline__ bool merge_into_bsr(const Map *m, const int *row_ptr, const int *col, double *val, F blk)
 {
     int slot[4][4];
-    for (int k = 0; k < 4; ++k) {
-        if (m[k].body >= 0) return false;
-        for (int l = 0; l < 4; ++l) {
-            slot[k][l] = -1;
-            if (m[k].node < 0 || m[l].node < 0) continue;
-            slot[k][l] = find_block(row_ptr, col, m[k].node, m[l].node);
-            if (slot[k][l] < 0) return false;
-        }
-    }
+    if (!bsr_slots(m, row_ptr, col, slot)) return false;
     double B[9];
-    for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)   // unrolled: blk sees compile-time (k, l)
+#pragma unroll
         for (int l = 0; l < 4; ++l) {
             if (slot[k][l] < 0) continue;
             blk(k, l, B);
@@ -966,6 +1012,32 @@ __global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 
     llam[i] = -kappa * m * barrier1(d, dh);
 }
 
+// Per lag: the matrix block of every (k, l) of a lag pair whose blocks are
+// all in the pattern (key nnzb: none), for the slot-sorted gather below.
+__global__ void k_lag_slots(int n, int nnzb, const int4 *__restrict__ lcv, const int *__restrict__ cv_node,
+                            const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
+                            const int *__restrict__ row_ptr, const int *__restrict__ col, int *__restrict__ lmerge,
+                            int *__restrict__ key, int *__restrict__ code)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int4 c4 = lcv[i];
+    int cv[4] = {c4.x, c4.y, c4.z, c4.w};
+    Map mp[4];
+    for (int k = 0; k < 4; ++k) mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
+    int slot[4][4];
+    bool on = bsr_slots(mp, row_ptr, col, slot);
+    lmerge[i] = on ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            size_t o = 16 * (size_t)i + 4 * k + l;
+            key[o] = on && slot[k][l] >= 0 ? slot[k][l] : nnzb;
+            code[o] = (int)o;
+        }
+}
+
 void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
 {
     Dev &D = c->d;
@@ -975,6 +1047,9 @@ void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
         D.lag_cv.alloc(c->cap_lag); D.lag_beta.alloc(4 * c->cap_lag); D.lag_nrm.alloc(3 * c->cap_lag);
         D.lag_lam.alloc(c->cap_lag); D.lag_rn.alloc(3 * c->cap_lag); D.lag_M.alloc(6 * c->cap_lag);
         D.lag_flag.alloc(c->cap_lag); D.lag_type.alloc(c->cap_lag); D.lag_ex.alloc(c->cap_lag);
+        D.lag_merge.alloc(c->cap_lag);
+        D.lag_key.alloc(16 * c->cap_lag); D.lag_code.alloc(16 * c->cap_lag);
+        D.lag_key2.alloc(16 * c->cap_lag); D.lag_code2.alloc(16 * c->cap_lag);
     }
     c->n_lag = n;
     c->h_lag_seg.assign(c->n_scenes + 1, 0);
@@ -983,6 +1058,60 @@ void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
     hipLaunchKernelGGL(k_lag, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,
                        D.edge.p, xw, D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p, D.lag_lam.p,
                        D.lag_rn.p, D.lag_type.p, D.lag_ex.p, xref);
+    // slot lists of the merged friction blocks, sorted by slot once per lag
+    int m = (int)(16 * n);
+    hipLaunchKernelGGL(k_lag_slots, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, c->nnzb, D.lag_cv.p, D.cv_node.p,
+                       D.cv_body.p, D.cv_x.p, D.body_node0.p, D.row_ptr.p, D.col.p, D.lag_merge.p, D.lag_key.p, D.lag_code.p);
+    int end_bit = 1;
+    while (end_bit < 31 && (1 << end_bit) <= c->nnzb) ++end_bit;
+    size_t bytes = 0;
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.lag_key.p, D.lag_key2.p, D.lag_code.p, D.lag_code2.p, m, 0, end_bit,
+                                               c->stream));
+    D.lag_sort_tmp.alloc(bytes + 16);
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.lag_sort_tmp.p, bytes, D.lag_key.p, D.lag_key2.p, D.lag_code.p, D.lag_code2.p, m, 0,
+                                               end_bit, c->stream));
+}
+
+// Friction Hessian blocks of the merged lag pairs into the matrix values.
+// One thread per (pair, k, l) entry of the slot-sorted list forms
+// beta_k beta_l M; a segmented scan over each wavefront's lanes (runs of
+// equal slots are contiguous) sums each run, and the run's last lane in the
+// wavefront adds the sum to the block.  A block gets one atomic add per
+// wavefront its run touches, however many pairs share it.
+__global__ void __launch_bounds__(256) k_fric_gather(int m, int nnzb, const int *__restrict__ key, const int *__restrict__ code,
+                                                     const double *__restrict__ lbeta, const double *__restrict__ lM,
+                                                     double *__restrict__ val)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int lane = threadIdx.x & 63;
+    int sl = t < m ? key[t] : -1;
+    bool on = sl >= 0 && sl < nnzb;
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (on) {
+        int cd = code[t], i = cd >> 4, k = (cd >> 2) & 3, l = cd & 3;
+        double w = lbeta[4 * (size_t)i + k] * lbeta[4 * (size_t)i + l];
+        const double *M = lM + 6 * (size_t)i;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) a[q] = w * M[q];
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int ok = __shfl_up(sl, d, 64);
+        double o[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = __shfl_up(a[q], d, 64);
+        if (lane >= d && ok == sl) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) a[q] += o[q];
+        }
+    }
+    int nx = __shfl_down(sl, 1, 64);
+    bool last = lane == 63 || t + 1 >= m || nx != sl;
+    if (!on || !last) return;
+    double *d = val + 9 * (size_t)sl;
+    atomicAdd(d + 0, a[0]); atomicAdd(d + 1, a[1]); atomicAdd(d + 2, a[2]);
+    atomicAdd(d + 3, a[1]); atomicAdd(d + 4, a[3]); atomicAdd(d + 5, a[4]);
+    atomicAdd(d + 6, a[2]); atomicAdd(d + 7, a[4]); atomicAdd(d + 8, a[5]);
 }
 
 template <int MODE>
@@ -991,8 +1120,7 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
                            const int *__restrict__ cv_scene, const double *__restrict__ sparam, const int *__restrict__ cv_node,
                            const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
                            double *__restrict__ g, double *__restrict__ lM,
-                           double *__restrict__ pe, const int *__restrict__ row_ptr, const int *__restrict__ col,
-                           double *__restrict__ val, int *__restrict__ lflag)
+                           double *__restrict__ pe, const int *__restrict__ lmerge, int *__restrict__ lflag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1029,11 +1157,9 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
             M[3 * a + b] = w * (cu * comp(u, a) * comp(u, b) + f1s * ((a == b ? 1.0 : 0.0) - comp(nr, a) * comp(nr, b)));
-    auto blk = [&](int k, int l, double *B) {
-        for (int q = 0; q < 9; ++q) B[q] = beta[k] * beta[l] * M[q];
-    };
-    if (merge_into_bsr(mp, row_ptr, col, val, blk)) { lflag[i] = 1; return; }
-    lflag[i] = 0;
+    // a pair whose blocks are all in the pattern is added into the matrix
+    // values by k_fric_gather; the others stay pair-local in the products
+    lflag[i] = lmerge[i];
     double *o = lM + 6 * (size_t)i;
     o[0] = M[0]; o[1] = M[1]; o[2] = M[2]; o[3] = M[4]; o[4] = M[5]; o[5] = M[8];
 }
@@ -1047,12 +1173,16 @@ void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p,
                            D.lag_lam.p, D.lag_rn.p, xw, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p,
-                           g, D.lag_M.p, D.fr_part.p, D.row_ptr.p, D.col.p, D.val.p, D.lag_flag.p);
+                           g, D.lag_M.p, D.fr_part.p, D.lag_merge.p, D.lag_flag.p);
     };
     D.fr_part.alloc(n + 1);
     if (mode == 0) go(k_friction<0>);
     else if (mode == 1) go(k_friction<1>);
-    else go(k_friction<2>);
+    else {
+        go(k_friction<2>);
+        hipLaunchKernelGGL(k_fric_gather, dim3(blocks_for(16 * n)), dim3(BLOCK), 0, c->stream, (int)(16 * n), c->nnzb,
+                           D.lag_key2.p, D.lag_code2.p, D.lag_beta.p, D.lag_M.p, D.val.p);
+    }
 }
 
 // ---------------------------------------------------------------------------

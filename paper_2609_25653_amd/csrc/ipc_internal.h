@@ -220,6 +220,10 @@ struct Dev {
     DBuf<double> lag_M;                    // 6 (symmetric 3x3) per lag pair, scaled
     DBuf<int> lag_type;                    // distance type at the lag state
     DBuf<double> lag_ex;                   // edge-edge mollifier threshold (0 for PT)
+    DBuf<int> lag_merge;                   // 1: all blocks of the lag pair are in the block-CSR pattern
+    DBuf<int> lag_key, lag_code;           // 16 per lag pair: block slot (nnzb: none) and 16 i + 4 k + l
+    DBuf<int> lag_key2, lag_code2;         // the same sorted by slot (stable)
+    DBuf<unsigned char> lag_sort_tmp;
     // scalars and partials
     DBuf<double> scal;                     // n_scenes x NSLOT
     DBuf<double> part_node, part_tet;      // one partial per wavefront
