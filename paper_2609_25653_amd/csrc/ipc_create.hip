@@ -535,7 +535,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     D.tv.upload(tv, st);
     D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);
     D.sc_ptr.upload(sc_ptr, st); D.sc_list.upload(sc_list, st);
-    D.tgrad.alloc(12 * (size_t)std::max(tet, 1)); D.telem.alloc(144 * (size_t)std::max(tet, 1));
+    D.tgrad.alloc(12 * (size_t)std::max(tet, 1)); D.telem.alloc(90 * (size_t)std::max(tet, 1));
     D.row_ptr.upload(row_ptr, st); D.col.upload(col, st); D.diag_slot.upload(diag_slot, st);
     D.val.alloc(9 * (size_t)std::max(c->nnzb, 1));
     D.val_const.alloc(9 * (size_t)std::max(c->nnzb, 1)); D.val_const.zero(st, 9 * (size_t)std::max(c->nnzb, 1));

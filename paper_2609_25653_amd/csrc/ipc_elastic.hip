@@ -4,10 +4,11 @@
 // One thread per tetrahedron / body / spring.  The FEM kernel forms the 9x9
 // Hessian of the energy density in F, projects it to PSD in registers (the
 // energy's closed-form eigensystem: only negative modes are removed), maps it
-// to the 16 3x3 blocks of the element and writes them, with its 12 gradient
-// entries, to per-tet arrays; two gather kernels then sum them per matrix slot
-// and per node in a fixed order (no atomics, deterministic).  Energies are
-// reduced per wavefront (scene-aligned tiles) for a deterministic sum.
+// to the 3x3 blocks of the element and writes the 10 upper ones, with its 12
+// gradient entries, to per-tet arrays; two gather kernels then sum them per
+// matrix slot and per node in a fixed order (no atomics, deterministic).
+// Energies are reduced per wavefront (scene-aligned tiles) for a
+// deterministic sum.
 #include "ipc_device.h"
 #include "ipc_internal.h"
 #include "ipc_kernels.h"
@@ -40,6 +41,9 @@ __global__ void k_node_inertia(int N, const double *__restrict__ y, const double
 // ---------------------------------------------------------------------------
 // FEM (rest-stable Stable Neo-Hookean)
 // ---------------------------------------------------------------------------
+// index of the upper block (A, B), A <= B, of a tet's 4x4 block matrix (0..9)
+__host__ __device__ constexpr int tet_ublk(int A, int B) { return A * (7 - A) / 2 + B; }
+
 template <int MODE>   // 0 energy, 1 energy+gradient, 2 gradient+Hessian
 __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv, const double *__restrict__ Bm,
                                              const double *__restrict__ vol, const double *__restrict__ tmu,
@@ -128,8 +132,8 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                     for (int q = 0; q < 3; ++q)
                         Tm[R][q] = c[B][0] * H[pk9(R, q)] + c[B][1] * H[pk9(R, 3 + q)] + c[B][2] * H[pk9(R, 6 + q)];
 #pragma unroll
-                for (int A = 0; A < 4; ++A) {
-                    double *blk = telem + 9 * ((size_t)(4 * A + B) * T + e);
+                for (int A = 0; A <= B; ++A) {   // upper blocks only: (B, A) is the transpose
+                    double *blk = telem + 9 * ((size_t)tet_ublk(A, B) * T + e);
 #pragma unroll
                     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -144,17 +148,21 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
 }
 
 // matrix values: the constant part (lumped mass, springs) plus the tet blocks
-// of each slot, summed in tet order; one thread per (slot, entry)
+// of each slot, summed in tet order; one thread per (slot, entry).  A tet
+// stores its 10 upper blocks (A <= B); block (A, B) with A > B is read as
+// entry (c, r) of block (B, A).
 __global__ void k_bsr_assemble(int64_t n9, int T, const int *__restrict__ sc_ptr, const int *__restrict__ sc_list,
                                const double *__restrict__ telem, const double *__restrict__ vc, double *__restrict__ val)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n9) return;
-    int k = (int)(i / 9), q = (int)(i % 9);
+    int k = (int)(i / 9), q = (int)(i % 9), qt = 3 * (q % 3) + q / 3;
     double acc = vc[i];
     for (int j = sc_ptr[k]; j < sc_ptr[k + 1]; ++j) {
-        int code = sc_list[j];
-        acc += telem[9 * ((size_t)(code & 15) * T + (code >> 4)) + q];
+        int code = sc_list[j], A = (code >> 2) & 3, B = code & 3;
+        bool tr = A > B;
+        int u = tr ? tet_ublk(B, A) : tet_ublk(A, B);
+        acc += telem[9 * ((size_t)u * T + (code >> 4)) + (tr ? qt : q)];
     }
     val[i] = acc;
 }
@@ -357,11 +365,11 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
     if (mode == 2)
         hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, c->T, D.sc_ptr.p, D.sc_list.p,
                            D.telem.p, D.val_const.p, D.val.p);
-    // algorithmic bytes: tet data in (112), per-tet gradient and blocks out and
-    // back in (96 and 1152, twice), node gradient in and out (48), matrix out
-    // and its constant part in (2 x 72 per block)
+    // algorithmic bytes: tet data in (112), per-tet gradient and upper blocks
+    // out and back in (96 and 720, twice), node gradient in and out (48),
+    // matrix out and its constant part in (2 x 72 per block)
     if (k >= 0)
-        prof_end(c, k, mode == 2 ? (112.0 + 2 * 1248.0) * c->TREAL + 48.0 * c->NFEM + 144.0 * c->nnzb : 112.0 * c->TREAL + 24.0 * c->NFEM);
+        prof_end(c, k, mode == 2 ? (112.0 + 2 * 816.0) * c->TREAL + 48.0 * c->NFEM + 144.0 * c->nnzb : 112.0 * c->TREAL + 24.0 * c->NFEM);
 }
 
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)
