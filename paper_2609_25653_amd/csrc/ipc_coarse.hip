@@ -144,13 +144,14 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
 }
 
 // One workgroup per domain: the inverse of its n x n block (n = 3 x groups)
-// by Gauss-Jordan elimination without pivoting in LDS (the pivots of an SPD
-// matrix are positive), written over the block.  The block is padded to
-// CG_N with the identity, which stays decoupled, so every thread keeps the
-// same CG_N^2 / CG_INV entries for all pivots.  A domain whose block shows a
-// pivot that is not positive (the unprojected Hessian of the adjoint can be
-// indefinite) gets a zero inverse: there the preconditioner is block-Jacobi
-// alone.
+// by Gauss-Jordan elimination in LDS on 3x3 diagonal pivot blocks, without
+// exchanges (every diagonal block of an SPD matrix is SPD), written over the
+// block: n / 3 steps of two barriers each.  The block is padded to CG_N with
+// the identity, which stays decoupled, so every thread keeps the same
+// CG_N^2 / CG_INV entries for all pivots.  A domain whose block shows a pivot
+// block that is not positive definite (the unprojected Hessian of the
+// adjoint can be indefinite) gets a zero inverse: there the preconditioner
+// is block-Jacobi alone.
 constexpr int CG_INV = 1024, CG_PER = CG_N * CG_N / CG_INV;
 static_assert(CG_N * CG_N % CG_INV == 0, "whole entries per thread");
 __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict__ ent, double *__restrict__ mat)
@@ -166,20 +167,50 @@ __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict_
         A[q] = (qi[m] < n && qj[m] < n) ? G[q] : (qi[m] == qj[m] ? 1.0 : 0.0);
     }
     __syncthreads();
+    // Gauss-Jordan on 3x3 diagonal pivot blocks K = {k, k+1, k+2} (n is a
+    // multiple of 3; the matrix is SPD, so every pivot block is and no
+    // exchanges are needed): A_ij -= A_iK P^-1 A_Kj off K, then row K <-
+    // P^-1 A_K., column K <- -A_.K P^-1 and the pivot block <- P^-1
     bool bad = false;
-    for (int k = 0; k < n; ++k) {
-        const double piv = A[k * CG_N + k];
-        if (!(piv > 0.0)) { bad = true; break; }   // uniform: every thread reads the same pivot
-        const double ip = 1.0 / piv;
-        // A[i][j] -= A[i][k] A[k][j] / piv for i, j != k (row and column k are only read)
+    for (int k = 0; k < n; k += 3) {
+        double p[3][3];   // every thread reads the same pivot block
 #pragma unroll
-        for (int m = 0; m < CG_PER; ++m)
-            if (qi[m] != k && qj[m] != k) A[qi[m] * CG_N + qj[m]] -= A[qi[m] * CG_N + k] * A[k * CG_N + qj[m]] * ip;
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) p[a][b] = A[(k + a) * CG_N + k + b];
+        const double c00 = p[1][1] * p[2][2] - p[1][2] * p[2][1], c01 = p[1][2] * p[2][0] - p[1][0] * p[2][2],
+                     c02 = p[1][0] * p[2][1] - p[1][1] * p[2][0], c10 = p[0][2] * p[2][1] - p[0][1] * p[2][2],
+                     c11 = p[0][0] * p[2][2] - p[0][2] * p[2][0], c12 = p[0][1] * p[2][0] - p[0][0] * p[2][1],
+                     c20 = p[0][1] * p[1][2] - p[0][2] * p[1][1], c21 = p[0][2] * p[1][0] - p[0][0] * p[1][2],
+                     c22 = p[0][0] * p[1][1] - p[0][1] * p[1][0];
+        const double det = p[0][0] * c00 + p[0][1] * c01 + p[0][2] * c02;
+        if (!(p[0][0] > 0.0 && c22 > 0.0 && det > 0.0)) { bad = true; break; }   // uniform
+        const double id = 1.0 / det;
+        const double q[3][3] = {{c00 * id, c10 * id, c20 * id}, {c01 * id, c11 * id, c21 * id}, {c02 * id, c12 * id, c22 * id}};
+#pragma unroll
+        for (int m = 0; m < CG_PER; ++m) {
+            const int i = qi[m], j = qj[m];
+            if ((unsigned)(i - k) < 3u || (unsigned)(j - k) < 3u) continue;
+            const double b0 = A[k * CG_N + j], b1 = A[(k + 1) * CG_N + j], b2 = A[(k + 2) * CG_N + j];
+            const double w0 = q[0][0] * b0 + q[0][1] * b1 + q[0][2] * b2, w1 = q[1][0] * b0 + q[1][1] * b1 + q[1][2] * b2,
+                         w2 = q[2][0] * b0 + q[2][1] * b1 + q[2][2] * b2;
+            A[i * CG_N + j] -= A[i * CG_N + k] * w0 + A[i * CG_N + k + 1] * w1 + A[i * CG_N + k + 2] * w2;
+        }
         __syncthreads();
-        const int t = threadIdx.x;
+        const int t = threadIdx.x;   // column t of the pivot rows and row t of the pivot columns
         if (t < n) {
-            if (t != k) { A[k * CG_N + t] *= ip; A[t * CG_N + k] *= -ip; }
-            else A[k * CG_N + k] = ip;
+            if ((unsigned)(t - k) >= 3u) {
+                const double b0 = A[k * CG_N + t], b1 = A[(k + 1) * CG_N + t], b2 = A[(k + 2) * CG_N + t];
+                const double a0 = A[t * CG_N + k], a1 = A[t * CG_N + k + 1], a2 = A[t * CG_N + k + 2];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    A[(k + r) * CG_N + t] = q[r][0] * b0 + q[r][1] * b1 + q[r][2] * b2;
+                    A[t * CG_N + k + r] = -(a0 * q[0][r] + a1 * q[1][r] + a2 * q[2][r]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) A[t * CG_N + k + r] = q[t - k][r];
+            }
         }
         __syncthreads();
     }
