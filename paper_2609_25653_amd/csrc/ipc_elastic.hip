@@ -158,11 +158,24 @@ __global__ void k_bsr_assemble(int64_t n9, int T, const int *__restrict__ sc_ptr
     if (i >= n9) return;
     int k = (int)(i / 9), q = (int)(i % 9), qt = 3 * (q % 3) + q / 3;
     double acc = vc[i];
-    for (int j = sc_ptr[k]; j < sc_ptr[k + 1]; ++j) {
-        int code = sc_list[j], A = (code >> 2) & 3, B = code & 3;
-        bool tr = A > B;
-        int u = tr ? tet_ublk(B, A) : tet_ublk(A, B);
-        acc += telem[9 * ((size_t)u * T + (code >> 4)) + (tr ? qt : q)];
+    // eight contributions at a time: their codes, then their entries, are
+    // loaded together; the sum keeps the list order
+    const int je = sc_ptr[k + 1];
+    for (int j = sc_ptr[k]; j < je; j += 8) {
+        int code[8];
+        double v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) code[m] = j + m < je ? sc_list[j + m] : 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            int A = (code[m] >> 2) & 3, B = code[m] & 3;
+            bool tr = A > B;
+            int u = tr ? tet_ublk(B, A) : tet_ublk(A, B);
+            v[m] = j + m < je ? telem[9 * ((size_t)u * T + (code[m] >> 4)) + (tr ? qt : q)] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (j + m < je) acc += v[m];
     }
     val[i] = acc;
 }
