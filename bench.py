@@ -41,40 +41,29 @@ def product_traffic():
     return rec.get("bytes_per_launch") if rec.get("source_sha256") == sha else None
 
 
-def cpu_baseline(scene, pcg_per_newton):
-    """Oracle timing on a bounded sample: one assembly + solve of the first
-    Newton iteration of step 0, split into the assembly and the per-iteration
-    PCG cost, scaled to Newton iterations/s with the GPU's measured mean PCG
-    iterations per Newton iteration (CCD and line search are not counted, which
-    favours the CPU)."""
+def cpu_baseline(scene):
+    """The oracle on the host cores: one complete Newton iteration of step 0
+    of the same scene (step set-up with its broad phase and friction lag,
+    assembly, PCG to the scene's tolerance, CCD and line search), timed as a
+    whole.  The oracle runs its FEM element loop on OpenMP threads and
+    everything else on one thread."""
     import numpy as np
     import oracle as O
-    sc1 = dict(scene); sc1["max_pcg"] = np.asarray(1.0)
-    sc2 = dict(scene); sc2["max_pcg"] = np.asarray(6.0)
-    times = []
-    for sc in (sc1, sc2):
-        o = O.Oracle(sc)
-        o.begin_step(0)
-        y, _ = o.state()
-        g, _ = o.gradient(y)
-        t0 = time.perf_counter()
-        _, it = o.pcg(y, -g, 1e-300)
-        times.append((time.perf_counter() - t0, it))
-        del o
-    (t1, i1), (t2, i2) = times
-    t_iter = max((t2 - t1) / max(i2 - i1, 1), 0.0)
-    t_asm = max(t1 - i1 * t_iter, 0.0)
-    t_newton = t_asm + pcg_per_newton * t_iter
-    cores = len(os.sched_getaffinity(0))
+    sc = dict(scene)
+    sc["max_newton"] = np.asarray(1.0)   # stop after the first Newton iteration
+    o = O.Oracle(sc)
+    t0 = time.perf_counter()
+    rc, st = o.step()
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     try:
         model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
     except Exception:
         model = "unknown"
-    return {"value": 1.0 / t_newton, "unit": "Newton iters/s", "cores": int(os.environ.get("OMP_NUM_THREADS", cores)),
-            "kind": "oracle",
-            "sample": (f"step 0 of the 200k-tet scene: assembly {t_asm:.2f} s + {t_iter:.3f} s per PCG iteration "
-                       f"(timed with 1 and 6 iterations), scaled by {pcg_per_newton:.0f} PCG iterations per Newton "
-                       f"iteration; CPU {model}")}
+    return {"value": 1.0 / t, "unit": "Newton iters/s", "cores": threads, "kind": "oracle",
+            "sample": (f"one complete Newton iteration of step 0 of the 200k-tet scene ({t:.1f} s: set-up, assembly, "
+                       f"{st['pcg_iters_total']} PCG iterations, CCD, line search); OpenMP on {threads} threads over the "
+                       f"FEM element loop only, the rest single-threaded; CPU {model}")}
 
 
 def write_traffic(fetch_csv, write_csv):
@@ -127,8 +116,8 @@ def probe_spmv(sim):
 
 
 def bench_batched(args):
-    """256 squeeze scenes of 1k-40k tets stepped together, against the same
-    scenes stepped one at a time (a stratified sample, scaled to all)."""
+    """256 squeeze scenes of 1k-40k tets stepped together, against a sample of
+    the same scenes spread over the size range, each stepped alone."""
     import numpy as np
     import torch
     import ipcscenes
@@ -140,10 +129,12 @@ def bench_batched(args):
     sim = Sim(scenes)
     t_create = time.perf_counter() - t0
     print(f"# batched: {len(scenes)} scenes, {tets.sum()} tets, created in {t_create:.1f} s", file=sys.stderr, flush=True)
-    # a scene whose Newton loop ends without convergence (3) or without a
-    # decreasing line-search step (4) stays at its last iterate and continues
+    # A scene whose Newton loop ends without convergence (3) or without a
+    # decreasing line-search step (4) stays at its last iterate and goes on;
+    # such scene-steps are counted and named, and left out of the throughput.
     ok_codes = (3, 4)
-    not_ok = 0
+    status = {}
+    failed = []
     for _ in range(args.warmup):
         sim.step(allow_status=ok_codes)
     lanes, _ = sim.autotune(10)
@@ -152,16 +143,25 @@ def bench_batched(args):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         rc, st = sim.step(allow_status=ok_codes)
-        not_ok += sum(1 for s in st if s["status"] != 0)
+        for i, s in enumerate(st):
+            status[s["status"]] = status.get(s["status"], 0) + 1
+            if s["status"] != 0:
+                failed.append({"step": sim.step_index - 1, "scene": i, "status": s["status"], "tets": int(tets[i]),
+                               "E": float(scenes[i]["tet_E"][0]), "mu": float(scenes[i]["mu"]),
+                               "newton": s["newton_iters"], "alpha_min": s["alpha_min"]})
+                print(f"# step {sim.step_index - 1} scene {i}: status {s['status']} tets={tets[i]} newton={s['newton_iters']} "
+                      f"alpha_min={s['alpha_min']:.3g} pairs={s['n_pt_max'] + s['n_ee_max']}", file=sys.stderr, flush=True)
         newton.append(max(s["newton_iters"] for s in st))
         print(f"# step {sim.step_index}: rc={rc} max newton={newton[-1]} "
               f"pairs={sum(s['n_pt_max'] + s['n_ee_max'] for s in st)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    converged = status.get(0, 0)
     # one at a time: a sample spread over the size range, same steps
     order = np.argsort(tets)
     pick = order[np.linspace(0, len(scenes) - 1, min(args.single_sample, len(scenes))).round().astype(int)]
     t_single = 0.0
+    single_ok = single_all = 0
     for i in pick:
         s1 = Sim(scenes[i])
         for _ in range(args.warmup):
@@ -170,22 +170,28 @@ def bench_batched(args):
         torch.cuda.synchronize()
         a = time.perf_counter()
         for _ in range(args.steps):
-            s1.step(allow_status=ok_codes)
+            _, st1 = s1.step(allow_status=ok_codes)
+            single_ok += st1[0]["status"] == 0
+            single_all += 1
         torch.cuda.synchronize()
         t_single += time.perf_counter() - a
         del s1
-    t_single_all = t_single * len(scenes) / len(pick)
+    # converged scene-steps per second of the sample, as for the batch
+    single_rate = single_ok / t_single
     line = {
-        "metric": "batched scene-steps/s", "value": len(scenes) * args.steps / t, "unit": "scene-steps/s", "n_gpus": 1,
+        "metric": "batched scene-steps/s", "value": converged / t, "unit": "scene-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(scenes)} uneven squeeze scenes stepped together", "tets": int(tets.sum()),
                    "tets_min": int(tets.min()), "tets_max": int(tets.max()), "parallelism": "single GPU"},
-        "one_at_a_time": {"value": len(scenes) * args.steps / t_single_all, "unit": "scene-steps/s",
-                          "sample": f"{len(pick)} scenes spread over the size range, scaled by {len(scenes)}/{len(pick)}"},
-        "speedup_vs_one_at_a_time": t_single_all / t,
+        "value_counts": "converged scene-steps only",
+        "one_at_a_time": {"value": single_rate, "unit": "scene-steps/s",
+                          "sample": f"{len(pick)} scenes spread over the size range, each stepped alone over the same steps "
+                                    f"({single_ok} of {single_all} scene-steps converged)"},
+        "speedup_vs_one_at_a_time": (converged / t) / single_rate,
         "max_newton_per_step": newton, "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
-        "scene_steps_not_converged": not_ok,
+        "scene_steps_by_status": {str(k): v for k, v in sorted(status.items())},
+        "failed_scene_steps": failed,
     }
     print(json.dumps(line))
 
@@ -216,18 +222,26 @@ def bench_adjoint(args):
     with torch.no_grad():
         Et = E0 * torch.as_tensor(info["target_E_scale"], device="cuda")
         _, _, targets = rollout(sim, Et, mu0 * info["target_mu_scale"], y0, v0, first, K, every, observe=idx)
-    E = E0.clone().requires_grad_(True)
-    mu = torch.tensor([mu0], dtype=torch.float64, device="cuda", requires_grad=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, Y = rollout(sim, E, mu, y0, v0, first, K, every, observe=idx)
-    loss = ((Y - targets) ** 2).sum()
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t_bwd = time.perf_counter() - t0
+    def run(every):
+        E = E0.clone().requires_grad_(True)
+        mu = torch.tensor([mu0], dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, Y = rollout(sim, E, mu, y0, v0, first, K, every, observe=idx)
+        loss = ((Y - targets) ** 2).sum()
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        return t_fwd, time.perf_counter() - t0, loss, E, mu
+
+    # with checkpoints every `every` steps (the backward pass recomputes each
+    # segment), then with every state kept (no recompute): the backward pass
+    # is then the adjoint solves and VJPs alone
+    t_fwd, t_bwd, loss, E, mu = run(every)
+    t_fwd_keep, t_bwd_keep, loss_keep, E_keep, mu_keep = run(0)
+    same = bool(torch.equal(E.grad, E_keep.grad)) and bool(torch.equal(mu.grad, mu_keep.grad))
     line = {
         "metric": "adjoint/forward time", "value": t_bwd / t_fwd, "unit": "ratio", "n_gpus": 1, "steps": K, "warmup": first,
         "ms_per_step": 1e3 * t_fwd / K, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -235,7 +249,12 @@ def bench_adjoint(args):
         "config": {"workload": "squeeze steps 40-89, theta = per-tet E (20k) and mu, 64 tracked vertices",
                    "tets": int(len(sc["tets"])), "parallelism": "single GPU"},
         "forward_s": t_fwd, "backward_s": t_bwd, "backward_ms_per_step": 1e3 * t_bwd / K,
-        "note": "backward = recompute of each 10-step segment from its checkpoint + one adjoint solve per step",
+        "note": f"value: backward (recompute of each {every}-step segment from its checkpoint + one adjoint solve per "
+                f"step) over forward",
+        "without_recompute": {"forward_s": t_fwd_keep, "backward_s": t_bwd_keep, "ratio": t_bwd_keep / t_fwd_keep,
+                              "backward_ms_per_step": 1e3 * t_bwd_keep / K, "forward_ms_per_step": 1e3 * t_fwd_keep / K,
+                              "note": "every state kept by the forward pass; the backward pass is the adjoint solves alone"},
+        "gradients_equal_with_and_without_recompute": same,
         "loss": float(loss.detach()), "dL_dE_norm": float(E.grad.norm()), "dL_dmu": float(mu.grad[0]),
         "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
     }
@@ -459,9 +478,16 @@ def main():
     torch.cuda.synchronize()
     newton = pcg = 0
     pairs = []
+    status = {}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rc, st = sim.step(allow_status=(3,))
+    for k in range(args.steps):
+        if k == args.steps - 1:
+            # the last timed step runs with the library's kernel timing on:
+            # every product launch inside PCG stamps HIP events at its own
+            # start and end (eager launches for this step only)
+            sim._check(lib().ipc_profile(sim._h, 1))
+        rc, st = sim.step(allow_status=(3, 4))
+        status[st[0]["status"]] = status.get(st[0]["status"], 0) + 1
         newton += st[0]["newton_iters"]
         pcg += st[0]["pcg_iters_total"]
         pairs.append(st[0]["n_pt_max"] + st[0]["n_ee_max"])
@@ -470,17 +496,26 @@ def main():
               f"pairs={pairs[-1]} pair_local={nloc} cand_max={st[0]['n_cand_max']} alpha_min={st[0]['alpha_min']:.3g}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    # Dominant kernel: the block-CSR Hessian product inside PCG.  Its launch
-    # duration: 200 back-to-back launches on the matrix of the last timed
-    # Newton iteration between two HIP events on the library's stream (events
-    # around single launches add their own dispatch overhead to each one).
-    us, by = ctypes.c_double(), ctypes.c_double()
-    sim._check(lib().ipc_time_kernel(sim._h, K_SPMV, 200, ctypes.byref(us), ctypes.byref(by)))
-    achieved = by.value / (us.value * 1e-6) / 1e9
+    # Dominant kernel: the Hessian product inside PCG.  Launch duration: the
+    # dispatch-stamped HIP events of its launches in the last timed step.
+    tot, nl, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    sim._check(lib().ipc_kernel_time(sim._h, K_SPMV, ctypes.byref(tot), ctypes.byref(nl), ctypes.byref(by)))
+    sim._check(lib().ipc_profile(sim._h, 0))
+    us_pcg = 1e3 * tot.value / max(nl.value, 1)
+    bytes_launch = by.value / max(nl.value, 1)
+    # secondary figure: 200 back-to-back launches on the last matrix between
+    # two HIP events (the matrix then stays warm in the caches)
+    us, by2 = ctypes.c_double(), ctypes.c_double()
+    sim._check(lib().ipc_time_kernel(sim._h, K_SPMV, 200, ctypes.byref(us), ctypes.byref(by2)))
+    achieved = bytes_launch / (us_pcg * 1e-6) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": product_traffic(), "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)",
-            "bytes_per_launch": by.value,
-            "avg_us": us.value, "launches_timed": 200}
+            "bytes_per_launch": bytes_launch, "avg_us": us_pcg, "launches_timed": int(nl.value),
+            "timing": "HIP events stamped by each product launch inside PCG during the last timed step",
+            "back_to_back": {"avg_us": us.value, "achieved": by2.value / (us.value * 1e-6) / 1e9,
+                             "frac": by2.value / (us.value * 1e-6) / 1e9 / HBM_PEAK_GBS, "launches_timed": 200,
+                             "timing": "200 back-to-back launches on the last matrix between two HIP events"},
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE: bytes between L2 and the memory fabric (Infinity Cache or HBM)"}
     kt = {}
     line = {
         "metric": METRIC, "value": newton / t, "unit": "Newton iters/s", "n_gpus": 1, "steps": args.steps,
@@ -493,11 +528,12 @@ def main():
         "newton_per_step": newton / args.steps,
         "pcg_per_newton": pcg / max(newton, 1),
         "active_pairs": {"min": int(min(pairs)), "median": float(np.median(pairs)), "max": int(max(pairs))},
+        "steps_by_status": {str(k): v for k, v in sorted(status.items())},
         "roofline": roof,
         "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(scene, pcg / max(newton, 1))
+        line["cpu_baseline"] = cpu_baseline(scene)
     print(json.dumps(line))
 
 

@@ -1,4 +1,4 @@
-/* Dual-mesh mapping of PhyVisGen (arXiv 2609.25653, Sec. IV, Eq. (6)-(7)):
+/* Dual-mesh mapping of PhyVisGen (arXiv 2609.25653, Sec. III-D, Eq. (6)-(7)):
  * the fine render mesh of a deformable object is L levels of Loop
  * subdivision of its coarse simulation mesh.  Every level is linear in the
  * positions, so the whole subdivision is one sparse matrix

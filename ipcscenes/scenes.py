@@ -569,6 +569,7 @@ def tiny_scene(kind="tet", seed=0, **kw):
              edge (an active edge-edge mollifier)
     pad_box  a 2x1x1-cell pad squeezing a small affine box (springs, bodies, contact)
     arm_box  pad_box's squeeze on the joint-space arm (joint springs)
+    free_body one affine box (4 cm, 0.2 kg) with contact geometry and nothing to touch
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     b = _Builder()
@@ -593,6 +594,8 @@ def tiny_scene(kind="tet", seed=0, **kw):
                       [0.005, 0.005, 0.008], [-0.005, -0.005, 0.008]], np.float64) + [0.0, 0.0, 6e-4]
         b.add_fem(X, orient(X, np.array([[0, 1, 2, 3]], np.int32)), 1e5, 0.4, 1000.0)
         b.add_static(*ground_quad())
+    elif kind == "free_body":
+        b.add_body((0.3, 0.3, 0.5), (0.04, 0.04, 0.04), 0.2, contact=True)
     elif kind == "arm_box":
         b.add_body((0.3, 0.3, 0.01 + 5e-4), (0.02, 0.02, 0.02), 0.05, contact=True)
         drive, _, _ = _add_arm_gripper(b, rng, center_xy=(0.3, 0.3), z_mid=0.01 + 5e-4, inner_half_gap=0.0115,

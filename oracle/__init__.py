@@ -65,6 +65,7 @@ def lib():
         L.or_energy.argtypes = [P, D, D]
         L.or_gradient.argtypes = [P, D, D, D]
         L.or_hessian_matvec.argtypes = [P, D, ctypes.c_int, D, D]
+        L.or_hessian_matvec_abs.argtypes = [P, D, ctypes.c_int, ctypes.c_int, D, D, D]
         L.or_pairs.restype = ctypes.c_int
         L.or_pairs.argtypes = [P, D, I, ctypes.c_int, I, ctypes.c_int, I, I]
         L.or_ccd.restype = ctypes.c_double
@@ -227,11 +228,16 @@ class Oracle:
         lib().or_gradient(self._h, _d(y), _d(g), _d(ga))
         return g, ga
 
-    def hess_matvec(self, y, v, project=True):
+    def hess_matvec(self, y, v, project=True, with_abs=False, friction=True):
+        """H(y) v (friction=False: without the lagged friction terms);
+        with_abs=True also returns |P|^T |H| |P| |v| per entry (the scale of
+        the operands that form it)."""
         y = _f64(y); v = _f64(v)
         out = np.zeros(self.ndof)
-        lib().or_hessian_matvec(self._h, _d(y), int(project), _d(v), _d(out))
-        return out
+        scale = np.zeros(self.ndof) if with_abs else None
+        lib().or_hessian_matvec_abs(self._h, _d(y), int(project), int(friction), _d(v), _d(out),
+                                    _d(scale) if with_abs else None)
+        return (out, scale) if with_abs else out
 
     def pairs(self, y, cap=1 << 22):
         y = _f64(y)

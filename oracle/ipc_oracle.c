@@ -1317,27 +1317,41 @@ static double eval_ip(OScene *s, const double *y, const IVec *apt, const IVec *a
     return tot;
 }
 
-static void terms_matvec(const OScene *s, const Terms *T, const double *v, double *out)
+/* out = sum over terms of P^T H P v; outabs (nullable) receives the same sum
+ * with every factor replaced by its absolute value, |P|^T |H| |P| |v|: the
+ * size of the operands whose rounding forms each entry of out. */
+static void terms_matvec(const OScene *s, const Terms *T, const double *v, double *out, double *outabs)
 {
     memset(out, 0, sizeof(double) * s->ndof);
+    if (outabs) memset(outabs, 0, sizeof(double) * s->ndof);
     for (size_t k = 0; k < T->n; ++k) {
         const OTerm *t = T->t + k;
         int m = 3 * t->np;
-        double vl[12], yl[12];
+        double vl[12], yl[12], va[12], ya[12];
         for (int a = 0; a < t->np; ++a)
             for (int c = 0; c < 3; ++c) {
-                double acc = 0.0;
-                for (int q = 0; q < t->pt[a].n; ++q) acc += t->pt[a].w[q] * v[3 * (size_t)t->pt[a].node[q] + c];
+                double acc = 0.0, aa = 0.0;
+                for (int q = 0; q < t->pt[a].n; ++q) {
+                    double vq = v[3 * (size_t)t->pt[a].node[q] + c];
+                    acc += t->pt[a].w[q] * vq;
+                    aa += fabs(t->pt[a].w[q]) * fabs(vq);
+                }
                 vl[3 * a + c] = acc;
+                va[3 * a + c] = aa;
             }
         for (int i = 0; i < m; ++i) {
-            double acc = 0.0;
-            for (int j = 0; j < m; ++j) acc += t->H[i * m + j] * vl[j];
+            double acc = 0.0, aa = 0.0;
+            for (int j = 0; j < m; ++j) { acc += t->H[i * m + j] * vl[j]; aa += fabs(t->H[i * m + j]) * va[j]; }
             yl[i] = acc;
+            ya[i] = aa;
         }
         for (int a = 0; a < t->np; ++a)
             for (int q = 0; q < t->pt[a].n; ++q)
-                for (int c = 0; c < 3; ++c) out[3 * (size_t)t->pt[a].node[q] + c] += t->pt[a].w[q] * yl[3 * a + c];
+                for (int c = 0; c < 3; ++c) {
+                    size_t o = 3 * (size_t)t->pt[a].node[q] + c;
+                    out[o] += t->pt[a].w[q] * yl[3 * a + c];
+                    if (outabs) outabs[o] += fabs(t->pt[a].w[q]) * ya[3 * a + c];
+                }
     }
 }
 
@@ -1447,12 +1461,18 @@ void or_gradient(OScene *s, const double *y, double *g, double *gabs)
 
 void or_hessian_matvec(OScene *s, const double *y, int project, const double *v, double *out)
 {
+    or_hessian_matvec_abs(s, y, project, 1, v, out, NULL);
+}
+
+void or_hessian_matvec_abs(OScene *s, const double *y, int project, int with_friction, const double *v, double *out,
+                           double *outabs)
+{
     IVec apt = {0}, aee = {0};
     pairs_at(s, y, &apt, &aee);
     Terms T = {0};
     double *g = xmalloc(sizeof(double) * s->ndof);
-    eval_ip(s, y, &apt, &aee, NULL, g, NULL, &T, project, 1);
-    terms_matvec(s, &T, v, out);
+    eval_ip(s, y, &apt, &aee, NULL, g, NULL, &T, project, with_friction);
+    terms_matvec(s, &T, v, out, outabs);
     free(g); free(T.t); free(apt.v); free(aee.v);
 }
 
@@ -1516,7 +1536,7 @@ static int pcg_terms(OScene *s, const Terms *T, const double *b, double *x, doub
         double rz = 0.0;
         for (int i = 0; i < n; ++i) { p[i] = z[i]; rz += r[i] * z[i]; }
         for (it = 1; it <= maxit; ++it) {
-            terms_matvec(s, T, p, Ap);
+            terms_matvec(s, T, p, Ap, NULL);
             double pAp = 0.0;
             for (int i = 0; i < n; ++i) pAp += p[i] * Ap[i];
             if (!(pAp > 0.0)) { if (indef) *indef = 1; break; }

@@ -65,6 +65,12 @@ double  or_energy(OScene *s, const double *y, double *terms);
 void    or_gradient(OScene *s, const double *y, double *g, double *gabs);
 /* out = H(y) v, with PSD projection when project != 0. */
 void    or_hessian_matvec(OScene *s, const double *y, int project, const double *v, double *out);
+/* The same product, with or without the lagged friction terms; outabs
+ * (nullable) receives, per entry, the sum over all terms of |P|^T |H| |P| |v|
+ * (absolute values of every factor), the scale of the operands whose sums
+ * and cancellations form that entry. */
+void    or_hessian_matvec_abs(OScene *s, const double *y, int project, int with_friction, const double *v, double *out,
+                              double *outabs);
 /* Active pair set at y as vertex tuples (PT: v,t0,t1,t2 ; EE: a0,a1,b0,b1),
  * canonical order.  Returns 0, or -1 when a capacity is too small. */
 int     or_pairs(OScene *s, const double *y, int *pt, int cap_pt, int *ee, int cap_ee,

@@ -1,4 +1,4 @@
-"""Oracle of the dual-mesh mapping (Sec. IV, Eq. (6)-(7)): L levels of Loop
+"""Oracle of the dual-mesh mapping (Sec. III-D, Eq. (6)-(7)): L levels of Loop
 subdivision of a coarse triangle mesh, computed directly on vertex positions,
 one level at a time, in plain Python loops.  Test infrastructure only: it is
 used by the tests and by bench.py's CPU baseline, never by the library.

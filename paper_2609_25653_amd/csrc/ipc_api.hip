@@ -1036,6 +1036,22 @@ void prof_begin(ipc_ctx *c, int k)
     c->timers[k].ev.push_back(e);
 }
 
+void prof_dispatch_events(ipc_ctx *c, int k, hipEvent_t *start, hipEvent_t *stop, double bytes)
+{
+    *start = *stop = nullptr;
+    if (!c->prof) return;
+    auto &T = c->timers[k];
+    // read the pending pairs first: the new pair is stamped only once its
+    // launch has been issued
+    if (T.ev.size() >= 2048) prof_flush(c, k);
+    *start = prof_event(c, k);
+    *stop = prof_event(c, k);
+    T.ev.push_back(*start);
+    T.ev.push_back(*stop);
+    T.launches += 1;
+    T.bytes += bytes;
+}
+
 void prof_end(ipc_ctx *c, int k, double bytes)
 {
     if (!c->prof) return;

@@ -1615,13 +1615,16 @@ void build_dyn_blocks(ipc_ctx *c)
 // ---------------------------------------------------------------------------
 __device__ double accd(int kind, const d3 *x0, const d3 *p, double s)
 {
+    // every operation in its written order, unfused: the bound of each
+    // candidate is the same double on any implementation of this recipe
+#pragma clang fp contract(off)
     d3 pm = {0.25 * (p[0].x + p[1].x + p[2].x + p[3].x), 0.25 * (p[0].y + p[1].y + p[2].y + p[3].y),
              0.25 * (p[0].z + p[1].z + p[2].z + p[3].z)};
     d3 dp[4];
     double nrm[4];
     for (int k = 0; k < 4; ++k) {
         dp[k] = {p[k].x - pm.x, p[k].y - pm.y, p[k].z - pm.z};
-        nrm[k] = sqrt(dt(dp[k], dp[k]));
+        nrm[k] = sqrt(xdot(dp[k], dp[k]));
     }
     double lp = kind == 0 ? nrm[0] + fmax(nrm[1], fmax(nrm[2], nrm[3])) : fmax(nrm[0], nrm[1]) + fmax(nrm[2], nrm[3]);
     if (lp == 0.0) return 1.0;

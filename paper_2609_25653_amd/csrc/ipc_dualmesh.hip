@@ -1,4 +1,4 @@
-// Dual-mesh mapping (Sec. IV, Eq. (6)-(7)): W = S^(L) ... S^(1), the L-level
+// Dual-mesh mapping (Sec. III-D, Eq. (6)-(7)): W = S^(L) ... S^(1), the L-level
 // Loop subdivision of the coarse simulation mesh as one sparse matrix, built
 // on the host at creation; X^f = W X^c for many frames per launch.
 //

@@ -1,5 +1,5 @@
 // Closed-form PSD projections of the Hessians of two isotropic energies of
-// the incremental potential (Eq. (1)), both over vec of a 3x3 matrix M and
+// the incremental potential (Eq. (3)), both over vec of a 3x3 matrix M and
 // both built on a signed SVD M = U diag(s) V^T (U, V proper rotations, s3 < 0
 // for an inverted M).  For an energy Psi(s) of the singular values alone the
 // nine eigenpairs are known (the isotropic-energy eigensystems of Smith,

@@ -326,6 +326,10 @@ RedSrc src(const double *v, const int *seg, int off, int base);
 int *seg_ptr(ipc_ctx *c, int region);
 void prof_begin(ipc_ctx *c, int k);
 void prof_end(ipc_ctx *c, int k, double bytes);
+// While timing is enabled: two events for a launch that stamps them itself at
+// its start and end (hipExtLaunchKernelGGL), counted as one launch of kernel
+// k with the given algorithmic bytes; both stay null when timing is off.
+void prof_dispatch_events(ipc_ctx *c, int k, hipEvent_t *start, hipEvent_t *stop, double bytes);
 __global__ void k_fill_int_api(int n, int *p, int v);
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part);
 void autotune_spmv(ipc_ctx *c, int reps, double *us);

@@ -4,6 +4,8 @@
 // blocks that fit its pattern, plus pair-local contact blocks for the rest),
 // the block-Jacobi preconditioner (3x3 per FEM vertex, 12x12 per body) and a
 // PCG that runs all scenes at once with per-scene scalars and flags.
+#include <hip/hip_ext.h>
+
 #include <chrono>
 #include <cmath>
 
@@ -234,14 +236,22 @@ double spmv_bytes(const ipc_ctx *c)
     return 76.0 * ((double)c->nnzb + (double)c->n_dyn) + 8.0 * (c->N + 1) + 48.0 * (c->NFEM + 4.0 * c->NB);
 }
 
-static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const int *active, double *part)
+// ev0 / ev1 (nullable): HIP events stamped by the dispatch itself at the
+// kernel's start and end, so that no marker packet enters the interval
+static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const int *active, double *part,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     Dev &D = c->d;
     int ntiles = (c->N + TILE - 1) / TILE;
     dim3 grid(ntiles + c->long_cap), blk(64 * L);   // extra workgroups beyond the long-row count exit at once
     double *pl = part ? D.part_long.p : nullptr;
-#define IPC_SPMV(LL) hipLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, c->N, ntiles, D.long_count.p, D.long_rows.p, D.row_ptr.p, D.col.p, \
-                                        D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, v, D.node_scene.p, active, out, part, pl)
+    // plain launches otherwise (they are the ones captured into graphs)
+#define IPC_SPMV_ARGS c->N, ntiles, D.long_count.p, D.long_rows.p, D.row_ptr.p, D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, \
+                      v, D.node_scene.p, active, out, part, pl
+#define IPC_SPMV(LL) do { \
+        if (ev0) hipExtLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, ev0, ev1, 0, IPC_SPMV_ARGS); \
+        else hipLaunchKernelGGL(k_spmv<LL>, grid, blk, 0, c->stream, IPC_SPMV_ARGS); \
+    } while (0)
     switch (L) {
     case 1: IPC_SPMV(1); break;
     case 2: IPC_SPMV(2); break;
@@ -250,13 +260,14 @@ static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const i
     default: IPC_SPMV(16); break;
     }
 #undef IPC_SPMV
+#undef IPC_SPMV_ARGS
 }
 
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part)
 {
-    prof_begin(c, IPC_K_SPMV);
-    spmv_launch(c, c->spmv_lanes, v, out, active, part);
-    prof_end(c, IPC_K_SPMV, spmv_bytes(c));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    prof_dispatch_events(c, IPC_K_SPMV, &e0, &e1, spmv_bytes(c));
+    spmv_launch(c, c->spmv_lanes, v, out, active, part, e0, e1);
 }
 
 // Time every lane count on the current matrix (reps back-to-back launches

@@ -1,7 +1,7 @@
 """ctypes binding of the dual-mesh mapping in include/ipc_dualmesh.h
 (argument marshalling only): the fine render mesh of a deformable object as
 L levels of Loop subdivision of its coarse simulation mesh, W X^c per frame
-(Sec. IV, Eq. (6)-(7)).  W is built by the library on the host; the product
+(Sec. III-D, Eq. (6)-(7)).  W is built by the library on the host; the product
 runs in the library's HIP kernel."""
 import ctypes
 

@@ -9,7 +9,9 @@ checkpoint, then calls the library's one-step adjoint for each step of the
 segment, newest first, adding the observed DOFs' upstream gradients as it
 passes their step, accumulating dL/dE and dL/dmu and carrying the state
 adjoints (ybar, vbar) back to the start.  Memory: one (y, ydot) pair per
-checkpoint, the states of one segment and the observed trajectory.
+checkpoint, the states of one segment and the observed trajectory.  With
+``checkpoint_every=0`` the forward pass keeps every state instead and the
+backward pass recomputes nothing (memory: one (y, ydot) pair per step).
 """
 import torch
 
@@ -31,11 +33,16 @@ class IPCRollout(torch.autograd.Function):
         y, v = y0.detach().contiguous().clone(), ydot0.detach().contiguous().clone()
         sim.set_state(y, v)
         ckpts, obs = [], []
+        keep_all = checkpoint_every == 0
+        if keep_all:
+            ckpts.append((0, [(y, v)]))
         for k in range(n_steps):
-            if k % checkpoint_every == 0:
+            if not keep_all and k % checkpoint_every == 0:
                 ckpts.append((k, y, v))
             sim.step(first_step + k)
             y, v = sim.state()
+            if keep_all:
+                ckpts[0][1].append((y, v))
             if observe is not None:
                 obs.append(y[observe])
         ctx.sim, ctx.first, ctx.n, ctx.every, ctx.eta, ctx.observe = sim, first_step, n_steps, checkpoint_every, eta, observe
@@ -54,13 +61,17 @@ class IPCRollout(torch.autograd.Function):
         vbar = zeros() if vbar is None else vbar.contiguous().clone()
         Ebar = torch.zeros(sim.n_tets, dtype=torch.float64, device=sim.device)
         mubar = torch.zeros(sim.n_scenes, dtype=torch.float64, device=sim.device)
-        for c0, y, v in reversed(ctx.ckpts):
-            c1 = min(c0 + ctx.every, ctx.n)
-            states = [(y, v)]
-            sim.set_state(y, v)
-            for k in range(c0, c1):
-                sim.step(ctx.first + k)
-                states.append(sim.state())
+        segments = ctx.ckpts if ctx.every == 0 else [(c0, (y, v)) for c0, y, v in ctx.ckpts]
+        for c0, first_state in reversed(segments):
+            if ctx.every == 0:   # every state kept by the forward pass
+                states, c1 = first_state, ctx.n
+            else:
+                c1 = min(c0 + ctx.every, ctx.n)
+                states = [first_state]
+                sim.set_state(*first_state)
+                for k in range(c0, c1):
+                    sim.step(ctx.first + k)
+                    states.append(sim.state())
             for k in range(c1 - 1, c0 - 1, -1):
                 if ctx.observe is not None and gobs is not None and gobs.numel():
                     ybar = ybar.index_add(0, ctx.observe, gobs[k])
@@ -73,7 +84,8 @@ class IPCRollout(torch.autograd.Function):
 
 def rollout(sim, E, mu, y0, ydot0, first_step, n_steps, checkpoint_every=10, eta=1e-12, observe=None):
     """Differentiable rollout; returns (y_K, ydot_K), or (y_K, ydot_K, Y_obs)
-    with Y_obs[k] = y_{k+1}[observe] when ``observe`` is given.  See ``IPCRollout``."""
+    with Y_obs[k] = y_{k+1}[observe] when ``observe`` is given.  checkpoint_every
+    = 0 keeps every state (no recompute in the backward pass).  See ``IPCRollout``."""
     mu = torch.as_tensor(mu, dtype=torch.float64, device=sim.device).reshape(-1)
     if mu.numel() == 1 and sim.n_scenes > 1:
         mu = mu.expand(sim.n_scenes).contiguous()

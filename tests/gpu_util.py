@@ -21,10 +21,21 @@ def energy_tol(terms):
 
 
 def assert_grad_close(g_gpu, g_or, gabs, rel=1e-10):
+    """Per entry: |g_gpu - g_or| <= rel * gabs, gabs the oracle's sum of the
+    absolute values of the operands that form the entry (no global floor)."""
     err = np.abs(g_gpu - g_or)
-    tol = rel * gabs + 1e-14 * (np.abs(gabs).max() + 1e-300)
+    tol = rel * gabs + 1e-300
     bad = np.nonzero(err > tol)[0]
-    assert len(bad) == 0, f"{len(bad)} gradient entries off; worst {np.max(err / (tol + 1e-300)):.3g}x tol at {bad[:5]}"
+    assert len(bad) == 0, f"{len(bad)} gradient entries off; worst {np.max(err / tol):.3g}x tol at {bad[:5]}"
+
+
+def assert_hv_close(hv_gpu, hv_or, scale, rel=1e-9, what=""):
+    """Per entry: |Hv_gpu - Hv_or| <= rel * (|P|^T |H| |P| |v|)_i, the
+    oracle's absolute product scale of that entry."""
+    err = np.abs(hv_gpu - hv_or)
+    tol = rel * scale + 1e-300
+    bad = np.nonzero(err > tol)[0]
+    assert len(bad) == 0, f"{what}: {len(bad)} Hessian-product entries off; worst {np.max(err / tol):.3g}x tol at {bad[:5]}"
 
 
 def to_np(t):

@@ -1,4 +1,4 @@
-"""Dual-mesh mapping (Sec. IV, Eq. (6)-(7)): the library's host-built W and
+"""Dual-mesh mapping (Sec. III-D, Eq. (6)-(7)): the library's host-built W and
 fine triangles against the oracle, which subdivides positions level by
 level.  Host work only (no GPU): W X^c is formed here with numpy from the
 library's W, and compared with the oracle's fine positions."""

@@ -1,4 +1,4 @@
-"""Dual-mesh mapping on the GPU (Sec. IV, Eq. (6)-(7)): X^f = W X^c for many
+"""Dual-mesh mapping on the GPU (Sec. III-D, Eq. (6)-(7)): X^f = W X^c for many
 frames in one launch against the oracle's level-by-level Loop subdivision of
 each frame (needs a GPU).  Bar: every coordinate within 1e-13 of the
 coordinates' magnitude (a handful of weighted sums in FP64 in another

@@ -1,16 +1,18 @@
 """Parity of the HIP library with the oracle at identical inputs (needs a GPU).
 
-Bars: contact-pair sets bit-exact; energies within 1e-10 of the sum of the
-absolute terms; gradients within 1e-10 of the per-entry sum of absolute
-contributions; Hessian products within 1e-9 relative; trajectories within
-1e-6 of the scene's bounding-box diagonal at every step.
+Bars: contact-pair sets and CCD step bounds bit-exact; energies within 1e-10
+of the sum of the absolute terms; gradients within 1e-10 of the per-entry sum
+of absolute contributions; Hessian products within 1e-9 of the per-entry
+absolute product scale |P|^T |H| |P| |v|, also for the friction blocks alone
+(the product with friction minus the one without); trajectories within 1e-6
+of the scene's bounding-box diagonal at every step.
 """
 import numpy as np
 import pytest
 
 import ipcscenes as S
 import oracle as O
-from gpu_util import assert_grad_close, energy_tol, oracle_states, to_np
+from gpu_util import assert_grad_close, assert_hv_close, energy_tol, oracle_states, to_np
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
@@ -62,9 +64,18 @@ def test_energy_gradient_hessian(name, states):
             assert rc == 0
             assert abs(to_np(E)[0] - E_or) <= energy_tol(terms), (k, to_np(E)[0], E_or)
             assert_grad_close(to_np(g), g_or, gabs)
-            Hv_or = o.hess_matvec(yq, vv, project)
-            err = np.linalg.norm(to_np(Hv) - Hv_or)
-            assert err <= 1e-9 * np.linalg.norm(Hv_or), (name, k, project, err / np.linalg.norm(Hv_or))
+            Hv_or, sc_or = o.hess_matvec(yq, vv, project, with_abs=True)
+            assert_hv_close(to_np(Hv), Hv_or, sc_or, what=f"{name} step {k} project={project}")
+            # the friction blocks alone: the product without friction, subtracted
+            _, _, Hv0, rc = sim.energy_grad_hess(yq, vv, project=project, friction=False, energy=False, grad=False)
+            assert rc == 0
+            Hv0_or, sc0_or = o.hess_matvec(yq, vv, project, with_abs=True, friction=False)
+            d_gpu, d_or = to_np(Hv) - to_np(Hv0), Hv_or - Hv0_or
+            # scale: the friction terms' own absolute product, plus the rounding
+            # of the two full products the difference cancels (each a sum of
+            # tens of terms: a few 1e-16 of its absolute scale)
+            sc_fr = (sc_or - sc0_or) + 1e-5 * sc_or
+            assert_hv_close(d_gpu, d_or, sc_fr, what=f"{name} step {k} friction blocks project={project}")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -91,7 +102,9 @@ def test_ccd(name, states):
             p = scale * rng.standard_normal(len(y))
             a = to_np(sim.ccd(y, p))[0]
             a_or = o.ccd(y, p)
-            assert a == pytest.approx(a_or, rel=1e-12, abs=1e-15), (name, k, scale, a, a_or)
+            # both sides evaluate every candidate's additive CCD with the same
+            # operations in the same order, unfused: the bound is bit-exact
+            assert a == a_or, (name, k, scale, a, a_or)
 
 
 @pytest.mark.parametrize("coarse", [False, True])

@@ -176,19 +176,61 @@ def test_momentum_conserved_without_gravity():
         assert np.abs(p - p0).max() <= 1e-6 * np.abs(m[:, None] * sc["V"]).sum()
 
 
-def test_affine_body_free_flight():
-    sc = S.tiny_scene("pad_box", n_steps=3, h=0.01)
-    # only the box: no FEM, no springs; give it a spin-free linear velocity
+def test_kappa_auto_closed_form():
+    """Automatic barrier stiffness: 10 times the mean lumped FEM vertex mass
+    times |g| h^2 / dhat.  The lumped masses sum to the mesh's mass, so the
+    mean is rho * (sum of tet volumes) / nv, with volumes from the rest
+    positions; for the 625-tet block (0.125 kg over 216 vertices, h = 0.01,
+    dhat = 1e-3) that is about 5.7e-3."""
+    sc = S.block_drop(n_steps=2)
     o = O.Oracle(sc)
-    y, v = o.state()
-    nv = len(sc["X"])
-    b0 = 3 * nv
-    v[:] = 0
-    v[b0:b0 + 3] = [0.1, -0.05, 0.2]
-    o.set_state(y, v)
-    o.begin_step()
+    X, T = sc["X"], sc["tets"]
+    D = np.stack([X[T[:, 1]] - X[T[:, 0]], X[T[:, 2]] - X[T[:, 0]], X[T[:, 3]] - X[T[:, 0]]], -1)
+    vol = np.linalg.det(D) / 6.0
+    mass = float(np.sum(sc["tet_rho"] * vol))
+    want = 10.0 * mass / len(X) * np.linalg.norm(sc["g"]) * float(sc["h"]) ** 2 / float(sc["dhat"])
+    assert mass == pytest.approx(0.125, rel=1e-2)
+    assert o.kappa == pytest.approx(want, rel=1e-12)
+    assert o.kappa == pytest.approx(5.68e-3, rel=1e-2)
+
+
+def _rotation(a, u):
+    u = np.asarray(u, np.float64) / np.linalg.norm(u)
+    K = np.array([[0.0, -u[2], u[1]], [u[2], 0.0, -u[0]], [-u[1], u[0], 0.0]])
+    return np.eye(3) + np.sin(a) * K + (1.0 - np.cos(a)) * (K @ K)
+
+
+@pytest.mark.parametrize("gravity", [False, True])
+def test_affine_body_free_flight(gravity):
+    """A free affine body whose frame is a fixed rotation R (A = R, dA/dt = 0)
+    and whose translation moves with v0: the orthogonality energy and its
+    gradient vanish at any rotation, so implicit Euler reduces to
+    p_{n+1} = p_n + h v_n + h^2 g, i.e. p_n = p_0 + n h v0 + h^2 g n(n+1)/2
+    and v_n = v0 + n h g, while A and its rate stay exactly as they were."""
+    n = 6
+    sc = S.tiny_scene("free_body", n_steps=n, h=0.01)
+    if not gravity:
+        sc["g"] = np.zeros(3)
+    R = _rotation(0.7, [1.0, -2.0, 0.5])
+    p0 = sc["body_q"][0, :3].copy()
+    v0 = np.array([0.1, -0.05, 0.2])
+    sc["body_q"][0, 3:] = R.T.ravel()          # columns of A, one after another
+    sc["body_qdot"][0, :3] = v0
+    o = O.Oracle(sc)
+    g, h = sc["g"], float(sc["h"])
+    for k in range(1, n + 1):
+        rc, st = o.step()
+        assert rc == 0
+        y, v = o.state()
+        p_want = p0 + k * h * v0 + h * h * g * k * (k + 1) / 2.0
+        assert np.abs(y[:3] - p_want).max() <= 1e-12 * (np.abs(p0).max() + 1.0)
+        assert np.abs(v[:3] - (v0 + k * h * g)).max() <= 1e-9 * (np.abs(v0).max() + 1.0)
+        assert np.abs(y[3:] - R.T.ravel()).max() <= 1e-13
+        assert np.abs(v[3:]).max() <= 1e-10
+        if not gravity:
+            assert np.abs(v[:3] - v0).max() <= 1e-9 * np.abs(v0).max()
     E, terms = o.energy(y)
-    assert terms[2] == pytest.approx(0.0, abs=1e-20)   # orthogonality energy zero at rotation
+    assert terms[2] == pytest.approx(0.0, abs=1e-20)   # orthogonality energy zero at a rotation
 
 
 def test_resting_block_contact_force():
