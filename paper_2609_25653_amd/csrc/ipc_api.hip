@@ -274,8 +274,8 @@ void eval_energy(ipc_ctx *c, const double *y, bool from_candidates)
     launch_fem(c, 0, y, nullptr, false, D.part_tet.p, D.h2s.p);
     launch_body(c, 0, y, nullptr, false, D.body_part.p, D.h2s.p);
     launch_spring(c, 0, y, nullptr, D.sp_part.p, D.h2s.p);
-    launch_barrier(c, 0, from_candidates, D.xw.p, nullptr, false);
-    if (c->fr_on) launch_friction(c, 0, D.xw.p, nullptr);
+    launch_barrier(c, 0, from_candidates, D.xw.p, false);
+    if (c->fr_on) launch_friction(c, 0, D.xw.p);
     int64_t npt = from_candidates ? c->n_cand_pt : c->n_pt, nee = from_candidates ? c->n_cand_ee : c->n_ee;
     // the per-pair values are pre-summed in chunks of 64, so that a scene's
     // reduction reads its chunk sums and at most 126 single entries
@@ -319,13 +319,18 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     launch_world(c, y, D.xw.p);
     hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
     // inertia writes g; the FEM gathers then write the matrix values (constant
-    // part + tets) and add the tets' gradients; every later term adds atomically
+    // part + tets) and add the tets' gradients; the bodies add their own
+    // nodes; springs, barrier and friction pairs add through sorted run sums
+    // (one writer per destination, in an order fixed by the inputs), so the
+    // gradient and the matrix are the same bit for bit on every run
     launch_node_inertia(c, y, g, D.part_node.p);
     launch_fem(c, hess ? 2 : 1, y, g, project, D.part_tet.p, D.h2s.p);
     launch_body(c, hess ? 2 : 1, y, g, project, D.body_part.p, D.h2s.p);
     launch_spring(c, 1, y, g, D.sp_part.p, D.h2s.p);
-    launch_barrier(c, hess ? 2 : 1, false, D.xw.p, g, project);
-    if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p, g);
+    contact_grad_begin(c);
+    launch_barrier(c, hess ? 2 : 1, false, D.xw.p, project);
+    if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p);
+    contact_grad_end(c, g);
     if (hess) build_dyn_blocks(c);
 }
 

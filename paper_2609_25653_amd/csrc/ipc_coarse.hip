@@ -107,11 +107,14 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
 }
 
 // The domains' blocks of P^T A P: one workgroup per group (32 rows of 8
-// lanes) sums, in LDS, the 3x3 blocks of its nodes' rows (block-CSR and
-// pair-local) whose column node lies in a group of the same domain, then
-// stores the group's 3 rows of its domain's block (all CG_N columns; a
-// group owns its rows, so no other workgroup writes them).
-constexpr int CG_ASM = 256, CG_LPR = CG_ASM / CG_AGG;   // lanes per row
+// lanes) sums the 3x3 blocks of its nodes' rows (block-CSR and pair-local)
+// whose column node lies in a group of the same domain, then stores the
+// group's 3 rows of its domain's block (all CG_N columns; a group owns its
+// rows, so no other workgroup writes them).  The sums come out the same on
+// every run: each row adds into a strip of its own in LDS, its 8 lanes take
+// turns in lane order (blocks loaded ahead into registers, CG_PRE at a time),
+// and the 32 strips are then summed in row order.
+constexpr int CG_ASM = 256, CG_LPR = CG_ASM / CG_AGG, CG_PRE = 4;   // lanes per row; blocks per lane per round
 __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restrict__ grp, const int *__restrict__ ent,
                                                             const int *__restrict__ nodes, const int *__restrict__ node_da,
                                                             const int *__restrict__ row_ptr, const int *__restrict__ col,
@@ -119,28 +122,62 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
                                                             const int *__restrict__ dcol, const double *__restrict__ dval,
                                                             double *__restrict__ mat)
 {
-    __shared__ double S[3 * CG_N];
+    __shared__ double P[CG_AGG][3 * CG_N];   // 72 KB: one strip per row
     const int g = grp[blockIdx.x], d = g / CG_DOM, a = g % CG_DOM;
-    for (int q = threadIdx.x; q < 3 * CG_N; q += CG_ASM) S[q] = 0.0;
+    for (int q = threadIdx.x; q < CG_AGG * 3 * CG_N; q += CG_ASM) (&P[0][0])[q] = 0.0;
     __syncthreads();
-    const int e = ent[d] + a * CG_AGG + (int)threadIdx.x / CG_LPR, sub = threadIdx.x % CG_LPR;
-    if (e < ent[d + 1]) {
-        const int i = nodes[e];
-        auto add = [&](int j, const double *__restrict__ B) {
+    const int row = (int)threadIdx.x / CG_LPR, sub = threadIdx.x % CG_LPR, e = ent[d] + a * CG_AGG + row;
+    const bool live = e < ent[d + 1];
+    const int i = live ? nodes[e] : 0;
+    const int n0 = live ? row_ptr[i + 1] - row_ptr[i] : 0, n1 = live ? dptr[i + 1] - dptr[i] : 0;
+    // the lane's blocks: k = sub, sub + 8, ... over the row's static then
+    // pair-local blocks; every lane runs the same number of rounds
+    int mine = n0 + n1 > sub ? (n0 + n1 - sub + CG_LPR - 1) / CG_LPR : 0;
+    int most = mine;
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o, 64));
+    __shared__ int wmost[CG_ASM / 64];
+    if ((threadIdx.x & 63) == 0) wmost[threadIdx.x / 64] = most;
+    __syncthreads();
+    most = 0;
+    for (int w = 0; w < CG_ASM / 64; ++w) most = max(most, wmost[w]);
+    for (int r0 = 0; r0 < most; r0 += CG_PRE) {
+        double B[CG_PRE][9];
+        int dst[CG_PRE];
+#pragma unroll
+        for (int u = 0; u < CG_PRE; ++u) {
+            dst[u] = -1;
+            const int kk = sub + CG_LPR * (r0 + u);
+            if (r0 + u >= mine) continue;
+            const bool dyn = kk >= n0;
+            const int j = dyn ? dcol[dptr[i] + kk - n0] : col[row_ptr[i] + kk];
+            const double *src = dyn ? dval + 9 * (size_t)(dptr[i] + kk - n0) : val + 9 * (size_t)(row_ptr[i] + kk);
             const int tj = node_da[j];
-            if (tj < 0 || tj / CG_DOM != d) return;
-            double *o = S + 3 * (tj % CG_DOM);
+            if (tj < 0 || tj / CG_DOM != d) continue;
+            dst[u] = 3 * (tj % CG_DOM);
 #pragma unroll
-            for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 9; ++q) B[u][q] = src[q];
+        }
+        for (int turn = 0; turn < CG_LPR; ++turn) {
+            if (sub == turn) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) atomicAdd(&o[r * CG_N + k], B[3 * r + k]);
-        };
-        for (int k = row_ptr[i] + sub; k < row_ptr[i + 1]; k += CG_LPR) add(col[k], val + 9 * (size_t)k);
-        for (int k = dptr[i] + sub; k < dptr[i + 1]; k += CG_LPR) add(dcol[k], dval + 9 * (size_t)k);
+                for (int u = 0; u < CG_PRE; ++u) {
+                    if (dst[u] < 0) continue;
+                    double *o = &P[row][dst[u]];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) o[r * CG_N + k] += B[u][3 * r + k];
+                }
+            }
+            __syncthreads();
+        }
     }
-    __syncthreads();
     double *G = mat + (size_t)d * CG_N * CG_N + (size_t)(3 * a) * CG_N;   // rows 3a .. 3a + 2, contiguous
-    for (int q = threadIdx.x; q < 3 * CG_N; q += CG_ASM) G[q] = S[q];
+    for (int q = threadIdx.x; q < 3 * CG_N; q += CG_ASM) {
+        double t = 0.0;
+        for (int r = 0; r < CG_AGG; ++r) t += P[r][q];
+        G[q] = t;
+    }
 }
 
 // One workgroup per domain: the inverse of its n x n block (n = 3 x groups)

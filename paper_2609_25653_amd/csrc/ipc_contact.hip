@@ -17,6 +17,7 @@
 
 #include "ipc_device.h"
 #include "ipc_internal.h"
+#include "ipc_runsum.h"
 #include "ipc_kernels.h"
 
 namespace ipc {
@@ -676,16 +677,6 @@ __device__ __forceinline__ Map cv_map(int cv, const int *cv_node, const int *cv_
     m.xb = (b >= 0) ? ld3(cv_x, cv) : mk(0, 0, 0);
     return m;
 }
-__device__ __forceinline__ void scatter_cv(const Map &m, double *out, d3 f)
-{
-    if (m.node >= 0) atomic_add3(out, m.node, f);
-    else if (m.body >= 0) {
-        atomic_add3(out, m.body, f);
-        atomic_add3(out, m.body + 1, {m.xb.x * f.x, m.xb.x * f.y, m.xb.x * f.z});
-        atomic_add3(out, m.body + 2, {m.xb.y * f.x, m.xb.y * f.y, m.xb.y * f.z});
-        atomic_add3(out, m.body + 3, {m.xb.z * f.x, m.xb.z * f.y, m.xb.z * f.z});
-    }
-}
 __device__ __forceinline__ d3 gather_cv(const Map &m, const double *v)
 {
     if (m.node >= 0) return ld3(v, m.node);
@@ -763,31 +754,33 @@ __device__ __forceinline__ bool bsr_slots(const Map *m, const int *row_ptr, cons
         }
     return all;
 }
-template <class F>
-__device__ __forceinline__ bool merge_into_bsr(const Map *m, const int *row_ptr, const int *col, double *val, F blk)
+// The pair's 16 (k, l) entries for the slot-sorted merge: the block's slot
+// when every block of the pair is in the pattern (nnzb for a static
+// vertex's blocks), else nnzb for all and false (the pair stays pair-local).
+__device__ __forceinline__ bool pair_slot_keys(const Map *m, const int *row_ptr, const int *col, int nnzb, int i,
+                                               int *__restrict__ key, int *__restrict__ code)
 {
     int slot[4][4];
-    if (!bsr_slots(m, row_ptr, col, slot)) return false;
-    double B[9];
+    bool on = bsr_slots(m, row_ptr, col, slot);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)   // unrolled: blk sees compile-time (k, l)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-            if (slot[k][l] < 0) continue;
-            blk(k, l, B);
-            double *d = val + 9 * (size_t)slot[k][l];
-            for (int q = 0; q < 9; ++q) atomicAdd(d + q, B[q]);
+            size_t o = 16 * (size_t)i + 4 * k + l;
+            key[o] = on && slot[k][l] >= 0 ? slot[k][l] : nnzb;
+            code[o] = (int)o;
         }
-    return true;
+    return on;
 }
 
 template <int MODE>   // 0 energy, 1 energy + gradient, 2 gradient + projected Hessian
 __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee,
     const int4 *__restrict__ tri, const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
     const double *__restrict__ sparam, const double *__restrict__ rest2, const int *__restrict__ cv_node,
-    const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ g,
-    int4 *__restrict__ pair_cv, double *__restrict__ pair_H,
-    double *__restrict__ pe, int project, int *__restrict__ inf_flag, const int *__restrict__ row_ptr, const int *__restrict__ col, double *__restrict__ val, int *__restrict__ pair_flag)
+    const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ pg,
+    int *__restrict__ gkey, int *__restrict__ gcode, int ncv, int4 *__restrict__ pair_cv, double *__restrict__ pair_H,
+    double *__restrict__ pe, int project, int *__restrict__ inf_flag, const int *__restrict__ row_ptr, const int *__restrict__ col,
+    int nnzb, int *__restrict__ bkey, int *__restrict__ bcode, int *__restrict__ pair_flag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npt + nee) return;
@@ -801,15 +794,23 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     int type;
     double d2 = pair_d2(kind, x, &type);
     if (MODE == 2) pair_cv[i] = make_int4(cv[0], cv[1], cv[2], cv[3]);
-    if (!(d2 > 0.0)) {
+    // a pair with no contribution: no gradient entries and no blocks
+    auto none = [&]() {
         if (pe) pe[i] = 0.0;
+        if (MODE >= 1)
+            for (int k = 0; k < 4; ++k) { gkey[4 * (size_t)i + k] = ncv; gcode[4 * (size_t)i + k] = 4 * i + k; }
+        if (MODE == 2) {
+            pair_flag[i] = 1;
+            for (int q = 0; q < 16; ++q) { bkey[16 * (size_t)i + q] = nnzb; bcode[16 * (size_t)i + q] = 16 * i + q; }
+        }
+    };
+    if (!(d2 > 0.0)) {
         atomicOr(inf_flag + s, 1);
-        if (MODE == 2) pair_flag[i] = 1;
+        none();
         return;
     }
     if (d2 >= dh * dh) {
-        if (pe) pe[i] = 0.0;
-        if (MODE == 2) pair_flag[i] = 1;
+        none();
         return;
     }
     double d = sqrt(d2);
@@ -857,7 +858,10 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
             gk.y += cb * (su[k] * cu.y + sv[k] * cvv.y);
             gk.z += cb * (su[k] * cu.z + sv[k] * cvv.z);
         }
-        scatter_cv(mp[k], g, gk);
+        // summed per contact vertex by the slot-ordered gather (static: none)
+        st3(pg, 4 * i + k, gk);
+        gkey[4 * (size_t)i + k] = (mp[k].node >= 0 || mp[k].body >= 0) ? cv[k] : ncv;
+        gcode[4 * (size_t)i + k] = 4 * i + k;
     }
     if (MODE < 2) return;
     // reduced (translation-free) 9x9 Hessian, index 3*i + c
@@ -914,49 +918,162 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
             H[pk9(R, C)] = hv;
         }
     if (project) psd_project9(H);
-    // world-vertex block H12[k][l] = sum_ij U_ki U_lj H9[i][j]
-    auto blk = [&](int k, int l, double *B) {
+    // The reduced Hessian of every pair is kept.  A pair whose blocks are all
+    // in the matrix pattern is added into the matrix values by the
+    // slot-sorted gather (flag 1); the others stay pair-local blocks of the
+    // product (flag 0).
+    double *out = pair_H + 45 * (size_t)i;
+#pragma unroll
+    for (int q = 0; q < 45; ++q) out[q] = H[q];
+    pair_flag[i] = pair_slot_keys(mp, row_ptr, col, nnzb, i, bkey, bcode) ? 1 : 0;
+}
+
+// ---- run-sum values (ipc_runsum.h) ------------------------------------------
+// world-vertex block (k, l) of a barrier pair from its reduced Hessian
+struct ValBarrierBlock {
+    const double *pH;
+    __device__ void operator()(int code, double *B) const
+    {
+        const int i = code >> 4, k = (code >> 2) & 3, l = code & 3;
+        const double *H = pH + 45 * (size_t)i;
+        double uk[3], ul[3];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) { uk[ii] = helmert(k, ii); ul[ii] = helmert(l, ii); }
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
+            for (int b = 0; b < 3; ++b) {
                 double acc = 0.0;
 #pragma unroll
                 for (int ii = 0; ii < 3; ++ii)
 #pragma unroll
-                    for (int jj = 0; jj < 3; ++jj) acc += helmert(k, ii) * helmert(l, jj) * H[pk9(3 * ii + a, 3 * jj + bb)];
-                B[3 * a + bb] = acc;
+                    for (int jj = 0; jj < 3; ++jj) acc += uk[ii] * ul[jj] * H[pk9(3 * ii + a, 3 * jj + b)];
+                B[3 * a + b] = acc;
             }
-    };
-    if (merge_into_bsr(mp, row_ptr, col, val, blk)) {
-        pair_flag[i] = 1;
-        return;
     }
-    pair_flag[i] = 0;
-    double *out = pair_H + 45 * (size_t)i;
-#pragma unroll
-    for (int q = 0; q < 45; ++q) out[q] = H[q];
+};
+// friction block (k, l) of a lag pair: beta_k beta_l M
+struct ValLagBlock {
+    const double *lbeta, *lM;
+    __device__ void operator()(int code, double *B) const
+    {
+        const int i = code >> 4, k = (code >> 2) & 3, l = code & 3;
+        const double w = lbeta[4 * (size_t)i + k] * lbeta[4 * (size_t)i + l];
+        const double *M = lM + 6 * (size_t)i;
+        B[0] = w * M[0]; B[1] = w * M[1]; B[2] = w * M[2];
+        B[3] = w * M[1]; B[4] = w * M[3]; B[5] = w * M[4];
+        B[6] = w * M[2]; B[7] = w * M[4]; B[8] = w * M[5];
+    }
+};
+
+// stable sort of m (key, code) int pairs by the low end_bit bits of the key
+void sort_entries(ipc_ctx *c, const int *key, int *key2, const int *code, int *code2, int64_t m, int end_bit)
+{
+    if (m <= 0) return;
+    size_t bytes = 0;
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, key, key2, code, code2, (int)m, 0, end_bit, c->stream));
+    c->d.sort_tmp.alloc(bytes + 16);
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(c->d.sort_tmp.p, bytes, key, key2, code, code2, (int)m, 0, end_bit, c->stream));
 }
 
-void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project)
+int bits_for(int64_t n)   // bits that hold every value in [0, n]
+{
+    int b = 1;
+    while (b < 31 && (1ll << b) <= n) ++b;
+    return b;
+}
+
+// Barrier pairs.  Gradients (mode >= 1) are summed per contact vertex into
+// D.gcv; projected or plain blocks (mode 2) whose slots exist are summed per
+// matrix slot into the values, both through sorted run sums.
+void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, bool project)
 {
     Dev &D = c->d;
     int64_t npt = candidates ? c->n_cand_pt : c->n_pt, nee = candidates ? c->n_cand_ee : c->n_ee;
     const int2 *pt = candidates ? D.cand_pt.p : D.pt.p, *ee = candidates ? D.cand_ee.p : D.ee.p;
     int64_t n = npt + nee;
     D.pair_part.alloc(n + 1);
-    if (mode == 2) { D.pair_cv.alloc(n + 1); D.pair_H.alloc(45 * (size_t)(n + 1)); D.pair_flag.alloc(n + 1); }
+    if (mode >= 1) {
+        D.pair_g.alloc(12 * (size_t)n + 3);
+        for (auto *b : {&D.pg_key, &D.pg_code, &D.pg_key2, &D.pg_code2}) b->alloc(4 * (size_t)n + 1);
+    }
+    if (mode == 2) {
+        D.pair_cv.alloc(n + 1); D.pair_H.alloc(45 * (size_t)(n + 1)); D.pair_flag.alloc(n + 1);
+        for (auto *b : {&D.pb_key, &D.pb_code, &D.pb_key2, &D.pb_code2}) b->alloc(16 * (size_t)n + 1);
+    }
     if (n == 0) return;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)npt, (int)nee, pt, ee, D.tri.p, D.edge.p, xw,
-                           D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, g,
-                           D.pair_cv.p, D.pair_H.p, D.pair_part.p, (int)project, D.inf_flag.p, D.row_ptr.p, D.col.p, D.val.p, D.pair_flag.p);
+                           D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.pair_g.p,
+                           D.pg_key.p, D.pg_code.p, c->CV, D.pair_cv.p, D.pair_H.p, D.pair_part.p, (int)project, D.inf_flag.p,
+                           D.row_ptr.p, D.col.p, c->nnzb, D.pb_key.p, D.pb_code.p, D.pair_flag.p);
     };
     if (mode == 2) prof_begin(c, IPC_K_BARRIER_HESS);
     if (mode == 0) go(k_barrier<0>);
     else if (mode == 1) go(k_barrier<1>);
     else go(k_barrier<2>);
+    if (mode >= 1) {
+        sort_entries(c, D.pg_key.p, D.pg_key2.p, D.pg_code.p, D.pg_code2.p, 4 * n, bits_for(c->CV));
+        runsum<3>(c, 4 * n, c->CV, D.pg_key2.p, D.pg_code2.p, ValVec3{D.pair_g.p}, EmitAdd3{D.gcv.p});
+    }
+    if (mode == 2) {
+        sort_entries(c, D.pb_key.p, D.pb_key2.p, D.pb_code.p, D.pb_code2.p, 16 * n, bits_for(c->nnzb));
+        runsum<9>(c, 16 * n, c->nnzb, D.pb_key2.p, D.pb_code2.p, ValBarrierBlock{D.pair_H.p}, EmitAdd9{D.val.p});
+    }
     if (mode == 2) prof_end(c, IPC_K_BARRIER_HESS, 0.0);
+}
+
+// The contact-vertex sums into DOF gradients: a FEM contact vertex is its
+// node's only contact vertex; a body's contact vertices are summed over the
+// body in their listed order (one wavefront per body, fixed-order shuffle
+// reduction) into its 4 nodes with weights (1, xb).
+__global__ void k_cv_fem(int CV, const int *__restrict__ cv_node, const double *__restrict__ gcv, double *__restrict__ g)
+{
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= CV) return;
+    int n = cv_node[v];
+    if (n < 0) return;
+    d3 a = ld3(gcv, v), b = ld3(g, n);
+    st3(g, n, {b.x + a.x, b.y + a.y, b.z + a.z});
+}
+
+__global__ void __launch_bounds__(64) k_cv_bodies(const int *__restrict__ ptr, const int *__restrict__ list,
+                                                  const double *__restrict__ cv_x, const int *__restrict__ body_node0,
+                                                  const double *__restrict__ gcv, double *__restrict__ g)
+{
+    const int b = blockIdx.x, lane = threadIdx.x;
+    double a[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) a[q] = 0.0;
+    for (int e = ptr[b] + lane; e < ptr[b + 1]; e += 64) {
+        int v = list[e];
+        d3 f = ld3(gcv, v), xb = ld3(cv_x, v);
+        a[0] += f.x; a[1] += f.y; a[2] += f.z;
+        a[3] += xb.x * f.x; a[4] += xb.x * f.y; a[5] += xb.x * f.z;
+        a[6] += xb.y * f.x; a[7] += xb.y * f.y; a[8] += xb.y * f.z;
+        a[9] += xb.z * f.x; a[10] += xb.z * f.y; a[11] += xb.z * f.z;
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) a[q] = wave_sum(a[q]);
+    if (lane != 0) return;
+    double *o = g + 3 * (size_t)body_node0[b];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[q] += a[q];
+}
+
+void contact_grad_begin(ipc_ctx *c)
+{
+    c->d.gcv.alloc(3 * (size_t)c->CV + 3);
+    c->d.gcv.zero(c->stream, 3 * (size_t)c->CV + 3);
+}
+
+void contact_grad_end(ipc_ctx *c, double *g)
+{
+    Dev &D = c->d;
+    if (c->CV == 0) return;
+    hipLaunchKernelGGL(k_cv_fem, dim3(blocks_for(c->CV)), dim3(BLOCK), 0, c->stream, c->CV, D.cv_node.p, D.gcv.p, g);
+    if (c->NB) hipLaunchKernelGGL(k_cv_bodies, dim3(c->NB), dim3(64), 0, c->stream, D.body_cv_ptr.p, D.body_cv.p, D.cv_x.p,
+                                  D.body_node0.p, D.gcv.p, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,10 +1131,11 @@ __global__ void k_lag(int npt, int nee, const int2 *__restrict__ pt, const int2 
 
 // Per lag: the matrix block of every (k, l) of a lag pair whose blocks are
 // all in the pattern (key nnzb: none), for the slot-sorted gather below.
-__global__ void k_lag_slots(int n, int nnzb, const int4 *__restrict__ lcv, const int *__restrict__ cv_node,
+// Also the pair's 4 gradient entries keyed by contact vertex (CV: static).
+__global__ void k_lag_slots(int n, int nnzb, int ncv, const int4 *__restrict__ lcv, const int *__restrict__ cv_node,
                             const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
                             const int *__restrict__ row_ptr, const int *__restrict__ col, int *__restrict__ lmerge,
-                            int *__restrict__ key, int *__restrict__ code)
+                            int *__restrict__ key, int *__restrict__ code, int *__restrict__ gkey, int *__restrict__ gcode)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1025,17 +1143,11 @@ __global__ void k_lag_slots(int n, int nnzb, const int4 *__restrict__ lcv, const
     int cv[4] = {c4.x, c4.y, c4.z, c4.w};
     Map mp[4];
     for (int k = 0; k < 4; ++k) mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
-    int slot[4][4];
-    bool on = bsr_slots(mp, row_ptr, col, slot);
-    lmerge[i] = on ? 1 : 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            size_t o = 16 * (size_t)i + 4 * k + l;
-            key[o] = on && slot[k][l] >= 0 ? slot[k][l] : nnzb;
-            code[o] = (int)o;
-        }
+    lmerge[i] = pair_slot_keys(mp, row_ptr, col, nnzb, i, key, code) ? 1 : 0;
+    for (int k = 0; k < 4; ++k) {
+        gkey[4 * (size_t)i + k] = (mp[k].node >= 0 || mp[k].body >= 0) ? cv[k] : ncv;
+        gcode[4 * (size_t)i + k] = 4 * i + k;
+    }
 }
 
 void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
@@ -1050,6 +1162,8 @@ void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
         D.lag_merge.alloc(c->cap_lag);
         D.lag_key.alloc(16 * c->cap_lag); D.lag_code.alloc(16 * c->cap_lag);
         D.lag_key2.alloc(16 * c->cap_lag); D.lag_code2.alloc(16 * c->cap_lag);
+        D.lag_g.alloc(12 * c->cap_lag);
+        for (auto *b : {&D.lg_key, &D.lg_code, &D.lg_key2, &D.lg_code2}) b->alloc(4 * c->cap_lag);
     }
     c->n_lag = n;
     c->h_lag_seg.assign(c->n_scenes + 1, 0);
@@ -1058,60 +1172,13 @@ void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
     hipLaunchKernelGGL(k_lag, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,
                        D.edge.p, xw, D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p, D.lag_lam.p,
                        D.lag_rn.p, D.lag_type.p, D.lag_ex.p, xref);
-    // slot lists of the merged friction blocks, sorted by slot once per lag
-    int m = (int)(16 * n);
-    hipLaunchKernelGGL(k_lag_slots, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, c->nnzb, D.lag_cv.p, D.cv_node.p,
-                       D.cv_body.p, D.cv_x.p, D.body_node0.p, D.row_ptr.p, D.col.p, D.lag_merge.p, D.lag_key.p, D.lag_code.p);
-    int end_bit = 1;
-    while (end_bit < 31 && (1 << end_bit) <= c->nnzb) ++end_bit;
-    size_t bytes = 0;
-    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, D.lag_key.p, D.lag_key2.p, D.lag_code.p, D.lag_code2.p, m, 0, end_bit,
-                                               c->stream));
-    D.lag_sort_tmp.alloc(bytes + 16);
-    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(D.lag_sort_tmp.p, bytes, D.lag_key.p, D.lag_key2.p, D.lag_code.p, D.lag_code2.p, m, 0,
-                                               end_bit, c->stream));
-}
-
-// Friction Hessian blocks of the merged lag pairs into the matrix values.
-// One thread per (pair, k, l) entry of the slot-sorted list forms
-// beta_k beta_l M; a segmented scan over each wavefront's lanes (runs of
-// equal slots are contiguous) sums each run, and the run's last lane in the
-// wavefront adds the sum to the block.  A block gets one atomic add per
-// wavefront its run touches, however many pairs share it.
-__global__ void __launch_bounds__(256) k_fric_gather(int m, int nnzb, const int *__restrict__ key, const int *__restrict__ code,
-                                                     const double *__restrict__ lbeta, const double *__restrict__ lM,
-                                                     double *__restrict__ val)
-{
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int lane = threadIdx.x & 63;
-    int sl = t < m ? key[t] : -1;
-    bool on = sl >= 0 && sl < nnzb;
-    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (on) {
-        int cd = code[t], i = cd >> 4, k = (cd >> 2) & 3, l = cd & 3;
-        double w = lbeta[4 * (size_t)i + k] * lbeta[4 * (size_t)i + l];
-        const double *M = lM + 6 * (size_t)i;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) a[q] = w * M[q];
-    }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int ok = __shfl_up(sl, d, 64);
-        double o[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) o[q] = __shfl_up(a[q], d, 64);
-        if (lane >= d && ok == sl) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) a[q] += o[q];
-        }
-    }
-    int nx = __shfl_down(sl, 1, 64);
-    bool last = lane == 63 || t + 1 >= m || nx != sl;
-    if (!on || !last) return;
-    double *d = val + 9 * (size_t)sl;
-    atomicAdd(d + 0, a[0]); atomicAdd(d + 1, a[1]); atomicAdd(d + 2, a[2]);
-    atomicAdd(d + 3, a[1]); atomicAdd(d + 4, a[3]); atomicAdd(d + 5, a[4]);
-    atomicAdd(d + 6, a[2]); atomicAdd(d + 7, a[4]); atomicAdd(d + 8, a[5]);
+    // slot lists of the merged friction blocks and the gradient entries by
+    // contact vertex, sorted once per lag
+    hipLaunchKernelGGL(k_lag_slots, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, c->nnzb, c->CV, D.lag_cv.p, D.cv_node.p,
+                       D.cv_body.p, D.cv_x.p, D.body_node0.p, D.row_ptr.p, D.col.p, D.lag_merge.p, D.lag_key.p, D.lag_code.p,
+                       D.lg_key.p, D.lg_code.p);
+    sort_entries(c, D.lag_key.p, D.lag_key2.p, D.lag_code.p, D.lag_code2.p, 16 * n, bits_for(c->nnzb));
+    sort_entries(c, D.lg_key.p, D.lg_key2.p, D.lg_code.p, D.lg_code2.p, 4 * n, bits_for(c->CV));
 }
 
 template <int MODE>
@@ -1119,7 +1186,7 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
                            const double *__restrict__ llam, const double *__restrict__ lrn, const double *__restrict__ xw,
                            const int *__restrict__ cv_scene, const double *__restrict__ sparam, const int *__restrict__ cv_node,
                            const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0,
-                           double *__restrict__ g, double *__restrict__ lM,
+                           double *__restrict__ lg, double *__restrict__ lM,
                            double *__restrict__ pe, const int *__restrict__ lmerge, int *__restrict__ lflag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1145,11 +1212,10 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
     if (pe) pe[i] = w * f0;
     if (MODE == 0) return;
     double f1s = sn < ea ? 2.0 / ea - sn / (ea * ea) : 1.0 / sn;
-    Map mp[4];
-    for (int k = 0; k < 4; ++k) mp[k] = cv_map(cv[k], cv_node, cv_body, cv_x, body_node0);
+    // per-vertex gradients, summed per contact vertex by the sorted run sums
     for (int k = 0; k < 4; ++k) {
         double cc = w * f1s * beta[k];
-        scatter_cv(mp[k], g, {cc * u.x, cc * u.y, cc * u.z});
+        st3(lg, 4 * i + k, {cc * u.x, cc * u.y, cc * u.z});
     }
     if (MODE < 2) return;
     double cu = sn < ea ? (sn > 0.0 ? -1.0 / (sn * ea * ea) : 0.0) : -1.0 / (sn * sn * sn);
@@ -1164,7 +1230,10 @@ __global__ void k_friction(int n, const int4 *__restrict__ lcv, const double *__
     o[0] = M[0]; o[1] = M[1]; o[2] = M[2]; o[3] = M[4]; o[4] = M[5]; o[5] = M[8];
 }
 
-void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
+// Lagged friction.  Gradients (mode >= 1) are summed per contact vertex into
+// D.gcv; the blocks of the merged lag pairs (mode 2) per matrix slot into the
+// values, both through the lists sorted once per lag.
+void launch_friction(ipc_ctx *c, int mode, const double *xw)
 {
     Dev &D = c->d;
     int64_t n = c->n_lag;
@@ -1173,16 +1242,14 @@ void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g)
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, D.lag_cv.p, D.lag_beta.p, D.lag_nrm.p,
                            D.lag_lam.p, D.lag_rn.p, xw, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p,
-                           g, D.lag_M.p, D.fr_part.p, D.lag_merge.p, D.lag_flag.p);
+                           D.lag_g.p, D.lag_M.p, D.fr_part.p, D.lag_merge.p, D.lag_flag.p);
     };
     D.fr_part.alloc(n + 1);
     if (mode == 0) go(k_friction<0>);
     else if (mode == 1) go(k_friction<1>);
-    else {
-        go(k_friction<2>);
-        hipLaunchKernelGGL(k_fric_gather, dim3(blocks_for(16 * n)), dim3(BLOCK), 0, c->stream, (int)(16 * n), c->nnzb,
-                           D.lag_key2.p, D.lag_code2.p, D.lag_beta.p, D.lag_M.p, D.val.p);
-    }
+    else go(k_friction<2>);
+    if (mode >= 1) runsum<3>(c, 4 * n, c->CV, D.lg_key2.p, D.lg_code2.p, ValVec3{D.lag_g.p}, EmitAdd3{D.gcv.p});
+    if (mode == 2) runsum<9>(c, 16 * n, c->nnzb, D.lag_key2.p, D.lag_code2.p, ValLagBlock{D.lag_beta.p, D.lag_M.p}, EmitAdd9{D.val.p});
 }
 
 // ---------------------------------------------------------------------------
@@ -1199,7 +1266,7 @@ __global__ void k_lag_vjp(int n, int npt, const int4 *__restrict__ lcv, const in
                           const double *__restrict__ xw, const double *__restrict__ xwn, const int *__restrict__ cv_scene,
                           const double *__restrict__ sparam, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
                           const double *__restrict__ cv_x, const int *__restrict__ body_node0, const double *__restrict__ w,
-                          double *__restrict__ ybar, double *__restrict__ part)
+                          double *__restrict__ lg, double *__restrict__ part)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1291,7 +1358,7 @@ __global__ void k_lag_vjp(int n, int npt, const int4 *__restrict__ lcv, const in
             double dpsi = dt(gpsi, du) + f1s * dWu;
             res[c] = -mu * (dlam * psi + lam * dpsi);
         }
-        scatter_cv(mp[j], ybar, {res[0], res[1], res[2]});
+        st3(lg, 4 * i + j, {res[0], res[1], res[2]});
     }
 }
 
@@ -1302,8 +1369,12 @@ void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const doubl
     D.fr_part.alloc(n + 1);
     if (n == 0) return;
     hipLaunchKernelGGL(k_lag_vjp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, (int)c->n_lag_pt, D.lag_cv.p, D.lag_type.p,
-                       D.lag_ex.p, xw, xwn, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, w, ybar,
+                       D.lag_ex.p, xw, xwn, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, w, D.lag_g.p,
                        D.fr_part.p);
+    // per-vertex values summed per contact vertex, then into ybar
+    contact_grad_begin(c);
+    runsum<3>(c, 4 * n, c->CV, D.lg_key2.p, D.lg_code2.p, ValVec3{D.lag_g.p}, EmitAdd3{D.gcv.p});
+    contact_grad_end(c, ybar);
 }
 
 // ---------------------------------------------------------------------------

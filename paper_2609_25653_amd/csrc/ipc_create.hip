@@ -13,6 +13,7 @@
 
 #include "ipc_device.h"
 #include "ipc_internal.h"
+#include "ipc_runsum.h"
 
 namespace ipc {
 
@@ -75,17 +76,6 @@ __global__ void k_node_mass(int N, const int *__restrict__ adj_ptr, const int *_
     mass[n] = m;
 }
 
-// find the block slot of column cc in row r (rows are sorted)
-__device__ __forceinline__ int slot_of(const int *row_ptr, const int *col, int r, int cc)
-{
-    int lo = row_ptr[r], hi = row_ptr[r + 1];
-    while (lo < hi) {
-        int m = (lo + hi) >> 1;
-        if (col[m] < cc) lo = m + 1; else hi = m;
-    }
-    return lo;
-}
-
 // constant part of the matrix: lumped FEM mass on the diagonal blocks
 __global__ void k_const_mass(int N, const int *__restrict__ kind, const int *__restrict__ diag_slot, const double *__restrict__ mass,
                              double *__restrict__ vc)
@@ -97,38 +87,39 @@ __global__ void k_const_mass(int N, const int *__restrict__ kind, const int *__r
 }
 
 // constant part of the matrix: spring Hessians h^2 k (u u^T) (x) I3 where u
-// lists the side nodes with weights +w (side a) and -w (side b)
-__global__ void k_const_springs(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
-                                const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
-                                const double *__restrict__ k, const int *__restrict__ sp_scene, const double *__restrict__ h2s,
-                                const int *__restrict__ body_node0, const int *__restrict__ row_ptr, const int *__restrict__ col,
-                                double *__restrict__ vc)
+// lists the side nodes with weights +w (side a) and -w (side b).  Entry code
+// 64 s + 8 i + j of the slot-sorted list is h^2 k u_i u_j; the run sums add
+// it to the three diagonal entries of the slot's block.
+__device__ __forceinline__ double spring_u(int s, int i, const int *ka, const double *xa, const int *kb, const double *xb)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= NS) return;
-    double kk = h2s[sp_scene[s]] * k[s];
-    int nd[8];
-    double w[8];
-    int m = 0;
     for (int side = 0; side < 2; ++side) {
         int kind = side ? kb[s] : ka[s];
-        int idx = side ? ib[s] : ia[s];
-        const double *xbar = (side ? xb : xa) + 3 * (size_t)s;
-        double sg = side ? -1.0 : 1.0;
-        if (kind == 0) { nd[m] = idx; w[m++] = sg; }
-        else if (kind == 1) {
-            int n0 = body_node0[idx];
-            nd[m] = n0; w[m++] = sg;
-            for (int c = 0; c < 3; ++c) { nd[m] = n0 + 1 + c; w[m++] = sg * xbar[c]; }
+        int n = kind == 0 ? 1 : (kind == 1 ? 4 : 0);
+        if (i < n) {
+            double sg = side ? -1.0 : 1.0;
+            return (kind == 0 || i == 0) ? sg : sg * (side ? xb : xa)[3 * (size_t)s + i - 1];
         }
+        i -= n;
     }
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-            double v = kk * w[i] * w[j];
-            double *b = vc + 9 * (size_t)slot_of(row_ptr, col, nd[i], nd[j]);
-            atomicAdd(b, v); atomicAdd(b + 4, v); atomicAdd(b + 8, v);
-        }
+    return 0.0;
 }
+struct ValConstSpring {
+    const int *ka, *kb, *sscene;
+    const double *xa, *xb, *k, *h2s;
+    __device__ void operator()(int code, double *a) const
+    {
+        const int s = code >> 6, i = (code >> 3) & 7, j = code & 7;
+        a[0] = h2s[sscene[s]] * k[s] * spring_u(s, i, ka, xa, kb, xb) * spring_u(s, j, ka, xa, kb, xb);
+    }
+};
+struct EmitDiag {   // the scalar onto the diagonal of a 3x3 block
+    double *out;
+    __device__ void operator()(int key, const double *a) const
+    {
+        double *b = out + 9 * (size_t)key;
+        b[0] += a[0]; b[4] += a[0]; b[8] += a[0];
+    }
+};
 
 __global__ void k_zero_vals(int64_t n, double *__restrict__ v)
 {
@@ -269,10 +260,8 @@ void build_const_part(ipc_ctx *c, const double *h2s)
     hipLaunchKernelGGL(k_zero_vals, dim3(blocks_for(nv)), dim3(BLOCK), 0, st, nv, D.val_const.p);
     hipLaunchKernelGGL(k_const_mass, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_kind.p, D.diag_slot.p, D.mass.p,
                        D.val_const.p);
-    if (c->NS > 0)
-        hipLaunchKernelGGL(k_const_springs, dim3(blocks_for(c->NS)), dim3(BLOCK), 0, st, c->NS, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
-                           D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, D.body_node0.p, D.row_ptr.p, D.col.p,
-                           D.val_const.p);
+    runsum<1>(c, D.n_spc, c->nnzb, D.spc_key.p, D.spc_code.p,
+              ValConstSpring{D.sp_ka.p, D.sp_kb.p, D.sp_scene.p, D.sp_xa.p, D.sp_xb.p, D.sp_k.p, h2s}, EmitDiag{D.val_const.p});
 }
 
 
@@ -524,6 +513,39 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     }
     c->seg_surf[n] = cv; c->seg_tri[n] = tri; c->seg_edge[n] = edge; c->seg_sp[n] = sp; c->seg_body[n] = body;
 
+    // Entry lists of the deterministic run sums (ipc_runsum.h), built once:
+    //  spring gradients: code 8 s + 4 side + q -> node, sorted by node;
+    //  constant spring blocks: code 64 s + 8 i + j -> matrix slot, sorted by
+    //   slot, with i, j the positions of the two nodes in the spring's node
+    //   list (side a's nodes, then side b's, as spring_nodes lists them);
+    //  contact vertices of every body, in contact-vertex order.
+    std::vector<std::pair<int, int>> spg, spc;
+    for (int k = 0; k < sp; ++k) {
+        std::vector<int> nd;
+        for (int side = 0; side < 2; ++side) {
+            int kind = side ? skb[k] : ska[k], idx = side ? sib[k] : sia[k];
+            if (kind == 0) spg.push_back({idx, 8 * k + 4 * side});
+            else if (kind == 1)
+                for (int q = 0; q < 4; ++q) spg.push_back({body_node0[idx] + q, 8 * k + 4 * side + q});
+            spring_nodes(kind, idx, nd);
+        }
+        for (int i = 0; i < (int)nd.size(); ++i)
+            for (int j = 0; j < (int)nd.size(); ++j) spc.push_back({find_slot(nd[i], nd[j]), 64 * k + 8 * i + j});
+    }
+    std::sort(spg.begin(), spg.end());
+    std::sort(spc.begin(), spc.end());
+    std::vector<int> spg_key(spg.size() + 1), spg_code(spg.size() + 1), spc_key(spc.size() + 1), spc_code(spc.size() + 1);
+    for (size_t i = 0; i < spg.size(); ++i) { spg_key[i] = spg[i].first; spg_code[i] = spg[i].second; }
+    for (size_t i = 0; i < spc.size(); ++i) { spc_key[i] = spc[i].first; spc_code[i] = spc[i].second; }
+    std::vector<int> body_cv_ptr(body + 1, 0), body_cv;
+    for (int g = 0; g < cv; ++g) if (cv_body[g] >= 0) body_cv_ptr[cv_body[g] + 1]++;
+    for (int b = 0; b < body; ++b) body_cv_ptr[b + 1] += body_cv_ptr[b];
+    body_cv.resize(body_cv_ptr[body] + 1);
+    {
+        std::vector<int> fill(body_cv_ptr.begin(), body_cv_ptr.end() - 1);
+        for (int g = 0; g < cv; ++g) if (cv_body[g] >= 0) body_cv[fill[cv_body[g]]++] = g;
+    }
+
     // ---- upload
     Dev &D = c->d;
     D.y.upload(X, st); D.ydot.upload(V, st);
@@ -547,6 +569,10 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     D.sp_ka.upload(ska, st); D.sp_ia.upload(sia, st); D.sp_kb.upload(skb, st); D.sp_ib.upload(sib, st);
     D.sp_scene.upload(sscene, st); D.sp_xa.upload(sxa, st); D.sp_xb.upload(sxb, st); D.sp_k.upload(sk, st);
     D.sp_part.alloc(std::max(sp, 1));
+    D.sp_f.alloc(3 * (size_t)std::max(sp, 1));
+    D.spg_key.upload(spg_key, st); D.spg_code.upload(spg_code, st); D.n_spg = (int64_t)spg.size();
+    D.spc_key.upload(spc_key, st); D.spc_code.upload(spc_code, st); D.n_spc = (int64_t)spc.size();
+    D.body_cv_ptr.upload(body_cv_ptr, st); D.body_cv.upload(body_cv, st);
     D.targets.upload(targets, st); D.driven_body.upload(driven, st); D.joint_sp.upload(joint_sp, st);
     D.cv_node.upload(cv_node, st); D.cv_body.upload(cv_body, st); D.cv_obj.upload(cv_obj, st); D.cv_scene.upload(cv_scene, st);
     D.cv_x.upload(cv_x, st);

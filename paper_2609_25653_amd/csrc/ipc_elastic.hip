@@ -11,6 +11,7 @@
 // deterministic sum.
 #include "ipc_device.h"
 #include "ipc_internal.h"
+#include "ipc_runsum.h"
 #include "ipc_kernels.h"
 #include "ipc_eigsys.h"
 
@@ -313,24 +314,27 @@ __device__ __forceinline__ d3 spring_side(int kind, int idx, const double *xb, c
     return xaffine(mk(q[0], q[1], q[2]), mk(q[3], q[4], q[5]), mk(q[6], q[7], q[8]), mk(q[9], q[10], q[11]), w);
 }
 
-__device__ __forceinline__ void spring_scatter(int kind, int idx, const double *xb, const int *body_node0, double *out, d3 f)
-{
-    if (kind == 0) atomic_add3(out, idx, f);
-    else if (kind == 1) {
-        int n0 = body_node0[idx];
-        atomic_add3(out, n0, f);
-        atomic_add3(out, n0 + 1, {xb[0] * f.x, xb[0] * f.y, xb[0] * f.z});
-        atomic_add3(out, n0 + 2, {xb[1] * f.x, xb[1] * f.y, xb[1] * f.z});
-        atomic_add3(out, n0 + 3, {xb[2] * f.x, xb[2] * f.y, xb[2] * f.z});
+// Gradient entry code 8 s + 4 side + q of spring s: the force on side a
+// (+f) or b (-f), times the side's weight q (1 for a FEM vertex; 1, xb0, xb1,
+// xb2 for the 4 nodes of a body point).  The entries, sorted by node once at
+// creation, are summed per node by the run sums.
+struct ValSpring {
+    const double *f, *xa, *xb;
+    __device__ void operator()(int code, double *a) const
+    {
+        const int s = code >> 3, side = (code >> 2) & 1, q = code & 3;
+        const double sg = side ? -1.0 : 1.0;
+        const double w = q == 0 ? sg : sg * (side ? xb : xa)[3 * (size_t)s + q - 1];
+        a[0] = w * f[3 * (size_t)s]; a[1] = w * f[3 * (size_t)s + 1]; a[2] = w * f[3 * (size_t)s + 2];
     }
-}
+};
 
 template <int MODE>   // 0 energy, 1 energy+gradient
 __global__ void k_spring(int NS, const int *__restrict__ ka, const int *__restrict__ ia, const double *__restrict__ xa,
                          const int *__restrict__ kb, const int *__restrict__ ib, const double *__restrict__ xb,
                          const double *__restrict__ k, const int *__restrict__ sscene, const double *__restrict__ h2s,
                          const double *__restrict__ y, const int *__restrict__ body_node0, const double *__restrict__ targets,
-                         double *__restrict__ g, double *__restrict__ part)
+                         double *__restrict__ f, double *__restrict__ part)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= NS) return;
@@ -340,9 +344,7 @@ __global__ void k_spring(int NS, const int *__restrict__ ka, const int *__restri
     double kk = h2s[sscene[s]] * k[s];
     if (part) part[s] = 0.5 * kk * dt(d, d);
     if (MODE == 0) return;
-    d3 f = {kk * d.x, kk * d.y, kk * d.z};
-    spring_scatter(ka[s], ia[s], xa + 3 * (size_t)s, body_node0, g, f);
-    spring_scatter(kb[s], ib[s], xb + 3 * (size_t)s, body_node0, g, {-f.x, -f.y, -f.z});
+    st3(f, s, {kk * d.x, kk * d.y, kk * d.z});
 }
 
 // ---------------------------------------------------------------------------
@@ -404,10 +406,14 @@ void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *par
     Dev &D = c->d;
     auto args = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(c->NS)), dim3(BLOCK), 0, c->stream, c->NS, D.sp_ka.p, D.sp_ia.p, D.sp_xa.p,
-                           D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, y, D.body_node0.p, D.targets.p, g, part);
+                           D.sp_kb.p, D.sp_ib.p, D.sp_xb.p, D.sp_k.p, D.sp_scene.p, h2s, y, D.body_node0.p, D.targets.p, D.sp_f.p, part);
     };
-    if (mode == 0) args(k_spring<0>);
-    else args(k_spring<1>);
+    if (mode == 0) {
+        args(k_spring<0>);
+        return;
+    }
+    args(k_spring<1>);
+    runsum<3>(c, D.n_spg, c->N, D.spg_key.p, D.spg_code.p, ValSpring{D.sp_f.p, D.sp_xa.p, D.sp_xb.p}, EmitAdd3{g});
 }
 
 } // namespace ipc

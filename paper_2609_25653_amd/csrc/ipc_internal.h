@@ -251,6 +251,21 @@ struct Dev {
     DBuf<int> tickets;                     // small device counters
     DBuf<double> grav;
     DBuf<double> red_tmp;
+    // deterministic scatters: sorted (key, code) entries summed per run of
+    // equal keys (ipc_runsum.h) instead of floating-point atomics
+    DBuf<double> rs_first, rs_last;        // per-wavefront pieces of runs crossing wavefront boundaries
+    DBuf<double> pair_g;                   // barrier: world gradient of each pair vertex (12 per pair)
+    DBuf<int> pg_key, pg_code, pg_key2, pg_code2;   // 4 per pair: contact vertex (CV: static) / 4 i + k, unsorted and sorted
+    DBuf<int> pb_key, pb_code, pb_key2, pb_code2;   // 16 per pair: matrix slot (nnzb: none) / 16 i + 4 k + l
+    DBuf<double> lag_g;                    // friction (and its adjoint): per lag-pair vertex values (12 per pair)
+    DBuf<int> lg_key, lg_code, lg_key2, lg_code2;   // 4 per lag pair, sorted by contact vertex once per lag
+    DBuf<double> gcv;                      // contact-vertex sums (3 per contact vertex)
+    DBuf<int> body_cv_ptr, body_cv;        // contact vertices of every body (CSR over bodies)
+    DBuf<double> sp_f;                     // spring force h^2 k (a - b) per spring
+    DBuf<int> spg_key, spg_code;           // spring gradient entries sorted by node: code 8 s + 4 side + q
+    int64_t n_spg = 0;
+    DBuf<int> spc_key, spc_code;           // constant spring blocks sorted by slot: code 64 s + 8 i + j
+    int64_t n_spc = 0;
 };
 
 } // namespace ipc

@@ -33,10 +33,19 @@ void broad_phase_cached(ipc_ctx *c, const double *xw0, const double *xw1);
 void cand_check(ipc_ctx *c, const double *xw0, const double *xw1, int *flag);
 // narrow phase: active pairs from the candidate lists at xw
 void narrow_phase(ipc_ctx *c, const double *xw);
-void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, double *g, bool project);
+// barrier (mode 0 energy, 1 + gradient, 2 + Hessian blocks) and friction:
+// gradients are summed per contact vertex into D.gcv, between
+// contact_grad_begin (zeroes it) and contact_grad_end (adds it into g)
+void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, bool project);
 // the lag at world positions xw; slips measured from xref (nullptr: xw)
 void launch_lag(ipc_ctx *c, const double *xw, const double *xref = nullptr);
-void launch_friction(ipc_ctx *c, int mode, const double *xw, double *g);
+void launch_friction(ipc_ctx *c, int mode, const double *xw);
+void contact_grad_begin(ipc_ctx *c);
+void contact_grad_end(ipc_ctx *c, double *g);
+// stable sort of m (key, code) pairs by the low end_bit bits of the key, and
+// the bits that hold every value in [0, n]
+void sort_entries(ipc_ctx *c, const int *key, int *key2, const int *code, int *code2, int64_t m, int end_bit);
+int bits_for(int64_t n);
 // pair-local contact blocks as row-sorted extra blocks of the product, and the
 // rows the product takes one wavefront per row
 void build_dyn_blocks(ipc_ctx *c);
