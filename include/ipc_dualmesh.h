@@ -71,6 +71,21 @@ int ipc_dualmesh_weights(const ipc_dualmesh *m, int32_t *row_ptr, int32_t *col, 
  * work is done. */
 int ipc_dualmesh_apply(ipc_dualmesh *m, const double *xc_dev, double *xf_dev, int32_t n_frames);
 
+/* The same product for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * this entry point calls no hipMalloc, hipFree or other allocating routine.
+ * W is staged in a fixed device array of 16 MiB per GPU that the library
+ * holds until the process ends; a W that needs more (its CSR arrays, plus
+ * the per-block column lists when every block fits the staged kernel, each
+ * rounded up to 256 bytes) is rejected with IPC_E_CAPACITY.  Every call on
+ * one GPU shares that array: it keeps the W of the last call (a call with the
+ * same handle copies nothing, another handle's call copies its W from host
+ * memory first), so calls that overlap on one GPU, from several host threads
+ * or on different streams, race.  Arguments, results and errors are those of
+ * ipc_dualmesh_apply; the calling thread's current device must be the one
+ * the creation stream belongs to. */
+int ipc_dualmesh_apply_noalloc(ipc_dualmesh *m, const double *xc_dev, double *xf_dev, int32_t n_frames);
+
 /* Duration of one ipc_dualmesh_apply launch, from `reps` back-to-back
  * launches between two HIP events on the creation stream; bytes = the
  * launch's algorithmic bytes (12 per nonzero of W and 4 per row pointer,

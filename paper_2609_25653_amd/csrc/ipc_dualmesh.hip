@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -30,6 +31,7 @@ struct ipc_dualmesh {
     // blk_off[b]) and, per nonzero, the column's place in its block's list
     std::vector<int> blk_off, blk_cols, lcol;
     int max_block = 0;
+    uint64_t id = 0;   // unique per handle: names the W that the no-alloc path last staged
     int *d_row = nullptr, *d_col = nullptr, *d_lcol = nullptr, *d_boff = nullptr, *d_bcols = nullptr;
     double *d_val = nullptr;
     std::string err;
@@ -283,6 +285,9 @@ __global__ void __launch_bounds__(DM_ROWS) k_dm_apply_lds(int nf, int nc, int fr
     }
 }
 
+// the staged kernel serves every W whose blocks fit in LDS and rows in 16 registers
+bool staged(const ipc_dualmesh *m) { return m->max_block <= DM_STAGE && m->max_row <= 16; }
+
 hipError_t upload(ipc_dualmesh *m)
 {
     if (m->d_row) return hipSuccess;
@@ -294,7 +299,7 @@ hipError_t upload(ipc_dualmesh *m)
         e = hipMemcpyAsync(m->d_col, m->col.data(), sizeof(int) * m->col.size(), hipMemcpyHostToDevice, m->stream);
     if (e == hipSuccess && !m->val.empty())
         e = hipMemcpyAsync(m->d_val, m->val.data(), sizeof(double) * m->val.size(), hipMemcpyHostToDevice, m->stream);
-    if (e == hipSuccess && m->max_block <= DM_STAGE && m->max_row <= 16) {
+    if (e == hipSuccess && staged(m)) {
         e = hipMalloc(&m->d_lcol, sizeof(int) * std::max<size_t>(m->lcol.size(), 1));
         if (e == hipSuccess) e = hipMalloc(&m->d_boff, sizeof(int) * m->blk_off.size());
         if (e == hipSuccess) e = hipMalloc(&m->d_bcols, sizeof(int) * std::max<size_t>(m->blk_cols.size(), 1));
@@ -309,17 +314,24 @@ hipError_t upload(ipc_dualmesh *m)
     return e;
 }
 
-hipError_t launch(ipc_dualmesh *m, const double *xc, double *xf, int frames)
+// W on the device: CSR arrays, and for the staged kernel the renumbered
+// columns and the per-block coarse-vertex lists
+struct DevW {
+    const int *row, *col, *lcol, *boff, *bcols;
+    const double *val;
+};
+
+hipError_t launch(ipc_dualmesh *m, const DevW &w, const double *xc, double *xf, int frames)
 {
     const dim3 grid((m->n_fine + 255) / 256), blk(256);
     const int R = m->max_row;
-    if (m->d_lcol) {   // every block's coarse vertices fit in LDS and every row in 16 registers
+    if (w.lcol) {
         hipLaunchKernelGGL(k_dm_apply_lds<16>, dim3((m->n_fine + DM_ROWS - 1) / DM_ROWS), dim3(DM_ROWS), 0, m->stream, m->n_fine,
-                           m->n_coarse, frames, m->d_row, m->d_lcol, m->d_val, m->d_boff, m->d_bcols, xc, xf);
+                           m->n_coarse, frames, w.row, w.lcol, w.val, w.boff, w.bcols, xc, xf);
         return hipGetLastError();
     }
-#define IPC_DM(KK) hipLaunchKernelGGL(k_dm_apply<KK>, grid, blk, 0, m->stream, m->n_fine, m->n_coarse, frames, m->d_row, m->d_col, \
-                                      m->d_val, xc, xf)
+#define IPC_DM(KK) hipLaunchKernelGGL(k_dm_apply<KK>, grid, blk, 0, m->stream, m->n_fine, m->n_coarse, frames, w.row, w.col, \
+                                      w.val, xc, xf)
     if (R <= 8) IPC_DM(8);
     else if (R <= 16) IPC_DM(16);
     else if (R <= 32) IPC_DM(32);
@@ -328,6 +340,49 @@ hipError_t launch(ipc_dualmesh *m, const double *xc, double *xf, int frames)
     else IPC_DM(0);
 #undef IPC_DM
     return hipGetLastError();
+}
+
+DevW owned(const ipc_dualmesh *m) { return {m->d_row, m->d_col, m->d_lcol, m->d_boff, m->d_bcols, m->d_val}; }
+
+// ---- the variant that allocates nothing ------------------------------------
+// W is staged in a file-scope device array of fixed size instead of memory
+// the library allocates.  Every GPU holds its own copy of the array, at its
+// own address, taken once per device with hipGetSymbolAddress; the host-side
+// name of the array is not a device address and is never passed to a kernel
+// or a copy.  The array keeps the W of the last call on that GPU: a call with
+// the same handle does not copy it again.
+constexpr size_t DM_SCRATCH_BYTES = 16u << 20;
+static __device__ __align__(256) unsigned char scratch[DM_SCRATCH_BYTES];
+constexpr int DM_MAX_DEVICES = 64;
+struct ScratchSlot {
+    unsigned char *ptr = nullptr;   // this device's address of the array
+    uint64_t holds = 0;             // id of the handle whose W it holds (0: none)
+};
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[DM_MAX_DEVICES];
+uint64_t g_dm_next_id = 1;
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// byte offsets of W's arrays in the array (0 for an unused one); the total
+struct ScratchLayout {
+    size_t row = 0, col = 0, lcol = 0, val = 0, boff = 0, bcols = 0, total = 0;
+};
+ScratchLayout scratch_layout(const ipc_dualmesh *m)
+{
+    ScratchLayout L;
+    size_t o = 0;
+    L.row = o; o += align256(sizeof(int) * m->row_ptr.size());
+    L.val = o; o += align256(sizeof(double) * std::max<size_t>(m->val.size(), 1));
+    if (staged(m)) {
+        L.lcol = o; o += align256(sizeof(int) * std::max<size_t>(m->lcol.size(), 1));
+        L.boff = o; o += align256(sizeof(int) * m->blk_off.size());
+        L.bcols = o; o += align256(sizeof(int) * std::max<size_t>(m->blk_cols.size(), 1));
+    } else {
+        L.col = o; o += align256(sizeof(int) * std::max<size_t>(m->col.size(), 1));
+    }
+    L.total = o;
+    return L;
 }
 
 } // namespace
@@ -349,6 +404,10 @@ extern "C" int ipc_dualmesh_create(const int32_t *tri_host, int32_t n_tri, int32
         }
         auto *m = new ipc_dualmesh;
         m->stream = (hipStream_t)hip_stream;
+        {
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            m->id = g_dm_next_id++;
+        }
         // W = identity, then one level at a time: W <- S W
         Csr W;
         for (int i = 0; i < n_vert; ++i) { W.col.push_back(i); W.val.push_back(1.0); W.ptr.push_back(i + 1); }
@@ -439,7 +498,49 @@ extern "C" int ipc_dualmesh_apply(ipc_dualmesh *m, const double *xc_dev, double 
     if (!m) return IPC_E_INVALID;
     if (!xc_dev || !xf_dev || n_frames < 1) { m->err = "need device arrays and at least one frame"; return IPC_E_INVALID; }
     hipError_t e = upload(m);
-    if (e == hipSuccess) e = launch(m, xc_dev, xf_dev, n_frames);
+    if (e == hipSuccess) e = launch(m, owned(m), xc_dev, xf_dev, n_frames);
+    if (e != hipSuccess) { m->err = std::string("HIP: ") + hipGetErrorString(e); return IPC_E_DEVICE; }
+    return IPC_OK;
+}
+
+extern "C" int ipc_dualmesh_apply_noalloc(ipc_dualmesh *m, const double *xc_dev, double *xf_dev, int32_t n_frames)
+{
+    if (!m) return IPC_E_INVALID;
+    if (!xc_dev || !xf_dev || n_frames < 1) { m->err = "need device arrays and at least one frame"; return IPC_E_INVALID; }
+    const ScratchLayout L = scratch_layout(m);
+    if (L.total > DM_SCRATCH_BYTES) {
+        m->err = "W needs " + std::to_string(L.total) + " bytes of staging; the no-alloc path holds at most " +
+                 std::to_string(DM_SCRATCH_BYTES);
+        return IPC_E_CAPACITY;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= DM_MAX_DEVICES)) { m->err = "device ordinal out of range"; return IPC_E_INVALID; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot &S = g_scratch[dev];
+    if (e == hipSuccess && !S.ptr) e = hipGetSymbolAddress((void **)&S.ptr, HIP_SYMBOL(scratch));   // once per device
+    if (e == hipSuccess && S.holds != m->id) {
+        auto put = [&](size_t off, const void *src, size_t bytes) {
+            if (e == hipSuccess && bytes) e = hipMemcpyAsync(S.ptr + off, src, bytes, hipMemcpyHostToDevice, m->stream);
+        };
+        S.holds = 0;
+        put(L.row, m->row_ptr.data(), sizeof(int) * m->row_ptr.size());
+        put(L.val, m->val.data(), sizeof(double) * m->val.size());
+        if (staged(m)) {
+            put(L.lcol, m->lcol.data(), sizeof(int) * m->lcol.size());
+            put(L.boff, m->blk_off.data(), sizeof(int) * m->blk_off.size());
+            put(L.bcols, m->blk_cols.data(), sizeof(int) * m->blk_cols.size());
+        } else {
+            put(L.col, m->col.data(), sizeof(int) * m->col.size());
+        }
+        if (e == hipSuccess) S.holds = m->id;
+    }
+    if (e == hipSuccess) {
+        const bool st = staged(m);
+        DevW w{(const int *)(S.ptr + L.row), st ? nullptr : (const int *)(S.ptr + L.col), st ? (const int *)(S.ptr + L.lcol) : nullptr,
+               st ? (const int *)(S.ptr + L.boff) : nullptr, st ? (const int *)(S.ptr + L.bcols) : nullptr, (const double *)(S.ptr + L.val)};
+        e = launch(m, w, xc_dev, xf_dev, n_frames);
+    }
     if (e != hipSuccess) { m->err = std::string("HIP: ") + hipGetErrorString(e); return IPC_E_DEVICE; }
     return IPC_OK;
 }
@@ -451,11 +552,11 @@ extern "C" int ipc_dualmesh_time(ipc_dualmesh *m, const double *xc_dev, double *
     if (!xc_dev || !xf_dev || n_frames < 1 || reps < 1 || !avg_us) { m->err = "invalid timing arguments"; return IPC_E_INVALID; }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = upload(m);
-    if (e == hipSuccess) e = launch(m, xc_dev, xf_dev, n_frames);   // warm
+    if (e == hipSuccess) e = launch(m, owned(m), xc_dev, xf_dev, n_frames);   // warm
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipEventRecord(e0, m->stream);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch(m, xc_dev, xf_dev, n_frames);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch(m, owned(m), xc_dev, xf_dev, n_frames);
     if (e == hipSuccess) e = hipEventRecord(e1, m->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;

@@ -76,6 +76,18 @@ class DualMesh:
         self._check(lib().ipc_dualmesh_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), x.shape[0]))
         return out[0] if single else out
 
+    def apply_noalloc(self, xc, out):
+        """As apply, through the entry point that allocates nothing (W staged
+        in the library's fixed device array); ``out`` is required."""
+        import torch
+        if not (xc.is_cuda and xc.dtype == torch.float64 and xc.is_contiguous() and xc.dim() == 3):
+            raise ValueError("xc must be a contiguous float64 CUDA tensor of shape (frames, N_c, 3)")
+        if xc.shape[1:] != (self.n_coarse, 3) or out.shape != (xc.shape[0], self.n_fine, 3) or not out.is_contiguous():
+            raise ValueError("shape mismatch")
+        self._check(lib().ipc_dualmesh_apply_noalloc(self._h, ctypes.c_void_p(xc.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                                     xc.shape[0]))
+        return out
+
     def time(self, xc, out, reps=20):
         """Average launch duration (us) of apply and its algorithmic bytes."""
         us, by = ctypes.c_double(), ctypes.c_double()
