@@ -136,12 +136,15 @@ enum {
                              did not fit the matrix pattern                      */
     IPC_Q_NPAIRS = 8,     /* active barrier pairs of the last assembly         */
     IPC_Q_NTETS_EXT = 9,  /* tetrahedra of all scenes (external numbering)     */
-    IPC_Q_COARSE = 10     /* 1 when the PCG preconditioner applies its coarse
+    IPC_Q_COARSE = 10,    /* 1 when the PCG preconditioner applies its coarse
                              correction: for contexts of at least 32768 nodes
                              (its cost per iteration is a fixed few
                              microseconds); the environment variable
                              IPC_PCG_COARSE = 0 or 1, read at ipc_create,
                              switches it off or on whatever the size       */
+    IPC_Q_WS_BYTES = 11,  /* workspace size of an ipc_create_ws context (0: the
+                             context allocates its own memory)                */
+    IPC_Q_WS_PEAK = 12    /* the most workspace bytes in use at once so far    */
 };
 
 /* Flags of ipc_energy_grad_hess. */
@@ -153,6 +156,34 @@ enum { IPC_PSD_PROJECT = 1u, IPC_WITH_FRICTION = 2u };
  * the current device.  Validates the scene data on the host; allocates the
  * device memory the context needs (released by ipc_destroy). */
 int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_stream, ipc_ctx **out);
+
+/* Capacity of a context over a caller's workspace (ipc_create_ws): the most
+ * active contact pairs (point-triangle plus edge-edge, all scenes together)
+ * any evaluation meets, the most swept candidates of one broad phase (per
+ * kind), and the most pair-local contact blocks of one assembly (the blocks
+ * of pairs whose vertices do not all share one mesh's pattern, before equal
+ * blocks are merged; up to 16 per pair of FEM vertices and 64 or more when
+ * affine bodies are involved). */
+typedef struct ipc_capacity {
+    int64_t max_pairs, max_candidates, max_local_blocks;
+} ipc_capacity;
+
+/* The device bytes a context over these scenes takes at this capacity (an
+ * upper bound from the scenes' sizes), after the host checks of ipc_create
+ * (IPC_E_INVALID with a message from ipc_last_error(NULL)).  Host work only:
+ * no HIP call. */
+int ipc_plan(const ipc_scene_desc *scenes, int n_scenes, const ipc_capacity *cap, size_t *workspace_bytes);
+
+/* ipc_create over a caller-owned device workspace of workspace_bytes (256-byte
+ * aligned, at least what ipc_plan returned): every device buffer of the
+ * context is a range of it, and neither creation nor any later call makes a
+ * hipMalloc (the library still creates a private stream for graph capture
+ * and pinned host staging).  The workspace must outlive the context.  A call
+ * whose contact state exceeds the capacity returns IPC_E_CAPACITY with the
+ * count it met (the context is then left in the state of that call's start
+ * for a step, and should be recreated with a larger capacity). */
+int ipc_create_ws(const ipc_scene_desc *scenes, int n_scenes, const ipc_capacity *cap, void *workspace_dev,
+                  size_t workspace_bytes, void *hip_stream, ipc_ctx **out);
 int ipc_destroy(ipc_ctx *ctx);
 const char *ipc_last_error(const ipc_ctx *ctx);
 int ipc_query(const ipc_ctx *ctx, int what, int64_t *value);
@@ -173,6 +204,18 @@ int ipc_set_timestep(ipc_ctx *ctx, const double *h_host);
  * measured from the step start) and runs Newton again from it; the stats
  * count the iterations of all passes.  ipc_step_vjp needs 1 pass. */
 int ipc_set_friction_lag(ipc_ctx *ctx, int passes);
+/* Adaptive barrier stiffness (a robustness variant of the barrier term of
+ * Eq. (3), whose contact model Sec. III-C.1 takes from IPC; the doubling rule
+ * is IPC's).  Off by default.  With frac > 0: after every accepted Newton
+ * update of a scene, its kappa doubles when the smallest distance d over its
+ * active pairs is below frac * dhat and below that of its previous iterate
+ * (the step start for a step's first update), capped at factor * kappa0,
+ * kappa0 being the scene's kappa at this call.  kappa carries over to later
+ * steps (ipc_scene_scalars reports it after each step) and enters the
+ * friction lag from the next step on.  frac = 0 switches the rule off; kappa
+ * keeps its value.  IPC_E_INVALID for frac < 0, factor < 1 or non-finite
+ * values.  ipc_step_vjp refuses contexts with the rule on.  Synchronous. */
+int ipc_set_kappa_adaptive(ipc_ctx *ctx, double frac, double factor);
 
 /* State in the external layout (ndof doubles each).  ydot may be NULL on get. */
 int ipc_get_state(ipc_ctx *ctx, double *y_dev, double *ydot_dev);
@@ -195,6 +238,21 @@ int ipc_begin_step(ipc_ctx *ctx, const double *targets_dev);
  * Returns IPC_E_INTERSECTING (and E = +inf) when a pair has zero distance. */
 int ipc_energy_grad_hess(ipc_ctx *ctx, const double *y_dev, double *E_dev, double *g_dev,
                          const double *v_dev, double *Hv_dev, uint32_t flags);
+
+/* The Hessian of the potential of the step set up by ipc_begin_step(), at any
+ * y_dev (external layout), as one block-CSR matrix over external nodes (a node
+ * is 3 consecutive DOFs: a FEM vertex, or one of a body's p, A[:,0], A[:,1],
+ * A[:,2]): row_ptr_dev[nodes + 1], col_dev[nnzb], val_dev[9 nnzb] (each 3x3
+ * block row-major), columns ascending in every row.  It is the matrix the
+ * Newton step solves with: inertia, elasticity, orthogonality, springs,
+ * barrier and (with IPC_WITH_FRICTION) lagged friction, each term's block
+ * projected to PSD with IPC_PSD_PROJECT; the contact blocks that the
+ * product keeps pair-local are merged in.  All arrays are device arrays the
+ * caller owns; *nnzb_out receives the block count.  With cap_blocks below it
+ * (or col_dev / val_dev NULL) only row_ptr_dev is written and the call
+ * returns IPC_E_CAPACITY; IPC_E_INTERSECTING as ipc_energy_grad_hess. */
+int ipc_hessian_bsr(ipc_ctx *ctx, const double *y_dev, uint32_t flags, int32_t *row_ptr_dev, int32_t *col_dev, double *val_dev,
+                    int64_t cap_blocks, int64_t *nnzb_out);
 
 /* Active contact pairs at y_dev for one scene, as vertex tuples in the scene's
  * own vertex numbering (FEM vertices, then body surface vertices, then static

@@ -66,6 +66,7 @@ def lib():
         L.or_gradient.argtypes = [P, D, D, D]
         L.or_hessian_matvec.argtypes = [P, D, ctypes.c_int, D, D]
         L.or_hessian_matvec_abs.argtypes = [P, D, ctypes.c_int, ctypes.c_int, D, D, D]
+        L.or_hessian_dense.argtypes = [P, D, ctypes.c_int, ctypes.c_int, D, D]
         L.or_pairs.restype = ctypes.c_int
         L.or_pairs.argtypes = [P, D, I, ctypes.c_int, I, ctypes.c_int, I, I]
         L.or_ccd.restype = ctypes.c_double
@@ -91,6 +92,10 @@ def lib():
         L.or_set_timestep.restype = None
         L.or_set_friction_lag.argtypes = [P, ctypes.c_int]
         L.or_set_friction_lag.restype = None
+        L.or_set_kappa_adaptive.argtypes = [P, ctypes.c_double, ctypes.c_double]
+        L.or_set_kappa_adaptive.restype = None
+        L.or_set_kappa.argtypes = [P, ctypes.c_double]
+        L.or_set_kappa.restype = None
         L.or_dG_dyn_T.argtypes = [P, D, D, D, D, D, D]
         L.or_dG_dtheta_T.restype = ctypes.c_double
         L.or_dG_dtheta_T.argtypes = [P, D, D, D, D, D, D]
@@ -132,7 +137,8 @@ def scene_params(sc):
     g = sc["g"]
     return [float(sc["h"]), float(g[0]), float(g[1]), float(g[2]), float(sc["dhat"]), float(sc["kappa"]),
             float(sc["mu"]), float(sc["eps_v"]), float(sc["newton_tol"]), float(sc["max_newton"]),
-            float(sc["pcg_tol"]), float(sc["max_pcg"]), float(sc["ccd_s"])]
+            float(sc["pcg_tol"]), float(sc["max_pcg"]), float(sc["ccd_s"])] + \
+        [float(v) for v in np.asarray(sc.get("half_space", np.zeros(4)), np.float64).ravel()[:4]]
 
 
 class Oracle:
@@ -239,6 +245,13 @@ class Oracle:
                                     _d(scale) if with_abs else None)
         return (out, scale) if with_abs else out
 
+    def hessian_dense(self, y, project=True, friction=True):
+        """(H, |H|-scale) as dense ndof x ndof arrays (small scenes only)."""
+        y = _f64(y)
+        H = np.zeros((self.ndof, self.ndof)); A = np.zeros((self.ndof, self.ndof))
+        lib().or_hessian_dense(self._h, _d(y), int(project), int(friction), _d(H), _d(A))
+        return H, A
+
     def pairs(self, y, cap=1 << 22):
         y = _f64(y)
         while True:
@@ -279,6 +292,16 @@ class Oracle:
 
     def set_friction_lag(self, passes):
         lib().or_set_friction_lag(self._h, int(passes))
+
+    def set_kappa_adaptive(self, frac, factor=100.0):
+        """Adaptive barrier stiffness: kappa doubles after an accepted Newton
+        update whose smallest active-pair distance is below frac dhat and
+        below the previous iterate's, capped at factor times the kappa at
+        this call (frac = 0: off)."""
+        lib().or_set_kappa_adaptive(self._h, float(frac), float(factor))
+
+    def set_kappa(self, kappa):
+        lib().or_set_kappa(self._h, float(kappa))
 
     def step_adaptive(self, max_depth=3):
         """One step with sub-stepping on failure (the recovery policy of the

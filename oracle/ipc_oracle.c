@@ -165,6 +165,15 @@ struct OScene {
     int *driven;
     int *joint_spring;           /* joint slot -> spring whose b-side point follows the joint reference */
     int lag_passes;              /* friction lag passes per step (>= 1) */
+    /* adaptive barrier stiffness: kappa doubles after an accepted Newton
+     * update whose smallest active-pair distance is below kappa_frac dhat and
+     * below the previous iterate's, up to kappa_factor kappa0 (off when
+     * kappa_frac is 0) */
+    double kappa_frac, kappa_factor, kappa0, dmin_prev;
+    /* analytic half-space ground {x : n . x >= c} (n unit) against every
+     * dynamic surface vertex; hs_on = 0 when the scene has none */
+    int hs_on;
+    double hs_n[3], hs_c;
     double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
     int max_newton, max_pcg;
     /* precompute (C1) */
@@ -280,7 +289,10 @@ OScene *or_create(const int *sz, const void *const *pp, const double *prm)
     s->dhat = prm[4]; s->kappa = prm[5]; s->mu = prm[6]; s->eps_v = prm[7];
     s->newton_tol = prm[8]; s->max_newton = (int)prm[9]; s->pcg_tol = prm[10];
     s->lag_passes = 1;
+    s->kappa_frac = 0.0; s->kappa_factor = 100.0; s->dmin_prev = INFINITY;
     s->max_pcg = (int)prm[11]; s->ccd_s = prm[12];
+    s->hs_n[0] = prm[13]; s->hs_n[1] = prm[14]; s->hs_n[2] = prm[15]; s->hs_c = prm[16];
+    s->hs_on = s->hs_n[0] != 0.0 || s->hs_n[1] != 0.0 || s->hs_n[2] != 0.0;
 
     /* C1: per-tet inverse rest shape matrix, volume, Lame parameters, lumped mass */
     s->Bm = xmalloc(D * 9 * s->nt); s->vol = xmalloc(D * s->nt);
@@ -390,6 +402,7 @@ OScene *or_create(const int *sz, const void *const *pp, const double *prm)
     }
     double gn = sqrt(dot3(s->g, s->g));
     if (s->kappa <= 0.0) s->kappa = 10.0 * s->mbar * gn * s->h * s->h / s->dhat;
+    s->kappa0 = s->kappa;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = 0; i < s->nv; ++i)
         for (int k = 0; k < 3; ++k) { double x = s->X[3 * i + k]; if (x < lo[k]) lo[k] = x; if (x > hi[k]) hi[k] = x; }
@@ -715,6 +728,16 @@ static double barrier_d2(double d, double dh)
     if (d >= dh) return 0.0;
     return -2.0 * log(d / dh) - 4.0 * (d - dh) / d + (d - dh) * (d - dh) / (d * d);
 }
+
+/* The signed distance of a point to the half-space's boundary plane,
+ * n . x - c (n unit), summed left to right. */
+static double hs_dist(const OScene *s, const double *x)
+{
+    return s->hs_n[0] * x[0] + s->hs_n[1] * x[1] + s->hs_n[2] * x[2] - s->hs_c;
+}
+
+/* Whether contact vertex c moves (a FEM or body vertex, not static). */
+static int cv_dynamic(const OScene *s, int c) { return c < s->nv + s->nbv; }
 
 void or_barrier3(double d, double dh, double *b3)
 {
@@ -1295,6 +1318,30 @@ static double eval_ip(OScene *s, const double *y, const IVec *apt, const IVec *a
             }
         }
     }
+    /* the half-space: kappa b(d) per dynamic surface vertex, d = n . x - c;
+     * gradient kappa b'(d) n, Hessian kappa b''(d) n n^T (b'' > 0 below
+     * dhat, so the term is convex and needs no projection) */
+    if (s->hs_on)
+        for (int k = 0; k < s->nsurf; ++k) {
+            int c = s->surf_v[k];
+            if (!cv_dynamic(s, c)) continue;
+            double d = hs_dist(s, P3(xw, c));
+            if (d <= 0.0) { inf = 1; continue; }
+            if (d >= s->dhat) continue;
+            Ebar += s->kappa * barrier(d, s->dhat);
+            OPt p = cv_point(s, c);
+            if (g) {
+                double b1 = s->kappa * barrier_d1(d, s->dhat), gp[3];
+                for (int q = 0; q < 3; ++q) gp[q] = b1 * s->hs_n[q];
+                scatter_grad(&p, gp, g, gabs);
+            }
+            if (T) {
+                double b2 = s->kappa * barrier_d2(d, s->dhat);
+                memset(&tm, 0, sizeof tm); tm.np = 1; tm.pt[0] = p;
+                for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) tm.H[3 * i + j] = b2 * s->hs_n[i] * s->hs_n[j];
+                terms_push(T, &tm);
+            }
+        }
     /* friction (C10) */
     if (with_friction)
         for (int k = 0; k < s->nlag; ++k) {
@@ -1355,6 +1402,32 @@ static void terms_matvec(const OScene *s, const Terms *T, const double *v, doubl
     }
 }
 
+/* The dense Hessian (ndof x ndof, row-major) of the terms T, P^T H P summed
+ * over terms; Habs (nullable) the same sum of |P|^T |H| |P|. */
+static void terms_dense(const OScene *s, const Terms *T, double *H, double *Habs)
+{
+    size_t n = (size_t)s->ndof;
+    memset(H, 0, sizeof(double) * n * n);
+    if (Habs) memset(Habs, 0, sizeof(double) * n * n);
+    for (size_t k = 0; k < T->n; ++k) {
+        const OTerm *t = T->t + k;
+        int m = 3 * t->np;
+        for (int a = 0; a < t->np; ++a)
+            for (int qa = 0; qa < t->pt[a].n; ++qa)
+                for (int b = 0; b < t->np; ++b)
+                    for (int qb = 0; qb < t->pt[b].n; ++qb) {
+                        double w = t->pt[a].w[qa] * t->pt[b].w[qb];
+                        size_t r0 = 3 * (size_t)t->pt[a].node[qa], c0 = 3 * (size_t)t->pt[b].node[qb];
+                        for (int i = 0; i < 3; ++i)
+                            for (int j = 0; j < 3; ++j) {
+                                double h = t->H[(3 * a + i) * m + 3 * b + j];
+                                H[(r0 + i) * n + c0 + j] += w * h;
+                                if (Habs) Habs[(r0 + i) * n + c0 + j] += fabs(w) * fabs(h);
+                            }
+                    }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* friction lag (C10)                                                        */
 /* ------------------------------------------------------------------------ */
@@ -1370,7 +1443,7 @@ static void compute_lag_at(OScene *s, const double *ylag, const double *yref)
     IVec cpt = {0}, cee = {0}, apt = {0}, aee = {0};
     candidates(s, xw, xw, &cpt, &cee);
     active_pairs(s, xw, &cpt, &cee, &apt, &aee);
-    int n = (int)(apt.n / 2 + aee.n / 2);
+    int n = (int)(apt.n / 2 + aee.n / 2) + (s->hs_on ? s->nsurf : 0);
     s->lag = xmalloc(sizeof(OLag) * (size_t)(n ? n : 1));
     for (int kind = 0; kind < 2; ++kind) {
         const IVec *L = kind == 0 ? &apt : &aee;
@@ -1409,6 +1482,25 @@ static void compute_lag_at(OScene *s, const double *ylag, const double *yref)
             s->nlag++;
         }
     }
+    /* the half-space: a vertex closer than dhat at the lag state is one
+     * lagged contact with normal n, weights (1, 0, 0, 0) on the vertex itself
+     * and offset its reference position */
+    if (s->hs_on)
+        for (int k = 0; k < s->nsurf; ++k) {
+            int c = s->surf_v[k];
+            if (!cv_dynamic(s, c)) continue;
+            double d = hs_dist(s, P3(xw, c));
+            if (!(d > 0.0) || d >= s->dhat) continue;
+            OLag *lg = s->lag + s->nlag;
+            for (int q = 0; q < 4; ++q) { lg->cv[q] = c; lg->beta[q] = q == 0 ? 1.0 : 0.0; }
+            memcpy(lg->nrm, s->hs_n, 3 * sizeof(double));
+            memcpy(lg->rn, P3(xr ? xr : xw, c), 3 * sizeof(double));
+            lg->kind = 2;
+            lg->type = 0;
+            lg->ex = 0.0;
+            lg->lam = -s->kappa * barrier_d1(d, s->dhat);
+            s->nlag++;
+        }
     free(cpt.v); free(cee.v); free(apt.v); free(aee.v); free(xw); free(xr);
 }
 
@@ -1473,6 +1565,17 @@ void or_hessian_matvec_abs(OScene *s, const double *y, int project, int with_fri
     double *g = xmalloc(sizeof(double) * s->ndof);
     eval_ip(s, y, &apt, &aee, NULL, g, NULL, &T, project, with_friction);
     terms_matvec(s, &T, v, out, outabs);
+    free(g); free(T.t); free(apt.v); free(aee.v);
+}
+
+void or_hessian_dense(OScene *s, const double *y, int project, int with_friction, double *H, double *Habs)
+{
+    IVec apt = {0}, aee = {0};
+    pairs_at(s, y, &apt, &aee);
+    Terms T = {0};
+    double *g = xmalloc(sizeof(double) * s->ndof);
+    eval_ip(s, y, &apt, &aee, NULL, g, NULL, &T, project, with_friction);
+    terms_dense(s, &T, H, Habs);
     free(g); free(T.t); free(apt.v); free(aee.v);
 }
 
@@ -1617,6 +1720,21 @@ static double ccd_alpha(const OScene *s, const double *xw0, const double *xw1, c
             if (t < a) a = t;
         }
     }
+    /* the half-space: along x0 + t p the distance d0 + t (n . p) is linear,
+     * so the step at which it reaches the additive CCD's gap s d0 is exact */
+    if (s->hs_on)
+        for (int k = 0; k < s->nsurf; ++k) {
+            int c = s->surf_v[k];
+            if (!cv_dynamic(s, c)) continue;
+            const double *x0 = P3(xw0, c), *x1 = P3(xw1, c);
+            double p[3] = {x1[0] - x0[0], x1[1] - x0[1], x1[2] - x0[2]};
+            double d0 = hs_dist(s, x0);
+            double np = s->hs_n[0] * p[0] + s->hs_n[1] * p[1] + s->hs_n[2] * p[2];
+            if (np < 0.0) {
+                double t = (1.0 - s->ccd_s) * d0 / -np;
+                if (t < a) a = t;
+            }
+        }
     return a;
 }
 
@@ -1662,6 +1780,51 @@ void or_set_friction_lag(OScene *s, int passes)
     if (passes >= 1) s->lag_passes = passes;
 }
 
+/* The smallest distance over the pairs active at y (closer than dhat);
+ * INFINITY when none is. */
+static double min_active_distance(OScene *s, const double *y)
+{
+    IVec apt = {0}, aee = {0};
+    pairs_at(s, y, &apt, &aee);
+    double *xw = world_alloc(s, y);
+    double m2 = INFINITY;
+    for (int kind = 0; kind < 2; ++kind) {
+        const IVec *L = kind == 0 ? &apt : &aee;
+        for (size_t k = 0; k < L->n / 2; ++k) {
+            int cv[4]; double x[12];
+            pair_x(s, xw, kind, L->v[2 * k], L->v[2 * k + 1], cv, x);
+            double d2 = dist2_kind(kind, x, NULL);
+            if (d2 < m2) m2 = d2;
+        }
+    }
+    double m = sqrt(m2);
+    if (s->hs_on)   /* vertices closer than dhat to the half-space */
+        for (int k = 0; k < s->nsurf; ++k) {
+            int c = s->surf_v[k];
+            if (!cv_dynamic(s, c)) continue;
+            double d = hs_dist(s, P3(xw, c));
+            if (d < s->dhat && d < m) m = d > 0.0 ? d : 0.0;
+        }
+    free(xw); free(apt.v); free(aee.v);
+    return m;
+}
+
+/* Adaptive barrier stiffness (IPC's rule; a robustness variant of the
+ * barrier term of Eq. (3)): frac > 0 switches it on with kappa0 = the
+ * current kappa, frac = 0 off (kappa keeps its value); factor >= 1 caps
+ * kappa at factor kappa0. */
+void or_set_kappa_adaptive(OScene *s, double frac, double factor)
+{
+    if (frac >= 0.0) s->kappa_frac = frac;
+    if (factor >= 1.0) s->kappa_factor = factor;
+    s->kappa0 = s->kappa;
+}
+
+void or_set_kappa(OScene *s, double kappa)
+{
+    if (kappa > 0.0) s->kappa = s->kappa0 = kappa;
+}
+
 int or_step(OScene *s, const double *targets, OStats *st)
 {
     OStats loc; memset(&loc, 0, sizeof loc);
@@ -1674,6 +1837,7 @@ int or_step(OScene *s, const double *targets, OStats *st)
     memcpy(y, s->y, sizeof(double) * n);
     double thr = s->newton_tol * s->h * s->L;
     int status = 3;
+    if (s->kappa_frac > 0.0) s->dmin_prev = min_active_distance(s, y);
     /* friction lag passes: after a converged pass, the lag is taken again at
      * the solution (displacements still from the step start) and Newton
      * runs again from there */
@@ -1704,6 +1868,16 @@ int or_step(OScene *s, const double *targets, OStats *st)
         IVec cpt = {0}, cee = {0};
         candidates(s, xw0, xw1, &cpt, &cee);
         double alpha = ccd_alpha(s, xw0, xw1, &cpt, &cee);
+        /* the energy the trials are compared with: E(y) over the active pairs
+         * taken from the same candidate list as the trials', summed in the
+         * same order, so that a decrease smaller than the sums' rounding is
+         * not lost to a change of summation order */
+        {
+            IVec cp0 = {0}, ce0 = {0};
+            active_pairs(s, xw0, &cpt, &cee, &cp0, &ce0);
+            E0 = eval_ip(s, y, &cp0, &ce0, NULL, NULL, NULL, NULL, 0, 1);
+            free(cp0.v); free(ce0.v);
+        }
         free(xw0); free(xw1);
         int h;
         double E1 = INFINITY;
@@ -1723,6 +1897,14 @@ int or_step(OScene *s, const double *targets, OStats *st)
         if (alpha < loc.alpha_min) loc.alpha_min = alpha;
         memcpy(y, yt, sizeof(double) * n);
         loc.energy = E1;
+        if (s->kappa_frac > 0.0) {
+            double d = min_active_distance(s, y);
+            if (d < s->kappa_frac * s->dhat && d < s->dmin_prev) {
+                double k2 = 2.0 * s->kappa, kmax = s->kappa_factor * s->kappa0;
+                s->kappa = k2 < kmax ? k2 : kmax;
+            }
+            s->dmin_prev = d;
+        }
     }
     }
     for (int i = 0; i < n; ++i) s->ydot[i] = (y[i] - s->y[i]) / s->h;
@@ -1785,6 +1967,37 @@ static double friction_lag_vjp(const OScene *s, const double *xw, const double *
     double ea = s->eps_v * s->h, dh = s->dhat, wgf = 0.0;
     for (int k = 0; k < s->nlag; ++k) {
         const OLag *L = s->lag + k;
+        if (L->kind == 2) {
+            /* the half-space: the normal is fixed, lam = -kappa b'(n . x^n - c)
+             * and u = P (x - x^n), so d lam / d x^n = -kappa b'' n and
+             * d u / d x^n = -P */
+            const double *xv = P3(xw, L->cv[0]), *xnv = P3(xwn, L->cv[0]), *n = s->hs_n;
+            OPt pt = cv_point(s, L->cv[0]);
+            double W[3], D[3], u[3];
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int q = 0; q < pt.n; ++q) acc += pt.w[q] * w[3 * (size_t)pt.node[q] + c];
+                W[c] = acc;
+                D[c] = xv[c] - xnv[c];
+            }
+            double d = hs_dist(s, xnv), b1 = barrier_d1(d, dh), b2 = barrier_d2(d, dh), lam = -s->kappa * b1;
+            double nD = dot3(n, D);
+            for (int c = 0; c < 3; ++c) u[c] = D[c] - n[c] * nD;
+            double sg = sqrt(dot3(u, u));
+            double f1s = sg < ea ? 2.0 / ea - sg / (ea * ea) : 1.0 / sg;
+            double df1s = sg < ea ? -1.0 / (ea * ea) : -1.0 / (sg * sg);
+            double Wu = dot3(W, u), psi = f1s * Wu, dpsi_du[3];
+            for (int c = 0; c < 3; ++c) dpsi_du[c] = f1s * W[c] + (sg > 0.0 ? Wu * df1s * u[c] / sg : 0.0);
+            wgf += lam * psi;
+            for (int c = 0; c < 3; ++c) {
+                double du[3];
+                for (int i = 0; i < 3; ++i) du[i] = -((i == c ? 1.0 : 0.0) - n[i] * n[c]);
+                double dlam = -s->kappa * b2 * n[c];
+                double dphi = s->mu * (dlam * psi + lam * dot3(dpsi_du, du));
+                for (int q = 0; q < pt.n; ++q) out[3 * (size_t)pt.node[q] + c] += pt.w[q] * dphi;
+            }
+            continue;
+        }
         double x[12], xn[12], wv[12];
         OPt pts[4];
         for (int a = 0; a < 4; ++a) {

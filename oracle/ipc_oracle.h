@@ -13,8 +13,10 @@
  *                body_ext, body_obj, bv_xbar, bv_body, btri, sv_x, stri,
  *                obj_kind, excl, sp_ka, sp_ia, sp_xa, sp_kb, sp_ib, sp_xb,
  *                sp_k, driven_body, joint_spring (layouts as in the scene dict)
- *   params[13] = h, gx, gy, gz, dhat, kappa(0 = automatic), mu, eps_v,
- *                newton_tol, max_newton, pcg_tol, max_pcg, ccd_s
+ *   params[17] = h, gx, gy, gz, dhat, kappa(0 = automatic), mu, eps_v,
+ *                newton_tol, max_newton, pcg_tol, max_pcg, ccd_s,
+ *                nx, ny, nz, c: an analytic half-space ground {x : n . x >= c}
+ *                (n unit) against every moving surface vertex; n = 0: none
  * All inputs are copied.  The DOF vector is y = [FEM vertices xyz ; per body
  * (p, A[:,0], A[:,1], A[:,2])], i.e. node n owns y[3n..3n+2], body b owns the
  * four nodes nv+4b .. nv+4b+3.
@@ -71,6 +73,9 @@ void    or_hessian_matvec(OScene *s, const double *y, int project, const double 
  * and cancellations form that entry. */
 void    or_hessian_matvec_abs(OScene *s, const double *y, int project, int with_friction, const double *v, double *out,
                               double *outabs);
+/* The Hessian as a dense ndof x ndof row-major matrix (small scenes), and in
+ * Habs (nullable) the same sum with every factor's absolute value. */
+void    or_hessian_dense(OScene *s, const double *y, int project, int with_friction, double *H, double *Habs);
 /* Active pair set at y as vertex tuples (PT: v,t0,t1,t2 ; EE: a0,a1,b0,b1),
  * canonical order.  Returns 0, or -1 when a capacity is too small. */
 int     or_pairs(OScene *s, const double *y, int *pt, int cap_pt, int *ee, int cap_ee,
@@ -115,6 +120,14 @@ void    or_set_timestep(OScene *s, double h);
 /* Friction lag passes per step (default 1): after a converged pass the lag
  * is retaken at the solution, displacements still from the step start. */
 void    or_set_friction_lag(OScene *s, int passes);
+/* Adaptive barrier stiffness (off by default): after every accepted Newton
+ * update, kappa doubles when the smallest active-pair distance d is below
+ * frac dhat and below that of the previous iterate (the step start for the
+ * first update), up to factor kappa0; kappa0 is kappa when this is called,
+ * and kappa carries over to later steps.  frac = 0 switches it off. */
+void    or_set_kappa_adaptive(OScene *s, double frac, double factor);
+/* Set kappa (> 0) and kappa0 to a value. */
+void    or_set_kappa(OScene *s, double kappa);
 void    or_dG_dyn_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,
                     const double *y_next, const double *w, double *out);
 double  or_dG_dtheta_T(OScene *s, const double *y_prev, const double *yd_prev, const double *targets,

@@ -35,10 +35,28 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-class Sim:
-    """A context over ``scenes`` (a scene dict or a list of them)."""
+def plan(scenes, capacity):
+    """Device bytes of a context over ``scenes`` created over a workspace with
+    ``capacity`` = (max_pairs, max_candidates, max_local_blocks) (host work only)."""
+    if isinstance(scenes, dict):
+        scenes = [scenes]
+    keep = []
+    arr = (_lib.SceneDesc * len(scenes))(*[_lib.make_desc(s, keep) for s in scenes])
+    cap = _lib.Capacity(*[int(x) for x in capacity])
+    out = ctypes.c_size_t()
+    rc = lib().ipc_plan(arr, len(scenes), ctypes.byref(cap), ctypes.byref(out))
+    if rc != 0:
+        raise IPCError(rc, lib().ipc_last_error(None).decode())
+    return out.value
 
-    def __init__(self, scenes, device="cuda"):
+
+class Sim:
+    """A context over ``scenes`` (a scene dict or a list of them).  With
+    ``capacity`` = (max_pairs, max_candidates, max_local_blocks) the context is
+    created over a workspace that torch allocates (``workspace_bytes``, default
+    the planned size): the library then allocates no device memory."""
+
+    def __init__(self, scenes, device="cuda", capacity=None, workspace_bytes=None):
         torch = _torch()
         if isinstance(scenes, dict):
             scenes = [scenes]
@@ -49,7 +67,15 @@ class Sim:
         arr = (_lib.SceneDesc * len(self.scenes))(*[_lib.make_desc(s, keep) for s in self.scenes])
         h = ctypes.c_void_p()
         self._stream = torch.cuda.current_stream(self.device)
-        rc = L.ipc_create(arr, len(self.scenes), ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
+        self._ws = None
+        if capacity is None:
+            rc = L.ipc_create(arr, len(self.scenes), ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
+        else:
+            nbytes = plan(self.scenes, capacity) if workspace_bytes is None else int(workspace_bytes)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)   # torch owns the memory
+            cap = _lib.Capacity(*[int(x) for x in capacity])
+            rc = L.ipc_create_ws(arr, len(self.scenes), ctypes.byref(cap), ctypes.c_void_p(self._ws.data_ptr()), nbytes,
+                                 ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
         if rc != 0:
             raise IPCError(rc, L.ipc_last_error(None).decode())
         self._h = h
@@ -88,6 +114,23 @@ class Sim:
         if n is not None and t.numel() != n:
             raise ValueError(f"expected {n} values, got {t.numel()}")
         return t
+
+    def hessian_bsr(self, y, project=True, friction=True):
+        """The assembled Hessian at y as (row_ptr, col, val) device tensors
+        (external nodes, 3x3 blocks, val of shape (nnzb, 3, 3))."""
+        torch = _torch()
+        y = self._as_dev(y, self.ndof)
+        nodes = self.ndof // 3
+        rp = torch.empty(nodes + 1, dtype=torch.int32, device=self.device)
+        n = ctypes.c_int64()
+        flags = (IPC_PSD_PROJECT if project else 0) | (IPC_WITH_FRICTION if friction else 0)
+        rc = lib().ipc_hessian_bsr(self._h, _ptr(y), flags, ctypes.c_void_p(rp.data_ptr()), None, None, 0, ctypes.byref(n))
+        self._check(rc, allow=(_lib.IPC_E_CAPACITY,))
+        col = torch.empty(max(n.value, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty((max(n.value, 1), 3, 3), dtype=torch.float64, device=self.device)
+        self._check(lib().ipc_hessian_bsr(self._h, _ptr(y), flags, ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                                          ctypes.c_void_p(val.data_ptr()), n.value, ctypes.byref(n)))
+        return rp, col[:n.value], val[:n.value]
 
     def scene_scalars(self, s=0):
         k, L, t = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -182,6 +225,13 @@ class Sim:
     def set_friction_lag(self, passes):
         """Friction lag passes per step (1: lagged once at the step start)."""
         self._check(lib().ipc_set_friction_lag(self._h, int(passes)))
+
+    def set_kappa_adaptive(self, frac, factor=100.0):
+        """Adaptive barrier stiffness: after an accepted Newton update a
+        scene's kappa doubles when its smallest active-pair distance is below
+        frac dhat and below the previous iterate's, capped at factor times
+        its kappa at this call (frac = 0: off)."""
+        self._check(lib().ipc_set_kappa_adaptive(self._h, float(frac), float(factor)))
 
     def step_adaptive(self, max_depth=3):
         """One step of a single-scene context with sub-stepping on failure:

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "CAPACITY", 3: "NOT_CONVERGED", 4: "LI
 IPC_PSD_PROJECT = 1
 IPC_WITH_FRICTION = 2
 
-Q_NDOF, Q_NSCENES, Q_NDRIVEN, Q_NTRI, Q_NEDGE, Q_NNODES, Q_NTETS, Q_NLOCAL, Q_NPAIRS, Q_NTETS_EXT, Q_COARSE = range(11)
+Q_NDOF, Q_NSCENES, Q_NDRIVEN, Q_NTRI, Q_NEDGE, Q_NNODES, Q_NTETS, Q_NLOCAL, Q_NPAIRS, Q_NTETS_EXT, Q_COARSE, Q_WS_BYTES, Q_WS_PEAK = range(13)
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int32)
@@ -68,6 +68,10 @@ def lib():
         L = ctypes.CDLL(SO_PATH)
         P = ctypes.c_void_p
         L.ipc_create.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_int, P, ctypes.POINTER(P)]
+        L.ipc_plan.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_int, ctypes.POINTER(Capacity), ctypes.POINTER(ctypes.c_size_t)]
+        L.ipc_create_ws.argtypes = [ctypes.POINTER(SceneDesc), ctypes.c_int, ctypes.POINTER(Capacity), P, ctypes.c_size_t, P,
+                                    ctypes.POINTER(P)]
+        L.ipc_hessian_bsr.argtypes = [P, P, ctypes.c_uint32, P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.ipc_destroy.argtypes = [P]
         L.ipc_last_error.restype = ctypes.c_char_p
         L.ipc_last_error.argtypes = [P]
@@ -90,6 +94,7 @@ def lib():
         L.ipc_autotune.argtypes = [P, ctypes.c_int, _D, _I]
         L.ipc_set_timestep.argtypes = [P, _D]
         L.ipc_set_friction_lag.argtypes = [P, ctypes.c_int]
+        L.ipc_set_kappa_adaptive.argtypes = [P, ctypes.c_double, ctypes.c_double]
         L.ipc_dualmesh_create.argtypes = [_I, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)]
         L.ipc_dualmesh_destroy.argtypes = [P]
         L.ipc_dualmesh_destroy.restype = None
@@ -106,10 +111,15 @@ def lib():
         for n in ("ipc_create", "ipc_destroy", "ipc_query", "ipc_scene_scalars", "ipc_get_state", "ipc_set_state",
                   "ipc_begin_step", "ipc_energy_grad_hess", "ipc_get_pairs", "ipc_ccd", "ipc_pcg", "ipc_step",
                   "ipc_set_params", "ipc_step_vjp", "ipc_profile", "ipc_kernel_time", "ipc_time_kernel",
-                  "ipc_autotune", "ipc_set_timestep", "ipc_set_friction_lag"):
+                  "ipc_autotune", "ipc_set_timestep", "ipc_set_friction_lag", "ipc_set_kappa_adaptive"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+class Capacity(ctypes.Structure):
+    """ipc_capacity of include/ipc.h."""
+    _fields_ = [("max_pairs", ctypes.c_int64), ("max_candidates", ctypes.c_int64), ("max_local_blocks", ctypes.c_int64)]
 
 
 def make_desc(sc, keep):

@@ -7,6 +7,7 @@
 // pair counts (to size buffers), the Newton measure and line-search energies.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -269,7 +270,7 @@ void eval_energy(ipc_ctx *c, const double *y, bool from_candidates)
     Dev &D = c->d;
     hipStream_t st = c->stream;
     launch_world(c, y, D.xw.p);
-    hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
+    hipLaunchKernelGGL(k_fill_int_api, dim3(blocks_for(c->n_scenes)), dim3(BLOCK), 0, st, c->n_scenes, D.inf_flag.p, 0);
     launch_node_inertia(c, y, nullptr, D.part_node.p);
     launch_fem(c, 0, y, nullptr, false, D.part_tet.p, D.h2s.p);
     launch_body(c, 0, y, nullptr, false, D.body_part.p, D.h2s.p);
@@ -317,7 +318,7 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     Dev &D = c->d;
     hipStream_t st = c->stream;
     launch_world(c, y, D.xw.p);
-    hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.inf_flag.p, 0);
+    hipLaunchKernelGGL(k_fill_int_api, dim3(blocks_for(c->n_scenes)), dim3(BLOCK), 0, st, c->n_scenes, D.inf_flag.p, 0);
     // inertia writes g; the FEM gathers then write the matrix values (constant
     // part + tets) and add the tets' gradients; the bodies add their own
     // nodes; springs, barrier and friction pairs add through sorted run sums
@@ -360,8 +361,8 @@ void begin_step_impl(ipc_ctx *c, const double *targets_dev)
     pairs_from_scratch(c, D.y.p);
     launch_lag(c, D.xw.p);
     c->n_lag_pt = c->n_pt;
-    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_PT), seg_ptr(c, R_LPT));
-    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_EE), seg_ptr(c, R_LEE));
+    hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes + 1, seg_ptr(c, R_PT), seg_ptr(c, R_LPT));
+    hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes + 1, seg_ptr(c, R_EE), seg_ptr(c, R_LEE));
     c->step_ready = true;
 }
 
@@ -435,9 +436,15 @@ using namespace ipc;
 // ---------------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------------
+namespace ipc {
+thread_local Arena *g_arena = nullptr;
+}
+
 template <class F>
 static int guard(ipc_ctx *c, F f)
 {
+    // device buffers of a workspace context come from its workspace
+    ArenaScope scope(c && c->ws.base ? &c->ws : nullptr);
     try {
         f();
         return IPC_OK;
@@ -453,32 +460,104 @@ static int guard(ipc_ctx *c, F f)
     }
 }
 
+// run-time options of a new context (environment variables read at creation)
+static void read_options(ipc_ctx *c)
+{
+    const char *ng = std::getenv("IPC_NO_GRAPH");
+    c->use_graphs = !(ng && ng[0] == '1');
+    const char *nl = std::getenv("IPC_SPMV_LANES");
+    if (nl) {
+        int L = std::atoi(nl);
+        if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) {
+            c->spmv_lanes = L;
+            c->spmv_lanes_forced = true;
+        }
+    }
+    const char *nc = std::getenv("IPC_PCG_COARSE");   // 0: never, 1: always, else by size and the autotuner
+    c->coarse = !(nc && nc[0] == '0');
+    c->coarse_forced = nc && nc[0] == '1';
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
+}
+
+// scene checks on the host, before any HIP call
+static int precheck(const ipc_scene_desc *scenes, int n_scenes)
+{
+    try {
+        validate_scenes(scenes, n_scenes);
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        return e.code;
+    }
+    return IPC_OK;
+}
+
 extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_stream, ipc_ctx **out)
 {
     if (!out) return IPC_E_INVALID;
     *out = nullptr;
-    if (!scenes || n_scenes < 1) { g_create_error = "need at least one scene"; return IPC_E_INVALID; }
+    if (int rc = precheck(scenes, n_scenes)) return rc;
     ipc_ctx *c = new ipc_ctx;
     c->stream = (hipStream_t)hip_stream;
-    {
-        const char *ng = std::getenv("IPC_NO_GRAPH");
-        c->use_graphs = !(ng && ng[0] == '1');
-        const char *nl = std::getenv("IPC_SPMV_LANES");
-        if (nl) {
-            int L = std::atoi(nl);
-            if (L == 1 || L == 2 || L == 4 || L == 8 || L == 16) {
-                c->spmv_lanes = L;
-                c->spmv_lanes_forced = true;
-            }
-        }
-        const char *nc = std::getenv("IPC_PCG_COARSE");   // 0: never, 1: always, else by size and the autotuner
-        c->coarse = !(nc && nc[0] == '0');
-        c->coarse_forced = nc && nc[0] == '1';
-        if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
-    }
+    read_options(c);
     int rc = guard(c, [&] {
         create_context(c, scenes, n_scenes);
         setup_after_create(c);
+    });
+    if (rc != IPC_OK) {
+        g_create_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return IPC_OK;
+}
+
+static bool caps_ok(const ipc_capacity *cap)
+{
+    return cap && cap->max_pairs >= 0 && cap->max_candidates >= 0 && cap->max_local_blocks >= 0 &&
+           16 * std::max(cap->max_pairs, cap->max_candidates) < (int64_t)INT32_MAX && cap->max_local_blocks < (int64_t)INT32_MAX;
+}
+
+extern "C" int ipc_plan(const ipc_scene_desc *scenes, int n_scenes, const ipc_capacity *cap, size_t *workspace_bytes)
+{
+    if (!workspace_bytes) return IPC_E_INVALID;
+    *workspace_bytes = 0;
+    if (!caps_ok(cap)) { g_create_error = "invalid capacity"; return IPC_E_INVALID; }
+    if (int rc = precheck(scenes, n_scenes)) return rc;
+    try {
+        ipc_ctx tmp;   // the host half of the creation only: no HIP call
+        const int64_t caps[3] = {cap->max_pairs, cap->max_candidates, cap->max_local_blocks};
+        create_context(&tmp, scenes, n_scenes, caps, workspace_bytes);
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        g_create_error = e.what();
+        return IPC_E_INVALID;
+    }
+    return IPC_OK;
+}
+
+extern "C" int ipc_create_ws(const ipc_scene_desc *scenes, int n_scenes, const ipc_capacity *cap, void *workspace_dev,
+                             size_t workspace_bytes, void *hip_stream, ipc_ctx **out)
+{
+    if (!out) return IPC_E_INVALID;
+    *out = nullptr;
+    if (!caps_ok(cap)) { g_create_error = "invalid capacity"; return IPC_E_INVALID; }
+    if (!workspace_dev || workspace_bytes == 0 || ((uintptr_t)workspace_dev & 255)) {
+        g_create_error = "need a workspace of nonzero size aligned to 256 bytes";
+        return IPC_E_INVALID;
+    }
+    if (int rc = precheck(scenes, n_scenes)) return rc;
+    ipc_ctx *c = new ipc_ctx;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws.init(workspace_dev, workspace_bytes);
+    read_options(c);
+    int rc = guard(c, [&] {
+        create_context(c, scenes, n_scenes);
+        setup_after_create(c);
+        reserve_capacity(c, cap->max_pairs, cap->max_candidates, cap->max_local_blocks);
+        IPC_HIP(hipStreamSynchronize(c->stream));
     });
     if (rc != IPC_OK) {
         g_create_error = c->err;
@@ -514,6 +593,8 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_NPAIRS: *v = c->n_pt + c->n_ee; return IPC_OK;
     case IPC_Q_NTETS_EXT: *v = c->ext_tets; return IPC_OK;
     case IPC_Q_COARSE: *v = c->coarse_on ? 1 : 0; return IPC_OK;
+    case IPC_Q_WS_BYTES: *v = (int64_t)c->ws.size; return IPC_OK;
+    case IPC_Q_WS_PEAK: *v = (int64_t)c->ws.peak; return IPC_OK;
     }
     return IPC_E_INVALID;
 }
@@ -547,6 +628,23 @@ extern "C" int ipc_set_friction_lag(ipc_ctx *c, int passes)
     if (passes < 1 || passes > 16) { c->err = "friction lag passes must lie in [1, 16]"; return IPC_E_INVALID; }
     c->lag_passes = passes;
     return IPC_OK;
+}
+
+extern "C" int ipc_set_kappa_adaptive(ipc_ctx *c, double frac, double factor)
+{
+    if (!c) return IPC_E_INVALID;
+    if (!(frac >= 0.0) || !std::isfinite(frac) || !(factor >= 1.0) || !std::isfinite(factor)) {
+        c->err = "adaptive kappa needs a finite frac >= 0 and factor >= 1";
+        return IPC_E_INVALID;
+    }
+    return guard(c, [&] {
+        std::vector<double> sc = read_scal(c);
+        for (int s = 0; s < c->n_scenes; ++s) sc[(size_t)s * NSLOT + S_KAPPA0] = c->sc[s].kappa;
+        write_scal(c, sc);
+        c->kappa_frac = frac;
+        c->kappa_factor = factor;
+        sync(c);
+    });
 }
 
 extern "C" int ipc_scene_scalars(const ipc_ctx *c, int s, double *kappa, double *L, double *thr)
@@ -631,6 +729,91 @@ extern "C" int ipc_energy_grad_hess(ipc_ctx *c, const double *y_dev, double *E_d
     return rc != IPC_OK ? rc : status;
 }
 
+namespace ipc {
+// internal node -> external node (-1: padding)
+__global__ void k_int2ext(int64_t NE, const int *__restrict__ ext2node, int *__restrict__ int2ext)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < NE) int2ext[ext2node[i]] = (int)i;
+}
+// Export of the assembled matrix in the external numbering: row i of the
+// result is internal row ext2node[i], the union of its block-CSR columns and
+// its pair-local columns (both ascending), equal columns summed.
+template <bool WRITE>
+__global__ void k_bsr_export(int64_t NE, const int *__restrict__ ext2node, const int *__restrict__ int2ext,
+                             const int *__restrict__ rp, const int *__restrict__ col, const double *__restrict__ val,
+                             const int *__restrict__ dp, const int *__restrict__ dcol, const double *__restrict__ dval,
+                             int *__restrict__ cnt, const int *__restrict__ off, int *__restrict__ ocol, double *__restrict__ oval)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= NE) return;
+    const int r = ext2node[i];
+    int a = rp[r], ae = rp[r + 1], b = dp[r], be = dp[r + 1], n = 0;
+    int o = WRITE ? off[i] : 0;
+    while (a < ae || b < be) {
+        const int ca = a < ae ? col[a] : INT_MAX, cb = b < be ? dcol[b] : INT_MAX;
+        const int cc = min(ca, cb);
+        if (WRITE) {
+            double blk[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) blk[q] = 0.0;
+            if (ca == cc) for (int q = 0; q < 9; ++q) blk[q] += val[9 * (size_t)a + q];
+            if (cb == cc) for (int q = 0; q < 9; ++q) blk[q] += dval[9 * (size_t)b + q];
+            ocol[o + n] = int2ext[cc];
+            for (int q = 0; q < 9; ++q) oval[9 * (size_t)(o + n) + q] = blk[q];
+        }
+        if (ca == cc) ++a;
+        if (cb == cc) ++b;
+        ++n;
+    }
+    if (!WRITE) cnt[i] = n;
+}
+} // namespace ipc
+
+extern "C" int ipc_hessian_bsr(ipc_ctx *c, const double *y_dev, uint32_t flags, int32_t *row_ptr_dev, int32_t *col_dev,
+                               double *val_dev, int64_t cap_blocks, int64_t *nnzb_out)
+{
+    if (!c || !y_dev || !row_ptr_dev || !nnzb_out || cap_blocks < 0) return IPC_E_INVALID;
+    if (!c->step_ready) { c->err = "call ipc_begin_step first"; return IPC_E_INVALID; }
+    int status = IPC_OK;
+    int rc = guard(c, [&] {
+        Dev &D = c->d;
+        hipStream_t st = c->stream;
+        c->fr_on = (flags & IPC_WITH_FRICTION) != 0;
+        double *y = D.v2.p;
+        hipLaunchKernelGGL(k_zero, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, y);
+        hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(c->ext_nodes)), dim3(BLOCK), 0, st, c->ext_nodes, D.ext2node.p, y_dev, y);
+        pairs_from_scratch(c, y);
+        eval_grad_hess(c, y, D.g.p, true, (flags & IPC_PSD_PROJECT) != 0);
+        c->fr_on = true;
+        const int64_t NE = c->ext_nodes;
+        D.int2ext.alloc(c->N);
+        hipLaunchKernelGGL(k_int2ext, dim3(blocks_for(NE)), dim3(BLOCK), 0, st, NE, D.ext2node.p, D.int2ext.p);
+        D.bsr_cnt.alloc(NE + 1);
+        hipLaunchKernelGGL(k_bsr_export<false>, dim3(blocks_for(NE)), dim3(BLOCK), 0, st, NE, D.ext2node.p, D.int2ext.p, D.row_ptr.p,
+                           D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.bsr_cnt.p, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(64), 0, st, 1, D.bsr_cnt.p + NE, 0);
+        exclusive_scan_int(c, D.bsr_cnt.p, row_ptr_dev, (int)NE);
+        int total = 0;
+        std::vector<int> inf(c->n_scenes);
+        IPC_HIP(hipMemcpyAsync(&total, row_ptr_dev + NE, sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipMemcpyAsync(inf.data(), D.inf_flag.p, c->n_scenes * sizeof(int), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        *nnzb_out = total;
+        for (int s = 0; s < c->n_scenes; ++s) if (inf[s]) status = IPC_E_INTERSECTING;
+        if (total > cap_blocks || !col_dev || !val_dev) {
+            if (status == IPC_OK) status = IPC_E_CAPACITY;
+            c->err = "the matrix has " + std::to_string(total) + " blocks";
+            return;
+        }
+        hipLaunchKernelGGL(k_bsr_export<true>, dim3(blocks_for(NE)), dim3(BLOCK), 0, st, NE, D.ext2node.p, D.int2ext.p, D.row_ptr.p,
+                           D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, nullptr, row_ptr_dev, col_dev, val_dev);
+        IPC_HIP(hipGetLastError());
+        IPC_HIP(hipStreamSynchronize(st));
+    });
+    return rc != IPC_OK ? rc : status;
+}
+
 extern "C" int ipc_get_pairs(ipc_ctx *c, const double *y_dev, int scene, int32_t *pt_host, int32_t *ee_host, int64_t cap, int64_t *n_pt,
                              int64_t *n_ee)
 {
@@ -685,7 +868,7 @@ extern "C" int ipc_ccd(ipc_ctx *c, const double *y_dev, const double *p_dev, dou
         launch_world(c, D.yt.p, D.xw1.p);
         broad_phase(c, D.xw.p, D.xw1.p);
         hipLaunchKernelGGL(k_set_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_CCD, 1.0);
-        hipLaunchKernelGGL(k_fill_int_api, dim3(1), dim3(256), 0, st, c->n_scenes, D.ls_active.p, 1);
+        hipLaunchKernelGGL(k_fill_int_api, dim3(blocks_for(c->n_scenes)), dim3(BLOCK), 0, st, c->n_scenes, D.ls_active.p, 1);
         launch_ccd(c, D.xw.p, D.xw1.p);
         hipLaunchKernelGGL(k_gather_slot, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_CCD, alpha_dev);
         IPC_HIP(hipStreamSynchronize(st));
@@ -748,6 +931,7 @@ extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *
     if ((c->ND || c->NJ) && !targets_dev) { c->err = "targets required: the scenes have driven links or joint springs"; return IPC_E_INVALID; }
     if (!(eta > 0.0)) { c->err = "eta must be > 0"; return IPC_E_INVALID; }
     if (c->lag_passes != 1) { c->err = "the adjoint differentiates steps lagged once at their start (ipc_set_friction_lag(ctx, 1))"; return IPC_E_INVALID; }
+    if (c->kappa_frac > 0.0) { c->err = "the adjoint holds kappa fixed: switch adaptive kappa off (ipc_set_kappa_adaptive(ctx, 0, ...))"; return IPC_E_INVALID; }
     int status = IPC_OK;
     int rc = guard(c, [&] {
         Dev &D = c->d;
@@ -830,6 +1014,8 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         S[s].n_lag = 0;
     }
     std::vector<int> on(ns, 1);
+    const bool kappa_adapt = c->kappa_frac > 0.0;
+    if (kappa_adapt) launch_kappa_update(c, D.xw.p, true);   // pairs and world positions at y^n
     // energy at the start
     eval_energy(c, D.y.p, false);
     std::vector<double> sc = read_scal(c);
@@ -843,6 +1029,14 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
     int max_newton = 0;
     for (auto &si : c->sc) max_newton = std::max(max_newton, si.max_newton);
     std::vector<int> want(ns);
+    // E0 holds each scene's energy at its iterate.  The trials are summed over
+    // the swept candidate list; E0 is compared with them only when it was
+    // summed over the same list in the same order (after an accepted trial),
+    // and is evaluated again over the list whenever the list is rebuilt: a
+    // decrease smaller than the rounding of the sums must not be lost to a
+    // change of summation order (rebuilds follow any scene's sweep, so in a
+    // batch they come far more often than a scene's own sweep asks for).
+    bool e0_on_list = false;
     // friction lag passes: after a converged pass the lag is taken again at
     // the solution (slips still measured from the step start) and Newton
     // runs again from there, for the scenes that converged
@@ -858,12 +1052,13 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         launch_world(c, D.y0.p, D.xw1.p);      // the step start
         launch_lag(c, D.xw.p, D.xw1.p);
         c->n_lag_pt = c->n_pt;
-        hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_PT), seg_ptr(c, R_LPT));
-        hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(256), 0, st, c->n_scenes + 1, seg_ptr(c, R_EE), seg_ptr(c, R_LEE));
+        hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes + 1, seg_ptr(c, R_PT), seg_ptr(c, R_LPT));
+        hipLaunchKernelGGL(k_copy_int, dim3(blocks_for(c->n_scenes + 1)), dim3(BLOCK), 0, st, c->n_scenes + 1, seg_ptr(c, R_EE), seg_ptr(c, R_LEE));
         eval_energy(c, D.y.p, false);
         sc = read_scal(c);
         for (int s = 0; s < ns; ++s)
             if (on[s]) { E0[s] = sc[(size_t)s * NSLOT + S_E]; S[s].energy = E0[s]; }
+        e0_on_list = false;
     }
     for (int j = 0; j < max_newton; ++j) {
         bool any = false;
@@ -929,7 +1124,10 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         // still covers every iterating scene's sweep, else a new one
         bool rebuild = !cached;
         for (int s = 0; s < ns; ++s) rebuild = rebuild || (on[s] && stale[s]);
-        if (rebuild) broad_phase_cached(c, D.xw.p, D.xw1.p);
+        if (rebuild) {
+            broad_phase_cached(c, D.xw.p, D.xw1.p);
+            e0_on_list = false;
+        }
         for (int s = 0; s < ns; ++s) S[s].n_cand_max = std::max(S[s].n_cand_max, (c->h_cand_pt_seg[s + 1] - c->h_cand_pt_seg[s]) +
                                                                              (c->h_cand_ee_seg[s + 1] - c->h_cand_ee_seg[s]));
         launch_ccd(c, D.xw.p, D.xw1.p);
@@ -940,6 +1138,13 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             if (!on[s]) continue;
             alpha[s] = std::min(1.0, sc[(size_t)s * NSLOT + S_CCD]);
             ls[s] = 1;
+        }
+        if (!e0_on_list) {   // E(y) over the list the trials use
+            eval_energy(c, D.y.p, true);
+            std::vector<double> se = read_scal(c);
+            for (int s = 0; s < ns; ++s)
+                if (on[s]) E0[s] = se[(size_t)s * NSLOT + S_E];
+            e0_on_list = true;
         }
         // backtracking: halve each scene's step until its energy does not increase
         std::vector<double> Eacc(ns, 0.0);
@@ -979,7 +1184,18 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         // pairs at the new iterate from the swept candidates (a superset)
         launch_world(c, D.y.p, D.xw.p);
         narrow_phase(c, D.xw.p);
+        if (kappa_adapt) {
+            // kappa may have changed: the next comparison energy is evaluated afresh
+            launch_kappa_update(c, D.xw.p, false);
+            e0_on_list = false;
+        }
     }
+    }
+    if (kappa_adapt) {
+        std::vector<double> sp(8 * (size_t)ns);
+        IPC_HIP(hipMemcpyAsync(sp.data(), D.sparam.p, sp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        IPC_HIP(hipStreamSynchronize(st));
+        for (int s = 0; s < ns; ++s) c->sc[s].kappa = sp[8 * (size_t)s + P_KAPPA];
     }
     hipLaunchKernelGGL(k_velocity, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.sparam.p, D.y.p, D.y0.p, D.ydot.p);
     IPC_HIP(hipStreamSynchronize(st));

@@ -278,7 +278,7 @@ __global__ void k_node_box(int P, SegLevels L, const double *__restrict__ lev, c
 // stashes the first TRAV_STASH candidates of each query; WRITE = true writes
 // every candidate at off[q]: from the stash when it held them all, else by
 // traversing again (with stash = nullptr: always traversing).
-constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64, TRAV_STASH = 16;
+constexpr int TRAV_BLOCK = 128, TRAV_DEPTH = 64;
 template <bool WRITE>
 __global__ void __launch_bounds__(TRAV_BLOCK) k_traverse(int Q, int kind, const int2 *__restrict__ qedge, const int *__restrict__ cv_scene,
                            const int4 *__restrict__ tri, const int2 *__restrict__ edge, const int *__restrict__ cv_obj,
@@ -403,6 +403,14 @@ __global__ void k_compact_seg(int n_scenes, int ncand, const int *__restrict__ c
     seg[s] = woff[w] + (l ? __popcll(mask[w] & ((1ull << l) - 1ull)) : 0);
 }
 
+void exclusive_scan_int(ipc_ctx *c, const int *in, int *out, int n)
+{
+    size_t bytes = 0;
+    IPC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n + 1, c->stream));
+    c->d.sort_tmp.alloc(bytes + 16);
+    IPC_HIP(hipcub::DeviceScan::ExclusiveSum(c->d.sort_tmp.p, bytes, in, out, n + 1, c->stream));
+}
+
 // exclusive scan helper (count[n] -> off[n + 1], off[n] = total)
 static void exclusive_scan(ipc_ctx *c, const int *in, int *out, int n)
 {
@@ -424,7 +432,7 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     hseg.assign(ns + 1, 0);
     count = 0;
     if (P == 0 || Q == 0) {
-        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, ns + 1, seg_ptr(c, kind == 0 ? R_CPT : R_CEE), 0);
+        hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns + 1, seg_ptr(c, kind == 0 ? R_CPT : R_CEE), 0);
         return;
     }
     D.box.alloc(6 * (size_t)P); D.mkey.alloc(P); D.mkey2.alloc(P); D.mid.alloc(P); D.mid2.alloc(P);
@@ -500,6 +508,9 @@ static void bvh_query(ipc_ctx *c, int kind, const double *xw0, const double *xw1
     }
     if (of[0]) throw Error(IPC_E_CAPACITY, "BVH traversal stack overflow");
     if (total > cap) {
+        if (c->ws.base)
+            throw Error(IPC_E_CAPACITY, std::to_string(total) + (kind == 0 ? " point-triangle" : " edge-edge") +
+                                            " candidates exceed the planned capacity of " + std::to_string(cap));
         cap = (int64_t)(total * 1.5) + 1024;
         outbuf.alloc(cap);
     }
@@ -626,7 +637,7 @@ static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &ca
     count = 0;
     int *sseg = seg_ptr(c, pseg_region);
     if (ncand == 0) {
-        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, ns + 1, sseg, 0);
+        hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(ns + 1)), dim3(BLOCK), 0, st, ns + 1, sseg, 0);
         return;
     }
     int nw = (int)((ncand + TILE - 1) / TILE);
@@ -648,7 +659,13 @@ static void compact(ipc_ctx *c, int kind, const double *xw, const DBuf<int2> &ca
         r.add(hseg.data(), sseg, (ns + 1) * sizeof(int));
         r.wait();
     }
-    if (total > cap) { cap = (int64_t)(total * 1.5) + 1024; out.alloc(cap); }
+    if (total > cap) {
+        if (c->ws.base)
+            throw Error(IPC_E_CAPACITY, std::to_string(total) + (kind == 0 ? " point-triangle" : " edge-edge") +
+                                            " pairs exceed the planned capacity of " + std::to_string(cap));
+        cap = (int64_t)(total * 1.5) + 1024;
+        out.alloc(cap);
+    }
     count = total;
     hipLaunchKernelGGL(k_narrow<true>, dim3(blocks_for(ncand)), dim3(BLOCK), 0, st, (int)ncand, kind, cand.p, D.tri.p, D.edge.p,
                        D.cv_scene.p, xw, D.sparam.p, mask.p, D.wcount.p, D.woff.p, out.p);
@@ -1155,6 +1172,8 @@ void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
     Dev &D = c->d;
     int64_t n = c->n_pt + c->n_ee;
     if (n > c->cap_lag) {
+        if (c->ws.base)
+            throw Error(IPC_E_CAPACITY, std::to_string(n) + " friction pairs exceed the planned capacity of " + std::to_string(c->cap_lag));
         c->cap_lag = (int64_t)(n * 1.5) + 1024;
         D.lag_cv.alloc(c->cap_lag); D.lag_beta.alloc(4 * c->cap_lag); D.lag_nrm.alloc(3 * c->cap_lag);
         D.lag_lam.alloc(c->cap_lag); D.lag_rn.alloc(3 * c->cap_lag); D.lag_M.alloc(6 * c->cap_lag);
@@ -1626,6 +1645,9 @@ void build_dyn_blocks(ipc_ctx *c)
     int64_t E = c->n_dyn;
     if (E > 0) {
         if (E > c->cap_dyn) {
+            if (c->ws.base)
+                throw Error(IPC_E_CAPACITY, std::to_string(E) + " pair-local blocks exceed the planned capacity of " +
+                                                std::to_string(c->cap_dyn));
             c->cap_dyn = E + E / 2 + 1024;
             D.dyn_key64.alloc(c->cap_dyn); D.dyn_key64b.alloc(c->cap_dyn);
             for (auto *b : {&D.dyn_idx, &D.dyn_idx2, &D.dyn_head, &D.dyn_pos, &D.dyn_start, &D.dyn_row, &D.dyn_col}) b->alloc(c->cap_dyn + 1);
@@ -1766,6 +1788,136 @@ void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1)
                        D.cand_ee.p, D.tri.p, D.edge.p, xw0, xw1, D.cv_scene.p, D.sparam.p, D.ls_active.p,
                        (unsigned long long *)(D.scal.p + S_CCD), NSLOT);
     prof_end(c, IPC_K_CCD, 0.0);
+}
+
+// Adaptive barrier stiffness (IPC's doubling rule, applied to the barrier
+// term of Eq. (3)).  k_pair_dmin: the smallest squared distance over each
+// scene's active pairs, an atomic min on the bit pattern (non-negative
+// doubles order as their bits; the result does not depend on the order).
+static __global__ void k_set_slot_c(int ns, double *scal, int slot, double v)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) scal[(size_t)s * NSLOT + slot] = v;
+}
+
+__global__ void k_pair_dmin(int npt, int nee, const int2 *__restrict__ pt, const int2 *__restrict__ ee, const int4 *__restrict__ tri,
+                            const int2 *__restrict__ edge, const double *__restrict__ xw, const int *__restrict__ cv_scene,
+                            unsigned long long *__restrict__ dmin, int stride)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npt + nee) return;
+    int kind = i < npt ? 0 : 1;
+    int2 pr = kind == 0 ? pt[i] : ee[i - npt];
+    int cv[4];
+    pair_vertices(kind, pr, tri, edge, cv);
+    d3 x[4] = {ld3(xw, cv[0]), ld3(xw, cv[1]), ld3(xw, cv[2]), ld3(xw, cv[3])};
+    int type;
+    double d2 = pair_d2(kind, x, &type);
+    if (!(d2 > 0.0)) d2 = 0.0;
+    atomicMin(dmin + (size_t)stride * cv_scene[cv[0]], (unsigned long long)__double_as_longlong(d2));
+}
+
+// Per scene, from its smallest active distance d (infinite without pairs):
+// at an accepted update (S_LS_ON set), kappa doubles when d < frac dhat and d
+// is below the previous iterate's, capped at factor kappa0; the previous
+// distance then becomes d.  first: the step start only records d.
+__global__ void k_kappa_update(int ns, double frac, double factor, int first, double *__restrict__ sparam, double *__restrict__ scal)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    double *S = scal + (size_t)s * NSLOT;
+    double d = sqrt(S[S_DMIN]);
+    bool accepted = S[S_LS_ON] != 0.0;
+    if (!first && accepted) {
+        double *sp = sparam + 8 * (size_t)s;
+        if (d < frac * sp[P_DHAT] && d < S[S_DPREV]) {
+            double k2 = 2.0 * sp[P_KAPPA], kmax = factor * S[S_KAPPA0];
+            sp[P_KAPPA] = k2 < kmax ? k2 : kmax;
+        }
+    }
+    if (first || accepted) S[S_DPREV] = d;
+}
+
+void launch_kappa_update(ipc_ctx *c, const double *xw, bool first)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_set_slot_c, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_DMIN, INFINITY);
+    int64_t n = c->n_pt + c->n_ee;
+    if (n)
+        hipLaunchKernelGGL(k_pair_dmin, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,
+                           D.edge.p, xw, D.cv_scene.p, (unsigned long long *)(D.scal.p + S_DMIN), NSLOT);
+    hipLaunchKernelGGL(k_kappa_update, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, c->kappa_frac,
+                       c->kappa_factor, (int)first, D.sparam.p, D.scal.p);
+}
+
+} // namespace ipc
+
+namespace ipc {
+
+// Sizes every buffer whose length depends on the contact state for the given
+// capacity, once, at creation over a caller's workspace: later calls then
+// take no memory, and a state beyond the capacity ends with IPC_E_CAPACITY.
+void reserve_capacity(ipc_ctx *c, int64_t P, int64_t C, int64_t B)
+{
+    Dev &D = c->d;
+    hipStream_t st = c->stream;
+    P = std::max<int64_t>(P, 1); C = std::max<int64_t>(C, 1); B = std::max<int64_t>(B, 1);
+    const int64_t Pp = std::max<int64_t>(std::max(c->TRI, c->EDGE), 1), Q = std::max<int64_t>(std::max(c->NSURF, c->EDGE), 1);
+    // broad phase over the larger kind of primitive and of query
+    D.box.alloc(6 * Pp); D.mid.alloc(Pp); D.mid2.alloc(Pp);
+    D.bvh_left.alloc(Pp); D.bvh_right.alloc(Pp); D.bvh_range.alloc(Pp); D.bvh_flag.alloc(Pp); D.bvh_box.alloc(6 * Pp);
+    D.bvh_lev.alloc(6 * (2 * Pp + 64)); D.bvh_moving.alloc(Pp + 1); D.bvh_mscan.alloc(Pp + 1); D.bvh_nmoving.alloc(Pp);
+    D.qcount.alloc(Q + 1); D.qoff.alloc(Q + 1); D.qstash.alloc(Q * TRAV_STASH);
+    D.qkey.alloc(Q); D.qkey2.alloc(Q); D.qid.alloc(Q); D.qperm.alloc(Q);
+    // scratch words shared by the Morton keys, the narrow phase's masks and the long rows' masks
+    const int64_t nw = std::max<int64_t>(C, c->N) / TILE + 1;
+    D.mkey.alloc(std::max<int64_t>(Pp, nw)); D.mkey2.alloc(Pp);
+    D.wcount.alloc(nw + 1); D.woff.alloc(nw + 1);
+    c->cap_cand_pt = c->cap_cand_ee = C;
+    D.cand_pt.alloc(C); D.cand_ee.alloc(C);
+    D.cand_ref.alloc(6 * (size_t)c->CV + 1);
+    c->cap_pt = c->cap_ee = P;
+    D.pt.alloc(P); D.ee.alloc(P);
+    // barrier: per-pair values over pairs or candidates, gradients and blocks over pairs
+    const int64_t PC = std::max(P, C);
+    D.pair_part.alloc(PC + 1); D.pair_w64.alloc(PC / TILE + 1);
+    D.pair_g.alloc(12 * P + 3);
+    for (auto *b : {&D.pg_key, &D.pg_code, &D.pg_key2, &D.pg_code2}) b->alloc(4 * P + 1);
+    D.pair_cv.alloc(P + 1); D.pair_H.alloc(45 * (P + 1)); D.pair_flag.alloc(P + 1);
+    for (auto *b : {&D.pb_key, &D.pb_code, &D.pb_key2, &D.pb_code2}) b->alloc(16 * P + 1);
+    // friction lag
+    c->cap_lag = P;
+    D.lag_cv.alloc(P); D.lag_beta.alloc(4 * P); D.lag_nrm.alloc(3 * P); D.lag_lam.alloc(P); D.lag_rn.alloc(3 * P);
+    D.lag_M.alloc(6 * P); D.lag_flag.alloc(P); D.lag_type.alloc(P); D.lag_ex.alloc(P); D.lag_merge.alloc(P);
+    for (auto *b : {&D.lag_key, &D.lag_code, &D.lag_key2, &D.lag_code2}) b->alloc(16 * P);
+    D.lag_g.alloc(12 * P);
+    for (auto *b : {&D.lg_key, &D.lg_code, &D.lg_key2, &D.lg_code2}) b->alloc(4 * P);
+    D.fr_part.alloc(P + 1); D.fr_w64.alloc(P / TILE + 1);
+    D.gcv.alloc(3 * (size_t)c->CV + 3);
+    // pair-local blocks
+    D.dyn_cnt.alloc(2 * P + 1); D.dyn_off.alloc(2 * P + 1);
+    c->cap_dyn = B;
+    D.dyn_key64.alloc(B); D.dyn_key64b.alloc(B);
+    for (auto *b : {&D.dyn_idx, &D.dyn_idx2, &D.dyn_head, &D.dyn_pos, &D.dyn_start, &D.dyn_row, &D.dyn_col}) b->alloc(B + 1);
+    D.dyn_val.alloc(9 * B); D.dyn_val_coo.alloc(9 * B);
+    // run sums: the largest has 16 entries of 9 doubles per pair
+    D.rs_first.alloc(9 * (16 * P / TILE + 1) + 1); D.rs_last.alloc(9 * (16 * P / TILE + 1) + 1);
+    // PCG: long rows at most every row
+    c->long_cap = std::max(c->long_cap, (c->N + 63) / 64 * 64);
+    D.part_long.alloc(c->long_cap + 1);
+    D.part_node3.alloc(c->N / TILE + 1); D.pcg_part.alloc(4 * (size_t)(c->N / TILE) + 1);
+    D.pcg_st.alloc(8 * (size_t)c->n_scenes); D.pcg_act.alloc(2 * (size_t)c->n_scenes); D.pcg_it.alloc(2 * (size_t)c->n_scenes);
+    D.pcg_prev.alloc(c->n_scenes); D.cand_flag.alloc(c->n_scenes);
+    // the sorts' temporary storage at these sizes
+    size_t tmp = 0, b = 0;
+    auto upd = [&]() { tmp = std::max(tmp, b); };
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.pb_key.p, D.pb_key2.p, D.pb_code.p, D.pb_code2.p, (int)(16 * P), 0, 31, st)); upd();
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.dyn_key64.p, D.dyn_key64b.p, D.dyn_idx.p, D.dyn_idx2.p, (int)B, 0, 64, st)); upd();
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.mkey.p, D.mkey2.p, D.mid.p, D.mid2.p, (int)Pp, 0, 64, st)); upd();
+    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.qkey.p, D.qkey2.p, D.qid.p, D.qperm.p, (int)Q, 0, 64, st)); upd();
+    IPC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b, D.dyn_cnt.p, D.dyn_off.p, (int)std::max<int64_t>(std::max(B, 2 * P + 1), std::max(nw, Q + 1)), st)); upd();
+    D.sort_tmp.alloc(tmp + 16);
 }
 
 } // namespace ipc

@@ -157,6 +157,21 @@ void validate(const ipc_scene_desc &s, int si)
     if (s.nv < 0 || s.nt < 0 || s.nb < 0 || s.nbv < 0 || s.nbt < 0 || s.nsv < 0 || s.nst < 0 || s.nobj < 0 || s.nex < 0 ||
         s.ns < 0 || s.nd < 0)
         fail(pre + "negative size");
+    // every array that a nonzero count asks for must be there
+    auto need = [&](bool cond, const void *p, const char *what) { if (cond && !p) fail(pre + "missing array " + what); };
+    need(s.nv > 0, s.X, "X"); need(s.nv > 0, s.V, "V"); need(s.nv > 0, s.vobj, "vobj");
+    need(s.nt > 0, s.tets, "tets"); need(s.nt > 0, s.tet_E, "tet_E"); need(s.nt > 0, s.tet_nu, "tet_nu");
+    need(s.nt > 0, s.tet_rho, "tet_rho");
+    for (const void *p : {(const void *)s.body_q, (const void *)s.body_qdot, (const void *)s.body_mass, (const void *)s.body_S,
+                          (const void *)s.body_vol, (const void *)s.body_kappa, (const void *)s.body_ext, (const void *)s.body_obj})
+        need(s.nb > 0, p, "body arrays");
+    need(s.nbv > 0, s.bv_xbar, "bv_xbar"); need(s.nbv > 0, s.bv_body, "bv_body"); need(s.nbt > 0, s.btri, "btri");
+    need(s.nsv > 0, s.sv_x, "sv_x"); need(s.nst > 0, s.stri, "stri"); need(s.nobj > 0, s.obj_kind, "obj_kind");
+    need(s.nex > 0, s.excl, "excl");
+    for (const void *p : {(const void *)s.sp_ka, (const void *)s.sp_ia, (const void *)s.sp_xa, (const void *)s.sp_kb,
+                          (const void *)s.sp_ib, (const void *)s.sp_xb, (const void *)s.sp_k})
+        need(s.ns > 0, p, "spring arrays");
+    need(s.nd > 0, s.driven_body, "driven_body");
     if (s.nv + s.nb == 0) fail(pre + "no degrees of freedom");
     if (!(s.h > 0) || !(s.dhat > 0) || !(s.mu >= 0) || !(s.eps_v > 0) || !(s.newton_tol > 0) || !(s.pcg_tol > 0) ||
         !(s.ccd_s > 0 && s.ccd_s < 1) || s.max_newton < 1 || s.max_pcg < 1)
@@ -252,6 +267,12 @@ HostTopo topology(const ipc_scene_desc &s)
 
 } // namespace
 
+void validate_scenes(const ipc_scene_desc *scenes, int n)
+{
+    if (!scenes || n < 1) fail("need at least one scene");
+    for (int s = 0; s < n; ++s) validate(scenes[s], s);
+}
+
 void build_const_part(ipc_ctx *c, const double *h2s)
 {
     Dev &D = c->d;
@@ -265,7 +286,7 @@ void build_const_part(ipc_ctx *c, const double *h2s)
 }
 
 
-void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
+void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64_t *caps, size_t *plan)
 {
     hipStream_t st = c->stream;
     c->n_scenes = n;
@@ -544,6 +565,64 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n)
     {
         std::vector<int> fill(body_cv_ptr.begin(), body_cv_ptr.end() - 1);
         for (int g = 0; g < cv; ++g) if (cv_body[g] >= 0) body_cv[fill[cv_body[g]]++] = g;
+    }
+
+    // ---- plan only: the device bytes a context over a caller's workspace
+    // takes, an upper bound from the sizes above.  Buffers are listed as the
+    // creation, set-up, reserve_capacity and the first calls take them; each
+    // is rounded up to the arena's 256-byte granule, sums of sorted-entry
+    // tables, coarse domains and sort storage are bounded from above.
+    if (plan) {
+        const int64_t P = std::max<int64_t>(caps[0], 1), C = std::max<int64_t>(caps[1], 1), B = std::max<int64_t>(caps[2], 1);
+        const int64_t N = node, T = tet, NB = std::max(body, 1), NS = std::max(sp, 1), CVn = std::max(cv, 1), NZ = std::max(c->nnzb, 1);
+        const int64_t Pp = std::max<int64_t>(std::max(tri, edge), 1), Q = std::max<int64_t>(std::max(cv, edge), 1);
+        const int64_t NW = std::max<int64_t>(C, N) / TILE + 1, PC = std::max(P, C);
+        const int64_t ndom = N / (CG_AGG * CG_DOM) + 2 * (int64_t)n, ngrp = N / CG_AGG + 2 * (int64_t)n;
+        const std::vector<int64_t> nbuf = {
+            // nodes: state, predictor and solver vectors (14 x 3 doubles), kinds, maps, mass, inverse blocks
+            14 * 24 * N, 4 * N, 4 * N, 4 * (int64_t)(dof / 3) + 4, 8 * N, 72 * N, 8 * (N / TILE + 1), 4 * N, 4 * N,
+            // tetrahedra: vertices, inverse rest shape, volume and Lame, modulus and ratio, gradients and blocks,
+            // slot and adjacency lists, the temporary density and validity
+            16 * T, 72 * T, 8 * T, 8 * T, 8 * T, 8 * T, 8 * T, 4 * T + 4, 96 * std::max<int64_t>(T, 1), 720 * std::max<int64_t>(T, 1),
+            4 * (NZ + 1), 4 * (int64_t)sc_list.size() + 4, 4 * (N + 1), 4 * (int64_t)adj.size() + 4, 8 * T, 4 * T, 8 * (T / TILE + 1),
+            // matrix: pattern, values, constant part, slots
+            4 * (N + 1), 4 * NZ, 4 * N, 72 * NZ, 72 * NZ, 64 * NB,
+            // bodies
+            128 * NB, 8 * NB, 8 * NB, 24 * NB, 4 * NB, 4 * NB, 1152 * NB, 8 * NB, 4 * (NB + 1), 4 * (int64_t)body_cv.size() + 4,
+            // springs, drive targets, joint points, their entry lists
+            4 * NS, 4 * NS, 4 * NS, 4 * NS, 4 * NS, 24 * NS, 24 * NS, 8 * NS, 8 * NS, 24 * NS,
+            8 * (int64_t)spg.size() + 8, 8 * (int64_t)spc.size() + 8, 96 * std::max(drv, 1) + 96, 4 * std::max(drv, 1), 4 * std::max(jt, 1),
+            // contact vertices, triangles, edges, objects
+            16 * CVn, 24 * CVn, 48 * CVn, 16 * std::max(tri, 1), 8 * std::max(edge, 1), 8 * std::max(edge, 1), 4 * std::max(obj, 1),
+            8 * std::max(ex, 1) + 8,
+            // per scene: scalars, parameters, segment tables, flags, PCG state, Morton boxes
+            8 * NSLOT * (int64_t)n, 64 * (int64_t)n, 24 * (int64_t)n, 4 * (int64_t)n, 16 * (int64_t)(n + 1), 4 * NREGION * (int64_t)(n + 1),
+            16 * (int64_t)n, 64 * (int64_t)n, 16 * (int64_t)n, 8 * (int64_t)n, 48 * (int64_t)n, 4 * (int64_t)n, 16, 16,
+            // tiles and PCG partials, workgroup records
+            4 * (N / TILE + 1), 4 * (T / TILE + 1), 8 * (N / TILE + 1), 32 * (N / TILE + 1), 32 * (N / 256 + 1),
+            // coarse correction: groups, domains, inverses
+            4 * ngrp, 4 * (ndom + 1), 4 * N, 4 * N, 4 * ndom, 8 * CG_N * CG_N * ndom, 16 * ndom,
+            // reserve_capacity: broad phase
+            48 * Pp, 8 * Pp, 8 * Pp, 8 * Pp, 8 * Pp, 4 * Pp, 4 * Pp, 8 * Pp, 4 * Pp, 48 * Pp, 48 * (2 * Pp + 64), 4 * (Pp + 1),
+            4 * (Pp + 1), 4 * Pp, 4 * (Q + 1), 4 * (Q + 1), 8 * TRAV_STASH * Q, 8 * Q, 8 * Q, 4 * Q, 4 * Q,
+            // candidates, masks, pairs
+            8 * std::max(Pp, NW), 4 * (NW + 1), 4 * (NW + 1), 8 * C, 8 * C, 48 * CVn + 8, 8 * P, 8 * P,
+            // barrier
+            8 * (PC + 1), 8 * (PC / TILE + 1), 96 * P + 24, 4 * 4 * (4 * P + 1), 16 * (P + 1), 360 * (P + 1), 4 * (P + 1),
+            4 * 4 * (16 * P + 1),
+            // friction lag
+            16 * P, 32 * P, 24 * P, 8 * P, 24 * P, 48 * P, 4 * P, 4 * P, 8 * P, 4 * P, 4 * 4 * 16 * P, 96 * P, 4 * 4 * 4 * P,
+            8 * (P + 1), 8 * (P / TILE + 1), 24 * CVn + 24,
+            // pair-local blocks
+            4 * (2 * P + 1), 4 * (2 * P + 1), 16 * B, 7 * 4 * (B + 1), 144 * B, 16,
+            // run sums, PCG long rows and partials
+            2 * 8 * (9 * (16 * P / TILE + 1) + 1), 8 * (N + 65), 8 * (N / TILE + 1), 32 * (N / TILE + 1), 4 * (N + 1),
+            // sort and scan storage (rocprim: a copy of keys and values plus per-block counts), bounded
+            16 * std::max<int64_t>(std::max(16 * P, B), std::max(Pp, Q)) + (4 << 20)};
+        size_t bytes = 0;
+        for (int64_t b : nbuf) bytes += Arena::round((size_t)std::max<int64_t>(b, 1));
+        *plan = bytes + bytes / 16 + (1 << 20);   // 6 % and 1 MiB against fragmentation of the free list
+        return;
     }
 
     // ---- upload

@@ -12,10 +12,6 @@ struct d3 { double x, y, z; };
 __device__ __forceinline__ d3 mk(double x, double y, double z) { return {x, y, z}; }
 __device__ __forceinline__ d3 ld3(const double *p, int i) { return {p[3 * (size_t)i], p[3 * (size_t)i + 1], p[3 * (size_t)i + 2]}; }
 __device__ __forceinline__ void st3(double *p, int i, d3 v) { p[3 * (size_t)i] = v.x; p[3 * (size_t)i + 1] = v.y; p[3 * (size_t)i + 2] = v.z; }
-__device__ __forceinline__ void atomic_add3(double *p, int i, d3 v)
-{
-    atomicAdd(p + 3 * (size_t)i, v.x); atomicAdd(p + 3 * (size_t)i + 1, v.y); atomicAdd(p + 3 * (size_t)i + 2, v.z);
-}
 
 // ---------------------------------------------------------------------------
 // Exact-order vector arithmetic.  The contact-pair predicate d^2 < dhat^2 must

@@ -9,7 +9,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -24,6 +26,7 @@ constexpr int CG_DOM = 32;    // groups per coarse domain
 constexpr int CG_N = 3 * CG_DOM;   // coarse unknowns per domain
 constexpr int CG_MIN_NODES = 32768;  // contexts from this size apply it by default
 constexpr int LONG_ROW = 64;  // rows with more blocks go to the wavefront-per-row path
+constexpr int TRAV_STASH = 16;   // broad phase: candidates a query keeps from its counting pass
 
 // per-scene device scalar slots
 enum Slot {
@@ -38,6 +41,9 @@ enum Slot {
     S_NEWTON_ON,    // 1 while the scene's Newton loop runs
     S_INDEF,        // 1 when the scene's PCG met p.Ap <= 0
     S_MUBAR,        // adjoint: w . dG/dmu of the last step
+    S_DMIN,         // adaptive kappa: smallest squared distance over the active pairs (bit pattern, atomic min)
+    S_DPREV,        // adaptive kappa: smallest distance at the previous iterate
+    S_KAPPA0,       // adaptive kappa: the scene's kappa when the rule was switched on
     NSLOT
 };
 
@@ -92,22 +98,93 @@ struct Error {
     Error(int c, std::string m) : code(c), msg(std::move(m)) {}
 };
 
+// Device memory of a context created over a caller's workspace
+// (ipc_create_ws): sub-ranges handed out first fit from a free list, with
+// neighbours merged on release, so that no hipMalloc is made.  Every use of a
+// range is ordered on the context's stream, so a released range can be handed
+// out again at once.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0, peak = 0;
+    std::map<size_t, size_t> free;   // offset -> bytes
+    void init(void *b, size_t bytes)
+    {
+        base = (char *)b; size = bytes; used = peak = 0;
+        free.clear();
+        if (bytes) free[0] = bytes;
+    }
+    static size_t round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+    void *take(size_t bytes)
+    {
+        bytes = round(bytes);
+        for (auto it = free.begin(); it != free.end(); ++it) {
+            if (it->second < bytes) continue;
+            size_t off = it->first, sz = it->second;
+            free.erase(it);
+            if (sz > bytes) free[off + bytes] = sz - bytes;
+            used += bytes;
+            peak = std::max(peak, used);
+            return base + off;
+        }
+        return nullptr;
+    }
+    void give(void *p, size_t bytes)
+    {
+        bytes = round(bytes);
+        size_t off = (size_t)((char *)p - base);
+        used -= bytes;
+        auto nx = free.lower_bound(off);
+        if (nx != free.end() && off + bytes == nx->first) { bytes += nx->second; nx = free.erase(nx); }
+        if (nx != free.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) { pv->second += bytes; return; }
+        }
+        free[off] = bytes;
+    }
+};
+// The arena of the context whose call is running on this thread (null: the
+// context allocates with hipMalloc).
+extern thread_local Arena *g_arena;
+struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a) : prev(g_arena) { g_arena = a; }
+    ~ArenaScope() { g_arena = prev; }
+};
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    Arena *from = nullptr;   // the arena the range came from (null: hipMalloc)
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    ~DBuf() { if (p) (void)hipFree(p); }
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) {
+            if (from) from->give(p, n * sizeof(T));
+            else (void)hipFree(p);
+        }
+        p = nullptr;
+        n = 0;
+        from = nullptr;
+    }
     void alloc(size_t count)
     {
         if (count <= n && p) return;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
+        release();
         if (count == 0) count = 1;
-        IPC_HIP(hipMalloc(&p, count * sizeof(T)));
+        if (g_arena) {
+            p = (T *)g_arena->take(count * sizeof(T));
+            if (!p)
+                throw Error(IPC_E_CAPACITY, "workspace exhausted: " + std::to_string(Arena::round(count * sizeof(T))) +
+                                                " more bytes needed (" + std::to_string(g_arena->used) + " of " +
+                                                std::to_string(g_arena->size) + " in use); plan a larger capacity");
+            from = g_arena;
+        } else {
+            IPC_HIP(hipMalloc(&p, count * sizeof(T)));
+        }
         n = count;
     }
     void upload(const std::vector<T> &h, hipStream_t s)
@@ -266,6 +343,7 @@ struct Dev {
     int64_t n_spg = 0;
     DBuf<int> spc_key, spc_code;           // constant spring blocks sorted by slot: code 64 s + 8 i + j
     int64_t n_spc = 0;
+    DBuf<int> int2ext, bsr_cnt;            // matrix export: internal -> external node, blocks per exported row
 };
 
 } // namespace ipc
@@ -286,6 +364,8 @@ struct ipc_ctx {
     bool coarse_on = false;               // the PCG applies the coarse correction
     bool coarse_forced = false;           // on by request, whatever the size
     int lag_passes = 1;                   // friction lag passes per step
+    double kappa_frac = 0.0;              // adaptive kappa: distance threshold / dhat (0: off)
+    double kappa_factor = 100.0;          // adaptive kappa: cap / kappa0
     int n_cdom = 0, n_cgrp = 0;           // its domains and groups over all scenes
     std::vector<int> seg_cdom;            // per scene: first domain (n_scenes + 1)
     int64_t ext_nodes = 0;
@@ -296,7 +376,8 @@ struct ipc_ctx {
     int64_t cap_cand_pt = 0, cap_cand_ee = 0, n_cand_pt = 0, n_cand_ee = 0;
     int64_t cap_pt = 0, cap_ee = 0, n_pt = 0, n_ee = 0, cap_lag = 0, n_lag = 0;
     std::vector<int> h_cand_pt_seg, h_cand_ee_seg, h_pt_seg, h_ee_seg, h_lag_seg;
-    ipc::Dev d;
+    ipc::Arena ws;                        // the caller's workspace (ipc_create_ws); empty: hipMalloc
+    ipc::Dev d;                           // (declared after ws: released into it before it goes)
     bool step_ready = false;
     bool fr_on = true;
     bool use_graphs = true;              // PCG iterations replayed from a captured graph
@@ -333,7 +414,13 @@ struct ipc_ctx {
 namespace ipc {
 
 // ---- helpers implemented in the .hip files ---------------------------------
-void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n);
+// plan (non-null): only the host half; *plan = the device bytes a workspace
+// context takes for the capacity caps = {pairs, candidates, pair-local blocks}
+void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64_t *caps = nullptr, size_t *plan = nullptr);
+// size every contact-state buffer for that capacity (workspace contexts)
+void reserve_capacity(ipc_ctx *c, int64_t max_pairs, int64_t max_candidates, int64_t max_local_blocks);
+// host checks of the scene data (throws Error(IPC_E_INVALID, ...)); no HIP call
+void validate_scenes(const ipc_scene_desc *scenes, int n);
 void reduce(ipc_ctx *c, const RedArgs &a);
 // w[k] = sum of v[64 k .. 64 k + 63] (entries past n count as 0), k < ceil(n / 64)
 void sum64(ipc_ctx *c, const double *v, int64_t n, double *w);
@@ -359,6 +446,8 @@ void coarse_build(ipc_ctx *c);
 void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int parity);
 
 void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *want);
+// exclusive scan of n ints into out[0..n] (out[n] = total), on the context's stream
+void exclusive_scan_int(ipc_ctx *c, const int *in, int *out, int n);
 void pcg_wginfo(ipc_ctx *c);
 // constant part of the matrix (lumped mass, spring blocks) from the current
 // spring points; h2s: h^2 per scene

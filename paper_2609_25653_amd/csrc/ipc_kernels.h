@@ -50,6 +50,7 @@ int bits_for(int64_t n);
 // rows the product takes one wavefront per row
 void build_dyn_blocks(ipc_ctx *c);
 void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1);
+void launch_kappa_update(ipc_ctx *c, const double *xw, bool first);
 
 // adjoint of the friction lag: ybar -= (dG_F/dy^n)^T w; per-pair w . dG/dmu into fr_part
 void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const double *w, double *ybar);

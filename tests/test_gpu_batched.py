@@ -122,3 +122,27 @@ def test_batched_with_coarse_correction(monkeypatch):
             part = yb[offs[i]:offs[i + 1]]
             assert np.abs(part - sim.state()[0].cpu().numpy()).max() <= 1e-6 * o.L, (k, i)
             assert np.abs(part - o.state()[0]).max() <= 1e-6 * o.L, (k, i)
+
+
+def test_batch_wider_than_one_workgroup():
+    """300 scenes: the per-scene tables (segment bounds of the contact and
+    lagged friction lists, line-search flags) span more than one workgroup;
+    scenes on both sides of the 64- and 256-entry boundaries, and the last
+    one, step like the oracle, with the oracle's lagged friction count."""
+    from paper_2609_25653_amd import Sim
+    n = 300
+    scenes = [S.tiny_scene("pad_box", seed=i % 7, h=0.01, n_steps=3) for i in range(n)]
+    batch = Sim(scenes)
+    pick = [0, 63, 64, 255, 256, n - 1]
+    oracles = {i: O.Oracle(scenes[i]) for i in pick}
+    offs = batch.dof_offsets
+    for k in range(3):
+        rc, st = batch.step()
+        assert rc == 0 and all(s["status"] == 0 for s in st), (k, sorted({s["status"] for s in st}))
+        yb = batch.state()[0].cpu().numpy()
+        for i, o in oracles.items():
+            rco, sto = o.step()
+            assert rco == 0
+            assert st[i]["n_lag"] == sto["n_lag"] > 0, (k, i, st[i]["n_lag"], sto["n_lag"])
+            err = np.abs(yb[offs[i]:offs[i + 1]] - o.state()[0]).max()
+            assert err <= 1e-6 * o.L, (k, i, err / o.L)

@@ -1,0 +1,77 @@
+"""Adaptive barrier stiffness on the GPU against the oracle (needs a GPU):
+the same kappa after every step (both sides take the rule's decisions on
+the same pair distances), trajectories within 1e-6 of the scene's bounding-box
+diagonal, alone and in a batch; the adjoint refuses contexts with the rule on."""
+import numpy as np
+import pytest
+
+import ipcscenes as S
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a ROCm GPU")]
+
+
+@pytest.mark.parametrize("max_newton", [1, 100])
+def test_adaptive_kappa_block(max_newton):
+    from paper_2609_25653_amd import Sim
+    n = 30
+    # PCG to 1e-10: with one Newton update per step the states are single
+    # unconverged updates, which agree only to the linear solve's tolerance
+    sc = S.tiny_scene("cube", h=0.01, n_steps=n, max_newton=max_newton, pcg_tol=1e-10)
+    o, sim = O.Oracle(sc), Sim(sc)
+    k0 = o.kappa
+    assert sim.scene_scalars()["kappa"] == pytest.approx(k0, rel=1e-13)
+    o.set_kappa_adaptive(0.8, 100.0)
+    sim.set_kappa_adaptive(0.8, 100.0)
+    for k in range(n):
+        rc, st = sim.step(allow_status=(3,))
+        rco, sto = o.step()
+        assert st[0]["status"] == sto["status"], (k, st[0], sto)
+        assert sim.scene_scalars()["kappa"] / k0 == pytest.approx(o.kappa / k0, rel=1e-13), k
+        err = np.abs(sim.state()[0].cpu().numpy() - o.state()[0]).max()
+        assert err <= 1e-6 * o.L, (k, err / o.L)
+    assert o.kappa >= 4.0 * k0
+
+
+def test_adaptive_kappa_batch():
+    """A block and the pad squeezing a box (contact on affine bodies)
+    stepped together, each scene with its own kappa."""
+    from paper_2609_25653_amd import Sim
+    n = 16
+    scenes = [S.tiny_scene("cube", h=0.01, n_steps=n), S.tiny_scene("pad_box", h=0.01, n_steps=n)]
+    sim = Sim(scenes)
+    orc = [O.Oracle(s) for s in scenes]
+    k0 = [o.kappa for o in orc]
+    for o in orc:
+        o.set_kappa_adaptive(0.8, 100.0)
+    sim.set_kappa_adaptive(0.8, 100.0)
+    off = sim.dof_offsets
+    for k in range(n):
+        rc, st = sim.step()
+        y = sim.state()[0].cpu().numpy()
+        for i, o in enumerate(orc):
+            assert o.step()[0] == 0
+            assert sim.scene_scalars(i)["kappa"] / k0[i] == pytest.approx(o.kappa / k0[i], rel=1e-13), (k, i)
+            assert np.abs(y[off[i]:off[i + 1]] - o.state()[0]).max() <= 1e-6 * o.L, (k, i)
+    assert all(o.kappa > k for o, k in zip(orc, k0))
+
+
+def test_adaptive_kappa_refused_by_the_adjoint_and_switched_off():
+    from paper_2609_25653_amd import IPCError, Sim
+    sc = S.tiny_scene("cube", h=0.01, n_steps=4)
+    sim = Sim(sc)
+    with pytest.raises(IPCError) as ei:
+        sim.set_kappa_adaptive(-1.0)
+    assert ei.value.code == 1
+    sim.set_kappa_adaptive(0.8)
+    y0, v0 = sim.state()
+    sim.step()
+    y1, _ = sim.state()
+    z = torch.zeros_like(y0)
+    with pytest.raises(IPCError) as ei:
+        sim.step_vjp(y0, v0, 0, y1, z, z)
+    assert ei.value.code == 1 and "kappa" in str(ei.value)
+    sim.set_kappa_adaptive(0.0)
+    sim.step_vjp(y0, v0, 0, y1, z, z)

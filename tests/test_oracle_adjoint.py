@@ -194,3 +194,26 @@ def test_rollout_gradient_matches_fd(kind):
     # recomputation from checkpoints reproduces the stored forward exactly
     loss3, Eb3, mb3 = run(E0, mu0, grad=True, checkpoint_every=3)
     assert loss3 == loss and np.array_equal(Eb3, Eb) and mb3 == mb
+
+
+def test_adjoint_indefinite_status():
+    """A strongly compressed stiff tetrahedron: M + h^2 H (unprojected) is
+    indefinite, and the adjoint PCG reports it (status 6) instead of a
+    solution, at every compression tried, inverted included."""
+    sc = ipcscenes.tiny_scene("tet", n_steps=2, h=0.1)
+    sc["tet_E"] = np.array([1e9])
+    sc["g"] = np.zeros(3)
+    o = O.Oracle(sc)
+    y0, v0 = o.state()
+    X = sc["X"]
+    c = X.mean(0)
+    H = np.zeros((12, 12))
+    for f in (0.5, 0.3, -0.2):
+        yn = (c + f * (X - c)).ravel()
+        for j in range(12):
+            e = np.zeros(12); e[j] = 1.0
+            o.set_state(y0, v0); o.begin_step(0)
+            H[:, j] = o.hess_matvec(yn, e, project=False)
+        assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() < 0          # indefinite indeed
+        rc = o.step_vjp(y0, v0, 0, yn, np.ones(12), np.zeros(12))[0]
+        assert rc == 6, f
