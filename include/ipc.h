@@ -105,6 +105,13 @@ typedef struct ipc_scene_desc {
      * points arrive with every step's targets (see ipc_begin_step) */
     int32_t nj;
     const int32_t *joint_spring;   /* nj spring indices (b side of kind 1) */
+    /* an analytic half-space ground {x : n . x >= c}, half_space = (n, c) with
+     * n a unit normal (|n|^2 within 1e-12 of 1), or n = 0 for none.  Every
+     * moving surface vertex (FEM or body) meets it with the barrier of
+     * Sec. III-C.1 on d = n . x - c, its lagged friction (normal n, tangent
+     * displacement (I - n n^T)(x - x^n)) and an exact CCD bound (the step at
+     * which d reaches ccd_s times its start value on the straight path). */
+    double half_space[4];
 } ipc_scene_desc;
 
 /* Per-scene statistics of the last ipc_step(). */

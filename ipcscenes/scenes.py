@@ -52,7 +52,7 @@ SCENE_KEYS = (
     "sp_ka", "sp_ia", "sp_xa", "sp_kb", "sp_ib", "sp_xb", "sp_k",
     "driven_body", "drive_q", "joint_spring", "joint_xbar",
     "h", "g", "dhat", "kappa", "mu", "eps_v", "newton_tol", "max_newton",
-    "pcg_tol", "max_pcg", "ccd_s", "n_steps",
+    "pcg_tol", "max_pcg", "ccd_s", "n_steps", "half_space",
 )
 
 INT_KEYS = {"tets", "vobj", "body_obj", "bv_body", "btri", "stri", "obj_kind",
@@ -294,7 +294,8 @@ class _Builder:
 
 def _params(**kw):
     p = dict(h=0.01, g=np.array([0.0, 0.0, -9.81]), dhat=1e-3, kappa=0.0, mu=0.3, eps_v=1e-3,
-             newton_tol=1e-6, max_newton=100, pcg_tol=1e-4, max_pcg=20000, ccd_s=0.1, n_steps=20)
+             newton_tol=1e-6, max_newton=100, pcg_tol=1e-4, max_pcg=20000, ccd_s=0.1, n_steps=20,
+             half_space=np.zeros(4))
     p.update(kw)
     return p
 
@@ -470,17 +471,30 @@ def _add_arm_gripper(b, rng, *, center_xy, z_mid, inner_half_gap, pad_cells, pad
 # --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------
-def block_drop(seed=0, n_steps=20):
-    """Soft 5x5x5-cell block (625 tets) dropped 2 mm onto a static plane."""
+def block_drop(seed=0, n_steps=20, ground="triangles"):
+    """Soft 5x5x5-cell block (625 tets) dropped 2 mm onto a static plane:
+    two static triangles (ground="triangles") or the analytic half-space
+    z >= 0 (ground="half_space")."""
     rng = np.random.Generator(np.random.PCG64(seed))
     b = _Builder()
     n = 5
     X = grid_vertices(n, n, n, (0.3 - 0.025, 0.3 - 0.025, 0.002), (0.01, 0.01, 0.01))
     X = X + rng.uniform(-1e-4, 1e-4, size=X.shape)
     b.add_fem(X, orient(X, hex_tets(n, n, n)), 1e5, 0.45, 1000.0)
-    b.add_static(*ground_quad())
-    p = _params(h=0.01, dhat=1e-3, mu=0.3, n_steps=n_steps)
+    hs = _ground(b, ground)
+    p = _params(h=0.01, dhat=1e-3, mu=0.3, n_steps=n_steps, half_space=hs)
     return b.finish(p, np.zeros((n_steps, 0, 12)))
+
+
+def _ground(b, ground):
+    """The ground at z = 0: two static triangles, or the half-space (its
+    (n, c) is returned; zeros for triangles)."""
+    if ground == "triangles":
+        b.add_static(*ground_quad())
+        return np.zeros(4)
+    if ground == "half_space":
+        return np.array([0.0, 0.0, 1.0, 0.0])
+    raise ValueError(ground)
 
 
 def gripper_squeeze(seed=0, n_steps=200, pad_cells=(20, 10, 10), pad_E=2e5, mu=0.5, h=0.005):
@@ -570,10 +584,14 @@ def tiny_scene(kind="tet", seed=0, **kw):
     pad_box  a 2x1x1-cell pad squeezing a small affine box (springs, bodies, contact)
     arm_box  pad_box's squeeze on the joint-space arm (joint springs)
     free_body one affine box (4 cm, 0.2 kg) with contact geometry and nothing to touch
+
+    ground="half_space" replaces the two ground triangles of cube, edge_tet,
+    pad_box and arm_box by the analytic half-space z >= 0.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     b = _Builder()
     drive = None
+    ground = kw.pop("ground", "triangles")
     p = _params(n_steps=kw.pop("n_steps", 4), **kw)
     if kind == "tet":
         X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], np.float64) * 0.01 + 0.3
@@ -586,14 +604,14 @@ def tiny_scene(kind="tet", seed=0, **kw):
         X = grid_vertices(2, 2, 2, (0.29, 0.29, 0.0015), (0.01, 0.01, 0.01))
         X = X + rng.uniform(-1e-4, 1e-4, size=X.shape)
         b.add_fem(X, orient(X, hex_tets(2, 2, 2)), 1e5, 0.45, 1000.0)
-        b.add_static(*ground_quad())
+        p["half_space"] = _ground(b, ground)
     elif kind == "edge_tet":
         # one tetrahedron resting on an edge 0.6 mm above the ground's diagonal
         # edge and about 1 degree off parallel to it
         X = np.array([[0.005, -0.005, 0.0], [-0.005, 0.005 + 2.5e-4, 0.0],
                       [0.005, 0.005, 0.008], [-0.005, -0.005, 0.008]], np.float64) + [0.0, 0.0, 6e-4]
         b.add_fem(X, orient(X, np.array([[0, 1, 2, 3]], np.int32)), 1e5, 0.4, 1000.0)
-        b.add_static(*ground_quad())
+        p["half_space"] = _ground(b, ground)
     elif kind == "free_body":
         b.add_body((0.3, 0.3, 0.5), (0.04, 0.04, 0.04), 0.2, contact=True)
     elif kind == "arm_box":
@@ -601,13 +619,13 @@ def tiny_scene(kind="tet", seed=0, **kw):
         drive, _, _ = _add_arm_gripper(b, rng, center_xy=(0.3, 0.3), z_mid=0.01 + 5e-4, inner_half_gap=0.0115,
                                        pad_cells=(4, 2, 2), pad_E=1e5, pad_nu=0.45, n_steps=int(p["n_steps"]),
                                        h=p["h"], t_close=0.5, v_close=0.01, v_lift=0.02)
-        b.add_static(*ground_quad())
+        p["half_space"] = _ground(b, ground)
     elif kind == "pad_box":
         b.add_body((0.3, 0.3, 0.01 + 5e-4), (0.02, 0.02, 0.02), 0.05, contact=True)
         drive, _, _ = _add_gripper(b, rng, center_xy=(0.3, 0.3), z_mid=0.01 + 5e-4, inner_half_gap=0.0115,
                                    pad_cells=(4, 2, 2), pad_E=1e5, pad_nu=0.45, n_steps=int(p["n_steps"]),
                                    h=p["h"], t_close=0.5, v_close=0.01, v_lift=0.02)
-        b.add_static(*ground_quad())
+        p["half_space"] = _ground(b, ground)
     else:
         raise ValueError(kind)
     if drive is None:

@@ -43,7 +43,7 @@ class SceneDesc(ctypes.Structure):
         ("h", ctypes.c_double), ("g", ctypes.c_double * 3), ("dhat", ctypes.c_double), ("kappa", ctypes.c_double),
         ("mu", ctypes.c_double), ("eps_v", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("pcg_tol", ctypes.c_double), ("ccd_s", ctypes.c_double), ("max_newton", ctypes.c_int32),
-        ("max_pcg", ctypes.c_int32), ("nj", ctypes.c_int32), ("joint_spring", _I)]
+        ("max_pcg", ctypes.c_int32), ("nj", ctypes.c_int32), ("joint_spring", _I), ("half_space", ctypes.c_double * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -143,4 +143,7 @@ def make_desc(sc, keep):
         setattr(d, k, float(sc[k]))
     d.max_newton = int(sc["max_newton"])
     d.max_pcg = int(sc["max_pcg"])
+    hs = np.asarray(sc.get("half_space", np.zeros(4)), np.float64).ravel()
+    for k in range(4):
+        d.half_space[k] = float(hs[k])
     return d

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libipc_hip.so")
-SOURCES = ["ipc_create.hip", "ipc_elastic.hip", "ipc_contact.hip", "ipc_solver.hip", "ipc_coarse.hip", "ipc_adjoint.hip", "ipc_api.hip", "ipc_dualmesh.hip"]
+SOURCES = ["ipc_create.hip", "ipc_elastic.hip", "ipc_contact.hip", "ipc_solver.hip", "ipc_coarse.hip", "ipc_adjoint.hip", "ipc_api.hip", "ipc_dualmesh.hip", "ipc_halfspace.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast-honor-pragmas",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]

@@ -258,6 +258,7 @@ void setup_after_create(ipc_ctx *c)
     upload_seg_region(c, R_TRI, c->seg_tri);
     upload_seg_region(c, R_EDGE, c->seg_edge);
     upload_seg_region(c, R_CDOM, c->seg_cdom);
+    upload_seg_region(c, R_HS, c->seg_hs);
     build_dyn_blocks(c);   // no pairs yet: row pointers and the long rows of the static pattern
     sync(c);
 }
@@ -277,6 +278,7 @@ void eval_energy(ipc_ctx *c, const double *y, bool from_candidates)
     launch_spring(c, 0, y, nullptr, D.sp_part.p, D.h2s.p);
     launch_barrier(c, 0, from_candidates, D.xw.p, false);
     if (c->fr_on) launch_friction(c, 0, D.xw.p);
+    launch_hs(c, 0, D.xw.p);
     int64_t npt = from_candidates ? c->n_cand_pt : c->n_pt, nee = from_candidates ? c->n_cand_ee : c->n_ee;
     // the per-pair values are pre-summed in chunks of 64, so that a scene's
     // reduction reads its chunk sums and at most 126 single entries
@@ -303,6 +305,13 @@ void eval_energy(ipc_ctx *c, const double *y, bool from_candidates)
     fp.w64 = fe.w64 = D.fr_w64.p;
     add(fp, -1, 2);
     add(fe, -1, 2);
+    if (c->M_HS) {   // the half-space's barrier and friction
+        RedSrc hb = src(D.hs_part.p, seg_ptr(c, R_HS), 0, 0), hf = src(c->fr_on ? D.hs_fpart.p : nullptr, seg_ptr(c, R_HS), 0, 0);
+        hb.w64 = D.hs_w64.p;
+        hf.w64 = D.hs_fw64.p;
+        add(hb, -1, 1);
+        add(hf, -1, 2);
+    }
     a.slot1 = S_E_BAR;
     a.slot2 = S_E_FR;
     a.total = S_E;
@@ -331,6 +340,7 @@ void eval_grad_hess(ipc_ctx *c, const double *y, double *g, bool hess, bool proj
     contact_grad_begin(c);
     launch_barrier(c, hess ? 2 : 1, false, D.xw.p, project);
     if (c->fr_on) launch_friction(c, hess ? 2 : 1, D.xw.p);
+    launch_hs(c, hess ? 2 : 1, D.xw.p);
     contact_grad_end(c, g);
     if (hess) build_dyn_blocks(c);
 }
@@ -978,6 +988,10 @@ extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *
         f.src[f.nsrc++] = src(c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LPT), 0, 0);
         f.src[f.nsrc++] = src(c->n_lag - c->n_lag_pt ? D.fr_part.p : nullptr, seg_ptr(c, R_LEE), (int)c->n_lag_pt, 0);
         f.src[0].w64 = f.src[1].w64 = D.fr_w64.p;
+        if (c->M_HS) {
+            f.src[f.nsrc] = src(D.hs_fpart.p, seg_ptr(c, R_HS), 0, 0);
+            f.src[f.nsrc++].w64 = D.hs_fw64.p;
+        }
         f.slot = S_MUBAR;
         reduce(c, f);
         if (mubar_dev)
@@ -1018,13 +1032,20 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
     if (kappa_adapt) launch_kappa_update(c, D.xw.p, true);   // pairs and world positions at y^n
     // energy at the start
     eval_energy(c, D.y.p, false);
-    std::vector<double> sc = read_scal(c);
+    std::vector<double> sc((size_t)ns * NSLOT);
+    std::vector<int> hs_nlag(ns, 0);
+    {
+        HostReads rd(c);
+        rd.add(sc.data(), D.scal.p, sc.size() * sizeof(double));
+        if (c->M_HS) rd.add(hs_nlag.data(), D.hs_nlag.p, ns * sizeof(int));
+        rd.wait();
+    }
     std::vector<double> E0(ns);
     for (int s = 0; s < ns; ++s) {
         E0[s] = sc[(size_t)s * NSLOT + S_E];
         if (sc[(size_t)s * NSLOT + S_INF] != 0.0) { S[s].status = IPC_E_INTERSECTING; on[s] = 0; }
         S[s].energy = E0[s];
-        S[s].n_lag = (c->h_pt_seg[s + 1] - c->h_pt_seg[s]) + (c->h_ee_seg[s + 1] - c->h_ee_seg[s]);
+        S[s].n_lag = (c->h_pt_seg[s + 1] - c->h_pt_seg[s]) + (c->h_ee_seg[s + 1] - c->h_ee_seg[s]) + hs_nlag[s];
     }
     int max_newton = 0;
     for (auto &si : c->sc) max_newton = std::max(max_newton, si.max_newton);

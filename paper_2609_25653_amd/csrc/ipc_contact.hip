@@ -1170,6 +1170,7 @@ __global__ void k_lag_slots(int n, int nnzb, int ncv, const int4 *__restrict__ l
 void launch_lag(ipc_ctx *c, const double *xw, const double *xref)
 {
     Dev &D = c->d;
+    launch_hs_lag(c, xw, xref);
     int64_t n = c->n_pt + c->n_ee;
     if (n > c->cap_lag) {
         if (c->ws.base)
@@ -1386,13 +1387,17 @@ void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const doubl
     Dev &D = c->d;
     int64_t n = c->n_lag;
     D.fr_part.alloc(n + 1);
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_lag_vjp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, (int)c->n_lag_pt, D.lag_cv.p, D.lag_type.p,
-                       D.lag_ex.p, xw, xwn, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, w, D.lag_g.p,
-                       D.fr_part.p);
-    // per-vertex values summed per contact vertex, then into ybar
+    if (n == 0 && !c->M_HS) return;
+    // per-vertex values summed per contact vertex (the pairs' through run
+    // sums, then the half-space entries'), then into ybar
     contact_grad_begin(c);
-    runsum<3>(c, 4 * n, c->CV, D.lg_key2.p, D.lg_code2.p, ValVec3{D.lag_g.p}, EmitAdd3{D.gcv.p});
+    if (n) {
+        hipLaunchKernelGGL(k_lag_vjp, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)n, (int)c->n_lag_pt, D.lag_cv.p, D.lag_type.p,
+                           D.lag_ex.p, xw, xwn, D.cv_scene.p, D.sparam.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, w,
+                           D.lag_g.p, D.fr_part.p);
+        runsum<3>(c, 4 * n, c->CV, D.lg_key2.p, D.lg_code2.p, ValVec3{D.lag_g.p}, EmitAdd3{D.gcv.p});
+    }
+    launch_hs_lag_vjp(c, xw, xwn, w);
     contact_grad_end(c, ybar);
 }
 
@@ -1781,6 +1786,7 @@ __global__ void k_ccd(int npt, int nee, const int2 *__restrict__ pt, const int2 
 void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1)
 {
     Dev &D = c->d;
+    launch_hs_ccd(c, xw0, xw1);
     int64_t n = c->n_cand_pt + c->n_cand_ee;
     if (n == 0) return;
     prof_begin(c, IPC_K_CCD);
@@ -1843,6 +1849,7 @@ void launch_kappa_update(ipc_ctx *c, const double *xw, bool first)
     Dev &D = c->d;
     hipStream_t st = c->stream;
     hipLaunchKernelGGL(k_set_slot_c, dim3(blocks_for(c->n_scenes, 64)), dim3(64), 0, st, c->n_scenes, D.scal.p, S_DMIN, INFINITY);
+    launch_hs_dmin(c, xw);
     int64_t n = c->n_pt + c->n_ee;
     if (n)
         hipLaunchKernelGGL(k_pair_dmin, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)c->n_pt, (int)c->n_ee, D.pt.p, D.ee.p, D.tri.p,

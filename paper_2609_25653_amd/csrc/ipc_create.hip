@@ -13,6 +13,7 @@
 
 #include "ipc_device.h"
 #include "ipc_internal.h"
+#include "ipc_kernels.h"
 #include "ipc_runsum.h"
 
 namespace ipc {
@@ -176,6 +177,12 @@ void validate(const ipc_scene_desc &s, int si)
     if (!(s.h > 0) || !(s.dhat > 0) || !(s.mu >= 0) || !(s.eps_v > 0) || !(s.newton_tol > 0) || !(s.pcg_tol > 0) ||
         !(s.ccd_s > 0 && s.ccd_s < 1) || s.max_newton < 1 || s.max_pcg < 1)
         fail(pre + "invalid parameters");
+    {
+        const double *q = s.half_space, n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(q[k])) fail(pre + "invalid half-space");
+        if (n2 != 0.0 && !(std::fabs(n2 - 1.0) <= 1e-12)) fail(pre + "half-space normal is not a unit vector");
+    }
     if (!finite_all(s.X, 3 * (size_t)s.nv) || !finite_all(s.V, 3 * (size_t)s.nv)) fail(pre + "non-finite FEM state");
     for (int e = 0; e < s.nt; ++e) {
         for (int k = 0; k < 4; ++k)
@@ -305,6 +312,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         S.h = d.h; S.g[0] = d.g[0]; S.g[1] = d.g[1]; S.g[2] = d.g[2]; S.dhat = d.dhat; S.kappa = d.kappa; S.mu = d.mu;
         S.eps_v = d.eps_v; S.newton_tol = d.newton_tol; S.pcg_tol = d.pcg_tol; S.ccd_s = d.ccd_s;
         S.max_newton = d.max_newton; S.max_pcg = d.max_pcg;
+        for (int k = 0; k < 4; ++k) S.hs[k] = d.half_space[k];
+        S.hs_on = d.half_space[0] != 0.0 || d.half_space[1] != 0.0 || d.half_space[2] != 0.0;
         topo[s] = topology(d);
         S.node0 = node; S.nnode = d.nv + 4 * d.nb; S.nnode_pad = pad64(S.nnode);
         S.tet0 = tet; S.nt_pad = pad64(d.nt);
@@ -533,6 +542,20 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         c->seg_sp[s] = c->sc[s].sp0; c->seg_body[s] = c->sc[s].body0;
     }
     c->seg_surf[n] = cv; c->seg_tri[n] = tri; c->seg_edge[n] = edge; c->seg_sp[n] = sp; c->seg_body[n] = body;
+    // half-space entries: the moving surface vertices of each scene that has one
+    std::vector<int> hs_cv;
+    std::vector<double> hs_plane(4 * (size_t)n, 0.0);
+    c->seg_hs.assign(n + 1, 0);
+    for (int s = 0; s < n; ++s) {
+        const SceneInfo &S = c->sc[s];
+        c->seg_hs[s] = (int)hs_cv.size();
+        for (int k = 0; k < 4; ++k) hs_plane[4 * (size_t)s + k] = S.hs[k];
+        if (!S.hs_on) continue;
+        for (int i = 0; i < S.ncv; ++i)
+            if (S.surf_ext[i] < scenes[s].nv + scenes[s].nbv) hs_cv.push_back(S.cv0 + i);
+    }
+    c->seg_hs[n] = (int)hs_cv.size();
+    c->M_HS = (int64_t)hs_cv.size();
 
     // Entry lists of the deterministic run sums (ipc_runsum.h), built once:
     //  spring gradients: code 8 s + 4 side + q -> node, sorted by node;
@@ -578,6 +601,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         const int64_t Pp = std::max<int64_t>(std::max(tri, edge), 1), Q = std::max<int64_t>(std::max(cv, edge), 1);
         const int64_t NW = std::max<int64_t>(C, N) / TILE + 1, PC = std::max(P, C);
         const int64_t ndom = N / (CG_AGG * CG_DOM) + 2 * (int64_t)n, ngrp = N / CG_AGG + 2 * (int64_t)n;
+        const int64_t MH = std::max<int64_t>(c->M_HS, 1);
         const std::vector<int64_t> nbuf = {
             // nodes: state, predictor and solver vectors (14 x 3 doubles), kinds, maps, mass, inverse blocks
             14 * 24 * N, 4 * N, 4 * N, 4 * (int64_t)(dof / 3) + 4, 8 * N, 72 * N, 8 * (N / TILE + 1), 4 * N, 4 * N,
@@ -617,8 +641,11 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
             4 * (2 * P + 1), 4 * (2 * P + 1), 16 * B, 7 * 4 * (B + 1), 144 * B, 16,
             // run sums, PCG long rows and partials
             2 * 8 * (9 * (16 * P / TILE + 1) + 1), 8 * (N + 65), 8 * (N / TILE + 1), 32 * (N / TILE + 1), 4 * (N + 1),
+            // half-space entries: list, planes, energies and chunk sums, lag, Hessian blocks, slot entries
+            4 * MH, 32 * (int64_t)n, 8 * (MH + 1), 8 * (MH + 1), 8 * (MH / TILE + 1), 8 * (MH / TILE + 1), 8 * MH, 24 * MH,
+            72 * MH, 4 * 4 * 16 * MH, 4 * (int64_t)n,
             // sort and scan storage (rocprim: a copy of keys and values plus per-block counts), bounded
-            16 * std::max<int64_t>(std::max(16 * P, B), std::max(Pp, Q)) + (4 << 20)};
+            16 * std::max<int64_t>(std::max(std::max(16 * P, 16 * MH), B), std::max(Pp, Q)) + (4 << 20)};
         size_t bytes = 0;
         for (int64_t b : nbuf) bytes += Arena::round((size_t)std::max<int64_t>(b, 1));
         *plan = bytes + bytes / 16 + (1 << 20);   // 6 % and 1 MiB against fragmentation of the free list
@@ -656,6 +683,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
     D.cv_node.upload(cv_node, st); D.cv_body.upload(cv_body, st); D.cv_obj.upload(cv_obj, st); D.cv_scene.upload(cv_scene, st);
     D.cv_x.upload(cv_x, st);
     D.xw.alloc(3 * (size_t)std::max(cv, 1)); D.xw1.alloc(3 * (size_t)std::max(cv, 1));
+    D.hs_cv.upload(hs_cv, st); D.hs_plane.upload(hs_plane, st);
+    hs_setup(c);
     D.tri.upload(tri4, st); D.edge.upload(edge2, st); D.edge_rest2.upload(rest2, st);
     D.obj_kind.upload(okind, st); D.excl.upload(excl, st);
     D.scal.alloc((size_t)n * NSLOT); D.scal.zero(st, (size_t)n * NSLOT);

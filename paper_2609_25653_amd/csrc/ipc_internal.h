@@ -57,6 +57,7 @@ enum Region {
     R_LPT, R_LEE,   // friction lag lists
     R_LONG,         // rows of the product handled one wavefront per row
     R_CDOM,         // domains of the coarse preconditioner
+    R_HS,           // vertices that meet the scene's half-space
     NREGION
 };
 
@@ -70,18 +71,19 @@ struct RedSrc {
     int base;
     const double *w64 = nullptr;   // optional sums of v[64 k .. 64 k + 63] (whole chunks are read from here)
 };
-// Per-scene reduction of up to 8 sources.  Each source's sum can be stored in
+constexpr int RED_MAX = 10;
+// Per-scene reduction of up to RED_MAX sources.  Each source's sum can be stored in
 // its own slot; the sources of group g (grp[k] = g) are combined in source
 // order into the slot of that group (slot, slot1, slot2).
 struct RedArgs {
-    RedSrc src[8];
+    RedSrc src[RED_MAX];
     int nsrc = 0;
     int slot = -1;          // total of group 0 (-1: none)
     int slot1 = -1;         // total of group 1
     int slot2 = -1;         // total of group 2
     int acc = 0;            // accumulate into the group-0 slot
-    int slots[8] = {-1, -1, -1, -1, -1, -1, -1, -1};   // per-source sums (-1: none)
-    int grp[8] = {0, 0, 0, 0, 0, 0, 0, 0};             // group of each source (-1: none)
+    int slots[RED_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1};   // per-source sums (-1: none)
+    int grp[RED_MAX] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};             // group of each source (-1: none)
     int op = 0;             // 0 sum, 1 max
     int total = -1;         // slot of the combination of every source in source order (-1: none)
 };
@@ -213,6 +215,8 @@ struct SceneInfo {
     double h, g[3], dhat, kappa, mu, eps_v, newton_tol, pcg_tol, ccd_s;
     int max_newton, max_pcg;
     double L, thr, mbar;
+    double hs[4];                    // half-space (n, c); hs_on when n != 0
+    bool hs_on;
     // host topology in the scene's vertex numbering (for the pair export)
     std::vector<int> tri_ext, edge_ext, surf_ext;
 };
@@ -302,6 +306,11 @@ struct Dev {
     DBuf<int> lag_key2, lag_code2;         // the same sorted by slot (stable)
     DBuf<unsigned char> lag_sort_tmp;
     // scalars and partials
+    // half-space ground: entries (moving surface vertices of scenes with
+    // one), the planes, per-entry energies, lag data, Hessian blocks and
+    // their sorted slot entries, lagged contacts per scene
+    DBuf<int> hs_cv, hs_key, hs_code, hs_key2, hs_code2, hs_nlag;
+    DBuf<double> hs_plane, hs_part, hs_fpart, hs_w64, hs_fw64, hs_lam, hs_xn, hs_H;
     DBuf<double> scal;                     // n_scenes x NSLOT
     DBuf<double> part_node, part_tet;      // one partial per wavefront
     DBuf<int> seg;                         // scratch segment offsets (broad phase)
@@ -371,7 +380,8 @@ struct ipc_ctx {
     int64_t ext_nodes = 0;
     int64_t ext_tets = 0;
     // host copies of segment tables
-    std::vector<int> seg_surf, seg_tri, seg_edge, seg_sp, seg_body;
+    std::vector<int> seg_surf, seg_tri, seg_edge, seg_sp, seg_body, seg_hs;
+    int64_t M_HS = 0;                      // half-space entries: moving surface vertices of scenes with one
     // dynamic counts
     int64_t cap_cand_pt = 0, cap_cand_ee = 0, n_cand_pt = 0, n_cand_ee = 0;
     int64_t cap_pt = 0, cap_ee = 0, n_pt = 0, n_ee = 0, cap_lag = 0, n_lag = 0;

@@ -51,6 +51,13 @@ int bits_for(int64_t n);
 void build_dyn_blocks(ipc_ctx *c);
 void launch_ccd(ipc_ctx *c, const double *xw0, const double *xw1);
 void launch_kappa_update(ipc_ctx *c, const double *xw, bool first);
+// half-space ground
+void hs_setup(ipc_ctx *c);
+void launch_hs(ipc_ctx *c, int mode, const double *xw);
+void launch_hs_lag(ipc_ctx *c, const double *xw, const double *xref);
+void launch_hs_ccd(ipc_ctx *c, const double *xw0, const double *xw1);
+void launch_hs_dmin(ipc_ctx *c, const double *xw);
+void launch_hs_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const double *w);
 
 // adjoint of the friction lag: ybar -= (dG_F/dy^n)^T w; per-pair w . dG/dmu into fr_part
 void launch_lag_vjp(ipc_ctx *c, const double *xw, const double *xwn, const double *w, double *ybar);

@@ -23,14 +23,14 @@ namespace ipc {
 __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__restrict__ scal)
 {
     int s = blockIdx.x;
-    __shared__ double sh[8][BLOCK / TILE];
+    __shared__ double sh[RED_MAX][BLOCK / TILE];
     int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
     // all loads first (independent, in flight together), then the shuffles:
     // the first 4 strided partials of every source are loaded unconditionally
     // (predicated), the rest (scenes with more than 1024 partials) in a loop
-    double part[8];
+    double part[RED_MAX];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < RED_MAX; ++k) {
         part[k] = 0.0;
         if (k >= a.nsrc) continue;
         const RedSrc &r = a.src[k];
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) k_reduce(int ns, RedArgs a, double *__res
         part[k] = a.op ? fmax(acc, 0.0) : acc;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < RED_MAX; ++k) {
         if (k >= a.nsrc) break;
         double v = a.op ? wave_max(part[k]) : wave_sum(part[k]);
         if (lane == 0) sh[k][wave] = v;

@@ -48,6 +48,9 @@ CASES = {
     "tet index out of range": (lambda sc: sc["tets"].__setitem__((2, 1), len(sc["X"])), "tet index out of range"),
     "time step 0": (lambda sc: sc.__setitem__("h", np.asarray(0.0)), "invalid parameters"),
     "ccd fraction 1": (lambda sc: sc.__setitem__("ccd_s", np.asarray(1.0)), "invalid parameters"),
+    "half-space normal of length 2": (lambda sc: sc.__setitem__("half_space", np.array([0.0, 0.0, 2.0, 0.0])),
+                                      "half-space normal is not a unit vector"),
+    "NaN half-space offset": (lambda sc: sc.__setitem__("half_space", np.array([0.0, 0.0, 1.0, np.nan])), "invalid half-space"),
 }
 
 

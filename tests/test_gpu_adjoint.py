@@ -22,15 +22,18 @@ pytestmark = [pytest.mark.gpu,
 
 
 def _scene(kind):
-    if kind == "pad_box":
-        return S.tiny_scene("pad_box", n_steps=30)
-    sc = S.tiny_scene(kind, n_steps=12)
+    if kind in ("pad_box", "pad_box_hs"):
+        return S.tiny_scene("pad_box", n_steps=30, ground="half_space" if kind == "pad_box_hs" else "triangles")
+    if kind == "cube_hs":   # the block sliding on the analytic half-space
+        sc = S.tiny_scene("cube", n_steps=12, ground="half_space")
+    else:
+        sc = S.tiny_scene(kind, n_steps=12)
     sc["V"] = np.array(sc["V"])
-    sc["V"][:, 0], sc["V"][:, 1] = (0.05, 0.02) if kind == "cube" else (0.03, 0.01)
+    sc["V"][:, 0], sc["V"][:, 1] = (0.05, 0.02) if kind in ("cube", "cube_hs") else (0.03, 0.01)
     return sc
 
 
-PRE = {"cube": 6, "edge_tet": 2, "pad_box": 20}
+PRE = {"cube": 6, "cube_hs": 6, "edge_tet": 2, "pad_box": 20, "pad_box_hs": 20}
 
 
 def _close(a, ref, rel):
@@ -41,7 +44,7 @@ def _close(a, ref, rel):
     assert err <= rel * scale, f"max err {err:.3g} vs scale {scale:.3g} ({err / scale:.3g} relative)"
 
 
-@pytest.mark.parametrize("kind", ["cube", "edge_tet", "pad_box"])
+@pytest.mark.parametrize("kind", ["cube", "edge_tet", "pad_box", "cube_hs", "pad_box_hs"])
 def test_step_vjp_matches_oracle(kind):
     from paper_2609_25653_amd import Sim
     sc = _scene(kind)

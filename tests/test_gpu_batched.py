@@ -146,3 +146,26 @@ def test_batch_wider_than_one_workgroup():
             assert st[i]["n_lag"] == sto["n_lag"] > 0, (k, i, st[i]["n_lag"], sto["n_lag"])
             err = np.abs(yb[offs[i]:offs[i + 1]] - o.state()[0]).max()
             assert err <= 1e-6 * o.L, (k, i, err / o.L)
+
+
+def test_batched_with_half_space_scenes():
+    """Scenes on the analytic half-space batched with scenes on ground
+    triangles (a scene without a half-space contributes no entries)."""
+    from paper_2609_25653_amd import Sim
+    n = 10
+    scenes = [S.tiny_scene("pad_box", ground="half_space", h=0.01, n_steps=n),
+              S.tiny_scene("cube", h=0.01, n_steps=n),
+              S.block_drop(n_steps=n, ground="half_space"),
+              S.tiny_scene("pad_box", seed=2, h=0.01, n_steps=n)]
+    batch = Sim(scenes)
+    oracles = [O.Oracle(s) for s in scenes]
+    offs = batch.dof_offsets
+    for k in range(n):
+        rc, st = batch.step()
+        assert rc == 0, st
+        yb = batch.state()[0].cpu().numpy()
+        for i, o in enumerate(oracles):
+            rco, so = o.step()
+            assert rco == 0
+            assert st[i]["n_lag"] == so["n_lag"], (k, i, st[i]["n_lag"], so["n_lag"])
+            assert np.abs(yb[offs[i]:offs[i + 1]] - o.state()[0]).max() <= 1e-6 * o.L, (k, i)

@@ -36,11 +36,13 @@ def test_adaptive_kappa_block(max_newton):
 
 
 def test_adaptive_kappa_batch():
-    """A block and the pad squeezing a box (contact on affine bodies)
-    stepped together, each scene with its own kappa."""
+    """A block, the pad squeezing a box (contact on affine bodies) and a
+    block on the half-space (whose distances enter the rule too) stepped
+    together, each scene with its own kappa."""
     from paper_2609_25653_amd import Sim
     n = 16
-    scenes = [S.tiny_scene("cube", h=0.01, n_steps=n), S.tiny_scene("pad_box", h=0.01, n_steps=n)]
+    scenes = [S.tiny_scene("cube", h=0.01, n_steps=n), S.tiny_scene("pad_box", h=0.01, n_steps=n),
+              S.tiny_scene("cube", ground="half_space", h=0.01, n_steps=n)]
     sim = Sim(scenes)
     orc = [O.Oracle(s) for s in scenes]
     k0 = [o.kappa for o in orc]

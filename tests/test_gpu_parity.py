@@ -20,11 +20,35 @@ pytestmark = [pytest.mark.gpu,
 
 rng = np.random.default_rng(99)
 
+def _rotation(a, u):
+    u = np.asarray(u, np.float64) / np.linalg.norm(u)
+    K = np.array([[0.0, -u[2], u[1]], [u[2], 0.0, -u[0]], [-u[1], u[0], 0.0]])
+    return np.eye(3) + np.sin(a) * K + (1.0 - np.cos(a)) * (K @ K)
+
+
+def tilted_cube(n_steps):
+    """The block on the half-space, turned by a rotation off every axis
+    (mesh, gravity and normal) and pushed sideways, so that the barrier,
+    friction and CCD of the half-space see a general normal."""
+    sc = S.tiny_scene("cube", ground="half_space", h=0.01, n_steps=n_steps)
+    R = _rotation(0.6, [1.0, 2.0, -0.5])
+    sc["V"] = np.tile([0.05, -0.02, 0.0], (len(sc["X"]), 1)) @ R.T
+    sc["X"] = sc["X"] @ R.T
+    sc["g"] = R @ sc["g"]
+    n = R @ np.array([0.0, 0.0, 1.0])
+    sc["half_space"] = np.array([n[0], n[1], n[2], 0.0])
+    return sc
+
+
 CASES = {
     "block": (lambda: S.block_drop(n_steps=8), [0, 2, 6]),
     "cube": (lambda: S.tiny_scene("cube", h=0.01, n_steps=8), [0, 6]),
     "pad_box": (lambda: S.tiny_scene("pad_box", h=0.01, n_steps=34), [0, 20, 32]),
     "arm_box": (lambda: S.tiny_scene("arm_box", h=0.01, n_steps=17), [0, 8, 16]),
+    # the analytic half-space ground in place of the ground triangles
+    "cube_hs": (lambda: S.tiny_scene("cube", ground="half_space", h=0.01, n_steps=8), [0, 6]),
+    "tilted_hs": (lambda: tilted_cube(8), [0, 3, 6]),
+    "pad_box_hs": (lambda: S.tiny_scene("pad_box", ground="half_space", h=0.01, n_steps=34), [0, 20, 32]),
 }
 
 
@@ -108,7 +132,7 @@ def test_ccd(name, states):
 
 
 @pytest.mark.parametrize("coarse", [False, True])
-@pytest.mark.parametrize("name", ["block", "pad_box", "arm_box"])
+@pytest.mark.parametrize("name", ["block", "pad_box", "arm_box", "pad_box_hs"])
 def test_pcg(name, coarse, states, monkeypatch):
     """The solution of H x = b agrees with the oracle's PCG.  With the block-
     Jacobi preconditioner alone (the coarse correction switched off) the
@@ -132,13 +156,21 @@ def test_pcg(name, coarse, states, monkeypatch):
 
 
 @pytest.mark.parametrize("coarse", [False, True])
-@pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34), ("arm_box", 30)])
+@pytest.mark.parametrize("name,n", [("block", 20), ("pad_box", 34), ("arm_box", 30), ("block_hs", 20), ("tilted_hs", 16),
+                                    ("pad_box_hs", 34)])
 def test_trajectory(name, n, coarse, monkeypatch):
     """Steps agree with the oracle with the PCG's coarse correction switched
     off and on (these small scenes leave it off by default)."""
     from paper_2609_25653_amd import Sim
     monkeypatch.setenv("IPC_PCG_COARSE", "1" if coarse else "0")
-    sc = S.block_drop(n_steps=n) if name == "block" else S.tiny_scene(name, h=0.01, n_steps=n)
+    if name in ("block", "block_hs"):
+        sc = S.block_drop(n_steps=n, ground="half_space" if name == "block_hs" else "triangles")
+    elif name == "tilted_hs":
+        sc = tilted_cube(n)
+    elif name == "pad_box_hs":
+        sc = S.tiny_scene("pad_box", ground="half_space", h=0.01, n_steps=n)
+    else:
+        sc = S.tiny_scene(name, h=0.01, n_steps=n)
     sim = Sim(sc)
     assert sim.pcg_coarse == coarse
     o = O.Oracle(sc)

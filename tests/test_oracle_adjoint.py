@@ -20,8 +20,8 @@ import oracle as O
 
 
 def _scene(kind):
-    if kind == "cube":
-        sc = ipcscenes.tiny_scene("cube", n_steps=12)
+    if kind in ("cube", "cube_hs"):   # on the ground triangles / the half-space z >= 0
+        sc = ipcscenes.tiny_scene("cube", n_steps=12, ground="half_space" if kind == "cube_hs" else "triangles")
         vel = (0.05, 0.02)
     elif kind == "edge_tet":
         sc = ipcscenes.tiny_scene("edge_tet", n_steps=6)
@@ -33,7 +33,7 @@ def _scene(kind):
     return sc
 
 
-PRE = {"cube": 6, "edge_tet": 2, "pad_box": 20}
+PRE = {"cube": 6, "cube_hs": 6, "edge_tet": 2, "pad_box": 20}
 _CACHE = {}
 
 
@@ -61,7 +61,7 @@ def _phi(o, n, y_prev, v_prev, y_next, w):
     return float(g @ w)
 
 
-@pytest.mark.parametrize("kind", ["cube", "edge_tet", "pad_box"])
+@pytest.mark.parametrize("kind", ["cube", "cube_hs", "edge_tet", "pad_box"])
 def test_dG_dyn_matches_fd(kind):
     o, sc, n, yp, vp, yn = _step_data(kind)
     rng = np.random.default_rng(11)
@@ -95,7 +95,7 @@ def test_edge_tet_has_mollified_lag_pair():
     assert min(ratios) < 0.9
 
 
-@pytest.mark.parametrize("kind", ["cube", "pad_box"])
+@pytest.mark.parametrize("kind", ["cube", "cube_hs", "pad_box"])
 def test_dG_dtheta_matches_fd(kind):
     o, sc, n, yp, vp, yn = _step_data(kind)
     rng = np.random.default_rng(12)
@@ -120,7 +120,7 @@ def test_dG_dtheta_matches_fd(kind):
     assert abs((fp - fm) / (2 * h * mu0) - mb) <= 1e-8 * abs(mb)
 
 
-@pytest.mark.parametrize("kind", ["cube", "pad_box"])
+@pytest.mark.parametrize("kind", ["cube", "cube_hs", "pad_box"])
 def test_step_vjp_state_matches_fd(kind):
     """ybar^n and vbar^n of one step against differences of full steps.
 
@@ -161,10 +161,10 @@ def test_step_vjp_state_matches_fd(kind):
     assert abs(fd_y - yb @ d) <= 2e-5 * np.abs(yb) @ np.abs(d), (fd_y, yb @ d)
 
 
-ROLLOUT = {"cube": (5, 4, 1e-5), "pad_box": (16, 4, 3e-5)}
+ROLLOUT = {"cube": (5, 4, 1e-5), "cube_hs": (5, 4, 1e-5), "pad_box": (16, 4, 3e-5)}
 
 
-@pytest.mark.parametrize("kind", ["cube", "pad_box"])
+@pytest.mark.parametrize("kind", ["cube", "cube_hs", "pad_box"])
 def test_rollout_gradient_matches_fd(kind):
     """dL/dE and dL/dmu of a 4-step rollout against central differences.
 
