@@ -236,8 +236,8 @@ void setup_after_create(ipc_ctx *c)
     for (int s = 0; s < ns; ++s) {
         SceneInfo &S = c->sc[s];
         for (int b = 0; b < S.nb; ++b) {
-            is_trans[S.node0 + S.nv + 4 * b] = 1;
-            node_body[S.node0 + S.nv + 4 * b] = S.body0 + b;
+            is_trans[S.bnode0 + 4 * b] = 1;
+            node_body[S.bnode0 + 4 * b] = S.body0 + b;
         }
     }
     D.is_trans.upload(is_trans, c->stream);

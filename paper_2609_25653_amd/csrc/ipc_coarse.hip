@@ -55,7 +55,7 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
         const SceneInfo &S = c->sc[s];
         std::vector<int> part;
         for (int i = 0; i < S.nv; ++i) part.push_back(S.node0 + i);
-        for (int b = 0; b < S.nb; ++b) part.push_back(S.node0 + S.nv + 4 * b);   // translation node
+        for (int b = 0; b < S.nb; ++b) part.push_back(S.bnode0 + 4 * b);   // translation node
         if (part.empty()) continue;
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int n : part)

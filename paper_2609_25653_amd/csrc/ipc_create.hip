@@ -315,7 +315,9 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         for (int k = 0; k < 4; ++k) S.hs[k] = d.half_space[k];
         S.hs_on = d.half_space[0] != 0.0 || d.half_space[1] != 0.0 || d.half_space[2] != 0.0;
         topo[s] = topology(d);
-        S.node0 = node; S.nnode = d.nv + 4 * d.nb; S.nnode_pad = pad64(S.nnode);
+        S.node0 = node; S.nnode = d.nv + 4 * d.nb;
+        S.bnode0 = node + (d.nv + 3) / 4 * 4;
+        S.nnode_pad = pad64(S.bnode0 - node + 4 * d.nb);
         S.tet0 = tet; S.nt_pad = pad64(d.nt);
         S.body0 = body; S.drv0 = drv; S.sp0 = sp; S.jt0 = jt;
         S.cv0 = cv; S.ncv = (int)topo[s].surf.size(); S.nsurf = S.ncv;
@@ -370,11 +372,11 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         }
         for (int b = 0; b < d.nb; ++b)
             for (int cc = 0; cc < 4; ++cc) {
-                int nd = S.node0 + d.nv + 4 * b + cc;
+                int nd = S.bnode0 + 4 * b + cc;
                 node_kind[nd] = 1;
                 for (int k = 0; k < 3; ++k) { X[3 * (size_t)nd + k] = d.body_q[12 * b + 3 * cc + k]; V[3 * (size_t)nd + k] = d.body_qdot[12 * b + 3 * cc + k]; }
             }
-        for (int i = 0; i < S.nnode; ++i) ext2node[S.dof0 / 3 + i] = S.node0 + i;
+        for (int i = 0; i < S.nnode; ++i) ext2node[S.dof0 / 3 + i] = i < d.nv ? S.node0 + i : S.bnode0 + (i - d.nv);
         for (int e = 0; e < S.nt_pad; ++e) {
             int g = S.tet0 + e;
             if (e < d.nt) {
@@ -391,7 +393,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
             for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) bM[16 * (size_t)g + (1 + i) * 4 + 1 + j] = d.body_S[9 * b + 3 * i + j];
             bvol[g] = d.body_vol[b]; bkappa[g] = d.body_kappa[b];
             for (int k = 0; k < 3; ++k) bext[3 * (size_t)g + k] = d.body_ext[3 * b + k];
-            body_node0[g] = S.node0 + d.nv + 4 * b;
+            body_node0[g] = S.bnode0 + 4 * b;
             body_scene[g] = s;
         }
         for (int k = 0; k < d.ns; ++k) {

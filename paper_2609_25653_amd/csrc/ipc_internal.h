@@ -204,7 +204,9 @@ struct SceneInfo {
     // sizes
     int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd, nj;
     // offsets into the concatenated device arrays
-    int node0, nnode, nnode_pad;     // nodes: FEM vertices then 4 per body
+    int node0, nnode, nnode_pad;     // nodes: FEM vertices then 4 per body (nnode: without padding)
+    int bnode0;                      // first body node: node0 + nv rounded up to 4, so that a body's
+                                     // 4 nodes are 4 lanes of one wavefront
     int tet0, nt_pad;
     int body0, drv0, sp0, jt0;       // bodies, driven slots, springs, joint springs
     int cv0, ncv, nsurf;             // contact vertices; the first nsurf are PT query points

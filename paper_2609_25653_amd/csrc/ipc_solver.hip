@@ -576,8 +576,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     double Mi[9];
     if (n < N) {
         k = kind[n];
+        if (k != 2) { zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n); }
         if (k == 0) {
-            zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n);
 #pragma unroll
             for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)n + q];
         }
@@ -648,27 +648,37 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv); st3(z, n, zv);
         rr = dt(rv, rv);
         rz = dt(rv, zv);
-    } else if (on && k == 1 && node_body[n] >= 0) {
-        // the body's 4 nodes (12 DOFs) and its 12x12 inverse block
-        size_t o = 3 * (size_t)n;
+    } else if (on && k == 1) {
+        // An affine body's 4 nodes are 4 consecutive lanes of this wavefront
+        // (its first node is a multiple of 4).  Each lane updates its own
+        // node, gathers the body's 12 residual entries from the 4 lanes and
+        // forms 3 rows of the body's 12x12 inverse block times them.
+        pv = {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z};
+        sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
+        xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
+        rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
+        st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv);
+        const int a = n & 3, first = lane - a;
         double rb[12];
-        for (int i = 0; i < 12; ++i) {
-            double pi = z[o + i] + be * p[o + i];
-            double si = w[o + i] + be * s[o + i];
-            p[o + i] = pi;
-            s[o + i] = si;
-            x[o + i] += al * pi;
-            rb[i] = r[o + i] - al * si;
-            r[o + i] = rb[i];
-            rr += rb[i] * rb[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rb[3 * q] = __shfl(rv.x, first + q);
+            rb[3 * q + 1] = __shfl(rv.y, first + q);
+            rb[3 * q + 2] = __shfl(rv.z, first + q);
         }
-        const double *M = dinvB + 144 * (size_t)node_body[n];
-        for (int i = 0; i < 12; ++i) {
+        const double *M = dinvB + 144 * (size_t)node_body[n - a] + 36 * a;
+        double zz[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
             double acc = 0.0;
-            for (int j = 0; j < 12; ++j) acc += M[12 * i + j] * rb[j];
-            z[o + i] = acc;
-            rz += rb[i] * acc;
+#pragma unroll
+            for (int j = 0; j < 12; ++j) acc += M[12 * c + j] * rb[j];
+            zz[c] = acc;
         }
+        zv = {zz[0], zz[1], zz[2]};
+        st3(z, n, zv);
+        rr = dt(rv, rv);
+        rz = dt(rv, zv);
     }
     rz = wave_sum(rz); rr = wave_sum(rr);
     if (lane == 0 && t < ntile) { rz_out[t] = rz; rr_out[t] = rr; }
