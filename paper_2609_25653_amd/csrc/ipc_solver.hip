@@ -441,16 +441,34 @@ __device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, int
                                            const double *__restrict__ cl, const double *__restrict__ ca, double (*sh)[WG_TILES],
                                            double &ta, double &tb, double &tc)
 {
-    double va = 0.0, vb = 0.0, vc = 0.0;
-    for (int i = lo + (int)threadIdx.x; i < hi; i += BLOCK) {
+    // the first 4 strided entries of every source (scenes of up to 1024
+    // tiles, 64k nodes), the long rows' first and the domains' first entry
+    // are loaded predicated, all before the first add, so their latencies
+    // overlap instead of following each other; longer ranges finish in loops
+    const int t = (int)threadIdx.x;
+    double ea[4], eb[4], ec[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = lo + t + u * BLOCK;
+        const bool in = i < hi;
+        ea[u] = in ? a[i] : 0.0;
+        eb[u] = in ? b[i] : 0.0;
+        ec[u] = in && c ? c[i] : 0.0;
+    }
+    const double el = cl && llo + t < lhi ? cl[llo + t] : 0.0;
+    const double ec0 = ca && clo + t < chi ? ca[clo + t] : 0.0;
+    double va = (ea[0] + ea[1]) + (ea[2] + ea[3]), vb = (eb[0] + eb[1]) + (eb[2] + eb[3]), vc = (ec[0] + ec[1]) + (ec[2] + ec[3]);
+    for (int i = lo + t + 4 * BLOCK; i < hi; i += BLOCK) {
         va += a[i];
         vb += b[i];
         if (c) vc += c[i];
     }
+    vc += el;
     if (cl)
-        for (int i = llo + (int)threadIdx.x; i < lhi; i += BLOCK) vc += cl[i];
+        for (int i = llo + t + BLOCK; i < lhi; i += BLOCK) vc += cl[i];
+    va += ec0;
     if (ca)
-        for (int i = clo + (int)threadIdx.x; i < chi; i += BLOCK) va += ca[i];
+        for (int i = clo + t + BLOCK; i < chi; i += BLOCK) va += ca[i];
     va = wave_sum(va); vb = wave_sum(vb); vc = wave_sum(vc);
     int wave = threadIdx.x / TILE;
     if ((threadIdx.x & (TILE - 1)) == 0) { sh[0][wave] = va; sh[1][wave] = vb; sh[2][wave] = vc; }
