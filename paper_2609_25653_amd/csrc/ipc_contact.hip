@@ -14,6 +14,7 @@
 // and compacts the survivors with a wavefront ballot and a scan over
 // per-wavefront counts.
 #include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "ipc_device.h"
 #include "ipc_internal.h"
@@ -984,13 +985,29 @@ struct ValLagBlock {
 };
 
 // stable sort of m (key, code) int pairs by the low end_bit bits of the key
+// Stable sort of (key, code) entries by key, for the run sums.  rocPRIM's
+// radix sort picks a block sort with merge passes below a million entries
+// (about 20 launches for the barrier's entries); a merge limit of 0 makes it
+// use the onesweep radix passes at every size, a handful of launches.  A
+// stable sort has one result, so the choice does not change any sum.
+using EntrySortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config, rocprim::default_config, 0>;
+
+size_t sort_entries_bytes(ipc_ctx *c, int64_t m, int end_bit)
+{
+    size_t bytes = 0;
+    IPC_HIP(rocprim::radix_sort_pairs<EntrySortConfig>(nullptr, bytes, (const int *)nullptr, (int *)nullptr, (const int *)nullptr,
+                                                       (int *)nullptr, (unsigned int)std::max<int64_t>(m, 1), 0u,
+                                                       (unsigned int)end_bit, c->stream));
+    return bytes;
+}
+
 void sort_entries(ipc_ctx *c, const int *key, int *key2, const int *code, int *code2, int64_t m, int end_bit)
 {
     if (m <= 0) return;
-    size_t bytes = 0;
-    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, key, key2, code, code2, (int)m, 0, end_bit, c->stream));
+    size_t bytes = sort_entries_bytes(c, m, end_bit);
     c->d.sort_tmp.alloc(bytes + 16);
-    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(c->d.sort_tmp.p, bytes, key, key2, code, code2, (int)m, 0, end_bit, c->stream));
+    IPC_HIP(rocprim::radix_sort_pairs<EntrySortConfig>(c->d.sort_tmp.p, bytes, key, key2, code, code2, (unsigned int)m, 0u,
+                                                       (unsigned int)end_bit, c->stream));
 }
 
 int bits_for(int64_t n)   // bits that hold every value in [0, n]
@@ -1919,7 +1936,7 @@ void reserve_capacity(ipc_ctx *c, int64_t P, int64_t C, int64_t B)
     // the sorts' temporary storage at these sizes
     size_t tmp = 0, b = 0;
     auto upd = [&]() { tmp = std::max(tmp, b); };
-    IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.pb_key.p, D.pb_key2.p, D.pb_code.p, D.pb_code2.p, (int)(16 * P), 0, 31, st)); upd();
+    b = sort_entries_bytes(c, 16 * std::max(P, std::max<int64_t>(c->M_HS, 1)), 31); upd();   // the run sums' entry sorts
     IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.dyn_key64.p, D.dyn_key64b.p, D.dyn_idx.p, D.dyn_idx2.p, (int)B, 0, 64, st)); upd();
     IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.mkey.p, D.mkey2.p, D.mid.p, D.mid2.p, (int)Pp, 0, 64, st)); upd();
     IPC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, b, D.qkey.p, D.qkey2.p, D.qid.p, D.qperm.p, (int)Q, 0, 64, st)); upd();

@@ -45,6 +45,7 @@ void contact_grad_end(ipc_ctx *c, double *g);
 // stable sort of m (key, code) pairs by the low end_bit bits of the key, and
 // the bits that hold every value in [0, n]
 void sort_entries(ipc_ctx *c, const int *key, int *key2, const int *code, int *code2, int64_t m, int end_bit);
+size_t sort_entries_bytes(ipc_ctx *c, int64_t m, int end_bit);
 int bits_for(int64_t n);
 // pair-local contact blocks as row-sorted extra blocks of the product, and the
 // rows the product takes one wavefront per row
