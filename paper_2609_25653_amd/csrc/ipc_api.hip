@@ -81,6 +81,20 @@ __global__ void k_ls_begin(int ns, const int *__restrict__ on, double *__restric
     S[S_LS_ALPHA] = 1.0;
     S[S_CCD] = 1.0;
 }
+// the first line-search trial of each scene still iterating: min(1, CCD bound)
+__global__ void k_ls_first(int ns, double *__restrict__ scal)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    double *S = scal + (size_t)s * NSLOT;
+    const double a = S[S_CCD];
+    S[S_LS_ALPHA] = S[S_LS_ON] != 0.0 ? (a < 1.0 ? a : 1.0) : 0.0;
+}
+__global__ void k_copy_slot(int ns, double *__restrict__ scal, int from, int to)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns) scal[(size_t)s * NSLOT + to] = scal[(size_t)s * NSLOT + from];
+}
 // yt = y + alpha_s p (alpha from the scene's line-search slot, 0 when off)
 __global__ void k_trial(int N, const int *__restrict__ node_scene, const double *__restrict__ scal, const double *__restrict__ y,
                         const double *__restrict__ p, double *__restrict__ yt)
@@ -1152,6 +1166,20 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         for (int s = 0; s < ns; ++s) S[s].n_cand_max = std::max(S[s].n_cand_max, (c->h_cand_pt_seg[s + 1] - c->h_cand_pt_seg[s]) +
                                                                              (c->h_cand_ee_seg[s + 1] - c->h_cand_ee_seg[s]));
         launch_ccd(c, D.xw.p, D.xw1.p);
+        // The first trial is queued behind the CCD without a host read: the
+        // step min(1, CCD bound) is set on the device, E(y) over the list the
+        // trials use is evaluated first when that list is new (kept in S_E0),
+        // then E(y + alpha p).  One read returns the bound, E(y) and the
+        // first trial's energy.
+        hipLaunchKernelGGL(k_ls_first, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.scal.p);
+        const bool new_e0 = !e0_on_list;
+        if (new_e0) {
+            eval_energy(c, D.y.p, true);
+            hipLaunchKernelGGL(k_copy_slot, dim3(blocks_for(ns, 64)), dim3(64), 0, st, ns, D.scal.p, S_E, S_E0);
+            e0_on_list = true;
+        }
+        hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
+        eval_energy(c, D.yt.p, true);
         sc = read_scal(c);
         std::vector<double> alpha(ns, 0.0);
         std::vector<int> ls(ns, 0);
@@ -1159,13 +1187,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             if (!on[s]) continue;
             alpha[s] = std::min(1.0, sc[(size_t)s * NSLOT + S_CCD]);
             ls[s] = 1;
-        }
-        if (!e0_on_list) {   // E(y) over the list the trials use
-            eval_energy(c, D.y.p, true);
-            std::vector<double> se = read_scal(c);
-            for (int s = 0; s < ns; ++s)
-                if (on[s]) E0[s] = se[(size_t)s * NSLOT + S_E];
-            e0_on_list = true;
+            if (new_e0) E0[s] = sc[(size_t)s * NSLOT + S_E0];
         }
         // backtracking: halve each scene's step until its energy does not increase
         std::vector<double> Eacc(ns, 0.0);
@@ -1177,10 +1199,13 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
                 pending |= ls[s] != 0;
             }
             if (!pending) break;
-            write_scal(c, sc);
-            hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p, D.yt.p);
-            eval_energy(c, D.yt.p, true);
-            sc = read_scal(c);
+            if (h > 0) {   // the first trial is already evaluated
+                write_scal(c, sc);
+                hipLaunchKernelGGL(k_trial, dim3(blocks_for(c->N)), dim3(BLOCK), 0, st, c->N, D.node_scene.p, D.scal.p, D.y.p, D.x.p,
+                                   D.yt.p);
+                eval_energy(c, D.yt.p, true);
+                sc = read_scal(c);
+            }
             for (int s = 0; s < ns; ++s) {
                 if (!ls[s]) continue;
                 double E1 = sc[(size_t)s * NSLOT + S_E];
