@@ -1026,6 +1026,14 @@ extern "C" int ipc_step_vjp(ipc_ctx *c, const double *y_prev_dev, const double *
 // ---------------------------------------------------------------------------------
 namespace ipc {
 
+// Sets the context's assembly flags for a scope; cleared on exit, also when
+// a device error unwinds it, so no later call assembles a subset.
+struct AssembleOnly {
+    ipc_ctx *c;
+    AssembleOnly(ipc_ctx *cc, const int *flags) : c(cc) { c->assemble_only = flags; }
+    ~AssembleOnly() { c->assemble_only = nullptr; }
+};
+
 void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
 {
     Dev &D = c->d;
@@ -1106,11 +1114,18 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             S[s].n_pt_max = std::max(S[s].n_pt_max, c->h_pt_seg[s + 1] - c->h_pt_seg[s]);
             S[s].n_ee_max = std::max(S[s].n_ee_max, c->h_ee_seg[s + 1] - c->h_ee_seg[s]);
         }
-        // assemble and solve H p = -g for the scenes still iterating
-        eval_grad_hess(c, D.y.p, D.g.p, true, true);
-        build_preconditioner(c);
-        hipLaunchKernelGGL(k_negate, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.g.p, D.v1.p);
+        // assemble and solve H p = -g for the scenes still iterating (in a
+        // batch, the FEM, matrix, preconditioner and coarse blocks of scenes
+        // that have converged are not formed again)
         upload_async(c, D.newton_on.p, on.data(), ns * sizeof(int));
+        bool all_on = true;
+        for (int s = 0; s < ns; ++s) all_on = all_on && on[s];
+        {
+            AssembleOnly only(c, all_on ? nullptr : D.newton_on.p);
+            eval_grad_hess(c, D.y.p, D.g.p, true, true);
+            build_preconditioner(c);
+        }
+        hipLaunchKernelGGL(k_negate, dim3(blocks_for(3 * (int64_t)c->N)), dim3(BLOCK), 0, st, 3 * (int64_t)c->N, D.g.p, D.v1.p);
         pcg_solve(c, D.v1.p, D.x.p, -1.0, D.newton_on.p);
         std::vector<int> it(ns);
         // the trial point y + p (step 1) and world positions at both ends,

@@ -120,10 +120,12 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
                                                             const int *__restrict__ row_ptr, const int *__restrict__ col,
                                                             const double *__restrict__ val, const int *__restrict__ dptr,
                                                             const int *__restrict__ dcol, const double *__restrict__ dval,
-                                                            double *__restrict__ mat)
+                                                            double *__restrict__ mat, const int *__restrict__ dom_scene,
+                                                            const int *__restrict__ active)
 {
     __shared__ double P[CG_AGG][3 * CG_N];   // 72 KB: one strip per row
     const int g = grp[blockIdx.x], d = g / CG_DOM, a = g % CG_DOM;
+    if (active && !active[dom_scene[d]]) return;   // uniform over the workgroup
     for (int q = threadIdx.x; q < CG_AGG * 3 * CG_N; q += CG_ASM) (&P[0][0])[q] = 0.0;
     __syncthreads();
     const int row = (int)threadIdx.x / CG_LPR, sub = threadIdx.x % CG_LPR, e = ent[d] + a * CG_AGG + row;
@@ -191,10 +193,12 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
 // is block-Jacobi alone.
 constexpr int CG_INV = 1024, CG_PER = CG_N * CG_N / CG_INV;
 static_assert(CG_N * CG_N % CG_INV == 0, "whole entries per thread");
-__global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict__ ent, double *__restrict__ mat)
+__global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict__ ent, double *__restrict__ mat,
+                                                          const int *__restrict__ dom_scene, const int *__restrict__ active)
 {
     __shared__ double A[CG_N * CG_N];
     const int d = blockIdx.x, ne = ent[d + 1] - ent[d], n = 3 * ((ne + CG_AGG - 1) / CG_AGG);
+    if (active && !active[dom_scene[d]]) return;   // uniform over the workgroup
     double *G = mat + (size_t)d * CG_N * CG_N;
     int qi[CG_PER], qj[CG_PER];
 #pragma unroll
@@ -341,8 +345,10 @@ void coarse_build(ipc_ctx *c)
     if (!c->n_cdom || !c->coarse_on) return;
     Dev &D = c->d;
     hipLaunchKernelGGL(k_coarse_assemble, dim3(c->n_cgrp), dim3(CG_ASM), 0, c->stream, D.cg_grp.p, D.cg_ent.p, D.cg_nodes.p,
-                       D.cg_node_da.p, D.row_ptr.p, D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.cg_inv.p);
-    hipLaunchKernelGGL(k_coarse_invert, dim3(c->n_cdom), dim3(CG_INV), 0, c->stream, D.cg_ent.p, D.cg_inv.p);
+                       D.cg_node_da.p, D.row_ptr.p, D.col.p, D.val.p, D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.cg_inv.p,
+                       D.cg_dom_scene.p, c->assemble_only);
+    hipLaunchKernelGGL(k_coarse_invert, dim3(c->n_cdom), dim3(CG_INV), 0, c->stream, D.cg_ent.p, D.cg_inv.p, D.cg_dom_scene.p,
+                       c->assemble_only);
 }
 
 void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int parity)

@@ -611,8 +611,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
             // slot and adjacency lists, the temporary density and validity
             16 * T, 72 * T, 8 * T, 8 * T, 8 * T, 8 * T, 8 * T, 4 * T + 4, 96 * std::max<int64_t>(T, 1), 720 * std::max<int64_t>(T, 1),
             4 * (NZ + 1), 4 * (int64_t)sc_list.size() + 4, 4 * (N + 1), 4 * (int64_t)adj.size() + 4, 8 * T, 4 * T, 8 * (T / TILE + 1),
-            // matrix: pattern, values, constant part, slots
-            4 * (N + 1), 4 * NZ, 4 * N, 72 * NZ, 72 * NZ, 64 * NB,
+            // matrix: pattern, values, constant part, slots, scene of each block
+            4 * (N + 1), 4 * NZ, 4 * N, 72 * NZ, 72 * NZ, 64 * NB, 4 * NZ,
             // bodies
             128 * NB, 8 * NB, 8 * NB, 24 * NB, 4 * NB, 4 * NB, 1152 * NB, 8 * NB, 4 * (NB + 1), 4 * (int64_t)body_cv.size() + 4,
             // springs, drive targets, joint points, their entry lists
@@ -667,6 +667,12 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
     D.sc_ptr.upload(sc_ptr, st); D.sc_list.upload(sc_list, st);
     D.tgrad.alloc(12 * (size_t)std::max(tet, 1)); D.telem.alloc(90 * (size_t)std::max(tet, 1));
     D.row_ptr.upload(row_ptr, st); D.col.upload(col, st); D.diag_slot.upload(diag_slot, st);
+    {
+        std::vector<int> slot_scene(std::max(c->nnzb, 1), 0);
+        for (int r = 0; r < node; ++r)
+            for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) slot_scene[k] = node_scene[r];
+        D.slot_scene.upload(slot_scene, st);
+    }
     D.val.alloc(9 * (size_t)std::max(c->nnzb, 1));
     D.val_const.alloc(9 * (size_t)std::max(c->nnzb, 1)); D.val_const.zero(st, 9 * (size_t)std::max(c->nnzb, 1));
     D.bslot.upload(bslot, st);

@@ -51,11 +51,13 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
                                              const double *__restrict__ tlam, const double *__restrict__ y,
                                              const int *__restrict__ tile_scene, const double *__restrict__ h2s,
                                              double *__restrict__ tgrad, double *__restrict__ telem, int project,
-                                             double *__restrict__ part)
+                                             double *__restrict__ part, const int *__restrict__ active)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     double energy = 0.0;
-    if (e < T && vol[e] > 0.0) {
+    // active (nullable): only the tets of scenes whose flag is set (a wavefront
+    // of tets is one scene's, so the test is uniform over it)
+    if (e < T && vol[e] > 0.0 && (!active || active[tile_scene[e / TILE]])) {
         int4 t = tv[e];
         int vi[4] = {t.x, t.y, t.z, t.w};
         d3 x[4];
@@ -153,11 +155,13 @@ __global__ void __launch_bounds__(256) k_fem(int T, const int4 *__restrict__ tv,
 // stores its 10 upper blocks (A <= B); block (A, B) with A > B is read as
 // entry (c, r) of block (B, A).
 __global__ void k_bsr_assemble(int64_t n9, int T, const int *__restrict__ sc_ptr, const int *__restrict__ sc_list,
-                               const double *__restrict__ telem, const double *__restrict__ vc, double *__restrict__ val)
+                               const double *__restrict__ telem, const double *__restrict__ vc, double *__restrict__ val,
+                               const int *__restrict__ slot_scene, const int *__restrict__ active)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n9) return;
     int k = (int)(i / 9), q = (int)(i % 9), qt = 3 * (q % 3) + q / 3;
+    if (active && !active[slot_scene[k]]) return;
     double acc = vc[i];
     // eight contributions at a time: their codes, then their entries, are
     // loaded together; the sum keeps the list order
@@ -183,10 +187,12 @@ __global__ void k_bsr_assemble(int64_t n9, int T, const int *__restrict__ sc_ptr
 
 // node gradients of the tets: g[n] += sum over incident (tet, vertex), in order
 __global__ void k_fem_grad_gather(int N, int T, const int *__restrict__ adj_ptr, const int *__restrict__ adj,
-                                  const double *__restrict__ tgrad, double *__restrict__ g)
+                                  const double *__restrict__ tgrad, double *__restrict__ g, const int *__restrict__ node_scene,
+                                  const int *__restrict__ active)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    if (active && !active[node_scene[n]]) return;
     int k0 = adj_ptr[n], k1 = adj_ptr[n + 1];
     if (k0 == k1) return;
     d3 acc = ld3(g, n);
@@ -362,12 +368,13 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
     int64_t n9 = 9 * (int64_t)c->nnzb;
     if (c->T == 0) {
         if (mode == 2) hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, 1, D.sc_ptr.p,
-                                          D.sc_list.p, D.telem.p, D.val_const.p, D.val.p);
+                                          D.sc_list.p, D.telem.p, D.val_const.p, D.val.p, D.slot_scene.p, c->assemble_only);
         return;
     }
+    const int *active = mode >= 1 ? c->assemble_only : nullptr;
     auto args = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks_for(c->T)), dim3(BLOCK), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p, D.tmu.p,
-                           D.tlam.p, y, D.tile_scene_tet.p, h2s, D.tgrad.p, D.telem.p, (int)project, part);
+                           D.tlam.p, y, D.tile_scene_tet.p, h2s, D.tgrad.p, D.telem.p, (int)project, part, active);
     };
     int k = mode == 2 ? IPC_K_FEM_HESS : (mode == 0 ? IPC_K_FEM_ENERGY : -1);
     if (k >= 0) prof_begin(c, k);
@@ -376,10 +383,10 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
     else args(k_fem<2>);
     if (mode >= 1)
         hipLaunchKernelGGL(k_fem_grad_gather, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, c->T, D.fadj_ptr.p, D.fadj.p,
-                           D.tgrad.p, g);
+                           D.tgrad.p, g, D.node_scene.p, active);
     if (mode == 2)
         hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, c->T, D.sc_ptr.p, D.sc_list.p,
-                           D.telem.p, D.val_const.p, D.val.p);
+                           D.telem.p, D.val_const.p, D.val.p, D.slot_scene.p, active);
     // algorithmic bytes: tet data in (112), per-tet gradient and upper blocks
     // out and back in (96 and 720, twice), node gradient in and out (48),
     // matrix out and its constant part in (2 x 72 per block)

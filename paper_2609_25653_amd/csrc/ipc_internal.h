@@ -227,6 +227,7 @@ struct Dev {
     // nodes
     DBuf<double> y, ydot, xt, y0, yt, g, p, r, z, q, w, x, v1, v2;
     DBuf<int> node_scene, node_kind;       // kind: 0 FEM, 1 body node, 2 padding
+    DBuf<int> slot_scene;                  // scene of each block-CSR block (its row's)
     DBuf<double> mass;                     // lumped FEM vertex mass (0 elsewhere)
     DBuf<double> dinv;                     // 3x3 inverse diagonal block per node
     DBuf<int> ext2node;                    // external node -> internal node
@@ -392,6 +393,11 @@ struct ipc_ctx {
     ipc::Dev d;                           // (declared after ws: released into it before it goes)
     bool step_ready = false;
     bool fr_on = true;
+    // per-scene flags (device, nullable): while set, the FEM assembly, the
+    // block-CSR values, the preconditioner blocks and the coarse blocks are
+    // formed for the flagged scenes only (a batch's Newton iterations after
+    // some scenes have converged); the others keep stale values they never use
+    const int *assemble_only = nullptr;
     bool use_graphs = true;              // PCG iterations replayed from a captured graph
     hipStream_t cap_stream = nullptr;    // private stream used only for graph capture
     // PCG batch graphs, reused while every launch argument they captured is unchanged

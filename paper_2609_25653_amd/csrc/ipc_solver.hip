@@ -318,10 +318,11 @@ __device__ __forceinline__ int dyn_find(const int *__restrict__ dptr, const int 
 
 __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__restrict__ diag_slot, const double *__restrict__ val,
                            const int *__restrict__ dptr, const int *__restrict__ dcol, const double *__restrict__ dval,
-                           double *__restrict__ dinv)
+                           double *__restrict__ dinv, const int *__restrict__ node_scene, const int *__restrict__ active)
 {
     int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    if (active && !active[node_scene[n]]) return;
     double *o = dinv + 9 * (size_t)n;
     if (kind[n] != 0) { for (int q = 0; q < 9; ++q) o[q] = 0.0; return; }
     double a[9];
@@ -343,10 +344,12 @@ __global__ void k_prec_fem(int N, const int *__restrict__ kind, const int *__res
 __global__ void __launch_bounds__(64) k_prec_body(int NB, const int *__restrict__ bslot, const int *__restrict__ node0,
                                                   const double *__restrict__ val, const int *__restrict__ dptr,
                                                   const int *__restrict__ dcol, const double *__restrict__ dval,
-                                                  double *__restrict__ dinvB)
+                                                  double *__restrict__ dinvB, const int *__restrict__ body_scene,
+                                                  const int *__restrict__ active)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= NB) return;
+    if (active && !active[body_scene[b]]) return;
     double L[144];
     int n0 = node0[b];
 #pragma unroll
@@ -408,11 +411,10 @@ void build_preconditioner(ipc_ctx *c)
 {
     Dev &D = c->d;
     hipLaunchKernelGGL(k_prec_fem, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, D.node_kind.p, D.diag_slot.p, D.val.p,
-                       D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.dinv.p);
+                       D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.dinv.p, D.node_scene.p, c->assemble_only);
     if (c->NB)
         hipLaunchKernelGGL(k_prec_body, dim3(blocks_for(c->NB, 64)), dim3(64), 0, c->stream, c->NB, D.bslot.p, D.body_node0.p, D.val.p,
-                           D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p,
-                           D.dinvB.p);
+                           D.dyn_ptr.p, D.dyn_col.p, D.dyn_val.p, D.dinvB.p, D.body_scene.p, c->assemble_only);
     coarse_build(c);
 }
 
