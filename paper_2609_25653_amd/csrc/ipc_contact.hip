@@ -1499,11 +1499,14 @@ __device__ __forceinline__ void pair_maps(int i, int nb, const int4 *pcv, const 
 __global__ void k_dyn_count(int nb, int nf, const int *__restrict__ pflag, const int *__restrict__ lflag, const int4 *__restrict__ pcv,
                             const int4 *__restrict__ lcv, const int *__restrict__ cv_node, const int *__restrict__ cv_body,
                             const double *__restrict__ cv_x, const int *__restrict__ body_node0, int *__restrict__ cnt,
-                            int *__restrict__ nlocal)
+                            int *__restrict__ nlocal, const int *__restrict__ cv_scene, const int *__restrict__ active)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb + nf) return;
     bool local = (i < nb ? pflag[i] : lflag[i - nb]) == 0;
+    // active (nullable): the pairs of scenes whose flag is clear get no
+    // blocks (their rows are not used until they are assembled again)
+    if (local && active && !active[cv_scene[i < nb ? pcv[i].x : lcv[i - nb].x]]) local = false;
     int n = 0;
     if (local) {
         Map mp[4];
@@ -1653,7 +1656,8 @@ void build_dyn_blocks(ipc_ctx *c)
         D.tickets.alloc(4);
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.tickets.p, 0);
         hipLaunchKernelGGL(k_dyn_count, dim3(blocks_for(n)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.pair_flag.p, D.lag_flag.p,
-                           D.pair_cv.p, D.lag_cv.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_cnt.p, D.tickets.p);
+                           D.pair_cv.p, D.lag_cv.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_cnt.p, D.tickets.p,
+                           D.cv_scene.p, c->assemble_only);
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, 1, D.dyn_cnt.p + n, 0);
         exclusive_scan(c, D.dyn_cnt.p, D.dyn_off.p, (int)n);
         int hv[2];
