@@ -798,7 +798,7 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
     const int *__restrict__ cv_body, const double *__restrict__ cv_x, const int *__restrict__ body_node0, double *__restrict__ pg,
     int *__restrict__ gkey, int *__restrict__ gcode, int ncv, int4 *__restrict__ pair_cv, double *__restrict__ pair_H,
     double *__restrict__ pe, int project, int *__restrict__ inf_flag, const int *__restrict__ row_ptr, const int *__restrict__ col,
-    int nnzb, int *__restrict__ bkey, int *__restrict__ bcode, int *__restrict__ pair_flag)
+    int nnzb, int *__restrict__ bkey, int *__restrict__ bcode, int *__restrict__ pair_flag, const int *__restrict__ active)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npt + nee) return;
@@ -827,7 +827,7 @@ __global__ void __launch_bounds__(256) k_barrier(int npt, int nee, const int2 *_
         none();
         return;
     }
-    if (d2 >= dh * dh) {
+    if (d2 >= dh * dh || (MODE == 2 && active && !active[s])) {   // beyond dhat, or a scene not being assembled
         none();
         return;
     }
@@ -1040,7 +1040,7 @@ void launch_barrier(ipc_ctx *c, int mode, bool candidates, const double *xw, boo
         hipLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(BLOCK), 0, c->stream, (int)npt, (int)nee, pt, ee, D.tri.p, D.edge.p, xw,
                            D.cv_scene.p, D.sparam.p, D.edge_rest2.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.pair_g.p,
                            D.pg_key.p, D.pg_code.p, c->CV, D.pair_cv.p, D.pair_H.p, D.pair_part.p, (int)project, D.inf_flag.p,
-                           D.row_ptr.p, D.col.p, c->nnzb, D.pb_key.p, D.pb_code.p, D.pair_flag.p);
+                           D.row_ptr.p, D.col.p, c->nnzb, D.pb_key.p, D.pb_code.p, D.pair_flag.p, mode == 2 ? c->assemble_only : nullptr);
     };
     if (mode == 2) prof_begin(c, IPC_K_BARRIER_HESS);
     if (mode == 0) go(k_barrier<0>);
