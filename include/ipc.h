@@ -151,7 +151,8 @@ enum {
                              switches it off or on whatever the size       */
     IPC_Q_WS_BYTES = 11,  /* workspace size of an ipc_create_ws context (0: the
                              context allocates its own memory)                */
-    IPC_Q_WS_PEAK = 12    /* the most workspace bytes in use at once so far    */
+    IPC_Q_WS_PEAK = 12,   /* the most workspace bytes in use at once so far    */
+    IPC_Q_SPMV_LANES = 13 /* lanes per row the Hessian product uses             */
 };
 
 /* Flags of ipc_energy_grad_hess. */
@@ -352,7 +353,11 @@ int ipc_time_kernel(ipc_ctx *ctx, int kernel, int reps, double *avg_us, double *
  * (nullable) the choice.  The default before any call is 8 lanes; the
  * environment variable IPC_SPMV_LANES (1, 2, 4, 8 or 16), read at
  * ipc_create, fixes the count instead: the autotuner still times every
- * count but keeps that one.  Uses the context's solver scratch vectors. */
+ * count but keeps that one.  Otherwise the choice is also kept for the
+ * process, keyed by the context's size bucket (the powers of two of the
+ * static pattern's block count and of the node count, and whether it holds
+ * several scenes); a context created later in the same bucket starts with
+ * it (IPC_Q_SPMV_LANES).  Uses the context's solver scratch vectors. */
 int ipc_autotune(ipc_ctx *ctx, int reps, double *us_host, int32_t *lanes_host);
 
 #ifdef __cplusplus

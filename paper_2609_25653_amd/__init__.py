@@ -281,6 +281,12 @@ class Sim:
         """Whether the PCG preconditioner applies its coarse correction."""
         return bool(self._query(_lib.Q_COARSE))
 
+    @property
+    def spmv_lanes(self):
+        """Lanes per row of the Hessian product (the autotuner's choice, or
+        the one tuned earlier in this process for a context of this size)."""
+        return int(self._query(_lib.Q_SPMV_LANES))
+
     # ---- adjoint --------------------------------------------------------------
     @property
     def n_tets(self):

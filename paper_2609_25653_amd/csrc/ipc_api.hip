@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "ipc_device.h"
@@ -515,6 +516,27 @@ static int precheck(const ipc_scene_desc *scenes, int n_scenes)
     return IPC_OK;
 }
 
+// The autotuner's choices, kept for the process and keyed by the size
+// bucket of the context: powers of two of the block count of the static
+// matrix pattern and of the node count, and whether it holds several scenes.
+// A new context of a known bucket starts with the product's tuned lane count.
+static std::mutex g_tune_mu;
+static std::map<uint32_t, int> g_tuned_lanes;
+
+static uint32_t tune_key(const ipc_ctx *c)
+{
+    auto lg = [](int64_t n) { uint32_t b = 0; while (b < 40 && (int64_t(1) << b) < n) ++b; return b; };
+    return (lg(c->nnzb) << 16) | (lg(c->N) << 1) | (c->n_scenes > 1 ? 1u : 0u);
+}
+
+static void adopt_tuned(ipc_ctx *c)
+{
+    if (c->spmv_lanes_forced) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned_lanes.find(tune_key(c));
+    if (it != g_tuned_lanes.end()) c->spmv_lanes = it->second;
+}
+
 extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_stream, ipc_ctx **out)
 {
     if (!out) return IPC_E_INVALID;
@@ -526,6 +548,7 @@ extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_
     int rc = guard(c, [&] {
         create_context(c, scenes, n_scenes);
         setup_after_create(c);
+        adopt_tuned(c);
     });
     if (rc != IPC_OK) {
         g_create_error = c->err;
@@ -580,6 +603,7 @@ extern "C" int ipc_create_ws(const ipc_scene_desc *scenes, int n_scenes, const i
     int rc = guard(c, [&] {
         create_context(c, scenes, n_scenes);
         setup_after_create(c);
+        adopt_tuned(c);
         reserve_capacity(c, cap->max_pairs, cap->max_candidates, cap->max_local_blocks);
         IPC_HIP(hipStreamSynchronize(c->stream));
     });
@@ -619,6 +643,7 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_COARSE: *v = c->coarse_on ? 1 : 0; return IPC_OK;
     case IPC_Q_WS_BYTES: *v = (int64_t)c->ws.size; return IPC_OK;
     case IPC_Q_WS_PEAK: *v = (int64_t)c->ws.peak; return IPC_OK;
+    case IPC_Q_SPMV_LANES: *v = c->spmv_lanes; return IPC_OK;
     }
     return IPC_E_INVALID;
 }
@@ -1393,6 +1418,10 @@ extern "C" int ipc_autotune(ipc_ctx *c, int reps, double *us_host, int32_t *lane
         int keep = c->spmv_lanes;
         autotune_spmv(c, reps, us_host);
         if (c->spmv_lanes_forced) c->spmv_lanes = keep;
+        else {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned_lanes[tune_key(c)] = c->spmv_lanes;
+        }
         c->prof = prof;
         if (lanes_host) *lanes_host = c->spmv_lanes;
     });

@@ -113,3 +113,20 @@ def test_hessian_bsr(name, k):
             stored[i, col[rp[i]:rp[i + 1]]] = True
         nz = np.abs(Ho).reshape(n // 3, 3, n // 3, 3).max(axis=(1, 3)) > 0
         assert not (nz & ~stored).any()
+
+
+def test_autotuned_lanes_carry_over_to_contexts_of_the_same_size():
+    """The autotuner's lane count is kept per size bucket for the process: a
+    second context of the same scene starts with it, and a context of a
+    different size keeps the default until tuned itself."""
+    from paper_2609_25653_amd import Sim
+    # a batch of two free tetrahedra: a bucket no other test tunes
+    pair = [S.tiny_scene("tet", h=0.01, n_steps=4), S.tiny_scene("tet", seed=1, h=0.01, n_steps=4)]
+    a = Sim(pair)
+    a.step()
+    lanes, us = a.autotune(5)
+    assert lanes in (1, 2, 4, 8, 16) and a.spmv_lanes == lanes and len(us) == 5
+    b = Sim(pair)
+    assert b.spmv_lanes == lanes
+    other = Sim(pair[0])          # one scene: another bucket, not tuned
+    assert other.spmv_lanes == 8
