@@ -15,10 +15,11 @@
 // of at most 96 x 96 that is inverted after every assembly.  Nothing crosses
 // scenes: groups and domains are per scene.
 //
-// Per PCG iteration one launch (a workgroup per domain) restricts the new
-// residual to its groups, multiplies by the domain's inverse, adds the
-// result to z on every node of the group and writes r . z of the correction,
-// which the next step's reduction adds to r . z of the block-Jacobi part.
+// Per PCG iteration one launch (CG_SPLIT workgroups per domain) restricts
+// the new residual to its groups, multiplies by the domain's inverse, adds
+// the result to z on every node of the group and writes r . z of the
+// correction, which the next step's reduction adds to r . z of the
+// block-Jacobi part.
 #include <algorithm>
 #include <cstdlib>
 #include <numeric>
@@ -103,7 +104,7 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
     // are read as 0 by the product with the inverse
     D.cg_inv.alloc((size_t)std::max(ndom, 1) * CG_N * CG_N);
     D.cg_inv.zero(c->stream, (size_t)std::max(ndom, 1) * CG_N * CG_N);
-    D.cg_part.alloc(2 * (size_t)std::max(ndom, 1));
+    D.cg_part.alloc(2 * (size_t)CG_SPLIT * std::max(ndom, 1));
 }
 
 // The domains' blocks of P^T A P: one workgroup per group (32 rows of 8
@@ -260,31 +261,47 @@ __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict_
         if (qi[m] < n && qj[m] < n) G[threadIdx.x + m * CG_INV] = bad ? 0.0 : A[threadIdx.x + m * CG_INV];
 }
 
-// One workgroup per domain of a scene that updated its residual (act != 0):
-// rc = P^T r over the domain's groups, zc = C^-1 rc, z += P zc, and the
-// partial rc . zc (= r . P zc) into part[d].  The stages are latency-bound,
-// so every load that does not wait for another is issued first: the
-// inverse's columns (entries past a short domain's n are 0), the scene's
-// flag, then the entries' r and z.  A group is 32 consecutive entries, i.e.
-// half a wavefront of one pass over the entries.
+// CG_SPLIT workgroups per domain of a scene that updated its residual
+// (act != 0).  Each one restricts the whole residual, rc = P^T r over the
+// domain's groups, multiplies its slice of CG_N / CG_SPLIT rows of the
+// domain's inverse by rc, adds the result to z on the nodes of its slice's
+// groups, and writes the partial of rc . zc (= r . P zc) over its rows into
+// part[CG_SPLIT d + slice].  The stages are latency-bound and one workgroup
+// per domain left most CUs idle while each of the few busy ones streamed a
+// 74 KB inverse; a slice reads a quarter of it.  Every load that does not
+// wait for another is issued first: the inverse's rows (entries past a short
+// domain's n are 0), the scene's flag, then the entries' r and z.  A group is
+// 32 consecutive entries, i.e. half a wavefront of one pass over the entries.
+// The slices of a domain are numbered so that they share an XCD (workgroups
+// go round-robin over the 8 XCDs): the residual's repeated reads hit its L2.
 constexpr int CG_APPLY = 256;
 constexpr int CG_PASSES = CG_AGG * CG_DOM / CG_APPLY;
-__global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict__ ent, const int *__restrict__ nodes,
+constexpr int CG_ROWS = CG_N / CG_SPLIT;              // inverse rows per slice
+constexpr int CG_SNODES = CG_AGG * CG_DOM / CG_SPLIT; // entries per slice
+constexpr int CG_CLANES = 192 / CG_ROWS;              // lanes per row in the product
+constexpr int CG_CPL = CG_N / CG_CLANES;              // columns per lane
+constexpr int NXCD = 8;
+static_assert(CG_N % CG_SPLIT == 0 && CG_ROWS * CG_CLANES == 192 && CG_N % CG_CLANES == 0, "whole rows and columns per lane");
+static_assert(TILE % CG_CLANES == 0 && CG_SNODES <= CG_APPLY && CG_APPLY % CG_SNODES == 0, "lane groups inside a wavefront");
+__global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, const int *__restrict__ ent, const int *__restrict__ nodes,
                                                            const int *__restrict__ dom_scene, const int *__restrict__ act,
                                                            const double *__restrict__ inv, const double *__restrict__ r,
                                                            double *__restrict__ z, double *__restrict__ part)
 {
-    static_assert(CG_APPLY == 4 * TILE && CG_N == 96, "four wavefronts of 24 columns");
-    constexpr int KW = CG_N / (CG_APPLY / TILE);   // 24 columns per wavefront
-    __shared__ double rc[CG_N], zp[CG_APPLY / TILE][CG_N], zc[CG_N], sh[CG_APPLY / TILE];
-    const int d = blockIdx.x, t = threadIdx.x, lane = t & (TILE - 1), wave = t / TILE;
-    // wavefront w multiplies columns [KW w, KW w + KW) for rows lane and
-    // lane + 64 (the inverse is symmetric: row k is column k, read coalesced)
-    const double *M = inv + (size_t)d * CG_N * CG_N + (size_t)wave * KW * CG_N;
-    const int i1 = min(lane + TILE, CG_N - 1);
-    double m0[KW], m1[KW];
+    __shared__ double rc[CG_N], zl[CG_ROWS];
+    const int b = blockIdx.x, k = b / NXCD;
+    const int sl = k % CG_SPLIT, d = b % NXCD + NXCD * (k / CG_SPLIT);
+    if (d >= ndom) return;   // the grid is rounded up to whole XCD rounds
+    const int t = threadIdx.x, lane = t & (TILE - 1);
+    // product lanes: row i of the slice, columns cl + CG_CLANES j (the
+    // inverse is symmetric, so its row is read for the row of the product)
+    const int i = t / CG_CLANES, cl = t % CG_CLANES, row = CG_ROWS * sl + i;
+    double m[CG_CPL];
+    if (t < 192) {
+        const double *M = inv + (size_t)d * CG_N * CG_N + (size_t)row * CG_N + cl;
 #pragma unroll
-    for (int j = 0; j < KW; ++j) { m0[j] = M[(size_t)j * CG_N + lane]; m1[j] = M[(size_t)j * CG_N + i1]; }
+        for (int j = 0; j < CG_CPL; ++j) m[j] = M[CG_CLANES * j];
+    }
     const int on = act[dom_scene[d]];
     const int e0 = ent[d], ne = ent[d + 1] - e0, n = 3 * ((ne + CG_AGG - 1) / CG_AGG);
     int nd[CG_PASSES];
@@ -293,15 +310,21 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict
         const int e = t + j * CG_APPLY;
         nd[j] = e < ne ? nodes[e0 + e] : -1;
     }
-    d3 rv[CG_PASSES], zv[CG_PASSES];
+    // the slice's entries are those of pass jp on a contiguous range of threads
+    constexpr int PER_PASS = CG_APPLY / CG_SNODES;
+    const int jp = sl / PER_PASS, eo = t + jp * CG_APPLY - CG_SNODES * sl;
+    const bool mine = eo >= 0 && eo < CG_SNODES;
+    int ndp = -1;
 #pragma unroll
-    for (int j = 0; j < CG_PASSES; ++j) {
-        rv[j] = nd[j] >= 0 ? ld3(r, nd[j]) : d3{0.0, 0.0, 0.0};
-        zv[j] = nd[j] >= 0 ? ld3(z, nd[j]) : d3{0.0, 0.0, 0.0};
-    }
+    for (int j = 0; j < CG_PASSES; ++j)
+        if (j == jp) ndp = mine ? nd[j] : -1;
+    d3 rv[CG_PASSES], zv{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < CG_PASSES; ++j) rv[j] = nd[j] >= 0 ? ld3(r, nd[j]) : d3{0.0, 0.0, 0.0};
+    if (ndp >= 0) zv = ld3(z, ndp);
     if (!on) return;   // uniform over the workgroup; nothing written yet
-    if (t < CG_N) rc[t] = 0.0;
-    __syncthreads();
+    // every group of the domain is one half wavefront of one pass, so each
+    // rc entry is written exactly once (0 for groups past the domain's end)
 #pragma unroll
     for (int j = 0; j < CG_PASSES; ++j) {
         double x = rv[j].x, y = rv[j].y, zz = rv[j].z;
@@ -311,33 +334,28 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(const int *__restrict
             y += __shfl_xor(y, o, TILE);
             zz += __shfl_xor(zz, o, TILE);
         }
-        const int g = (t + j * CG_APPLY) / CG_AGG;   // group of this half wavefront
-        if ((lane & (CG_AGG - 1)) == 0 && 3 * g < n) { rc[3 * g] = x; rc[3 * g + 1] = y; rc[3 * g + 2] = zz; }
-    }
-    __syncthreads();
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < KW; ++j) {
-        const double rk = rc[wave * KW + j];
-        a0 += m0[j] * rk;
-        a1 += m1[j] * rk;
-    }
-    zp[wave][lane] = a0;
-    if (lane + TILE < CG_N) zp[wave][lane + TILE] = a1;
-    __syncthreads();
-    if (t < CG_N) zc[t] = t < n ? (zp[0][t] + zp[1][t]) + (zp[2][t] + zp[3][t]) : 0.0;
-    __syncthreads();
-    double dot = t < n ? rc[t] * zc[t] : 0.0;
-    dot = wave_sum(dot);
-    if (lane == 0) sh[wave] = dot;
-#pragma unroll
-    for (int j = 0; j < CG_PASSES; ++j) {
-        if (nd[j] < 0) continue;
         const int g = (t + j * CG_APPLY) / CG_AGG;
-        st3(z, nd[j], {zv[j].x + zc[3 * g], zv[j].y + zc[3 * g + 1], zv[j].z + zc[3 * g + 2]});
+        if ((lane & (CG_AGG - 1)) == 0) { rc[3 * g] = x; rc[3 * g + 1] = y; rc[3 * g + 2] = zz; }
     }
     __syncthreads();
-    if (t == 0) part[d] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    if (t < 192) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < CG_CPL; ++j) a += m[j] * rc[cl + CG_CLANES * j];
+#pragma unroll
+        for (int o = CG_CLANES / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, TILE);
+        if (cl == 0) zl[i] = row < n ? a : 0.0;
+    }
+    __syncthreads();
+    if (ndp >= 0) {
+        const int g = eo / CG_AGG;
+        st3(z, ndp, {zv.x + zl[3 * g], zv.y + zl[3 * g + 1], zv.z + zl[3 * g + 2]});
+    }
+    if (t < TILE) {
+        double dot = t < CG_ROWS ? rc[CG_ROWS * sl + t] * zl[t] : 0.0;
+        dot = wave_sum(dot);
+        if (t == 0) part[(size_t)CG_SPLIT * d + sl] = dot;
+    }
 }
 
 void coarse_build(ipc_ctx *c)
@@ -355,8 +373,9 @@ void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int pa
 {
     if (!c->n_cdom || !c->coarse_on) return;
     Dev &D = c->d;
-    hipLaunchKernelGGL(k_coarse_apply, dim3(c->n_cdom), dim3(CG_APPLY), 0, c->stream, D.cg_ent.p, D.cg_nodes.p, D.cg_dom_scene.p,
-                       act, D.cg_inv.p, r, z, D.cg_part.p + (size_t)parity * c->n_cdom);
+    const int rounds = (c->n_cdom + NXCD - 1) / NXCD;
+    hipLaunchKernelGGL(k_coarse_apply, dim3(NXCD * CG_SPLIT * rounds), dim3(CG_APPLY), 0, c->stream, c->n_cdom, D.cg_ent.p,
+                       D.cg_nodes.p, D.cg_dom_scene.p, act, D.cg_inv.p, r, z, D.cg_part.p + (size_t)parity * CG_SPLIT * c->n_cdom);
 }
 
 } // namespace ipc

@@ -24,6 +24,7 @@ constexpr int BLOCK = 256;    // default workgroup: 4 wavefronts
 constexpr int CG_AGG = 32;    // coarse preconditioner: nodes per group
 constexpr int CG_DOM = 32;    // groups per coarse domain
 constexpr int CG_N = 3 * CG_DOM;   // coarse unknowns per domain
+constexpr int CG_SPLIT = 4;   // workgroups (row slices of the inverse) per domain in the apply
 constexpr int CG_MIN_NODES = 32768;  // contexts from this size apply it by default
 constexpr int LONG_ROW = 64;  // rows with more blocks go to the wavefront-per-row path
 constexpr int TRAV_STASH = 16;   // broad phase: candidates a query keeps from its counting pass

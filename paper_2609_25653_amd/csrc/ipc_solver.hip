@@ -607,7 +607,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     // the workgroup's scenes and the first one's tile and long-row ranges in
     // one record, so the partials' loads wait for a single load
     const int *wi = wginfo + WGI * (size_t)blockIdx.x;
-    const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction
+    const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction (CG_SPLIT per domain)
     const int sc_lo = wi[0], sc_hi = wi[1];
     const int my_sc = t < ntile ? tile_scene[t] : -1;
     double al = 0.0, be = 0.0;
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
             continue;
         }
         double gam, rr, del;
-        block_sums(tlo, thi, llo, lhi, clo, chi, rz_in, rr_in, part_zw, part_long, cz_in, sh, gam, rr, del);
+        block_sums(tlo, thi, llo, lhi, CG_SPLIT * clo, CG_SPLIT * chi, rz_in, rr_in, part_zw, part_long, cz_in, sh, gam, rr, del);
         // gamma = r.z, delta = z.Az of the current residual:
         //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
         //   alpha = gamma / p.Ap
@@ -774,7 +774,7 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
         prof_begin(c, IPC_K_PCG_UPDATE);
         hipLaunchKernelGGL(k_pcg_step, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p, D.node_body.p,
                            D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM), D.pcg_wginfo.p,
-                           D.cg_part.p, c->coarse_on ? c->n_cdom : 0, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
+                           D.cg_part.p, c->coarse_on ? CG_SPLIT * c->n_cdom : 0, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
                            r, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
         coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
