@@ -152,6 +152,11 @@ __device__ __forceinline__ int tile_of(int b, int n)
     return x * q + min(x, rem) + j;
 }
 
+#ifndef IPC_SPMV_U
+#define IPC_SPMV_U 2
+#endif
+constexpr int SPMV_U = IPC_SPMV_U;   // blocks per lane fetched together
+
 template <int L>
 __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *__restrict__ nlong, const int *__restrict__ long_rows,
                                                  const int *__restrict__ row_ptr, const int *__restrict__ col,
@@ -175,11 +180,37 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *_
         bool mine = false, on = false;
         if (n < N) {
             int k0 = row_ptr[n], k1 = row_ptr[n + 1], d0 = dptr[n], d1 = dptr[n + 1];
+            const int sc = node_scene[n];
             if ((k1 - k0) + (d1 - d0) <= LONG_ROW) {
                 mine = true;
-                on = !active || active[node_scene[n]];
+                // The lane's first SPMV_U blocks are fetched together: their
+                // columns before the scene's flag is known, then every block
+                // and vector entry at once, so that a row costs two round
+                // trips to memory instead of two per block.  Lanes past the
+                // row's end read slot 0 and column 0 and add nothing.
+                int ks[SPMV_U], cs[SPMV_U];
+#pragma unroll
+                for (int u = 0; u < SPMV_U; ++u) {
+                    const int k = k0 + sub + u * L;
+                    ks[u] = k < k1 ? k : 0;
+                    cs[u] = k < k1 ? col[k] : 0;
+                }
+                on = !active || active[sc];
                 if (on) {
-                    for (int k = k0 + sub; k < k1; k += L) acc_block(val + 9 * (size_t)k, ld3(v, col[k]), ax, ay, az);
+                    d3 w[SPMV_U];
+                    double B[SPMV_U][9];
+#pragma unroll
+                    for (int u = 0; u < SPMV_U; ++u) {
+                        w[u] = ld3(v, cs[u]);
+#pragma unroll
+                        for (int q = 0; q < 9; ++q) B[u][q] = val[9 * (size_t)ks[u] + q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < SPMV_U; ++u) {
+                        if (k0 + sub + u * L >= k1) w[u] = {0.0, 0.0, 0.0};
+                        acc_block(B[u], w[u], ax, ay, az);
+                    }
+                    for (int k = k0 + sub + SPMV_U * L; k < k1; k += L) acc_block(val + 9 * (size_t)k, ld3(v, col[k]), ax, ay, az);
                     for (int k = d0 + sub; k < d1; k += L) acc_block(dval + 9 * (size_t)k, ld3(v, dcol[k]), ax, ay, az);
                 }
             }
