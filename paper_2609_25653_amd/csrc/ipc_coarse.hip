@@ -98,6 +98,12 @@ void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
     D.cg_grp.upload(grp.empty() ? std::vector<int>(1, 0) : grp, c->stream);
     D.cg_ent.upload(ent, c->stream);
     D.cg_nodes.upload(nodes.empty() ? std::vector<int>(1, 0) : nodes, c->stream);
+    {   // the same lists padded to CG_AGG * CG_DOM entries per domain (-1 after the end)
+        std::vector<int> pn((size_t)std::max(ndom, 1) * CG_AGG * CG_DOM, -1);
+        for (int d = 0; d < ndom; ++d)
+            for (int e = ent[d]; e < ent[d + 1]; ++e) pn[(size_t)d * CG_AGG * CG_DOM + (e - ent[d])] = nodes[e];
+        D.cg_pnodes.upload(pn, c->stream);
+    }
     D.cg_node_da.upload(node_da, c->stream);
     D.cg_dom_scene.upload(dom_scene.empty() ? std::vector<int>(1, 0) : dom_scene, c->stream);
     // zero once: the entries past a short domain's n are never written and
@@ -283,7 +289,7 @@ constexpr int CG_CPL = CG_N / CG_CLANES;              // columns per lane
 constexpr int NXCD = 8;
 static_assert(CG_N % CG_SPLIT == 0 && CG_ROWS * CG_CLANES == 192 && CG_N % CG_CLANES == 0, "whole rows and columns per lane");
 static_assert(TILE % CG_CLANES == 0 && CG_SNODES <= CG_APPLY && CG_APPLY % CG_SNODES == 0, "lane groups inside a wavefront");
-__global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, const int *__restrict__ ent, const int *__restrict__ nodes,
+__global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, int single, const int *__restrict__ pnodes,
                                                            const int *__restrict__ dom_scene, const int *__restrict__ act,
                                                            const double *__restrict__ inv, const double *__restrict__ r,
                                                            double *__restrict__ z, double *__restrict__ part)
@@ -302,14 +308,12 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, const int *
 #pragma unroll
         for (int j = 0; j < CG_CPL; ++j) m[j] = M[CG_CLANES * j];
     }
-    const int on = act[dom_scene[d]];
-    const int e0 = ent[d], ne = ent[d + 1] - e0, n = 3 * ((ne + CG_AGG - 1) / CG_AGG);
+    const int on = act[single ? 0 : dom_scene[d]];
+    // the domain's entries from its padded list (-1 past a short domain's
+    // end): no wait for the entry offsets
     int nd[CG_PASSES];
 #pragma unroll
-    for (int j = 0; j < CG_PASSES; ++j) {
-        const int e = t + j * CG_APPLY;
-        nd[j] = e < ne ? nodes[e0 + e] : -1;
-    }
+    for (int j = 0; j < CG_PASSES; ++j) nd[j] = pnodes[(size_t)d * (CG_AGG * CG_DOM) + t + j * CG_APPLY];
     // the slice's entries are those of pass jp on a contiguous range of threads
     constexpr int PER_PASS = CG_APPLY / CG_SNODES;
     const int jp = sl / PER_PASS, eo = t + jp * CG_APPLY - CG_SNODES * sl;
@@ -344,7 +348,7 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, const int *
         for (int j = 0; j < CG_CPL; ++j) a += m[j] * rc[cl + CG_CLANES * j];
 #pragma unroll
         for (int o = CG_CLANES / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, TILE);
-        if (cl == 0) zl[i] = row < n ? a : 0.0;
+        if (cl == 0) zl[i] = a;   // rows past a short domain's end: rc and the inverse are 0 there
     }
     __syncthreads();
     if (ndp >= 0) {
@@ -374,8 +378,9 @@ void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int pa
     if (!c->n_cdom || !c->coarse_on) return;
     Dev &D = c->d;
     const int rounds = (c->n_cdom + NXCD - 1) / NXCD;
-    hipLaunchKernelGGL(k_coarse_apply, dim3(NXCD * CG_SPLIT * rounds), dim3(CG_APPLY), 0, c->stream, c->n_cdom, D.cg_ent.p,
-                       D.cg_nodes.p, D.cg_dom_scene.p, act, D.cg_inv.p, r, z, D.cg_part.p + (size_t)parity * CG_SPLIT * c->n_cdom);
+    hipLaunchKernelGGL(k_coarse_apply, dim3(NXCD * CG_SPLIT * rounds), dim3(CG_APPLY), 0, c->stream, c->n_cdom,
+                       (int)(c->n_scenes == 1), D.cg_pnodes.p, D.cg_dom_scene.p, act, D.cg_inv.p, r, z,
+                       D.cg_part.p + (size_t)parity * CG_SPLIT * c->n_cdom);
 }
 
 } // namespace ipc

@@ -335,6 +335,7 @@ struct Dev {
     // domain * CG_DOM + group, or -1 for nodes outside every group
     DBuf<int> cg_ent, cg_nodes, cg_node_da, cg_dom_scene;
     DBuf<int> cg_grp;                      // per group: domain * CG_DOM + group in the domain
+    DBuf<int> cg_pnodes;                   // per domain its node list padded to CG_AGG * CG_DOM entries (-1 after the end)
     DBuf<double> cg_inv, cg_part;
     DBuf<int> pcg_act, pcg_it;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix

@@ -241,7 +241,10 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *_
     // one workgroup per long row: all 64 L lanes stride over its blocks
     __shared__ double shl[3][NW];
     int w = (int)blockIdx.x - ntiles;
-    if (w >= nlong[0]) return;
+    if (w >= nlong[0]) {   // unused: a zero partial, so that a reduction may span all of them
+        if (part_long && threadIdx.x == 0) part_long[w] = 0.0;
+        return;
+    }
     int n = long_rows[w];
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool on = !active || active[node_scene[n]];
@@ -608,7 +611,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_init(int N, int ns, const int *__
 __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const int *__restrict__ kind, const int *__restrict__ node_body,
                                                     const int *__restrict__ tile_scene, const int *__restrict__ seg_nodew,
                                                     const int *__restrict__ seg_long, const int *__restrict__ seg_cdom,
-                                                    const int *__restrict__ wginfo, const double *__restrict__ cg_part, int ncdom,
+                                                    const int *__restrict__ wginfo, int single, int lcap,
+                                                    const double *__restrict__ cg_part, int ncdom,
                                                     const int *__restrict__ maxit, const double *__restrict__ dinv,
                                                     const double *__restrict__ dinvB, const double *__restrict__ w, double *__restrict__ p,
                                                     double *__restrict__ s, double *__restrict__ x, double *__restrict__ r,
@@ -621,33 +625,34 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     const int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
     const int t0 = blockIdx.x * WG_TILES, t = t0 + wave;
     const int n = t * TILE + lane;
-    // this node's operands first: their loads overlap the reductions below
+    // this node's operands first, without waiting for its kind: their loads
+    // overlap the reductions below
     int k = 2;
     d3 zv{}, pv{}, wv{}, sv{}, xv{}, rv{};
     double Mi[9];
     if (n < N) {
         k = kind[n];
-        if (k != 2) { zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n); }
-        if (k == 0) {
+        zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)n + q];
-        }
+        for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)n + q];
     }
     const double *rz_in = part + (size_t)(2 * q) * ntile, *rr_in = rz_in + ntile;
     double *rz_out = part + (size_t)(2 * (q ^ 1)) * ntile, *rr_out = rz_out + ntile;
     // the workgroup's scenes and the first one's tile and long-row ranges in
     // one record, so the partials' loads wait for a single load
+    // (a single scene needs no record: its ranges are all tiles, every
+    // long-row partial, unused ones being 0, and every coarse domain)
     const int *wi = wginfo + WGI * (size_t)blockIdx.x;
     const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction (CG_SPLIT per domain)
-    const int sc_lo = wi[0], sc_hi = wi[1];
-    const int my_sc = t < ntile ? tile_scene[t] : -1;
+    const int sc_lo = single ? 0 : wi[0], sc_hi = single ? 0 : wi[1];
+    const int my_sc = t < ntile ? (single ? 0 : tile_scene[t]) : -1;
     double al = 0.0, be = 0.0;
     bool on = false;
     for (int sc = sc_lo; sc <= sc_hi; ++sc) {   // uniform over the workgroup
         const bool first = sc == sc_lo;
-        const int tlo = first ? wi[2] : seg_nodew[sc], thi = first ? wi[3] : seg_nodew[sc + 1];
-        const int llo = first ? wi[4] : seg_long[sc], lhi = first ? wi[5] : seg_long[sc + 1];
-        const int clo = first ? wi[6] : seg_cdom[sc], chi = first ? wi[7] : seg_cdom[sc + 1];
+        const int tlo = single ? 0 : first ? wi[2] : seg_nodew[sc], thi = single ? ntile : first ? wi[3] : seg_nodew[sc + 1];
+        const int llo = single ? 0 : first ? wi[4] : seg_long[sc], lhi = single ? lcap : first ? wi[5] : seg_long[sc + 1];
+        const int clo = single ? 0 : first ? wi[6] : seg_cdom[sc], chi = single ? ncdom / CG_SPLIT : first ? wi[7] : seg_cdom[sc + 1];
         const int a = act[q * ns + sc], itc = it[q * ns + sc];
         const double *S = st + ((size_t)q * ns + sc) * 4;
         const bool writer = tlo / WG_TILES == (int)blockIdx.x && threadIdx.x == 0;
@@ -805,7 +810,7 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
         prof_begin(c, IPC_K_PCG_UPDATE);
         hipLaunchKernelGGL(k_pcg_step, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p, D.node_body.p,
                            D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM), D.pcg_wginfo.p,
-                           D.cg_part.p, c->coarse_on ? CG_SPLIT * c->n_cdom : 0, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
+                           (int)(ns == 1), c->long_cap, D.cg_part.p, c->coarse_on ? CG_SPLIT * c->n_cdom : 0, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
                            r, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
         coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
@@ -869,7 +874,7 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                                       (uintptr_t)D.row_ptr.p, (uintptr_t)D.col.p, (uintptr_t)D.val.p, (uintptr_t)D.dyn_ptr.p,
                                       (uintptr_t)D.dyn_col.p, (uintptr_t)D.dyn_val.p, (uintptr_t)D.node_scene.p,
                                       (uintptr_t)D.pcg_wginfo.p, (uintptr_t)(c->coarse_on ? c->n_cdom : 0), (uintptr_t)D.cg_ent.p, (uintptr_t)D.cg_nodes.p,
-                                      (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p};
+                                      (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p, (uintptr_t)D.cg_pnodes.p};
         bool have = key == c->pcg_key;
         for (auto xg : c->pcg_exec) have = have && xg;
         if (!have) {
