@@ -66,6 +66,42 @@ def cpu_baseline(scene):
                        f"FEM element loop only, the rest single-threaded; CPU {model}")}
 
 
+def bench_oracle(args):
+    """The oracle alone on the host cores (no GPU): the first --steps steps of
+    the 200k-tet squeeze, each complete, with the number of OpenMP threads
+    that OMP_NUM_THREADS gives (the FEM element loop; the rest runs on one
+    thread).  The CPU baseline of the contact workload over whole steps."""
+    import numpy as np
+    import ipcscenes
+    import oracle as O
+    scene = ipcscenes.contact_rich(n_steps=args.steps, s_g=args.s_g)
+    o = O.Oracle(scene)
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    steps = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        rc, st = o.step()
+        dt = time.perf_counter() - ts
+        steps.append({"step": k, "status": int(rc), "newton": int(st["newton_iters"]), "pcg": int(st["pcg_iters_total"]),
+                      "s": dt})
+        print(f"# oracle step {k}: rc={rc} newton={st['newton_iters']} pcg={st['pcg_iters_total']} {dt:.1f} s",
+              file=sys.stderr, flush=True)
+    t = time.perf_counter() - t0
+    newton = sum(x["newton"] for x in steps)
+    print(json.dumps({
+        "metric": "oracle Newton iters/s at 200k tets", "value": newton / t, "unit": "Newton iters/s", "steps": args.steps,
+        "steps_per_s": args.steps / t, "newton_per_step": newton / args.steps, "kind": "oracle", "cores": threads,
+        "cpu": model, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "contact-rich squeeze: 2 pads + soft cylinder on a ground patch",
+                   "tets": int(len(scene["tets"])), "ground_spacing": args.s_g},
+        "per_step": steps}))
+
+
 def write_traffic(fetch_csv, write_csv):
     """Calibrate FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by the 256 MiB
     device copy of a --traffic-run and store the product's bytes per launch
@@ -415,11 +451,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=8e-4, help="ground patch spacing (m): 0.8 mm keeps the median active pairs inside 50k-300k")
-    ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm", "dualmesh"], default="contact",
+    ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm", "dualmesh", "oracle"], default="contact",
                     help="contact: the 200k-tet squeeze (default line); batched: 256 uneven squeeze scenes stepped "
                          "together vs one at a time; adjoint: 50-step squeeze rollout, forward vs backward time; "
                          "arm: the squeeze on the joint-space arm vs on link-space target drives; "
-                         "dualmesh: the render mesh of the soft cylinder, 3 Loop levels, 100 frames per launch")
+                         "dualmesh: the render mesh of the soft cylinder, 3 Loop levels, 100 frames per launch; "
+                         "oracle: the first --steps steps of the 200k-tet squeeze on the CPU oracle alone (no GPU)")
     ap.add_argument("--frames", type=int, default=100, help="dualmesh: frames per launch")
     ap.add_argument("--scenes", type=int, default=256, help="batched: number of scenes")
     ap.add_argument("--single-sample", type=int, default=16, help="batched: scenes stepped one at a time for the baseline")
@@ -440,6 +477,8 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "oracle":
+        return bench_oracle(args)
     import numpy as np
     import torch
 
