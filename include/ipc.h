@@ -284,7 +284,14 @@ int ipc_pcg(ipc_ctx *ctx, const double *y_dev, const double *b_dev, double *x_de
  * Newton iterations with PCG directions, CCD step bounds and backtracking line
  * search until each scene's Newton measure is below its threshold.  stats_host
  * (nullable) receives n_scenes records.  Returns IPC_OK, or the first non-OK
- * scene status (IPC_E_NOT_CONVERGED leaves that scene at its last iterate). */
+ * scene status (IPC_E_NOT_CONVERGED leaves that scene at its last iterate).
+ * A scene also stops as converged at the energy's rounding floor: when its
+ * measure is within 10x its threshold and the line search had to cut the
+ * step below 1/1024 before the energy stopped increasing, with the accepted
+ * step changing the energy by at most 1e-13 of its value (the environment
+ * variable IPC_NO_FLOOR_STOP=1, read at create, turns this off).
+ * IPC_TRACE_NEWTON=<scene index>, read at create, prints that scene's
+ * Newton measures and line-search steps to stderr. */
 int ipc_step(ipc_ctx *ctx, const double *targets_dev, ipc_stats *stats_host);
 
 /* Differentiable parameters theta: the Young's modulus of every tetrahedron

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
 #include <map>
 #include <mutex>
 
@@ -501,6 +502,10 @@ static void read_options(ipc_ctx *c)
     const char *nc = std::getenv("IPC_PCG_COARSE");   // 0: never, 1: always, else by size and the autotuner
     c->coarse = !(nc && nc[0] == '0');
     c->coarse_forced = nc && nc[0] == '1';
+    const char *nf = std::getenv("IPC_NO_FLOOR_STOP");   // 1: no stop at the energy's rounding floor
+    c->floor_stop = !(nf && nf[0] == '1');
+    const char *tr = std::getenv("IPC_TRACE_NEWTON");   // a scene index: its Newton iterations on stderr
+    c->trace_scene = tr ? std::atoi(tr) : -1;
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) c->use_graphs = false;
 }
 
@@ -1059,6 +1064,9 @@ struct AssembleOnly {
     ~AssembleOnly() { c->assemble_only = nullptr; }
 };
 
+// The stop at the energy's rounding floor (see the line search below).
+constexpr double FLOOR_ALPHA = 1.0 / 1024.0, FLOOR_MEASURE = 10.0, FLOOR_ENERGY = 1e-13;
+
 void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
 {
     Dev &D = c->d;
@@ -1087,7 +1095,7 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         if (c->M_HS) rd.add(hs_nlag.data(), D.hs_nlag.p, ns * sizeof(int));
         rd.wait();
     }
-    std::vector<double> E0(ns);
+    std::vector<double> E0(ns), meas(ns, 0.0);
     for (int s = 0; s < ns; ++s) {
         E0[s] = sc[(size_t)s * NSLOT + S_E];
         if (sc[(size_t)s * NSLOT + S_INF] != 0.0) { S[s].status = IPC_E_INTERSECTING; on[s] = 0; }
@@ -1191,7 +1199,11 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
             S[s].newton_iters += 1;
             S[s].pcg_iters_total += it[s];
             S[s].pcg_iters_max = std::max(S[s].pcg_iters_max, it[s]);
-            if (sc[(size_t)s * NSLOT + S_NEWTON_MAX] <= c->sc[s].thr) { on[s] = 0; S[s].status = IPC_OK; }
+            if (s == c->trace_scene)
+                std::fprintf(stderr, "ipc trace: scene %d newton %d: measure %.6g (stop %.6g), pcg %d\n", s, S[s].newton_iters,
+                             sc[(size_t)s * NSLOT + S_NEWTON_MAX], c->sc[s].thr, it[s]);
+            meas[s] = sc[(size_t)s * NSLOT + S_NEWTON_MAX];
+            if (meas[s] <= c->sc[s].thr) { on[s] = 0; S[s].status = IPC_OK; }
             any |= on[s] != 0;
         }
         if (!any) break;
@@ -1258,7 +1270,21 @@ void newton_step(ipc_ctx *c, const double *targets_dev, ipc_stats *stats)
         for (int s = 0; s < ns; ++s) {
             sc[(size_t)s * NSLOT + S_LS_ON] = alpha[s] > 0.0 ? 1.0 : 0.0;
             sc[(size_t)s * NSLOT + S_LS_ALPHA] = alpha[s];
+            if (s == c->trace_scene)
+                std::fprintf(stderr, "ipc trace: scene %d line search: alpha %.6g (CCD bound %.6g), E %.17g -> %.17g\n", s, alpha[s],
+                             sc[(size_t)s * NSLOT + S_CCD], E0[s], Eacc[s]);
             if (alpha[s] > 0.0) {
+                // The rounding floor: a direction whose measure is within
+                // FLOOR_MEASURE of the stop, cut below FLOOR_ALPHA before the
+                // energy stopped increasing, and whose step changed the
+                // energy by no more than its rounding, cannot be resolved
+                // further by the energy: the step is taken and the scene
+                // stops as converged.
+                if (c->floor_stop && alpha[s] <= FLOOR_ALPHA && meas[s] <= FLOOR_MEASURE * c->sc[s].thr &&
+                    std::fabs(Eacc[s] - E0[s]) <= FLOOR_ENERGY * std::fabs(E0[s])) {
+                    on[s] = 0;
+                    S[s].status = IPC_OK;
+                }
                 E0[s] = Eacc[s];
                 S[s].energy = Eacc[s];
                 S[s].alpha_min = std::min(S[s].alpha_min, alpha[s]);

@@ -401,6 +401,8 @@ struct ipc_ctx {
     // some scenes have converged); the others keep stale values they never use
     const int *assemble_only = nullptr;
     bool use_graphs = true;              // PCG iterations replayed from a captured graph
+    int trace_scene = -1;                // IPC_TRACE_NEWTON: the scene whose Newton iterations go to stderr
+    bool floor_stop = true;              // the Newton stop at the energy's rounding floor (IPC_NO_FLOOR_STOP=1: off)
     hipStream_t cap_stream = nullptr;    // private stream used only for graph capture
     // PCG batch graphs, reused while every launch argument they captured is unchanged
     std::vector<uintptr_t> pcg_key;

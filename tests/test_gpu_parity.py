@@ -222,17 +222,27 @@ def test_half_steps_match_oracle():
     assert sim.scene_scalars()["newton_threshold"] == pytest.approx(o.newton_threshold, rel=1e-14)
 
 
-def test_step_adaptive_completes_and_conserves_momentum():
-    """Every one of 40 random velocity draws of two free tets completes 5
-    steps with the retry (11 of them end a plain step unconverged on the
-    oracle); linear momentum is conserved across every piece."""
+def _two_tet_draws(floor_stop):
+    """40 random velocity draws of two free tets, 5 steps each through
+    step_adaptive; returns the number of steps that needed the retry.  With
+    floor_stop False the Newton loop has no stop at the energy's rounding
+    floor (IPC_NO_FLOOR_STOP=1 at create), as in the oracle."""
+    import os
     from paper_2609_25653_amd import Sim
     retried = 0
     for seed in range(40):
         sc = S.tiny_scene("two_tets", n_steps=5, h=0.01)
         sc["g"] = np.zeros(3)
         sc["V"] = 0.05 * np.random.default_rng(seed).standard_normal(sc["V"].shape)
-        sim = Sim(sc)
+        old = os.environ.get("IPC_NO_FLOOR_STOP")
+        os.environ["IPC_NO_FLOOR_STOP"] = "0" if floor_stop else "1"
+        try:
+            sim = Sim(sc)
+        finally:
+            if old is None:
+                del os.environ["IPC_NO_FLOOR_STOP"]
+            else:
+                os.environ["IPC_NO_FLOOR_STOP"] = old
         m = O.Oracle(sc).mass()
         p0 = (m[:, None] * sc["V"]).sum(0)
         for k in range(5):
@@ -241,7 +251,23 @@ def test_step_adaptive_completes_and_conserves_momentum():
             retried += pieces > 1
             v = to_np(sim.state()[1]).reshape(-1, 3)
             assert np.abs((m[:, None] * v).sum(0) - p0).max() <= 1e-6 * np.abs(m[:, None] * sc["V"]).sum(), (seed, k)
-    assert retried >= 1
+    return retried
+
+
+def test_step_adaptive_completes_and_conserves_momentum():
+    """Without the rounding-floor stop, as in the oracle, some plain steps of
+    these draws end unconverged (11 of them on the oracle): every draw still
+    completes its 5 steps with the retry, and linear momentum is conserved
+    across every piece."""
+    assert _two_tet_draws(floor_stop=False) >= 1
+
+
+def test_rounding_floor_stop_converges_the_plain_steps():
+    """With the rounding-floor stop (the default), the same draws need no
+    retry: the steps that stalled with the measure just above its stop and
+    the energy unable to resolve a further decrease now end converged, and
+    momentum is conserved."""
+    assert _two_tet_draws(floor_stop=True) == 0
 
 
 def test_changed_timestep_free_fall():
