@@ -225,7 +225,7 @@ def bench_batched(args):
                           "sample": f"{len(pick)} scenes spread over the size range, each stepped alone over the same steps "
                                     f"({single_ok} of {single_all} scene-steps converged)"},
         "speedup_vs_one_at_a_time": (converged / t) / single_rate,
-        "max_newton_per_step": newton, "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
+        "max_newton_per_step": newton, "spmv_lanes_per_row": lanes, "fem_blocks": list(sim.fem_blocks), "pcg_coarse": sim.pcg_coarse,
         "scene_steps_by_status": {str(k): v for k, v in sorted(status.items())},
         "failed_scene_steps": failed,
     }
@@ -569,7 +569,7 @@ def main():
         "active_pairs": {"min": int(min(pairs)), "median": float(np.median(pairs)), "max": int(max(pairs))},
         "steps_by_status": {str(k): v for k, v in sorted(status.items())},
         "roofline": roof,
-        "spmv_lanes_per_row": lanes, "pcg_coarse": sim.pcg_coarse,
+        "spmv_lanes_per_row": lanes, "fem_blocks": list(sim.fem_blocks), "pcg_coarse": sim.pcg_coarse,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene)

@@ -152,7 +152,9 @@ enum {
     IPC_Q_WS_BYTES = 11,  /* workspace size of an ipc_create_ws context (0: the
                              context allocates its own memory)                */
     IPC_Q_WS_PEAK = 12,   /* the most workspace bytes in use at once so far    */
-    IPC_Q_SPMV_LANES = 13 /* lanes per row the Hessian product uses             */
+    IPC_Q_SPMV_LANES = 13, /* lanes per row the Hessian product uses            */
+    IPC_Q_FEM_BLOCKS = 14  /* workgroup sizes of the FEM assembly's kernels:
+                              (k_fem << 32) | (k_bsr_assemble << 16) | k_fem_grad_gather */
 };
 
 /* Flags of ipc_energy_grad_hess. */
@@ -364,7 +366,15 @@ int ipc_time_kernel(ipc_ctx *ctx, int kernel, int reps, double *avg_us, double *
  * process, keyed by the context's size bucket (the powers of two of the
  * static pattern's block count and of the node count, and whether it holds
  * several scenes); a context created later in the same bucket starts with
- * it (IPC_Q_SPMV_LANES).  Uses the context's solver scratch vectors. */
+ * it (IPC_Q_SPMV_LANES).  The same call then times the three kernels of the
+ * FEM assembly (element blocks and gradients, matrix-slot gather, node
+ * gradient gather) alone with 64, 128 and 256 threads per workgroup on the
+ * current state and keeps the fastest of each (256 unless another is more
+ * than 3 % faster; IPC_Q_FEM_BLOCKS), in the same per-bucket record.  No
+ * result depends on these choices.  The matrix values are left without the
+ * contact and body blocks until the next assembly (every step and
+ * ipc_energy_grad_hess assemble first).  Uses the context's solver scratch
+ * vectors. */
 int ipc_autotune(ipc_ctx *ctx, int reps, double *us_host, int32_t *lanes_host);
 
 #ifdef __cplusplus

@@ -269,8 +269,9 @@ class Sim:
         return rc, pieces
 
     def autotune(self, reps=20):
-        """Pick the product's lanes per row on the current matrix; returns
-        (lanes, {lanes: microseconds})."""
+        """Pick the product's lanes per row on the current matrix and the FEM
+        assembly's workgroup sizes on the current state (see fem_blocks);
+        returns (lanes, {lanes: microseconds})."""
         us = np.zeros(5)
         L = ctypes.c_int32()
         self._check(lib().ipc_autotune(self._h, int(reps), us.ctypes.data_as(_lib._D), ctypes.byref(L)))
@@ -286,6 +287,14 @@ class Sim:
         """Lanes per row of the Hessian product (the autotuner's choice, or
         the one tuned earlier in this process for a context of this size)."""
         return int(self._query(_lib.Q_SPMV_LANES))
+
+    @property
+    def fem_blocks(self):
+        """Workgroup sizes of the FEM assembly's three kernels (element
+        blocks, slot gather, gradient gather): the autotuner's choice, or the
+        one tuned earlier in this process for a context of this size."""
+        v = int(self._query(_lib.Q_FEM_BLOCKS))
+        return (v >> 32) & 0xffff, (v >> 16) & 0xffff, v & 0xffff
 
     # ---- adjoint --------------------------------------------------------------
     @property

@@ -525,8 +525,11 @@ static int precheck(const ipc_scene_desc *scenes, int n_scenes)
 // bucket of the context: powers of two of the block count of the static
 // matrix pattern and of the node count, and whether it holds several scenes.
 // A new context of a known bucket starts with the product's tuned lane count.
+struct Tuned {
+    int lanes, fem_block, asm_block, grad_block;
+};
 static std::mutex g_tune_mu;
-static std::map<uint32_t, int> g_tuned_lanes;
+static std::map<uint32_t, Tuned> g_tuned;
 
 static uint32_t tune_key(const ipc_ctx *c)
 {
@@ -536,10 +539,13 @@ static uint32_t tune_key(const ipc_ctx *c)
 
 static void adopt_tuned(ipc_ctx *c)
 {
-    if (c->spmv_lanes_forced) return;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned_lanes.find(tune_key(c));
-    if (it != g_tuned_lanes.end()) c->spmv_lanes = it->second;
+    auto it = g_tuned.find(tune_key(c));
+    if (it == g_tuned.end()) return;
+    if (!c->spmv_lanes_forced) c->spmv_lanes = it->second.lanes;
+    c->fem_block = it->second.fem_block;
+    c->asm_block = it->second.asm_block;
+    c->grad_block = it->second.grad_block;
 }
 
 extern "C" int ipc_create(const ipc_scene_desc *scenes, int n_scenes, void *hip_stream, ipc_ctx **out)
@@ -649,6 +655,7 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_WS_BYTES: *v = (int64_t)c->ws.size; return IPC_OK;
     case IPC_Q_WS_PEAK: *v = (int64_t)c->ws.peak; return IPC_OK;
     case IPC_Q_SPMV_LANES: *v = c->spmv_lanes; return IPC_OK;
+    case IPC_Q_FEM_BLOCKS: *v = ((int64_t)c->fem_block << 32) | ((int64_t)c->asm_block << 16) | c->grad_block; return IPC_OK;
     }
     return IPC_E_INVALID;
 }
@@ -1444,9 +1451,16 @@ extern "C" int ipc_autotune(ipc_ctx *c, int reps, double *us_host, int32_t *lane
         int keep = c->spmv_lanes;
         autotune_spmv(c, reps, us_host);
         if (c->spmv_lanes_forced) c->spmv_lanes = keep;
-        else {
+        autotune_fem(c, reps);
+        {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tuned_lanes[tune_key(c)] = c->spmv_lanes;
+            auto it = g_tuned.find(tune_key(c));
+            Tuned t = it != g_tuned.end() ? it->second : Tuned{8, BLOCK, BLOCK, BLOCK};
+            if (!c->spmv_lanes_forced) t.lanes = c->spmv_lanes;   // a fixed lane count is not a choice
+            t.fem_block = c->fem_block;
+            t.asm_block = c->asm_block;
+            t.grad_block = c->grad_block;
+            g_tuned[tune_key(c)] = t;
         }
         c->prof = prof;
         if (lanes_host) *lanes_host = c->spmv_lanes;

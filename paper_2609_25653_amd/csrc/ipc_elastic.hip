@@ -367,13 +367,13 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
     Dev &D = c->d;
     int64_t n9 = 9 * (int64_t)c->nnzb;
     if (c->T == 0) {
-        if (mode == 2) hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, 1, D.sc_ptr.p,
+        if (mode == 2) hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9, c->asm_block)), dim3(c->asm_block), 0, c->stream, n9, 1, D.sc_ptr.p,
                                           D.sc_list.p, D.telem.p, D.val_const.p, D.val.p, D.slot_scene.p, c->assemble_only);
         return;
     }
     const int *active = mode >= 1 ? c->assemble_only : nullptr;
     auto args = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(blocks_for(c->T)), dim3(BLOCK), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p, D.tmu.p,
+        hipLaunchKernelGGL(kern, dim3(blocks_for(c->T, c->fem_block)), dim3(c->fem_block), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p, D.tmu.p,
                            D.tlam.p, y, D.tile_scene_tet.p, h2s, D.tgrad.p, D.telem.p, (int)project, part, active);
     };
     int k = mode == 2 ? IPC_K_FEM_HESS : (mode == 0 ? IPC_K_FEM_ENERGY : -1);
@@ -382,16 +382,66 @@ void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, 
     else if (mode == 1) args(k_fem<1>);
     else args(k_fem<2>);
     if (mode >= 1)
-        hipLaunchKernelGGL(k_fem_grad_gather, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, c->T, D.fadj_ptr.p, D.fadj.p,
+        hipLaunchKernelGGL(k_fem_grad_gather, dim3(blocks_for(c->N, c->grad_block)), dim3(c->grad_block), 0, c->stream, c->N, c->T, D.fadj_ptr.p, D.fadj.p,
                            D.tgrad.p, g, D.node_scene.p, active);
     if (mode == 2)
-        hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9)), dim3(BLOCK), 0, c->stream, n9, c->T, D.sc_ptr.p, D.sc_list.p,
+        hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9, c->asm_block)), dim3(c->asm_block), 0, c->stream, n9, c->T, D.sc_ptr.p, D.sc_list.p,
                            D.telem.p, D.val_const.p, D.val.p, D.slot_scene.p, active);
     // algorithmic bytes: tet data in (112), per-tet gradient and upper blocks
     // out and back in (96 and 720, twice), node gradient in and out (48),
     // matrix out and its constant part in (2 x 72 per block)
     if (k >= 0)
         prof_end(c, k, mode == 2 ? (112.0 + 2 * 816.0) * c->TREAL + 48.0 * c->NFEM + 144.0 * c->nnzb : 112.0 * c->TREAL + 24.0 * c->NFEM);
+}
+
+// The workgroup sizes of the three kernels of the FEM assembly: each is timed
+// alone with 64, 128 and 256 threads (reps launches between HIP events on
+// the context's stream, on the current state; the gradient goes to a solver
+// scratch vector) and the fastest kept, 256 unless another is more than 3 %
+// faster.  The sums do not depend on the size (per thread, or per wavefront
+// of 64 consecutive tets), so the choice changes no result.  The matrix
+// values are left as const + FEM blocks: the next assembly rewrites them.
+void autotune_fem(ipc_ctx *c, int reps)
+{
+    if (c->T == 0) return;
+    Dev &D = c->d;
+    hipEvent_t e0, e1;
+    IPC_HIP(hipEventCreate(&e0));
+    IPC_HIP(hipEventCreate(&e1));
+    const int64_t n9 = 9 * (int64_t)c->nnzb;
+    const int sizes[3] = {64, 128, 256};
+    int *choice[3] = {&c->fem_block, &c->asm_block, &c->grad_block};
+    for (int which = 0; which < 3; ++which) {
+        double t256 = 1e300, best = 1e300;
+        int pick = BLOCK;
+        for (int bs : sizes) {
+            auto launch = [&] {
+                if (which == 0)
+                    hipLaunchKernelGGL(k_fem<2>, dim3(blocks_for(c->T, bs)), dim3(bs), 0, c->stream, c->T, D.tv.p, D.Bm.p, D.vol.p,
+                                       D.tmu.p, D.tlam.p, D.y.p, D.tile_scene_tet.p, D.h2s.p, D.tgrad.p, D.telem.p, 1, D.part_tet.p,
+                                       (const int *)nullptr);
+                else if (which == 1)
+                    hipLaunchKernelGGL(k_bsr_assemble, dim3(blocks_for(n9, bs)), dim3(bs), 0, c->stream, n9, c->T, D.sc_ptr.p,
+                                       D.sc_list.p, D.telem.p, D.val_const.p, D.val.p, D.slot_scene.p, (const int *)nullptr);
+                else
+                    hipLaunchKernelGGL(k_fem_grad_gather, dim3(blocks_for(c->N, bs)), dim3(bs), 0, c->stream, c->N, c->T, D.fadj_ptr.p,
+                                       D.fadj.p, D.tgrad.p, D.v2.p, D.node_scene.p, (const int *)nullptr);
+            };
+            launch();
+            IPC_HIP(hipEventRecord(e0, c->stream));
+            for (int k = 0; k < reps; ++k) launch();
+            IPC_HIP(hipEventRecord(e1, c->stream));
+            IPC_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            IPC_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double t = (double)ms / reps;
+            if (bs == BLOCK) t256 = t;
+            if (t < best) { best = t; pick = bs; }
+        }
+        *choice[which] = best < 0.97 * t256 ? pick : BLOCK;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s)

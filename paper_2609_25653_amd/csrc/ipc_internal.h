@@ -374,6 +374,7 @@ struct ipc_ctx {
     int64_t n_dyn = 0, cap_dyn = 0;       // pair-local blocks of the last assembly (merged), capacity
     int spmv_lanes = 8;                   // lanes per row of the product (autotuned)
     bool spmv_lanes_forced = false;       // set by IPC_SPMV_LANES: the autotuner times but keeps it
+    int fem_block = ipc::BLOCK, asm_block = ipc::BLOCK, grad_block = ipc::BLOCK;   // workgroups of k_fem, k_bsr_assemble, k_fem_grad_gather (autotuned)
     bool coarse = true;                   // coarse domains built (the PCG preconditioner's correction)
     bool coarse_on = false;               // the PCG applies the coarse correction
     bool coarse_forced = false;           // on by request, whatever the size

@@ -19,6 +19,7 @@ __device__ __forceinline__ double wave_max(double v)
 
 // elastic terms (ipc_elastic.hip)
 void launch_node_inertia(ipc_ctx *c, const double *y, double *g, double *part);
+void autotune_fem(ipc_ctx *c, int reps);
 void launch_fem(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s);
 void launch_body(ipc_ctx *c, int mode, const double *y, double *g, bool project, double *part, const double *h2s);
 void launch_spring(ipc_ctx *c, int mode, const double *y, double *g, double *part, const double *h2s);

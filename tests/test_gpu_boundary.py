@@ -130,3 +130,26 @@ def test_autotuned_lanes_carry_over_to_contexts_of_the_same_size():
     assert b.spmv_lanes == lanes
     other = Sim(pair[0])          # one scene: another bucket, not tuned
     assert other.spmv_lanes == 8
+
+
+def test_autotuned_fem_blocks_carry_over_and_change_no_result():
+    """The autotuner also picks the FEM assembly's workgroup sizes (64, 128
+    or 256 each), keeps them for the size bucket, and no result depends on
+    them: a tuned context and an untuned one step the pad squeeze bit for bit
+    alike."""
+    from paper_2609_25653_amd import Sim
+    sc = S.tiny_scene("pad_box", h=0.01, n_steps=12)
+    ref = Sim(sc)                   # created before this bucket is tuned: default sizes
+    assert ref.fem_blocks == (256, 256, 256)
+    a = Sim(sc)
+    a.step()
+    a.autotune(5)
+    blocks = a.fem_blocks
+    assert all(b in (64, 128, 256) for b in blocks)
+    b = Sim(sc)                     # same bucket: starts with the tuned sizes
+    assert b.fem_blocks == blocks
+    for k in range(6):
+        assert b.step()[0] == 0 and ref.step()[0] == 0
+        yb, vb = b.state()
+        yr, vr = ref.state()
+        assert torch.equal(yb, yr) and torch.equal(vb, vr), k
