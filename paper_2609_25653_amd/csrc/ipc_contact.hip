@@ -1518,25 +1518,28 @@ __global__ void k_dyn_count(int nb, int nf, const int *__restrict__ pflag, const
     cnt[i] = n;
 }
 
-// One wavefront per pair entry: lane j writes output block j of the entry,
-// row node j / total and column node j % total in the owner groups' order
-// (a pair touches at most two bodies, so at most 8 nodes and 64 blocks).  A
+// DYN_LANES lanes per pair entry: lane j writes output blocks j, j +
+// DYN_LANES, ... of the entry, block b at row node b / total and column node
+// b % total in the owner groups' order (a pair touches at most two bodies, so
+// at most 8 nodes and 64 blocks; one between FEM vertices at most 16).  A
 // thread per entry walked up to 64 blocks one after another, which took
-// 0.26 ms per assembly where a body met the pads.
+// 0.26 ms per assembly where a body met the pads; a wavefront per entry left
+// most lanes idle on FEM pairs (40 -> 72 us on the 200k-tet squeeze).
+constexpr int DYN_LANES = 16;
 __global__ void k_dyn_write(int nb, int nf, const int *__restrict__ off, const int4 *__restrict__ pcv, const int4 *__restrict__ lcv,
                             const double *__restrict__ pH, const double *__restrict__ lbeta, const double *__restrict__ lM,
                             const int *__restrict__ cv_node, const int *__restrict__ cv_body, const double *__restrict__ cv_x,
                             const int *__restrict__ body_node0, unsigned long long *__restrict__ key, int *__restrict__ idx,
                             double *__restrict__ valc)
 {
-    const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / TILE), lane = threadIdx.x & (TILE - 1);
+    const int i = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / DYN_LANES), lane = threadIdx.x & (DYN_LANES - 1);
     if (i >= nb + nf) return;
     const int o0 = off[i], n = off[i + 1] - o0;
     if (n == 0) return;
     Map mp[4];
     pair_maps(i, nb, pcv, lcv, cv_node, cv_body, cv_x, body_node0, mp);
     const PairNodes P = pair_nodes(mp);
-    for (int j = lane; j < n; j += TILE) {
+    for (int j = lane; j < n; j += DYN_LANES) {
         int ga = 0, qa = j / P.total, gb = 0, qb = j % P.total;
         while (qa >= P.nn[ga]) qa -= P.nn[ga++];
         while (qb >= P.nn[gb]) qb -= P.nn[gb++];
@@ -1702,7 +1705,7 @@ void build_dyn_blocks(ipc_ctx *c)
             for (auto *b : {&D.dyn_idx, &D.dyn_idx2, &D.dyn_head, &D.dyn_pos, &D.dyn_start, &D.dyn_row, &D.dyn_col}) b->alloc(c->cap_dyn + 1);
             D.dyn_val.alloc(9 * (size_t)c->cap_dyn); D.dyn_val_coo.alloc(9 * (size_t)c->cap_dyn);
         }
-        hipLaunchKernelGGL(k_dyn_write, dim3(blocks_for(n * TILE)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.dyn_off.p, D.pair_cv.p, D.lag_cv.p,
+        hipLaunchKernelGGL(k_dyn_write, dim3(blocks_for(n * DYN_LANES)), dim3(BLOCK), 0, st, (int)nb, (int)nf, D.dyn_off.p, D.pair_cv.p, D.lag_cv.p,
                            D.pair_H.p, D.lag_beta.p, D.lag_M.p, D.cv_node.p, D.cv_body.p, D.cv_x.p, D.body_node0.p, D.dyn_key64.p,
                            D.dyn_idx.p, D.dyn_val_coo.p);
         int end_bit = 33;
