@@ -151,13 +151,36 @@ def probe_spmv(sim):
                       "spmv_launches": 20, "spmv_avg_us": us.value, "spmv_algorithmic_bytes": by.value}))
 
 
+def product_roofline(sim, lib, traffic=None):
+    """The Hessian product's roofline: algorithmic bytes per launch over its
+    average duration inside PCG during the last timed step (HIP events that
+    each dispatch records; the step ran with ipc_profile on), and, as a
+    secondary figure, over 200 back-to-back launches on the last matrix."""
+    tot, nl, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    sim._check(lib().ipc_kernel_time(sim._h, K_SPMV, ctypes.byref(tot), ctypes.byref(nl), ctypes.byref(by)))
+    sim._check(lib().ipc_profile(sim._h, 0))
+    us_pcg = 1e3 * tot.value / max(nl.value, 1)
+    bytes_launch = by.value / max(nl.value, 1)
+    us, by2 = ctypes.c_double(), ctypes.c_double()
+    sim._check(lib().ipc_time_kernel(sim._h, K_SPMV, 200, ctypes.byref(us), ctypes.byref(by2)))
+    achieved = bytes_launch / (us_pcg * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)",
+            "bytes_per_launch": bytes_launch, "avg_us": us_pcg, "launches_timed": int(nl.value),
+            "timing": "HIP events stamped by each product launch inside PCG during the last timed step",
+            "back_to_back": {"avg_us": us.value, "achieved": by2.value / (us.value * 1e-6) / 1e9,
+                             "frac": by2.value / (us.value * 1e-6) / 1e9 / HBM_PEAK_GBS, "launches_timed": 200,
+                             "timing": "200 back-to-back launches on the last matrix between two HIP events"},
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE: bytes between L2 and the memory fabric (Infinity Cache or HBM)"}
+
+
 def bench_batched(args):
     """256 squeeze scenes of 1k-40k tets stepped together, against a sample of
     the same scenes spread over the size range, each stepped alone."""
     import numpy as np
     import torch
     import ipcscenes
-    from paper_2609_25653_amd import Sim
+    from paper_2609_25653_amd import Sim, lib
     n_total = args.warmup + args.steps
     scenes = ipcscenes.batched_squeeze(n_scenes=args.scenes, n_steps=n_total)
     tets = np.array([len(s["tets"]) for s in scenes])
@@ -177,7 +200,11 @@ def bench_batched(args):
     torch.cuda.synchronize()
     newton = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        if k == args.steps - 1:
+            # the product's launches inside PCG stamp HIP events in the last
+            # timed step, as in the contact workload
+            sim._check(lib().ipc_profile(sim._h, 1))
         rc, st = sim.step(allow_status=ok_codes)
         for i, s in enumerate(st):
             status[s["status"]] = status.get(s["status"], 0) + 1
@@ -193,6 +220,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     converged = status.get(0, 0)
+    roof = product_roofline(sim, lib)
     # one at a time: a sample spread over the size range, same steps
     order = np.argsort(tets)
     pick = order[np.linspace(0, len(scenes) - 1, min(args.single_sample, len(scenes))).round().astype(int)]
@@ -226,6 +254,7 @@ def bench_batched(args):
                                     f"({single_ok} of {single_all} scene-steps converged)"},
         "speedup_vs_one_at_a_time": (converged / t) / single_rate,
         "max_newton_per_step": newton, "spmv_lanes_per_row": lanes, "fem_blocks": list(sim.fem_blocks), "pcg_coarse": sim.pcg_coarse,
+        "roofline": roof,
         "scene_steps_by_status": {str(k): v for k, v in sorted(status.items())},
         "failed_scene_steps": failed,
     }
@@ -535,27 +564,8 @@ def main():
               f"pairs={pairs[-1]} pair_local={nloc} cand_max={st[0]['n_cand_max']} alpha_min={st[0]['alpha_min']:.3g}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    # Dominant kernel: the Hessian product inside PCG.  Launch duration: the
-    # dispatch-stamped HIP events of its launches in the last timed step.
-    tot, nl, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-    sim._check(lib().ipc_kernel_time(sim._h, K_SPMV, ctypes.byref(tot), ctypes.byref(nl), ctypes.byref(by)))
-    sim._check(lib().ipc_profile(sim._h, 0))
-    us_pcg = 1e3 * tot.value / max(nl.value, 1)
-    bytes_launch = by.value / max(nl.value, 1)
-    # secondary figure: 200 back-to-back launches on the last matrix between
-    # two HIP events (the matrix then stays warm in the caches)
-    us, by2 = ctypes.c_double(), ctypes.c_double()
-    sim._check(lib().ipc_time_kernel(sim._h, K_SPMV, 200, ctypes.byref(us), ctypes.byref(by2)))
-    achieved = bytes_launch / (us_pcg * 1e-6) / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": product_traffic(), "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)",
-            "bytes_per_launch": bytes_launch, "avg_us": us_pcg, "launches_timed": int(nl.value),
-            "timing": "HIP events stamped by each product launch inside PCG during the last timed step",
-            "back_to_back": {"avg_us": us.value, "achieved": by2.value / (us.value * 1e-6) / 1e9,
-                             "frac": by2.value / (us.value * 1e-6) / 1e9 / HBM_PEAK_GBS, "launches_timed": 200,
-                             "timing": "200 back-to-back launches on the last matrix between two HIP events"},
-            "traffic_note": "FETCH_SIZE + WRITE_SIZE: bytes between L2 and the memory fabric (Infinity Cache or HBM)"}
-    kt = {}
+    # Dominant kernel: the Hessian product inside PCG (see product_roofline).
+    roof = product_roofline(sim, lib, product_traffic())
     line = {
         "metric": METRIC, "value": newton / t, "unit": "Newton iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True, "scaling": "weak",

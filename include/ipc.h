@@ -333,7 +333,10 @@ int ipc_step_vjp(ipc_ctx *ctx, const double *y_prev_dev, const double *ydot_prev
  * the operation must move at minimum for its storage format: for IPC_K_SPMV,
  * 76 per stored 3x3 block (9 doubles + column index) of the matrix and of the
  * row-sorted pair-local contact blocks, 4 per row pointer of each, and 24 read
- * plus 24 written per FEM vertex and per body node). */
+ * plus 24 written per FEM vertex and per body node).  The products count
+ * these bytes themselves on the device, row by row: a row of a scene whose
+ * PCG has stopped adds only its row pointers, so a product launched past a
+ * scene's convergence is not credited with that scene's matrix. */
 enum {
     IPC_K_SPMV = 0,          /* Hessian product (block CSR + pair-local blocks) */
     IPC_K_FEM_HESS = 1,      /* FEM gradient + projected Hessian assembly        */

@@ -1427,6 +1427,17 @@ extern "C" int ipc_profile(ipc_ctx *c, int enable)
             prof_flush(c, k);
             if (enable) { c->timers[k].total_ms = 0.0; c->timers[k].launches = 0; c->timers[k].bytes = 0.0; }
         }
+        if (enable) {
+            c->d.prof_bytes.alloc(1);
+            c->d.prof_bytes.zero(c->stream, 1);
+            std::vector<int> rng(3 * (size_t)c->n_scenes);
+            for (int k = 0; k < c->n_scenes; ++k) {
+                rng[3 * (size_t)k] = c->sc[k].node0;
+                rng[3 * (size_t)k + 1] = c->sc[k].node0 + c->sc[k].nnode_pad;
+                rng[3 * (size_t)k + 2] = c->sc[k].nnode;
+            }
+            c->d.prof_scene.upload(rng, c->stream);
+        }
         c->prof = enable != 0;
     });
 }
@@ -1439,6 +1450,13 @@ extern "C" int ipc_kernel_time(ipc_ctx *c, int kernel, double *total_ms, int64_t
         if (total_ms) *total_ms = c->timers[kernel].total_ms;
         if (launches) *launches = c->timers[kernel].launches;
         if (bytes) *bytes = c->timers[kernel].bytes;
+        if (bytes && kernel == IPC_K_SPMV && c->d.prof_bytes.p) {
+            // counted per launch on the device: rows of stopped scenes are skipped
+            double nb = 0.0;
+            IPC_HIP(hipMemcpyAsync(&nb, c->d.prof_bytes.p, sizeof(nb), hipMemcpyDeviceToHost, c->stream));
+            IPC_HIP(hipStreamSynchronize(c->stream));
+            *bytes = nb;
+        }
     });
 }
 

@@ -328,6 +328,8 @@ struct Dev {
     // eta^2 b.b, r.r}, running flag and update count; per-tile partials of
     // r.z and r.r
     DBuf<double> pcg_st, pcg_part, pcg_prev;   // pcg_prev: r.r at the previous peek
+    DBuf<double> prof_bytes;               // profiled products: the algorithmic bytes they moved (1 counter)
+    DBuf<int> prof_scene;                  // per scene: first row, end row, real nodes (for that count)
     DBuf<int> pcg_wginfo;                  // per step workgroup: scenes and the first scene's ranges (8 ints)
     // coarse preconditioner: per domain its entry range (ent, n_cdom + 1) into
     // the node list (groups of CG_AGG consecutive entries), its scene, its

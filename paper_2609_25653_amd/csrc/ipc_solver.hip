@@ -297,11 +297,40 @@ static void spmv_launch(ipc_ctx *c, int L, const double *v, double *out, const i
 #undef IPC_SPMV_ARGS
 }
 
+// Profiled products: the algorithmic bytes of one launch from the scenes it
+// did not skip, added to a counter by a small launch after the product (its
+// HIP events bracket the product alone): per scene 8 B per row, and for a
+// scene still iterating 76 B per block of its rows (matrix and pair-local)
+// and 48 B per real node.  With every scene on this is spmv_bytes.
+__global__ void __launch_bounds__(BLOCK) k_spmv_bytes(int ns, const int *__restrict__ rng, const int *__restrict__ row_ptr,
+                                                      const int *__restrict__ dptr, const int *__restrict__ active,
+                                                      double *__restrict__ total)
+{
+    __shared__ double sh[BLOCK / TILE];
+    double b = 0.0;
+    for (int s = threadIdx.x; s < ns; s += BLOCK) {
+        const int n0 = rng[3 * (size_t)s], n1 = rng[3 * (size_t)s + 1];
+        b += 8.0 * (n1 - n0);
+        if (!active || active[s]) b += 76.0 * ((row_ptr[n1] - row_ptr[n0]) + (dptr[n1] - dptr[n0])) + 48.0 * rng[3 * (size_t)s + 2];
+    }
+    b = wave_sum(b);
+    if ((threadIdx.x & (TILE - 1)) == 0) sh[threadIdx.x / TILE] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int q = 1; q < BLOCK / TILE; ++q) t += sh[q];
+        total[0] += t;
+    }
+}
+
 void hess_apply(ipc_ctx *c, const double *v, double *out, const int *active, double *part)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     prof_dispatch_events(c, IPC_K_SPMV, &e0, &e1, spmv_bytes(c));
     spmv_launch(c, c->spmv_lanes, v, out, active, part, e0, e1);
+    if (e0 && c->d.prof_bytes.p)
+        hipLaunchKernelGGL(k_spmv_bytes, dim3(1), dim3(BLOCK), 0, c->stream, c->n_scenes, c->d.prof_scene.p, c->d.row_ptr.p,
+                           c->d.dyn_ptr.p, active, c->d.prof_bytes.p);
 }
 
 // Time every lane count on the current matrix (reps back-to-back launches
