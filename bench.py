@@ -5,7 +5,8 @@ Young's modulus) that rests on a finely meshed static ground patch, 200k tets
 in all, dhat = 5e-4 m, dt = 5 ms.  Synthetic seeded geometry; FP64 throughout.
 
 Timed: K full steps (every Newton iteration with assembly, PCG, CCD, line
-search), after W untimed warm-up steps, between device synchronisations.  The
+search), after W untimed warm-up steps, between device synchronisations; by
+default steps 2-100 of the scene (K = 99, W = 1): the squeeze and the lift.  The
 JSON line reports Newton iterations per second as ``value`` plus steps per
 second, the roofline object of the dominant kernel (durations from HIP events
 the library records on its own stream during the timed steps) and the oracle's
@@ -476,8 +477,10 @@ def write_dm_traffic(fetch_csv, write_csv):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: contact and batched 99, arm 160, dualmesh 20 launches, oracle 5)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warm-up steps (default: contact and batched 1, arm 40, dualmesh 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=8e-4, help="ground patch spacing (m): 0.8 mm keeps the median active pairs inside 50k-300k")
     ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm", "dualmesh", "oracle"], default="contact",
@@ -499,6 +502,14 @@ def main():
                     help="spmv: assemble the Hessian of the 200k-tet scene once, then run a plain 256 MiB device copy "
                          "and 20 back-to-back block-CSR products (for hardware-counter runs)")
     args = ap.parse_args()
+    # the contact default times steps 2-100 of the 100-step scene: the squeeze
+    # and the lift; the first step (the most pairs) warms up
+    steps_default = {"contact": 99, "batched": 99, "arm": 160, "dualmesh": 20, "oracle": 5, "adjoint": 50}
+    warmup_default = {"contact": 1, "batched": 1, "arm": 40, "dualmesh": 2, "oracle": 0, "adjoint": 40}
+    if args.steps is None:
+        args.steps = 4 if (args.traffic_run or args.probe) else steps_default[args.workload]
+    if args.warmup is None:
+        args.warmup = 1 if (args.traffic_run or args.probe) else warmup_default[args.workload]
     if args.traffic_from:
         if args.workload == "dualmesh":
             return write_dm_traffic(*args.traffic_from)
