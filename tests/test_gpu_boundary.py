@@ -137,17 +137,28 @@ def test_autotuned_fem_blocks_carry_over_and_change_no_result():
     or 256 each), keeps them for the size bucket, and no result depends on
     them: a tuned context and an untuned one step the pad squeeze bit for bit
     alike."""
+    import os
     from paper_2609_25653_amd import Sim
     sc = S.tiny_scene("pad_box", h=0.01, n_steps=12)
-    ref = Sim(sc)                   # created before this bucket is tuned: default sizes
-    assert ref.fem_blocks == (256, 256, 256)
-    a = Sim(sc)
-    a.step()
-    a.autotune(5)
-    blocks = a.fem_blocks
-    assert all(b in (64, 128, 256) for b in blocks)
-    b = Sim(sc)                     # same bucket: starts with the tuned sizes
-    assert b.fem_blocks == blocks
+    # the product's lane count changes the order of its sums, so it is fixed
+    # here: only the FEM workgroup sizes differ between the two contexts
+    old = os.environ.get("IPC_SPMV_LANES")
+    os.environ["IPC_SPMV_LANES"] = "8"
+    try:
+        ref = Sim(sc)               # created before this bucket is tuned: default sizes
+        assert ref.fem_blocks == (256, 256, 256)
+        a = Sim(sc)
+        a.step()
+        a.autotune(5)
+        blocks = a.fem_blocks
+        assert all(b in (64, 128, 256) for b in blocks)
+        b = Sim(sc)                 # same bucket: starts with the tuned sizes
+    finally:
+        if old is None:
+            del os.environ["IPC_SPMV_LANES"]
+        else:
+            os.environ["IPC_SPMV_LANES"] = old
+    assert b.fem_blocks == blocks and b.spmv_lanes == ref.spmv_lanes == 8
     for k in range(6):
         assert b.step()[0] == 0 and ref.step()[0] == 0
         yb, vb = b.state()
