@@ -152,6 +152,27 @@ def probe_spmv(sim):
                       "spmv_launches": 20, "spmv_avg_us": us.value, "spmv_algorithmic_bytes": by.value}))
 
 
+def copy_bandwidth():
+    """The measured achievable bandwidth: a plain 1 GiB device-to-device copy
+    (torch's copy kernel; read + write bytes), best of 6, between CUDA events
+    on torch's stream."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (best * 1e-3) / 1e9
+
+
 def product_roofline(sim, lib, traffic=None):
     """The Hessian product's roofline: algorithmic bytes per launch over its
     average duration inside PCG during the last timed step (HIP events that
@@ -165,7 +186,11 @@ def product_roofline(sim, lib, traffic=None):
     us, by2 = ctypes.c_double(), ctypes.c_double()
     sim._check(lib().ipc_time_kernel(sim._h, K_SPMV, 200, ctypes.byref(us), ctypes.byref(by2)))
     achieved = bytes_launch / (us_pcg * 1e-6) / 1e9
+    copy = copy_bandwidth()
+    b2b = by2.value / (us.value * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "achievable": {"copy_gbs": copy, "frac_of_copy": achieved / copy, "back_to_back_frac_of_copy": b2b / copy,
+                           "note": "a plain 1 GiB device copy (read + write), best of 6: the measured bandwidth ceiling"},
             "traffic": traffic, "kernel": "k_spmv (Hessian product: block CSR + row-sorted pair-local blocks)",
             "bytes_per_launch": bytes_launch, "avg_us": us_pcg, "launches_timed": int(nl.value),
             "timing": "HIP events stamped by each product launch inside PCG during the last timed step",
