@@ -267,18 +267,32 @@ __global__ void __launch_bounds__(DM_ROWS) k_dm_apply_lds(int nf, int nc, int fr
             w[k] = in ? val[k0 + k] : 0.0;
         }
     }
-    for (int f = 0; f < frames; ++f) {
+    // the next frame's staged positions are loaded into registers while this
+    // frame is summed and stored, so the gather's latency overlaps the work
+    double pf[PER][3];
+    auto fetch = [&](int f) {
         const double *x = xc + (size_t)f * nc * 3;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (src[q] >= 0) {
+                pf[q][0] = x[3 * (size_t)src[q]];
+                pf[q][1] = x[3 * (size_t)src[q] + 1];
+                pf[q][2] = x[3 * (size_t)src[q] + 2];
+            }
+    };
+    if (frames > 0) fetch(0);
+    for (int f = 0; f < frames; ++f) {
         __syncthreads();   // the previous frame's reads of sx are done
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             if (src[q] >= 0) {
                 const int u = t + q * DM_ROWS;
-                sx[3 * u] = x[3 * (size_t)src[q]];
-                sx[3 * u + 1] = x[3 * (size_t)src[q] + 1];
-                sx[3 * u + 2] = x[3 * (size_t)src[q] + 2];
+                sx[3 * u] = pf[q][0];
+                sx[3 * u + 1] = pf[q][1];
+                sx[3 * u + 2] = pf[q][2];
             }
         }
+        if (f + 1 < frames) fetch(f + 1);
         __syncthreads();
         if (r < nf) {
             double ax = 0.0, ay = 0.0, az = 0.0;
