@@ -503,9 +503,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: contact and batched 99, arm 160, dualmesh 20 launches, oracle 5)")
+                    help="timed steps (default: contact and batched 99, arm 160, dualmesh 200 launches, oracle 5)")
     ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed warm-up steps (default: contact and batched 1, arm 40, dualmesh 2)")
+                    help="untimed warm-up steps (default: contact and batched 1, arm 40, dualmesh 10)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--s-g", type=float, default=8e-4, help="ground patch spacing (m): 0.8 mm keeps the median active pairs inside 50k-300k")
     ap.add_argument("--workload", choices=["contact", "batched", "adjoint", "arm", "dualmesh", "oracle"], default="contact",
@@ -529,8 +529,8 @@ def main():
     args = ap.parse_args()
     # the contact default times steps 2-100 of the 100-step scene: the squeeze
     # and the lift; the first step (the most pairs) warms up
-    steps_default = {"contact": 99, "batched": 99, "arm": 160, "dualmesh": 20, "oracle": 5, "adjoint": 50}
-    warmup_default = {"contact": 1, "batched": 1, "arm": 40, "dualmesh": 2, "oracle": 0, "adjoint": 40}
+    steps_default = {"contact": 99, "batched": 99, "arm": 160, "dualmesh": 200, "oracle": 5, "adjoint": 50}
+    warmup_default = {"contact": 1, "batched": 1, "arm": 40, "dualmesh": 10, "oracle": 0, "adjoint": 40}
     if args.steps is None:
         args.steps = 4 if (args.traffic_run or args.probe) else steps_default[args.workload]
     if args.warmup is None:
