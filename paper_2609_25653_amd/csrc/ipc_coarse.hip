@@ -198,34 +198,52 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
 // block that is not positive definite (the unprojected Hessian of the
 // adjoint can be indefinite) gets a zero inverse: there the preconditioner
 // is block-Jacobi alone.
-constexpr int CG_INV = 1024, CG_PER = CG_N * CG_N / CG_INV;
-static_assert(CG_N * CG_N % CG_INV == 0, "whole entries per thread");
+// One workgroup per domain: Gauss-Jordan on the 3x3 diagonal pivot blocks
+// K of the domain's block of P^T A P (n is a multiple of 3; the matrix is SPD,
+// so every pivot block is and no exchanges are needed):
+//     A_IJ -= A_IK P^-1 A_KJ off row and column K,
+//     A_KJ <- P^-1 A_KJ,  A_IK <- -A_IK P^-1,  A_KK <- P^-1,  P = A_KK.
+// Thread t keeps the 3x3 tile (I, J) = (t / 32, t % 32) of the 96 x 96
+// matrix in registers for the whole inversion; at each step the 63 tiles of
+// row and column K are published to LDS, every thread reads the pivot and
+// the two tiles it needs, and updates its own tile.  (The first version kept
+// the whole matrix in LDS and updated 9 scattered entries per thread, each
+// with six LDS reads and a read-modify-write: 97 us per assembly.)  Rows and
+// columns past a short domain's n stay the identity.  A pivot that is not
+// positive definite (the adjoint's unprojected Hessian) gives the domain a
+// zero inverse.
+constexpr int CG_INV = 1024, CG_T = CG_N / 3;   // threads; tiles per row
+static_assert(CG_T * CG_T == CG_INV, "one 3x3 tile per thread");
 __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict__ ent, double *__restrict__ mat,
                                                           const int *__restrict__ dom_scene, const int *__restrict__ active)
 {
-    __shared__ double A[CG_N * CG_N];
+    __shared__ double rowK[CG_T][9], colK[CG_T][9];   // the tiles of pivot row and column K
     const int d = blockIdx.x, ne = ent[d + 1] - ent[d], n = 3 * ((ne + CG_AGG - 1) / CG_AGG);
     if (active && !active[dom_scene[d]]) return;   // uniform over the workgroup
     double *G = mat + (size_t)d * CG_N * CG_N;
-    int qi[CG_PER], qj[CG_PER];
+    const int I = threadIdx.x / CG_T, J = threadIdx.x % CG_T;
+    double a[3][3];
 #pragma unroll
-    for (int m = 0; m < CG_PER; ++m) {
-        const int q = threadIdx.x + m * CG_INV;
-        qi[m] = q / CG_N; qj[m] = q % CG_N;
-        A[q] = (qi[m] < n && qj[m] < n) ? G[q] : (qi[m] == qj[m] ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    // Gauss-Jordan on 3x3 diagonal pivot blocks K = {k, k+1, k+2} (n is a
-    // multiple of 3; the matrix is SPD, so every pivot block is and no
-    // exchanges are needed): A_ij -= A_iK P^-1 A_Kj off K, then row K <-
-    // P^-1 A_K., column K <- -A_.K P^-1 and the pivot block <- P^-1
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = 3 * I + r, j = 3 * J + c;
+            a[r][c] = (i < n && j < n) ? G[(size_t)i * CG_N + j] : (i == j ? 1.0 : 0.0);
+        }
     bool bad = false;
-    for (int k = 0; k < n; k += 3) {
+    for (int K = 0; 3 * K < n; ++K) {
+        if (I == K) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) rowK[J][q] = a[q / 3][q % 3];
+        }
+        if (J == K) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) colK[I][q] = a[q / 3][q % 3];
+        }
+        __syncthreads();
         double p[3][3];   // every thread reads the same pivot block
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) p[a][b] = A[(k + a) * CG_N + k + b];
+        for (int q = 0; q < 9; ++q) p[q / 3][q % 3] = rowK[K][q];
         const double c00 = p[1][1] * p[2][2] - p[1][2] * p[2][1], c01 = p[1][2] * p[2][0] - p[1][0] * p[2][2],
                      c02 = p[1][0] * p[2][1] - p[1][1] * p[2][0], c10 = p[0][2] * p[2][1] - p[0][1] * p[2][2],
                      c11 = p[0][0] * p[2][2] - p[0][2] * p[2][0], c12 = p[0][1] * p[2][0] - p[0][0] * p[2][1],
@@ -234,37 +252,46 @@ __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict_
         const double det = p[0][0] * c00 + p[0][1] * c01 + p[0][2] * c02;
         if (!(p[0][0] > 0.0 && c22 > 0.0 && det > 0.0)) { bad = true; break; }   // uniform
         const double id = 1.0 / det;
-        const double q[3][3] = {{c00 * id, c10 * id, c20 * id}, {c01 * id, c11 * id, c21 * id}, {c02 * id, c12 * id, c22 * id}};
+        const double qi[3][3] = {{c00 * id, c10 * id, c20 * id}, {c01 * id, c11 * id, c21 * id}, {c02 * id, c12 * id, c22 * id}};
+        if (I != K && J != K) {
+            // w = P^-1 A_KJ, column by column, then A_IJ -= A_IK w
 #pragma unroll
-        for (int m = 0; m < CG_PER; ++m) {
-            const int i = qi[m], j = qj[m];
-            if ((unsigned)(i - k) < 3u || (unsigned)(j - k) < 3u) continue;
-            const double b0 = A[k * CG_N + j], b1 = A[(k + 1) * CG_N + j], b2 = A[(k + 2) * CG_N + j];
-            const double w0 = q[0][0] * b0 + q[0][1] * b1 + q[0][2] * b2, w1 = q[1][0] * b0 + q[1][1] * b1 + q[1][2] * b2,
-                         w2 = q[2][0] * b0 + q[2][1] * b1 + q[2][2] * b2;
-            A[i * CG_N + j] -= A[i * CG_N + k] * w0 + A[i * CG_N + k + 1] * w1 + A[i * CG_N + k + 2] * w2;
-        }
-        __syncthreads();
-        const int t = threadIdx.x;   // column t of the pivot rows and row t of the pivot columns
-        if (t < n) {
-            if ((unsigned)(t - k) >= 3u) {
-                const double b0 = A[k * CG_N + t], b1 = A[(k + 1) * CG_N + t], b2 = A[(k + 2) * CG_N + t];
-                const double a0 = A[t * CG_N + k], a1 = A[t * CG_N + k + 1], a2 = A[t * CG_N + k + 2];
+            for (int c = 0; c < 3; ++c) {
+                const double b0 = rowK[J][c], b1 = rowK[J][3 + c], b2 = rowK[J][6 + c];
+                const double w0 = qi[0][0] * b0 + qi[0][1] * b1 + qi[0][2] * b2, w1 = qi[1][0] * b0 + qi[1][1] * b1 + qi[1][2] * b2,
+                             w2 = qi[2][0] * b0 + qi[2][1] * b1 + qi[2][2] * b2;
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    A[(k + r) * CG_N + t] = q[r][0] * b0 + q[r][1] * b1 + q[r][2] * b2;
-                    A[t * CG_N + k + r] = -(a0 * q[0][r] + a1 * q[1][r] + a2 * q[2][r]);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) A[t * CG_N + k + r] = q[t - k][r];
+                for (int r = 0; r < 3; ++r) a[r][c] -= colK[I][3 * r] * w0 + colK[I][3 * r + 1] * w1 + colK[I][3 * r + 2] * w2;
             }
+        } else if (I == K && J != K) {
+            double b[3][3];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) b[q / 3][q % 3] = a[q / 3][q % 3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a[r][c] = qi[r][0] * b[0][c] + qi[r][1] * b[1][c] + qi[r][2] * b[2][c];
+        } else if (J == K && I != K) {
+            double b[3][3];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) b[q / 3][q % 3] = a[q / 3][q % 3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a[r][c] = -(b[r][0] * qi[0][c] + b[r][1] * qi[1][c] + b[r][2] * qi[2][c]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) a[q / 3][q % 3] = qi[q / 3][q % 3];
         }
-        __syncthreads();
+        __syncthreads();   // the tiles of row and column K are read before the next step publishes its own
     }
 #pragma unroll
-    for (int m = 0; m < CG_PER; ++m)
-        if (qi[m] < n && qj[m] < n) G[threadIdx.x + m * CG_INV] = bad ? 0.0 : A[threadIdx.x + m * CG_INV];
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i = 3 * I + r, j = 3 * J + c;
+            if (i < n && j < n) G[(size_t)i * CG_N + j] = bad ? 0.0 : a[r][c];
+        }
 }
 
 // CG_SPLIT workgroups per domain of a scene that updated its residual
