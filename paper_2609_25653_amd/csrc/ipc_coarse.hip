@@ -189,15 +189,6 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
     }
 }
 
-// One workgroup per domain: the inverse of its n x n block (n = 3 x groups)
-// by Gauss-Jordan elimination in LDS on 3x3 diagonal pivot blocks, without
-// exchanges (every diagonal block of an SPD matrix is SPD), written over the
-// block: n / 3 steps of two barriers each.  The block is padded to CG_N with
-// the identity, which stays decoupled, so every thread keeps the same
-// CG_N^2 / CG_INV entries for all pivots.  A domain whose block shows a pivot
-// block that is not positive definite (the unprojected Hessian of the
-// adjoint can be indefinite) gets a zero inverse: there the preconditioner
-// is block-Jacobi alone.
 // One workgroup per domain: Gauss-Jordan on the 3x3 diagonal pivot blocks
 // K of the domain's block of P^T A P (n is a multiple of 3; the matrix is SPD,
 // so every pivot block is and no exchanges are needed):
@@ -210,8 +201,9 @@ __global__ void __launch_bounds__(CG_ASM) k_coarse_assemble(const int *__restric
 // the whole matrix in LDS and updated 9 scattered entries per thread, each
 // with six LDS reads and a read-modify-write: 97 us per assembly.)  Rows and
 // columns past a short domain's n stay the identity.  A pivot that is not
-// positive definite (the adjoint's unprojected Hessian) gives the domain a
-// zero inverse.
+// positive definite (the adjoint's unprojected Hessian can be indefinite)
+// gives the domain a zero inverse: there the preconditioner is block-Jacobi
+// alone.  n / 3 steps of two barriers each.
 constexpr int CG_INV = 1024, CG_T = CG_N / 3;   // threads; tiles per row
 static_assert(CG_T * CG_T == CG_INV, "one 3x3 tile per thread");
 __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict__ ent, double *__restrict__ mat,
