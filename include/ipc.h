@@ -153,8 +153,13 @@ enum {
                              context allocates its own memory)                */
     IPC_Q_WS_PEAK = 12,   /* the most workspace bytes in use at once so far    */
     IPC_Q_SPMV_LANES = 13, /* lanes per row the Hessian product uses            */
-    IPC_Q_FEM_BLOCKS = 14  /* workgroup sizes of the FEM assembly's kernels:
+    IPC_Q_FEM_BLOCKS = 14, /* workgroup sizes of the FEM assembly's kernels:
                               (k_fem << 32) | (k_bsr_assemble << 16) | k_fem_grad_gather */
+    IPC_Q_PCG_FUSED = 15   /* 1 when a PCG iteration applies the coarse correction
+                              inside its update launch (one scene, correction on;
+                              the environment variable IPC_NO_FUSED_PCG = 1, read
+                              at ipc_create, keeps it in a launch of its own).
+                              Both forms give the same bits.                  */
 };
 
 /* Flags of ipc_energy_grad_hess. */

@@ -283,6 +283,12 @@ class Sim:
         return bool(self._query(_lib.Q_COARSE))
 
     @property
+    def pcg_fused(self):
+        """Whether a PCG iteration applies the coarse correction inside its
+        update launch (same bits as the two-launch form)."""
+        return bool(self._query(_lib.Q_PCG_FUSED))
+
+    @property
     def spmv_lanes(self):
         """Lanes per row of the Hessian product (the autotuner's choice, or
         the one tuned earlier in this process for a context of this size)."""

@@ -28,7 +28,7 @@ IPC_PSD_PROJECT = 1
 IPC_WITH_FRICTION = 2
 
 Q_NDOF, Q_NSCENES, Q_NDRIVEN, Q_NTRI, Q_NEDGE, Q_NNODES, Q_NTETS, Q_NLOCAL, Q_NPAIRS, Q_NTETS_EXT, Q_COARSE, Q_WS_BYTES, Q_WS_PEAK, \
-    Q_SPMV_LANES, Q_FEM_BLOCKS = range(15)
+    Q_SPMV_LANES, Q_FEM_BLOCKS, Q_PCG_FUSED = range(16)
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int32)

@@ -502,6 +502,8 @@ static void read_options(ipc_ctx *c)
     const char *nc = std::getenv("IPC_PCG_COARSE");   // 0: never, 1: always, else by size and the autotuner
     c->coarse = !(nc && nc[0] == '0');
     c->coarse_forced = nc && nc[0] == '1';
+    const char *nfp = std::getenv("IPC_NO_FUSED_PCG");   // 1: the coarse correction in a launch of its own
+    c->pcg_fused = !(nfp && nfp[0] == '1');
     const char *nf = std::getenv("IPC_NO_FLOOR_STOP");   // 1: no stop at the energy's rounding floor
     c->floor_stop = !(nf && nf[0] == '1');
     const char *tr = std::getenv("IPC_TRACE_NEWTON");   // a scene index: its Newton iterations on stderr
@@ -656,6 +658,7 @@ extern "C" int ipc_query(const ipc_ctx *c, int what, int64_t *v)
     case IPC_Q_WS_PEAK: *v = (int64_t)c->ws.peak; return IPC_OK;
     case IPC_Q_SPMV_LANES: *v = c->spmv_lanes; return IPC_OK;
     case IPC_Q_FEM_BLOCKS: *v = ((int64_t)c->fem_block << 32) | ((int64_t)c->asm_block << 16) | c->grad_block; return IPC_OK;
+    case IPC_Q_PCG_FUSED: *v = c->cg_fusable && c->coarse_on && c->pcg_fused && c->n_cdom > 0 ? 1 : 0; return IPC_OK;
     }
     return IPC_E_INVALID;
 }
@@ -799,7 +802,8 @@ __global__ void k_int2ext(int64_t NE, const int *__restrict__ ext2node, int *__r
 }
 // Export of the assembled matrix in the external numbering: row i of the
 // result is internal row ext2node[i], the union of its block-CSR columns and
-// its pair-local columns (both ascending), equal columns summed.
+// its pair-local columns (both ascending internally), equal columns summed,
+// then ordered by external column.
 template <bool WRITE>
 __global__ void k_bsr_export(int64_t NE, const int *__restrict__ ext2node, const int *__restrict__ int2ext,
                              const int *__restrict__ rp, const int *__restrict__ col, const double *__restrict__ val,
@@ -827,7 +831,27 @@ __global__ void k_bsr_export(int64_t NE, const int *__restrict__ ext2node, const
         if (cb == cc) ++b;
         ++n;
     }
-    if (!WRITE) cnt[i] = n;
+    if (!WRITE) {
+        cnt[i] = n;
+        return;
+    }
+    // the internal node order is not the external one: sort the row's blocks
+    // by external column (insertion sort; rows hold a few dozen blocks)
+    for (int u = 1; u < n; ++u) {
+        const int key = ocol[o + u];
+        double blk[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) blk[q] = oval[9 * (size_t)(o + u) + q];
+        int v = u - 1;
+        for (; v >= 0 && ocol[o + v] > key; --v) {
+            ocol[o + v + 1] = ocol[o + v];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) oval[9 * (size_t)(o + v + 1) + q] = oval[9 * (size_t)(o + v) + q];
+        }
+        ocol[o + v + 1] = key;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) oval[9 * (size_t)(o + v + 1) + q] = blk[q];
+    }
 }
 } // namespace ipc
 

@@ -9,7 +9,9 @@
 // the aggregation of nodes into groups of CG_AGG that share one translation:
 // FEM vertices and the translation node of every affine body, taken in the
 // Morton order of their positions at creation, so that a group is a compact
-// patch of one object.  C is block diagonal over domains of CG_DOM
+// patch of one object.  That order is also the order of a scene's first
+// nodes (a body's translation is represented there by an unused slot), so a
+// domain is one contiguous range of nodes.  C is block diagonal over domains of CG_DOM
 // consecutive groups: each block is the domain's part of P^T A P (the sum of
 // the 3x3 blocks of A between the nodes of two groups), a dense SPD matrix
 // of at most 96 x 96 that is inverted after every assembly.  Nothing crosses
@@ -27,67 +29,42 @@
 #include "ipc_device.h"
 #include "ipc_internal.h"
 #include "ipc_kernels.h"
+#include "ipc_pcgdev.h"
 
 namespace ipc {
 
-namespace {
-
-unsigned int spread10(unsigned int v)
-{
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000ffu;
-    v = (v | (v << 8)) & 0x0300f00fu;
-    v = (v | (v << 4)) & 0x030c30c3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
-} // namespace
-
-void coarse_setup(ipc_ctx *c, const std::vector<double> &X)
+void coarse_setup(ipc_ctx *c)
 {
     const int ns = c->n_scenes;
     c->seg_cdom.assign(ns + 1, 0);
     std::vector<int> ent, nodes, dom_scene, grp, node_da(c->N, -1);
     int ndom = 0;
+    bool windows = ns == 1;
     for (int s = 0; s < ns; ++s) {
         c->seg_cdom[s] = ndom;
         if (!c->coarse) continue;
         const SceneInfo &S = c->sc[s];
-        std::vector<int> part;
-        for (int i = 0; i < S.nv; ++i) part.push_back(S.node0 + i);
-        for (int b = 0; b < S.nb; ++b) part.push_back(S.bnode0 + 4 * b);   // translation node
-        if (part.empty()) continue;
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int n : part)
-            for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], X[3 * (size_t)n + k]); hi[k] = std::max(hi[k], X[3 * (size_t)n + k]); }
-        double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
-        double sc = ext > 0.0 ? 1023.0 / ext : 0.0;
-        std::vector<unsigned int> key(part.size());
-        for (size_t m = 0; m < part.size(); ++m) {
-            unsigned int q[3];
-            for (int k = 0; k < 3; ++k)
-                q[k] = (unsigned int)std::min(1023.0, std::max(0.0, (X[3 * (size_t)part[m] + k] - lo[k]) * sc));
-            key[m] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-        }
-        std::vector<size_t> ord(part.size());
-        std::iota(ord.begin(), ord.end(), (size_t)0);
-        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
-        // groups of CG_AGG consecutive nodes, domains of CG_DOM consecutive
-        // groups; a scene's last group and domain may be short
+        // groups of CG_AGG consecutive entries of the scene's Morton order,
+        // domains of CG_DOM consecutive groups; a scene's last group and
+        // domain may be short
         const int per_dom = CG_AGG * CG_DOM;
-        for (size_t m = 0; m < ord.size(); ++m) {
+        for (int m = 0; m < (int)S.entry.size(); ++m) {
             if (m % per_dom == 0) {
                 ent.push_back((int)nodes.size());
                 dom_scene.push_back(s);
                 ++ndom;
             }
-            const int g = (ndom - 1) * CG_DOM + (int)(m % per_dom) / CG_AGG;
+            const int g = (ndom - 1) * CG_DOM + (m % per_dom) / CG_AGG;
             if (m % CG_AGG == 0) grp.push_back(g);
-            node_da[part[ord[m]]] = g;
-            nodes.push_back(part[ord[m]]);
+            const int node = S.entry[m] >= 0 ? S.node0 + m : S.bnode0 + 4 * (-1 - S.entry[m]);
+            node_da[node] = g;
+            nodes.push_back(node);
         }
+        // one scene at node 0: entry e of domain d is node CG_AGG CG_DOM d + e
+        // or stands in that slot for a body's translation node
+        windows = windows && S.node0 == 0;
     }
+    c->cg_fusable = windows && ndom > 0;
     c->seg_cdom[ns] = ndom;
     ent.push_back((int)nodes.size());   // ndom + 1 offsets
     c->n_cdom = ndom;
@@ -299,15 +276,6 @@ __global__ void __launch_bounds__(CG_INV) k_coarse_invert(const int *__restrict_
 // 32 consecutive entries, i.e. half a wavefront of one pass over the entries.
 // The slices of a domain are numbered so that they share an XCD (workgroups
 // go round-robin over the 8 XCDs): the residual's repeated reads hit its L2.
-constexpr int CG_APPLY = 256;
-constexpr int CG_PASSES = CG_AGG * CG_DOM / CG_APPLY;
-constexpr int CG_ROWS = CG_N / CG_SPLIT;              // inverse rows per slice
-constexpr int CG_SNODES = CG_AGG * CG_DOM / CG_SPLIT; // entries per slice
-constexpr int CG_CLANES = 192 / CG_ROWS;              // lanes per row in the product
-constexpr int CG_CPL = CG_N / CG_CLANES;              // columns per lane
-constexpr int NXCD = 8;
-static_assert(CG_N % CG_SPLIT == 0 && CG_ROWS * CG_CLANES == 192 && CG_N % CG_CLANES == 0, "whole rows and columns per lane");
-static_assert(TILE % CG_CLANES == 0 && CG_SNODES <= CG_APPLY && CG_APPLY % CG_SNODES == 0, "lane groups inside a wavefront");
 __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, int single, const int *__restrict__ pnodes,
                                                            const int *__restrict__ dom_scene, const int *__restrict__ act,
                                                            const double *__restrict__ inv, const double *__restrict__ r,
@@ -350,23 +318,13 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, int single,
     // rc entry is written exactly once (0 for groups past the domain's end)
 #pragma unroll
     for (int j = 0; j < CG_PASSES; ++j) {
-        double x = rv[j].x, y = rv[j].y, zz = rv[j].z;
-#pragma unroll
-        for (int o = CG_AGG / 2; o > 0; o >>= 1) {
-            x += __shfl_xor(x, o, TILE);
-            y += __shfl_xor(y, o, TILE);
-            zz += __shfl_xor(zz, o, TILE);
-        }
+        const d3 v = cg_group_sum(rv[j]);
         const int g = (t + j * CG_APPLY) / CG_AGG;
-        if ((lane & (CG_AGG - 1)) == 0) { rc[3 * g] = x; rc[3 * g + 1] = y; rc[3 * g + 2] = zz; }
+        if ((lane & (CG_AGG - 1)) == 0) { rc[3 * g] = v.x; rc[3 * g + 1] = v.y; rc[3 * g + 2] = v.z; }
     }
     __syncthreads();
     if (t < 192) {
-        double a = 0.0;
-#pragma unroll
-        for (int j = 0; j < CG_CPL; ++j) a += m[j] * rc[cl + CG_CLANES * j];
-#pragma unroll
-        for (int o = CG_CLANES / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, TILE);
+        const double a = cg_row(m, rc, cl);
         if (cl == 0) zl[i] = a;   // rows past a short domain's end: rc and the inverse are 0 there
     }
     __syncthreads();

@@ -272,6 +272,44 @@ HostTopo topology(const ipc_scene_desc &s)
     return t;
 }
 
+unsigned int spread10(unsigned int v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// The order of a scene's first nv + nb nodes: its FEM vertices and its
+// bodies' translation nodes together, by the Morton code of their positions
+// at creation (10 bits per axis over their bounding box; equal codes keep
+// FEM vertices before bodies, each in input order).  Entry m >= 0 is FEM
+// vertex m's slot; -1 - b marks body b, whose slot is left as padding (the
+// body's 4 nodes follow the region).  The coarse preconditioner's groups are
+// runs of this order, so each of its domains is one contiguous node range.
+std::vector<int> morton_entries(const ipc_scene_desc &d)
+{
+    std::vector<int> part(d.nv + d.nb);
+    std::iota(part.begin(), part.end(), 0);
+    auto pos = [&](int m, int k) { return m < d.nv ? d.X[3 * (size_t)m + k] : d.body_q[12 * (size_t)(m - d.nv) + k]; };
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int m : part)
+        for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], pos(m, k)); hi[k] = std::max(hi[k], pos(m, k)); }
+    const double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    const double sc = ext > 0.0 ? 1023.0 / ext : 0.0;
+    std::vector<unsigned int> key(part.size());
+    for (int m : part) {
+        unsigned int q[3];
+        for (int k = 0; k < 3; ++k) q[k] = (unsigned int)std::min(1023.0, std::max(0.0, (pos(m, k) - lo[k]) * sc));
+        key[m] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    }
+    std::stable_sort(part.begin(), part.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (int &m : part) m = m < d.nv ? m : -1 - (m - d.nv);
+    return part;
+}
+
 } // namespace
 
 void validate_scenes(const ipc_scene_desc *scenes, int n)
@@ -316,7 +354,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         S.hs_on = d.half_space[0] != 0.0 || d.half_space[1] != 0.0 || d.half_space[2] != 0.0;
         topo[s] = topology(d);
         S.node0 = node; S.nnode = d.nv + 4 * d.nb;
-        S.bnode0 = node + (d.nv + 3) / 4 * 4;
+        S.entry = morton_entries(d);
+        S.bnode0 = node + (d.nv + d.nb + 3) / 4 * 4;
         S.nnode_pad = pad64(S.bnode0 - node + 4 * d.nb);
         S.tet0 = tet; S.nt_pad = pad64(d.nt);
         S.body0 = body; S.drv0 = drv; S.sp0 = sp; S.jt0 = jt;
@@ -366,9 +405,13 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         for (int i = 0; i < S.nnode_pad; ++i) node_scene[S.node0 + i] = s;
         for (int i = 0; i < S.nnode_pad / TILE; ++i) tile_node[S.node0 / TILE + i] = s;
         for (int i = 0; i < S.nt_pad / TILE; ++i) tile_tet[S.tet0 / TILE + i] = s;
+        // FEM vertex i sits at node fem[i] (its slot in the scene's Morton order)
+        std::vector<int> fem(d.nv);
+        for (int m = 0; m < (int)S.entry.size(); ++m)
+            if (S.entry[m] >= 0) fem[S.entry[m]] = S.node0 + m;
         for (int i = 0; i < d.nv; ++i) {
-            node_kind[S.node0 + i] = 0;
-            for (int k = 0; k < 3; ++k) { X[3 * (size_t)(S.node0 + i) + k] = d.X[3 * i + k]; V[3 * (size_t)(S.node0 + i) + k] = d.V[3 * i + k]; }
+            node_kind[fem[i]] = 0;
+            for (int k = 0; k < 3; ++k) { X[3 * (size_t)fem[i] + k] = d.X[3 * i + k]; V[3 * (size_t)fem[i] + k] = d.V[3 * i + k]; }
         }
         for (int b = 0; b < d.nb; ++b)
             for (int cc = 0; cc < 4; ++cc) {
@@ -376,11 +419,11 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
                 node_kind[nd] = 1;
                 for (int k = 0; k < 3; ++k) { X[3 * (size_t)nd + k] = d.body_q[12 * b + 3 * cc + k]; V[3 * (size_t)nd + k] = d.body_qdot[12 * b + 3 * cc + k]; }
             }
-        for (int i = 0; i < S.nnode; ++i) ext2node[S.dof0 / 3 + i] = i < d.nv ? S.node0 + i : S.bnode0 + (i - d.nv);
+        for (int i = 0; i < S.nnode; ++i) ext2node[S.dof0 / 3 + i] = i < d.nv ? fem[i] : S.bnode0 + (i - d.nv);
         for (int e = 0; e < S.nt_pad; ++e) {
             int g = S.tet0 + e;
             if (e < d.nt) {
-                tv[g] = make_int4(S.node0 + d.tets[4 * e], S.node0 + d.tets[4 * e + 1], S.node0 + d.tets[4 * e + 2], S.node0 + d.tets[4 * e + 3]);
+                tv[g] = make_int4(fem[d.tets[4 * e]], fem[d.tets[4 * e + 1]], fem[d.tets[4 * e + 2]], fem[d.tets[4 * e + 3]]);
                 tvalid[g] = 1; tE[g] = d.tet_E[e]; tnu[g] = d.tet_nu[e]; trho[g] = d.tet_rho[e];
                 ext2tet.push_back(g);
             } else {
@@ -398,7 +441,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         }
         for (int k = 0; k < d.ns; ++k) {
             int g = S.sp0 + k;
-            auto conv = [&](int kind, int idx) { return kind == 0 ? S.node0 + idx : (kind == 1 ? S.body0 + idx : S.drv0 + idx); };
+            auto conv = [&](int kind, int idx) { return kind == 0 ? fem[idx] : (kind == 1 ? S.body0 + idx : S.drv0 + idx); };
             ska[g] = d.sp_ka[k]; sia[g] = conv(d.sp_ka[k], d.sp_ia[k]);
             skb[g] = d.sp_kb[k]; sib[g] = conv(d.sp_kb[k], d.sp_ib[k]);
             for (int m = 0; m < 3; ++m) { sxa[3 * (size_t)g + m] = d.sp_xa[3 * k + m]; sxb[3 * (size_t)g + m] = d.sp_xb[3 * k + m]; }
@@ -418,7 +461,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
             int e = tp.surf[i], g = S.cv0 + i;
             ext2cv[e] = g;
             cv_scene[g] = s;
-            if (e < d.nv) { cv_node[g] = S.node0 + e; cv_obj[g] = S.obj0 + d.vobj[e]; }
+            if (e < d.nv) { cv_node[g] = fem[e]; cv_obj[g] = S.obj0 + d.vobj[e]; }
             else if (e < d.nv + d.nbv) {
                 int j = e - d.nv;
                 cv_body[g] = S.body0 + d.bv_body[j];
@@ -605,8 +648,9 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         const int64_t ndom = N / (CG_AGG * CG_DOM) + 2 * (int64_t)n, ngrp = N / CG_AGG + 2 * (int64_t)n;
         const int64_t MH = std::max<int64_t>(c->M_HS, 1);
         const std::vector<int64_t> nbuf = {
-            // nodes: state, predictor and solver vectors (14 x 3 doubles), kinds, maps, mass, inverse blocks
-            14 * 24 * N, 4 * N, 4 * N, 4 * (int64_t)(dof / 3) + 4, 8 * N, 72 * N, 8 * (N / TILE + 1), 4 * N, 4 * N,
+            // nodes: state, predictor and solver vectors (14 x 3 doubles, 3 more for one scene), kinds, maps, mass,
+            // inverse blocks
+            (n == 1 ? 17 : 14) * 24 * N, 4 * N, 4 * N, 4 * (int64_t)(dof / 3) + 4, 8 * N, 72 * N, 8 * (N / TILE + 1), 4 * N, 4 * N,
             // tetrahedra: vertices, inverse rest shape, volume and Lame, modulus and ratio, gradients and blocks,
             // slot and adjacency lists, the temporary density and validity
             16 * T, 72 * T, 8 * T, 8 * T, 8 * T, 8 * T, 8 * T, 4 * T + 4, 96 * std::max<int64_t>(T, 1), 720 * std::max<int64_t>(T, 1),
@@ -658,9 +702,11 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
     Dev &D = c->d;
     D.y.upload(X, st); D.ydot.upload(V, st);
     for (auto *b : {&D.xt, &D.y0, &D.yt, &D.g, &D.p, &D.r, &D.z, &D.q, &D.w, &D.x, &D.v1, &D.v2}) b->alloc(3 * (size_t)node);
+    if (n == 1)   // the one-launch PCG step's second r, z and s (a padding node's entries stay 0)
+        for (auto *b : {&D.r2, &D.z2, &D.q2}) { b->alloc(3 * (size_t)node); b->zero(st, 3 * (size_t)node); }
     IPC_HIP(hipMemcpyAsync(D.xt.p, D.y.p, 3 * (size_t)node * sizeof(double), hipMemcpyDeviceToDevice, st));
     D.node_scene.upload(node_scene, st); D.node_kind.upload(node_kind, st); D.ext2node.upload(ext2node, st);
-    coarse_setup(c, X);   // groups and domains of the coarse preconditioner from the initial positions
+    coarse_setup(c);   // groups and domains of the coarse preconditioner: runs of the Morton order
     D.mass.alloc(node); D.dinv.alloc(9 * (size_t)node);
     D.tv.upload(tv, st);
     D.Bm.alloc(9 * (size_t)tet); D.vol.alloc(tet); D.tmu.alloc(tet); D.tlam.alloc(tet);
@@ -720,7 +766,8 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
         DBuf<double> msum; msum.alloc(n);
         for (int s = 0; s < n; ++s)
             if (scenes[s].nv > 0)
-                hipLaunchKernelGGL(k_sum_mass, dim3(1), dim3(256), 0, st, scenes[s].nv, D.mass.p, c->sc[s].node0, msum.p + s);
+                hipLaunchKernelGGL(k_sum_mass, dim3(1), dim3(256), 0, st, (int)c->sc[s].entry.size(), D.mass.p, c->sc[s].node0,
+                                   msum.p + s);   // the FEM region: the bodies' slots in it hold no mass
         std::vector<double> hm(n, 0.0);
         IPC_HIP(hipMemcpyAsync(hm.data(), msum.p, n * sizeof(double), hipMemcpyDeviceToHost, st));
         IPC_HIP(hipStreamSynchronize(st));

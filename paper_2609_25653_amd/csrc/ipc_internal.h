@@ -205,9 +205,11 @@ struct SceneInfo {
     // sizes
     int nv, nt, nb, nbv, nbt, nsv, nst, nobj, nex, ns, nd, nj;
     // offsets into the concatenated device arrays
-    int node0, nnode, nnode_pad;     // nodes: FEM vertices then 4 per body (nnode: without padding)
-    int bnode0;                      // first body node: node0 + nv rounded up to 4, so that a body's
-                                     // 4 nodes are 4 lanes of one wavefront
+    int node0, nnode, nnode_pad;     // nodes: FEM region then 4 per body (nnode: without padding)
+    int bnode0;                      // first body node: node0 + nv + nb rounded up to 4, so that a
+                                     // body's 4 nodes are 4 lanes of one wavefront
+    std::vector<int> entry;          // the FEM region's nv + nb slots in Morton order: FEM vertex
+                                     // entry[m] at node0 + m, or -1 - b for body b's translation
     int tet0, nt_pad;
     int body0, drv0, sp0, jt0;       // bodies, driven slots, springs, joint springs
     int cv0, ncv, nsurf;             // contact vertices; the first nsurf are PT query points
@@ -227,6 +229,7 @@ struct SceneInfo {
 struct Dev {
     // nodes
     DBuf<double> y, ydot, xt, y0, yt, g, p, r, z, q, w, x, v1, v2;
+    DBuf<double> r2, z2, q2;               // the PCG's r, z and s of odd iterations (one-launch step)
     DBuf<int> node_scene, node_kind;       // kind: 0 FEM, 1 body node, 2 padding
     DBuf<int> slot_scene;                  // scene of each block-CSR block (its row's)
     DBuf<double> mass;                     // lumped FEM vertex mass (0 elsewhere)
@@ -380,6 +383,9 @@ struct ipc_ctx {
     bool coarse = true;                   // coarse domains built (the PCG preconditioner's correction)
     bool coarse_on = false;               // the PCG applies the coarse correction
     bool coarse_forced = false;           // on by request, whatever the size
+    bool cg_fusable = false;              // one scene whose domains match the step's workgroups (see coarse_setup)
+    bool pcg_fused = true;                // IPC_NO_FUSED_PCG unset: a fusable context applies its coarse
+                                          // correction inside the PCG step
     int lag_passes = 1;                   // friction lag passes per step
     double kappa_frac = 0.0;              // adaptive kappa: distance threshold / dhat (0: off)
     double kappa_factor = 100.0;          // adaptive kappa: cap / kappa0
@@ -466,7 +472,7 @@ void build_preconditioner(ipc_ctx *c);
 // positions at creation; the domains' inverses after an assembly; z += its
 // correction of r for the scenes whose act entry is set, r . z partials into
 // the given parity
-void coarse_setup(ipc_ctx *c, const std::vector<double> &X);
+void coarse_setup(ipc_ctx *c);
 void coarse_build(ipc_ctx *c);
 void coarse_apply(ipc_ctx *c, const int *act, const double *r, double *z, int parity);
 

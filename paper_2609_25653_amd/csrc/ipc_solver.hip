@@ -12,6 +12,7 @@
 #include "ipc_device.h"
 #include "ipc_internal.h"
 #include "ipc_kernels.h"
+#include "ipc_pcgdev.h"
 
 namespace ipc {
 
@@ -637,6 +638,23 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_init(int N, int ns, const int *__
 // One iteration, parity q.  State per scene and parity: st[4] = {gamma,
 // alpha, eta^2 b.b, r.r}, act (0 stopped, 1 running, 2 first iteration), it
 // (updates done).  part holds [r.z | r.r] for parity 0 then parity 1.
+//
+// FUSED (one scene whose coarse domains are contiguous node ranges, see
+// coarse_setup): the workgroup of slice sl of domain d takes that slice's
+// 256 nodes and also applies the slice's part of the coarse correction, so
+// that no second launch is needed.  Workgroups number (domain, slice) so
+// that a domain's slices share an XCD.  Restricting the new residual over
+// the whole domain needs r of the other slices' nodes, which their own
+// workgroups are updating: r and s are read from the parity-q buffers
+// (r_in, s_in), the update is recomputed for the foreign entries with the
+// same arithmetic, and r, s and z are written to the other parity's buffers.
+// An entry whose slot holds a body's translation node gets its
+// block-Jacobi value recomputed here too (the same rows of the body's
+// inverse as its own workgroup, which does not store that node's z).  The
+// bits come out as those of the step followed by k_coarse_apply.  Without
+// FUSED the in and out buffers are the same and the correction follows in
+// its own launch.
+template <bool FUSED>
 __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const int *__restrict__ kind, const int *__restrict__ node_body,
                                                     const int *__restrict__ tile_scene, const int *__restrict__ seg_nodew,
                                                     const int *__restrict__ seg_long, const int *__restrict__ seg_cdom,
@@ -644,15 +662,25 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
                                                     const double *__restrict__ cg_part, int ncdom,
                                                     const int *__restrict__ maxit, const double *__restrict__ dinv,
                                                     const double *__restrict__ dinvB, const double *__restrict__ w, double *__restrict__ p,
-                                                    double *__restrict__ s, double *__restrict__ x, double *__restrict__ r,
-                                                    double *__restrict__ z, const double *__restrict__ part_zw,
+                                                    const double *s_in, double *s, double *__restrict__ x, const double *r_in,
+                                                    double *r, const double *z_in, double *z, const double *__restrict__ part_zw,
                                                     const double *__restrict__ part_long, double *__restrict__ part, int ntile,
                                                     double *__restrict__ st, int *__restrict__ act, int *__restrict__ it,
-                                                    double *__restrict__ scal)
+                                                    double *__restrict__ scal, int ndom, int nwin, const int *__restrict__ pnodes,
+                                                    const int *__restrict__ node_da, const double *__restrict__ inv, double *cg_out)
 {
     __shared__ double sh[3][WG_TILES];
-    const int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1);
-    const int t0 = blockIdx.x * WG_TILES, t = t0 + wave;
+    const int wave = threadIdx.x / TILE, lane = threadIdx.x & (TILE - 1), tid = threadIdx.x;
+    int L = blockIdx.x, d = 0, sl = 0;   // L: the workgroup's place in node order
+    if (FUSED) {
+        const int k = blockIdx.x / NXCD;
+        sl = k % CG_SPLIT;
+        d = blockIdx.x % NXCD + NXCD * (k / CG_SPLIT);
+        if (d >= nwin) return;   // the grid is rounded up to whole XCD rounds
+        L = CG_SPLIT * d + sl;
+    }
+    const bool cg = FUSED && d < ndom;   // uniform: this workgroup applies a slice of domain d
+    const int t0 = L * WG_TILES, t = t0 + wave;
     const int n = t * TILE + lane;
     // this node's operands first, without waiting for its kind: their loads
     // overlap the reductions below
@@ -661,17 +689,52 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     double Mi[9];
     if (n < N) {
         k = kind[n];
-        zv = ld3(z, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s, n); xv = ld3(x, n); rv = ld3(r, n);
+        zv = ld3(z_in, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s_in, n); xv = ld3(x, n); rv = ld3(r_in, n);
 #pragma unroll
         for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)n + q];
     }
+    // FUSED: the slice's inverse rows, the domain's entries and the foreign
+    // entries' operands, also before the reductions
+    const int i = tid / CG_CLANES, cl = tid % CG_CLANES;
+    double m[CG_CPL];
+    int nd[CG_PASSES];
+    d3 fr[CG_PASSES], fs[CG_PASSES], fw[CG_PASSES];
+    // an entry of this slice that stands for a body's translation node: the
+    // body's 4 nodes' operands and its block's first 3 rows
+    d3 br[4], bs[4], bw[4];
+    const double *bM = nullptr;
+    bool grouped_body = false;
+    if (cg) {
+        if (tid < 192) {
+            const double *M = inv + (size_t)d * CG_N * CG_N + (size_t)(CG_ROWS * sl + i) * CG_N + cl;
+#pragma unroll
+            for (int j = 0; j < CG_CPL; ++j) m[j] = M[CG_CLANES * j];
+        }
+#pragma unroll
+        for (int j = 0; j < CG_PASSES; ++j) nd[j] = pnodes[(size_t)d * (CG_AGG * CG_DOM) + tid + j * CG_APPLY];
+#pragma unroll
+        for (int j = 0; j < CG_PASSES; ++j) {
+            fr[j] = fs[j] = fw[j] = d3{0.0, 0.0, 0.0};
+            if (nd[j] >= 0 && nd[j] != n) { fr[j] = ld3(r_in, nd[j]); fs[j] = ld3(s_in, nd[j]); fw[j] = ld3(w, nd[j]); }
+        }
+        int me = -1;
+#pragma unroll
+        for (int j = 0; j < CG_PASSES; ++j)
+            if (j == sl) me = nd[j];
+        if (me >= 0 && me != n) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { br[c] = ld3(r_in, me + c); bs[c] = ld3(s_in, me + c); bw[c] = ld3(w, me + c); }
+            bM = dinvB + 144 * (size_t)node_body[me];
+        }
+    }
+    if (FUSED && k == 1) grouped_body = node_da[n] >= 0;   // its z comes from its entry's workgroup
     const double *rz_in = part + (size_t)(2 * q) * ntile, *rr_in = rz_in + ntile;
     double *rz_out = part + (size_t)(2 * (q ^ 1)) * ntile, *rr_out = rz_out + ntile;
     // the workgroup's scenes and the first one's tile and long-row ranges in
     // one record, so the partials' loads wait for a single load
     // (a single scene needs no record: its ranges are all tiles, every
     // long-row partial, unused ones being 0, and every coarse domain)
-    const int *wi = wginfo + WGI * (size_t)blockIdx.x;
+    const int *wi = wginfo + WGI * (size_t)L;
     const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction (CG_SPLIT per domain)
     const int sc_lo = single ? 0 : wi[0], sc_hi = single ? 0 : wi[1];
     const int my_sc = t < ntile ? (single ? 0 : tile_scene[t]) : -1;
@@ -684,7 +747,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         const int clo = single ? 0 : first ? wi[6] : seg_cdom[sc], chi = single ? ncdom / CG_SPLIT : first ? wi[7] : seg_cdom[sc + 1];
         const int a = act[q * ns + sc], itc = it[q * ns + sc];
         const double *S = st + ((size_t)q * ns + sc) * 4;
-        const bool writer = tlo / WG_TILES == (int)blockIdx.x && threadIdx.x == 0;
+        const bool writer = tlo / WG_TILES == L && threadIdx.x == 0;
         double *So = st + ((size_t)(q ^ 1) * ns + sc) * 4;
         if (!a) {
             if (writer) {
@@ -721,16 +784,19 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
             it[(q ^ 1) * ns + sc] = itc + na;
             if (indef) scal[(size_t)sc * NSLOT + S_INDEF] = 1.0;
         }
-        if (sc == my_sc) { on = na; al = as; be = bs; }
+        if (sc == my_sc || (FUSED && sc == 0)) { on = na; al = as; be = bs; }
     }
     double rz = 0.0, rr = 0.0;
+    // z of this node from its block-Jacobi part; the coarse correction is
+    // added before it is stored when the node is an entry of this slice
+    bool store_z = false;
     if (on && k == 0) {
         pv = {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z};
-        sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
         xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
-        rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
+        pcg_sr(wv, al, be, sv, rv);
         zv = mat3v(Mi, rv);
-        st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv); st3(z, n, zv);
+        st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv);
+        store_z = true;
         rr = dt(rv, rv);
         rz = dt(rv, zv);
     } else if (on && k == 1) {
@@ -739,9 +805,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         // node, gathers the body's 12 residual entries from the 4 lanes and
         // forms 3 rows of the body's 12x12 inverse block times them.
         pv = {zv.x + be * pv.x, zv.y + be * pv.y, zv.z + be * pv.z};
-        sv = {wv.x + be * sv.x, wv.y + be * sv.y, wv.z + be * sv.z};
         xv = {xv.x + al * pv.x, xv.y + al * pv.y, xv.z + al * pv.z};
-        rv = {rv.x - al * sv.x, rv.y - al * sv.y, rv.z - al * sv.z};
+        pcg_sr(wv, al, be, sv, rv);
         st3(p, n, pv); st3(s, n, sv); st3(x, n, xv); st3(r, n, rv);
         const int a = n & 3, first = lane - a;
         double rb[12];
@@ -751,20 +816,63 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
             rb[3 * q + 1] = __shfl(rv.y, first + q);
             rb[3 * q + 2] = __shfl(rv.z, first + q);
         }
-        const double *M = dinvB + 144 * (size_t)node_body[n - a] + 36 * a;
-        double zz[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < 12; ++j) acc += M[12 * c + j] * rb[j];
-            zz[c] = acc;
-        }
-        zv = {zz[0], zz[1], zz[2]};
-        st3(z, n, zv);
+        zv = body_rows(dinvB + 144 * (size_t)node_body[n - a] + 36 * a, rb);
+        store_z = !grouped_body;
         rr = dt(rv, rv);
         rz = dt(rv, zv);
     }
+    if (cg && on) {   // uniform: FUSED has one scene
+        __shared__ double rc[CG_N], zl[CG_ROWS];
+        // the new residual on every entry of the domain: this node's own,
+        // or recomputed from the parity-q operands
+        d3 rn[CG_PASSES];
+#pragma unroll
+        for (int j = 0; j < CG_PASSES; ++j) {
+            rn[j] = d3{0.0, 0.0, 0.0};
+            if (nd[j] == n) rn[j] = rv;
+            else if (nd[j] >= 0) {
+                d3 sj = fs[j], rj = fr[j];
+                pcg_sr(fw[j], al, be, sj, rj);
+                rn[j] = rj;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CG_PASSES; ++j) {
+            const d3 v = cg_group_sum(rn[j]);
+            const int g = (tid + j * CG_APPLY) / CG_AGG;
+            if ((lane & (CG_AGG - 1)) == 0) { rc[3 * g] = v.x; rc[3 * g + 1] = v.y; rc[3 * g + 2] = v.z; }
+        }
+        __syncthreads();
+        if (tid < 192) {
+            const double a = cg_row(m, rc, cl);
+            if (cl == 0) zl[i] = a;   // rows past a short domain's end: rc and the inverse are 0 there
+        }
+        __syncthreads();
+        int me = -1;
+#pragma unroll
+        for (int j = 0; j < CG_PASSES; ++j)
+            if (j == sl) me = nd[j];
+        const int g = tid / CG_AGG;
+        if (me == n) {
+            zv = {zv.x + zl[3 * g], zv.y + zl[3 * g + 1], zv.z + zl[3 * g + 2]};
+        } else if (me >= 0) {
+            double rb[12];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                d3 sc = bs[c], rc4 = br[c];
+                pcg_sr(bw[c], al, be, sc, rc4);
+                rb[3 * c] = rc4.x; rb[3 * c + 1] = rc4.y; rb[3 * c + 2] = rc4.z;
+            }
+            const d3 zb = body_rows(bM, rb);
+            st3(z, me, {zb.x + zl[3 * g], zb.y + zl[3 * g + 1], zb.z + zl[3 * g + 2]});
+        }
+        if (tid < TILE) {
+            double dot = tid < CG_ROWS ? rc[CG_ROWS * sl + tid] * zl[tid] : 0.0;
+            dot = wave_sum(dot);
+            if (tid == 0) cg_out[(size_t)CG_SPLIT * d + sl] = dot;
+        }
+    }
+    if (store_z) st3(z, n, zv);
     rz = wave_sum(rz); rr = wave_sum(rr);
     if (lane == 0 && t < ntile) { rz_out[t] = rz; rr_out[t] = rr; }
 }
@@ -818,6 +926,11 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
     hipStream_t st = c->stream;
     const int ns = c->n_scenes, ntile = c->N / TILE;
     double *r = D.r.p, *z = D.z.p, *p = D.p.p, *s = D.q.p, *w = D.w.p;
+    // the one-launch step keeps r, z and s of odd iterations in buffers of
+    // their own; otherwise the step updates them in place
+    const bool fused = c->cg_fusable && c->coarse_on && c->pcg_fused && c->n_cdom > 0;
+    double *rb[2] = {r, fused ? D.r2.p : r}, *zb[2] = {z, fused ? D.z2.p : z}, *sb[2] = {s, fused ? D.q2.p : s};
+    const int nwin = fused ? std::max(c->n_cdom, (ntile + CG_SPLIT * WG_TILES - 1) / (CG_SPLIT * WG_TILES)) : 0;
     D.part_node3.alloc(ntile + 1);
     D.part_long.alloc(c->long_cap + 1);
     D.pcg_part.alloc(4 * (size_t)ntile + 1);
@@ -837,13 +950,24 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
     // extra iterations after convergence change nothing
     auto iteration = [&](int q) {
         prof_begin(c, IPC_K_PCG_UPDATE);
-        hipLaunchKernelGGL(k_pcg_step, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p, D.node_body.p,
-                           D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM), D.pcg_wginfo.p,
-                           (int)(ns == 1), c->long_cap, D.cg_part.p, c->coarse_on ? CG_SPLIT * c->n_cdom : 0, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p, s, x,
-                           r, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p);
+        const int ncd = c->coarse_on ? CG_SPLIT * c->n_cdom : 0;
+        double *cg_out = D.cg_part.p + (size_t)(q ^ 1) * ncd;
+        if (fused)
+            hipLaunchKernelGGL(k_pcg_step<true>, dim3(NXCD * CG_SPLIT * ((nwin + NXCD - 1) / NXCD)), dim3(BLOCK), 0, c->stream, c->N, ns,
+                               q, D.node_kind.p, D.node_body.p, D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG),
+                               seg_ptr(c, R_CDOM), D.pcg_wginfo.p, 1, c->long_cap, D.cg_part.p, ncd, D.maxpcg.p, D.dinv.p, D.dinvB.p,
+                               w, p, sb[q], sb[q ^ 1], x, rb[q], rb[q ^ 1], zb[q], zb[q ^ 1], D.part_node3.p, D.part_long.p,
+                               D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p, c->n_cdom, nwin, D.cg_pnodes.p,
+                               D.cg_node_da.p, D.cg_inv.p, cg_out);
+        else
+            hipLaunchKernelGGL(k_pcg_step<false>, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p,
+                               D.node_body.p, D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM),
+                               D.pcg_wginfo.p, (int)(ns == 1), c->long_cap, D.cg_part.p, ncd, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p,
+                               s, s, x, r, r, z, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p,
+                               D.scal.p, 0, 0, nullptr, nullptr, nullptr, nullptr);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
-        coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
-        hess_apply(c, z, w, act + (q ^ 1) * ns, D.part_node3.p);
+        if (!fused) coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
+        hess_apply(c, zb[q ^ 1], w, act + (q ^ 1) * ns, D.part_node3.p);
     };
     // The peek kernel publishes one word per scene into pinned, coherent host
     // memory, which the host polls: no event and no stream synchronisation
@@ -903,7 +1027,8 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                                       (uintptr_t)D.row_ptr.p, (uintptr_t)D.col.p, (uintptr_t)D.val.p, (uintptr_t)D.dyn_ptr.p,
                                       (uintptr_t)D.dyn_col.p, (uintptr_t)D.dyn_val.p, (uintptr_t)D.node_scene.p,
                                       (uintptr_t)D.pcg_wginfo.p, (uintptr_t)(c->coarse_on ? c->n_cdom : 0), (uintptr_t)D.cg_ent.p, (uintptr_t)D.cg_nodes.p,
-                                      (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p, (uintptr_t)D.cg_pnodes.p};
+                                      (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p, (uintptr_t)D.cg_pnodes.p,
+                                      (uintptr_t)fused, (uintptr_t)D.r2.p, (uintptr_t)D.z2.p, (uintptr_t)D.q2.p, (uintptr_t)D.cg_node_da.p};
         bool have = key == c->pcg_key;
         for (auto xg : c->pcg_exec) have = have && xg;
         if (!have) {

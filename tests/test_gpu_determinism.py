@@ -96,3 +96,36 @@ def test_adjoint_bitwise(monkeypatch):
         outs.append((yb, vb, Eb, mb))
     for x, y in zip(*outs):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("name,n", [("pad_box", 24), ("arm_box", 12), ("block", 6), ("squeeze", 3)])
+def test_one_launch_pcg_step_matches_two_launches(name, n, monkeypatch):
+    """With the coarse correction on, a one-scene context applies it inside
+    the PCG's update launch (each domain a contiguous node range: the
+    update's workgroups recompute the new residual of the domain's other
+    nodes, and of the bodies whose translation is grouped).  It is written
+    to give the bits of the update followed by the correction's own launch:
+    the trajectories of the two forms are compared bit for bit, over scenes
+    with affine bodies (grouped with FEM vertices) and without."""
+    from paper_2609_25653_amd import Sim
+    if name == "block":
+        sc = S.block_drop(n_steps=n)
+    elif name == "squeeze":   # two pads of 12k tets and the gripper's bodies: several domains
+        sc = S.gripper_squeeze(n_steps=n)
+    else:
+        sc = S.tiny_scene(name, h=0.01, n_steps=n)
+    monkeypatch.setenv("IPC_PCG_COARSE", "1")
+    runs = []
+    for split in ("1", "0"):
+        monkeypatch.setenv("IPC_NO_FUSED_PCG", split)
+        sim = Sim(sc)
+        assert sim.pcg_coarse and sim.pcg_fused == (split == "0")
+        states = []
+        for _ in range(n):
+            rc, st = sim.step()
+            assert rc == 0, st
+            y, v = sim.state()
+            states.append((y.clone(), v.clone(), sum(s["pcg_iters_total"] for s in st)))
+        runs.append(states)
+    for k, ((ya, va, ia), (yb, vb, ib)) in enumerate(zip(*runs)):
+        assert ia == ib and torch.equal(ya, yb) and torch.equal(va, vb), (name, k)
