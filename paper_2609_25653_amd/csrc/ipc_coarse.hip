@@ -81,6 +81,23 @@ void coarse_setup(ipc_ctx *c)
             for (int e = ent[d]; e < ent[d + 1]; ++e) pn[(size_t)d * CG_AGG * CG_DOM + (e - ent[d])] = nodes[e];
         D.cg_pnodes.upload(pn, c->stream);
     }
+    {   // one scene: per domain the entries whose slot stands for a body's translation node
+        std::vector<int> ph_ptr(ndom + 1, 0), ph_e, ph_n;
+        if (c->cg_fusable) {
+            const SceneInfo &S = c->sc[0];
+            c->cg_nfr = (int)S.entry.size();
+            for (int m = 0; m < c->cg_nfr; ++m)
+                if (S.entry[m] < 0) {
+                    ph_ptr[m / (CG_AGG * CG_DOM) + 1]++;
+                    ph_e.push_back(m % (CG_AGG * CG_DOM));
+                    ph_n.push_back(S.bnode0 + 4 * (-1 - S.entry[m]));
+                }
+            for (int d = 0; d < ndom; ++d) ph_ptr[d + 1] += ph_ptr[d];
+        }
+        D.cg_ph_ptr.upload(ph_ptr, c->stream);
+        D.cg_ph_e.upload(ph_e.empty() ? std::vector<int>(1, 0) : ph_e, c->stream);
+        D.cg_ph_n.upload(ph_n.empty() ? std::vector<int>(1, 0) : ph_n, c->stream);
+    }
     D.cg_node_da.upload(node_da, c->stream);
     D.cg_dom_scene.upload(dom_scene.empty() ? std::vector<int>(1, 0) : dom_scene, c->stream);
     // zero once: the entries past a short domain's n are never written and
@@ -320,7 +337,7 @@ __global__ void __launch_bounds__(CG_APPLY) k_coarse_apply(int ndom, int single,
     for (int j = 0; j < CG_PASSES; ++j) {
         const d3 v = cg_group_sum(rv[j]);
         const int g = (t + j * CG_APPLY) / CG_AGG;
-        if ((lane & (CG_AGG - 1)) == 0) { rc[3 * g] = v.x; rc[3 * g + 1] = v.y; rc[3 * g + 2] = v.z; }
+        if ((lane & (CG_AGG - 1)) == CG_AGG - 1) { rc[3 * g] = v.x; rc[3 * g + 1] = v.y; rc[3 * g + 2] = v.z; }
     }
     __syncthreads();
     if (t < 192) {

@@ -672,6 +672,7 @@ void create_context(ipc_ctx *c, const ipc_scene_desc *scenes, int n, const int64
             4 * (N / TILE + 1), 4 * (T / TILE + 1), 8 * (N / TILE + 1), 32 * (N / TILE + 1), 32 * (N / 256 + 1),
             // coarse correction: groups, domains, inverses
             4 * ngrp, 4 * (ndom + 1), 4 * N, 4 * N, 4 * ndom, 8 * CG_N * CG_N * ndom, 16 * CG_SPLIT * ndom, 4 * CG_AGG * CG_DOM * ndom,
+            4 * (ndom + 1), 4 * NB, 4 * NB,
             // reserve_capacity: broad phase
             48 * Pp, 8 * Pp, 8 * Pp, 8 * Pp, 8 * Pp, 4 * Pp, 4 * Pp, 8 * Pp, 4 * Pp, 48 * Pp, 48 * (2 * Pp + 64), 4 * (Pp + 1),
             4 * (Pp + 1), 4 * Pp, 4 * (Q + 1), 4 * (Q + 1), 8 * TRAV_STASH * Q, 8 * Q, 8 * Q, 4 * Q, 4 * Q,

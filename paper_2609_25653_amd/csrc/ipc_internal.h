@@ -341,6 +341,7 @@ struct Dev {
     DBuf<int> cg_ent, cg_nodes, cg_node_da, cg_dom_scene;
     DBuf<int> cg_grp;                      // per group: domain * CG_DOM + group in the domain
     DBuf<int> cg_pnodes;                   // per domain its node list padded to CG_AGG * CG_DOM entries (-1 after the end)
+    DBuf<int> cg_ph_ptr, cg_ph_e, cg_ph_n; // one-launch step: per domain its entries that stand for a body (entry, node)
     DBuf<double> cg_inv, cg_part;
     DBuf<int> pcg_act, pcg_it;
     DBuf<int> pair_flag, lag_flag;         // 1: the pair's blocks were merged into the matrix
@@ -384,6 +385,7 @@ struct ipc_ctx {
     bool coarse_on = false;               // the PCG applies the coarse correction
     bool coarse_forced = false;           // on by request, whatever the size
     bool cg_fusable = false;              // one scene whose domains match the step's workgroups (see coarse_setup)
+    int cg_nfr = 0;                       // its entries (FEM vertices and body translations)
     bool pcg_fused = true;                // IPC_NO_FUSED_PCG unset: a fusable context applies its coarse
                                           // correction inside the PCG step
     int lag_passes = 1;                   // friction lag passes per step

@@ -4,11 +4,47 @@
 
 namespace ipc {
 
+// Cross-lane moves through DPP (a VALU operand modifier, no LDS round trip).
+// A double moves as its two 32-bit halves; lanes whose row is not in ROWS
+// (or whose source lane does not exist) receive 0.  Callers keep the whole
+// wavefront active.
+enum DppCtrl {
+    DPP_XOR1 = 0xB1,         // quad_perm [1,0,3,2]: lane ^ 1
+    DPP_XOR2 = 0x4E,         // quad_perm [2,3,0,1]: lane ^ 2
+    DPP_HALF_MIRROR = 0x141, // lane 7 - i within each 8
+    DPP_MIRROR = 0x140,      // lane 15 - i within each 16
+    DPP_BCAST15 = 0x142,     // lane 15 of the previous row of 16
+    DPP_BCAST31 = 0x143,     // lane 31, into rows 2 and 3
+};
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u & 0xffffffffull), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// sum over each aligned group of 8 lanes, in every lane of the group
+__device__ __forceinline__ double sum8(double v)
+{
+    v += dpp_d<DPP_XOR1>(v);
+    v += dpp_d<DPP_XOR2>(v);
+    return v + dpp_d<DPP_HALF_MIRROR>(v);
+}
+// sum over each aligned group of 16 lanes, in every lane of the group
+__device__ __forceinline__ double sum16(double v) { v = sum8(v); return v + dpp_d<DPP_MIRROR>(v); }
+// sum over each aligned group of 32 lanes, in its upper 16 lanes (lanes
+// 16-31 and 48-63; the lower 16 keep their 16-lane sums)
+__device__ __forceinline__ double sum32_hi(double v) { v = sum16(v); return v + dpp_d<DPP_BCAST15, 0xA>(v); }
+// sum over the wavefront, in every lane (the same order in every call)
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = sum32_hi(v);
+    v += dpp_d<DPP_BCAST31, 0xC>(v);
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 __device__ __forceinline__ double wave_max(double v)
 {

@@ -9,6 +9,7 @@
 
 #include "ipc_device.h"
 #include "ipc_internal.h"
+#include "ipc_kernels.h"
 
 namespace ipc {
 
@@ -45,28 +46,19 @@ __device__ __forceinline__ d3 body_rows(const double *__restrict__ M, const doub
     return {zz[0], zz[1], zz[2]};
 }
 
-// sum over the CG_AGG lanes of a group (aligned lanes of one wavefront)
-__device__ __forceinline__ d3 cg_group_sum(d3 v)
-{
-#pragma unroll
-    for (int o = CG_AGG / 2; o > 0; o >>= 1) {
-        v.x += __shfl_xor(v.x, o, TILE);
-        v.y += __shfl_xor(v.y, o, TILE);
-        v.z += __shfl_xor(v.z, o, TILE);
-    }
-    return v;
-}
+// sum over the CG_AGG lanes of a group (aligned lanes of one wavefront),
+// held by the group's last lane (lane & (CG_AGG - 1)) == CG_AGG - 1
+static_assert(CG_AGG == 32 && CG_CLANES == 8, "the DPP sums below are for groups of 32 and rows of 8 lanes");
+__device__ __forceinline__ d3 cg_group_sum(d3 v) { return {sum32_hi(v.x), sum32_hi(v.y), sum32_hi(v.z)}; }
 
 // one row of the product with a domain's inverse: this lane's CG_CPL columns
-// cl + CG_CLANES j, then the sum over the row's CG_CLANES lanes
+// cl + CG_CLANES j, then the sum over the row's CG_CLANES lanes (in each)
 __device__ __forceinline__ double cg_row(const double (&m)[CG_CPL], const double *rc, int cl)
 {
     double a = 0.0;
 #pragma unroll
     for (int j = 0; j < CG_CPL; ++j) a += m[j] * rc[cl + CG_CLANES * j];
-#pragma unroll
-    for (int o = CG_CLANES / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, TILE);
-    return a;
+    return sum8(a);
 }
 
 } // namespace ipc

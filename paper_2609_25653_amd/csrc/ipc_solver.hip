@@ -502,37 +502,47 @@ constexpr int WG_TILES = BLOCK / TILE;   // node tiles per step workgroup
 // Sums of up to three per-tile sources and one per-long-row source over a
 // scene's ranges; every thread of the workgroup returns the same totals.
 // (ca: per-domain partials added to the first sum, over [clo, chi))
-__device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, int clo, int chi, const double *__restrict__ a,
-                                           const double *__restrict__ b, const double *__restrict__ c,
-                                           const double *__restrict__ cl, const double *__restrict__ ca, double (*sh)[WG_TILES],
-                                           double &ta, double &tb, double &tc)
+// The first 4 strided entries of every source (scenes of up to 1024 tiles,
+// 64k nodes), the long rows' first and the domains' first entry are loaded
+// predicated, all before the first add, so their latencies overlap instead
+// of following each other; longer ranges finish in loops.  bs_issue makes
+// those first loads (a caller may issue them early), bs_finish the rest.
+struct BsFirst {
+    double ea[4], eb[4], ec[4], el, ec0;
+};
+__device__ __forceinline__ void bs_issue(int lo, int hi, int llo, int lhi, int clo, int chi, const double *__restrict__ a,
+                                         const double *__restrict__ b, const double *__restrict__ c,
+                                         const double *__restrict__ cl, const double *__restrict__ ca, BsFirst &f)
 {
-    // the first 4 strided entries of every source (scenes of up to 1024
-    // tiles, 64k nodes), the long rows' first and the domains' first entry
-    // are loaded predicated, all before the first add, so their latencies
-    // overlap instead of following each other; longer ranges finish in loops
     const int t = (int)threadIdx.x;
-    double ea[4], eb[4], ec[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int i = lo + t + u * BLOCK;
         const bool in = i < hi;
-        ea[u] = in ? a[i] : 0.0;
-        eb[u] = in ? b[i] : 0.0;
-        ec[u] = in && c ? c[i] : 0.0;
+        f.ea[u] = in ? a[i] : 0.0;
+        f.eb[u] = in ? b[i] : 0.0;
+        f.ec[u] = in && c ? c[i] : 0.0;
     }
-    const double el = cl && llo + t < lhi ? cl[llo + t] : 0.0;
-    const double ec0 = ca && clo + t < chi ? ca[clo + t] : 0.0;
-    double va = (ea[0] + ea[1]) + (ea[2] + ea[3]), vb = (eb[0] + eb[1]) + (eb[2] + eb[3]), vc = (ec[0] + ec[1]) + (ec[2] + ec[3]);
+    f.el = cl && llo + t < lhi ? cl[llo + t] : 0.0;
+    f.ec0 = ca && clo + t < chi ? ca[clo + t] : 0.0;
+}
+__device__ __forceinline__ void bs_finish(int lo, int hi, int llo, int lhi, int clo, int chi, const double *__restrict__ a,
+                                          const double *__restrict__ b, const double *__restrict__ c,
+                                          const double *__restrict__ cl, const double *__restrict__ ca, const BsFirst &f,
+                                          double (*sh)[WG_TILES], double &ta, double &tb, double &tc)
+{
+    const int t = (int)threadIdx.x;
+    double va = (f.ea[0] + f.ea[1]) + (f.ea[2] + f.ea[3]), vb = (f.eb[0] + f.eb[1]) + (f.eb[2] + f.eb[3]),
+           vc = (f.ec[0] + f.ec[1]) + (f.ec[2] + f.ec[3]);
     for (int i = lo + t + 4 * BLOCK; i < hi; i += BLOCK) {
         va += a[i];
         vb += b[i];
         if (c) vc += c[i];
     }
-    vc += el;
+    vc += f.el;
     if (cl)
         for (int i = llo + t + BLOCK; i < lhi; i += BLOCK) vc += cl[i];
-    va += ec0;
+    va += f.ec0;
     if (ca)
         for (int i = clo + t + BLOCK; i < chi; i += BLOCK) va += ca[i];
     va = wave_sum(va); vb = wave_sum(vb); vc = wave_sum(vc);
@@ -543,6 +553,15 @@ __device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, int
     tb = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
     tc = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
     __syncthreads();
+}
+__device__ __forceinline__ void block_sums(int lo, int hi, int llo, int lhi, int clo, int chi, const double *__restrict__ a,
+                                           const double *__restrict__ b, const double *__restrict__ c,
+                                           const double *__restrict__ cl, const double *__restrict__ ca, double (*sh)[WG_TILES],
+                                           double &ta, double &tb, double &tc)
+{
+    BsFirst f;
+    bs_issue(lo, hi, llo, lhi, clo, chi, a, b, c, cl, ca, f);
+    bs_finish(lo, hi, llo, lhi, clo, chi, a, b, c, cl, ca, f, sh, ta, tb, tc);
 }
 
 __device__ __forceinline__ d3 mat3v(const double *__restrict__ M, d3 v)
@@ -666,7 +685,9 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
                                                     double *r, const double *z_in, double *z, const double *__restrict__ part_zw,
                                                     const double *__restrict__ part_long, double *__restrict__ part, int ntile,
                                                     double *__restrict__ st, int *__restrict__ act, int *__restrict__ it,
-                                                    double *__restrict__ scal, int ndom, int nwin, const int *__restrict__ pnodes,
+                                                    const double *__restrict__ st_in, const int *__restrict__ act_in,
+                                                    const int *__restrict__ it_in, double *__restrict__ scal, int ndom, int nwin, int nfr, int bnode0, const int *__restrict__ ph_ptr,
+                                                    const int *__restrict__ ph_e, const int *__restrict__ ph_n,
                                                     const int *__restrict__ node_da, const double *__restrict__ inv, double *cg_out)
 {
     __shared__ double sh[3][WG_TILES];
@@ -682,60 +703,70 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
     const bool cg = FUSED && d < ndom;   // uniform: this workgroup applies a slice of domain d
     const int t0 = L * WG_TILES, t = t0 + wave;
     const int n = t * TILE + lane;
-    // this node's operands first, without waiting for its kind: their loads
-    // overlap the reductions below
-    int k = 2;
-    d3 zv{}, pv{}, wv{}, sv{}, xv{}, rv{};
-    double Mi[9];
-    if (n < N) {
-        k = kind[n];
-        zv = ld3(z_in, n); pv = ld3(p, n); wv = ld3(w, n); sv = ld3(s_in, n); xv = ld3(x, n); rv = ld3(r_in, n);
+    const double *rz_in = part + (size_t)(2 * q) * ntile, *rr_in = rz_in + ntile;
+    const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction (CG_SPLIT per domain)
+    // The first scene's partials are the first loads, so that the loads
+    // below do not hold back its reduction.  Its ranges: for a single scene
+    // all tiles, every long-row partial (unused ones are 0) and every coarse
+    // domain; otherwise the workgroup's record.
+    const int *wi = wginfo + WGI * (size_t)L;
+    const int r0t = single ? 0 : wi[2], r1t = single ? ntile : wi[3], r0l = single ? 0 : wi[4], r1l = single ? lcap : wi[5],
+              r0c = single ? 0 : CG_SPLIT * wi[6], r1c = single ? ncdom : CG_SPLIT * wi[7];
+    BsFirst pre;
+    bs_issue(r0t, r1t, r0l, r1l, r0c, r1c, rz_in, rr_in, part_zw, part_long, cz_in, pre);
+    // FUSED: the domain's entries.  Entry e of domain d is node
+    // CG_AGG CG_DOM d + e, entries end at nfr, and the few slots that stand
+    // for a body's translation node come from a per-domain list read through
+    // scalar loads, so no vector load waits for another.
+    int nd[CG_PASSES];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)n + q];
+    for (int j = 0; j < CG_PASSES; ++j) {
+        const int slot = CG_AGG * CG_DOM * d + CG_APPLY * j + tid;
+        nd[j] = cg && slot < nfr ? slot : -1;
     }
-    // FUSED: the slice's inverse rows, the domain's entries and the foreign
-    // entries' operands, also before the reductions
+    if (cg)
+        for (int u = ph_ptr[d]; u < ph_ptr[d + 1]; ++u) {   // uniform
+            const int e = ph_e[u], node = ph_n[u];
+#pragma unroll
+            for (int j = 0; j < CG_PASSES; ++j)
+                if (e == CG_APPLY * j + tid) nd[j] = node;
+        }
+    // this node's operands, without waiting for its kind: their loads
+    // overlap the reductions below
+    // (a lane past the last node reads the last node, so that no branch
+    // joins values whose loads are still in flight; its kind counts as 2)
+    const bool live = n < N;
+    const int nc = live ? n : N - 1;
+    const int kraw = kind[nc];
+    const int da = FUSED ? node_da[nc] : -1;   // FUSED: the node's coarse group (a grouped body node's z comes from its entry's workgroup)
+    d3 zv = ld3(z_in, nc), pv = ld3(p, nc), wv = ld3(w, nc), sv = ld3(s_in, nc), xv = ld3(x, nc), rv = ld3(r_in, nc);
+    double Mi[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Mi[q] = dinv[9 * (size_t)nc + q];
+    // FUSED: the slice's inverse rows and the other entries' operands, also
+    // before the reductions
     const int i = tid / CG_CLANES, cl = tid % CG_CLANES;
     double m[CG_CPL];
-    int nd[CG_PASSES];
     d3 fr[CG_PASSES], fs[CG_PASSES], fw[CG_PASSES];
-    // an entry of this slice that stands for a body's translation node: the
-    // body's 4 nodes' operands and its block's first 3 rows
-    d3 br[4], bs[4], bw[4];
-    const double *bM = nullptr;
-    bool grouped_body = false;
-    if (cg) {
-        if (tid < 192) {
-            const double *M = inv + (size_t)d * CG_N * CG_N + (size_t)(CG_ROWS * sl + i) * CG_N + cl;
+    // (none of these loads is predicated: the waits for the partials count
+    // the loads issued after them, and a load that may be skipped would make
+    // them wait for more; a lane or workgroup without a use reads a valid
+    // address and discards the value)
+    if (FUSED) {
+        const double *M = inv + (size_t)(cg ? d : ndom - 1) * CG_N * CG_N + (size_t)(CG_ROWS * sl + min(i, CG_ROWS - 1)) * CG_N + cl;
 #pragma unroll
-            for (int j = 0; j < CG_CPL; ++j) m[j] = M[CG_CLANES * j];
-        }
-#pragma unroll
-        for (int j = 0; j < CG_PASSES; ++j) nd[j] = pnodes[(size_t)d * (CG_AGG * CG_DOM) + tid + j * CG_APPLY];
+        for (int j = 0; j < CG_CPL; ++j) m[j] = M[CG_CLANES * j];
 #pragma unroll
         for (int j = 0; j < CG_PASSES; ++j) {
-            fr[j] = fs[j] = fw[j] = d3{0.0, 0.0, 0.0};
-            if (nd[j] >= 0 && nd[j] != n) { fr[j] = ld3(r_in, nd[j]); fs[j] = ld3(s_in, nd[j]); fw[j] = ld3(w, nd[j]); }
-        }
-        int me = -1;
-#pragma unroll
-        for (int j = 0; j < CG_PASSES; ++j)
-            if (j == sl) me = nd[j];
-        if (me >= 0 && me != n) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) { br[c] = ld3(r_in, me + c); bs[c] = ld3(s_in, me + c); bw[c] = ld3(w, me + c); }
-            bM = dinvB + 144 * (size_t)node_body[me];
+            const int f = nd[j] >= 0 ? nd[j] : nc;
+            fr[j] = ld3(r_in, f); fs[j] = ld3(s_in, f); fw[j] = ld3(w, f);
         }
     }
-    if (FUSED && k == 1) grouped_body = node_da[n] >= 0;   // its z comes from its entry's workgroup
-    const double *rz_in = part + (size_t)(2 * q) * ntile, *rr_in = rz_in + ntile;
     double *rz_out = part + (size_t)(2 * (q ^ 1)) * ntile, *rr_out = rz_out + ntile;
     // the workgroup's scenes and the first one's tile and long-row ranges in
     // one record, so the partials' loads wait for a single load
     // (a single scene needs no record: its ranges are all tiles, every
     // long-row partial, unused ones being 0, and every coarse domain)
-    const int *wi = wginfo + WGI * (size_t)L;
-    const double *cz_in = ncdom ? cg_part + (size_t)q * ncdom : nullptr;   // r . z of the coarse correction (CG_SPLIT per domain)
     const int sc_lo = single ? 0 : wi[0], sc_hi = single ? 0 : wi[1];
     const int my_sc = t < ntile ? (single ? 0 : tile_scene[t]) : -1;
     double al = 0.0, be = 0.0;
@@ -745,8 +776,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         const int tlo = single ? 0 : first ? wi[2] : seg_nodew[sc], thi = single ? ntile : first ? wi[3] : seg_nodew[sc + 1];
         const int llo = single ? 0 : first ? wi[4] : seg_long[sc], lhi = single ? lcap : first ? wi[5] : seg_long[sc + 1];
         const int clo = single ? 0 : first ? wi[6] : seg_cdom[sc], chi = single ? ncdom / CG_SPLIT : first ? wi[7] : seg_cdom[sc + 1];
-        const int a = act[q * ns + sc], itc = it[q * ns + sc];
-        const double *S = st + ((size_t)q * ns + sc) * 4;
+        const int a = act_in[q * ns + sc], itc = it_in[q * ns + sc];
+        const double *S = st_in + ((size_t)q * ns + sc) * 4;
         const bool writer = tlo / WG_TILES == L && threadIdx.x == 0;
         double *So = st + ((size_t)(q ^ 1) * ns + sc) * 4;
         if (!a) {
@@ -758,7 +789,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
             continue;
         }
         double gam, rr, del;
-        block_sums(tlo, thi, llo, lhi, CG_SPLIT * clo, CG_SPLIT * chi, rz_in, rr_in, part_zw, part_long, cz_in, sh, gam, rr, del);
+        if (first) bs_finish(r0t, r1t, r0l, r1l, r0c, r1c, rz_in, rr_in, part_zw, part_long, cz_in, pre, sh, gam, rr, del);
+        else block_sums(tlo, thi, llo, lhi, CG_SPLIT * clo, CG_SPLIT * chi, rz_in, rr_in, part_zw, part_long, cz_in, sh, gam, rr, del);
         // gamma = r.z, delta = z.Az of the current residual:
         //   beta = gamma / gamma_old,  p.Ap = delta - beta gamma / alpha_old,
         //   alpha = gamma / p.Ap
@@ -786,6 +818,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         }
         if (sc == my_sc || (FUSED && sc == 0)) { on = na; al = as; be = bs; }
     }
+    const int k = live ? kraw : 2;
     double rz = 0.0, rr = 0.0;
     // z of this node from its block-Jacobi part; the coarse correction is
     // added before it is stored when the node is an entry of this slice
@@ -817,7 +850,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
             rb[3 * q + 2] = __shfl(rv.z, first + q);
         }
         zv = body_rows(dinvB + 144 * (size_t)node_body[n - a] + 36 * a, rb);
-        store_z = !grouped_body;
+        store_z = !(FUSED && da >= 0);
         rr = dt(rv, rv);
         rz = dt(rv, zv);
     }
@@ -840,7 +873,7 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         for (int j = 0; j < CG_PASSES; ++j) {
             const d3 v = cg_group_sum(rn[j]);
             const int g = (tid + j * CG_APPLY) / CG_AGG;
-            if ((lane & (CG_AGG - 1)) == 0) { rc[3 * g] = v.x; rc[3 * g + 1] = v.y; rc[3 * g + 2] = v.z; }
+            if ((lane & (CG_AGG - 1)) == CG_AGG - 1) { rc[3 * g] = v.x; rc[3 * g + 1] = v.y; rc[3 * g + 2] = v.z; }
         }
         __syncthreads();
         if (tid < 192) {
@@ -856,14 +889,18 @@ __global__ void __launch_bounds__(BLOCK) k_pcg_step(int N, int ns, int q, const 
         if (me == n) {
             zv = {zv.x + zl[3 * g], zv.y + zl[3 * g + 1], zv.z + zl[3 * g + 2]};
         } else if (me >= 0) {
+            // an entry that stands for a body's translation node: the body's
+            // 4 nodes' new residual and the first 3 rows of its inverse block
+            // (read here, with the block, to keep registers for the loads
+            // every workgroup waits for)
             double rb[12];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                d3 sc = bs[c], rc4 = br[c];
-                pcg_sr(bw[c], al, be, sc, rc4);
+                d3 sc = ld3(s_in, me + c), rc4 = ld3(r_in, me + c);
+                pcg_sr(ld3(w, me + c), al, be, sc, rc4);
                 rb[3 * c] = rc4.x; rb[3 * c + 1] = rc4.y; rb[3 * c + 2] = rc4.z;
             }
-            const d3 zb = body_rows(bM, rb);
+            const d3 zb = body_rows(dinvB + 144 * (size_t)((me - bnode0) / 4), rb);   // one scene: body b at bnode0 + 4 b
             st3(z, me, {zb.x + zl[3 * g], zb.y + zl[3 * g + 1], zb.z + zl[3 * g + 2]});
         }
         if (tid < TILE) {
@@ -957,14 +994,15 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                                q, D.node_kind.p, D.node_body.p, D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG),
                                seg_ptr(c, R_CDOM), D.pcg_wginfo.p, 1, c->long_cap, D.cg_part.p, ncd, D.maxpcg.p, D.dinv.p, D.dinvB.p,
                                w, p, sb[q], sb[q ^ 1], x, rb[q], rb[q ^ 1], zb[q], zb[q ^ 1], D.part_node3.p, D.part_long.p,
-                               D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.scal.p, c->n_cdom, nwin, D.cg_pnodes.p,
-                               D.cg_node_da.p, D.cg_inv.p, cg_out);
+                               D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p, D.pcg_st.p, act, D.pcg_it.p, D.scal.p, c->n_cdom,
+                               nwin, c->cg_nfr, c->sc[0].bnode0,
+                               D.cg_ph_ptr.p, D.cg_ph_e.p, D.cg_ph_n.p, D.cg_node_da.p, D.cg_inv.p, cg_out);
         else
             hipLaunchKernelGGL(k_pcg_step<false>, dim3(blocks_for(c->N)), dim3(BLOCK), 0, c->stream, c->N, ns, q, D.node_kind.p,
                                D.node_body.p, D.tile_scene_node.p, seg_ptr(c, R_NODEW), seg_ptr(c, R_LONG), seg_ptr(c, R_CDOM),
                                D.pcg_wginfo.p, (int)(ns == 1), c->long_cap, D.cg_part.p, ncd, D.maxpcg.p, D.dinv.p, D.dinvB.p, w, p,
                                s, s, x, r, r, z, z, D.part_node3.p, D.part_long.p, D.pcg_part.p, ntile, D.pcg_st.p, act, D.pcg_it.p,
-                               D.scal.p, 0, 0, nullptr, nullptr, nullptr, nullptr);
+                               D.pcg_st.p, act, D.pcg_it.p, D.scal.p, 0, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
         prof_end(c, IPC_K_PCG_UPDATE, update_bytes(c));
         if (!fused) coarse_apply(c, act + (q ^ 1) * ns, r, z, q ^ 1);
         hess_apply(c, zb[q ^ 1], w, act + (q ^ 1) * ns, D.part_node3.p);
@@ -1028,7 +1066,8 @@ void pcg_solve(ipc_ctx *c, const double *b, double *x, double eta, const int *wa
                                       (uintptr_t)D.dyn_col.p, (uintptr_t)D.dyn_val.p, (uintptr_t)D.node_scene.p,
                                       (uintptr_t)D.pcg_wginfo.p, (uintptr_t)(c->coarse_on ? c->n_cdom : 0), (uintptr_t)D.cg_ent.p, (uintptr_t)D.cg_nodes.p,
                                       (uintptr_t)D.cg_dom_scene.p, (uintptr_t)D.cg_inv.p, (uintptr_t)D.cg_part.p, (uintptr_t)D.cg_pnodes.p,
-                                      (uintptr_t)fused, (uintptr_t)D.r2.p, (uintptr_t)D.z2.p, (uintptr_t)D.q2.p, (uintptr_t)D.cg_node_da.p};
+                                      (uintptr_t)fused, (uintptr_t)D.r2.p, (uintptr_t)D.z2.p, (uintptr_t)D.q2.p, (uintptr_t)D.cg_node_da.p,
+                                      (uintptr_t)c->cg_nfr, (uintptr_t)D.cg_ph_ptr.p, (uintptr_t)D.cg_ph_e.p, (uintptr_t)D.cg_ph_n.p};
         bool have = key == c->pcg_key;
         for (auto xg : c->pcg_exec) have = have && xg;
         if (!have) {
