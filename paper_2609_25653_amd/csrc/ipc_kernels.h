@@ -31,6 +31,18 @@ __device__ __forceinline__ double sum8(double v)
     v += dpp_d<DPP_XOR2>(v);
     return v + dpp_d<DPP_HALF_MIRROR>(v);
 }
+// sum over each aligned group of L lanes (L = 1, 2, 4, 8 or 16), in every
+// lane of the group
+template <int L>
+__device__ __forceinline__ double lane_sum(double v)
+{
+    static_assert(L == 1 || L == 2 || L == 4 || L == 8 || L == 16, "groups of 1 to 16 lanes");
+    if (L >= 2) v += dpp_d<DPP_XOR1>(v);
+    if (L >= 4) v += dpp_d<DPP_XOR2>(v);
+    if (L >= 8) v += dpp_d<DPP_HALF_MIRROR>(v);
+    if (L >= 16) v += dpp_d<DPP_MIRROR>(v);
+    return v;
+}
 // sum over each aligned group of 16 lanes, in every lane of the group
 __device__ __forceinline__ double sum16(double v) { v = sum8(v); return v + dpp_d<DPP_MIRROR>(v); }
 // sum over each aligned group of 32 lanes, in its upper 16 lanes (lanes

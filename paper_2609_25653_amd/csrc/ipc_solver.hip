@@ -216,12 +216,8 @@ __global__ void __launch_bounds__(64 * L) k_spmv(int N, int ntiles, const int *_
                 }
             }
         }
-#pragma unroll
-        for (int o = L / 2; o > 0; o >>= 1) {
-            ax += __shfl_xor(ax, o, TILE);
-            ay += __shfl_xor(ay, o, TILE);
-            az += __shfl_xor(az, o, TILE);
-        }
+        // the row's L lanes are aligned lanes of one wavefront: DPP sums
+        ax = lane_sum<L>(ax); ay = lane_sum<L>(ay); az = lane_sum<L>(az);
         double dot = 0.0;
         if (mine && sub == 0) {
             st3(out, n, {ax, ay, az});
