@@ -21,7 +21,9 @@
 // the new residual to its groups, multiplies by the domain's inverse, adds
 // the result to z on every node of the group and writes r . z of the
 // correction, which the next step's reduction adds to r . z of the
-// block-Jacobi part.
+// block-Jacobi part.  For a context of one scene the PCG step does the same
+// inside its own launch (k_pcg_step<true>); this kernel then runs once per
+// solve, for the first z.
 #include <algorithm>
 #include <cstdlib>
 #include <numeric>
